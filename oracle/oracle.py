@@ -1,0 +1,492 @@
+"""Plain FP64 CPU oracle for U(1) block-sparse contraction and H_eff.psi.
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+benchmark's CPU-baseline leg may import this module; the GPU library never
+does, and this module imports nothing from the library.
+
+It is written to be read against the paper (arXiv:2401.01921, "The Cytnx
+Library for Tensor Networks"):
+
+* block structure and zero flux ........ Sec. "UniTensor with Symmetries",
+  Sec. "Bond with quantum numbers", Sec. "Symmetric UniTensor" (the printed
+  block list of the rank-3 example fixes the lexicographic block order)
+* row-major data, permute semantics .... Sec. "Permute", App. "Contiguous"
+* contraction over common labels ....... Sec. "Tensor contraction" (checks of
+  direction, quantum numbers and per-sector dims)
+* combining bonds ...................... Sec. "Combining bonds with quantum
+  numbers" (equal charges grouped, ascending)
+* dense <-> symmetric conversion ....... Sec. "Conversion between UniTensor
+  with and without symmetries"
+* H_eff.psi ............................ Sec. "Benchmarks", Fig. Hpsi_fig
+  (L, two-site MPO, R, two-site wavefunction)
+* Lanczos on a linear operator ......... Sec. "Eigenvalue decomposition"
+  (LinOp + Lanczos; the paper gives no algorithmic detail, so this is the
+  textbook method with full classical Gram-Schmidt reorthogonalisation done
+  twice, a Sturm-bisection tridiagonal eigensolve and inverse iteration)
+
+Everything is float64.  numpy matmul is used as the per-block product; there
+is no blocking, fusion or reordering beyond the definitions.
+"""
+from __future__ import annotations
+
+import itertools
+import math
+from typing import Callable, Dict, List, Sequence, Tuple
+
+import numpy as np
+
+IN, OUT = +1, -1
+
+
+class OracleError(Exception):
+    status = "E_INVALID"
+
+
+class DirectionError(OracleError):
+    status = "E_DIRECTION"
+
+
+class QnumError(OracleError):
+    status = "E_QNUM"
+
+
+class DimError(OracleError):
+    status = "E_DIM"
+
+
+class LabelError(OracleError):
+    status = "E_LABEL"
+
+
+class NoBlockError(OracleError):
+    status = "E_NOBLOCK"
+
+
+class StructureError(OracleError):
+    status = "E_STRUCTURE"
+
+
+Leg = Tuple[int, List[Tuple[int, int]]]
+
+
+# --------------------------------------------------------------------------
+# Structure (Sec. "UniTensor with Symmetries"; block order from the printed
+# block list of the rank-3 example in Sec. "Symmetric UniTensor")
+# --------------------------------------------------------------------------
+def check_legs(legs: Sequence[Leg]) -> None:
+    for d, secs in legs:
+        if d not in (IN, OUT):
+            raise OracleError("direction must be +1 (in) or -1 (out)")
+        if len(secs) == 0:
+            raise OracleError("a leg needs at least one sector")
+        for _, g in secs:
+            if g < 1:
+                raise OracleError("sector dims must be >= 1")
+
+
+def valid_blocks(legs: Sequence[Leg]) -> List[Tuple[int, ...]]:
+    """All sector-index tuples whose flux (sum of in charges minus sum of out
+    charges) is zero, in lexicographic order with leg 0 most significant."""
+    out = []
+    for t in itertools.product(*[range(len(secs)) for _, secs in legs]):
+        flux = sum(d * secs[k][0] for (d, secs), k in zip(legs, t))
+        if flux == 0:
+            out.append(t)
+    return out
+
+
+class BlockTensor:
+    """Labels, legs, canonical block list, and one flat float64 buffer with the
+    blocks stored one after another in block order, each row-major."""
+
+    def __init__(self, labels: Sequence[str], legs: Sequence[Leg], data: np.ndarray | None = None):
+        if len(labels) != len(legs):
+            raise LabelError("one label per leg")
+        if len(set(labels)) != len(labels):
+            raise LabelError("labels must be unique")
+        check_legs(legs)
+        self.labels = list(labels)
+        self.legs = [(int(d), [(int(q), int(g)) for q, g in secs]) for d, secs in legs]
+        self.blocks = valid_blocks(self.legs)
+        self.shapes = [tuple(self.legs[i][1][k][1] for i, k in enumerate(t)) for t in self.blocks]
+        self.offsets = []
+        off = 0
+        for sh in self.shapes:
+            self.offsets.append(off)
+            off += int(np.prod(sh)) if sh else 1
+        self.numel = off
+        self.index = {t: b for b, t in enumerate(self.blocks)}
+        if data is None:
+            data = np.zeros(self.numel)
+        data = np.asarray(data, dtype=np.float64)
+        if data.shape != (self.numel,):
+            raise OracleError("data length does not match the block structure")
+        self.data = data
+
+    @property
+    def rank(self) -> int:
+        return len(self.legs)
+
+    def block(self, b: int) -> np.ndarray:
+        sh = self.shapes[b]
+        n = int(np.prod(sh))
+        return self.data[self.offsets[b]:self.offsets[b] + n].reshape(sh)
+
+    def find_block(self, qn_idx: Sequence[int]) -> int:
+        t = tuple(int(k) for k in qn_idx)
+        if t not in self.index:
+            raise NoBlockError("no valid block with these Qn indices")
+        return self.index[t]
+
+    def table(self):
+        return [(t, sh, off) for t, sh, off in zip(self.blocks, self.shapes, self.offsets)]
+
+    def sector_offsets(self) -> List[List[int]]:
+        """Start of each sector inside the full (dense) range of each leg."""
+        return [list(np.cumsum([0] + [g for _, g in secs])[:-1]) for _, secs in self.legs]
+
+    def dims(self) -> List[int]:
+        return [sum(g for _, g in secs) for _, secs in self.legs]
+
+    def exists(self, element: Sequence[int]) -> bool:
+        """Whether a dense element index lies inside a valid block."""
+        t = []
+        for (_, secs), e in zip(self.legs, element):
+            acc = 0
+            for k, (_, g) in enumerate(secs):
+                if e < acc + g:
+                    t.append(k)
+                    break
+                acc += g
+            else:
+                raise IndexError("element index out of range")
+        return tuple(t) in self.index
+
+
+# --------------------------------------------------------------------------
+# Dense embedding and extraction (Sec. "Conversion between UniTensor with and
+# without symmetries": convert_from, with and without force)
+# --------------------------------------------------------------------------
+def embed(T: BlockTensor) -> np.ndarray:
+    dense = np.zeros(T.dims())
+    so = T.sector_offsets()
+    for b, t in enumerate(T.blocks):
+        sl = tuple(slice(so[i][k], so[i][k] + T.shapes[b][i]) for i, k in enumerate(t))
+        dense[sl] = T.block(b)
+    return dense
+
+
+def from_dense(labels, legs, dense: np.ndarray, force: bool = False) -> BlockTensor:
+    T = BlockTensor(labels, legs)
+    dense = np.asarray(dense, dtype=np.float64)
+    if list(dense.shape) != T.dims():
+        raise DimError("dense shape does not match the bonds")
+    so = T.sector_offsets()
+    kept = np.zeros(dense.shape, dtype=bool)
+    for b, t in enumerate(T.blocks):
+        sl = tuple(slice(so[i][k], so[i][k] + T.shapes[b][i]) for i, k in enumerate(t))
+        T.block(b)[...] = dense[sl]
+        kept[sl] = True
+    if not force and np.any(dense[~kept] != 0.0):
+        raise StructureError("nonzero elements in symmetry-violating blocks")
+    return T
+
+
+# --------------------------------------------------------------------------
+# Combining bonds (Sec. "Combining bonds with quantum numbers")
+# --------------------------------------------------------------------------
+def combine_bonds(a: Leg, b: Leg, grouped: bool = True) -> Leg:
+    """Charges add (U(1) combine rule).  Ungrouped: pairs in row-major order
+    (a slow).  Grouped: equal charges merged, ascending charge."""
+    da, sa = a
+    db, sb = b
+    if da != db:
+        raise DirectionError("combined bonds must have the same direction")
+    pairs = [(qa + qb, ga * gb) for qa, ga in sa for qb, gb in sb]
+    if not grouped:
+        return (da, pairs)
+    acc: Dict[int, int] = {}
+    for q, g in pairs:
+        acc[q] = acc.get(q, 0) + g
+    return (da, sorted(acc.items()))
+
+
+# --------------------------------------------------------------------------
+# Permute (Sec. "Permute": new leg i is the old leg with label order[i];
+# App. "Contiguous": data is moved into the new row-major order)
+# --------------------------------------------------------------------------
+def permute(T: BlockTensor, order: Sequence) -> BlockTensor:
+    if all(isinstance(o, (int, np.integer)) for o in order):
+        perm = [int(o) for o in order]
+    else:
+        try:
+            perm = [T.labels.index(o) for o in order]
+        except ValueError:
+            raise LabelError("unknown label in permutation")
+    if sorted(perm) != list(range(T.rank)):
+        raise LabelError("not a permutation of the legs")
+    out = BlockTensor([T.labels[p] for p in perm], [T.legs[p] for p in perm])
+    for b, t in enumerate(T.blocks):
+        nt = tuple(t[p] for p in perm)
+        out.block(out.index[nt])[...] = np.transpose(T.block(b), perm)
+    return out
+
+
+# --------------------------------------------------------------------------
+# Contract (Sec. "Tensor contraction")
+# --------------------------------------------------------------------------
+def contract(A: BlockTensor, B: BlockTensor) -> BlockTensor:
+    """Sum over all labels common to A and B.
+
+    Each common leg must have opposite directions and the same (charge, dim)
+    sector list in the same order.  The result has A's free legs (A order)
+    then B's free legs (B order) and holds every zero-flux block, zero-filled
+    where nothing contributes.  Output block (fa, fb) is the sum, over the
+    contracted sector tuples kc in lexicographic order (A's leg order), of
+    A[fa, kc] . B[kc, fb] with the contracted multi-index row-major in A's
+    contracted-leg order.
+    """
+    common = [l for l in A.labels if l in B.labels]
+    ac = [A.labels.index(l) for l in common]
+    bc = [B.labels.index(l) for l in common]
+    for i, j in zip(ac, bc):
+        (da, sa), (db, sb) = A.legs[i], B.legs[j]
+        if da == db:
+            raise DirectionError(f"leg '{A.labels[i]}' has the same direction on both tensors")
+        if [q for q, _ in sa] != [q for q, _ in sb]:
+            raise QnumError(f"leg '{A.labels[i]}' has different quantum numbers")
+        if [g for _, g in sa] != [g for _, g in sb]:
+            raise DimError(f"leg '{A.labels[i]}' has different sector dims")
+    af = [i for i in range(A.rank) if i not in ac]
+    bf = [j for j in range(B.rank) if j not in bc]
+    C = BlockTensor([A.labels[i] for i in af] + [B.labels[j] for j in bf],
+                    [A.legs[i] for i in af] + [B.legs[j] for j in bf])
+    by_kc: Dict[Tuple[int, ...], List[int]] = {}
+    for b, t in enumerate(B.blocks):
+        by_kc.setdefault(tuple(t[j] for j in bc), []).append(b)
+    for a, ta in enumerate(A.blocks):
+        kc = tuple(ta[i] for i in ac)
+        fa = tuple(ta[i] for i in af)
+        ablk = A.block(a)
+        m = int(np.prod([ablk.shape[i] for i in af])) if af else 1
+        k = int(np.prod([ablk.shape[i] for i in ac])) if ac else 1
+        amat = np.transpose(ablk, af + ac).reshape(m, k)
+        for b in by_kc.get(kc, []):
+            tb = B.blocks[b]
+            fb = tuple(tb[j] for j in bf)
+            bblk = B.block(b)
+            n = int(np.prod([bblk.shape[j] for j in bf])) if bf else 1
+            bmat = np.transpose(bblk, bc + bf).reshape(k, n)
+            cb = C.index[fa + fb]
+            C.block(cb)[...] += (amat @ bmat).reshape(C.shapes[cb])
+    return C
+
+
+# --------------------------------------------------------------------------
+# H_eff.psi (Sec. "Benchmarks", Fig. Hpsi_fig), pairwise in the order
+# L -> psi -> W1 -> W2 -> R.
+# --------------------------------------------------------------------------
+def relabel(T: BlockTensor, labels: Sequence[str]) -> BlockTensor:
+    return BlockTensor(labels, T.legs, T.data)
+
+
+def heff_apply(L: BlockTensor, W1: BlockTensor, W2: BlockTensor, R: BlockTensor,
+               psi: BlockTensor) -> BlockTensor:
+    """out[a,s1,s2,b] = sum L[a,w1,a'] psi[a',t1,t2,b'] W1[w1,s1,t1,w2]
+    W2[w2,s2,t2,w3] R[b,w3,b'], legs as in the workload specs:
+    L[a,w,a'], W[wl,s(ket),s'(bra),wr], R[b,w,b'], psi[a,s1,s2,b]."""
+    Lr = relabel(L, ["a", "w1", "x"])
+    Pr = relabel(psi, ["x", "t1", "t2", "y"])
+    W1r = relabel(W1, ["w1", "s1", "t1", "w2"])
+    W2r = relabel(W2, ["w2", "s2", "t2", "w3"])
+    Rr = relabel(R, ["b", "w3", "y"])
+    T1 = contract(Lr, Pr)        # a, w1, t1, t2, y
+    T2 = contract(T1, W1r)       # a, t2, y, s1, w2
+    T3 = contract(T2, W2r)       # a, y, s1, s2, w3
+    out = contract(T3, Rr)       # a, s1, s2, b
+    out = permute(out, ["a", "s1", "s2", "b"])
+    return relabel(out, psi.labels)
+
+
+def heff_flops(L: BlockTensor, W1: BlockTensor, W2: BlockTensor, R: BlockTensor,
+               psi: BlockTensor) -> List[int]:
+    """Algorithmic flops (2 m n k over valid block products) of the four steps."""
+    Lr = relabel(L, ["a", "w1", "x"])
+    Pr = relabel(psi, ["x", "t1", "t2", "y"])
+    W1r = relabel(W1, ["w1", "s1", "t1", "w2"])
+    W2r = relabel(W2, ["w2", "s2", "t2", "w3"])
+    Rr = relabel(R, ["b", "w3", "y"])
+    f = []
+    T1 = BlockTensor(*_contract_meta(Lr, Pr)); f.append(_contract_flops(Lr, Pr))
+    T2 = BlockTensor(*_contract_meta(T1, W1r)); f.append(_contract_flops(T1, W1r))
+    T3 = BlockTensor(*_contract_meta(T2, W2r)); f.append(_contract_flops(T2, W2r))
+    f.append(_contract_flops(T3, Rr))
+    return f
+
+
+def _contract_meta(A, B):
+    common = [l for l in A.labels if l in B.labels]
+    af = [i for i, l in enumerate(A.labels) if l not in common]
+    bf = [j for j, l in enumerate(B.labels) if l not in common]
+    return ([A.labels[i] for i in af] + [B.labels[j] for j in bf],
+            [A.legs[i] for i in af] + [B.legs[j] for j in bf])
+
+
+def _contract_flops(A, B) -> int:
+    common = [l for l in A.labels if l in B.labels]
+    ac = [A.labels.index(l) for l in common]
+    bc = [B.labels.index(l) for l in common]
+    bf = [j for j in range(B.rank) if j not in bc]
+    by_kc: Dict[Tuple[int, ...], List[int]] = {}
+    for b, t in enumerate(B.blocks):
+        by_kc.setdefault(tuple(t[j] for j in bc), []).append(b)
+    total = 0
+    for a, ta in enumerate(A.blocks):
+        size_a = int(np.prod(A.shapes[a]))
+        for b in by_kc.get(tuple(ta[i] for i in ac), []):
+            n = int(np.prod([B.shapes[b][j] for j in bf])) if bf else 1
+            total += 2 * size_a * n
+    return total
+
+
+# --------------------------------------------------------------------------
+# Lanczos (Sec. "Eigenvalue decomposition": lowest eigenpair of a Hermitian
+# LinOp).  Textbook Lanczos with CGS2 full reorthogonalisation.
+# --------------------------------------------------------------------------
+def sturm_count(alpha: np.ndarray, beta: np.ndarray, x: float) -> int:
+    """Number of eigenvalues of the symmetric tridiagonal (alpha, beta) below x
+    (negative pivots of the LDL^T factorisation of T - x I)."""
+    count = 0
+    d = 1.0
+    tiny = np.finfo(np.float64).tiny
+    for i in range(len(alpha)):
+        b2 = beta[i - 1] ** 2 if i > 0 else 0.0
+        d = (alpha[i] - x) - b2 / d
+        if d == 0.0:
+            d = -tiny
+        if d < 0.0:
+            count += 1
+    return count
+
+
+def tridiag_lowest(alpha: Sequence[float], beta: Sequence[float]):
+    """Lowest eigenpair of the symmetric tridiagonal matrix with diagonal alpha
+    and off-diagonal beta: Sturm bisection to full precision for the value,
+    inverse iteration for the vector (largest component made positive)."""
+    a = np.asarray(alpha, dtype=np.float64)
+    b = np.asarray(beta, dtype=np.float64)
+    n = len(a)
+    if n == 1:
+        return float(a[0]), np.ones(1)
+    radius = np.zeros(n)
+    radius[:-1] += np.abs(b)
+    radius[1:] += np.abs(b)
+    lo = float(np.min(a - radius))
+    hi = float(np.max(a + radius))
+    for _ in range(2000):
+        mid = 0.5 * (lo + hi)
+        if mid <= lo or mid >= hi:
+            break
+        if sturm_count(a, b, mid) >= 1:
+            hi = mid
+        else:
+            lo = mid
+    theta = hi
+    # inverse iteration on T - theta I with a tridiagonal LU (partial pivoting)
+    shift = theta - 4.0 * np.finfo(np.float64).eps * max(1.0, abs(theta))
+    s = np.ones(n) / math.sqrt(n)
+    T = np.diag(a - shift) + np.diag(b, 1) + np.diag(b, -1)
+    for _ in range(3):
+        s = np.linalg.solve(T, s)
+        s /= np.linalg.norm(s)
+    if s[np.argmax(np.abs(s))] < 0:
+        s = -s
+    return theta, s
+
+
+def lanczos_ground(matvec: Callable[[np.ndarray], np.ndarray], psi0: np.ndarray, nsteps: int,
+                   refine_matvec: Callable[[np.ndarray], np.ndarray] | None = None,
+                   breakdown: float = 1e-12):
+    """Lowest eigenpair of a symmetric operator by nsteps Lanczos steps.
+
+    v1 = psi0/|psi0|; for each j: w = H v_j; c = V^T w; w -= V c; d = V^T w;
+    w -= V d; alpha_j = c_j + d_j; beta_j = |w|; stop if beta_j is below
+    breakdown * max(|alpha|, beta_j); v_{j+1} = w / beta_j.  The Ritz pair
+    (theta, y = V s) comes from the tridiagonal (alpha, beta); the refined
+    energy is the Rayleigh quotient y.Hy / y.y with one more (FP64) apply.
+    """
+    x = np.asarray(psi0, dtype=np.float64)
+    n = x.size
+    V = np.empty((nsteps, n))
+    V[0] = x / np.linalg.norm(x)
+    alpha: List[float] = []
+    beta: List[float] = []
+    for j in range(nsteps):
+        w = matvec(V[j])
+        Vj = V[:j + 1]
+        c = Vj @ w
+        w = w - Vj.T @ c
+        d = Vj @ w
+        w = w - Vj.T @ d
+        alpha.append(float(c[j] + d[j]))
+        bj = float(np.linalg.norm(w))
+        if bj <= breakdown * max(max(abs(v) for v in alpha), bj):
+            break
+        if j + 1 == nsteps:
+            beta.append(bj)
+            break
+        beta.append(bj)
+        V[j + 1] = w / bj
+    m = len(alpha)
+    theta, s = tridiag_lowest(alpha, beta[:m - 1])
+    y = s @ V[:m]
+    hm = refine_matvec if refine_matvec is not None else matvec
+    hy = hm(y)
+    yy = float(y @ y)
+    E = float(y @ hy) / yy
+    resid = float(np.linalg.norm(hy - E * y))
+    return dict(theta=theta, energy=E, y=y, residual=resid, alpha=np.array(alpha),
+                beta=np.array(beta), steps=m, V=V[:m])
+
+
+# --------------------------------------------------------------------------
+# Exact diagonalisation of open Heisenberg chains (dense, Kronecker products)
+# --------------------------------------------------------------------------
+def _spin_ops(spin: str):
+    if spin == "1/2":
+        sp = np.array([[0.0, 1.0], [0.0, 0.0]])
+        sz = np.diag([0.5, -0.5])
+        q = np.array([1, -1])
+    elif spin == "1":
+        sp = np.sqrt(2.0) * np.array([[0.0, 1.0, 0.0], [0.0, 0.0, 1.0], [0.0, 0.0, 0.0]])
+        sz = np.diag([1.0, 0.0, -1.0])
+        q = np.array([1, 0, -1])
+    else:
+        raise ValueError(spin)
+    return sp, sp.T, sz, q
+
+
+def heisenberg_chain_hamiltonian(nsites: int, spin: str, J: float = 1.0) -> np.ndarray:
+    """H = J sum_i S_i.S_{i+1} (open chain), dense, basis highest Sz first."""
+    sp, sm, sz, _ = _spin_ops(spin)
+    d = sp.shape[0]
+    H = np.zeros((d ** nsites, d ** nsites))
+    for i in range(nsites - 1):
+        left = np.eye(d ** i)
+        right = np.eye(d ** (nsites - i - 2))
+        bond = 0.5 * J * (np.kron(sp, sm) + np.kron(sm, sp)) + J * np.kron(sz, sz)
+        H += np.kron(np.kron(left, bond), right)
+    return H
+
+
+def heisenberg_chain_ground(nsites: int, spin: str, J: float = 1.0, charge: int | None = 0) -> float:
+    """Lowest eigenvalue, optionally restricted to one total-charge sector."""
+    H = heisenberg_chain_hamiltonian(nsites, spin, J)
+    if charge is not None:
+        _, _, _, q = _spin_ops(spin)
+        tot = np.zeros(1, dtype=int)
+        for _ in range(nsites):
+            tot = (tot[:, None] + q[None, :]).ravel()
+        keep = np.nonzero(tot == charge)[0]
+        H = H[np.ix_(keep, keep)]
+    return float(np.linalg.eigvalsh(H)[0])
