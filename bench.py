@@ -1,0 +1,246 @@
+"""Benchmark: Lanczos ground state of the two-site H_eff on one MI355X.
+
+One step = one 40-step Lanczos solve of the spin-1 Heisenberg two-site
+H_eff at chi = 4096 (41 charge sectors, 4,589,718 psi elements): 40 H_eff.psi
+applies in a reduced-precision MFMA form, CGS2 reorthogonalisation,
+tridiagonal eigensolve and one float64 apply for the refined energy.  Inputs
+are resident on the GPU before timing starts.  The same solve in plain
+float64 is timed beside it, and the refined energies of both are compared.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec bf16x6]
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "H_eff·psi GFLOP/s & % MFMA peak, split-prec vs FP64 at 1e-10 energy err"
+PEAK = {  # MI355X published dense peaks
+    "hbm_gbs": 8000.0,
+    "fp64_tflops": 78.6,
+    "fp32_tflops": 157.3,
+    "bf16_tflops": 2516.6,
+}
+WORKLOAD = 5
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--prec", default="bf16x6", choices=["fp32", "bf16x3", "bf16x6", "fp64"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    return ap.parse_args()
+
+
+def lanczos_vector_flops(n: int, m: int) -> float:
+    """Algorithmic flops of CGS2 reorthogonalisation, normalisation and Ritz
+    vector for m steps on vectors of n elements."""
+    f = 0.0
+    for j in range(1, m + 1):
+        f += 4 * 2.0 * n * j      # two passes of V^T w and w -= V c
+        f += 2.0 * n + n          # |w|^2 and scaling
+    return f + 2.0 * n * m + 6.0 * n
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU; multi-GPU runs are not part "
+                                   "of this build (the path would shard by left charge sector)",
+                          "n_gpus": a.gpus}))
+        sys.exit(2)
+    import torch
+    from paper_2401_01921_amd import bst, workloads as wl
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    dev = "cuda"
+    w = wl.WORKLOADS[WORKLOAD]
+    v = wl.gaussian_sector_dims(w["chi"], w["qmax"])
+    specs = wl.heff_specs(w["spin"], v, v)
+    T = {k: bst.Tensor(*s) for k, s in specs.items()}
+    plan = bst.heff_plan(T["L"], T["W1"], T["W2"], T["R"], T["psi"], "fp64")
+    n = T["psi"].numel
+    m = w["steps"]
+    host = {
+        "L": wl.dmrg_like_env(T["L"].table(), T["L"].numel, wl.seed_for(WORKLOAD, "L"), "L", v),
+        "R": wl.dmrg_like_env(T["R"].table(), T["R"].numel, wl.seed_for(WORKLOAD, "R"), "R", v),
+        "W1": T["W1"].from_dense(wl.heisenberg_mpo_dense(w["spin"])),
+        "psi0": wl.normal(wl.seed_for(WORKLOAD, "psi0"), n),
+    }
+    host["W2"] = host["W1"]
+    g = {k: torch.from_numpy(x).to(dev) for k, x in host.items()}
+    ops = [g["L"], g["W1"], g["W2"], g["R"]]
+    ws = bst.workspace(bst.lanczos_workspace(plan, m))
+    psi_out = torch.empty(n, dtype=torch.float64, device=dev)
+    apply_flops = plan.stats().flops
+    step_flops = (m + 1) * apply_flops + lanczos_vector_flops(n, m)
+
+    def solve(prec, timing=False):
+        return bst.lanczos_ground(plan, ops, g["psi0"], m, prec, True, ws=ws, psi_out=psi_out,
+                                  timing=timing)
+
+    def timed(prec, steps, warmup):
+        for _ in range(warmup):
+            solve(prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = None
+        for _ in range(steps):
+            res = solve(prec)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps, res
+
+    # ---- timed region: the split-precision solve --------------------------
+    ms_split, res_split = timed(a.prec, a.steps, a.warmup)
+    # plain float64 solve on the same inputs
+    ms64, res64 = timed("fp64", max(2, a.steps // 2), 1)
+    # per-kernel HIP-event times of one solve of each form
+    prof_split = solve(a.prec, timing=True)
+    prof64 = solve("fp64", timing=True)
+
+    e64, es = res64["energy"], res_split["energy"]
+    err = abs(es - e64) / abs(e64)
+
+    # ---- roofline of the kernels (algorithmic work / HIP-event time) ------
+    steps = {s["name"]: s for s in plan.steps()}
+    inter32 = a.prec != "fp64"
+    km, kc = prof_split["kernel_ms"], prof_split["kernel_calls"]
+    mf = {"fp64": 1, "fp32": 1, "bf16x3": 3, "bf16x6": 6}[a.prec]
+    peak_mm = {"fp64": PEAK["fp64_tflops"], "fp32": PEAK["fp32_tflops"]}.get(a.prec, PEAK["bf16_tflops"])
+
+    def gemm_roof(name, ms_key, prof, prec, peak):
+        calls = prof["kernel_calls"][ms_key]
+        avg_ms = prof["kernel_ms"][ms_key] / max(calls, 1)
+        fl = steps[name]["flops"]
+        mult = {"fp64": 1, "fp32": 1, "bf16x3": 3, "bf16x6": 6}[prec]
+        return dict(kernel=name, avg_ms=avg_ms, alg_tflops=fl / avg_ms / 1e9,
+                    mfma_tflops=fl * mult / avg_ms / 1e9, peak_tflops=peak,
+                    mfma_frac=fl * mult / avg_ms / 1e9 / peak,
+                    bytes_gbs=(steps[name]["bytes_fp32" if prec != "fp64" else "bytes_fp64"])
+                    / avg_ms / 1e6)
+
+    def cgs_bytes(pass_id):
+        # algorithmic bytes of one solve's pass (V rows read, w read/written)
+        tot = 0.0
+        for j in range(1, m + 1):
+            if pass_id == 1:
+                tot += 8.0 * n * (j + 1)
+            else:
+                tot += 8.0 * n * (j + 2)
+        return tot
+
+    def hbm_roof(key, total_bytes, prof):
+        ms = prof["kernel_ms"][key]
+        calls = prof["kernel_calls"][key]
+        return dict(kernel=key, avg_ms=ms / max(calls, 1), calls=calls,
+                    achieved_gbs=total_bytes / ms / 1e6, frac=total_bytes / ms / 1e6 / PEAK["hbm_gbs"])
+
+    mpo_bytes = steps["mpo_apply"]["bytes_fp32" if inter32 else "bytes_fp64"]
+    kern = {
+        "gemm_L_psi": gemm_roof("gemm_L_psi", "gemm_L_psi", prof_split, a.prec, peak_mm),
+        "gemm_T3_R": gemm_roof("gemm_T3_R", "gemm_T3_R", prof_split, a.prec, peak_mm),
+        "mpo_apply": hbm_roof("mpo_apply", mpo_bytes * kc["mpo_apply"], prof_split),
+        "cgs_pass1": hbm_roof("cgs_pass1", cgs_bytes(1), prof_split),
+        "cgs_pass2": hbm_roof("cgs_pass2", cgs_bytes(2), prof_split),
+        "cgs_pass3": hbm_roof("cgs_pass3", cgs_bytes(3), prof_split),
+        "fp64_gemm_L_psi": gemm_roof("gemm_L_psi", "gemm_L_psi", prof64, "fp64", PEAK["fp64_tflops"]),
+        "fp64_gemm_T3_R": gemm_roof("gemm_T3_R", "gemm_T3_R", prof64, "fp64", PEAK["fp64_tflops"]),
+    }
+    # dominant kernel of the step = largest summed time
+    sums = {k: km[k] for k in km}
+    dom = max(sums, key=sums.get)
+    if dom.startswith("gemm"):
+        r = kern[dom]
+        roof = {"bound": "mfma", "kernel": dom, "achieved": round(r["mfma_tflops"], 2),
+                "peak": peak_mm, "unit": "TFLOP/s", "frac": round(r["mfma_frac"], 4), "traffic": None}
+    else:
+        r = kern[dom]
+        per_launch = r["achieved_gbs"] * r["avg_ms"] * 1e6
+        roof = {"bound": "hbm", "kernel": dom, "achieved": round(r["achieved_gbs"], 1),
+                "peak": PEAK["hbm_gbs"], "unit": "GB/s", "frac": round(r["frac"], 4),
+                "traffic": None, "alg_bytes_per_launch": per_launch}
+
+    # ---- CPU baseline: the oracle's H_eff apply on the host cores ----------
+    cpu = None
+    if not a.no_cpu:
+        cpu = cpu_baseline(specs, host, apply_flops, a.cpu_seconds)
+
+    out = {
+        "metric": METRIC,
+        "value": round(step_flops / ms_split / 1e9, 1),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(ms_split * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"bf16x3": "bf16x3(f32 acc)+f64", "bf16x6": "bf16x6(f32 acc)+f64",
+                  "fp32": "f32+f64", "fp64": "f64"}[a.prec],
+        "data": "synthetic",
+        "config": {"workload": w["name"], "chi": w["chi"], "sectors": len(v), "spin": w["spin"],
+                   "psi_elements": n, "lanczos_steps": m, "matvec": a.prec, "refine": "fp64",
+                   "flops_per_step": step_flops, "heff_flops_per_apply": apply_flops},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "fp64_ms_per_step": round(ms64 * 1e3, 3),
+        "speedup_vs_fp64": round(ms64 / ms_split, 3),
+        "energy": {"split": es, "fp64": e64, "rel_err_vs_fp64": err,
+                   "theta_rel_err": abs(res_split["theta"] - res64["theta"]) / abs(e64),
+                   "residual_split": res_split["residual"], "residual_fp64": res64["residual"],
+                   "meets_1e-10": bool(err <= 1e-10)},
+        "kernels_split": {k: round(v, 4) for k, v in km.items()},
+        "kernels_fp64": {k: round(v, 4) for k, v in prof64["kernel_ms"].items()},
+        "kernel_roofline": kern,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(specs, host, apply_flops, seconds):
+    """The float64 oracle's H_eff apply on this host (numpy; BLAS threads as
+    configured), repeated for about `seconds`."""
+    from oracle import oracle as orc
+    O = {k: orc.BlockTensor(*specs[k]) for k in ("L", "R", "psi")}
+    O["L"].data[:] = host["L"]
+    O["R"].data[:] = host["R"]
+    O["psi"].data[:] = host["psi0"]
+    W1 = orc.BlockTensor(*specs["W1"], host["W1"])
+    W2 = orc.BlockTensor(*specs["W2"], host["W2"])
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        orc.heff_apply(O["L"], W1, W2, O["R"], O["psi"])
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= seconds or reps >= 20:
+            break
+    threads = None
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max((i.get("num_threads") or 0) for i in threadpool_info()) or None
+    except Exception:
+        pass
+    if threads is None:
+        threads = len(os.sched_getaffinity(0))
+    return {"value": round(apply_flops * reps / el / 1e9, 2), "unit": "GFLOP/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{reps} float64 H_eff.psi applies of the chi=4096 spin-1 workload "
+                      f"({el:.1f} s, numpy oracle)"}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,273 @@
+/*
+ * bst.h -- C ABI of the MI355X block-sparse U(1) tensor library.
+ *
+ * The library implements the hot path of the tensor-network method of
+ * arXiv:2401.01921 ("The Cytnx Library for Tensor Networks"): contraction of
+ * Abelian (U(1) charge-conserving) block-sparse tensors -- charge-sector
+ * matching, leg permutation and per-sector GEMMs -- and its use in the DMRG
+ * two-site effective-Hamiltonian product H_eff.psi = L.psi.W.W.R inside a
+ * Lanczos ground-state solver (Sec. "Benchmarks", Fig. Hpsi_fig; Sec.
+ * "Eigenvalue decomposition", LinOp/Lanczos).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Leg (bond): a direction (+1 incoming, -1 outgoing), and a list of sectors,
+ *   each an integer U(1) charge q and a dimension g >= 1 (Sec. "Bond with
+ *   quantum numbers").  Charges on one leg need not be distinct.
+ * Valid block: a tuple of sector indices (one per leg) whose flux, the sum of
+ *   the incoming charges minus the sum of the outgoing charges, is zero
+ *   (Sec. "UniTensor with Symmetries").  Only valid blocks are stored.
+ * Block order: lexicographic in the sector indices with leg 0 most
+ *   significant (the order of the block list printed for the rank-3 example
+ *   of Sec. "Symmetric UniTensor").
+ * Data layout: one flat buffer per tensor holding the valid blocks one after
+ *   another in block order, each block a dense row-major array (Sec.
+ *   "Tensor", App. "Contiguous").  Element type float64 at the boundary.
+ * Labels: every leg has a label, unique within its tensor (Sec. "Viewing/
+ *   Changing labels"); contraction sums over the labels two tensors share
+ *   (Sec. "Tensor contraction").
+ *
+ * Memory and ownership
+ * --------------------
+ * Tensor descriptors and plans are host objects owned by the library and
+ * released with bst_tensor_destroy / bst_plan_destroy.  All numeric buffers
+ * (inputs, outputs, workspace) are device pointers owned by the caller; the
+ * library never allocates, frees or retains device memory.  Plan tables are
+ * uploaded into the caller's workspace on the first execute with that
+ * workspace.  Work is enqueued on the caller's HIP stream (passed as void*).
+ *
+ * Errors
+ * ------
+ * Every call returns a bst_status; on failure bst_last_error() returns a
+ * message (thread-local, valid until the next call on the same thread).
+ * No C++ exception crosses the ABI.  Faults of asynchronously enqueued
+ * kernels surface on a later call as BST_E_DEVICE.
+ */
+#ifndef BST_H
+#define BST_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  BST_OK = 0,
+  BST_E_INVALID = 1,   /* bad argument: null pointer, dim < 1, bad rank, size */
+  BST_E_DIRECTION = 2, /* contracted legs with the same direction (Sec. "Bond")  */
+  BST_E_QNUM = 3,      /* contracted legs with different charge lists            */
+  BST_E_DIM = 4,       /* contracted legs with different sector dims             */
+  BST_E_LABEL = 5,     /* duplicate or unknown label                            */
+  BST_E_NOBLOCK = 6,   /* sector tuple is not a valid block (Sec. "Accessing
+                          elements of a symmetric tensor")                     */
+  BST_E_STRUCTURE = 7, /* operands whose block structures do not fit the op    */
+  BST_E_DEVICE = 8,    /* HIP runtime error                                    */
+  BST_E_NOTCONV = 9    /* Lanczos produced no usable step                      */
+} bst_status;
+
+/* Arithmetic form of the per-sector products.  Inputs and outputs stay
+ * float64; the form decides what the MFMA units compute:
+ *   BST_FP64   float64 operands, float64 accumulate;
+ *   BST_FP32   operands rounded to float32 (nearest-even), float32 accumulate;
+ *   BST_BF16X3 each operand split a = a0 + a1 into bfloat16 (nearest-even,
+ *              a1 = bf16(a - a0)); a0b0 + a0b1 + a1b0 accumulated in float32;
+ *   BST_BF16X6 three-term split a0 + a1 + a2 and the six products whose
+ *              plane orders add up to at most 2, accumulated in float32.
+ * Intermediates of H_eff are float64 in BST_FP64 and float32 otherwise. */
+typedef enum { BST_FP64 = 0, BST_FP32 = 1, BST_BF16X3 = 2, BST_BF16X6 = 3 } bst_precision;
+
+typedef struct bst_tensor bst_tensor;
+typedef struct bst_plan bst_plan;
+
+/* ---- tensors (host metadata only) ------------------------------------ */
+
+/* Builds the descriptor of a block-sparse tensor (Sec. "Bond with quantum
+ * numbers", Sec. "Creating a symmetric UniTensor").
+ *   rank     number of legs, 0..8
+ *   dir      [rank] +1 (incoming) or -1 (outgoing)
+ *   nsec     [rank] number of sectors of each leg, >= 1
+ *   qn       [sum nsec] charges, leg by leg
+ *   dim      [sum nsec] sector dims, leg by leg, each >= 1
+ *   labels   [rank] NUL-terminated labels, unique
+ *   out      receives the descriptor
+ * A tensor with no valid block is legal (numel 0).  Errors: BST_E_INVALID,
+ * BST_E_LABEL. */
+bst_status bst_tensor_create(int32_t rank, const int32_t* dir, const int32_t* nsec,
+                             const int32_t* qn, const int64_t* dim,
+                             const char* const* labels, bst_tensor** out);
+bst_status bst_tensor_destroy(bst_tensor* t);
+
+/* Rank, number of valid blocks and total element count. */
+bst_status bst_tensor_info(const bst_tensor* t, int32_t* rank, int64_t* nblocks, int64_t* numel);
+
+/* Leg description: direction, sector count, and (if the arrays are non-null)
+ * the charges and dims, and the label copied into a buffer of label_cap
+ * bytes.  Error BST_E_INVALID for a bad leg index or a short buffer. */
+bst_status bst_tensor_leg(const bst_tensor* t, int32_t leg, int32_t* dir, int32_t* nsec,
+                          int32_t* qn, int64_t* dim, char* label, size_t label_cap);
+
+/* Block b (0-based, canonical order): sector indices [rank], shape [rank]
+ * and element offset into the flat buffer.  Any output pointer may be null.
+ * Error BST_E_INVALID for b out of range. */
+bst_status bst_tensor_block(const bst_tensor* t, int64_t b, int32_t* qn_idx, int64_t* shape,
+                            int64_t* offset);
+
+/* Block number of the sector tuple qn_idx [rank]; BST_E_NOBLOCK if the tuple
+ * has nonzero flux (Sec. "Accessing elements of a symmetric tensor"). */
+bst_status bst_tensor_find_block(const bst_tensor* t, const int32_t* qn_idx, int64_t* b);
+
+/* ---- plans ------------------------------------------------------------ */
+
+/* Permute (Sec. "Permute", App. "Contiguous"): new leg i is the old leg
+ * labelled new_order[i]; every block is transposed accordingly and the
+ * blocks are stored in the canonical order of the new leg order.
+ *   in         input descriptor
+ *   new_order  [rank] labels
+ *   out_meta   receives the output descriptor (caller destroys)
+ *   plan       receives the plan; execute with in = {X}, out = {Y}.
+ * Errors: BST_E_LABEL. */
+bst_status bst_permute_plan(const bst_tensor* in, const char* const* new_order,
+                            bst_tensor** out_meta, bst_plan** plan);
+
+/* Contract A and B over all labels they share (Sec. "Tensor contraction").
+ * Each shared leg must have opposite directions (BST_E_DIRECTION) and the
+ * same charge list (BST_E_QNUM) and dims (BST_E_DIM) in the same order.  The
+ * result has A's free legs in A's order followed by B's free legs in B's
+ * order and holds every valid block (zero where nothing contributes).
+ * Execute with in = {A, B}, out = {C}. */
+bst_status bst_contract_plan(const bst_tensor* A, const bst_tensor* B, bst_precision prec,
+                             bst_tensor** C_meta, bst_plan** plan);
+
+/* Two-site effective Hamiltonian (Sec. "Benchmarks", Fig. Hpsi_fig):
+ *   out[a,s1,s2,b] = sum L[a,w1,a'] W1[w1,s1,t1,w2] W2[w2,s2,t2,w3]
+ *                        R[b,w3,b'] psi[a',t1,t2,b']
+ * contracted in the order L -> psi -> W1 -> W2 -> R.  Leg order of the
+ * operands: L[a, w, a'], W[w_left, s_ket, s_bra, w_right], R[b, w, b'],
+ * psi[a, s1, s2, b].  The pairs (L.a', psi.a), (L.w, W1.w_left),
+ * (W1.s_bra, psi.s1), (W1.w_right, W2.w_left), (W2.s_bra, psi.s2),
+ * (W2.w_right, R.w), (R.b', psi.b) must be contractible; L.a, W1.s_ket,
+ * W2.s_ket and R.b must equal psi's legs, so out has psi's block table.
+ * Execute with in = {L, W1, W2, R, psi}, out = {out}. */
+bst_status bst_heff_plan(const bst_tensor* L, const bst_tensor* W1, const bst_tensor* W2,
+                         const bst_tensor* R, const bst_tensor* psi, bst_precision prec,
+                         bst_plan** plan);
+
+/* Merges n H_eff plans into one: each step of all n applies runs as one
+ * grouped launch.  Execute with in = {L_0, W1_0, W2_0, R_0, psi_0, L_1, ...}
+ * (5n pointers) and out = {out_0, ..., out_{n-1}}.  The sub-plans stay owned
+ * by the caller and may be destroyed after this call. */
+bst_status bst_heff_batch_plan(int32_t n, const bst_plan* const* plans, bst_plan** batch);
+
+/* Device workspace the plan needs (bytes, 256-byte aligned pointer). */
+bst_status bst_plan_workspace(const bst_plan* p, size_t* bytes);
+
+/* Algorithmic work of one execute: flops (2mnk over valid block products,
+ * all steps) and the number of GEMM problems and tiles of the main steps. */
+typedef struct {
+  double flops;
+  double gemm_flops;
+  double bytes;          /* algorithmic HBM bytes at float64 storage          */
+  int64_t gemm_problems;
+  int64_t gemm_tiles;
+  int64_t launches;      /* kernels enqueued per execute                      */
+  int32_t nsteps;        /* steps (kernel launches) of one execute            */
+} bst_plan_stats;
+bst_status bst_plan_info(const bst_plan* p, bst_plan_stats* st);
+
+/* One step (one kernel launch) of a plan: its name, algorithmic flops, and
+ * algorithmic HBM bytes (each operand read once, each result written once)
+ * with float64 intermediates and with float32 intermediates. */
+typedef struct {
+  char name[32];
+  double flops;
+  double bytes_fp64;
+  double bytes_fp32;
+  int64_t items;         /* tiles / work items of the launch                   */
+} bst_step_info;
+bst_status bst_plan_step_info(const bst_plan* p, int32_t step, bst_step_info* info);
+
+/* Overrides the arithmetic form of an H_eff (or contract) plan. */
+bst_status bst_plan_set_precision(bst_plan* p, bst_precision prec);
+
+/* Record the plan's kernels in a hipGraph on the next execute and replay the
+ * graph afterwards (on = 1), or launch kernels directly (on = 0). */
+bst_status bst_plan_use_graph(bst_plan* p, int32_t on);
+
+/* Enqueues the plan on stream (a hipStream_t, or null for the default
+ * stream).  in / out are device pointers to float64 data in canonical
+ * layout; ws points to bst_plan_workspace() bytes of device memory that no
+ * other concurrent execute uses.  Returns after enqueueing. */
+bst_status bst_execute(bst_plan* p, const void* const* in, void* const* out, void* ws,
+                       void* stream);
+
+/* Times every compiled tile shape of each GEMM step on the given buffers,
+ * keeps the fastest per step and (if the environment variable BST_TUNE_CACHE
+ * names a file) records the choice there.  Synchronises the stream. */
+bst_status bst_plan_autotune(bst_plan* p, const void* const* in, void* const* out, void* ws,
+                             void* stream, int32_t reps);
+
+/* Tile shapes chosen for the plan's GEMM steps, as text ("step:BMxBN;...")
+ * written into buf (NUL-terminated, truncated to cap). */
+bst_status bst_plan_tiles(const bst_plan* p, char* buf, size_t cap);
+
+/* Per-step kernel times (ms) of the last bst_plan_profile call. */
+bst_status bst_plan_profile(bst_plan* p, const void* const* in, void* const* out, void* ws,
+                            void* stream, int32_t reps, double* step_ms, int32_t cap,
+                            int32_t* nsteps);
+
+bst_status bst_plan_destroy(bst_plan* p);
+
+/* ---- Lanczos ground state (Sec. "Eigenvalue decomposition") ----------- */
+
+typedef struct {
+  int32_t flags;        /* in: BST_LANCZOS_TIMING records HIP events around
+                           every kernel and fills kernel_ms / kernel_calls    */
+  int32_t steps;        /* Lanczos steps kept (<= nsteps; fewer on breakdown) */
+  double theta;         /* lowest Ritz value of the tridiagonal matrix        */
+  double beta_min;      /* smallest off-diagonal beta of the kept steps       */
+  double residual;      /* |H y - E y| with the float64 operator, |y| = 1     */
+  double alpha[128];    /* diagonal of the tridiagonal matrix (first 128)     */
+  double beta[128];     /* off-diagonal (first 128)                           */
+  /* Summed kernel time (ms) and launch count per kernel class, with
+   * BST_LANCZOS_TIMING: 0 L.psi GEMM, 1 MPO apply, 2 T3.R GEMM, 3 MPO
+   * coefficients, 4 Gram-Schmidt pass 1 (V^T w), 5 pass 2 (w -= V c and
+   * V^T w), 6 pass 3 (w -= V d and |w|^2), 7 other vector kernels.        */
+  double kernel_ms[8];
+  int32_t kernel_calls[8];
+} bst_lanczos_info;
+#define BST_LANCZOS_TIMING 1
+
+/* Workspace of bst_lanczos_ground for a plan and step count. */
+bst_status bst_lanczos_workspace(const bst_plan* heff, int32_t nsteps, size_t* bytes);
+
+/* Lowest eigenpair of the H_eff of `heff` (a bst_heff_plan), which must be
+ * symmetric.  Textbook Lanczos: v1 = psi0/|psi0|; per step w = H v_j in the
+ * form `matvec_prec`, two passes of classical Gram-Schmidt against all
+ * previous vectors in float64, alpha_j, beta_j = |w|, v_{j+1} = w/beta_j;
+ * the steps stop at the first beta_j <= 1e-12 max(|alpha|, beta_j).  The
+ * float64 tridiagonal eigensolve (Sturm bisection, inverse iteration) gives
+ * the Ritz pair (theta, y = V s).  With refine != 0, one float64 apply gives
+ * E = y.Hy / y.y; otherwise E = theta.
+ *   ops        {L, W1, W2, R} device pointers (float64, canonical layout)
+ *   psi0       device pointer, start vector (psi's layout)
+ *   psi_out    device pointer, receives y / |y| (may alias nothing else)
+ *   energy     receives E
+ *   info       may be null; info->flags is read on entry
+ * Blocks until the result is on the host.  BST_E_NOTCONV if psi0 is zero. */
+bst_status bst_lanczos_ground(bst_plan* heff, const void* const* ops, const void* psi0,
+                              int32_t nsteps, bst_precision matvec_prec, int32_t refine,
+                              void* psi_out, double* energy, bst_lanczos_info* info, void* ws,
+                              void* stream);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* bst_last_error(void);
+
+/* Library version string. */
+const char* bst_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BST_H */

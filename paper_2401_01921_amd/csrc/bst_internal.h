@@ -1,0 +1,219 @@
+// Internal types of the block-sparse library: host descriptors, plan tables
+// and the device-side records the kernels read.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/bst.h"
+
+namespace bst {
+
+// ------------------------------------------------------------------------
+// Errors
+// ------------------------------------------------------------------------
+struct Error {
+  bst_status status;
+  std::string msg;
+};
+[[noreturn]] void fail(bst_status s, const std::string& msg);
+void check_hip(hipError_t e, const char* what);
+
+// ------------------------------------------------------------------------
+// Tensor descriptor (host only)
+// ------------------------------------------------------------------------
+struct LegDesc {
+  int32_t dir = 1;
+  std::vector<int32_t> q;
+  std::vector<int64_t> g;
+  std::string label;
+  int64_t total() const {
+    int64_t s = 0;
+    for (auto v : g) s += v;
+    return s;
+  }
+  bool same_sectors(const LegDesc& o) const { return q == o.q && g == o.g; }
+};
+
+struct TensorDesc {
+  std::vector<LegDesc> legs;
+  int64_t nblocks = 0;
+  int64_t numel = 0;
+  std::vector<int32_t> qn;      // nblocks * rank sector indices
+  std::vector<int64_t> shape;   // nblocks * rank
+  std::vector<int64_t> offset;  // nblocks
+  std::unordered_map<std::string, int64_t> lookup;
+
+  int rank() const { return (int)legs.size(); }
+  // Enumerates the valid blocks in canonical order (called once by create).
+  void build();
+  // Block index of a sector tuple, -1 if it is not a valid block.
+  int64_t find(const int32_t* t) const;
+  const int32_t* block_qn(int64_t b) const { return qn.data() + b * rank(); }
+  const int64_t* block_shape(int64_t b) const { return shape.data() + b * rank(); }
+  int64_t block_size(int64_t b) const {
+    int64_t n = 1;
+    for (int i = 0; i < rank(); ++i) n *= block_shape(b)[i];
+    return n;
+  }
+  int label_index(const std::string& l) const;
+};
+
+std::unique_ptr<TensorDesc> make_tensor(std::vector<LegDesc> legs);
+
+// ------------------------------------------------------------------------
+// Device records
+// ------------------------------------------------------------------------
+// One K-segment of a grouped-GEMM problem.  A is [M x K] row-major with
+// leading dim lda; B is [K x N] (ldb) or, for transposed-B steps, [N x K].
+struct GemmSeg {
+  int64_t a_off, b_off;
+  int32_t a_buf, b_buf;
+  int32_t K, lda, ldb, pad;
+};
+// One output block: C[M x N] row-major (ldc) = sum over its segments.
+struct GemmProb {
+  int64_t c_off;
+  int32_t c_buf, M, N, ldc;
+  int32_t seg_begin, seg_count;
+};
+struct GemmTile {
+  int32_t prob, m0, n0, pad;
+};
+
+// Block permute job: one block, row-major input shape and, per input dim,
+// the stride of that dim in the output block.
+constexpr int kMaxRank = 8;
+struct PermJob {
+  int64_t in_off, out_off;
+  int32_t in_buf, out_buf;
+  int32_t rank;
+  int32_t pdim;       // input dim that is fastest in the output (tile jobs)
+  int32_t shape[kMaxRank];
+  int64_t istride[kMaxRank];
+  int64_t ostride[kMaxRank];
+};
+// A work item of the permute kernels: a tile (transposing jobs) or a row
+// range (jobs that keep the fastest dim).
+struct PermWork {
+  int32_t job;
+  int32_t kind;       // 0: rows, 1: tile
+  int64_t batch;      // rows: first row; tile: linear index over batch dims
+  int32_t t0, t1;     // tile origin along (p, last) or row count
+};
+
+// MPO (two-site h) apply: one (a-sector, b'-sector) pair of T1 / T3.
+struct HTask {
+  int32_t rows, cols;        // g_a, g_b'
+  int32_t cls;               // coefficient class
+  int32_t nin, nout;
+  int32_t plane_begin;       // nin input planes then nout output planes
+  int32_t in_buf, out_buf;
+};
+struct HPlane {
+  int64_t off;               // element offset of (row 0, col 0)
+  int64_t rowstride;
+};
+struct HWork {
+  int32_t task;
+  int32_t site0;
+};
+// coef[cls][o][i] = sum of W1[w1] * W2[w2] over the entry's terms.
+struct HTerm {
+  int32_t w1_buf, w2_buf;
+  int64_t w1_off, w2_off;
+};
+
+// ------------------------------------------------------------------------
+// Kernel launchers (kernels_*.hip)
+// ------------------------------------------------------------------------
+enum class ElemType : int { F64 = 0, F32 = 1 };
+
+struct TileShape {
+  int bm, bn;
+};
+// Tile shapes compiled for each arithmetic form.
+const std::vector<TileShape>& gemm_tile_shapes(bst_precision form);
+
+struct GemmLaunch {
+  bst_precision form;
+  ElemType ta, tb, tc;
+  bool transb;
+  int tile;                    // index into gemm_tile_shapes(form)
+  const GemmTile* tiles;
+  const GemmProb* probs;
+  const GemmSeg* segs;
+  void* const* ptrs;
+  int64_t ntiles;
+};
+hipError_t launch_gemm(const GemmLaunch& g, hipStream_t s);
+
+struct PermLaunch {
+  const PermJob* jobs;
+  const PermWork* work;
+  void* const* ptrs;
+  int64_t nwork;
+};
+hipError_t launch_permute(const PermLaunch& p, hipStream_t s);
+
+struct HCoefLaunch {
+  const HTerm* terms;
+  const int32_t* entry_begin;  // nentries + 1
+  int64_t nentries;
+  void* const* ptrs;
+  double* coef64;
+  float* coef32;
+};
+hipError_t launch_hcoef(const HCoefLaunch& c, hipStream_t s);
+
+struct HApplyLaunch {
+  ElemType t;
+  int nmax;
+  const HTask* tasks;
+  const HPlane* planes;
+  const HWork* work;
+  int64_t nwork;
+  void* const* ptrs;
+  const void* coef;            // double or float [ncls][nmax][nmax]
+};
+hipError_t launch_happly(const HApplyLaunch& h, hipStream_t s);
+
+// Lanczos vector kernels (float64).  Reductions are deterministic: every
+// block reduces a fixed element range in a fixed order into `partial`
+// ([kVecBlocks][nvals]) and one more kernel adds the partials in order.
+constexpr int kVecBlocks = 2048;
+constexpr int kMaxVecs = 128;   // vectors handled by the fused kernels
+// out[k] = sum_i V[k*ldv + i] w[i], k < nv
+hipError_t launch_multidot(const double* V, int64_t ldv, int64_t n, int nv, const double* w,
+                           double* partial, double* out, hipStream_t s);
+// wout[i] = w[i] - sum_k V[k*ldv+i] c[k]  (wout may equal w), then
+// mode 1: out[k] = sum_i V[k*ldv+i] wout[i] (k < nv)
+// mode 2: out[0] = |wout|^2
+hipError_t launch_project(const double* V, int64_t ldv, int64_t n, int nv, const double* c,
+                          const double* w, double* wout, int mode, double* partial, double* out,
+                          hipStream_t s);
+// dst[i] = src[i] / sqrt(norm2[0]) (0 if norm2 <= 0); norm2 read on device.
+hipError_t launch_scale_rnorm(const double* src, const double* norm2, double* dst, int64_t n,
+                              hipStream_t s);
+// y[i] = sum_k coef[k] V[k*ldv+i]  (coef on device)
+hipError_t launch_combine(const double* V, int64_t ldv, int64_t n, int nv, const double* coef,
+                          double* y, hipStream_t s);
+// out[0] = x.y, out[1] = y.y
+hipError_t launch_dot2(const double* x, const double* y, int64_t n, double* partial, double* out,
+                       hipStream_t s);
+// e = num[0]/num[1]; out[0] = |hy - e y|^2
+hipError_t launch_resid(const double* hy, const double* y, const double* num, int64_t n,
+                        double* partial, double* out, hipStream_t s);
+// alpha[j] = c[j] + d[j]; beta[j] = sqrt(norm2[0])
+hipError_t launch_lanczos_scalars(const double* c, const double* d, int j, const double* norm2,
+                                  double* alpha, double* beta, hipStream_t s);
+// plain device copy of n doubles
+hipError_t launch_copy(const double* src, double* dst, int64_t n, hipStream_t s);
+
+}  // namespace bst

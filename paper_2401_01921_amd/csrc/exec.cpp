@@ -1,0 +1,376 @@
+// Plan execution: workspace layout, device pointer tables, hipGraph replay,
+// per-step timing and the tile autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <mutex>
+#include <sstream>
+
+#include "plan.h"
+
+namespace bst {
+
+// Which plan's tables a workspace currently holds.
+static std::mutex g_ws_mu;
+static std::map<void*, uint64_t> g_ws_owner;
+
+hipError_t launch_set_ptrs(void** table, void* const* src, int n, hipStream_t s);
+
+std::vector<void*> build_ptrs(PlanData& P, const void* const* in, void* const* out, void* ws) {
+  std::vector<void*> ptrs((size_t)std::max(P.nslots, 1), nullptr);
+  for (size_t k = 0; k < P.in_slots.size(); ++k) {
+    const bool empty = k < P.in_numel.size() && P.in_numel[k] == 0;
+    if ((!in || !in[k]) && !empty) fail(BST_E_INVALID, "null input pointer " + std::to_string(k));
+    ptrs[P.in_slots[k]] = in ? const_cast<void*>(in[k]) : nullptr;
+  }
+  for (size_t k = 0; k < P.out_slots.size(); ++k) {
+    const bool empty = k < P.out_numel.size() && P.out_numel[k] == 0;
+    if ((!out || !out[k]) && !empty) fail(BST_E_INVALID, "null output pointer " + std::to_string(k));
+    ptrs[P.out_slots[k]] = out ? out[k] : nullptr;
+  }
+  for (const auto& ib : P.internals) ptrs[ib.slot] = static_cast<char*>(ws) + ib.ws_off;
+  return ptrs;
+}
+
+void* upload_table(PlanData& P, const std::vector<void*>& ptrs, void* ws, size_t off,
+                   hipStream_t s) {
+  (void)P;
+  void** table = reinterpret_cast<void**>(static_cast<char*>(ws) + off);
+  check_hip(launch_set_ptrs(table, ptrs.data(), (int)ptrs.size(), s), "pointer table");
+  return table;
+}
+
+void* prepare_ws(PlanData& P, const void* const* in, void* const* out, void* ws, hipStream_t s) {
+  if (!ws) fail(BST_E_INVALID, "null workspace");
+  if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) fail(BST_E_INVALID, "workspace must be 256-byte aligned");
+  auto ptrs = build_ptrs(P, in, out, ws);
+  bool need_blob;
+  {
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    auto it = g_ws_owner.find(ws);
+    need_blob = (it == g_ws_owner.end() || it->second != P.id || P.uploaded_ws != ws);
+  }
+  if (need_blob) {
+    if (!P.blob.empty()) {
+      check_hip(hipMemcpyAsync(static_cast<char*>(ws) + P.ws_blob_off, P.blob.data(), P.blob.size(),
+                               hipMemcpyHostToDevice, s),
+                "plan table upload");
+      check_hip(hipStreamSynchronize(s), "plan table upload");
+    }
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    g_ws_owner[ws] = P.id;
+    P.uploaded_ws = ws;
+    P.last_ptrs.clear();
+  }
+  if (ptrs != P.last_ptrs) {
+    upload_table(P, ptrs, ws, P.ws_ptr_off, s);
+    P.last_ptrs = ptrs;
+  }
+  return static_cast<char*>(ws) + P.ws_ptr_off;
+}
+
+void run_steps_impl(PlanData& P, void* ws, void* const* dptrs, bst_precision prec, hipStream_t s,
+                    bool skip_coef, int only_step,
+                    std::vector<std::pair<hipEvent_t, hipEvent_t>>* ev) {
+  const char* blob = static_cast<const char*>(ws) + P.ws_blob_off;
+  char* wsb = static_cast<char*>(ws);
+  const ElemType inter = (prec == BST_FP64) ? ElemType::F64 : ElemType::F32;
+  for (size_t k = 0; k < P.steps.size(); ++k) {
+    if (only_step >= 0 && (int)k != only_step) continue;
+    Step& st = P.steps[k];
+    if (ev) check_hip(hipEventRecord((*ev)[k].first, s), "event");
+    hipError_t e = hipSuccess;
+    switch (st.kind) {
+      case StepKind::Gemm: {
+        const bst_precision form = st.fixed_fp64 ? BST_FP64 : prec;
+        GemmLaunch g{};
+        g.form = form;
+        g.ta = st.ta == Elem::Inter ? inter : ElemType::F64;
+        g.tb = ElemType::F64;
+        g.tc = st.tc == Elem::Inter ? inter : ElemType::F64;
+        g.transb = st.transb;
+        g.tile = default_tile(st, form);
+        const auto& sh = gemm_tile_shapes(form)[g.tile];
+        auto it = st.tile_lists.find({sh.bm, sh.bn});
+        if (it == st.tile_lists.end()) fail(BST_E_INVALID, "internal: missing tile list");
+        g.tiles = reinterpret_cast<const GemmTile*>(blob + it->second.first);
+        g.ntiles = it->second.second;
+        g.probs = reinterpret_cast<const GemmProb*>(blob + st.off0);
+        g.segs = reinterpret_cast<const GemmSeg*>(blob + st.off1);
+        g.ptrs = dptrs;
+        e = launch_gemm(g, s);
+        break;
+      }
+      case StepKind::Permute: {
+        PermLaunch pl{reinterpret_cast<const PermJob*>(blob + st.off0),
+                      reinterpret_cast<const PermWork*>(blob + st.off1), dptrs, st.n0};
+        e = launch_permute(pl, s);
+        break;
+      }
+      case StepKind::HCoef: {
+        if (skip_coef) break;
+        HCoefLaunch c{};
+        c.terms = reinterpret_cast<const HTerm*>(blob + st.off0);
+        c.entry_begin = reinterpret_cast<const int32_t*>(blob + st.off1);
+        c.nentries = st.n0;
+        c.ptrs = dptrs;
+        c.coef64 = reinterpret_cast<double*>(wsb + P.ws_coef64_off);
+        c.coef32 = reinterpret_cast<float*>(wsb + P.ws_coef32_off);
+        e = launch_hcoef(c, s);
+        break;
+      }
+      case StepKind::HApply: {
+        HApplyLaunch h{};
+        h.t = inter;
+        h.nmax = st.nmax;
+        h.tasks = reinterpret_cast<const HTask*>(blob + st.off0);
+        h.planes = reinterpret_cast<const HPlane*>(blob + st.off1);
+        h.work = reinterpret_cast<const HWork*>(blob + st.off2);
+        h.nwork = st.n0;
+        h.ptrs = dptrs;
+        h.coef = inter == ElemType::F64 ? (const void*)(wsb + P.ws_coef64_off)
+                                        : (const void*)(wsb + P.ws_coef32_off);
+        e = launch_happly(h, s);
+        break;
+      }
+    }
+    check_hip(e, st.name.c_str());
+    if (ev) check_hip(hipEventRecord((*ev)[k].second, s), "event");
+  }
+}
+
+void run_steps(PlanData& P, void* ws, void* const* dptrs, bst_precision prec, hipStream_t s,
+               bool skip_coef, std::vector<std::pair<hipEvent_t, hipEvent_t>>* ev) {
+  run_steps_impl(P, ws, dptrs, prec, s, skip_coef, -1, ev);
+}
+
+static void drop_graph(PlanData& P) {
+  if (P.gexec) (void)hipGraphExecDestroy(P.gexec);
+  if (P.graph) (void)hipGraphDestroy(P.graph);
+  P.gexec = nullptr;
+  P.graph = nullptr;
+  P.graph_ws = nullptr;
+}
+
+static std::string tune_key(const PlanData& P, const Step& st, bst_precision form) {
+  // structure signature: problem sizes and segment counts
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](uint64_t v) {
+    h ^= v;
+    h *= 1099511628211ull;
+  };
+  mix((uint64_t)form);
+  mix((uint64_t)st.transb);
+  for (const auto& p : st.probs) {
+    mix((uint64_t)p.M);
+    mix((uint64_t)p.N);
+    mix((uint64_t)p.seg_count);
+  }
+  for (const auto& g : st.segs) mix((uint64_t)g.K);
+  (void)P;
+  std::ostringstream os;
+  os << st.name << "-" << std::hex << h;
+  return os.str();
+}
+
+static std::map<std::string, std::pair<int, int>> load_cache(const char* path) {
+  std::map<std::string, std::pair<int, int>> m;
+  std::ifstream f(path);
+  std::string line;
+  // one entry per line: "key": [bm, bn],
+  while (std::getline(f, line)) {
+    auto q1 = line.find('"');
+    auto q2 = line.find('"', q1 + 1);
+    auto b1 = line.find('[');
+    if (q1 == std::string::npos || q2 == std::string::npos || b1 == std::string::npos) continue;
+    int bm = 0, bn = 0;
+    if (std::sscanf(line.c_str() + b1, "[%d, %d]", &bm, &bn) == 2)
+      m[line.substr(q1 + 1, q2 - q1 - 1)] = {bm, bn};
+  }
+  return m;
+}
+
+static void save_cache(const char* path, const std::map<std::string, std::pair<int, int>>& m) {
+  std::ofstream f(path);
+  f << "{\n";
+  size_t i = 0;
+  for (const auto& kv : m) {
+    f << "  \"" << kv.first << "\": [" << kv.second.first << ", " << kv.second.second << "]"
+      << (++i < m.size() ? "," : "") << "\n";
+  }
+  f << "}\n";
+}
+
+// Applies cached tile choices (if BST_TUNE_CACHE names a readable file).
+void apply_tune_cache(PlanData& P) {
+  const char* path = std::getenv("BST_TUNE_CACHE");
+  if (!path) return;
+  auto m = load_cache(path);
+  for (auto& st : P.steps) {
+    if (st.kind != StepKind::Gemm) continue;
+    for (int f = 0; f < 4; ++f) {
+      auto it = m.find(tune_key(P, st, (bst_precision)f));
+      if (it == m.end()) continue;
+      const auto& shapes = gemm_tile_shapes((bst_precision)f);
+      for (size_t i = 0; i < shapes.size(); ++i)
+        if (shapes[i].bm == it->second.first && shapes[i].bn == it->second.second)
+          st.tile_choice[f] = (int)i;
+    }
+  }
+}
+
+}  // namespace bst
+
+using namespace bst;
+
+extern "C" {
+
+bst_status bst_plan_use_graph(bst_plan* p, int32_t on) {
+  BST_TRY
+  if (!p) fail(BST_E_INVALID, "null plan");
+  p->p.use_graph = on != 0;
+  if (!on) drop_graph(p->p);
+  BST_CATCH
+}
+
+bst_status bst_execute(bst_plan* p, const void* const* in, void* const* out, void* ws,
+                       void* stream) {
+  BST_TRY
+  if (!p) fail(BST_E_INVALID, "null plan");
+  PlanData& P = p->p;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  check_hip(hipGetLastError(), "pending device error");
+  void* dptrs = prepare_ws(P, in, out, ws, s);
+  if (!P.use_graph) {
+    run_steps(P, ws, static_cast<void* const*>(dptrs), P.prec, s, false);
+  } else {
+    if (!P.gexec || P.graph_ws != ws || P.graph_prec != P.prec) {
+      drop_graph(P);
+      hipStream_t cs;
+      check_hip(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "capture stream");
+      hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+      if (e != hipSuccess) {
+        (void)hipStreamDestroy(cs);
+        check_hip(e, "begin capture");
+      }
+      try {
+        run_steps(P, ws, static_cast<void* const*>(dptrs), P.prec, cs, false);
+      } catch (...) {
+        hipGraph_t g;
+        (void)hipStreamEndCapture(cs, &g);
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipStreamDestroy(cs);
+        throw;
+      }
+      e = hipStreamEndCapture(cs, &P.graph);
+      (void)hipStreamDestroy(cs);
+      check_hip(e, "end capture");
+      check_hip(hipGraphInstantiate(&P.gexec, P.graph, nullptr, nullptr, 0), "graph instantiate");
+      P.graph_ws = ws;
+      P.graph_prec = P.prec;
+    }
+    check_hip(hipGraphLaunch(P.gexec, s), "graph launch");
+  }
+  BST_CATCH
+}
+
+bst_status bst_plan_profile(bst_plan* p, const void* const* in, void* const* out, void* ws,
+                            void* stream, int32_t reps, double* step_ms, int32_t cap,
+                            int32_t* nsteps) {
+  BST_TRY
+  if (!p || !step_ms || !nsteps) fail(BST_E_INVALID, "null argument");
+  PlanData& P = p->p;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  void* dptrs = prepare_ws(P, in, out, ws, s);
+  const size_t n = P.steps.size();
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev(n);
+  for (auto& e : ev) {
+    check_hip(hipEventCreate(&e.first), "event");
+    check_hip(hipEventCreate(&e.second), "event");
+  }
+  std::vector<double> acc(n, 0.0);
+  reps = std::max(reps, 1);
+  for (int r = 0; r < reps; ++r) {
+    run_steps(P, ws, static_cast<void* const*>(dptrs), P.prec, s, false, &ev);
+    check_hip(hipStreamSynchronize(s), "profile sync");
+    for (size_t k = 0; k < n; ++k) {
+      float ms = 0;
+      check_hip(hipEventElapsedTime(&ms, ev[k].first, ev[k].second), "event time");
+      acc[k] += ms;
+    }
+  }
+  for (auto& e : ev) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  *nsteps = (int32_t)n;
+  for (size_t k = 0; k < n && (int)k < cap; ++k) step_ms[k] = acc[k] / reps;
+  BST_CATCH
+}
+
+bst_status bst_plan_autotune(bst_plan* p, const void* const* in, void* const* out, void* ws,
+                             void* stream, int32_t reps) {
+  BST_TRY
+  if (!p) fail(BST_E_INVALID, "null plan");
+  PlanData& P = p->p;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  reps = std::max(reps, 1);
+  void* dptrs = prepare_ws(P, in, out, ws, s);
+  // one full run so that intermediates hold realistic data
+  run_steps(P, ws, static_cast<void* const*>(dptrs), P.prec, s, false);
+  hipEvent_t e0, e1;
+  check_hip(hipEventCreate(&e0), "event");
+  check_hip(hipEventCreate(&e1), "event");
+  const char* path = std::getenv("BST_TUNE_CACHE");
+  auto cache = path ? load_cache(path) : std::map<std::string, std::pair<int, int>>{};
+  const bst_precision form = P.prec;
+  for (size_t k = 0; k < P.steps.size(); ++k) {
+    Step& st = P.steps[k];
+    if (st.kind != StepKind::Gemm) continue;
+    const bst_precision f = st.fixed_fp64 ? BST_FP64 : form;
+    const auto& shapes = gemm_tile_shapes(f);
+    double best = 1e30;
+    int best_i = default_tile(st, f);
+    for (size_t i = 0; i < shapes.size(); ++i) {
+      st.tile_choice[(int)f] = (int)i;
+      run_steps_impl(P, ws, static_cast<void* const*>(dptrs), P.prec, s, false, (int)k, nullptr);
+      check_hip(hipEventRecord(e0, s), "event");
+      for (int r = 0; r < reps; ++r)
+        run_steps_impl(P, ws, static_cast<void* const*>(dptrs), P.prec, s, false, (int)k, nullptr);
+      check_hip(hipEventRecord(e1, s), "event");
+      check_hip(hipEventSynchronize(e1), "event sync");
+      float ms = 0;
+      check_hip(hipEventElapsedTime(&ms, e0, e1), "event time");
+      if (ms < best) {
+        best = ms;
+        best_i = (int)i;
+      }
+    }
+    st.tile_choice[(int)f] = best_i;
+    cache[tune_key(P, st, f)] = {shapes[best_i].bm, shapes[best_i].bn};
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  drop_graph(P);
+  if (path) save_cache(path, cache);
+  BST_CATCH
+}
+
+bst_status bst_plan_destroy(bst_plan* p) {
+  if (p) {
+    drop_graph(p->p);
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    for (auto it = g_ws_owner.begin(); it != g_ws_owner.end();) {
+      if (it->second == p->p.id) it = g_ws_owner.erase(it);
+      else ++it;
+    }
+  }
+  delete p;
+  set_last_error("");
+  return BST_OK;
+}
+
+}  // extern "C"

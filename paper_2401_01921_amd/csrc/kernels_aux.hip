@@ -1,0 +1,427 @@
+// Bandwidth-bound kernels: block permute, the two-site MPO (h = W1.W2)
+// apply, and the float64 vector kernels of Lanczos.  All are HBM-bound; they
+// read and write each element once, coalesced along the fastest index, with
+// LDS used to turn transposes into coalesced reads and writes.
+#include "bst_internal.h"
+
+namespace bst {
+
+// ------------------------------------------------------------------------
+// Block permute (Sec. "Permute", App. "Contiguous")
+// ------------------------------------------------------------------------
+constexpr int kPT = 64;   // transpose tile edge
+
+__global__ __launch_bounds__(256) void permute_kernel(const PermJob* __restrict__ jobs,
+                                                      const PermWork* __restrict__ work,
+                                                      void* const* __restrict__ ptrs) {
+  __shared__ double tile[kPT][kPT + 1];
+  const PermWork w = work[blockIdx.x];
+  const PermJob& j = jobs[w.job];
+  const double* __restrict__ in = reinterpret_cast<const double*>(ptrs[j.in_buf]) + j.in_off;
+  double* __restrict__ out = reinterpret_cast<double*>(ptrs[j.out_buf]) + j.out_off;
+  const int r = j.rank;
+  const int tid = threadIdx.x;
+  if (w.kind == 0) {
+    // fastest dim kept: copy whole rows; rows w.batch .. w.batch + w.t0 - 1
+    const int64_t last = j.shape[r - 1];
+    const int wave = tid >> 6, lane = tid & 63;
+    for (int64_t row = w.batch + wave; row < w.batch + w.t0; row += 4) {
+      int64_t rem = row, ob = 0;
+      for (int d = r - 2; d >= 0; --d) {
+        const int64_t ext = j.shape[d];
+        const int64_t idx = rem % ext;
+        rem /= ext;
+        ob += idx * j.ostride[d];
+      }
+      const double* src = in + row * last;
+      double* dst = out + ob;
+      for (int64_t c = lane; c < last; c += 64) dst[c] = src[c];
+    }
+    return;
+  }
+  // transposing job: tile over (pdim, last) at origin (t0, t1)
+  const int p = j.pdim;
+  int64_t rem = w.batch, ib = 0, ob = 0;
+  for (int d = r - 1; d >= 0; --d) {
+    if (d == p || d == r - 1) continue;
+    const int64_t ext = j.shape[d];
+    const int64_t idx = rem % ext;
+    rem /= ext;
+    ib += idx * j.istride[d];
+    ob += idx * j.ostride[d];
+  }
+  const int np = j.shape[p], nl = j.shape[r - 1];
+  const int64_t isp = j.istride[p], osl = j.ostride[r - 1];
+  for (int e = tid; e < kPT * kPT; e += 256) {
+    const int y = e / kPT, x = e % kPT;
+    const int gy = w.t0 + y, gx = w.t1 + x;
+    if (gy < np && gx < nl) tile[y][x] = in[ib + gy * isp + gx];
+  }
+  __syncthreads();
+  for (int e = tid; e < kPT * kPT; e += 256) {
+    const int x = e / kPT, y = e % kPT;
+    const int gy = w.t0 + y, gx = w.t1 + x;
+    if (gy < np && gx < nl) out[ob + gy + gx * osl] = tile[y][x];
+  }
+}
+
+hipError_t launch_permute(const PermLaunch& p, hipStream_t s) {
+  if (p.nwork <= 0) return hipSuccess;
+  if (p.nwork > 0x7FFFFFFF) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(permute_kernel, dim3((unsigned)p.nwork), dim3(256), 0, s, p.jobs, p.work,
+                     p.ptrs);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------
+// Two-site MPO apply.  For every pair (a-sector, b'-sector) the T1 planes
+// (w1 channel, t1, t2) map to the T3 planes (s1, s2, w3) through the small
+// matrix h[o][i] = sum_w2 W1[w1,s1,t1,w2] W2[w2,s2,t2,w3] (Sec. "Benchmarks",
+// Fig. Hpsi_fig: the two W's form the two-site operator h).
+// ------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void hcoef_kernel(const HTerm* __restrict__ terms,
+                                                    const int32_t* __restrict__ entry_begin,
+                                                    int64_t nentries, void* const* __restrict__ ptrs,
+                                                    double* __restrict__ c64,
+                                                    float* __restrict__ c32) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= nentries) return;
+  double sum = 0.0;
+  for (int32_t k = entry_begin[e]; k < entry_begin[e + 1]; ++k) {
+    const HTerm t = terms[k];
+    const double w1 = reinterpret_cast<const double*>(ptrs[t.w1_buf])[t.w1_off];
+    const double w2 = reinterpret_cast<const double*>(ptrs[t.w2_buf])[t.w2_off];
+    sum += w1 * w2;
+  }
+  c64[e] = sum;
+  c32[e] = (float)sum;
+}
+
+hipError_t launch_hcoef(const HCoefLaunch& c, hipStream_t s) {
+  if (c.nentries <= 0) return hipSuccess;
+  const unsigned blocks = (unsigned)((c.nentries + 255) / 256);
+  hipLaunchKernelGGL(hcoef_kernel, dim3(blocks), dim3(256), 0, s, c.terms, c.entry_begin,
+                     c.nentries, c.ptrs, c.coef64, c.coef32);
+  return hipGetLastError();
+}
+
+template <typename T, int NMAX>
+__global__ __launch_bounds__(256) void happly_kernel(const HTask* __restrict__ tasks,
+                                                     const HPlane* __restrict__ planes,
+                                                     const HWork* __restrict__ work,
+                                                     void* const* __restrict__ ptrs,
+                                                     const T* __restrict__ coef) {
+  __shared__ T cf[NMAX * NMAX];
+  __shared__ HPlane pl[2 * NMAX];
+  const HWork w = work[blockIdx.x];
+  const HTask t = tasks[w.task];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < NMAX * NMAX; e += 256) cf[e] = coef[(int64_t)t.cls * NMAX * NMAX + e];
+  for (int e = tid; e < t.nin + t.nout; e += 256) pl[e] = planes[t.plane_begin + e];
+  __syncthreads();
+  const int site = w.site0 + tid;
+  if (site >= t.rows * t.cols) return;
+  const int i = site / t.cols, jc = site % t.cols;
+  const T* __restrict__ in = reinterpret_cast<const T*>(ptrs[t.in_buf]);
+  T* __restrict__ out = reinterpret_cast<T*>(ptrs[t.out_buf]);
+  T x[NMAX];
+#pragma unroll
+  for (int k = 0; k < NMAX; ++k)
+    x[k] = (k < t.nin) ? in[pl[k].off + (int64_t)i * pl[k].rowstride + jc] : T(0);
+#pragma unroll
+  for (int o = 0; o < NMAX; ++o) {
+    if (o < t.nout) {
+      T y = 0;
+#pragma unroll
+      for (int k = 0; k < NMAX; ++k) y += cf[o * NMAX + k] * x[k];
+      const HPlane q = pl[t.nin + o];
+      out[q.off + (int64_t)i * q.rowstride + jc] = y;
+    }
+  }
+}
+
+hipError_t launch_happly(const HApplyLaunch& h, hipStream_t s) {
+  if (h.nwork <= 0) return hipSuccess;
+  if (h.nwork > 0x7FFFFFFF) return hipErrorInvalidValue;
+  dim3 grid((unsigned)h.nwork), block(256);
+#define BST_HA(T_, N_)                                                                       \
+  if (h.nmax == N_) {                                                                        \
+    hipLaunchKernelGGL((happly_kernel<T_, N_>), grid, block, 0, s, h.tasks, h.planes, h.work, \
+                       h.ptrs, reinterpret_cast<const T_*>(h.coef));                         \
+    return hipGetLastError();                                                                \
+  }
+  if (h.t == ElemType::F64) {
+    BST_HA(double, 8) BST_HA(double, 16) BST_HA(double, 32) BST_HA(double, 64)
+  } else {
+    BST_HA(float, 8) BST_HA(float, 16) BST_HA(float, 32) BST_HA(float, 64)
+  }
+#undef BST_HA
+  return hipErrorInvalidValue;
+}
+
+// ------------------------------------------------------------------------
+// Lanczos vector kernels
+// ------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+// Sums acc[k] over the block in a fixed order and writes partial[k*G + blk].
+template <int NV>
+__device__ __forceinline__ void block_reduce_store(double (&acc)[NV], int nv, double* red,
+                                                   double* partial) {
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    if (k < nv) {
+      const double v = wave_sum(acc[k]);
+      if (lane == 0) red[wave * NV + k] = v;
+    }
+  }
+  __syncthreads();
+  for (int k = tid; k < nv; k += 256) {
+    const double v = ((red[k] + red[NV + k]) + red[2 * NV + k]) + red[3 * NV + k];
+    partial[(int64_t)k * gridDim.x + blockIdx.x] = v;
+  }
+}
+
+// out[k] = sum_b partial[k*G + b]  (one block per k, fixed order)
+__global__ __launch_bounds__(256) void reduce_partials_kernel(const double* __restrict__ partial,
+                                                              int G, double* __restrict__ out) {
+  __shared__ double red[4];
+  const int k = blockIdx.x, tid = threadIdx.x;
+  double s = 0.0;
+  for (int b = tid; b < G; b += 256) s += partial[(int64_t)k * G + b];
+  s = wave_sum(s);
+  if ((tid & 63) == 0) red[tid >> 6] = s;
+  __syncthreads();
+  if (tid == 0) out[k] = ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+static inline int vec_grid(int64_t n) {
+  int64_t g = (n + 255) / 256;
+  if (g > kVecBlocks) g = kVecBlocks;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+template <int NV>
+__global__ __launch_bounds__(256) void multidot_kernel(const double* __restrict__ V, int64_t ldv,
+                                                       int64_t n, int nv,
+                                                       const double* __restrict__ w,
+                                                       double* __restrict__ partial) {
+  __shared__ double red[4 * NV];
+  double acc[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
+    const double wi = w[i];
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+      if (k < nv) acc[k] += V[k * ldv + i] * wi;
+  }
+  block_reduce_store<NV>(acc, nv, red, partial);
+}
+
+template <int NV>
+__global__ __launch_bounds__(256) void project_kernel(const double* __restrict__ V, int64_t ldv,
+                                                      int64_t n, int nv,
+                                                      const double* __restrict__ c,
+                                                      const double* w, double* wout, int mode,
+                                                      double* __restrict__ partial) {
+  __shared__ double red[4 * NV];
+  __shared__ double cs[NV];
+  for (int k = threadIdx.x; k < NV; k += 256) cs[k] = (k < nv) ? c[k] : 0.0;
+  __syncthreads();
+  double acc[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
+    double v[NV];
+    double s = w[i];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      v[k] = (k < nv) ? V[k * ldv + i] : 0.0;
+      s -= v[k] * cs[k];
+    }
+    wout[i] = s;
+    if (mode == 1) {
+#pragma unroll
+      for (int k = 0; k < NV; ++k) acc[k] += v[k] * s;
+    } else {
+      acc[0] += s * s;
+    }
+  }
+  block_reduce_store<NV>(acc, mode == 1 ? nv : 1, red, partial);
+}
+
+#define BST_NV_DISPATCH(KERNEL, ...)                                                      \
+  do {                                                                                    \
+    if (nv <= 8) hipLaunchKernelGGL((KERNEL<8>), __VA_ARGS__);                            \
+    else if (nv <= 16) hipLaunchKernelGGL((KERNEL<16>), __VA_ARGS__);                     \
+    else if (nv <= 32) hipLaunchKernelGGL((KERNEL<32>), __VA_ARGS__);                     \
+    else if (nv <= 48) hipLaunchKernelGGL((KERNEL<48>), __VA_ARGS__);                     \
+    else if (nv <= 64) hipLaunchKernelGGL((KERNEL<64>), __VA_ARGS__);                     \
+    else if (nv <= 96) hipLaunchKernelGGL((KERNEL<96>), __VA_ARGS__);                     \
+    else hipLaunchKernelGGL((KERNEL<128>), __VA_ARGS__);                                  \
+  } while (0)
+
+hipError_t launch_multidot(const double* V, int64_t ldv, int64_t n, int nv, const double* w,
+                           double* partial, double* out, hipStream_t s) {
+  if (nv < 1 || nv > kMaxVecs) return hipErrorInvalidValue;
+  const int G = vec_grid(n);
+  BST_NV_DISPATCH(multidot_kernel, dim3(G), dim3(256), 0, s, V, ldv, n, nv, w, partial);
+  hipLaunchKernelGGL(reduce_partials_kernel, dim3(nv), dim3(256), 0, s, partial, G, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_project(const double* V, int64_t ldv, int64_t n, int nv, const double* c,
+                          const double* w, double* wout, int mode, double* partial, double* out,
+                          hipStream_t s) {
+  if (nv < 1 || nv > kMaxVecs) return hipErrorInvalidValue;
+  const int G = vec_grid(n);
+  BST_NV_DISPATCH(project_kernel, dim3(G), dim3(256), 0, s, V, ldv, n, nv, c, w, wout, mode,
+                  partial);
+  hipLaunchKernelGGL(reduce_partials_kernel, dim3(mode == 1 ? nv : 1), dim3(256), 0, s, partial,
+                     G, out);
+  return hipGetLastError();
+}
+
+template <int NV>
+__global__ __launch_bounds__(256) void combine_kernel(const double* __restrict__ V, int64_t ldv,
+                                                      int64_t n, int nv,
+                                                      const double* __restrict__ coef,
+                                                      double* __restrict__ y) {
+  __shared__ double cs[NV];
+  for (int k = threadIdx.x; k < NV; k += 256) cs[k] = (k < nv) ? coef[k] : 0.0;
+  __syncthreads();
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+      if (k < nv) s += cs[k] * V[k * ldv + i];
+    y[i] = s;
+  }
+}
+
+hipError_t launch_combine(const double* V, int64_t ldv, int64_t n, int nv, const double* coef,
+                          double* y, hipStream_t s) {
+  if (nv < 1 || nv > kMaxVecs) return hipErrorInvalidValue;
+  const int G = vec_grid(n);
+  BST_NV_DISPATCH(combine_kernel, dim3(G), dim3(256), 0, s, V, ldv, n, nv, coef, y);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void scale_rnorm_kernel(const double* __restrict__ src,
+                                                          const double* __restrict__ norm2,
+                                                          double* __restrict__ dst, int64_t n) {
+  const double q = norm2[0];
+  const double f = q > 0.0 ? 1.0 / sqrt(q) : 0.0;
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) dst[i] = src[i] * f;
+}
+
+hipError_t launch_scale_rnorm(const double* src, const double* norm2, double* dst, int64_t n,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(scale_rnorm_kernel, dim3(vec_grid(n)), dim3(256), 0, s, src, norm2, dst, n);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void dot2_kernel(const double* __restrict__ x,
+                                                   const double* __restrict__ y, int64_t n,
+                                                   double* __restrict__ partial) {
+  __shared__ double red[4 * 2];
+  double acc[2] = {0.0, 0.0};
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
+    acc[0] += x[i] * y[i];
+    acc[1] += y[i] * y[i];
+  }
+  block_reduce_store<2>(acc, 2, red, partial);
+}
+
+hipError_t launch_dot2(const double* x, const double* y, int64_t n, double* partial, double* out,
+                       hipStream_t s) {
+  const int G = vec_grid(n);
+  hipLaunchKernelGGL(dot2_kernel, dim3(G), dim3(256), 0, s, x, y, n, partial);
+  hipLaunchKernelGGL(reduce_partials_kernel, dim3(2), dim3(256), 0, s, partial, G, out);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void resid_kernel(const double* __restrict__ hy,
+                                                    const double* __restrict__ y,
+                                                    const double* __restrict__ num, int64_t n,
+                                                    double* __restrict__ partial) {
+  __shared__ double red[4];
+  const double e = num[0] / num[1];
+  double acc[1] = {0.0};
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
+    const double r = hy[i] - e * y[i];
+    acc[0] += r * r;
+  }
+  block_reduce_store<1>(acc, 1, red, partial);
+}
+
+hipError_t launch_resid(const double* hy, const double* y, const double* num, int64_t n,
+                        double* partial, double* out, hipStream_t s) {
+  const int G = vec_grid(n);
+  hipLaunchKernelGGL(resid_kernel, dim3(G), dim3(256), 0, s, hy, y, num, n, partial);
+  hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(256), 0, s, partial, G, out);
+  return hipGetLastError();
+}
+
+__global__ void lanczos_scalars_kernel(const double* c, const double* d, int j,
+                                       const double* norm2, double* alpha, double* beta) {
+  if (threadIdx.x == 0) {
+    alpha[j] = c[j] + d[j];
+    beta[j] = sqrt(norm2[0] > 0.0 ? norm2[0] : 0.0);
+  }
+}
+
+hipError_t launch_lanczos_scalars(const double* c, const double* d, int j, const double* norm2,
+                                  double* alpha, double* beta, hipStream_t s) {
+  hipLaunchKernelGGL(lanczos_scalars_kernel, dim3(1), dim3(64), 0, s, c, d, j, norm2, alpha, beta);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void copy_kernel(const double* __restrict__ src,
+                                                   double* __restrict__ dst, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+}
+
+struct PtrChunk {
+  void* p[256];
+};
+__global__ void set_ptrs_kernel(void** table, PtrChunk c, int n) {
+  const int i = threadIdx.x;
+  if (i < n) table[i] = c.p[i];
+}
+
+// Writes a device pointer table through a kernel argument (no host staging
+// buffer has to outlive the call).
+hipError_t launch_set_ptrs(void** table, void* const* src, int n, hipStream_t s) {
+  for (int base = 0; base < n; base += 256) {
+    PtrChunk c{};
+    const int m = n - base < 256 ? n - base : 256;
+    for (int i = 0; i < m; ++i) c.p[i] = src[base + i];
+    hipLaunchKernelGGL(set_ptrs_kernel, dim3(1), dim3(256), 0, s, table + base, c, m);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_copy(const double* src, double* dst, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(copy_kernel, dim3(vec_grid(n)), dim3(256), 0, s, src, dst, n);
+  return hipGetLastError();
+}
+
+}  // namespace bst

@@ -1,0 +1,984 @@
+// Plan builders: charge-sector matching for permute, pairwise contraction
+// and the two-site H_eff, all exact integer work done once per structure.
+#include "plan.h"
+
+#include <algorithm>
+#include <atomic>
+#include <cstring>
+#include <numeric>
+
+namespace bst {
+
+static std::atomic<uint64_t> g_plan_id{1};
+
+static void check_contractible(const LegDesc& a, const LegDesc& b, const std::string& what) {
+  if (a.dir == b.dir)
+    fail(BST_E_DIRECTION, "leg '" + what + "' has the same direction on both tensors");
+  if (a.q != b.q) fail(BST_E_QNUM, "leg '" + what + "' has different quantum numbers");
+  if (a.g != b.g) fail(BST_E_DIM, "leg '" + what + "' has different sector dims");
+}
+
+static void check_same(const LegDesc& a, const LegDesc& b, const std::string& what) {
+  if (a.dir != b.dir || a.q != b.q || a.g != b.g)
+    fail(BST_E_STRUCTURE, "leg '" + what + "' of the result does not match psi");
+}
+
+// ------------------------------------------------------------------------
+// Permute jobs
+// ------------------------------------------------------------------------
+// Appends the jobs that move every block of `in` (slot in_slot) to its place
+// in `out` = in with legs permuted by perm (new leg i = old leg perm[i]).
+static void add_permute_jobs(Step& st, const TensorDesc& in, const TensorDesc& out,
+                             const std::vector<int>& perm, int in_slot, int out_slot) {
+  const int r = in.rank();
+  std::vector<int> pos(r);
+  for (int k = 0; k < r; ++k) pos[perm[k]] = k;
+  std::vector<int32_t> nt(r);
+  for (int64_t b = 0; b < in.nblocks; ++b) {
+    const int32_t* t = in.block_qn(b);
+    for (int k = 0; k < r; ++k) nt[k] = t[perm[k]];
+    const int64_t ob = out.find(nt.data());
+    if (ob < 0) fail(BST_E_INVALID, "internal: permuted block missing");
+    const int64_t* sh = in.block_shape(b);
+    // output strides of the output block (row-major over the permuted shape)
+    std::vector<int64_t> ostr_out(r, 1);
+    for (int k = r - 2; k >= 0; --k) ostr_out[k] = ostr_out[k + 1] * sh[perm[k + 1]];
+    // reduce: drop size-1 dims, merge input-adjacent dims that stay adjacent
+    std::vector<int64_t> ext;
+    std::vector<int64_t> ost;
+    std::vector<int> opos;
+    for (int d = 0; d < r; ++d) {
+      if (sh[d] == 1) continue;
+      if (!ext.empty() && opos.back() + 1 == pos[d]) {
+        // check that no non-unit output dim sits between them (pos adjacent ensures it)
+        ext.back() *= sh[d];
+        ost.back() = ostr_out[pos[d]];
+        opos.back() = pos[d];
+        continue;
+      }
+      ext.push_back(sh[d]);
+      ost.push_back(ostr_out[pos[d]]);
+      opos.push_back(pos[d]);
+    }
+    if (ext.empty()) {
+      ext.push_back(1);
+      ost.push_back(1);
+    }
+    const int rr = (int)ext.size();
+    PermJob j{};
+    j.in_off = in.offset[b];
+    j.out_off = out.offset[ob];
+    j.in_buf = in_slot;
+    j.out_buf = out_slot;
+    j.rank = rr;
+    int64_t s = 1;
+    for (int d = rr - 1; d >= 0; --d) {
+      j.shape[d] = (int32_t)ext[d];
+      j.istride[d] = s;
+      j.ostride[d] = ost[d];
+      s *= ext[d];
+    }
+    j.pdim = -1;
+    for (int d = 0; d < rr; ++d)
+      if (ost[d] == 1 && ext[d] > 1) j.pdim = d;
+    const int jid = (int)st.jobs.size();
+    const int64_t last = ext[rr - 1];
+    const int64_t numel = s;
+    if (rr == 1 || j.pdim == rr - 1 || j.pdim < 0) {
+      j.pdim = rr - 1;
+      st.jobs.push_back(j);
+      const int64_t rows = numel / last;
+      int64_t per = std::max<int64_t>(1, 8192 / last);
+      per = std::min<int64_t>(per, 1 << 20);
+      for (int64_t r0 = 0; r0 < rows; r0 += per) {
+        PermWork w{};
+        w.job = jid;
+        w.kind = 0;
+        w.batch = r0;
+        w.t0 = (int32_t)std::min<int64_t>(per, rows - r0);
+        st.pwork.push_back(w);
+      }
+    } else {
+      st.jobs.push_back(j);
+      const int64_t np = ext[j.pdim];
+      int64_t nbatch = numel / (np * last);
+      for (int64_t bt = 0; bt < nbatch; ++bt)
+        for (int64_t y = 0; y < np; y += 64)
+          for (int64_t x = 0; x < last; x += 64) {
+            PermWork w{};
+            w.job = jid;
+            w.kind = 1;
+            w.batch = bt;
+            w.t0 = (int32_t)y;
+            w.t1 = (int32_t)x;
+            st.pwork.push_back(w);
+          }
+    }
+  }
+  st.bytes += 16.0 * (double)in.numel;
+  st.bytes32 += 16.0 * (double)in.numel;
+}
+
+static std::unique_ptr<TensorDesc> permuted_desc(const TensorDesc& in, const std::vector<int>& perm) {
+  std::vector<LegDesc> legs;
+  for (int k : perm) legs.push_back(in.legs[k]);
+  return make_tensor(std::move(legs));
+}
+
+// ------------------------------------------------------------------------
+// Pairwise contraction (Sec. "Tensor contraction")
+// ------------------------------------------------------------------------
+struct ContractBuild {
+  std::unique_ptr<TensorDesc> C;
+  std::unique_ptr<TensorDesc> Apack, Bpack;   // null if the operand is used in place
+  std::vector<int> permA, permB;
+};
+
+// Fills `st` (a GEMM step) for C = A . B with A given as [free.., contracted..]
+// (tensor Ause, slot a_slot) and B as [contracted.., free..] (NN) or
+// [free.., contracted..] (NT).
+static void build_gemm(Step& st, const TensorDesc& Ause, int a_slot, int na_free,
+                       const TensorDesc& Buse, int b_slot, int nb_free, bool transb,
+                       const TensorDesc& C, int c_slot) {
+  const int ra = Ause.rank(), rb = Buse.rank();
+  const int nc = ra - na_free;
+  // index A blocks by free tuple
+  std::unordered_map<std::string, std::vector<int64_t>> a_by_free;
+  for (int64_t b = 0; b < Ause.nblocks; ++b) {
+    const int32_t* t = Ause.block_qn(b);
+    a_by_free[std::string(reinterpret_cast<const char*>(t), 4 * na_free)].push_back(b);
+  }
+  std::vector<int32_t> bt(rb);
+  st.kind = StepKind::Gemm;
+  st.transb = transb;
+  for (int64_t cb = 0; cb < C.nblocks; ++cb) {
+    const int32_t* ct = C.block_qn(cb);
+    const int64_t* cs = C.block_shape(cb);
+    GemmProb p{};
+    int64_t M = 1, N = 1;
+    for (int i = 0; i < na_free; ++i) M *= cs[i];
+    for (int i = 0; i < nb_free; ++i) N *= cs[na_free + i];
+    if (M > 0x7FFFFFFF || N > 0x7FFFFFFF) fail(BST_E_INVALID, "block too large");
+    p.c_off = C.offset[cb];
+    p.c_buf = c_slot;
+    p.M = (int32_t)M;
+    p.N = (int32_t)N;
+    p.ldc = (int32_t)N;
+    p.seg_begin = (int32_t)st.segs.size();
+    auto it = a_by_free.find(std::string(reinterpret_cast<const char*>(ct), 4 * na_free));
+    if (it != a_by_free.end()) {
+      for (int64_t ab : it->second) {
+        const int32_t* at = Ause.block_qn(ab);
+        // B tuple
+        if (!transb) {
+          for (int i = 0; i < nc; ++i) bt[i] = at[na_free + i];
+          for (int i = 0; i < nb_free; ++i) bt[nc + i] = ct[na_free + i];
+        } else {
+          for (int i = 0; i < nb_free; ++i) bt[i] = ct[na_free + i];
+          for (int i = 0; i < nc; ++i) bt[nb_free + i] = at[na_free + i];
+        }
+        const int64_t bb = Buse.find(bt.data());
+        if (bb < 0) continue;
+        int64_t K = 1;
+        for (int i = 0; i < nc; ++i) K *= Ause.block_shape(ab)[na_free + i];
+        if (K > 0x7FFFFFFF) fail(BST_E_INVALID, "block too large");
+        GemmSeg g{};
+        g.a_off = Ause.offset[ab];
+        g.a_buf = a_slot;
+        g.b_off = Buse.offset[bb];
+        g.b_buf = b_slot;
+        g.K = (int32_t)K;
+        g.lda = (int32_t)K;
+        g.ldb = transb ? (int32_t)K : (int32_t)N;
+        st.segs.push_back(g);
+        st.flops += 2.0 * (double)M * (double)N * (double)K;
+      }
+    }
+    p.seg_count = (int32_t)st.segs.size() - p.seg_begin;
+    st.probs.push_back(p);
+  }
+}
+
+static void contract_plan(const TensorDesc& A, const TensorDesc& B, PlanData& P,
+                          std::unique_ptr<TensorDesc>& Cout) {
+  const int ra = A.rank(), rb = B.rank();
+  std::vector<int> ac, bc;
+  for (int i = 0; i < ra; ++i) {
+    int j = B.label_index(A.legs[i].label);
+    if (j >= 0) {
+      check_contractible(A.legs[i], B.legs[j], A.legs[i].label);
+      ac.push_back(i);
+      bc.push_back(j);
+    }
+  }
+  std::vector<int> af, bf;
+  for (int i = 0; i < ra; ++i)
+    if (std::find(ac.begin(), ac.end(), i) == ac.end()) af.push_back(i);
+  for (int j = 0; j < rb; ++j)
+    if (std::find(bc.begin(), bc.end(), j) == bc.end()) bf.push_back(j);
+  std::vector<LegDesc> cl;
+  for (int i : af) cl.push_back(A.legs[i]);
+  for (int j : bf) cl.push_back(B.legs[j]);
+  // the output's labels must be unique
+  Cout = make_tensor(cl);
+  const TensorDesc& C = *Cout;
+
+  P.kind = 1;
+  P.in_slots = {0, 1};
+  P.out_slots = {2};
+  P.in_numel = {A.numel, B.numel};
+  P.out_numel = {C.numel};
+  P.nslots = 3;
+  // A operand: [free.., contracted..]
+  std::vector<int> permA = af;
+  permA.insert(permA.end(), ac.begin(), ac.end());
+  bool packA = false;
+  for (int i = 0; i < ra; ++i)
+    if (permA[i] != i) packA = true;
+  // B operand
+  std::vector<int> nn = bc;
+  nn.insert(nn.end(), bf.begin(), bf.end());
+  std::vector<int> nt = bf;
+  nt.insert(nt.end(), bc.begin(), bc.end());
+  auto is_identity = [](const std::vector<int>& v) {
+    for (size_t i = 0; i < v.size(); ++i)
+      if (v[i] != (int)i) return false;
+    return true;
+  };
+  bool transb = false, packB = false;
+  if (is_identity(nn)) {
+    transb = false;
+  } else if (is_identity(nt)) {
+    transb = true;
+  } else {
+    packB = true;
+  }
+  std::unique_ptr<TensorDesc> Ap, Bp;
+  int a_slot = 0, b_slot = 1;
+  if (packA) {
+    Ap = permuted_desc(A, permA);
+    Step st;
+    st.kind = StepKind::Permute;
+    st.name = "pack_a";
+    a_slot = P.nslots++;
+    P.internals.push_back({a_slot, (size_t)A.numel * 8, 0});
+    add_permute_jobs(st, A, *Ap, permA, 0, a_slot);
+    P.steps.push_back(std::move(st));
+  }
+  if (packB) {
+    Bp = permuted_desc(B, nn);
+    Step st;
+    st.kind = StepKind::Permute;
+    st.name = "pack_b";
+    b_slot = P.nslots++;
+    P.internals.push_back({b_slot, (size_t)B.numel * 8, 0});
+    add_permute_jobs(st, B, *Bp, nn, 1, b_slot);
+    P.steps.push_back(std::move(st));
+  }
+  Step g;
+  g.name = "gemm";
+  build_gemm(g, packA ? *Ap : A, a_slot, (int)af.size(), packB ? *Bp : B, b_slot, (int)bf.size(),
+             transb, C, 2);
+  g.bytes = 8.0 * ((double)A.numel + (double)B.numel + (double)C.numel);
+  g.bytes32 = g.bytes;
+  P.steps.push_back(std::move(g));
+}
+
+// ------------------------------------------------------------------------
+// Two-site H_eff (Sec. "Benchmarks", Fig. Hpsi_fig)
+// ------------------------------------------------------------------------
+// Dense index -> (sector, index in sector) of a leg.
+struct LegMap {
+  std::vector<int32_t> sec, within;
+  std::vector<int64_t> start;
+  explicit LegMap(const LegDesc& L) {
+    int64_t s = 0;
+    for (size_t k = 0; k < L.g.size(); ++k) {
+      start.push_back(s);
+      for (int64_t e = 0; e < L.g[k]; ++e) {
+        sec.push_back((int32_t)k);
+        within.push_back((int32_t)e);
+      }
+      s += L.g[k];
+    }
+  }
+};
+
+// Flat offset of a dense element of a rank-4 tensor, -1 outside valid blocks.
+static int64_t elem_offset4(const TensorDesc& T, const LegMap* maps, const int64_t* idx) {
+  int32_t t[4];
+  for (int i = 0; i < 4; ++i) t[i] = maps[i].sec[idx[i]];
+  const int64_t b = T.find(t);
+  if (b < 0) return -1;
+  const int64_t* sh = T.block_shape(b);
+  int64_t off = 0;
+  for (int i = 0; i < 4; ++i) off = off * sh[i] + maps[i].within[idx[i]];
+  return T.offset[b] + off;
+}
+
+static void heff_plan(const TensorDesc& L, const TensorDesc& W1, const TensorDesc& W2,
+                      const TensorDesc& R, const TensorDesc& psi, PlanData& P) {
+  if (L.rank() != 3 || W1.rank() != 4 || W2.rank() != 4 || R.rank() != 3 || psi.rank() != 4)
+    fail(BST_E_STRUCTURE, "H_eff needs L[a,w,a'], W[wl,s,s',wr] (x2), R[b,w,b'], psi[a,s1,s2,b]");
+  check_contractible(L.legs[2], psi.legs[0], "L.a' / psi.a");
+  check_contractible(L.legs[1], W1.legs[0], "L.w / W1.wl");
+  check_contractible(W1.legs[2], psi.legs[1], "W1.s' / psi.s1");
+  check_contractible(W1.legs[3], W2.legs[0], "W1.wr / W2.wl");
+  check_contractible(W2.legs[2], psi.legs[2], "W2.s' / psi.s2");
+  check_contractible(W2.legs[3], R.legs[1], "W2.wr / R.w");
+  check_contractible(R.legs[2], psi.legs[3], "R.b' / psi.b");
+  check_same(L.legs[0], psi.legs[0], "a");
+  check_same(W1.legs[1], psi.legs[1], "s1");
+  check_same(W2.legs[1], psi.legs[2], "s2");
+  check_same(R.legs[0], psi.legs[3], "b");
+
+  // slots: 0 L, 1 W1, 2 W2, 3 R, 4 psi, 5 out, 6 T1, 7 T3
+  P.kind = 2;
+  P.in_slots = {0, 1, 2, 3, 4};
+  P.out_slots = {5};
+  P.in_numel = {L.numel, W1.numel, W2.numel, R.numel, psi.numel};
+  P.out_numel = {psi.numel};
+  P.nslots = 8;
+  P.psi_numel = psi.numel;
+
+  auto lab = [](LegDesc l, const char* s) {
+    l.label = s;
+    return l;
+  };
+  // T1[a, w1, t1, t2, y] and T3[a, s1, s2, w3, y]
+  auto T1 = make_tensor({lab(L.legs[0], "a"), lab(L.legs[1], "w1"), lab(psi.legs[1], "t1"),
+                         lab(psi.legs[2], "t2"), lab(psi.legs[3], "y")});
+  auto T3 = make_tensor({lab(psi.legs[0], "a"), lab(W1.legs[1], "s1"), lab(W2.legs[1], "s2"),
+                         lab(W2.legs[3], "w3"), lab(psi.legs[3], "y")});
+  P.t1_numel = T1->numel;
+  P.t3_numel = T3->numel;
+  P.internals.push_back({6, (size_t)T1->numel * 8, 0});
+  P.internals.push_back({7, (size_t)T3->numel * 8, 0});
+
+  // ---- step 1: T1[(a w) x (t1 t2 y)] = sum_a' L[(a w) x a'] psi[a' x (t1 t2 y)]
+  Step s1;
+  s1.kind = StepKind::Gemm;
+  s1.name = "gemm_L_psi";
+  s1.tc = Elem::Inter;
+  {
+    const int nA = (int)psi.legs[0].q.size();
+    int32_t lt[3], pt[4];
+    for (int64_t cb = 0; cb < T1->nblocks; ++cb) {
+      const int32_t* t = T1->block_qn(cb);
+      const int64_t* sh = T1->block_shape(cb);
+      GemmProb p{};
+      const int64_t M = sh[0] * sh[1], N = sh[2] * sh[3] * sh[4];
+      p.c_off = T1->offset[cb];
+      p.c_buf = 6;
+      p.M = (int32_t)M;
+      p.N = (int32_t)N;
+      p.ldc = (int32_t)N;
+      p.seg_begin = (int32_t)s1.segs.size();
+      for (int kap = 0; kap < nA; ++kap) {
+        lt[0] = t[0]; lt[1] = t[1]; lt[2] = kap;
+        pt[0] = kap; pt[1] = t[2]; pt[2] = t[3]; pt[3] = t[4];
+        const int64_t lb = L.find(lt), pb = psi.find(pt);
+        if (lb < 0 || pb < 0) continue;
+        GemmSeg g{};
+        const int64_t K = psi.legs[0].g[kap];
+        g.a_off = L.offset[lb];
+        g.a_buf = 0;
+        g.b_off = psi.offset[pb];
+        g.b_buf = 4;
+        g.K = (int32_t)K;
+        g.lda = (int32_t)K;
+        g.ldb = (int32_t)N;
+        s1.segs.push_back(g);
+        s1.flops += 2.0 * (double)M * (double)N * (double)K;
+      }
+      p.seg_count = (int32_t)s1.segs.size() - p.seg_begin;
+      s1.probs.push_back(p);
+    }
+    s1.bytes = 8.0 * ((double)L.numel + (double)psi.numel + (double)T1->numel);
+    s1.bytes32 = 8.0 * ((double)L.numel + (double)psi.numel) + 4.0 * (double)T1->numel;
+  }
+
+  // ---- steps 2+3: T3 = h . T1 with h = W1.W2, per (a, y) sector pair
+  Step hc, ha;
+  hc.kind = StepKind::HCoef;
+  hc.name = "mpo_coef";
+  ha.kind = StepKind::HApply;
+  ha.name = "mpo_apply";
+  {
+    const LegDesc& lw = L.legs[1];
+    const LegDesc& lt1 = psi.legs[1];
+    const LegDesc& lt2 = psi.legs[2];
+    const LegDesc& ls1 = W1.legs[1];
+    const LegDesc& ls2 = W2.legs[1];
+    const LegDesc& lw3 = W2.legs[3];
+    LegMap mw1(W1.legs[0]), ms1(W1.legs[1]), mt1(W1.legs[2]), mw2(W1.legs[3]);
+    LegMap nw2(W2.legs[0]), ns2(W2.legs[1]), nt2(W2.legs[2]), nw3(W2.legs[3]);
+    LegMap m1[4] = {mw1, ms1, mt1, mw2};
+    LegMap m2[4] = {nw2, ns2, nt2, nw3};
+    LegMap lwm(lw), lt1m(lt1), lt2m(lt2), ls1m(ls1), ls2m(ls2), lw3m(lw3);
+    std::map<std::vector<int64_t>, int32_t> classes;
+    const int nA = (int)psi.legs[0].q.size(), nY = (int)psi.legs[3].q.size();
+    int32_t t[5];
+    for (int ka = 0; ka < nA; ++ka)
+      for (int ky = 0; ky < nY; ++ky) {
+        std::vector<HPlane> ins, outs;
+        std::vector<int64_t> key;   // class key: input then output element triples
+        for (int kw = 0; kw < (int)lw.q.size(); ++kw)
+          for (int k1 = 0; k1 < (int)lt1.q.size(); ++k1)
+            for (int k2 = 0; k2 < (int)lt2.q.size(); ++k2) {
+              t[0] = ka; t[1] = kw; t[2] = k1; t[3] = k2; t[4] = ky;
+              const int64_t b = T1->find(t);
+              if (b < 0) continue;
+              const int64_t gw = lw.g[kw], g1 = lt1.g[k1], g2 = lt2.g[k2], gy = psi.legs[3].g[ky];
+              for (int64_t c = 0; c < gw; ++c)
+                for (int64_t e1 = 0; e1 < g1; ++e1)
+                  for (int64_t e2 = 0; e2 < g2; ++e2) {
+                    ins.push_back({T1->offset[b] + ((c * g1 + e1) * g2 + e2) * gy, gw * g1 * g2 * gy});
+                    key.push_back(lwm.start[kw] + c);
+                    key.push_back(lt1m.start[k1] + e1);
+                    key.push_back(lt2m.start[k2] + e2);
+                  }
+            }
+        key.push_back(-1);
+        for (int k1 = 0; k1 < (int)ls1.q.size(); ++k1)
+          for (int k2 = 0; k2 < (int)ls2.q.size(); ++k2)
+            for (int kw = 0; kw < (int)lw3.q.size(); ++kw) {
+              t[0] = ka; t[1] = k1; t[2] = k2; t[3] = kw; t[4] = ky;
+              const int64_t b = T3->find(t);
+              if (b < 0) continue;
+              const int64_t g1 = ls1.g[k1], g2 = ls2.g[k2], gw = lw3.g[kw], gy = psi.legs[3].g[ky];
+              for (int64_t e1 = 0; e1 < g1; ++e1)
+                for (int64_t e2 = 0; e2 < g2; ++e2)
+                  for (int64_t c = 0; c < gw; ++c) {
+                    outs.push_back({T3->offset[b] + ((e1 * g2 + e2) * gw + c) * gy, g1 * g2 * gw * gy});
+                    key.push_back(ls1m.start[k1] + e1);
+                    key.push_back(ls2m.start[k2] + e2);
+                    key.push_back(lw3m.start[kw] + c);
+                  }
+            }
+        if (outs.empty()) continue;
+        const int nin = (int)ins.size(), nout = (int)outs.size();
+        int32_t cls;
+        auto it = classes.find(key);
+        if (it != classes.end()) {
+          cls = it->second;
+        } else {
+          cls = (int32_t)classes.size();
+          classes[key] = cls;
+          // terms of coef[cls][o][i] = sum_w2 W1[w1,s1,t1,w2] W2[w2,s2,t2,w3]
+          for (int o = 0; o < nout; ++o) {
+            const int64_t S1 = key[3 * nin + 1 + 3 * o], S2 = key[3 * nin + 2 + 3 * o],
+                          W3 = key[3 * nin + 3 + 3 * o];
+            for (int i = 0; i < nin; ++i) {
+              const int64_t Wl = key[3 * i], T1i = key[3 * i + 1], T2i = key[3 * i + 2];
+              for (int64_t w2 = 0; w2 < (int64_t)mw2.sec.size(); ++w2) {
+                const int64_t i1[4] = {Wl, S1, T1i, w2};
+                const int64_t i2[4] = {w2, S2, T2i, W3};
+                const int64_t o1 = elem_offset4(W1, m1, i1);
+                if (o1 < 0) continue;
+                const int64_t o2 = elem_offset4(W2, m2, i2);
+                if (o2 < 0) continue;
+                Step::RawTerm rt{};
+                rt.cls = cls;
+                rt.o = o;
+                rt.i = i;
+                rt.t.w1_buf = 1;
+                rt.t.w2_buf = 2;
+                rt.t.w1_off = o1;
+                rt.t.w2_off = o2;
+                hc.terms.push_back(rt);
+              }
+            }
+          }
+        }
+        hc.nmax = std::max(hc.nmax, std::max(nin, nout));
+        HTask task{};
+        task.rows = (int32_t)psi.legs[0].g[ka];
+        task.cols = (int32_t)psi.legs[3].g[ky];
+        task.cls = cls;
+        task.nin = nin;
+        task.nout = nout;
+        task.plane_begin = (int32_t)ha.planes.size();
+        task.in_buf = 6;
+        task.out_buf = 7;
+        for (auto& q : ins) ha.planes.push_back(q);
+        for (auto& q : outs) ha.planes.push_back(q);
+        ha.tasks.push_back(task);
+      }
+    hc.ncls = (int32_t)classes.size();
+    ha.ncls = hc.ncls;
+    ha.nmax = hc.nmax;
+    // algorithmic flops of the two pairwise MPO contractions
+    // step 2: T1[a,w1,t1,t2,y] . W1[w1,s1,t1,w2]; step 3: T2[a,t2,y,s1,w2] . W2[w2,s2,t2,w3]
+    double f2 = 0, f3 = 0;
+    int32_t wt[4];
+    for (int64_t b = 0; b < T1->nblocks; ++b) {
+      const int32_t* tb = T1->block_qn(b);
+      for (int ks = 0; ks < (int)W1.legs[1].q.size(); ++ks)
+        for (int kw2 = 0; kw2 < (int)W1.legs[3].q.size(); ++kw2) {
+          wt[0] = tb[1]; wt[1] = ks; wt[2] = tb[2]; wt[3] = kw2;
+          if (W1.find(wt) < 0) continue;
+          f2 += 2.0 * (double)T1->block_size(b) * (double)(W1.legs[1].g[ks] * W1.legs[3].g[kw2]);
+        }
+    }
+    auto T2 = make_tensor({lab(psi.legs[0], "a"), lab(psi.legs[2], "t2"), lab(psi.legs[3], "y"),
+                           lab(W1.legs[1], "s1"), lab(W1.legs[3], "w2")});
+    for (int64_t b = 0; b < T2->nblocks; ++b) {
+      const int32_t* tb = T2->block_qn(b);
+      for (int ks = 0; ks < (int)W2.legs[1].q.size(); ++ks)
+        for (int kw3 = 0; kw3 < (int)W2.legs[3].q.size(); ++kw3) {
+          wt[0] = tb[4]; wt[1] = ks; wt[2] = tb[1]; wt[3] = kw3;
+          if (W2.find(wt) < 0) continue;
+          f3 += 2.0 * (double)T2->block_size(b) * (double)(W2.legs[1].g[ks] * W2.legs[3].g[kw3]);
+        }
+    }
+    ha.flops = f2 + f3;
+    ha.bytes = 8.0 * ((double)T1->numel + (double)T3->numel);
+    ha.bytes32 = 4.0 * ((double)T1->numel + (double)T3->numel);
+  }
+
+  // ---- step 4: out[(a s1 s2) x b] = sum_(w3,y) T3[(a s1 s2) x (w3 y)] R[b x (w3 y)]^T
+  Step s4;
+  s4.kind = StepKind::Gemm;
+  s4.name = "gemm_T3_R";
+  s4.ta = Elem::Inter;
+  s4.transb = true;
+  {
+    const int nW = (int)W2.legs[3].q.size(), nY = (int)psi.legs[3].q.size();
+    int32_t tt[5], rt[3];
+    for (int64_t cb = 0; cb < psi.nblocks; ++cb) {
+      const int32_t* t = psi.block_qn(cb);
+      const int64_t* sh = psi.block_shape(cb);
+      GemmProb p{};
+      const int64_t M = sh[0] * sh[1] * sh[2], N = sh[3];
+      p.c_off = psi.offset[cb];
+      p.c_buf = 5;
+      p.M = (int32_t)M;
+      p.N = (int32_t)N;
+      p.ldc = (int32_t)N;
+      p.seg_begin = (int32_t)s4.segs.size();
+      for (int kw = 0; kw < nW; ++kw)
+        for (int ky = 0; ky < nY; ++ky) {
+          tt[0] = t[0]; tt[1] = t[1]; tt[2] = t[2]; tt[3] = kw; tt[4] = ky;
+          rt[0] = t[3]; rt[1] = kw; rt[2] = ky;
+          const int64_t ab = T3->find(tt), bb = R.find(rt);
+          if (ab < 0 || bb < 0) continue;
+          const int64_t K = W2.legs[3].g[kw] * psi.legs[3].g[ky];
+          GemmSeg g{};
+          g.a_off = T3->offset[ab];
+          g.a_buf = 7;
+          g.b_off = R.offset[bb];
+          g.b_buf = 3;
+          g.K = (int32_t)K;
+          g.lda = (int32_t)K;
+          g.ldb = (int32_t)K;
+          s4.segs.push_back(g);
+          s4.flops += 2.0 * (double)M * (double)N * (double)K;
+        }
+      p.seg_count = (int32_t)s4.segs.size() - p.seg_begin;
+      s4.probs.push_back(p);
+    }
+    s4.bytes = 8.0 * ((double)T3->numel + (double)R.numel + (double)psi.numel);
+    s4.bytes32 = 4.0 * (double)T3->numel + 8.0 * ((double)R.numel + (double)psi.numel);
+  }
+  P.steps.push_back(std::move(hc));
+  P.steps.push_back(std::move(s1));
+  P.steps.push_back(std::move(ha));
+  P.steps.push_back(std::move(s4));
+}
+
+// Merges n H_eff plans: slot s of plan i becomes base_i + s.
+static void heff_batch(const std::vector<const PlanData*>& subs, PlanData& P) {
+  P.kind = 3;
+  P.nslots = 0;
+  int32_t cls_base = 0;
+  for (size_t i = 0; i < subs.size(); ++i) {
+    const PlanData& S = *subs[i];
+    if (S.kind != 2) fail(BST_E_INVALID, "batch members must be H_eff plans");
+    const int32_t base = P.nslots;
+    for (auto s : S.in_slots) P.in_slots.push_back(base + s);
+    for (auto s : S.out_slots) P.out_slots.push_back(base + s);
+    for (auto n : S.in_numel) P.in_numel.push_back(n);
+    for (auto n : S.out_numel) P.out_numel.push_back(n);
+    for (auto ib : S.internals) P.internals.push_back({base + ib.slot, ib.bytes, 0});
+    if (P.steps.empty()) {
+      for (const auto& st : S.steps) {
+        Step e;
+        e.kind = st.kind;
+        e.name = st.name;
+        e.ta = st.ta;
+        e.tc = st.tc;
+        e.transb = st.transb;
+        e.th = st.th;
+        P.steps.push_back(std::move(e));
+      }
+    }
+    if (P.steps.size() != S.steps.size()) fail(BST_E_INVALID, "inconsistent batch members");
+    for (size_t k = 0; k < S.steps.size(); ++k) {
+      const Step& a = S.steps[k];
+      Step& b = P.steps[k];
+      b.flops += a.flops;
+      b.bytes += a.bytes;
+      b.bytes32 += a.bytes32;
+      if (a.kind == StepKind::Gemm) {
+        const int32_t sb = (int32_t)b.segs.size();
+        for (auto g : a.segs) {
+          g.a_buf += base;
+          g.b_buf += base;
+          b.segs.push_back(g);
+        }
+        for (auto p : a.probs) {
+          p.c_buf += base;
+          p.seg_begin += sb;
+          b.probs.push_back(p);
+        }
+      } else if (a.kind == StepKind::HCoef) {
+        for (auto rt : a.terms) {
+          rt.cls += cls_base;
+          rt.t.w1_buf += base;
+          rt.t.w2_buf += base;
+          b.terms.push_back(rt);
+        }
+        b.ncls += a.ncls;
+        b.nmax = std::max(b.nmax, a.nmax);
+      } else if (a.kind == StepKind::HApply) {
+        const int32_t pb = (int32_t)b.planes.size();
+        for (auto q : a.planes) b.planes.push_back(q);
+        for (auto t : a.tasks) {
+          t.cls += cls_base;
+          t.plane_begin += pb;
+          t.in_buf += base;
+          t.out_buf += base;
+          b.tasks.push_back(t);
+        }
+        b.ncls += a.ncls;
+        b.nmax = std::max(b.nmax, a.nmax);
+      }
+    }
+    // class ids advance by the member's class count
+    for (const auto& st : S.steps)
+      if (st.kind == StepKind::HCoef) cls_base += st.ncls;
+    P.nslots += S.nslots;
+    P.psi_numel += S.psi_numel;
+  }
+}
+
+// ------------------------------------------------------------------------
+// Finalize: device tables laid out in one blob, workspace layout
+// ------------------------------------------------------------------------
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+template <typename T>
+static size_t put(std::vector<uint8_t>& blob, const std::vector<T>& v) {
+  size_t off = align256(blob.size());
+  blob.resize(off + v.size() * sizeof(T));
+  if (!v.empty()) std::memcpy(blob.data() + off, v.data(), v.size() * sizeof(T));
+  return off;
+}
+
+static int round_nmax(int n) {
+  if (n <= 8) return 8;
+  if (n <= 16) return 16;
+  if (n <= 32) return 32;
+  if (n <= 64) return 64;
+  fail(BST_E_INVALID, "two-site MPO apply needs more than 64 channels per sector pair");
+}
+
+// Tiles of a grouped GEMM for one tile shape, largest cost first (a stable
+// sort keeps the tiles of one problem together).
+static std::vector<GemmTile> make_tiles(const Step& st, int bm, int bn) {
+  struct TC {
+    double cost;
+    GemmTile t;
+  };
+  std::vector<TC> v;
+  for (size_t pi = 0; pi < st.probs.size(); ++pi) {
+    const auto& p = st.probs[pi];
+    int64_t k = 0;
+    for (int s = 0; s < p.seg_count; ++s) k += st.segs[p.seg_begin + s].K;
+    for (int m0 = 0; m0 < p.M; m0 += bm)
+      for (int n0 = 0; n0 < p.N; n0 += bn) v.push_back({(double)(k + 16), {(int32_t)pi, m0, n0, 0}});
+  }
+  std::stable_sort(v.begin(), v.end(), [](const TC& a, const TC& b) { return a.cost > b.cost; });
+  std::vector<GemmTile> out;
+  out.reserve(v.size());
+  for (auto& x : v) out.push_back(x.t);
+  return out;
+}
+
+int default_tile(const Step& st, bst_precision form) {
+  auto it = st.tile_choice.find((int)form);
+  if (it != st.tile_choice.end()) return it->second;
+  // heuristic: 64x64 unless most problems are small
+  const auto& shapes = gemm_tile_shapes(form);
+  double avg = 0;
+  for (auto& p : st.probs) avg += std::min(p.M, p.N);
+  if (!st.probs.empty()) avg /= (double)st.probs.size();
+  for (size_t i = 0; i < shapes.size(); ++i)
+    if (shapes[i].bm == (avg < 48 ? 32 : 64) && shapes[i].bn == (avg < 48 ? 32 : 64)) return (int)i;
+  return 0;
+}
+
+void finalize(PlanData& P) {
+  P.blob.clear();
+  P.coef_entries = 0;
+  for (auto& st : P.steps) {
+    switch (st.kind) {
+      case StepKind::Gemm: {
+        st.off0 = put(P.blob, st.probs);
+        st.off1 = put(P.blob, st.segs);
+        st.tile_lists.clear();
+        for (int f = 0; f < 4; ++f)
+          for (const auto& sh : gemm_tile_shapes((bst_precision)f)) {
+            auto key = std::make_pair(sh.bm, sh.bn);
+            if (st.tile_lists.count(key)) continue;
+            auto tl = make_tiles(st, sh.bm, sh.bn);
+            st.tile_lists[key] = {put(P.blob, tl), (int64_t)tl.size()};
+          }
+        break;
+      }
+      case StepKind::Permute:
+        st.off0 = put(P.blob, st.jobs);
+        st.off1 = put(P.blob, st.pwork);
+        st.n0 = (int64_t)st.pwork.size();
+        break;
+      case StepKind::HCoef: {
+        const int nm = st.terms.empty() && st.ncls == 0 ? 8 : round_nmax(st.nmax);
+        st.nmax = nm;
+        const int64_t nent = (int64_t)st.ncls * nm * nm;
+        std::vector<std::vector<HTerm>> per(nent);
+        for (auto& rt : st.terms) per[((int64_t)rt.cls * nm + rt.o) * nm + rt.i].push_back(rt.t);
+        std::vector<HTerm> flat;
+        std::vector<int32_t> begin(nent + 1, 0);
+        for (int64_t e = 0; e < nent; ++e) {
+          begin[e] = (int32_t)flat.size();
+          for (auto& t : per[e]) flat.push_back(t);
+        }
+        begin[nent] = (int32_t)flat.size();
+        st.off0 = put(P.blob, flat);
+        st.off1 = put(P.blob, begin);
+        st.n0 = nent;
+        P.coef_entries = (int32_t)std::max<int64_t>(P.coef_entries, nent);
+        break;
+      }
+      case StepKind::HApply: {
+        st.nmax = st.ncls == 0 ? 8 : round_nmax(st.nmax);
+        std::vector<HWork> work;
+        for (size_t ti = 0; ti < st.tasks.size(); ++ti) {
+          const int64_t sites = (int64_t)st.tasks[ti].rows * st.tasks[ti].cols;
+          for (int64_t s0 = 0; s0 < sites; s0 += 256) work.push_back({(int32_t)ti, (int32_t)s0});
+        }
+        st.off0 = put(P.blob, st.tasks);
+        st.off1 = put(P.blob, st.planes);
+        st.off2 = put(P.blob, work);
+        st.n0 = (int64_t)work.size();
+        break;
+      }
+    }
+  }
+  size_t off = 0;
+  P.ws_ptr_off = off;
+  off = align256(off + sizeof(void*) * (size_t)std::max(P.nslots, 1));
+  P.ws_blob_off = off;
+  off = align256(off + P.blob.size());
+  P.ws_coef64_off = off;
+  off = align256(off + sizeof(double) * (size_t)std::max(P.coef_entries, 1));
+  P.ws_coef32_off = off;
+  off = align256(off + sizeof(float) * (size_t)std::max(P.coef_entries, 1));
+  for (auto& ib : P.internals) {
+    ib.ws_off = off;
+    off = align256(off + std::max<size_t>(ib.bytes, 8));
+  }
+  P.ws_bytes = off;
+  P.finalized = true;
+  P.uploaded_ws = nullptr;
+  P.last_ptrs.clear();
+  P.id = g_plan_id++;
+}
+
+}  // namespace bst
+
+using namespace bst;
+
+static bst_plan* new_plan() { return new bst_plan; }
+
+extern "C" {
+
+bst_status bst_permute_plan(const bst_tensor* in, const char* const* new_order,
+                            bst_tensor** out_meta, bst_plan** plan) {
+  BST_TRY
+  if (!in || !out_meta || !plan) fail(BST_E_INVALID, "null argument");
+  *out_meta = nullptr;
+  *plan = nullptr;
+  const TensorDesc& T = *desc_of(in);
+  if (T.rank() > 0 && !new_order) fail(BST_E_INVALID, "null label list");
+  std::vector<int> perm;
+  for (int i = 0; i < T.rank(); ++i) {
+    if (!new_order[i]) fail(BST_E_LABEL, "null label");
+    int k = T.label_index(new_order[i]);
+    if (k < 0) fail(BST_E_LABEL, std::string("unknown label '") + new_order[i] + "'");
+    if (std::find(perm.begin(), perm.end(), k) != perm.end())
+      fail(BST_E_LABEL, std::string("label listed twice '") + new_order[i] + "'");
+    perm.push_back(k);
+  }
+  auto out = permuted_desc(T, perm);
+  auto* p = new_plan();
+  PlanData& P = p->p;
+  P.kind = 0;
+  P.in_slots = {0};
+  P.out_slots = {1};
+  P.in_numel = {T.numel};
+  P.out_numel = {out->numel};
+  P.nslots = 2;
+  Step st;
+  st.kind = StepKind::Permute;
+  st.name = "permute";
+  add_permute_jobs(st, T, *out, perm, 0, 1);
+  P.steps.push_back(std::move(st));
+  finalize(P);
+  *plan = p;
+  *out_meta = wrap_tensor(std::move(out));
+  BST_CATCH
+}
+
+bst_status bst_contract_plan(const bst_tensor* A, const bst_tensor* B, bst_precision prec,
+                             bst_tensor** C_meta, bst_plan** plan) {
+  BST_TRY
+  if (!A || !B || !C_meta || !plan) fail(BST_E_INVALID, "null argument");
+  *C_meta = nullptr;
+  *plan = nullptr;
+  if (prec < BST_FP64 || prec > BST_BF16X6) fail(BST_E_INVALID, "unknown precision");
+  std::unique_ptr<TensorDesc> C;
+  auto* p = new_plan();
+  try {
+    contract_plan(*desc_of(A), *desc_of(B), p->p, C);
+    p->p.prec = prec;
+    finalize(p->p);
+    apply_tune_cache(p->p);
+  } catch (...) {
+    delete p;
+    throw;
+  }
+  *plan = p;
+  *C_meta = wrap_tensor(std::move(C));
+  BST_CATCH
+}
+
+bst_status bst_heff_plan(const bst_tensor* L, const bst_tensor* W1, const bst_tensor* W2,
+                         const bst_tensor* R, const bst_tensor* psi, bst_precision prec,
+                         bst_plan** plan) {
+  BST_TRY
+  if (!L || !W1 || !W2 || !R || !psi || !plan) fail(BST_E_INVALID, "null argument");
+  *plan = nullptr;
+  if (prec < BST_FP64 || prec > BST_BF16X6) fail(BST_E_INVALID, "unknown precision");
+  auto* p = new_plan();
+  try {
+    heff_plan(*desc_of(L), *desc_of(W1), *desc_of(W2), *desc_of(R), *desc_of(psi), p->p);
+    p->p.prec = prec;
+    finalize(p->p);
+    apply_tune_cache(p->p);
+  } catch (...) {
+    delete p;
+    throw;
+  }
+  *plan = p;
+  BST_CATCH
+}
+
+bst_status bst_heff_batch_plan(int32_t n, const bst_plan* const* plans, bst_plan** batch) {
+  BST_TRY
+  if (n < 1 || !plans || !batch) fail(BST_E_INVALID, "bad batch arguments");
+  *batch = nullptr;
+  std::vector<const PlanData*> subs;
+  for (int i = 0; i < n; ++i) {
+    if (!plans[i]) fail(BST_E_INVALID, "null plan");
+    subs.push_back(&plans[i]->p);
+  }
+  auto* p = new_plan();
+  try {
+    heff_batch(subs, p->p);
+    p->p.prec = subs[0]->prec;
+    finalize(p->p);
+    apply_tune_cache(p->p);
+  } catch (...) {
+    delete p;
+    throw;
+  }
+  *batch = p;
+  BST_CATCH
+}
+
+bst_status bst_plan_workspace(const bst_plan* p, size_t* bytes) {
+  BST_TRY
+  if (!p || !bytes) fail(BST_E_INVALID, "null argument");
+  *bytes = p->p.ws_bytes;
+  BST_CATCH
+}
+
+bst_status bst_plan_info(const bst_plan* p, bst_plan_stats* st) {
+  BST_TRY
+  if (!p || !st) fail(BST_E_INVALID, "null argument");
+  std::memset(st, 0, sizeof(*st));
+  const PlanData& P = p->p;
+  for (const auto& s : P.steps) {
+    st->flops += s.flops;
+    st->bytes += s.bytes;
+    if (s.kind == StepKind::Gemm) {
+      st->gemm_flops += s.flops;
+      st->gemm_problems += (int64_t)s.probs.size();
+      const int t = default_tile(s, P.prec);
+      const auto& sh = gemm_tile_shapes(P.prec)[t];
+      auto it = s.tile_lists.find({sh.bm, sh.bn});
+      if (it != s.tile_lists.end()) st->gemm_tiles += it->second.second;
+    }
+  }
+  st->launches = (int64_t)P.steps.size();
+  st->nsteps = (int32_t)P.steps.size();
+  BST_CATCH
+}
+
+bst_status bst_plan_step_info(const bst_plan* p, int32_t step, bst_step_info* info) {
+  BST_TRY
+  if (!p || !info) fail(BST_E_INVALID, "null argument");
+  const PlanData& P = p->p;
+  if (step < 0 || step >= (int32_t)P.steps.size()) fail(BST_E_INVALID, "step out of range");
+  const Step& s = P.steps[step];
+  std::memset(info, 0, sizeof(*info));
+  std::strncpy(info->name, s.name.c_str(), sizeof(info->name) - 1);
+  info->flops = s.flops;
+  info->bytes_fp64 = s.bytes;
+  info->bytes_fp32 = s.bytes32;
+  if (s.kind == StepKind::Gemm) {
+    const int t = default_tile(s, P.prec);
+    const auto& sh = gemm_tile_shapes(P.prec)[t];
+    auto it = s.tile_lists.find({sh.bm, sh.bn});
+    info->items = it == s.tile_lists.end() ? 0 : it->second.second;
+  } else {
+    info->items = s.n0;
+  }
+  BST_CATCH
+}
+
+bst_status bst_plan_set_precision(bst_plan* p, bst_precision prec) {
+  BST_TRY
+  if (!p) fail(BST_E_INVALID, "null plan");
+  if (prec < BST_FP64 || prec > BST_BF16X6) fail(BST_E_INVALID, "unknown precision");
+  p->p.prec = prec;
+  BST_CATCH
+}
+
+bst_status bst_plan_tiles(const bst_plan* p, char* buf, size_t cap) {
+  BST_TRY
+  if (!p || !buf || cap == 0) fail(BST_E_INVALID, "null argument");
+  std::string s;
+  for (const auto& st : p->p.steps) {
+    if (st.kind != StepKind::Gemm) continue;
+    const auto& sh = gemm_tile_shapes(p->p.prec)[default_tile(st, p->p.prec)];
+    s += st.name + ":" + std::to_string(sh.bm) + "x" + std::to_string(sh.bn) + ";";
+  }
+  std::strncpy(buf, s.c_str(), cap - 1);
+  buf[cap - 1] = 0;
+  BST_CATCH
+}
+
+}  // extern "C"

@@ -1,0 +1,129 @@
+// Plans: the integer bookkeeping of a contraction (charge-sector matching,
+// GEMM problem lists, permute jobs, MPO-apply tasks) and its execution.
+#pragma once
+
+#include "bst_internal.h"
+
+struct bst_tensor {
+  std::unique_ptr<bst::TensorDesc> d;
+};
+
+#define BST_TRY try {
+#define BST_CATCH                                            \
+  }                                                          \
+  catch (const bst::Error& e) {                              \
+    bst::set_last_error(e.msg);                              \
+    return e.status;                                         \
+  }                                                          \
+  catch (const std::bad_alloc&) {                            \
+    bst::set_last_error("host out of memory");               \
+    return BST_E_INVALID;                                    \
+  }                                                          \
+  catch (const std::exception& e) {                          \
+    bst::set_last_error(e.what());                           \
+    return BST_E_INVALID;                                    \
+  }                                                          \
+  bst::set_last_error("");                                   \
+  return BST_OK;
+
+namespace bst {
+
+const TensorDesc* desc_of(const bst_tensor* t);
+bst_tensor* wrap_tensor(std::unique_ptr<TensorDesc> d);
+void set_last_error(const std::string& s);
+
+enum class StepKind { Permute, Gemm, HCoef, HApply };
+
+// Element type of a step operand: fixed, or the plan's intermediate type
+// (float64 for BST_FP64, float32 for the other forms).
+enum class Elem { F64, Inter };
+
+struct Step {
+  StepKind kind;
+  std::string name;
+  double flops = 0;   // algorithmic flops of this step
+  double bytes = 0;   // algorithmic HBM bytes with float64 intermediates
+  double bytes32 = 0; // the same with float32 intermediates
+  // GEMM
+  Elem ta = Elem::F64, tc = Elem::F64;
+  bool transb = false;
+  bool fixed_fp64 = false;   // always runs in BST_FP64 (packing-free exact steps)
+  std::vector<GemmProb> probs;
+  std::vector<GemmSeg> segs;
+  std::map<int, int> tile_choice;   // form -> index into gemm_tile_shapes(form)
+  // Permute
+  std::vector<PermJob> jobs;
+  std::vector<PermWork> pwork;
+  // HCoef / HApply (paired: the apply uses the coefficients of the coef step)
+  struct RawTerm {
+    int32_t cls, o, i;
+    HTerm t;
+  };
+  std::vector<RawTerm> terms;
+  int32_t ncls = 0;
+  int32_t nmax = 0;
+  std::vector<HTask> tasks;
+  std::vector<HPlane> planes;
+  Elem th = Elem::Inter;
+  // device table offsets inside the plan blob (filled by finalize)
+  size_t off0 = 0, off1 = 0, off2 = 0, off3 = 0;
+  int64_t n0 = 0, n1 = 0;
+  std::map<std::pair<int, int>, std::pair<size_t, int64_t>> tile_lists;  // (bm,bn) -> (off, n)
+};
+
+struct InternalBuf {
+  int32_t slot;
+  size_t bytes;     // sized for float64
+  size_t ws_off;
+};
+
+struct PlanData {
+  int kind = 0;                 // 0 permute, 1 contract, 2 heff, 3 heff batch
+  bst_precision prec = BST_FP64;
+  std::vector<int32_t> in_slots, out_slots;
+  std::vector<int64_t> in_numel, out_numel;   // elements per buffer (null allowed when 0)
+  std::vector<InternalBuf> internals;
+  int32_t nslots = 0;
+  std::vector<Step> steps;
+  // heff bookkeeping (single apply): psi numel for Lanczos
+  int64_t psi_numel = 0;
+  int64_t t1_numel = 0, t3_numel = 0;
+  // finalize
+  std::vector<uint8_t> blob;
+  size_t ws_ptr_off = 0, ws_blob_off = 0, ws_coef64_off = 0, ws_coef32_off = 0, ws_bytes = 0;
+  int32_t coef_entries = 0;
+  bool finalized = false;
+  // execution state
+  bool use_graph = false;
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  void* graph_ws = nullptr;
+  bst_precision graph_prec = BST_FP64;
+  std::vector<void*> last_ptrs;
+  void* uploaded_ws = nullptr;
+  uint64_t id = 0;
+};
+
+void finalize(PlanData& p);
+// Uploads tables (if this plan's tables are not in ws yet) and the pointer
+// table built from in / out; returns the device address of the pointer table.
+void* prepare_ws(PlanData& p, const void* const* in, void* const* out, void* ws, hipStream_t s);
+// Uploads an extra pointer table at ws + off (Lanczos) and returns it.
+void* upload_table(PlanData& p, const std::vector<void*>& ptrs, void* ws, size_t off,
+                   hipStream_t s);
+std::vector<void*> build_ptrs(PlanData& p, const void* const* in, void* const* out, void* ws);
+// Enqueues the plan's kernels with the given device pointer table.
+void run_steps(PlanData& p, void* ws, void* const* dptrs, bst_precision prec, hipStream_t s,
+               bool skip_coef, std::vector<std::pair<hipEvent_t, hipEvent_t>>* ev = nullptr);
+int default_tile(const Step& st, bst_precision form);
+void run_steps_impl(PlanData& p, void* ws, void* const* dptrs, bst_precision prec, hipStream_t s,
+                    bool skip_coef, int only_step,
+                    std::vector<std::pair<hipEvent_t, hipEvent_t>>* ev);
+// Applies tile choices recorded by the autotuner (file named by BST_TUNE_CACHE).
+void apply_tune_cache(PlanData& p);
+
+}  // namespace bst
+
+struct bst_plan {
+  bst::PlanData p;
+};

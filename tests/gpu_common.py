@@ -1,0 +1,77 @@
+"""Shared pieces of the GPU parity tests: operand generation on the host
+(seeded, identical buffers for the oracle and the library), device copies
+and error metrics."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import oracle as orc  # noqa: E402
+from paper_2401_01921_amd import bst, workloads as wl  # noqa: E402
+
+DEV = "cuda"
+
+
+def require_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+
+
+def dev(x: np.ndarray):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).to(DEV)
+
+
+def host(t) -> np.ndarray:
+    return t.detach().cpu().numpy()
+
+
+def rel_err(got: np.ndarray, ref: np.ndarray):
+    """(normwise relative error, max-abs error over max |ref|)."""
+    nr = np.linalg.norm(ref)
+    if nr == 0:
+        return float(np.linalg.norm(got)), float(np.max(np.abs(got), initial=0.0))
+    return (float(np.linalg.norm(got - ref) / nr),
+            float(np.max(np.abs(got - ref)) / np.max(np.abs(ref))))
+
+
+# Tolerances of the arithmetic forms (normwise relative error of one
+# contraction or H_eff apply against the float64 oracle): float64 rounding;
+# float32 operands and accumulation; bf16 split with 2 and 3 planes.
+TOL = {"fp64": 1e-12, "fp32": 2e-6, "bf16x3": 5e-5, "bf16x6": 2e-6}
+
+
+def heff_operands(k: int, recipe: str = "normal", chi=None, qmax=None, spin=None):
+    """Oracle tensors and host data of an H_eff workload."""
+    wlk = wl.WORKLOADS[k]
+    spin = spin or wlk["spin"]
+    v = wl.gaussian_sector_dims(chi or wlk["chi"], qmax if qmax is not None else wlk["qmax"])
+    specs = wl.heff_specs(spin, v, v)
+    O = {n: orc.BlockTensor(*s) for n, s in specs.items()}
+    if recipe == "normal":
+        O["L"].data[:] = wl.normal(wl.seed_for(k, "L"), O["L"].numel)
+        O["R"].data[:] = wl.normal(wl.seed_for(k, "R"), O["R"].numel)
+    else:
+        O["L"].data[:] = wl.dmrg_like_env(O["L"].table(), O["L"].numel, wl.seed_for(k, "L"), "L", v)
+        O["R"].data[:] = wl.dmrg_like_env(O["R"].table(), O["R"].numel, wl.seed_for(k, "R"), "R", v)
+    Wd = wl.heisenberg_mpo_dense(spin)
+    O["W1"] = orc.from_dense(*specs["W1"], Wd)
+    O["W2"] = orc.from_dense(*specs["W2"], Wd)
+    O["psi"].data[:] = wl.normal(wl.seed_for(k, "psi"), O["psi"].numel)
+    return specs, O
+
+
+def lib_heff(specs, prec="fp64"):
+    T = {n: bst.Tensor(*s) for n, s in specs.items()}
+    plan = bst.heff_plan(T["L"], T["W1"], T["W2"], T["R"], T["psi"], prec)
+    return T, plan
+
+
+def run_heff(plan, O, prec=None):
+    if prec is not None:
+        plan.set_precision(prec)
+    ins = [dev(O[n].data) for n in ("L", "W1", "W2", "R", "psi")]
+    out = torch.empty(O["psi"].numel, dtype=torch.float64, device=DEV)
+    ws = bst.workspace(plan.workspace_bytes)
+    plan.execute(ins, [out], ws)
+    torch.cuda.synchronize()
+    return host(out)

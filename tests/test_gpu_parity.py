@@ -1,0 +1,169 @@
+"""GPU parity through the C ABI: permute (bit-exact), pairwise contraction and
+H_eff.psi in every arithmetic form against the float64 oracle, on seeded
+inputs shared by both sides."""
+import numpy as np
+import pytest
+
+from tests.gpu_common import (DEV, TOL, dev, heff_operands, host, lib_heff, rel_err, require_gpu,
+                              run_heff, torch)
+from tests.helpers import _random_pair
+from oracle import oracle as orc
+from paper_2401_01921_amd import bst, workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def _print(*a):
+    print(*a, flush=True)
+
+
+def test_permute_bit_exact_random_structures():
+    rng = np.random.default_rng(11)
+    for case in range(25):
+        rank = int(rng.integers(1, 6))
+        legs = []
+        for _ in range(rank):
+            ns = int(rng.integers(1, 4))
+            qs = sorted(rng.choice(np.arange(-2, 3), ns, replace=False).tolist())
+            legs.append((int(rng.choice([1, -1])), [(q, int(rng.integers(1, 40))) for q in qs]))
+        labels = [f"l{i}" for i in range(rank)]
+        O = orc.BlockTensor(labels, legs)
+        if O.numel == 0 or O.numel > 3_000_000:
+            continue
+        O.data[:] = wl.normal(100 + case, O.numel)
+        order = [labels[i] for i in rng.permutation(rank)]
+        _print("permute case", case, rank, O.numel, order)
+        P = orc.permute(O, order)
+        T = bst.Tensor(labels, legs)
+        out_t, plan = bst.permute_plan(T, order)
+        x = dev(O.data)
+        y = torch.full((out_t.numel,), np.nan, dtype=torch.float64, device=DEV)
+        ws = bst.workspace(plan.workspace_bytes)
+        plan.execute([x], [y], ws)
+        torch.cuda.synchronize()
+        assert np.array_equal(host(y), P.data)
+
+
+def test_permute_paper_example():
+    T = bst.Tensor(["a", "b", "c"], [(1, [(0, 2)]), (1, [(0, 2)]), (-1, [(0, 2)])])
+    out_t, plan = bst.permute_plan(T, ["a", "c", "b"])
+    y = torch.empty(8, dtype=torch.float64, device=DEV)
+    plan.execute([dev(np.arange(8.0))], [y], bst.workspace(plan.workspace_bytes))
+    torch.cuda.synchronize()
+    assert host(y).tolist() == [0, 2, 1, 3, 4, 6, 5, 7]
+
+
+def _contract_case(A, B, prec):
+    C = orc.contract(A, B)
+    tA, tB = bst.Tensor(A.labels, A.legs), bst.Tensor(B.labels, B.legs)
+    tC, plan = bst.contract_plan(tA, tB, prec)
+    out = torch.full((tC.numel,), np.nan, dtype=torch.float64, device=DEV)
+    plan.execute([dev(A.data), dev(B.data)], [out], bst.workspace(plan.workspace_bytes))
+    torch.cuda.synchronize()
+    return host(out), C.data
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "bf16x6"])
+def test_pairwise_workload(prec):
+    specs = wl.pairwise_specs()
+    A = orc.BlockTensor(*specs["A"])
+    B = orc.BlockTensor(*specs["B"])
+    A.data[:] = wl.normal(wl.seed_for(1, "A"), A.numel)
+    B.data[:] = wl.normal(wl.seed_for(1, "B"), B.numel)
+    got, ref = _contract_case(A, B, prec)
+    nrm, mx = rel_err(got, ref)
+    _print("pairwise", prec, nrm, mx)
+    assert nrm <= TOL[prec]
+    # the two output blocks nothing reaches are exact zeros
+    zero = np.zeros_like(ref, dtype=bool)
+    C = orc.contract(A, B)
+    for b in range(len(C.blocks)):
+        if not np.any(C.block(b)):
+            zero[C.offsets[b]:C.offsets[b] + C.block(b).size] = True
+    assert zero.sum() > 0 and np.all(got[zero] == 0.0)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+def test_random_contractions(prec):
+    """Random structures and label orders: covers A packing, B packing,
+    transposed B, outer products, full contractions and ragged tiles."""
+    rng = np.random.default_rng(21)
+    for case in range(30):
+        ra, rb = int(rng.integers(1, 5)), int(rng.integers(1, 5))
+        nc = min(int(rng.integers(0, 4)), ra, rb)
+        A, B = _random_pair(rng, ra, rb, nc)
+        # stretch the dims so that tiles are ragged and span several tiles
+        free = [i for i, l in enumerate(A.labels) if l not in B.labels]
+        if free:
+            scale = int(rng.integers(1, 30))
+            A = orc.BlockTensor(A.labels, [(d, [(q, g * scale if i == free[0] else g) for q, g in s])
+                                           for i, (d, s) in enumerate(A.legs)])
+            A.data[:] = rng.standard_normal(A.numel)
+        if A.numel == 0 or B.numel == 0:
+            continue
+        got, ref = _contract_case(A, B, prec)
+        nrm, _ = rel_err(got, ref)
+        _print("contract case", case, A.labels, B.labels, nrm)
+        assert nrm <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "bf16x6"])
+def test_heff_spin_half_chi512(prec):
+    specs, O = heff_operands(2)
+    ref = orc.heff_apply(O["L"], O["W1"], O["W2"], O["R"], O["psi"]).data
+    T, plan = lib_heff(specs, prec)
+    got = run_heff(plan, O)
+    nrm, mx = rel_err(got, ref)
+    _print("heff chi512", prec, nrm, mx)
+    assert nrm <= TOL[prec]
+
+
+def test_heff_fp64_is_deterministic():
+    specs, O = heff_operands(2)
+    T, plan = lib_heff(specs, "fp64")
+    a = run_heff(plan, O)
+    b = run_heff(plan, O)
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "bf16x6"])
+def test_heff_spin_half_chi2048_error_table(prec):
+    specs, O = heff_operands(3)
+    ref = orc.heff_apply(O["L"], O["W1"], O["W2"], O["R"], O["psi"]).data
+    T, plan = lib_heff(specs, prec)
+    got = run_heff(plan, O)
+    nrm, mx = rel_err(got, ref)
+    _print("heff chi2048", prec, "normwise", nrm, "max", mx)
+    assert nrm <= TOL[prec]
+
+
+def test_heff_spin_one_chi4096_fp64():
+    """The Lanczos workload's operator at full size, float64 form."""
+    specs, O = heff_operands(5, recipe="dmrg_like")
+    ref = orc.heff_apply(O["L"], O["W1"], O["W2"], O["R"], O["psi"]).data
+    T, plan = lib_heff(specs, "fp64")
+    got = run_heff(plan, O)
+    nrm, mx = rel_err(got, ref)
+    _print("heff chi4096 fp64", nrm, mx)
+    assert nrm <= TOL["fp64"]
+
+
+def test_heff_graph_replay_matches_eager():
+    specs, O = heff_operands(2)
+    T, plan = lib_heff(specs, "bf16x3")
+    eager = run_heff(plan, O)
+    plan.use_graph(True)
+    ins = [dev(O[n].data) for n in ("L", "W1", "W2", "R", "psi")]
+    ws = bst.workspace(plan.workspace_bytes)
+    for rep in range(4):
+        out = torch.full((O["psi"].numel,), np.nan, dtype=torch.float64, device=DEV)
+        plan.execute(ins, [out], ws)
+        torch.cuda.synchronize()
+        junk = torch.randn(1000, device=DEV).sum().item()   # eager work between replays
+        assert np.array_equal(host(out), eager), rep
+    plan.use_graph(False)

@@ -9,6 +9,7 @@ from hypothesis import given, settings, strategies as st
 from oracle import oracle as orc
 from paper_2401_01921_amd import workloads as wl
 from tests.test_oracle_structure import _paper_examples
+from tests.helpers import _random_pair, _einsum_reference
 
 
 def dense_leg(n):
@@ -45,37 +46,6 @@ def test_ones_closed_forms():
     M1 = ones(["i", "j"], [dense_leg(2), dense_out(2)])
     M2 = ones(["j", "k"], [dense_leg(2), dense_out(2)])
     assert np.all(orc.contract(M1, M2).data == float(ex["network_matmul_value"]))
-
-
-def _random_pair(rng, rank_a, rank_b, ncommon):
-    def leg(d):
-        ns = int(rng.integers(1, 4))
-        qs = sorted(rng.choice(np.arange(-2, 3), ns, replace=False).tolist())
-        return (d, [(q, int(rng.integers(1, 4))) for q in qs])
-    la = [leg(int(rng.choice([1, -1]))) for _ in range(rank_a)]
-    lb = [leg(int(rng.choice([1, -1]))) for _ in range(rank_b)]
-    la_lab = [f"a{i}" for i in range(rank_a)]
-    lb_lab = [f"b{i}" for i in range(rank_b)]
-    ia = rng.choice(rank_a, ncommon, replace=False)
-    ib = rng.choice(rank_b, ncommon, replace=False)
-    for n, (i, j) in enumerate(zip(ia, ib)):
-        la_lab[i] = lb_lab[j] = f"c{n}"
-        lb[j] = (-la[i][0], list(la[i][1]))
-    A = orc.BlockTensor(la_lab, la)
-    B = orc.BlockTensor(lb_lab, lb)
-    A.data[:] = rng.standard_normal(A.numel)
-    B.data[:] = rng.standard_normal(B.numel)
-    return A, B
-
-
-def _einsum_reference(A, B):
-    letters = "abcdefghijklmnopqrstuvwxyz"
-    labs = {l: letters[i] for i, l in enumerate(dict.fromkeys(A.labels + B.labels))}
-    sa = "".join(labs[l] for l in A.labels)
-    sb = "".join(labs[l] for l in B.labels)
-    out = [l for l in A.labels if l not in B.labels] + [l for l in B.labels if l not in A.labels]
-    so = "".join(labs[l] for l in out)
-    return np.einsum(f"{sa},{sb}->{so}", orc.embed(A), orc.embed(B))
 
 
 @settings(max_examples=60, deadline=None)
