@@ -176,3 +176,23 @@ def test_planted_mpo_sign_error_is_caught():
     ops = heff_tensors(Ld, Rd, bad, specs)
     ev = np.linalg.eigvalsh(heff_matrix(*ops))
     assert abs(ev[0] + 0.75) > 1e-3
+
+
+def test_heff_flop_count_closed_form():
+    """With one sector per leg (dense tensors) the algorithmic flops of the
+    four steps have closed forms: 2 chi^2 D (chi d^2) for L.psi, 2 (chi d^2
+    chi D) d D for each MPO step (K = D d, N = d D), 2 (chi d^2) chi (D chi)
+    for T3.R."""
+    chi, D, d = 6, 5, 2
+    legs_v = [(0, chi)]
+    ph = [(0, d)]
+    mb = [(0, D)]
+    L = orc.BlockTensor(["a", "w", "ap"], [(1, legs_v), (-1, mb), (-1, legs_v)])
+    R = orc.BlockTensor(["b", "w", "bp"], [(-1, legs_v), (1, mb), (1, legs_v)])
+    W = orc.BlockTensor(["wl", "s", "sp", "wr"], [(1, mb), (1, ph), (-1, ph), (-1, mb)])
+    psi = orc.BlockTensor(["a", "s1", "s2", "b"], [(1, legs_v), (1, ph), (1, ph), (-1, legs_v)])
+    f = orc.heff_flops(L, W, W, R, psi)
+    assert f[0] == 2 * (chi * D) * chi * (d * d * chi)
+    assert f[1] == 2 * (chi * d * chi) * (D * d) * (d * D)
+    assert f[2] == 2 * (chi * d * chi) * (D * d) * (d * D)
+    assert f[3] == 2 * (chi * d * d) * (D * chi) * chi
