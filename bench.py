@@ -39,9 +39,11 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--prec", default="bf16x6", choices=["fp32", "bf16x3", "bf16x6", "fp64"])
+    ap.add_argument("--prec", default="bf16x3", choices=["fp32", "bf16x3", "bf16x6", "fp64"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the single-apply, batched-apply and permute measurements")
     return ap.parse_args()
 
 
@@ -88,6 +90,16 @@ def main():
     psi_out = torch.empty(n, dtype=torch.float64, device=dev)
     apply_flops = plan.stats().flops
     step_flops = (m + 1) * apply_flops + lanczos_vector_flops(n, m)
+
+    # autotune the tile variant of every GEMM step for both forms (untimed)
+    tune_out = torch.empty(n, dtype=torch.float64, device=dev)
+    tune_ws = bst.workspace(plan.workspace_bytes)
+    tuned = {}
+    for prec in (a.prec, "fp64"):
+        plan.set_precision(prec)
+        plan.autotune([g["L"], g["W1"], g["W2"], g["R"], g["psi0"]], [tune_out], tune_ws, reps=3)
+        tuned[prec] = plan.tiles()
+    del tune_ws, tune_out
 
     def solve(prec, timing=False):
         return bst.lanczos_ground(plan, ops, g["psi0"], m, prec, True, ws=ws, psi_out=psi_out,
@@ -174,6 +186,9 @@ def main():
                 "peak": PEAK["hbm_gbs"], "unit": "GB/s", "frac": round(r["frac"], 4),
                 "traffic": None, "alg_bytes_per_launch": per_launch}
 
+    extras = {} if a.no_extras else bench_extras(bst, wl, torch, dev, plan, ins_apply=[
+        g["L"], g["W1"], g["W2"], g["R"], g["psi0"]], apply_flops=apply_flops)
+
     # ---- CPU baseline: the oracle's H_eff apply on the host cores ----------
     cpu = None
     if not a.no_cpu:
@@ -207,8 +222,82 @@ def main():
         "kernels_split": {k: round(v, 4) for k, v in km.items()},
         "kernels_fp64": {k: round(v, 4) for k, v in prof64["kernel_ms"].items()},
         "kernel_roofline": kern,
+        "tiles": tuned,
+        "extras": extras,
     }
     print(json.dumps(out), flush=True)
+
+
+def _time_ms(torch, fn, reps, warm=2):
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps * 1e3
+
+
+def bench_extras(bst, wl, torch, dev, plan, ins_apply, apply_flops):
+    """Single H_eff applies per form, the 64-apply batched launch (one
+    hipGraph per step sequence) and the block permute on a tensor above 1 GiB."""
+    out = {}
+    # single applies of the chi=4096 operator, every form (tuned tiles)
+    res = torch.empty_like(ins_apply[4])
+    ws = bst.workspace(plan.workspace_bytes)
+    forms = {}
+    for prec in ("fp64", "fp32", "bf16x3", "bf16x6"):
+        plan.set_precision(prec)
+        if prec in ("fp32", "bf16x6"):
+            plan.autotune(ins_apply, [res], ws, reps=3)
+        ms = _time_ms(torch, lambda: plan.execute(ins_apply, [res], ws), 20)
+        forms[prec] = {"ms": round(ms, 4), "gflops": round(apply_flops / ms / 1e6, 1)}
+    out["apply_chi4096"] = forms
+    del ws, res
+    # batched: 64 uneven spin-1/2 applies, all sector GEMMs of a step in one launch
+    members, ins, outs = [], [], []
+    W = None
+    for i, (chi, q) in enumerate(wl.batch_draws()):
+        v = wl.gaussian_sector_dims(chi, q)
+        T = {k: bst.Tensor(*s) for k, s in wl.heff_specs("1/2", v, v).items()}
+        if W is None:
+            W = torch.from_numpy(T["W1"].from_dense(wl.heisenberg_mpo_dense("1/2"))).to(dev)
+        p = bst.heff_plan(T["L"], T["W1"], T["W2"], T["R"], T["psi"], "bf16x3")
+        members.append(p)
+        ins += [torch.randn(T["L"].numel, dtype=torch.float64, device=dev), W, W,
+                torch.randn(T["R"].numel, dtype=torch.float64, device=dev),
+                torch.randn(T["psi"].numel, dtype=torch.float64, device=dev)]
+        outs.append(torch.empty(T["psi"].numel, dtype=torch.float64, device=dev))
+    batch = bst.heff_batch_plan(members)
+    bflops = batch.stats().flops
+    wsb = bst.workspace(batch.workspace_bytes)
+    batch.autotune(ins, outs, wsb, reps=3)
+    batch.use_graph(True)
+    ms_b = _time_ms(torch, lambda: batch.execute(ins, outs, wsb), 20)
+    batch.use_graph(False)
+    ms_e = _time_ms(torch, lambda: batch.execute(ins, outs, wsb), 20)
+    out["batch64_bf16x3"] = {"ms_graph": round(ms_b, 4), "ms_eager": round(ms_e, 4),
+                             "gflops_graph": round(bflops / ms_b / 1e6, 1), "flops": bflops,
+                             "kernels_per_execute": batch.stats().nsteps,
+                             "gemm_problems": batch.stats().gemm_problems}
+    del wsb, ins, outs, batch, members
+    # block permute of a 1.2 GiB tensor (c, a, b) <- (a, b, c)
+    sec = [(q, 150) for q in range(-3, 4)]
+    T = bst.Tensor(["a", "b", "c"], [(1, sec), (1, sec), (-1, [(q, 150) for q in range(-6, 7)])])
+    Tp, pplan = bst.permute_plan(T, ["c", "a", "b"])
+    x = torch.randn(T.numel, dtype=torch.float64, device=dev)
+    y = torch.empty(T.numel, dtype=torch.float64, device=dev)
+    wsp = bst.workspace(pplan.workspace_bytes)
+    ms_p = _time_ms(torch, lambda: pplan.execute([x], [y], wsp), 10)
+    prof = pplan.profile([x], [y], wsp, reps=5)
+    kms = prof[0][1]
+    out["permute"] = {"numel": T.numel, "gib": round(T.numel * 8 / 2**30, 3), "blocks": T.nblocks,
+                      "ms": round(ms_p, 4), "kernel_ms": round(kms, 4),
+                      "gbs": round(2 * 8 * T.numel / kms / 1e6, 1),
+                      "hbm_frac": round(2 * 8 * T.numel / kms / 1e6 / PEAK["hbm_gbs"], 4)}
+    del x, y, wsp
+    return out
 
 
 def cpu_baseline(specs, host, apply_flops, seconds):

@@ -208,6 +208,12 @@ bst_status bst_execute(bst_plan* p, const void* const* in, void* const* out, voi
 bst_status bst_plan_autotune(bst_plan* p, const void* const* in, void* const* out, void* ws,
                              void* stream, int32_t reps);
 
+/* Number of compiled GEMM kernel variants (tile shape, with or without LDS
+ * staging) available to the plan's GEMM steps in the given form, and a manual
+ * choice of one of them for every GEMM step (0 <= tile < count). */
+bst_status bst_plan_tile_count(const bst_plan* p, bst_precision form, int32_t* count);
+bst_status bst_plan_set_tile(bst_plan* p, bst_precision form, int32_t tile);
+
 /* Tile shapes chosen for the plan's GEMM steps, as text ("step:BMxBN;...")
  * written into buf (NUL-terminated, truncated to cap). */
 bst_status bst_plan_tiles(const bst_plan* p, char* buf, size_t cap);

@@ -27,6 +27,7 @@ EXPORTS = [
     "bst_plan_step_info", "bst_plan_set_precision", "bst_plan_use_graph", "bst_execute",
     "bst_plan_autotune", "bst_plan_tiles", "bst_plan_profile", "bst_plan_destroy",
     "bst_lanczos_workspace", "bst_lanczos_ground", "bst_last_error", "bst_version",
+    "bst_plan_tile_count", "bst_plan_set_tile",
 ]
 
 
@@ -54,7 +55,7 @@ class LanczosInfo(C.Structure):
                 ("kernel_calls", C.c_int32 * 8)]
 
 
-LANCZOS_KERNEL_CLASSES = ["gemm_L_psi", "mpo_apply", "gemm_T3_R", "mpo_coef", "cgs_pass1",
+LANCZOS_KERNEL_CLASSES = ["gemm_L_psi", "mpo_apply", "gemm_T3_R", "prep", "cgs_pass1",
                           "cgs_pass2", "cgs_pass3", "vector_other"]
 
 
@@ -83,6 +84,8 @@ def _load():
         "bst_execute": [vp, P(vp), P(vp), vp, vp],
         "bst_plan_autotune": [vp, P(vp), P(vp), vp, vp, i32],
         "bst_plan_tiles": [vp, C.c_char_p, sz],
+        "bst_plan_tile_count": [vp, C.c_int, P(i32)],
+        "bst_plan_set_tile": [vp, C.c_int, i32],
         "bst_plan_profile": [vp, P(vp), P(vp), vp, vp, i32, P(C.c_double), i32, P(i32)],
         "bst_plan_destroy": [vp],
         "bst_lanczos_workspace": [vp, i32, P(sz)],
@@ -283,6 +286,14 @@ class Plan:
 
     def use_graph(self, on: bool = True):
         _check(_lib.bst_plan_use_graph(self._h, 1 if on else 0))
+
+    def tile_count(self, prec) -> int:
+        n = C.c_int32()
+        _check(_lib.bst_plan_tile_count(self._h, _prec(prec), C.byref(n)))
+        return n.value
+
+    def set_tile(self, prec, tile: int):
+        _check(_lib.bst_plan_set_tile(self._h, _prec(prec), tile))
 
     def tiles(self) -> str:
         buf = C.create_string_buffer(4096)

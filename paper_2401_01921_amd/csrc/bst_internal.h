@@ -76,6 +76,7 @@ struct GemmSeg {
   int64_t a_off, b_off;
   int32_t a_buf, b_buf;
   int32_t K, lda, ldb, pad;
+  int64_t a_ps, b_ps;   // plane strides (elements) of bfloat16 plane operands
 };
 // One output block: C[M x N] row-major (ldc) = sum over its segments.
 struct GemmProb {
@@ -115,6 +116,20 @@ struct HTask {
   int32_t nin, nout;
   int32_t plane_begin;       // nin input planes then nout output planes
   int32_t in_buf, out_buf;
+  int64_t out_ps;            // plane stride of a bfloat16-plane output
+};
+
+// Conversion of float64 blocks into bfloat16 planes with rows padded to a
+// multiple of 8 elements (16 bytes): out[q][out_off + r*out_ld + c] for
+// r < rows, c < out_ld (zero beyond cols).  With transpose set, the block
+// [rows x cols] is written as [cols x rows] (rows padded instead).
+struct SplitJob {
+  int64_t in_off, out_off, out_ps;
+  int32_t in_buf, out_buf;
+  int32_t rows, cols, out_ld, transpose;
+};
+struct SplitWork {
+  int32_t job, r0, c0, pad;
 };
 struct HPlane {
   int64_t off;               // element offset of (row 0, col 0)
@@ -137,6 +152,7 @@ enum class ElemType : int { F64 = 0, F32 = 1 };
 
 struct TileShape {
   int bm, bn;
+  int direct = 0;   // 1: LDS-free kernel (fragments loaded straight from memory)
 };
 // Tile shapes compiled for each arithmetic form.
 const std::vector<TileShape>& gemm_tile_shapes(bst_precision form);
@@ -153,6 +169,7 @@ struct GemmLaunch {
   int64_t ntiles;
 };
 hipError_t launch_gemm(const GemmLaunch& g, hipStream_t s);
+hipError_t launch_gemm_direct(const GemmLaunch& g, int bm, int bn, hipStream_t s);
 
 struct PermLaunch {
   const PermJob* jobs;
@@ -165,14 +182,46 @@ hipError_t launch_permute(const PermLaunch& p, hipStream_t s);
 struct HCoefLaunch {
   const HTerm* terms;
   const int32_t* entry_begin;  // nentries + 1
-  int64_t nentries;
+  int64_t nentries;            // ncls * nmax * nmax
+  int nmax;
   void* const* ptrs;
   double* coef64;
   float* coef32;
+  // compacted rows: cnt[ncls*nmax], idx / val[ncls*nmax*nmax]
+  int32_t* cnt;
+  int32_t* idx;
+  double* val64;
+  float* val32;
 };
 hipError_t launch_hcoef(const HCoefLaunch& c, hipStream_t s);
 
+struct SplitLaunch {
+  int np;
+  const SplitJob* jobs;
+  const SplitWork* work;
+  void* const* ptrs;
+  int64_t nwork;
+};
+hipError_t launch_split(const SplitLaunch& l, hipStream_t s);
+
+// Grouped GEMM on pre-split bfloat16 planes: A [M x K] and B [N x K], both
+// with K contiguous, rows padded to 8 elements, float32 accumulate.
+struct PlanesLaunch {
+  int np;                      // 2 (BF16X3) or 3 (BF16X6)
+  ElemType tc;
+  int tile;                    // index into gemm_planes_shapes(np)
+  const GemmTile* tiles;
+  const GemmProb* probs;
+  const GemmSeg* segs;
+  void* const* ptrs;
+  int64_t ntiles;
+};
+const std::vector<TileShape>& gemm_planes_shapes(int np);
+hipError_t launch_gemm_planes(const PlanesLaunch& g, hipStream_t s);
+hipError_t launch_gemm_direct_planes(const PlanesLaunch& g, int bm, int bn, hipStream_t s);
+
 struct HApplyLaunch {
+  int np = 0;                  // > 0: outputs written as np bfloat16 planes
   ElemType t;
   int nmax;
   const HTask* tasks;
@@ -181,8 +230,13 @@ struct HApplyLaunch {
   int64_t nwork;
   void* const* ptrs;
   const void* coef;            // double or float [ncls][nmax][nmax]
+  // compacted nonzero coefficients (sparse kernel, nmax <= 16); null: dense
+  const int32_t* cnt = nullptr;
+  const int32_t* idx = nullptr;
+  const void* val = nullptr;
 };
 hipError_t launch_happly(const HApplyLaunch& h, hipStream_t s);
+hipError_t launch_happly_sparse(const HApplyLaunch& h, hipStream_t s);
 
 // Lanczos vector kernels (float64).  Reductions are deterministic: every
 // block reduces a fixed element range in a fixed order into `partial`
@@ -210,6 +264,14 @@ hipError_t launch_dot2(const double* x, const double* y, int64_t n, double* part
 // e = num[0]/num[1]; out[0] = |hy - e y|^2
 hipError_t launch_resid(const double* hy, const double* y, const double* num, int64_t n,
                         double* partial, double* out, hipStream_t s);
+// Reduces the pass-3 partials (grid of the project kernel for n elements),
+// records alpha[j], beta[j], norm2_out[0] and writes vnext = w / beta_j
+// (vnext may be null on the last step).  launch_project with out == nullptr
+// leaves its partials unreduced for this kernel.
+hipError_t launch_lanczos_step_end(const double* partial, int64_t n_for_grid, const double* c,
+                                   const double* d, int j, double* alpha, double* beta,
+                                   double* norm2_out, const double* w, double* vnext, int64_t n,
+                                   hipStream_t s);
 // alpha[j] = c[j] + d[j]; beta[j] = sqrt(norm2[0])
 hipError_t launch_lanczos_scalars(const double* c, const double* d, int j, const double* norm2,
                                   double* alpha, double* beta, hipStream_t s);

@@ -72,19 +72,62 @@ void* prepare_ws(PlanData& P, const void* const* in, void* const* out, void* ws,
   return static_cast<char*>(ws) + P.ws_ptr_off;
 }
 
+bool uses_planes(const PlanData& P, bst_precision prec) {
+  return P.has_planes && (prec == BST_BF16X3 || prec == BST_BF16X6);
+}
+
+bool step_runs(const PlanData& P, const Step& st, bst_precision prec, bool skip_const) {
+  if (skip_const && st.constant) return false;
+  if (st.kind == StepKind::Split && !uses_planes(P, prec)) return false;
+  return true;
+}
+
+// Tile-choice key of the bfloat16-plane GEMM variant of a form.
+static int planes_key(bst_precision prec) { return 10 + (int)prec; }
+
+int planes_tile(const Step& st, bst_precision prec) {
+  auto it = st.tile_choice.find(planes_key(prec));
+  return it == st.tile_choice.end() ? 4 : it->second;   // default: LDS-staged 64x64
+}
+
 void run_steps_impl(PlanData& P, void* ws, void* const* dptrs, bst_precision prec, hipStream_t s,
-                    bool skip_coef, int only_step,
+                    bool skip_const, int only_step,
                     std::vector<std::pair<hipEvent_t, hipEvent_t>>* ev) {
   const char* blob = static_cast<const char*>(ws) + P.ws_blob_off;
   char* wsb = static_cast<char*>(ws);
   const ElemType inter = (prec == BST_FP64) ? ElemType::F64 : ElemType::F32;
+  const bool planes = uses_planes(P, prec);
+  const int np = prec == BST_BF16X6 ? 3 : 2;
   for (size_t k = 0; k < P.steps.size(); ++k) {
     if (only_step >= 0 && (int)k != only_step) continue;
     Step& st = P.steps[k];
+    if (!step_runs(P, st, prec, skip_const)) continue;
     if (ev) check_hip(hipEventRecord((*ev)[k].first, s), "event");
     hipError_t e = hipSuccess;
     switch (st.kind) {
+      case StepKind::Split: {
+        SplitLaunch l{np, reinterpret_cast<const SplitJob*>(blob + st.off0),
+                      reinterpret_cast<const SplitWork*>(blob + st.off1), dptrs, st.n0};
+        e = launch_split(l, s);
+        break;
+      }
       case StepKind::Gemm: {
+        if (planes && st.has_alt) {
+          PlanesLaunch g{};
+          g.np = np;
+          g.tc = st.tc == Elem::Inter ? ElemType::F32 : ElemType::F64;
+          g.tile = planes_tile(st, prec);
+          const auto& sh = gemm_planes_shapes(np)[g.tile];
+          auto it = st.tile_lists.find({sh.bm, sh.bn});
+          if (it == st.tile_lists.end()) fail(BST_E_INVALID, "internal: missing tile list");
+          g.tiles = reinterpret_cast<const GemmTile*>(blob + it->second.first);
+          g.ntiles = it->second.second;
+          g.probs = reinterpret_cast<const GemmProb*>(blob + st.off0);
+          g.segs = reinterpret_cast<const GemmSeg*>(blob + st.off2);
+          g.ptrs = dptrs;
+          e = launch_gemm_planes(g, s);
+          break;
+        }
         const bst_precision form = st.fixed_fp64 ? BST_FP64 : prec;
         GemmLaunch g{};
         g.form = form;
@@ -111,14 +154,18 @@ void run_steps_impl(PlanData& P, void* ws, void* const* dptrs, bst_precision pre
         break;
       }
       case StepKind::HCoef: {
-        if (skip_coef) break;
         HCoefLaunch c{};
         c.terms = reinterpret_cast<const HTerm*>(blob + st.off0);
         c.entry_begin = reinterpret_cast<const int32_t*>(blob + st.off1);
         c.nentries = st.n0;
         c.ptrs = dptrs;
+        c.nmax = st.nmax;
         c.coef64 = reinterpret_cast<double*>(wsb + P.ws_coef64_off);
         c.coef32 = reinterpret_cast<float*>(wsb + P.ws_coef32_off);
+        c.cnt = reinterpret_cast<int32_t*>(wsb + P.ws_cnt_off);
+        c.idx = reinterpret_cast<int32_t*>(wsb + P.ws_idx_off);
+        c.val64 = reinterpret_cast<double*>(wsb + P.ws_val64_off);
+        c.val32 = reinterpret_cast<float*>(wsb + P.ws_val32_off);
         e = launch_hcoef(c, s);
         break;
       }
@@ -133,6 +180,17 @@ void run_steps_impl(PlanData& P, void* ws, void* const* dptrs, bst_precision pre
         h.ptrs = dptrs;
         h.coef = inter == ElemType::F64 ? (const void*)(wsb + P.ws_coef64_off)
                                         : (const void*)(wsb + P.ws_coef32_off);
+        if (planes && st.has_alt) {
+          h.np = np;
+          h.tasks = reinterpret_cast<const HTask*>(blob + st.off3);
+          h.planes = reinterpret_cast<const HPlane*>(blob + st.off4);
+        }
+        if (P.sparse_mpo) {
+          h.cnt = reinterpret_cast<const int32_t*>(wsb + P.ws_cnt_off);
+          h.idx = reinterpret_cast<const int32_t*>(wsb + P.ws_idx_off);
+          h.val = inter == ElemType::F64 ? (const void*)(wsb + P.ws_val64_off)
+                                         : (const void*)(wsb + P.ws_val32_off);
+        }
         e = launch_happly(h, s);
         break;
       }
@@ -143,8 +201,8 @@ void run_steps_impl(PlanData& P, void* ws, void* const* dptrs, bst_precision pre
 }
 
 void run_steps(PlanData& P, void* ws, void* const* dptrs, bst_precision prec, hipStream_t s,
-               bool skip_coef, std::vector<std::pair<hipEvent_t, hipEvent_t>>* ev) {
-  run_steps_impl(P, ws, dptrs, prec, s, skip_coef, -1, ev);
+               bool skip_const, std::vector<std::pair<hipEvent_t, hipEvent_t>>* ev) {
+  run_steps_impl(P, ws, dptrs, prec, s, skip_const, -1, ev);
 }
 
 static void drop_graph(PlanData& P) {
@@ -211,10 +269,10 @@ void apply_tune_cache(PlanData& P) {
   auto m = load_cache(path);
   for (auto& st : P.steps) {
     if (st.kind != StepKind::Gemm) continue;
-    for (int f = 0; f < 4; ++f) {
+    for (int f : {0, 1, 2, 3, 12, 13}) {
       auto it = m.find(tune_key(P, st, (bst_precision)f));
       if (it == m.end()) continue;
-      const auto& shapes = gemm_tile_shapes((bst_precision)f);
+      const auto& shapes = f >= 10 ? gemm_planes_shapes(f == 13 ? 3 : 2) : gemm_tile_shapes((bst_precision)f);
       for (size_t i = 0; i < shapes.size(); ++i)
         if (shapes[i].bm == it->second.first && shapes[i].bn == it->second.second)
           st.tile_choice[f] = (int)i;
@@ -297,6 +355,7 @@ bst_status bst_plan_profile(bst_plan* p, const void* const* in, void* const* out
     run_steps(P, ws, static_cast<void* const*>(dptrs), P.prec, s, false, &ev);
     check_hip(hipStreamSynchronize(s), "profile sync");
     for (size_t k = 0; k < n; ++k) {
+      if (!step_runs(P, P.steps[k], P.prec, false)) continue;
       float ms = 0;
       check_hip(hipEventElapsedTime(&ms, ev[k].first, ev[k].second), "event time");
       acc[k] += ms;
@@ -331,11 +390,13 @@ bst_status bst_plan_autotune(bst_plan* p, const void* const* in, void* const* ou
     Step& st = P.steps[k];
     if (st.kind != StepKind::Gemm) continue;
     const bst_precision f = st.fixed_fp64 ? BST_FP64 : form;
-    const auto& shapes = gemm_tile_shapes(f);
+    const bool pl = uses_planes(P, form) && st.has_alt;
+    const int key = pl ? planes_key(form) : (int)f;
+    const auto& shapes = pl ? gemm_planes_shapes(form == BST_BF16X6 ? 3 : 2) : gemm_tile_shapes(f);
     double best = 1e30;
-    int best_i = default_tile(st, f);
+    int best_i = pl ? planes_tile(st, form) : default_tile(st, f);
     for (size_t i = 0; i < shapes.size(); ++i) {
-      st.tile_choice[(int)f] = (int)i;
+      st.tile_choice[key] = (int)i;
       run_steps_impl(P, ws, static_cast<void* const*>(dptrs), P.prec, s, false, (int)k, nullptr);
       check_hip(hipEventRecord(e0, s), "event");
       for (int r = 0; r < reps; ++r)
@@ -349,13 +410,44 @@ bst_status bst_plan_autotune(bst_plan* p, const void* const* in, void* const* ou
         best_i = (int)i;
       }
     }
-    st.tile_choice[(int)f] = best_i;
-    cache[tune_key(P, st, f)] = {shapes[best_i].bm, shapes[best_i].bn};
+    st.tile_choice[key] = best_i;
+    cache[tune_key(P, st, (bst_precision)key)] = {shapes[best_i].bm, shapes[best_i].bn};
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   drop_graph(P);
   if (path) save_cache(path, cache);
+  BST_CATCH
+}
+
+static const std::vector<TileShape>& variant_list(const PlanData& P, bst_precision form, bool& planes) {
+  planes = uses_planes(P, form);
+  return planes ? gemm_planes_shapes(form == BST_BF16X6 ? 3 : 2) : gemm_tile_shapes(form);
+}
+
+bst_status bst_plan_tile_count(const bst_plan* p, bst_precision form, int32_t* count) {
+  BST_TRY
+  if (!p || !count) fail(BST_E_INVALID, "null argument");
+  if (form < BST_FP64 || form > BST_BF16X6) fail(BST_E_INVALID, "unknown precision");
+  bool pl;
+  *count = (int32_t)variant_list(p->p, form, pl).size();
+  BST_CATCH
+}
+
+bst_status bst_plan_set_tile(bst_plan* p, bst_precision form, int32_t tile) {
+  BST_TRY
+  if (!p) fail(BST_E_INVALID, "null plan");
+  if (form < BST_FP64 || form > BST_BF16X6) fail(BST_E_INVALID, "unknown precision");
+  PlanData& P = p->p;
+  bool pl;
+  const auto& list = variant_list(P, form, pl);
+  if (tile < 0 || tile >= (int32_t)list.size()) fail(BST_E_INVALID, "tile index out of range");
+  for (auto& st : P.steps) {
+    if (st.kind != StepKind::Gemm) continue;
+    if (pl && st.has_alt) st.tile_choice[10 + (int)form] = tile;
+    else if (!pl) st.tile_choice[(int)form] = tile;
+  }
+  drop_graph(P);
   BST_CATCH
 }
 

@@ -79,30 +79,131 @@ hipError_t launch_permute(const PermLaunch& p, hipStream_t s) {
 // matrix h[o][i] = sum_w2 W1[w1,s1,t1,w2] W2[w2,s2,t2,w3] (Sec. "Benchmarks",
 // Fig. Hpsi_fig: the two W's form the two-site operator h).
 // ------------------------------------------------------------------------
+// One thread per coefficient row (class, output o): every entry of the row
+// is the sum of its W1*W2 terms in a fixed order; the row is written dense
+// (coef64/coef32) and compacted to its nonzero entries in increasing input
+// order (cnt, idx, val64, val32) for the sparse apply.
 __global__ __launch_bounds__(256) void hcoef_kernel(const HTerm* __restrict__ terms,
                                                     const int32_t* __restrict__ entry_begin,
-                                                    int64_t nentries, void* const* __restrict__ ptrs,
+                                                    int64_t nrows, int nmax,
+                                                    void* const* __restrict__ ptrs,
                                                     double* __restrict__ c64,
-                                                    float* __restrict__ c32) {
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= nentries) return;
-  double sum = 0.0;
-  for (int32_t k = entry_begin[e]; k < entry_begin[e + 1]; ++k) {
-    const HTerm t = terms[k];
-    const double w1 = reinterpret_cast<const double*>(ptrs[t.w1_buf])[t.w1_off];
-    const double w2 = reinterpret_cast<const double*>(ptrs[t.w2_buf])[t.w2_off];
-    sum += w1 * w2;
+                                                    float* __restrict__ c32,
+                                                    int32_t* __restrict__ cnt,
+                                                    int32_t* __restrict__ idx,
+                                                    double* __restrict__ v64,
+                                                    float* __restrict__ v32) {
+  const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (row >= nrows) return;
+  int32_t n = 0;
+  for (int i = 0; i < nmax; ++i) {
+    const int64_t e = row * nmax + i;
+    double sum = 0.0;
+    for (int32_t k = entry_begin[e]; k < entry_begin[e + 1]; ++k) {
+      const HTerm t = terms[k];
+      const double w1 = reinterpret_cast<const double*>(ptrs[t.w1_buf])[t.w1_off];
+      const double w2 = reinterpret_cast<const double*>(ptrs[t.w2_buf])[t.w2_off];
+      sum += w1 * w2;
+    }
+    c64[e] = sum;
+    c32[e] = (float)sum;
+    if (sum != 0.0) {
+      idx[row * nmax + n] = i;
+      v64[row * nmax + n] = sum;
+      v32[row * nmax + n] = (float)sum;
+      ++n;
+    }
   }
-  c64[e] = sum;
-  c32[e] = (float)sum;
+  cnt[row] = n;
 }
 
 hipError_t launch_hcoef(const HCoefLaunch& c, hipStream_t s) {
   if (c.nentries <= 0) return hipSuccess;
-  const unsigned blocks = (unsigned)((c.nentries + 255) / 256);
-  hipLaunchKernelGGL(hcoef_kernel, dim3(blocks), dim3(256), 0, s, c.terms, c.entry_begin,
-                     c.nentries, c.ptrs, c.coef64, c.coef32);
+  const int64_t nrows = c.nentries / c.nmax;
+  const unsigned blocks = (unsigned)((nrows + 255) / 256);
+  hipLaunchKernelGGL(hcoef_kernel, dim3(blocks), dim3(256), 0, s, c.terms, c.entry_begin, nrows,
+                     c.nmax, c.ptrs, c.coef64, c.coef32, c.cnt, c.idx, c.val64, c.val32);
   return hipGetLastError();
+}
+
+// Sparse two-site MPO apply: each lane stages its site's nin inputs in LDS
+// (one column per lane, no bank conflicts) and runs only the nonzero terms
+// of its class.  The terms of an output are added in increasing input order,
+// so the result equals the dense product bit for bit.
+template <typename T, int NMAX, int NP>
+__global__ __launch_bounds__(256) void happly_sparse_kernel(const HTask* __restrict__ tasks,
+                                                            const HPlane* __restrict__ planes,
+                                                            const HWork* __restrict__ work,
+                                                            void* const* __restrict__ ptrs,
+                                                            const int32_t* __restrict__ cnt,
+                                                            const int32_t* __restrict__ idx,
+                                                            const T* __restrict__ val) {
+  __shared__ T xs[NMAX][256];
+  __shared__ T sv[NMAX * NMAX];
+  __shared__ int32_t si[NMAX * NMAX];
+  __shared__ int32_t sc[NMAX];
+  __shared__ HPlane pl[2 * NMAX];
+  const HWork w = work[blockIdx.x];
+  const HTask t = tasks[w.task];
+  const int tid = threadIdx.x;
+  const int64_t cbase = (int64_t)t.cls * NMAX;
+  for (int e = tid; e < NMAX * NMAX; e += 256) {
+    sv[e] = val[cbase * NMAX + e];
+    si[e] = idx[cbase * NMAX + e];
+  }
+  for (int e = tid; e < NMAX; e += 256) sc[e] = cnt[cbase + e];
+  for (int e = tid; e < t.nin + t.nout; e += 256) pl[e] = planes[t.plane_begin + e];
+  __syncthreads();
+  const int site = w.site0 + tid;
+  if (site >= t.rows * t.cols) return;
+  const int i = site / t.cols, jc = site % t.cols;
+  const T* __restrict__ in = reinterpret_cast<const T*>(ptrs[t.in_buf]);
+  for (int k = 0; k < t.nin; ++k) xs[k][tid] = in[pl[k].off + (int64_t)i * pl[k].rowstride + jc];
+  for (int o = 0; o < t.nout; ++o) {
+    T y = 0;
+    const int n = sc[o];
+    for (int e = 0; e < n; ++e) y += sv[o * NMAX + e] * xs[si[o * NMAX + e]][tid];
+    const HPlane q = pl[t.nin + o];
+    const int64_t at = q.off + (int64_t)i * q.rowstride + jc;
+    if constexpr (NP == 0) {
+      reinterpret_cast<T*>(ptrs[t.out_buf])[at] = y;
+    } else {
+      unsigned short* out = reinterpret_cast<unsigned short*>(ptrs[t.out_buf]);
+      const float yf = (float)y;
+      unsigned int u = __float_as_uint(yf);
+      const unsigned short h0 = (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+      const float r1 = yf - __uint_as_float((unsigned int)h0 << 16);
+      u = __float_as_uint(r1);
+      const unsigned short h1 = (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+      out[at] = h0;
+      out[t.out_ps + at] = h1;
+      if constexpr (NP == 3) {
+        const float r2 = r1 - __uint_as_float((unsigned int)h1 << 16);
+        u = __float_as_uint(r2);
+        out[2 * t.out_ps + at] = (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+      }
+    }
+  }
+}
+
+hipError_t launch_happly_sparse(const HApplyLaunch& h, hipStream_t s) {
+  if (h.nwork <= 0) return hipSuccess;
+  if (h.nwork > 0x7FFFFFFF) return hipErrorInvalidValue;
+  dim3 grid((unsigned)h.nwork), block(256);
+#define BST_HS(T_, N_, P_)                                                                     \
+  if (h.nmax == N_ && h.np == P_) {                                                            \
+    hipLaunchKernelGGL((happly_sparse_kernel<T_, N_, P_>), grid, block, 0, s, h.tasks, h.planes, \
+                       h.work, h.ptrs, h.cnt, h.idx, reinterpret_cast<const T_*>(h.val));      \
+    return hipGetLastError();                                                                  \
+  }
+  if (h.t == ElemType::F64) {
+    BST_HS(double, 8, 0) BST_HS(double, 16, 0)
+  } else {
+    BST_HS(float, 8, 0) BST_HS(float, 16, 0) BST_HS(float, 8, 2) BST_HS(float, 16, 2)
+    BST_HS(float, 8, 3) BST_HS(float, 16, 3)
+  }
+#undef BST_HS
+  return hipErrorInvalidValue;
 }
 
 template <typename T, int NMAX>
@@ -140,7 +241,11 @@ __global__ __launch_bounds__(256) void happly_kernel(const HTask* __restrict__ t
   }
 }
 
+hipError_t launch_happly_planes(const HApplyLaunch& h, hipStream_t s);
+
 hipError_t launch_happly(const HApplyLaunch& h, hipStream_t s) {
+  if (h.cnt && h.nmax <= 16) return launch_happly_sparse(h, s);
+  if (h.np > 0) return launch_happly_planes(h, s);
   if (h.nwork <= 0) return hipSuccess;
   if (h.nwork > 0x7FFFFFFF) return hipErrorInvalidValue;
   dim3 grid((unsigned)h.nwork), block(256);
@@ -202,33 +307,53 @@ __global__ __launch_bounds__(256) void reduce_partials_kernel(const double* __re
 
 static inline int vec_grid(int64_t n) {
   int64_t g = (n + 255) / 256;
-  if (g > kVecBlocks) g = kVecBlocks;
+  if (g > 1024) g = 1024;
   if (g < 1) g = 1;
   return (int)g;
 }
 
+// The Krylov basis is read through one base pointer plus a 32-bit per-lane
+// byte offset (V is below 4 GiB, checked on the host), so the row addresses
+// need neither 64-bit VGPR pairs nor one SGPR pair per row; the empty asm
+// keeps the compiler from hoisting one offset per row into registers.
+// Streaming loads and stores are non-temporal: V is read once per pass.
 template <int NV>
-__global__ __launch_bounds__(256) void multidot_kernel(const double* __restrict__ V, int64_t ldv,
-                                                       int64_t n, int nv,
+__global__ __launch_bounds__(256) void multidot_kernel(const double* __restrict__ V, uint32_t ldv,
+                                                       uint32_t n, int nv,
                                                        const double* __restrict__ w,
                                                        double* __restrict__ partial) {
+  // two elements per lane (16-byte loads; V rows and w are 16-byte aligned)
   __shared__ double red[4 * NV];
   double acc[NV];
 #pragma unroll
   for (int k = 0; k < NV; ++k) acc[k] = 0.0;
-  const int64_t stride = (int64_t)gridDim.x * 256;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
-    const double wi = w[i];
+  const char* Vb = reinterpret_cast<const char*>(V);
+  const uint32_t rowb = ldv * 8u;
+  const uint32_t stride = gridDim.x * 512u;
+  for (uint32_t i = (blockIdx.x * 256u + threadIdx.x) * 2u; i + 1 < n; i += stride) {
+    const double2 wi = *reinterpret_cast<const double2*>(w + i);
+    uint32_t off = i * 8u;
 #pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      if (k < nv) {
+        const double2 v = *reinterpret_cast<const double2*>(Vb + off);
+        acc[k] += v.x * wi.x + v.y * wi.y;
+      }
+      off += rowb;
+      asm volatile("" : "+v"(off));
+    }
+  }
+  if ((n & 1u) && blockIdx.x == 0 && threadIdx.x == 0) {
+    const uint32_t i = n - 1;
     for (int k = 0; k < NV; ++k)
-      if (k < nv) acc[k] += V[k * ldv + i] * wi;
+      if (k < nv) acc[k] += V[(size_t)k * ldv + i] * w[i];
   }
   block_reduce_store<NV>(acc, nv, red, partial);
 }
 
 template <int NV>
-__global__ __launch_bounds__(256) void project_kernel(const double* __restrict__ V, int64_t ldv,
-                                                      int64_t n, int nv,
+__global__ __launch_bounds__(256) void project_kernel(const double* __restrict__ V, uint32_t ldv,
+                                                      uint32_t n, int nv,
                                                       const double* __restrict__ c,
                                                       const double* w, double* wout, int mode,
                                                       double* __restrict__ partial) {
@@ -239,16 +364,22 @@ __global__ __launch_bounds__(256) void project_kernel(const double* __restrict__
   double acc[NV];
 #pragma unroll
   for (int k = 0; k < NV; ++k) acc[k] = 0.0;
-  const int64_t stride = (int64_t)gridDim.x * 256;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
+  const char* Vb = reinterpret_cast<const char*>(V);
+  const uint32_t rowb = ldv * 8u;
+  const uint32_t stride = gridDim.x * 256u;
+  for (uint32_t i = blockIdx.x * 256u + threadIdx.x; i < n; i += stride) {
     double v[NV];
-    double s = w[i];
+    double s = __builtin_nontemporal_load(w + i);
+    uint32_t off = i * 8u;
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
-      v[k] = (k < nv) ? V[k * ldv + i] : 0.0;
-      s -= v[k] * cs[k];
+      v[k] = (k < nv) ? __builtin_nontemporal_load(reinterpret_cast<const double*>(Vb + off)) : 0.0;
+      off += rowb;
+      asm volatile("" : "+v"(off));
     }
-    wout[i] = s;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) s -= v[k] * cs[k];
+    __builtin_nontemporal_store(s, wout + i);
     if (mode == 1) {
 #pragma unroll
       for (int k = 0; k < NV; ++k) acc[k] += v[k] * s;
@@ -263,18 +394,26 @@ __global__ __launch_bounds__(256) void project_kernel(const double* __restrict__
   do {                                                                                    \
     if (nv <= 8) hipLaunchKernelGGL((KERNEL<8>), __VA_ARGS__);                            \
     else if (nv <= 16) hipLaunchKernelGGL((KERNEL<16>), __VA_ARGS__);                     \
+    else if (nv <= 24) hipLaunchKernelGGL((KERNEL<24>), __VA_ARGS__);                     \
     else if (nv <= 32) hipLaunchKernelGGL((KERNEL<32>), __VA_ARGS__);                     \
+    else if (nv <= 40) hipLaunchKernelGGL((KERNEL<40>), __VA_ARGS__);                     \
     else if (nv <= 48) hipLaunchKernelGGL((KERNEL<48>), __VA_ARGS__);                     \
     else if (nv <= 64) hipLaunchKernelGGL((KERNEL<64>), __VA_ARGS__);                     \
     else if (nv <= 96) hipLaunchKernelGGL((KERNEL<96>), __VA_ARGS__);                     \
     else hipLaunchKernelGGL((KERNEL<128>), __VA_ARGS__);                                  \
   } while (0)
 
+static bool fits32(const double* V, int64_t ldv, int64_t n, int nv) {
+  (void)V;
+  return n <= 0x7FFFFFFF && ldv <= 0x7FFFFFFF && (uint64_t)ldv * (uint64_t)nv * 8u < 0xFFFFFFFFull;
+}
+
 hipError_t launch_multidot(const double* V, int64_t ldv, int64_t n, int nv, const double* w,
                            double* partial, double* out, hipStream_t s) {
-  if (nv < 1 || nv > kMaxVecs) return hipErrorInvalidValue;
+  if (nv < 1 || nv > kMaxVecs || !fits32(V, ldv, n, nv)) return hipErrorInvalidValue;
   const int G = vec_grid(n);
-  BST_NV_DISPATCH(multidot_kernel, dim3(G), dim3(256), 0, s, V, ldv, n, nv, w, partial);
+  BST_NV_DISPATCH(multidot_kernel, dim3(G), dim3(256), 0, s, V, (uint32_t)ldv, (uint32_t)n, nv, w,
+                  partial);
   hipLaunchKernelGGL(reduce_partials_kernel, dim3(nv), dim3(256), 0, s, partial, G, out);
   return hipGetLastError();
 }
@@ -282,12 +421,51 @@ hipError_t launch_multidot(const double* V, int64_t ldv, int64_t n, int nv, cons
 hipError_t launch_project(const double* V, int64_t ldv, int64_t n, int nv, const double* c,
                           const double* w, double* wout, int mode, double* partial, double* out,
                           hipStream_t s) {
-  if (nv < 1 || nv > kMaxVecs) return hipErrorInvalidValue;
+  if (nv < 1 || nv > kMaxVecs || !fits32(V, ldv, n, nv)) return hipErrorInvalidValue;
   const int G = vec_grid(n);
-  BST_NV_DISPATCH(project_kernel, dim3(G), dim3(256), 0, s, V, ldv, n, nv, c, w, wout, mode,
-                  partial);
-  hipLaunchKernelGGL(reduce_partials_kernel, dim3(mode == 1 ? nv : 1), dim3(256), 0, s, partial,
-                     G, out);
+  BST_NV_DISPATCH(project_kernel, dim3(G), dim3(256), 0, s, V, (uint32_t)ldv, (uint32_t)n, nv, c,
+                  w, wout, mode, partial);
+  if (out)
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3(mode == 1 ? nv : 1), dim3(256), 0, s, partial,
+                       G, out);
+  return hipGetLastError();
+}
+
+// End of a Lanczos step: every block adds the pass-3 partial norms in the
+// same fixed order (so all blocks hold the same |w|^2), block 0 records
+// alpha_j = c_j + d_j and beta_j = |w|, and the blocks write
+// v_{j+1} = w / beta_j (skipped on the last step, vnext == nullptr).
+__global__ __launch_bounds__(256) void lanczos_step_end_kernel(
+    const double* __restrict__ partial, int G, const double* __restrict__ c,
+    const double* __restrict__ d, int j, double* __restrict__ alpha, double* __restrict__ beta,
+    double* __restrict__ norm2_out, const double* __restrict__ w, double* __restrict__ vnext,
+    int64_t n) {
+  __shared__ double red[4];
+  const int tid = threadIdx.x;
+  double s = 0.0;
+  for (int b = tid; b < G; b += 256) s += partial[b];
+  s = wave_sum(s);
+  if ((tid & 63) == 0) red[tid >> 6] = s;
+  __syncthreads();
+  const double q = ((red[0] + red[1]) + red[2]) + red[3];
+  if (blockIdx.x == 0 && tid == 0) {
+    alpha[j] = c[j] + d[j];
+    beta[j] = sqrt(q > 0.0 ? q : 0.0);
+    norm2_out[0] = q;
+  }
+  if (!vnext) return;
+  const double f = q > 0.0 ? 1.0 / sqrt(q) : 0.0;
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + tid; i < n; i += stride) vnext[i] = w[i] * f;
+}
+
+hipError_t launch_lanczos_step_end(const double* partial, int64_t n_for_grid, const double* c,
+                                   const double* d, int j, double* alpha, double* beta,
+                                   double* norm2_out, const double* w, double* vnext, int64_t n,
+                                   hipStream_t s) {
+  const int G = vec_grid(n_for_grid);
+  hipLaunchKernelGGL(lanczos_step_end_kernel, dim3(vnext ? vec_grid(n) : 1), dim3(256), 0, s,
+                     partial, G, c, d, j, alpha, beta, norm2_out, w, vnext, n);
   return hipGetLastError();
 }
 

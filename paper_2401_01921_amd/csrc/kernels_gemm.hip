@@ -24,15 +24,20 @@ typedef float flt4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned short us8 __attribute__((ext_vector_type(8)));
 
-static const std::vector<TileShape> kShapesF64 = {{32, 32}, {64, 64}, {64, 32}, {32, 64}};
-static const std::vector<TileShape> kShapesF32 = {{32, 32}, {64, 64}, {128, 64}, {64, 128}};
-static const std::vector<TileShape> kShapesBF = {{32, 32}, {64, 64}, {128, 64}, {64, 128}, {128, 128}};
+// Direct (LDS-free) variants first: index 0 is the default.
+static const std::vector<TileShape> kShapesF64 = {{64, 64, 1}, {128, 64, 1}, {64, 128, 1}, {32, 32, 1},
+                                                  {32, 32, 0}, {64, 64, 0}, {64, 32, 0}, {32, 64, 0}};
+static const std::vector<TileShape> kShapesF32 = {{64, 64, 1}, {128, 64, 1}, {64, 128, 1}, {32, 32, 1},
+                                                  {32, 32, 0}, {64, 64, 0}, {128, 64, 0}, {64, 128, 0}};
+static const std::vector<TileShape> kShapesBF3 = {{32, 32}, {64, 64}, {128, 64}, {64, 128}};
+static const std::vector<TileShape> kShapesBF6 = {{32, 32}, {64, 64}};
 
 const std::vector<TileShape>& gemm_tile_shapes(bst_precision form) {
   switch (form) {
     case BST_FP64: return kShapesF64;
     case BST_FP32: return kShapesF32;
-    default: return kShapesBF;
+    case BST_BF16X3: return kShapesBF3;
+    default: return kShapesBF6;
   }
 }
 
@@ -98,16 +103,18 @@ __global__ __launch_bounds__(256) void gemm_grouped_kernel(const GemmTile* __res
   using ACC = typename std::conditional<F64, dbl4, flt4>::type;
   constexpr int PADF = 2;   // float/double LDS row pad (elements)
   constexpr int PADH = 8;   // bf16 LDS row pad (elements): keeps 16-byte alignment
+  constexpr int EA = BM * BK / 256, EB = BN * BK / 256;   // tile elements per thread
 
-  // LDS: plain forms store [BK][BM+PADF] (k-major), bf16 forms store planes
-  // [NP][BM][BK+PADH] (k contiguous per row, 16-byte reads per lane).
+  // LDS, double buffered: plain forms store [BK][BM+PADF] (k-major), bf16
+  // forms store planes [NP][BM][BK+PADH] (k contiguous, 16-byte lane reads).
   constexpr int A_ELEMS = BF ? NP * BM * (BK + PADH) : BK * (BM + PADF);
   constexpr int B_ELEMS = BF ? NP * BN * (BK + PADH) : BK * (BN + PADF);
   using LT = typename std::conditional<BF, unsigned short, CT>::type;
-  __shared__ __attribute__((aligned(16))) LT As[A_ELEMS];
-  __shared__ __attribute__((aligned(16))) LT Bs[B_ELEMS];
+  __shared__ __attribute__((aligned(16))) LT As[2][A_ELEMS];
+  __shared__ __attribute__((aligned(16))) LT Bs[2][B_ELEMS];
 
   const GemmTile t = tiles[blockIdx.x];
+  if (t.prob < 0) return;   // padding of the per-XCD tile lists
   const GemmProb p = probs[t.prob];
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
@@ -120,97 +127,137 @@ __global__ __launch_bounds__(256) void gemm_grouped_kernel(const GemmTile* __res
 #pragma unroll
     for (int j = 0; j < SN; ++j) acc[i][j] = ACC{0, 0, 0, 0};
 
-  for (int s = 0; s < p.seg_count; ++s) {
-    const GemmSeg g = segs[p.seg_begin + s];
+  // next k-step to fetch: segment ls, offset lk; values staged in registers
+  int ls = 0, lk = 0;
+  TA ra[EA];
+  double rb[EB];
+  auto fetch = [&]() {
+    const GemmSeg g = segs[p.seg_begin + ls];
     const TA* __restrict__ A = reinterpret_cast<const TA*>(ptrs[g.a_buf]) + g.a_off;
     const double* __restrict__ B = reinterpret_cast<const double*>(ptrs[g.b_buf]) + g.b_off;
-    const int K = g.K;
-    for (int k0 = 0; k0 < K; k0 += BK) {
-      // ---- A tile: rows m0.., cols k0.. (coalesced along k) ----
-      for (int e = tid; e < BM * BK; e += 256) {
-        const int r = e / BK, k = e % BK;
-        const int gr = m0 + r, gk = k0 + k;
-        TA v = (gr < p.M && gk < K) ? A[(int64_t)gr * g.lda + gk] : TA(0);
-        if constexpr (BF) {
-          unsigned short h[3];
-          split_bf16<NP>(v, h);
 #pragma unroll
-          for (int q = 0; q < NP; ++q) As[(q * BM + r) * (BK + PADH) + k] = h[q];
-        } else {
-          As[k * (BM + PADF) + r] = (CT)v;
-        }
-      }
-      // ---- B tile ----
-      for (int e = tid; e < BN * BK; e += 256) {
-        int n, k;
-        if constexpr (TRANSB) { n = e / BK; k = e % BK; }
-        else { k = e / BN; n = e % BN; }
-        const int gn = n0 + n, gk = k0 + k;
-        double v = 0.0;
-        if (gn < p.N && gk < K)
-          v = TRANSB ? B[(int64_t)gn * g.ldb + gk] : B[(int64_t)gk * g.ldb + gn];
-        if constexpr (BF) {
-          unsigned short h[3];
-          split_bf16<NP>(v, h);
+    for (int e = 0; e < EA; ++e) {
+      const int idx = tid + e * 256;
+      const int r = idx / BK, k = idx % BK;
+      const int gr = m0 + r, gk = lk + k;
+      ra[e] = (gr < p.M && gk < g.K) ? A[(int64_t)gr * g.lda + gk] : TA(0);
+    }
 #pragma unroll
-          for (int q = 0; q < NP; ++q) Bs[(q * BN + n) * (BK + PADH) + k] = h[q];
-        } else {
-          Bs[k * (BN + PADF) + n] = (CT)v;
-        }
-      }
-      __syncthreads();
+    for (int e = 0; e < EB; ++e) {
+      const int idx = tid + e * 256;
+      int n, k;
+      if constexpr (TRANSB) { n = idx / BK; k = idx % BK; }
+      else { k = idx / BN; n = idx % BN; }
+      const int gn = n0 + n, gk = lk + k;
+      double v = 0.0;
+      if (gn < p.N && gk < g.K) v = TRANSB ? B[(int64_t)gn * g.ldb + gk] : B[(int64_t)gk * g.ldb + gn];
+      rb[e] = v;
+    }
+    lk += BK;
+    if (lk >= g.K) {
+      ls++;
+      lk = 0;
+    }
+  };
+  auto stage = [&](int buf) {
+#pragma unroll
+    for (int e = 0; e < EA; ++e) {
+      const int idx = tid + e * 256;
+      const int r = idx / BK, k = idx % BK;
       if constexpr (BF) {
-        bf16x8 a[NP][SM], b[NP][SN];
-        const int kl = 8 * (lane >> 4);
+        unsigned short h[3];
+        split_bf16<NP>(ra[e], h);
 #pragma unroll
-        for (int q = 0; q < NP; ++q) {
+        for (int q = 0; q < NP; ++q) As[buf][(q * BM + r) * (BK + PADH) + k] = h[q];
+      } else {
+        As[buf][k * (BM + PADF) + r] = (CT)ra[e];
+      }
+    }
 #pragma unroll
-          for (int i = 0; i < SM; ++i) {
-            const int r = wm * WM + i * 16 + (lane & 15);
-            us8 raw = *reinterpret_cast<const us8*>(&As[(q * BM + r) * (BK + PADH) + kl]);
-            a[q][i] = __builtin_bit_cast(bf16x8, raw);
-          }
+    for (int e = 0; e < EB; ++e) {
+      const int idx = tid + e * 256;
+      int n, k;
+      if constexpr (TRANSB) { n = idx / BK; k = idx % BK; }
+      else { k = idx / BN; n = idx % BN; }
+      if constexpr (BF) {
+        unsigned short h[3];
+        split_bf16<NP>(rb[e], h);
 #pragma unroll
-          for (int j = 0; j < SN; ++j) {
-            const int c = wn * WN + j * 16 + (lane & 15);
-            us8 raw = *reinterpret_cast<const us8*>(&Bs[(q * BN + c) * (BK + PADH) + kl]);
-            b[q][j] = __builtin_bit_cast(bf16x8, raw);
-          }
+        for (int q = 0; q < NP; ++q) Bs[buf][(q * BN + n) * (BK + PADH) + k] = h[q];
+      } else {
+        Bs[buf][k * (BN + PADF) + n] = (CT)rb[e];
+      }
+    }
+  };
+  auto compute = [&](int buf) {
+    if constexpr (BF) {
+      bf16x8 a[NP][SM], b[NP][SN];
+      const int kl = 8 * (lane >> 4);
+#pragma unroll
+      for (int q = 0; q < NP; ++q) {
+#pragma unroll
+        for (int i = 0; i < SM; ++i) {
+          const int r = wm * WM + i * 16 + (lane & 15);
+          us8 raw = *reinterpret_cast<const us8*>(&As[buf][(q * BM + r) * (BK + PADH) + kl]);
+          a[q][i] = __builtin_bit_cast(bf16x8, raw);
         }
+#pragma unroll
+        for (int j = 0; j < SN; ++j) {
+          const int c = wn * WN + j * 16 + (lane & 15);
+          us8 raw = *reinterpret_cast<const us8*>(&Bs[buf][(q * BN + c) * (BK + PADH) + kl]);
+          b[q][j] = __builtin_bit_cast(bf16x8, raw);
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < SM; ++i)
+#pragma unroll
+        for (int j = 0; j < SN; ++j) {
+          if constexpr (NP == 3) {
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2][i], b[0][j], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][i], b[1][j], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[2][j], acc[i][j], 0, 0, 0);
+          }
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][i], b[0][j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[1][j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[0][j], acc[i][j], 0, 0, 0);
+        }
+    } else {
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += 4) {
+        const int k = kk + (lane >> 4);
+        CT a[SM], b[SN];
+#pragma unroll
+        for (int i = 0; i < SM; ++i) a[i] = As[buf][k * (BM + PADF) + wm * WM + i * 16 + (lane & 15)];
+#pragma unroll
+        for (int j = 0; j < SN; ++j) b[j] = Bs[buf][k * (BN + PADF) + wn * WN + j * 16 + (lane & 15)];
 #pragma unroll
         for (int i = 0; i < SM; ++i)
 #pragma unroll
           for (int j = 0; j < SN; ++j) {
-            if constexpr (NP == 3) {
-              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2][i], b[0][j], acc[i][j], 0, 0, 0);
-              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][i], b[1][j], acc[i][j], 0, 0, 0);
-              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[2][j], acc[i][j], 0, 0, 0);
-            }
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][i], b[0][j], acc[i][j], 0, 0, 0);
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[1][j], acc[i][j], 0, 0, 0);
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[0][j], acc[i][j], 0, 0, 0);
+            if constexpr (F64)
+              acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+            else
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
           }
-      } else {
-#pragma unroll
-        for (int kk = 0; kk < BK; kk += 4) {
-          const int k = kk + (lane >> 4);
-          CT a[SM], b[SN];
-#pragma unroll
-          for (int i = 0; i < SM; ++i) a[i] = As[k * (BM + PADF) + wm * WM + i * 16 + (lane & 15)];
-#pragma unroll
-          for (int j = 0; j < SN; ++j) b[j] = Bs[k * (BN + PADF) + wn * WN + j * 16 + (lane & 15)];
-#pragma unroll
-          for (int i = 0; i < SM; ++i)
-#pragma unroll
-            for (int j = 0; j < SN; ++j) {
-              if constexpr (F64)
-                acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
-              else
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
-            }
-        }
       }
+    }
+  };
+
+  // pipeline: the next k-step's global loads are in flight while the
+  // current one runs on the MFMA units; one barrier per k-step
+  if (p.seg_count > 0) {
+    fetch();
+    stage(0);
+    __syncthreads();
+    int buf = 0;
+    while (true) {
+      const bool more = ls < p.seg_count;
+      if (more) fetch();
+      compute(buf);
+      if (more) stage(buf ^ 1);
       __syncthreads();
+      buf ^= 1;
+      if (!more) break;
     }
   }
   // ---- epilogue: each element written exactly once ----
@@ -241,7 +288,8 @@ static hipError_t launch_shape(int bm, int bn, const GemmLaunch& g, hipStream_t 
   } else if constexpr (FORM == BST_FP32) {
     BST_SHAPE(32, 32) BST_SHAPE(64, 64) BST_SHAPE(128, 64) BST_SHAPE(64, 128)
   } else {
-    BST_SHAPE(32, 32) BST_SHAPE(64, 64) BST_SHAPE(128, 64) BST_SHAPE(64, 128) BST_SHAPE(128, 128)
+    BST_SHAPE(32, 32) BST_SHAPE(64, 64)
+    if constexpr (FORM == BST_BF16X3) { BST_SHAPE(128, 64) BST_SHAPE(64, 128) }
   }
 #undef BST_SHAPE
   return hipErrorInvalidValue;
@@ -252,6 +300,7 @@ static hipError_t launch_form(const GemmLaunch& g, hipStream_t s) {
   const auto& shapes = gemm_tile_shapes((bst_precision)FORM);
   if (g.tile < 0 || g.tile >= (int)shapes.size()) return hipErrorInvalidValue;
   const int bm = shapes[g.tile].bm, bn = shapes[g.tile].bn;
+  if (shapes[g.tile].direct) return launch_gemm_direct(g, bm, bn, s);
   const bool a64 = g.ta == ElemType::F64, c64 = g.tc == ElemType::F64;
   if (g.tb != ElemType::F64) return hipErrorInvalidValue;
   if (a64 && c64) {

@@ -1,0 +1,379 @@
+// Split-bfloat16 path: conversion of float64 operands into bfloat16 planes
+// (a = a0 + a1 [+ a2], each plane rounded to nearest even) laid out for the
+// MFMA loads, and the grouped GEMM that consumes them.
+//
+// Splitting once per operand instead of once per tile load removes the
+// redundant conversions (each element of A is otherwise re-split for every
+// N-tile) and halves the bytes the GEMM streams (4 or 6 bytes instead of 8).
+// Plane rows are padded to 8 elements so that every tile row is a whole
+// number of 16-byte vectors.
+#include "bst_internal.h"
+
+namespace bst {
+
+typedef float flt4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short us8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ unsigned short rne_bf16(float x) {
+  unsigned int u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf16f(unsigned short h) { return __uint_as_float((unsigned int)h << 16); }
+
+template <int NP>
+__device__ __forceinline__ void split_planes(double a, unsigned short* h) {
+  h[0] = rne_bf16((float)a);
+  double r = a - (double)bf16f(h[0]);
+  h[1] = rne_bf16((float)r);
+  if constexpr (NP > 2) h[2] = rne_bf16((float)(r - (double)bf16f(h[1])));
+}
+template <int NP>
+__device__ __forceinline__ void split_planes(float a, unsigned short* h) {
+  h[0] = rne_bf16(a);
+  float r = a - bf16f(h[0]);
+  h[1] = rne_bf16(r);
+  if constexpr (NP > 2) h[2] = rne_bf16(r - bf16f(h[1]));
+}
+
+// ------------------------------------------------------------------------
+// float64 blocks -> bfloat16 planes (optionally transposed), 64x64 tiles
+// ------------------------------------------------------------------------
+template <int NP>
+__global__ __launch_bounds__(256) void split_kernel(const SplitJob* __restrict__ jobs,
+                                                    const SplitWork* __restrict__ work,
+                                                    void* const* __restrict__ ptrs) {
+  // One 64 x 64 tile of the output per workgroup; every lane converts 8
+  // consecutive output elements and writes them as one 16-byte vector per
+  // plane (output rows are padded to 8, so the vectors are aligned).
+  __shared__ double tile[64][65];
+  const SplitWork w = work[blockIdx.x];
+  const SplitJob j = jobs[w.job];
+  const double* __restrict__ in = reinterpret_cast<const double*>(ptrs[j.in_buf]) + j.in_off;
+  unsigned short* __restrict__ out = reinterpret_cast<unsigned short*>(ptrs[j.out_buf]) + j.out_off;
+  const int tid = threadIdx.x;
+  const int orow = tid >> 3, ocol = (tid & 7) * 8;   // 32 rows x 8 vectors per pass
+  if (!j.transpose) {
+    // output [rows x out_ld]: rows r0.., columns c0.. (zeros past cols)
+#pragma unroll
+    for (int pass = 0; pass < 2; ++pass) {
+      const int r = w.r0 + orow + 32 * pass, c = w.c0 + ocol;
+      if (r < j.rows && c < j.out_ld) {
+        us8 h[3];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const double v = (c + e) < j.cols ? in[(int64_t)r * j.cols + c + e] : 0.0;
+          unsigned short t[3];
+          split_planes<NP>(v, t);
+#pragma unroll
+          for (int q = 0; q < NP; ++q) h[q][e] = t[q];
+        }
+#pragma unroll
+        for (int q = 0; q < NP; ++q)
+          *reinterpret_cast<us8*>(out + q * j.out_ps + (int64_t)r * j.out_ld + c) = h[q];
+      }
+    }
+    return;
+  }
+  // transposed: input [rows x cols] -> output [cols x out_ld], out_ld >= rows
+  for (int e = tid; e < 64 * 64; e += 256) {
+    const int r = e / 64, c = e % 64;
+    const int gr = w.r0 + r, gc = w.c0 + c;
+    tile[r][c] = (gr < j.rows && gc < j.cols) ? in[(int64_t)gr * j.cols + gc] : 0.0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int pass = 0; pass < 2; ++pass) {
+    const int c = orow + 32 * pass;          // output row = input column
+    const int gc = w.c0 + c, gr = w.r0 + ocol;
+    if (gc < j.cols && gr < j.out_ld) {
+      us8 h[3];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        unsigned short t[3];
+        split_planes<NP>(tile[ocol + e][c], t);
+#pragma unroll
+        for (int q = 0; q < NP; ++q) h[q][e] = t[q];
+      }
+#pragma unroll
+      for (int q = 0; q < NP; ++q)
+        *reinterpret_cast<us8*>(out + q * j.out_ps + (int64_t)gc * j.out_ld + gr) = h[q];
+    }
+  }
+}
+
+hipError_t launch_split(const SplitLaunch& l, hipStream_t s) {
+  if (l.nwork <= 0) return hipSuccess;
+  if (l.nwork > 0x7FFFFFFF) return hipErrorInvalidValue;
+  if (l.np == 2)
+    hipLaunchKernelGGL(split_kernel<2>, dim3((unsigned)l.nwork), dim3(256), 0, s, l.jobs, l.work, l.ptrs);
+  else if (l.np == 3)
+    hipLaunchKernelGGL(split_kernel<3>, dim3((unsigned)l.nwork), dim3(256), 0, s, l.jobs, l.work, l.ptrs);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------
+// Grouped GEMM on bfloat16 planes: C[M x N] = sum_seg A[M x K] B[N x K]^T
+// ------------------------------------------------------------------------
+// Tile shapes whose double-buffered LDS fits in 64 KB for each plane count.
+// Direct (LDS-free) variants first: index 0 is the default.
+static const std::vector<TileShape> kPlaneShapes2 = {{64, 64, 1}, {128, 64, 1}, {64, 128, 1}, {32, 32, 1},
+                                                     {64, 64, 0}, {128, 64, 0}, {64, 128, 0}, {32, 32, 0}};
+static const std::vector<TileShape> kPlaneShapes3 = {{64, 64, 1}, {128, 64, 1}, {64, 128, 1}, {32, 32, 1},
+                                                     {64, 64, 0}, {32, 32, 0}};
+const std::vector<TileShape>& gemm_planes_shapes(int np) { return np == 3 ? kPlaneShapes3 : kPlaneShapes2; }
+
+template <int NP, typename TC, int BM, int BN>
+__global__ __launch_bounds__(256) void gemm_planes_kernel(const GemmTile* __restrict__ tiles,
+                                                          const GemmProb* __restrict__ probs,
+                                                          const GemmSeg* __restrict__ segs,
+                                                          void* const* __restrict__ ptrs) {
+  constexpr int BK = 32, LDR = BK + 8;   // LDS row: 80 bytes, 16-byte aligned
+  constexpr int WM = BM / 2, WN = BN / 2, SM = WM / 16, SN = WN / 16;
+  constexpr int NVA = (BM * 4 + 255) / 256, NVB = (BN * 4 + 255) / 256;   // 16-byte vectors per thread
+  __shared__ __attribute__((aligned(16))) unsigned short As[2][NP][BM * LDR];
+  __shared__ __attribute__((aligned(16))) unsigned short Bs[2][NP][BN * LDR];
+
+  const GemmTile t = tiles[blockIdx.x];
+  if (t.prob < 0) return;   // padding of the per-XCD tile lists
+  const GemmProb p = probs[t.prob];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int m0 = t.m0, n0 = t.n0;
+
+  flt4 acc[SM][SN];
+#pragma unroll
+  for (int i = 0; i < SM; ++i)
+#pragma unroll
+    for (int j = 0; j < SN; ++j) acc[i][j] = flt4{0, 0, 0, 0};
+
+  us8 ra[NP][NVA], rb[NP][NVB];
+  const us8 zero8 = {0, 0, 0, 0, 0, 0, 0, 0};
+
+  // cursor of the next k-step to load: (segment, k0)
+  int ls = 0, lk = 0;
+  auto load = [&](int s, int k0) {
+    const GemmSeg g = segs[p.seg_begin + s];
+    const unsigned short* A = reinterpret_cast<const unsigned short*>(ptrs[g.a_buf]) + g.a_off;
+    const unsigned short* B = reinterpret_cast<const unsigned short*>(ptrs[g.b_buf]) + g.b_off;
+#pragma unroll
+    for (int v = 0; v < NVA; ++v) {
+      const int idx = tid + v * 256;
+      const int r = idx >> 2, kv = k0 + (idx & 3) * 8;
+      const int gr = m0 + r;
+      const bool ok = (idx < BM * 4) && gr < p.M && kv < g.K;
+#pragma unroll
+      for (int q = 0; q < NP; ++q) {
+        us8 x = ok ? *reinterpret_cast<const us8*>(A + q * g.a_ps + (int64_t)gr * g.lda + kv) : zero8;
+        if (ok && kv + 8 > g.K) {
+#pragma unroll
+          for (int e = 0; e < 8; ++e)
+            if (kv + e >= g.K) x[e] = 0;
+        }
+        ra[q][v] = x;
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < NVB; ++v) {
+      const int idx = tid + v * 256;
+      const int r = idx >> 2, kv = k0 + (idx & 3) * 8;
+      const int gn = n0 + r;
+      const bool ok = (idx < BN * 4) && gn < p.N && kv < g.K;
+#pragma unroll
+      for (int q = 0; q < NP; ++q) {
+        us8 x = ok ? *reinterpret_cast<const us8*>(B + q * g.b_ps + (int64_t)gn * g.ldb + kv) : zero8;
+        if (ok && kv + 8 > g.K) {
+#pragma unroll
+          for (int e = 0; e < 8; ++e)
+            if (kv + e >= g.K) x[e] = 0;
+        }
+        rb[q][v] = x;
+      }
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int v = 0; v < NVA; ++v) {
+      const int idx = tid + v * 256;
+      if (idx < BM * 4) {
+#pragma unroll
+        for (int q = 0; q < NP; ++q)
+          *reinterpret_cast<us8*>(&As[buf][q][(idx >> 2) * LDR + (idx & 3) * 8]) = ra[q][v];
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < NVB; ++v) {
+      const int idx = tid + v * 256;
+      if (idx < BN * 4) {
+#pragma unroll
+        for (int q = 0; q < NP; ++q)
+          *reinterpret_cast<us8*>(&Bs[buf][q][(idx >> 2) * LDR + (idx & 3) * 8]) = rb[q][v];
+      }
+    }
+  };
+  auto advance = [&]() {
+    lk += BK;
+    if (lk >= segs[p.seg_begin + ls].K) {
+      ls++;
+      lk = 0;
+    }
+  };
+
+  int buf = 0;
+  if (p.seg_count > 0) {
+    load(ls, lk);
+    advance();
+    store(0);
+  }
+  __syncthreads();
+  bool more = p.seg_count > 0;
+  while (more) {
+    const bool have_next = ls < p.seg_count;
+    if (have_next) load(ls, lk);
+    // MFMA on the current buffer
+    {
+      const int kl = 8 * (lane >> 4);
+      bf16x8 a[NP][SM], b[NP][SN];
+#pragma unroll
+      for (int q = 0; q < NP; ++q) {
+#pragma unroll
+        for (int i = 0; i < SM; ++i) {
+          const int r = wm * WM + i * 16 + (lane & 15);
+          a[q][i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const us8*>(&As[buf][q][r * LDR + kl]));
+        }
+#pragma unroll
+        for (int j = 0; j < SN; ++j) {
+          const int c = wn * WN + j * 16 + (lane & 15);
+          b[q][j] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const us8*>(&Bs[buf][q][c * LDR + kl]));
+        }
+      }
+      // second 16-wide half of the 32-deep k step is in the same vectors (K = 32 per MFMA)
+#pragma unroll
+      for (int i = 0; i < SM; ++i)
+#pragma unroll
+        for (int j = 0; j < SN; ++j) {
+          if constexpr (NP == 3) {
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2][i], b[0][j], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][i], b[1][j], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[2][j], acc[i][j], 0, 0, 0);
+          }
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][i], b[0][j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[1][j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[0][j], acc[i][j], 0, 0, 0);
+        }
+    }
+    if (have_next) {
+      advance();
+      store(buf ^ 1);
+    }
+    __syncthreads();
+    buf ^= 1;
+    more = have_next;
+  }
+  TC* __restrict__ C = reinterpret_cast<TC*>(ptrs[p.c_buf]) + p.c_off;
+#pragma unroll
+  for (int i = 0; i < SM; ++i)
+#pragma unroll
+    for (int j = 0; j < SN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm * WM + i * 16 + 4 * (lane >> 4) + r;
+        const int col = n0 + wn * WN + j * 16 + (lane & 15);
+        if (row < p.M && col < p.N) C[(int64_t)row * p.ldc + col] = (TC)acc[i][j][r];
+      }
+}
+
+template <int NP, typename TC>
+static hipError_t planes_shape(int bm, int bn, const PlanesLaunch& g, hipStream_t s) {
+  dim3 grid((unsigned)g.ntiles), block(256);
+#define BST_PS(BM_, BN_)                                                                        \
+  if (bm == BM_ && bn == BN_) {                                                                 \
+    hipLaunchKernelGGL((gemm_planes_kernel<NP, TC, BM_, BN_>), grid, block, 0, s, g.tiles, g.probs, \
+                       g.segs, g.ptrs);                                                         \
+    return hipGetLastError();                                                                   \
+  }
+  BST_PS(64, 64) BST_PS(32, 32)
+  if constexpr (NP == 2) {
+    BST_PS(128, 64) BST_PS(64, 128)
+  }
+#undef BST_PS
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_gemm_planes(const PlanesLaunch& g, hipStream_t s) {
+  if (g.ntiles <= 0) return hipSuccess;
+  if (g.ntiles > 0x7FFFFFFF) return hipErrorInvalidValue;
+  const auto& sh = gemm_planes_shapes(g.np);
+  if (g.tile < 0 || g.tile >= (int)sh.size()) return hipErrorInvalidValue;
+  const int bm = sh[g.tile].bm, bn = sh[g.tile].bn;
+  if (sh[g.tile].direct) return launch_gemm_direct_planes(g, bm, bn, s);
+  if (g.np == 2)
+    return g.tc == ElemType::F64 ? planes_shape<2, double>(bm, bn, g, s) : planes_shape<2, float>(bm, bn, g, s);
+  if (g.np == 3)
+    return g.tc == ElemType::F64 ? planes_shape<3, double>(bm, bn, g, s) : planes_shape<3, float>(bm, bn, g, s);
+  return hipErrorInvalidValue;
+}
+
+// ------------------------------------------------------------------------
+// Two-site MPO apply writing its output as bfloat16 planes
+// ------------------------------------------------------------------------
+template <int NMAX, int NP>
+__global__ __launch_bounds__(256) void happly_planes_kernel(const HTask* __restrict__ tasks,
+                                                            const HPlane* __restrict__ planes,
+                                                            const HWork* __restrict__ work,
+                                                            void* const* __restrict__ ptrs,
+                                                            const float* __restrict__ coef) {
+  __shared__ float cf[NMAX * NMAX];
+  __shared__ HPlane pl[2 * NMAX];
+  const HWork w = work[blockIdx.x];
+  const HTask t = tasks[w.task];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < NMAX * NMAX; e += 256) cf[e] = coef[(int64_t)t.cls * NMAX * NMAX + e];
+  for (int e = tid; e < t.nin + t.nout; e += 256) pl[e] = planes[t.plane_begin + e];
+  __syncthreads();
+  const int site = w.site0 + tid;
+  if (site >= t.rows * t.cols) return;
+  const int i = site / t.cols, jc = site % t.cols;
+  const float* __restrict__ in = reinterpret_cast<const float*>(ptrs[t.in_buf]);
+  unsigned short* __restrict__ out = reinterpret_cast<unsigned short*>(ptrs[t.out_buf]);
+  float x[NMAX];
+#pragma unroll
+  for (int k = 0; k < NMAX; ++k)
+    x[k] = (k < t.nin) ? in[pl[k].off + (int64_t)i * pl[k].rowstride + jc] : 0.0f;
+#pragma unroll
+  for (int o = 0; o < NMAX; ++o) {
+    if (o < t.nout) {
+      float y = 0.0f;
+#pragma unroll
+      for (int k = 0; k < NMAX; ++k) y += cf[o * NMAX + k] * x[k];
+      const HPlane q = pl[t.nin + o];
+      unsigned short h[3];
+      split_planes<NP>(y, h);
+      const int64_t at = q.off + (int64_t)i * q.rowstride + jc;
+#pragma unroll
+      for (int pq = 0; pq < NP; ++pq) out[pq * t.out_ps + at] = h[pq];
+    }
+  }
+}
+
+hipError_t launch_happly_planes(const HApplyLaunch& h, hipStream_t s) {
+  if (h.nwork <= 0) return hipSuccess;
+  if (h.nwork > 0x7FFFFFFF) return hipErrorInvalidValue;
+  dim3 grid((unsigned)h.nwork), block(256);
+  const float* cf = reinterpret_cast<const float*>(h.coef);
+#define BST_HP(N_, P_)                                                                            \
+  if (h.nmax == N_ && h.np == P_) {                                                               \
+    hipLaunchKernelGGL((happly_planes_kernel<N_, P_>), grid, block, 0, s, h.tasks, h.planes, h.work, \
+                       h.ptrs, cf);                                                               \
+    return hipGetLastError();                                                                     \
+  }
+  BST_HP(8, 2) BST_HP(16, 2) BST_HP(32, 2) BST_HP(64, 2)
+  BST_HP(8, 3) BST_HP(16, 3) BST_HP(32, 3) BST_HP(64, 3)
+#undef BST_HP
+  return hipErrorInvalidValue;
+}
+
+}  // namespace bst

@@ -22,6 +22,7 @@ namespace {
 
 struct LanczosLayout {
   size_t tables, V, W, Y, HY, scal, partial, end;
+  int64_t ldv;   // row stride of V: psi's size rounded up to 512 bytes
   int nslots;
 };
 
@@ -30,12 +31,13 @@ size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 LanczosLayout layout(const PlanData& P, int nsteps) {
   LanczosLayout L{};
   const size_t n = (size_t)P.psi_numel;
+  L.ldv = (int64_t)((n + 63) / 64 * 64);
   size_t off = al(P.ws_bytes);
   L.nslots = std::max(P.nslots, 1);
   L.tables = off;
   off = al(off + sizeof(void*) * (size_t)L.nslots * (size_t)(nsteps + 1));
   L.V = off;
-  off = al(off + sizeof(double) * n * (size_t)nsteps);
+  off = al(off + sizeof(double) * (size_t)L.ldv * (size_t)nsteps);
   L.W = off;
   off = al(off + sizeof(double) * std::max<size_t>(n, 1));
   L.Y = off;
@@ -181,7 +183,7 @@ int step_class(const std::string& name) {
   if (name == "gemm_L_psi") return 0;
   if (name == "mpo_apply") return 1;
   if (name == "gemm_T3_R") return 2;
-  if (name == "mpo_coef") return 3;
+  if (name == "mpo_coef" || name.compare(0, 6, "split_") == 0) return 3;
   return 7;
 }
 
@@ -217,6 +219,9 @@ bst_status bst_lanczos_ground(bst_plan* heff, const void* const* ops, const void
   const LanczosLayout Lo = layout(P, nsteps);
   char* wb = static_cast<char*>(ws);
   const int64_t n = P.psi_numel;
+  const int64_t ldv = Lo.ldv;
+  if ((uint64_t)ldv * (uint64_t)nsteps * 8u >= 0xFFFFFFFFull)
+    fail(BST_E_INVALID, "Krylov basis above 4 GiB (reduce nsteps)");
   double* V = reinterpret_cast<double*>(wb + Lo.V);
   double* W = reinterpret_cast<double*>(wb + Lo.W);
   double* Y = reinterpret_cast<double*>(wb + Lo.Y);
@@ -236,7 +241,7 @@ bst_status bst_lanczos_ground(bst_plan* heff, const void* const* ops, const void
   prepare_ws(P, in0, out0, ws, s);
   std::vector<void* const*> tables;
   for (int j = 0; j <= nsteps; ++j) {
-    const void* in[5] = {ops[0], ops[1], ops[2], ops[3], j < nsteps ? (const void*)(V + (size_t)j * n)
+    const void* in[5] = {ops[0], ops[1], ops[2], ops[3], j < nsteps ? (const void*)(V + (size_t)j * ldv)
                                                                     : (const void*)Y};
     void* out[1] = {j < nsteps ? (void*)W : (void*)HY};
     auto ptrs = build_ptrs(P, in, out, ws);
@@ -254,7 +259,7 @@ bst_status bst_lanczos_ground(bst_plan* heff, const void* const* ops, const void
       return;
     }
     for (size_t k = 0; k < nps; ++k) {
-      const bool skipped = skip_coef && P.steps[k].kind == StepKind::HCoef;
+      const bool skipped = !step_runs(P, P.steps[k], prec, skip_coef);
       auto* e = skipped ? nullptr : tm.take(step_class(P.steps[k].name));
       // unused pairs still get recorded by run_steps; give them a spare
       stepev[k] = e ? *e : tm.pool.back();
@@ -277,12 +282,13 @@ bst_status bst_lanczos_ground(bst_plan* heff, const void* const* ops, const void
   for (int j = 0; j < nsteps; ++j) {
     matvec(tables[j], matvec_prec, j > 0);
     const int nv = j + 1;
-    timed(4, [&] { check_hip(launch_multidot(V, n, n, nv, W, partial, c, s), "cgs pass 1"); });
-    timed(5, [&] { check_hip(launch_project(V, n, n, nv, c, W, W, 1, partial, d, s), "cgs pass 2"); });
-    timed(6, [&] { check_hip(launch_project(V, n, n, nv, d, W, W, 2, partial, misc + 2, s), "cgs pass 3"); });
+    timed(4, [&] { check_hip(launch_multidot(V, ldv, n, nv, W, partial, c, s), "cgs pass 1"); });
+    timed(5, [&] { check_hip(launch_project(V, ldv, n, nv, c, W, W, 1, partial, d, s), "cgs pass 2"); });
+    timed(6, [&] { check_hip(launch_project(V, ldv, n, nv, d, W, W, 2, partial, nullptr, s), "cgs pass 3"); });
     timed(7, [&] {
-      check_hip(launch_lanczos_scalars(c, d, j, misc + 2, alpha, beta, s), "scalars");
-      if (j + 1 < nsteps) check_hip(launch_scale_rnorm(W, misc + 2, V + (size_t)(j + 1) * n, n, s), "scale");
+      double* vnext = j + 1 < nsteps ? V + (size_t)(j + 1) * ldv : nullptr;
+      check_hip(launch_lanczos_step_end(partial, n, c, d, j, alpha, beta, misc + 2, W, vnext, n, s),
+                "step end");
     });
   }
   std::vector<double> ha(nsteps), hb(nsteps), m0(2);
@@ -308,7 +314,7 @@ bst_status bst_lanczos_ground(bst_plan* heff, const void* const* ops, const void
   lowest_eigenpair(a, b, theta, sv);
   check_hip(hipMemcpyAsync(svec, sv.data(), sizeof(double) * m, hipMemcpyHostToDevice, s), "h2d");
   check_hip(hipStreamSynchronize(s), "h2d sync");
-  timed(7, [&] { check_hip(launch_combine(V, n, n, m, svec, Y, s), "ritz vector"); });
+  timed(7, [&] { check_hip(launch_combine(V, ldv, n, m, svec, Y, s), "ritz vector"); });
   double E = theta, resid = -1.0;
   if (refine) {
     matvec(tables[nsteps], BST_FP64, false);

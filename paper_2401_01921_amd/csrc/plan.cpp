@@ -316,6 +316,65 @@ static int64_t elem_offset4(const TensorDesc& T, const LegMap* maps, const int64
   return T.offset[b] + off;
 }
 
+// bfloat16-plane layout of a tensor seen as a matrix per block: rows are the
+// first `split` legs, columns the rest; rows (or, transposed, columns) are
+// padded to a multiple of 8 elements.
+struct PadLayout {
+  std::vector<int64_t> off, ld;
+  int64_t total = 0;   // elements per plane, a multiple of 8
+};
+static int64_t pad8(int64_t x) { return (x + 7) / 8 * 8; }
+
+static void block_matrix(const TensorDesc& T, int64_t b, int split, int64_t& rows, int64_t& cols) {
+  rows = 1;
+  cols = 1;
+  for (int i = 0; i < T.rank(); ++i) (i < split ? rows : cols) *= T.block_shape(b)[i];
+}
+
+static PadLayout pad_layout(const TensorDesc& T, int split, bool transpose) {
+  PadLayout P;
+  int64_t cum = 0;
+  for (int64_t b = 0; b < T.nblocks; ++b) {
+    int64_t rows, cols;
+    block_matrix(T, b, split, rows, cols);
+    const int64_t ld = transpose ? pad8(rows) : pad8(cols);
+    P.off.push_back(cum);
+    P.ld.push_back(ld);
+    cum += (transpose ? cols : rows) * ld;
+  }
+  P.total = pad8(std::max<int64_t>(cum, 8));
+  return P;
+}
+
+static void add_split_jobs(Step& st, const TensorDesc& T, int split, bool transpose,
+                           const PadLayout& Lay, int in_slot, int out_slot) {
+  st.kind = StepKind::Split;
+  for (int64_t b = 0; b < T.nblocks; ++b) {
+    int64_t rows, cols;
+    block_matrix(T, b, split, rows, cols);
+    if (rows > 0x7FFFFFFF || cols > 0x7FFFFFFF || Lay.ld[b] > 0x7FFFFFFF)
+      fail(BST_E_INVALID, "block too large for the bfloat16 split");
+    SplitJob j{};
+    j.in_off = T.offset[b];
+    j.out_off = Lay.off[b];
+    j.out_ps = Lay.total;
+    j.in_buf = in_slot;
+    j.out_buf = out_slot;
+    j.rows = (int32_t)rows;
+    j.cols = (int32_t)cols;
+    j.out_ld = (int32_t)Lay.ld[b];
+    j.transpose = transpose ? 1 : 0;
+    const int32_t jid = (int32_t)st.sjobs.size();
+    st.sjobs.push_back(j);
+    const int64_t rext = transpose ? Lay.ld[b] : rows;
+    const int64_t cext = transpose ? cols : Lay.ld[b];
+    for (int64_t r0 = 0; r0 < rext; r0 += 64)
+      for (int64_t c0 = 0; c0 < cext; c0 += 64) st.swork.push_back({jid, (int32_t)r0, (int32_t)c0, 0});
+  }
+  st.bytes += 8.0 * (double)T.numel + 4.0 * (double)Lay.total;
+  st.bytes32 = st.bytes;
+}
+
 static void heff_plan(const TensorDesc& L, const TensorDesc& W1, const TensorDesc& W2,
                       const TensorDesc& R, const TensorDesc& psi, PlanData& P) {
   if (L.rank() != 3 || W1.rank() != 4 || W2.rank() != 4 || R.rank() != 3 || psi.rank() != 4)
@@ -354,12 +413,31 @@ static void heff_plan(const TensorDesc& L, const TensorDesc& W1, const TensorDes
   P.t3_numel = T3->numel;
   P.internals.push_back({6, (size_t)T1->numel * 8, 0});
   P.internals.push_back({7, (size_t)T3->numel * 8, 0});
+  // bfloat16 planes for the split forms: L [(a w) x a'], R [b x (w b')],
+  // psi transposed to [(t1 t2 b') x a'], T3 [(a s1 s2) x (w3 b')]
+  P.has_planes = true;
+  P.nslots = 12;
+  const PadLayout Lp = pad_layout(L, 2, false), Rp = pad_layout(R, 1, false),
+                  Pp = pad_layout(psi, 1, true), Tp = pad_layout(*T3, 3, false);
+  P.internals.push_back({8, (size_t)Lp.total * 2 * 3, 0});
+  P.internals.push_back({9, (size_t)Rp.total * 2 * 3, 0});
+  P.internals.push_back({10, (size_t)Pp.total * 2 * 3, 0});
+  P.internals.push_back({11, (size_t)Tp.total * 2 * 3, 0});
+  Step spL, spR, spP;
+  spL.name = "split_L";
+  spR.name = "split_R";
+  spP.name = "split_psi";
+  add_split_jobs(spL, L, 2, false, Lp, 0, 8);
+  add_split_jobs(spR, R, 1, false, Rp, 3, 9);
+  add_split_jobs(spP, psi, 1, true, Pp, 4, 10);
+  spL.constant = spR.constant = true;
 
   // ---- step 1: T1[(a w) x (t1 t2 y)] = sum_a' L[(a w) x a'] psi[a' x (t1 t2 y)]
   Step s1;
   s1.kind = StepKind::Gemm;
   s1.name = "gemm_L_psi";
   s1.tc = Elem::Inter;
+  s1.has_alt = true;
   {
     const int nA = (int)psi.legs[0].q.size();
     int32_t lt[3], pt[4];
@@ -389,6 +467,16 @@ static void heff_plan(const TensorDesc& L, const TensorDesc& W1, const TensorDes
         g.lda = (int32_t)K;
         g.ldb = (int32_t)N;
         s1.segs.push_back(g);
+        GemmSeg h = g;
+        h.a_off = Lp.off[lb];
+        h.a_buf = 8;
+        h.lda = (int32_t)Lp.ld[lb];
+        h.a_ps = Lp.total;
+        h.b_off = Pp.off[pb];
+        h.b_buf = 10;
+        h.ldb = (int32_t)Pp.ld[pb];
+        h.b_ps = Pp.total;
+        s1.segs_alt.push_back(h);
         s1.flops += 2.0 * (double)M * (double)N * (double)K;
       }
       p.seg_count = (int32_t)s1.segs.size() - p.seg_begin;
@@ -402,8 +490,10 @@ static void heff_plan(const TensorDesc& L, const TensorDesc& W1, const TensorDes
   Step hc, ha;
   hc.kind = StepKind::HCoef;
   hc.name = "mpo_coef";
+  hc.constant = true;
   ha.kind = StepKind::HApply;
   ha.name = "mpo_apply";
+  ha.has_alt = true;
   {
     const LegDesc& lw = L.legs[1];
     const LegDesc& lt1 = psi.legs[1];
@@ -421,7 +511,7 @@ static void heff_plan(const TensorDesc& L, const TensorDesc& W1, const TensorDes
     int32_t t[5];
     for (int ka = 0; ka < nA; ++ka)
       for (int ky = 0; ky < nY; ++ky) {
-        std::vector<HPlane> ins, outs;
+        std::vector<HPlane> ins, outs, outs_alt;
         std::vector<int64_t> key;   // class key: input then output element triples
         for (int kw = 0; kw < (int)lw.q.size(); ++kw)
           for (int k1 = 0; k1 < (int)lt1.q.size(); ++k1)
@@ -451,6 +541,7 @@ static void heff_plan(const TensorDesc& L, const TensorDesc& W1, const TensorDes
                 for (int64_t e2 = 0; e2 < g2; ++e2)
                   for (int64_t c = 0; c < gw; ++c) {
                     outs.push_back({T3->offset[b] + ((e1 * g2 + e2) * gw + c) * gy, g1 * g2 * gw * gy});
+                    outs_alt.push_back({Tp.off[b] + (e1 * g2 + e2) * Tp.ld[b] + c * gy, g1 * g2 * Tp.ld[b]});
                     key.push_back(ls1m.start[k1] + e1);
                     key.push_back(ls2m.start[k2] + e2);
                     key.push_back(lw3m.start[kw] + c);
@@ -504,6 +595,12 @@ static void heff_plan(const TensorDesc& L, const TensorDesc& W1, const TensorDes
         for (auto& q : ins) ha.planes.push_back(q);
         for (auto& q : outs) ha.planes.push_back(q);
         ha.tasks.push_back(task);
+        for (auto& q : ins) ha.planes_alt.push_back(q);
+        for (auto& q : outs_alt) ha.planes_alt.push_back(q);
+        HTask ta = task;
+        ta.out_buf = 11;
+        ta.out_ps = Tp.total;
+        ha.tasks_alt.push_back(ta);
       }
     hc.ncls = (int32_t)classes.size();
     ha.ncls = hc.ncls;
@@ -543,6 +640,7 @@ static void heff_plan(const TensorDesc& L, const TensorDesc& W1, const TensorDes
   s4.name = "gemm_T3_R";
   s4.ta = Elem::Inter;
   s4.transb = true;
+  s4.has_alt = true;
   {
     const int nW = (int)W2.legs[3].q.size(), nY = (int)psi.legs[3].q.size();
     int32_t tt[5], rt[3];
@@ -573,6 +671,16 @@ static void heff_plan(const TensorDesc& L, const TensorDesc& W1, const TensorDes
           g.lda = (int32_t)K;
           g.ldb = (int32_t)K;
           s4.segs.push_back(g);
+          GemmSeg h = g;
+          h.a_off = Tp.off[ab];
+          h.a_buf = 11;
+          h.lda = (int32_t)Tp.ld[ab];
+          h.a_ps = Tp.total;
+          h.b_off = Rp.off[bb];
+          h.b_buf = 9;
+          h.ldb = (int32_t)Rp.ld[bb];
+          h.b_ps = Rp.total;
+          s4.segs_alt.push_back(h);
           s4.flops += 2.0 * (double)M * (double)N * (double)K;
         }
       p.seg_count = (int32_t)s4.segs.size() - p.seg_begin;
@@ -582,6 +690,9 @@ static void heff_plan(const TensorDesc& L, const TensorDesc& W1, const TensorDes
     s4.bytes32 = 4.0 * (double)T3->numel + 8.0 * ((double)R.numel + (double)psi.numel);
   }
   P.steps.push_back(std::move(hc));
+  P.steps.push_back(std::move(spL));
+  P.steps.push_back(std::move(spR));
+  P.steps.push_back(std::move(spP));
   P.steps.push_back(std::move(s1));
   P.steps.push_back(std::move(ha));
   P.steps.push_back(std::move(s4));
@@ -610,6 +721,8 @@ static void heff_batch(const std::vector<const PlanData*>& subs, PlanData& P) {
         e.tc = st.tc;
         e.transb = st.transb;
         e.th = st.th;
+        e.has_alt = st.has_alt;
+        e.constant = st.constant;
         P.steps.push_back(std::move(e));
       }
     }
@@ -632,6 +745,11 @@ static void heff_batch(const std::vector<const PlanData*>& subs, PlanData& P) {
           p.seg_begin += sb;
           b.probs.push_back(p);
         }
+        for (auto g : a.segs_alt) {
+          g.a_buf += base;
+          g.b_buf += base;
+          b.segs_alt.push_back(g);
+        }
       } else if (a.kind == StepKind::HCoef) {
         for (auto rt : a.terms) {
           rt.cls += cls_base;
@@ -651,8 +769,28 @@ static void heff_batch(const std::vector<const PlanData*>& subs, PlanData& P) {
           t.out_buf += base;
           b.tasks.push_back(t);
         }
+        const int32_t pba = (int32_t)b.planes_alt.size();
+        for (auto q : a.planes_alt) b.planes_alt.push_back(q);
+        for (auto t : a.tasks_alt) {
+          t.cls += cls_base;
+          t.plane_begin += pba;
+          t.in_buf += base;
+          t.out_buf += base;
+          b.tasks_alt.push_back(t);
+        }
         b.ncls += a.ncls;
         b.nmax = std::max(b.nmax, a.nmax);
+      } else if (a.kind == StepKind::Split) {
+        const int32_t jb = (int32_t)b.sjobs.size();
+        for (auto j : a.sjobs) {
+          j.in_buf += base;
+          j.out_buf += base;
+          b.sjobs.push_back(j);
+        }
+        for (auto w : a.swork) {
+          w.job += jb;
+          b.swork.push_back(w);
+        }
       }
     }
     // class ids advance by the member's class count
@@ -660,6 +798,7 @@ static void heff_batch(const std::vector<const PlanData*>& subs, PlanData& P) {
       if (st.kind == StepKind::HCoef) cls_base += st.ncls;
     P.nslots += S.nslots;
     P.psi_numel += S.psi_numel;
+    P.has_planes = (i == 0 ? S.has_planes : (P.has_planes && S.has_planes));
   }
 }
 
@@ -684,38 +823,67 @@ static int round_nmax(int n) {
   fail(BST_E_INVALID, "two-site MPO apply needs more than 64 channels per sector pair");
 }
 
-// Tiles of a grouped GEMM for one tile shape, largest cost first (a stable
-// sort keeps the tiles of one problem together).
+// Tiles of a grouped GEMM for one tile shape, in dispatch order.
+//
+// Workgroups go to the 8 XCDs round-robin by linear id, and each XCD has its
+// own L2.  The tiles of one problem share their A row panels and B column
+// panels, so whole problems are bin-packed onto XCDs (largest cost first,
+// each to the least loaded XCD), each XCD's tiles are ordered by cost with a
+// problem's tiles kept together, and the eight lists are interleaved so that
+// linear id 8*pos + x is tile pos of XCD x.  Short lists are padded with
+// empty tiles (prob = -1) that exit at once.
+constexpr int kXcds = 8;
+
 static std::vector<GemmTile> make_tiles(const Step& st, int bm, int bn) {
-  struct TC {
+  struct Prob {
     double cost;
-    GemmTile t;
+    int32_t idx;
   };
-  std::vector<TC> v;
+  std::vector<Prob> pr;
   for (size_t pi = 0; pi < st.probs.size(); ++pi) {
     const auto& p = st.probs[pi];
     int64_t k = 0;
     for (int s = 0; s < p.seg_count; ++s) k += st.segs[p.seg_begin + s].K;
-    for (int m0 = 0; m0 < p.M; m0 += bm)
-      for (int n0 = 0; n0 < p.N; n0 += bn) v.push_back({(double)(k + 16), {(int32_t)pi, m0, n0, 0}});
+    const double ntile = (double)((p.M + bm - 1) / bm) * (double)((p.N + bn - 1) / bn);
+    pr.push_back({ntile * (double)(k + 16), (int32_t)pi});
   }
-  std::stable_sort(v.begin(), v.end(), [](const TC& a, const TC& b) { return a.cost > b.cost; });
+  std::stable_sort(pr.begin(), pr.end(), [](const Prob& a, const Prob& b) { return a.cost > b.cost; });
+  std::vector<std::vector<GemmTile>> bins(kXcds);
+  std::vector<double> load(kXcds, 0.0);
+  for (const auto& q : pr) {
+    int x = 0;
+    for (int i = 1; i < kXcds; ++i)
+      if (load[i] < load[x]) x = i;
+    load[x] += q.cost;
+    const auto& p = st.probs[q.idx];
+    for (int m0 = 0; m0 < p.M; m0 += bm)
+      for (int n0 = 0; n0 < p.N; n0 += bn) bins[x].push_back({q.idx, m0, n0, 0});
+  }
+  size_t longest = 0;
+  for (auto& b : bins) longest = std::max(longest, b.size());
   std::vector<GemmTile> out;
-  out.reserve(v.size());
-  for (auto& x : v) out.push_back(x.t);
+  out.reserve(longest * kXcds);
+  for (size_t pos = 0; pos < longest; ++pos)
+    for (int x = 0; x < kXcds; ++x)
+      out.push_back(pos < bins[x].size() ? bins[x][pos] : GemmTile{-1, 0, 0, 0});
+  // drop trailing empty tiles
+  while (!out.empty() && out.back().prob < 0) out.pop_back();
   return out;
 }
 
 int default_tile(const Step& st, bst_precision form) {
   auto it = st.tile_choice.find((int)form);
   if (it != st.tile_choice.end()) return it->second;
-  // heuristic: 64x64 unless most problems are small
+  // float64 / float32: the LDS-staged 64x64 kernel
+  if (form == BST_FP64 || form == BST_FP32) return 5;
+  // on-the-fly split forms: 64x64 unless most problems are small
   const auto& shapes = gemm_tile_shapes(form);
   double avg = 0;
   for (auto& p : st.probs) avg += std::min(p.M, p.N);
   if (!st.probs.empty()) avg /= (double)st.probs.size();
+  const int want = avg < 48 ? 32 : 64;
   for (size_t i = 0; i < shapes.size(); ++i)
-    if (shapes[i].bm == (avg < 48 ? 32 : 64) && shapes[i].bn == (avg < 48 ? 32 : 64)) return (int)i;
+    if (shapes[i].bm == want && shapes[i].bn == want) return (int)i;
   return 0;
 }
 
@@ -727,14 +895,20 @@ void finalize(PlanData& P) {
       case StepKind::Gemm: {
         st.off0 = put(P.blob, st.probs);
         st.off1 = put(P.blob, st.segs);
+        if (st.has_alt) st.off2 = put(P.blob, st.segs_alt);
         st.tile_lists.clear();
+        std::vector<TileShape> all;
         for (int f = 0; f < 4; ++f)
-          for (const auto& sh : gemm_tile_shapes((bst_precision)f)) {
-            auto key = std::make_pair(sh.bm, sh.bn);
-            if (st.tile_lists.count(key)) continue;
-            auto tl = make_tiles(st, sh.bm, sh.bn);
-            st.tile_lists[key] = {put(P.blob, tl), (int64_t)tl.size()};
-          }
+          for (const auto& sh : gemm_tile_shapes((bst_precision)f)) all.push_back(sh);
+        if (st.has_alt)
+          for (int np = 2; np <= 3; ++np)
+            for (const auto& sh : gemm_planes_shapes(np)) all.push_back(sh);
+        for (const auto& sh : all) {
+          auto key = std::make_pair(sh.bm, sh.bn);
+          if (st.tile_lists.count(key)) continue;
+          auto tl = make_tiles(st, sh.bm, sh.bn);
+          st.tile_lists[key] = {put(P.blob, tl), (int64_t)tl.size()};
+        }
         break;
       }
       case StepKind::Permute:
@@ -772,8 +946,17 @@ void finalize(PlanData& P) {
         st.off1 = put(P.blob, st.planes);
         st.off2 = put(P.blob, work);
         st.n0 = (int64_t)work.size();
+        if (st.has_alt) {
+          st.off3 = put(P.blob, st.tasks_alt);
+          st.off4 = put(P.blob, st.planes_alt);
+        }
         break;
       }
+      case StepKind::Split:
+        st.off0 = put(P.blob, st.sjobs);
+        st.off1 = put(P.blob, st.swork);
+        st.n0 = (int64_t)st.swork.size();
+        break;
     }
   }
   size_t off = 0;
@@ -784,6 +967,14 @@ void finalize(PlanData& P) {
   P.ws_coef64_off = off;
   off = align256(off + sizeof(double) * (size_t)std::max(P.coef_entries, 1));
   P.ws_coef32_off = off;
+  off = align256(off + sizeof(float) * (size_t)std::max(P.coef_entries, 1));
+  P.ws_cnt_off = off;
+  off = align256(off + sizeof(int32_t) * (size_t)std::max(P.coef_entries, 1));
+  P.ws_idx_off = off;
+  off = align256(off + sizeof(int32_t) * (size_t)std::max(P.coef_entries, 1));
+  P.ws_val64_off = off;
+  off = align256(off + sizeof(double) * (size_t)std::max(P.coef_entries, 1));
+  P.ws_val32_off = off;
   off = align256(off + sizeof(float) * (size_t)std::max(P.coef_entries, 1));
   for (auto& ib : P.internals) {
     ib.ws_off = off;
@@ -971,10 +1162,14 @@ bst_status bst_plan_tiles(const bst_plan* p, char* buf, size_t cap) {
   BST_TRY
   if (!p || !buf || cap == 0) fail(BST_E_INVALID, "null argument");
   std::string s;
-  for (const auto& st : p->p.steps) {
+  const PlanData& P = p->p;
+  for (const auto& st : P.steps) {
     if (st.kind != StepKind::Gemm) continue;
-    const auto& sh = gemm_tile_shapes(p->p.prec)[default_tile(st, p->p.prec)];
-    s += st.name + ":" + std::to_string(sh.bm) + "x" + std::to_string(sh.bn) + ";";
+    const bool pl = uses_planes(P, P.prec) && st.has_alt;
+    const TileShape sh = pl ? gemm_planes_shapes(P.prec == BST_BF16X6 ? 3 : 2)[planes_tile(st, P.prec)]
+                            : gemm_tile_shapes(P.prec)[default_tile(st, P.prec)];
+    s += st.name + ":" + std::to_string(sh.bm) + "x" + std::to_string(sh.bn) +
+         (sh.direct ? "d" : "l") + (pl ? "p" : "") + ";";
   }
   std::strncpy(buf, s.c_str(), cap - 1);
   buf[cap - 1] = 0;

@@ -32,7 +32,7 @@ const TensorDesc* desc_of(const bst_tensor* t);
 bst_tensor* wrap_tensor(std::unique_ptr<TensorDesc> d);
 void set_last_error(const std::string& s);
 
-enum class StepKind { Permute, Gemm, HCoef, HApply };
+enum class StepKind { Permute, Gemm, HCoef, HApply, Split };
 
 // Element type of a step operand: fixed, or the plan's intermediate type
 // (float64 for BST_FP64, float32 for the other forms).
@@ -65,8 +65,19 @@ struct Step {
   std::vector<HTask> tasks;
   std::vector<HPlane> planes;
   Elem th = Elem::Inter;
+  // bfloat16-plane variant used by the split forms (H_eff only): GEMM
+  // segments on pre-split operands, MPO tasks writing T3 as planes
+  bool has_alt = false;
+  std::vector<GemmSeg> segs_alt;
+  std::vector<HTask> tasks_alt;
+  std::vector<HPlane> planes_alt;
+  // Split (float64 -> bfloat16 planes), run only by the split forms
+  std::vector<SplitJob> sjobs;
+  std::vector<SplitWork> swork;
+  // operand-only preparation, valid for as long as L, W and R do not change
+  bool constant = false;
   // device table offsets inside the plan blob (filled by finalize)
-  size_t off0 = 0, off1 = 0, off2 = 0, off3 = 0;
+  size_t off0 = 0, off1 = 0, off2 = 0, off3 = 0, off4 = 0, off5 = 0;
   int64_t n0 = 0, n1 = 0;
   std::map<std::pair<int, int>, std::pair<size_t, int64_t>> tile_lists;  // (bm,bn) -> (off, n)
 };
@@ -88,9 +99,12 @@ struct PlanData {
   // heff bookkeeping (single apply): psi numel for Lanczos
   int64_t psi_numel = 0;
   int64_t t1_numel = 0, t3_numel = 0;
+  bool has_planes = false;      // split forms run the bfloat16-plane variant
+  bool sparse_mpo = true;       // MPO apply runs only the nonzero h entries
   // finalize
   std::vector<uint8_t> blob;
   size_t ws_ptr_off = 0, ws_blob_off = 0, ws_coef64_off = 0, ws_coef32_off = 0, ws_bytes = 0;
+  size_t ws_cnt_off = 0, ws_idx_off = 0, ws_val64_off = 0, ws_val32_off = 0;
   int32_t coef_entries = 0;
   bool finalized = false;
   // execution state
@@ -113,11 +127,16 @@ void* upload_table(PlanData& p, const std::vector<void*>& ptrs, void* ws, size_t
                    hipStream_t s);
 std::vector<void*> build_ptrs(PlanData& p, const void* const* in, void* const* out, void* ws);
 // Enqueues the plan's kernels with the given device pointer table.
+// skip_const: leave out the steps that depend only on L, W and R (their
+// results from an earlier execute on the same workspace are still valid).
 void run_steps(PlanData& p, void* ws, void* const* dptrs, bst_precision prec, hipStream_t s,
-               bool skip_coef, std::vector<std::pair<hipEvent_t, hipEvent_t>>* ev = nullptr);
+               bool skip_const, std::vector<std::pair<hipEvent_t, hipEvent_t>>* ev = nullptr);
+bool uses_planes(const PlanData& p, bst_precision prec);
+bool step_runs(const PlanData& p, const Step& st, bst_precision prec, bool skip_const);
+int planes_tile(const Step& st, bst_precision prec);
 int default_tile(const Step& st, bst_precision form);
 void run_steps_impl(PlanData& p, void* ws, void* const* dptrs, bst_precision prec, hipStream_t s,
-                    bool skip_coef, int only_step,
+                    bool skip_const, int only_step,
                     std::vector<std::pair<hipEvent_t, hipEvent_t>>* ev);
 // Applies tile choices recorded by the autotuner (file named by BST_TUNE_CACHE).
 void apply_tune_cache(PlanData& p);

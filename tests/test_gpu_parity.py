@@ -167,3 +167,34 @@ def test_heff_graph_replay_matches_eager():
         junk = torch.randn(1000, device=DEV).sum().item()   # eager work between replays
         assert np.array_equal(host(out), eager), rep
     plan.use_graph(False)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "bf16x6"])
+def test_every_gemm_variant(prec):
+    """Every compiled GEMM variant (tile shape, LDS-staged or direct) that the
+    autotuner may pick gives the oracle's result on the chi = 512 H_eff."""
+    specs, O = heff_operands(2)
+    ref = orc.heff_apply(O["L"], O["W1"], O["W2"], O["R"], O["psi"]).data
+    T, plan = lib_heff(specs, prec)
+    for tile in range(plan.tile_count(prec)):
+        plan.set_tile(prec, tile)
+        got = run_heff(plan, O)
+        nrm, mx = rel_err(got, ref)
+        _print("variant", prec, tile, plan.tiles(), nrm)
+        assert nrm <= TOL[prec]
+    # the generic contraction path (no pre-split planes) with every variant
+    rng = np.random.default_rng(5)
+    A, B = _random_pair(rng, 3, 3, 2)
+    free = [i for i, l in enumerate(A.labels) if l not in B.labels]
+    A = orc.BlockTensor(A.labels, [(d, [(q, g * 23 if i == free[0] else g) for q, g in s])
+                                   for i, (d, s) in enumerate(A.legs)])
+    A.data[:] = rng.standard_normal(A.numel)
+    C = orc.contract(A, B)
+    tA, tB = bst.Tensor(A.labels, A.legs), bst.Tensor(B.labels, B.legs)
+    tC, cplan = bst.contract_plan(tA, tB, prec)
+    for tile in range(cplan.tile_count(prec)):
+        cplan.set_tile(prec, tile)
+        out = torch.full((tC.numel,), np.nan, dtype=torch.float64, device=DEV)
+        cplan.execute([dev(A.data), dev(B.data)], [out], bst.workspace(cplan.workspace_bytes))
+        torch.cuda.synchronize()
+        assert rel_err(host(out), C.data)[0] <= TOL[prec], tile
