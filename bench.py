@@ -44,6 +44,11 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the single-apply, batched-apply and permute measurements")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the default tile variants (short runs under a profiler)")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="first time a plain device copy of this many MiB (a kernel of known "
+                         "traffic that calibrates hardware byte counters)")
     return ap.parse_args()
 
 
@@ -70,6 +75,7 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
     dev = "cuda"
+    copy_cal = copy_calibration(torch, dev, a.copy_mib) if a.copy_mib > 0 else None
     w = wl.WORKLOADS[WORKLOAD]
     v = wl.gaussian_sector_dims(w["chi"], w["qmax"])
     specs = wl.heff_specs(w["spin"], v, v)
@@ -97,22 +103,24 @@ def main():
     tuned = {}
     for prec in (a.prec, "fp64"):
         plan.set_precision(prec)
-        plan.autotune([g["L"], g["W1"], g["W2"], g["R"], g["psi0"]], [tune_out], tune_ws, reps=3)
+        if not a.no_tune:
+            plan.autotune([g["L"], g["W1"], g["W2"], g["R"], g["psi0"]], [tune_out], tune_ws,
+                          reps=3)
         tuned[prec] = plan.tiles()
     del tune_ws, tune_out
 
-    def solve(prec, timing=False):
+    def solve(prec, timing=False, three_pass=False):
         return bst.lanczos_ground(plan, ops, g["psi0"], m, prec, True, ws=ws, psi_out=psi_out,
-                                  timing=timing)
+                                  timing=timing, three_pass=three_pass)
 
-    def timed(prec, steps, warmup):
+    def timed(prec, steps, warmup, three_pass=False):
         for _ in range(warmup):
-            solve(prec)
+            solve(prec, three_pass=three_pass)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         res = None
         for _ in range(steps):
-            res = solve(prec)
+            res = solve(prec, three_pass=three_pass)
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / steps, res
 
@@ -146,13 +154,14 @@ def main():
                     / avg_ms / 1e6)
 
     def cgs_bytes(pass_id):
-        # algorithmic bytes of one solve's pass (V rows read, w read/written)
+        # algorithmic bytes of one solve's pass, lagged schedule: step j
+        # (0-based) reads basis rows 0..j and z; the update pass also writes
+        # row j and (except on the last step) row j+1
         tot = 0.0
-        for j in range(1, m + 1):
-            if pass_id == 1:
-                tot += 8.0 * n * (j + 1)
-            else:
-                tot += 8.0 * n * (j + 2)
+        for j in range(m):
+            tot += 8.0 * n * (j + 2)
+            if pass_id == 2:
+                tot += 8.0 * n * (2 if j + 1 < m else 1)
         return tot
 
     def hbm_roof(key, total_bytes, prof):
@@ -168,7 +177,6 @@ def main():
         "mpo_apply": hbm_roof("mpo_apply", mpo_bytes * kc["mpo_apply"], prof_split),
         "cgs_pass1": hbm_roof("cgs_pass1", cgs_bytes(1), prof_split),
         "cgs_pass2": hbm_roof("cgs_pass2", cgs_bytes(2), prof_split),
-        "cgs_pass3": hbm_roof("cgs_pass3", cgs_bytes(3), prof_split),
         "fp64_gemm_L_psi": gemm_roof("gemm_L_psi", "gemm_L_psi", prof64, "fp64", PEAK["fp64_tflops"]),
         "fp64_gemm_T3_R": gemm_roof("gemm_T3_R", "gemm_T3_R", prof64, "fp64", PEAK["fp64_tflops"]),
     }
@@ -186,8 +194,17 @@ def main():
                 "peak": PEAK["hbm_gbs"], "unit": "GB/s", "frac": round(r["frac"], 4),
                 "traffic": None, "alg_bytes_per_launch": per_launch}
 
-    extras = {} if a.no_extras else bench_extras(bst, wl, torch, dev, plan, ins_apply=[
-        g["L"], g["W1"], g["W2"], g["R"], g["psi0"]], apply_flops=apply_flops)
+    extras = {}
+    if not a.no_extras:
+        # the same split solve under the textbook three-pass schedule
+        ms3, res3 = timed(a.prec, max(2, a.steps // 2), 1, three_pass=True)
+        extras["three_pass_schedule"] = {
+            "ms_per_solve": round(ms3 * 1e3, 3),
+            "kernels": {k: round(v, 4) for k, v in
+                        solve(a.prec, timing=True, three_pass=True)["kernel_ms"].items()},
+            "energy_rel_diff_vs_lagged": abs(res3["energy"] - es) / abs(es)}
+    extras.update({} if a.no_extras else bench_extras(bst, wl, torch, dev, plan, ins_apply=[
+        g["L"], g["W1"], g["W2"], g["R"], g["psi0"]], apply_flops=apply_flops))
 
     # ---- CPU baseline: the oracle's H_eff apply on the host cores ----------
     cpu = None
@@ -224,8 +241,20 @@ def main():
         "kernel_roofline": kern,
         "tiles": tuned,
         "extras": extras,
+        "copy_calibration": copy_cal,
     }
     print(json.dumps(out), flush=True)
+
+
+def copy_calibration(torch, dev, mib):
+    """Three device-to-device copies of `mib` MiB: each reads and writes
+    exactly mib MiB, which scales the FETCH_SIZE / WRITE_SIZE counters."""
+    src = torch.ones(mib * 2**20 // 8, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    ms = _time_ms(torch, lambda: dst.copy_(src), 3, warm=0)
+    del src, dst
+    return {"mib": mib, "reps": 3, "ms": round(ms, 4),
+            "gbs": round(2 * mib * 2**20 / ms / 1e6, 1)}
 
 
 def _time_ms(torch, fn, reps, warm=2):

@@ -55,6 +55,9 @@ class LanczosInfo(C.Structure):
                 ("kernel_calls", C.c_int32 * 8)]
 
 
+# Kernel classes of the timing record.  With the default (lagged) schedule
+# cgs_pass1 is the V^T z dot pass, cgs_pass2 the update pass and cgs_pass3 is
+# unused; the three-pass schedule uses all three.
 LANCZOS_KERNEL_CLASSES = ["gemm_L_psi", "mpo_apply", "gemm_T3_R", "prep", "cgs_pass1",
                           "cgs_pass2", "cgs_pass3", "vector_other"]
 
@@ -388,9 +391,12 @@ def lanczos_workspace(plan: Plan, nsteps: int) -> int:
 
 
 def lanczos_ground(plan: Plan, ops, psi0, nsteps: int, prec="fp64", refine: bool = True,
-                   ws=None, psi_out=None, stream=None, timing: bool = False):
+                   ws=None, psi_out=None, stream=None, timing: bool = False,
+                   three_pass: bool = False):
     """ops = [L, W1, W2, R] device tensors; psi0 device tensor.  Returns a dict
-    with energy, theta, steps, residual, beta_min, alpha, beta and psi."""
+    with energy, theta, steps, residual, beta_min, alpha, beta and psi.
+    three_pass selects the textbook reorthogonalisation schedule (three passes
+    over the basis per step) instead of the lagged two-pass one."""
     import torch
     if ws is None:
         ws = workspace(lanczos_workspace(plan, nsteps), psi0.device)
@@ -407,7 +413,7 @@ def lanczos_ground(plan: Plan, ops, psi0, nsteps: int, prec="fp64", refine: bool
     a = (C.c_void_p * 4)(*[_ptr(t) for t in ops])
     e = C.c_double()
     info = LanczosInfo()
-    info.flags = 1 if timing else 0
+    info.flags = (1 if timing else 0) | (2 if three_pass else 0)
     _check(_lib.bst_lanczos_ground(plan.handle, a, C.c_void_p(_ptr(psi0)), nsteps, _prec(prec),
                                    1 if refine else 0, C.c_void_p(_ptr(psi_out)), C.byref(e),
                                    C.byref(info), C.c_void_p(_ptr(ws)), _stream(stream)))

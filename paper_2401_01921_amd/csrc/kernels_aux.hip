@@ -469,6 +469,139 @@ hipError_t launch_lanczos_step_end(const double* partial, int64_t n_for_grid, co
   return hipGetLastError();
 }
 
+// Second Gram-Schmidt pass lagged by one step (delayed CGS2: Bielich et
+// al., Parallel Computing 2022).  On entry row j of V holds u_j, the
+// previous step's residual after one projection, and z = H u_j.  With
+// rb = 1/beta_{j-1} (1 when j = 0), dprev the previous step's second-pass
+// coefficients and p = V^T z over rows 0..j (row j read as u_j), each
+// element gets
+//   v_j = (u_j - sum_{k<j} dprev_k v_k) rb        written back into row j
+//   w   = z rb - sum_{k<j} c_k v_k - c_j v_j       written to vnext (if any)
+// where c_k = p_k rb and c_j = (p_j - sum_k dprev_k p_k) rb^2 are v_k.(z rb)
+// with the corrected v_j.  The block partials are v_k.w (k < j), v_j.w and
+// w.w (j + 2 values); block 0 stores c_0..c_j in c_out.
+template <int NV>
+__global__ __launch_bounds__(256) void cgs_lag_update_kernel(
+    double* V, uint32_t ldv, uint32_t n, int j, const double* __restrict__ z,
+    const double* __restrict__ p, const double* __restrict__ dprev,
+    const double* __restrict__ beta_prev, double* vnext, double* __restrict__ c_out,
+    double* __restrict__ partial) {
+  constexpr int NR = NV + 2;
+  __shared__ double red[4 * NR];
+  __shared__ double cs[NV], ds[NV];
+  __shared__ double csj_s;
+  const int tid = threadIdx.x;
+  const double b = j > 0 ? beta_prev[0] : 1.0;
+  const double rb = b > 0.0 ? 1.0 / b : 0.0;
+  for (int k = tid; k < NV; k += 256) {
+    cs[k] = k < j ? p[k] * rb : 0.0;
+    ds[k] = k < j ? dprev[k] : 0.0;
+  }
+  if (tid == 0) {
+    double t = p[j];
+    for (int k = 0; k < j; ++k) t -= dprev[k] * p[k];
+    csj_s = t * rb * rb;
+  }
+  __syncthreads();
+  const double csj = csj_s;
+  if (blockIdx.x == 0) {
+    for (int k = tid; k < j; k += 256) c_out[k] = cs[k];
+    if (tid == 0) c_out[j] = csj;
+  }
+  double acc[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+  double accj = 0.0, accw = 0.0;
+  char* Vb = reinterpret_cast<char*>(V);
+  const uint32_t rowb = ldv * 8u;
+  const uint32_t rowj = (uint32_t)j * rowb;
+  const uint32_t stride = gridDim.x * 256u;
+  for (uint32_t i = blockIdx.x * 256u + tid; i < n; i += stride) {
+    double v[NV];
+    uint32_t off = i * 8u;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      v[k] = (k < j) ? __builtin_nontemporal_load(reinterpret_cast<const double*>(Vb + off)) : 0.0;
+      off += rowb;
+      asm volatile("" : "+v"(off));
+    }
+    double* uj = reinterpret_cast<double*>(Vb + (i * 8u + rowj));
+    const double u = __builtin_nontemporal_load(uj);
+    const double zi = __builtin_nontemporal_load(z + i);
+    double t = 0.0, s = 0.0;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      t += ds[k] * v[k];
+      s += cs[k] * v[k];
+    }
+    const double vj = (u - t) * rb;
+    const double w = (zi * rb - s) - csj * vj;
+    __builtin_nontemporal_store(vj, uj);
+    if (vnext) __builtin_nontemporal_store(w, vnext + i);
+#pragma unroll
+    for (int k = 0; k < NV; ++k) acc[k] += v[k] * w;
+    accj += vj * w;
+    accw += w * w;
+  }
+  const int wave = tid >> 6, lane = tid & 63;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    if (k < j) {
+      const double r = wave_sum(acc[k]);
+      if (lane == 0) red[wave * NR + k] = r;
+    }
+  }
+  {
+    const double r1 = wave_sum(accj);
+    const double r2 = wave_sum(accw);
+    if (lane == 0) {
+      red[wave * NR + j] = r1;
+      red[wave * NR + j + 1] = r2;
+    }
+  }
+  __syncthreads();
+  for (int k = tid; k < j + 2; k += 256) {
+    const double r = ((red[k] + red[NR + k]) + red[2 * NR + k]) + red[3 * NR + k];
+    partial[(int64_t)k * gridDim.x + blockIdx.x] = r;
+  }
+}
+
+// After the lagged update of step j: dn holds v_k.w (k <= j) and w.w.
+// alpha_j = c_j - dprev_{j-1} + dn_j (the first term is v_j.(z rb); the
+// second removes the part of z rb that came from u_j's own correction, the
+// third is the second-pass coefficient); beta_j^2 = w.w - sum_k dn_k^2
+// (the norm of w after its lagged second projection); dprev <- dn.
+__global__ void cgs_lag_end_kernel(const double* __restrict__ dn, const double* __restrict__ c,
+                                   int j, double* dprev, double* __restrict__ alpha,
+                                   double* __restrict__ beta) {
+  if (threadIdx.x != 0) return;
+  double ss = 0.0;
+  for (int k = 0; k <= j; ++k) ss += dn[k] * dn[k];
+  const double q = dn[j + 1] - ss;
+  alpha[j] = (c[j] - (j > 0 ? dprev[j - 1] : 0.0)) + dn[j];
+  beta[j] = sqrt(q > 0.0 ? q : 0.0);
+  for (int k = 0; k <= j; ++k) dprev[k] = dn[k];
+}
+
+hipError_t launch_cgs_lag_update(double* V, int64_t ldv, int64_t n, int j, const double* z,
+                                 const double* p, const double* dprev, const double* beta_prev,
+                                 double* vnext, double* c_out, double* partial, double* dn,
+                                 hipStream_t s) {
+  if (j < 0 || j + 2 > kMaxVecs + 1 || !fits32(V, ldv, n, j + 1)) return hipErrorInvalidValue;
+  const int G = vec_grid(n);
+  const int nv = j > 0 ? j : 1;
+  BST_NV_DISPATCH(cgs_lag_update_kernel, dim3(G), dim3(256), 0, s, V, (uint32_t)ldv, (uint32_t)n,
+                  j, z, p, dprev, beta_prev, vnext, c_out, partial);
+  hipLaunchKernelGGL(reduce_partials_kernel, dim3(j + 2), dim3(256), 0, s, partial, G, dn);
+  return hipGetLastError();
+}
+
+hipError_t launch_cgs_lag_end(const double* dn, const double* c, int j, double* dprev,
+                              double* alpha, double* beta, hipStream_t s) {
+  hipLaunchKernelGGL(cgs_lag_end_kernel, dim3(1), dim3(64), 0, s, dn, c, j, dprev, alpha, beta);
+  return hipGetLastError();
+}
+
 template <int NV>
 __global__ __launch_bounds__(256) void combine_kernel(const double* __restrict__ V, int64_t ldv,
                                                       int64_t n, int nv,

@@ -45,8 +45,9 @@ LanczosLayout layout(const PlanData& P, int nsteps) {
   L.HY = off;
   off = al(off + sizeof(double) * std::max<size_t>(n, 1));
   L.scal = off;
-  // c[kMaxVecs], d[kMaxVecs], alpha, beta, s [kMaxVecs each], misc[16]
-  off = al(off + sizeof(double) * (5 * (size_t)kMaxVecs + 16));
+  // c, d, alpha, beta, s [kMaxVecs each], misc[16], cproj[kMaxVecs],
+  // dn[kMaxVecs + 2]
+  off = al(off + sizeof(double) * (7 * (size_t)kMaxVecs + 32));
   L.partial = off;
   off = al(off + sizeof(double) * (size_t)(kMaxVecs + 1) * kVecBlocks);
   L.end = off;
@@ -233,6 +234,9 @@ bst_status bst_lanczos_ground(bst_plan* heff, const void* const* ops, const void
   double* beta = sc + 3 * kMaxVecs;
   double* svec = sc + 4 * kMaxVecs;
   double* misc = sc + 5 * kMaxVecs;   // [0..1] psi0 dot2, [2] norm2, [4..5] num, [6] r2
+  double* cproj = misc + 16;
+  double* dn = cproj + kMaxVecs;
+  const bool three_pass = info && (info->flags & BST_LANCZOS_THREE_PASS);
   double* partial = reinterpret_cast<double*>(wb + Lo.partial);
 
   // plan tables, and one pointer table per Krylov vector plus the refinement
@@ -282,14 +286,27 @@ bst_status bst_lanczos_ground(bst_plan* heff, const void* const* ops, const void
   for (int j = 0; j < nsteps; ++j) {
     matvec(tables[j], matvec_prec, j > 0);
     const int nv = j + 1;
-    timed(4, [&] { check_hip(launch_multidot(V, ldv, n, nv, W, partial, c, s), "cgs pass 1"); });
-    timed(5, [&] { check_hip(launch_project(V, ldv, n, nv, c, W, W, 1, partial, d, s), "cgs pass 2"); });
-    timed(6, [&] { check_hip(launch_project(V, ldv, n, nv, d, W, W, 2, partial, nullptr, s), "cgs pass 3"); });
-    timed(7, [&] {
-      double* vnext = j + 1 < nsteps ? V + (size_t)(j + 1) * ldv : nullptr;
-      check_hip(launch_lanczos_step_end(partial, n, c, d, j, alpha, beta, misc + 2, W, vnext, n, s),
-                "step end");
-    });
+    double* vnext = j + 1 < nsteps ? V + (size_t)(j + 1) * ldv : nullptr;
+    if (three_pass) {
+      // w -= V (V^T w) twice, then alpha, beta and v_{j+1} = w / beta
+      timed(4, [&] { check_hip(launch_multidot(V, ldv, n, nv, W, partial, c, s), "cgs pass 1"); });
+      timed(5, [&] { check_hip(launch_project(V, ldv, n, nv, c, W, W, 1, partial, d, s), "cgs pass 2"); });
+      timed(6, [&] { check_hip(launch_project(V, ldv, n, nv, d, W, W, 2, partial, nullptr, s), "cgs pass 3"); });
+      timed(7, [&] {
+        check_hip(launch_lanczos_step_end(partial, n, c, d, j, alpha, beta, misc + 2, W, vnext, n, s),
+                  "step end");
+      });
+    } else {
+      // row j holds u_j (once projected); W = H u_j.  One pass of dots,
+      // then one pass that finishes v_j and projects W once into row j+1.
+      timed(4, [&] { check_hip(launch_multidot(V, ldv, n, nv, W, partial, c, s), "cgs dots"); });
+      timed(5, [&] {
+        check_hip(launch_cgs_lag_update(V, ldv, n, j, W, c, d, j > 0 ? beta + (j - 1) : beta,
+                                        vnext, cproj, partial, dn, s),
+                  "cgs update");
+      });
+      timed(7, [&] { check_hip(launch_cgs_lag_end(dn, cproj, j, d, alpha, beta, s), "step end"); });
+    }
   }
   std::vector<double> ha(nsteps), hb(nsteps), m0(2);
   check_hip(hipMemcpyAsync(ha.data(), alpha, sizeof(double) * nsteps, hipMemcpyDeviceToHost, s), "d2h");

@@ -102,23 +102,25 @@ def test_empty_and_degenerate_buffers():
 
 
 # ---------------------------------------------------------------- Lanczos
-def _lanczos_lib(specs, O, nsteps, prec, refine=True, psi0=None):
+def _lanczos_lib(specs, O, nsteps, prec, refine=True, psi0=None, three_pass=False):
     T, plan = lib_heff(specs, "fp64")
     ops = [dev(O[n].data) for n in ("L", "W1", "W2", "R")]
     p0 = dev(psi0 if psi0 is not None else wl.normal(999, O["psi"].numel))
-    r = bst.lanczos_ground(plan, ops, p0, nsteps, prec, refine)
+    r = bst.lanczos_ground(plan, ops, p0, nsteps, prec, refine, three_pass=three_pass)
     torch.cuda.synchronize()
     return r
 
 
+@pytest.mark.parametrize("three_pass", [False, True])
 @pytest.mark.parametrize("spin,singlet", [("1/2", -0.75), ("1", -2.0)])
-def test_lanczos_two_site_singlet(spin, singlet):
+def test_lanczos_two_site_singlet(spin, singlet, three_pass):
+    """Two sites: the Krylov space is exhausted (breakdown) before nsteps."""
     Ld, Rd, Wd, specs = chain_env.chain_heff_dense(2, spin)
     O = {"L": orc.from_dense(*specs["L"], Ld), "R": orc.from_dense(*specs["R"], Rd),
          "W1": orc.from_dense(*specs["W1"], Wd), "W2": orc.from_dense(*specs["W2"], Wd),
          "psi": orc.BlockTensor(*specs["psi"])}
-    r = _lanczos_lib(specs, O, O["psi"].numel, "fp64")
-    _print("singlet", spin, r["energy"], r["steps"])
+    r = _lanczos_lib(specs, O, O["psi"].numel, "fp64", three_pass=three_pass)
+    _print("singlet", spin, three_pass, r["energy"], r["steps"])
     assert abs(r["energy"] - singlet) < 1e-13
 
 
@@ -149,23 +151,27 @@ def test_lanczos_bf16x3_reports_its_error():
     assert abs(r["energy"] - E_ed) < 1e-6
 
 
-def test_lanczos_matches_oracle_medium():
+@pytest.mark.parametrize("three_pass", [False, True])
+def test_lanczos_matches_oracle_medium(three_pass):
     """Spin-1, chi = 256: the float64 GPU Lanczos reproduces the oracle's
-    alpha/beta and energies; the split forms reach the same refined energy."""
+    alpha/beta (all 40 steps) and energies under either reorthogonalisation
+    schedule; the split forms reach the same refined energy."""
     specs, O = heff_operands(5, recipe="dmrg_like", chi=256, qmax=8)
     psi0 = wl.normal(wl.seed_for(5, "psi0"), O["psi"].numel)
     mv = lambda v: orc.heff_apply(O["L"], O["W1"], O["W2"], O["R"],
                                   orc.BlockTensor(O["psi"].labels, O["psi"].legs, v)).data
     ref = orc.lanczos_ground(mv, psi0, 40)
-    r = _lanczos_lib(specs, O, 40, "fp64", psi0=psi0)
-    _print("medium fp64", r["energy"], ref["energy"], r["theta"] - ref["theta"])
+    r = _lanczos_lib(specs, O, 40, "fp64", psi0=psi0, three_pass=three_pass)
+    da = np.max(np.abs(r["alpha"] - ref["alpha"]))
+    db = np.max(np.abs(r["beta"][:39] - ref["beta"][:39]))
+    _print("medium fp64", three_pass, r["energy"], ref["energy"], r["theta"] - ref["theta"], da, db)
     assert r["steps"] == ref["steps"]
-    assert np.max(np.abs(r["alpha"][:10] - ref["alpha"][:10])) < 1e-10
+    assert da < 1e-11 and db < 1e-11
     assert abs(r["energy"] - ref["energy"]) <= 1e-12 * abs(ref["energy"])
     y = host(r["psi"])
     assert abs(abs(float(y @ ref["y"]) / np.linalg.norm(ref["y"])) - 1.0) < 1e-10
     for prec in ("fp32", "bf16x6", "bf16x3"):
-        rs = _lanczos_lib(specs, O, 40, prec, psi0=psi0)
+        rs = _lanczos_lib(specs, O, 40, prec, psi0=psi0, three_pass=three_pass)
         err = abs(rs["energy"] - ref["energy"]) / abs(ref["energy"])
         _print("medium", prec, "refined rel err", err, "theta rel err",
                abs(rs["theta"] - ref["theta"]) / abs(ref["theta"]))

@@ -179,3 +179,25 @@ def test_batch_plan_sums_members():
     b = bst.heff_batch_plan(plans)
     assert b.stats().flops == total
     assert b.n_in == 20 and b.n_out == 4
+
+
+def test_binding_fails_loudly_without_library(tmp_path):
+    """The binding has no fallback: a package copy without libbst.so must not import."""
+    import shutil
+    import subprocess
+    import sys
+    pkg = tmp_path / "paper_2401_01921_amd"
+    pkg.mkdir()
+    src = os.path.join(ROOT, "paper_2401_01921_amd")
+    for f in ("__init__.py", "bst.py"):
+        shutil.copy(os.path.join(src, f), pkg / f)
+    code = ("import sys\n"
+            "try:\n"
+            "    from paper_2401_01921_amd import bst\n"
+            "except ImportError as e:\n"
+            "    print('IMPORT_ERROR', e); sys.exit(0)\n"
+            "sys.exit(3)\n")
+    r = subprocess.run([sys.executable, "-c", code], cwd=str(tmp_path), capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "not built" in r.stdout
