@@ -153,15 +153,17 @@ def main():
                     bytes_gbs=(steps[name]["bytes_fp32" if prec != "fp64" else "bytes_fp64"])
                     / avg_ms / 1e6)
 
-    def cgs_bytes(pass_id):
-        # algorithmic bytes of one solve's pass, lagged schedule: step j
-        # (0-based) reads basis rows 0..j and z; the update pass also writes
-        # row j and (except on the last step) row j+1
+    def gs_bytes(kind):
+        # algorithmic bytes of one solve's Gram-Schmidt kernels (default
+        # schedule): the dot reads u_j and z; the pass of step j (0-based)
+        # reads basis rows 0..j and z and writes row j and (except on the
+        # last step) row j+1
         tot = 0.0
         for j in range(m):
-            tot += 8.0 * n * (j + 2)
-            if pass_id == 2:
-                tot += 8.0 * n * (2 if j + 1 < m else 1)
+            if kind == "dots":
+                tot += 16.0 * n
+            else:
+                tot += 8.0 * n * (j + 2) + 8.0 * n * (2 if j + 1 < m else 1)
         return tot
 
     def hbm_roof(key, total_bytes, prof):
@@ -175,14 +177,13 @@ def main():
         "gemm_L_psi": gemm_roof("gemm_L_psi", "gemm_L_psi", prof_split, a.prec, peak_mm),
         "gemm_T3_R": gemm_roof("gemm_T3_R", "gemm_T3_R", prof_split, a.prec, peak_mm),
         "mpo_apply": hbm_roof("mpo_apply", mpo_bytes * kc["mpo_apply"], prof_split),
-        "cgs_pass1": hbm_roof("cgs_pass1", cgs_bytes(1), prof_split),
-        "cgs_pass2": hbm_roof("cgs_pass2", cgs_bytes(2), prof_split),
+        "gs_dots": hbm_roof("gs_dots", gs_bytes("dots"), prof_split),
+        "gs_update": hbm_roof("gs_update", gs_bytes("update"), prof_split),
         "fp64_gemm_L_psi": gemm_roof("gemm_L_psi", "gemm_L_psi", prof64, "fp64", PEAK["fp64_tflops"]),
         "fp64_gemm_T3_R": gemm_roof("gemm_T3_R", "gemm_T3_R", prof64, "fp64", PEAK["fp64_tflops"]),
     }
     # dominant kernel of the step = largest summed time
-    sums = {k: km[k] for k in km}
-    dom = max(sums, key=sums.get)
+    dom = max((k for k in km if k in kern), key=km.get)
     if dom.startswith("gemm"):
         r = kern[dom]
         roof = {"bound": "mfma", "kernel": dom, "achieved": round(r["mfma_tflops"], 2),

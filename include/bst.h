@@ -238,16 +238,16 @@ typedef struct {
   double beta[128];     /* off-diagonal (first 128)                           */
   /* Summed kernel time (ms) and launch count per kernel class, with
    * BST_LANCZOS_TIMING: 0 L.psi GEMM, 1 MPO apply, 2 T3.R GEMM, 3 MPO
-   * coefficients and bf16 splits, 4 Gram-Schmidt dot pass (V^T w), 5
-   * update pass (lagged: finish v_j and project w; three-pass: w -= V c
-   * and V^T w), 6 third pass (three-pass only: w -= V d and |w|^2), 7
-   * other vector kernels.                                                 */
+   * coefficients and bf16 splits, 4 dot kernel (default schedule: u_j.z;
+   * three-pass: V^T w), 5 basis pass (default: the step's single pass over
+   * the basis; three-pass: w -= V c and V^T w), 6 third pass (three-pass
+   * only: w -= V d and |w|^2), 7 other vector and scalar kernels.         */
   double kernel_ms[8];
   int32_t kernel_calls[8];
 } bst_lanczos_info;
 #define BST_LANCZOS_TIMING 1
 /* Run the textbook schedule (three passes over the basis per step) instead
- * of the default lagged second projection (two passes per step). */
+ * of the default single pass with delayed projection. */
 #define BST_LANCZOS_THREE_PASS 2
 
 /* Workspace of bst_lanczos_ground for a plan and step count. */
@@ -255,16 +255,19 @@ bst_status bst_lanczos_workspace(const bst_plan* heff, int32_t nsteps, size_t* b
 
 /* Lowest eigenpair of the H_eff of `heff` (a bst_heff_plan), which must be
  * symmetric.  Lanczos with full reorthogonalisation: v1 = psi0/|psi0|; per
- * step w = H v_j in the form `matvec_prec`, two classical Gram-Schmidt
- * projections against all previous vectors in float64 (CGS2), alpha_j,
- * beta_j = |w|, v_{j+1} = w/beta_j; the steps stop at the first
- * beta_j <= 1e-12 max(|alpha|, beta_j).  By default the second projection
- * of step j is applied during step j+1 (delayed CGS2, Bielich et al. 2022):
- * the operator is applied to the once-projected vector and the same pass
- * that projects H v_j finishes v_j, so the basis is read twice per step,
- * not three times; alpha and beta equal the textbook ones in exact
- * arithmetic.  BST_LANCZOS_THREE_PASS in info->flags runs the textbook
- * order instead.  The
+ * step w = H v_j in the form `matvec_prec`, w projected against all
+ * previous vectors in float64 (the reference order: two classical
+ * Gram-Schmidt passes), alpha_j, beta_j = |w|, v_{j+1} = w/beta_j; the steps stop at the first
+ * beta_j <= 1e-12 max(|alpha|, beta_j).  By default a step reads the basis
+ * once: the operator is applied to the residual of the previous step before
+ * its full projection, the image of that projection under the operator is
+ * taken from the Lanczos relation, and the projection is applied (finishing
+ * v_j) in the same pass that forms the three-term residual and measures it
+ * against the basis (delayed reorthogonalisation after Swirydowicz et al.
+ * 2021 and Bielich et al. 2022); alpha and beta equal those of two full
+ * classical Gram-Schmidt passes in exact arithmetic.
+ * BST_LANCZOS_THREE_PASS in info->flags runs the textbook order (three
+ * passes over the basis per step).  The
  * float64 tridiagonal eigensolve (Sturm bisection, inverse iteration) gives
  * the Ritz pair (theta, y = V s).  With refine != 0, one float64 apply gives
  * E = y.Hy / y.y; otherwise E = theta.

@@ -55,11 +55,11 @@ class LanczosInfo(C.Structure):
                 ("kernel_calls", C.c_int32 * 8)]
 
 
-# Kernel classes of the timing record.  With the default (lagged) schedule
-# cgs_pass1 is the V^T z dot pass, cgs_pass2 the update pass and cgs_pass3 is
-# unused; the three-pass schedule uses all three.
-LANCZOS_KERNEL_CLASSES = ["gemm_L_psi", "mpo_apply", "gemm_T3_R", "prep", "cgs_pass1",
-                          "cgs_pass2", "cgs_pass3", "vector_other"]
+# Kernel classes of the timing record.  Default schedule: gs_dots is the
+# u_j.z dot, gs_update the single pass over the basis, gs_third unused;
+# three-pass schedule: V^T w, project + V^T w, project + norm.
+LANCZOS_KERNEL_CLASSES = ["gemm_L_psi", "mpo_apply", "gemm_T3_R", "prep", "gs_dots",
+                          "gs_update", "gs_third", "vector_other"]
 
 
 def _load():
@@ -396,7 +396,7 @@ def lanczos_ground(plan: Plan, ops, psi0, nsteps: int, prec="fp64", refine: bool
     """ops = [L, W1, W2, R] device tensors; psi0 device tensor.  Returns a dict
     with energy, theta, steps, residual, beta_min, alpha, beta and psi.
     three_pass selects the textbook reorthogonalisation schedule (three passes
-    over the basis per step) instead of the lagged two-pass one."""
+    over the basis per step) instead of the default single pass."""
     import torch
     if ws is None:
         ws = workspace(lanczos_workspace(plan, nsteps), psi0.device)

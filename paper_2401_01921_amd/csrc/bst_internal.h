@@ -272,16 +272,17 @@ hipError_t launch_lanczos_step_end(const double* partial, int64_t n_for_grid, co
                                    const double* d, int j, double* alpha, double* beta,
                                    double* norm2_out, const double* w, double* vnext, int64_t n,
                                    hipStream_t s);
-// Lagged second Gram-Schmidt pass of step j (see kernels_aux.hip): rewrites
-// row j of V as v_j, writes the once-projected residual to vnext (may be
-// null), c_out[0..j] = projection coefficients, dn[0..j+1] = (V_j^T w, w.w).
-// beta_prev points at beta_{j-1} (ignored for j = 0).
-hipError_t launch_cgs_lag_update(double* V, int64_t ldv, int64_t n, int j, const double* z,
-                                 const double* p, const double* dprev, const double* beta_prev,
-                                 double* vnext, double* c_out, double* partial, double* dn,
-                                 hipStream_t s);
-// alpha[j], beta[j] from the lagged update's sums; dprev <- dn[0..j].
-hipError_t launch_cgs_lag_end(const double* dn, const double* c, int j, double* dprev,
+// One-pass Lanczos step j (see kernels_aux.hip).  coef: from g = u_j.z
+// (device scalar), alpha/beta/dprev of the previous steps, writes
+// coef[0..j] and aest.  pass: rewrites row j of V as v_j, writes the new
+// residual to vnext (may be null), dn[0..j+1] = (V_j^T w, w.w).  end:
+// alpha[j], beta[j], dprev <- dn[0..j].
+hipError_t launch_lanczos_coef(int j, const double* g, const double* alpha, const double* beta,
+                               const double* dprev, double* coef, double* aest, hipStream_t s);
+hipError_t launch_lanczos_pass(double* V, int64_t ldv, int64_t n, int j, const double* z,
+                               const double* coef, const double* dprev, const double* beta,
+                               double* vnext, double* partial, double* dn, hipStream_t s);
+hipError_t launch_lanczos_end(const double* dn, const double* aest, int j, double* dprev,
                               double* alpha, double* beta, hipStream_t s);
 // alpha[j] = c[j] + d[j]; beta[j] = sqrt(norm2[0])
 hipError_t launch_lanczos_scalars(const double* c, const double* d, int j, const double* norm2,

@@ -158,7 +158,14 @@ __global__ __launch_bounds__(256) void happly_sparse_kernel(const HTask* __restr
   if (site >= t.rows * t.cols) return;
   const int i = site / t.cols, jc = site % t.cols;
   const T* __restrict__ in = reinterpret_cast<const T*>(ptrs[t.in_buf]);
-  for (int k = 0; k < t.nin; ++k) xs[k][tid] = in[pl[k].off + (int64_t)i * pl[k].rowstride + jc];
+  // all input loads in flight at once, then staged (each lane reads back
+  // only its own column, so no barrier is needed)
+  T xr[NMAX];
+#pragma unroll
+  for (int k = 0; k < NMAX; ++k)
+    xr[k] = (k < t.nin) ? in[pl[k].off + (int64_t)i * pl[k].rowstride + jc] : T(0);
+#pragma unroll
+  for (int k = 0; k < NMAX; ++k) xs[k][tid] = xr[k];
   for (int o = 0; o < t.nout; ++o) {
     T y = 0;
     const int n = sc[o];
@@ -330,13 +337,14 @@ __global__ __launch_bounds__(256) void multidot_kernel(const double* __restrict_
   const char* Vb = reinterpret_cast<const char*>(V);
   const uint32_t rowb = ldv * 8u;
   const uint32_t stride = gridDim.x * 512u;
+  typedef double dbl2 __attribute__((ext_vector_type(2)));
   for (uint32_t i = (blockIdx.x * 256u + threadIdx.x) * 2u; i + 1 < n; i += stride) {
-    const double2 wi = *reinterpret_cast<const double2*>(w + i);
+    const dbl2 wi = *reinterpret_cast<const dbl2*>(w + i);
     uint32_t off = i * 8u;
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
       if (k < nv) {
-        const double2 v = *reinterpret_cast<const double2*>(Vb + off);
+        const dbl2 v = __builtin_nontemporal_load(reinterpret_cast<const dbl2*>(Vb + off));
         acc[k] += v.x * wi.x + v.y * wi.y;
       }
       off += rowb;
@@ -469,45 +477,78 @@ hipError_t launch_lanczos_step_end(const double* partial, int64_t n_for_grid, co
   return hipGetLastError();
 }
 
-// Second Gram-Schmidt pass lagged by one step (delayed CGS2: Bielich et
-// al., Parallel Computing 2022).  On entry row j of V holds u_j, the
-// previous step's residual after one projection, and z = H u_j.  With
-// rb = 1/beta_{j-1} (1 when j = 0), dprev the previous step's second-pass
-// coefficients and p = V^T z over rows 0..j (row j read as u_j), each
-// element gets
-//   v_j = (u_j - sum_{k<j} dprev_k v_k) rb        written back into row j
-//   w   = z rb - sum_{k<j} c_k v_k - c_j v_j       written to vnext (if any)
-// where c_k = p_k rb and c_j = (p_j - sum_k dprev_k p_k) rb^2 are v_k.(z rb)
-// with the corrected v_j.  The block partials are v_k.w (k < j), v_j.w and
-// w.w (j + 2 values); block 0 stores c_0..c_j in c_out.
+// One pass over the Krylov basis per Lanczos step.  Row j of V holds u_j,
+// the residual of step j-1 before its full projection; dprev = V_{j-1}^T u_j
+// (measured by the previous pass) and beta_{j-1} = |u_j - V_{j-1} dprev|, so
+// v_j = (u_j - V_{j-1} dprev) / beta_{j-1}.  The operator was applied to
+// u_j (z = H u_j); H v_j = (z - H V_{j-1} dprev) / beta_{j-1}, and by the
+// Lanczos relation H V_{j-1} = V_j T (T the tridiagonal of alpha, beta so
+// far) the correction is the combination V_j e, e = T dprev, of vectors the
+// pass reads anyway.  The three-term residual
+//   w = H v_j - a v_j - beta_{j-1} v_{j-1}
+// (a = v_j.H v_j from g = u_j.z and the same relation) is then measured
+// against all of V_j in the same pass; its projection onto V_j is applied
+// lagged, in the next step.  This is the delayed-reorthogonalisation idea
+// of low-synchronisation Gram-Schmidt (Swirydowicz et al., Numer. Linear
+// Algebra Appl. 2021; Bielich et al., Parallel Comput. 2022) specialised to
+// the symmetric three-term recurrence; in exact arithmetic alpha_j and
+// beta_j equal those of Lanczos with two full classical Gram-Schmidt passes.
+//
+// Scalars of step j (one thread, fixed order): coef[0..j] are the
+// coefficients of v_0..v_j in w = z/beta_{j-1} - sum_k coef_k v_k, and
+// aest (= coef_j - e_j/beta_{j-1}) is the three-term estimate of alpha_j.
+__global__ void lanczos_coef_kernel(int j, const double* __restrict__ g,
+                                    const double* __restrict__ alpha,
+                                    const double* __restrict__ beta,
+                                    const double* __restrict__ dprev,
+                                    double* __restrict__ coef, double* __restrict__ aest) {
+  if (threadIdx.x != 0) return;
+  const double bp = j > 0 ? beta[j - 1] : 1.0;
+  const double rb = bp > 0.0 ? 1.0 / bp : 0.0;
+  // v_j . z = rb (g - dprev . f), f = (T^T y)_{k<j}, y = (dprev, beta_{j-1})
+  double s = 0.0;
+  for (int k = 0; k < j; ++k) {
+    const double yk = dprev[k];
+    const double yn = k + 1 < j ? dprev[k + 1] : bp;
+    double f = alpha[k] * yk + beta[k] * yn;
+    if (k > 0) f += beta[k - 1] * dprev[k - 1];
+    s += dprev[k] * f;
+  }
+  const double vz = rb * (g[0] - s);
+  // e = T dprev over rows 0..j; coef_k = rb e_k (+ beta_{j-1} for k = j-1)
+  for (int i = 0; i < j; ++i) {
+    double e = alpha[i] * dprev[i];
+    if (i > 0) e += beta[i - 1] * dprev[i - 1];
+    if (i + 1 < j) e += beta[i] * dprev[i + 1];
+    coef[i] = rb * e + (i == j - 1 ? bp : 0.0);
+  }
+  const double ej = j > 0 ? beta[j - 1] * dprev[j - 1] : 0.0;
+  const double a = rb * (vz - ej);
+  coef[j] = rb * ej + a;
+  aest[0] = a;
+}
+
+// The pass of step j: per element
+//   v_j = (u_j - sum_{k<j} dprev_k v_k) rb      written back into row j
+//   w   = z rb - sum_{k<j} coef_k v_k - coef_j v_j   written to vnext (if any)
+// and the block partials of v_k.w (k < j), v_j.w and w.w (j + 2 values).
 template <int NV>
-__global__ __launch_bounds__(256) void cgs_lag_update_kernel(
+__global__ __launch_bounds__(256) void lanczos_pass_kernel(
     double* V, uint32_t ldv, uint32_t n, int j, const double* __restrict__ z,
-    const double* __restrict__ p, const double* __restrict__ dprev,
-    const double* __restrict__ beta_prev, double* vnext, double* __restrict__ c_out,
-    double* __restrict__ partial) {
+    const double* __restrict__ coef, const double* __restrict__ dprev,
+    const double* __restrict__ beta, double* vnext, double* __restrict__ partial) {
   constexpr int NR = NV + 2;
   __shared__ double red[4 * NR];
   __shared__ double cs[NV], ds[NV];
-  __shared__ double csj_s;
   const int tid = threadIdx.x;
-  const double b = j > 0 ? beta_prev[0] : 1.0;
+  const double b = j > 0 ? beta[j - 1] : 1.0;
   const double rb = b > 0.0 ? 1.0 / b : 0.0;
   for (int k = tid; k < NV; k += 256) {
-    cs[k] = k < j ? p[k] * rb : 0.0;
+    cs[k] = k < j ? coef[k] : 0.0;
     ds[k] = k < j ? dprev[k] : 0.0;
   }
-  if (tid == 0) {
-    double t = p[j];
-    for (int k = 0; k < j; ++k) t -= dprev[k] * p[k];
-    csj_s = t * rb * rb;
-  }
   __syncthreads();
-  const double csj = csj_s;
-  if (blockIdx.x == 0) {
-    for (int k = tid; k < j; k += 256) c_out[k] = cs[k];
-    if (tid == 0) c_out[j] = csj;
-  }
+  const double csj = coef[j];
   double acc[NV];
 #pragma unroll
   for (int k = 0; k < NV; ++k) acc[k] = 0.0;
@@ -528,14 +569,14 @@ __global__ __launch_bounds__(256) void cgs_lag_update_kernel(
     double* uj = reinterpret_cast<double*>(Vb + (i * 8u + rowj));
     const double u = __builtin_nontemporal_load(uj);
     const double zi = __builtin_nontemporal_load(z + i);
-    double t = 0.0, s = 0.0;
+    double t = 0.0, sacc = 0.0;
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
       t += ds[k] * v[k];
-      s += cs[k] * v[k];
+      sacc += cs[k] * v[k];
     }
     const double vj = (u - t) * rb;
-    const double w = (zi * rb - s) - csj * vj;
+    const double w = (zi * rb - sacc) - csj * vj;
     __builtin_nontemporal_store(vj, uj);
     if (vnext) __builtin_nontemporal_store(w, vnext + i);
 #pragma unroll
@@ -566,39 +607,44 @@ __global__ __launch_bounds__(256) void cgs_lag_update_kernel(
   }
 }
 
-// After the lagged update of step j: dn holds v_k.w (k <= j) and w.w.
-// alpha_j = c_j - dprev_{j-1} + dn_j (the first term is v_j.(z rb); the
-// second removes the part of z rb that came from u_j's own correction, the
-// third is the second-pass coefficient); beta_j^2 = w.w - sum_k dn_k^2
-// (the norm of w after its lagged second projection); dprev <- dn.
-__global__ void cgs_lag_end_kernel(const double* __restrict__ dn, const double* __restrict__ c,
-                                   int j, double* dprev, double* __restrict__ alpha,
-                                   double* __restrict__ beta) {
+// End of step j: dn = (V_j^T w, w.w).  alpha_j = aest + dn_j (the lagged
+// projection's share along v_j); beta_j^2 = w.w - |dn|^2 (the norm of w once
+// projected); dprev <- dn.
+__global__ void lanczos_end_kernel(const double* __restrict__ dn,
+                                   const double* __restrict__ aest, int j, double* dprev,
+                                   double* __restrict__ alpha, double* __restrict__ beta) {
   if (threadIdx.x != 0) return;
   double ss = 0.0;
   for (int k = 0; k <= j; ++k) ss += dn[k] * dn[k];
   const double q = dn[j + 1] - ss;
-  alpha[j] = (c[j] - (j > 0 ? dprev[j - 1] : 0.0)) + dn[j];
+  alpha[j] = aest[0] + dn[j];
   beta[j] = sqrt(q > 0.0 ? q : 0.0);
   for (int k = 0; k <= j; ++k) dprev[k] = dn[k];
 }
 
-hipError_t launch_cgs_lag_update(double* V, int64_t ldv, int64_t n, int j, const double* z,
-                                 const double* p, const double* dprev, const double* beta_prev,
-                                 double* vnext, double* c_out, double* partial, double* dn,
-                                 hipStream_t s) {
+hipError_t launch_lanczos_coef(int j, const double* g, const double* alpha, const double* beta,
+                               const double* dprev, double* coef, double* aest, hipStream_t s) {
+  if (j < 0 || j >= kMaxVecs) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(lanczos_coef_kernel, dim3(1), dim3(64), 0, s, j, g, alpha, beta, dprev, coef,
+                     aest);
+  return hipGetLastError();
+}
+
+hipError_t launch_lanczos_pass(double* V, int64_t ldv, int64_t n, int j, const double* z,
+                               const double* coef, const double* dprev, const double* beta,
+                               double* vnext, double* partial, double* dn, hipStream_t s) {
   if (j < 0 || j + 2 > kMaxVecs + 1 || !fits32(V, ldv, n, j + 1)) return hipErrorInvalidValue;
   const int G = vec_grid(n);
   const int nv = j > 0 ? j : 1;
-  BST_NV_DISPATCH(cgs_lag_update_kernel, dim3(G), dim3(256), 0, s, V, (uint32_t)ldv, (uint32_t)n,
-                  j, z, p, dprev, beta_prev, vnext, c_out, partial);
+  BST_NV_DISPATCH(lanczos_pass_kernel, dim3(G), dim3(256), 0, s, V, (uint32_t)ldv, (uint32_t)n, j,
+                  z, coef, dprev, beta, vnext, partial);
   hipLaunchKernelGGL(reduce_partials_kernel, dim3(j + 2), dim3(256), 0, s, partial, G, dn);
   return hipGetLastError();
 }
 
-hipError_t launch_cgs_lag_end(const double* dn, const double* c, int j, double* dprev,
+hipError_t launch_lanczos_end(const double* dn, const double* aest, int j, double* dprev,
                               double* alpha, double* beta, hipStream_t s) {
-  hipLaunchKernelGGL(cgs_lag_end_kernel, dim3(1), dim3(64), 0, s, dn, c, j, dprev, alpha, beta);
+  hipLaunchKernelGGL(lanczos_end_kernel, dim3(1), dim3(64), 0, s, dn, aest, j, dprev, alpha, beta);
   return hipGetLastError();
 }
 

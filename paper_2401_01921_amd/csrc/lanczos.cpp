@@ -233,7 +233,8 @@ bst_status bst_lanczos_ground(bst_plan* heff, const void* const* ops, const void
   double* alpha = sc + 2 * kMaxVecs;
   double* beta = sc + 3 * kMaxVecs;
   double* svec = sc + 4 * kMaxVecs;
-  double* misc = sc + 5 * kMaxVecs;   // [0..1] psi0 dot2, [2] norm2, [4..5] num, [6] r2
+  double* misc = sc + 5 * kMaxVecs;   // [0..1] psi0 dot2, [2] norm2, [4..5] num, [6] r2,
+                                      // [8..9] u_j.z, z.z, [10] alpha estimate
   double* cproj = misc + 16;
   double* dn = cproj + kMaxVecs;
   const bool three_pass = info && (info->flags & BST_LANCZOS_THREE_PASS);
@@ -297,15 +298,20 @@ bst_status bst_lanczos_ground(bst_plan* heff, const void* const* ops, const void
                   "step end");
       });
     } else {
-      // row j holds u_j (once projected); W = H u_j.  One pass of dots,
-      // then one pass that finishes v_j and projects W once into row j+1.
-      timed(4, [&] { check_hip(launch_multidot(V, ldv, n, nv, W, partial, c, s), "cgs dots"); });
-      timed(5, [&] {
-        check_hip(launch_cgs_lag_update(V, ldv, n, j, W, c, d, j > 0 ? beta + (j - 1) : beta,
-                                        vnext, cproj, partial, dn, s),
-                  "cgs update");
+      // row j holds u_j, W = H u_j: one dot, the step's scalars, then one
+      // pass over rows 0..j that finishes v_j and measures the residual
+      timed(4, [&] {
+        check_hip(launch_dot2(V + (size_t)j * ldv, W, n, partial, misc + 8, s), "u.z");
       });
-      timed(7, [&] { check_hip(launch_cgs_lag_end(dn, cproj, j, d, alpha, beta, s), "step end"); });
+      timed(7, [&] {
+        check_hip(launch_lanczos_coef(j, misc + 8, alpha, beta, d, cproj, misc + 10, s),
+                  "step scalars");
+      });
+      timed(5, [&] {
+        check_hip(launch_lanczos_pass(V, ldv, n, j, W, cproj, d, beta, vnext, partial, dn, s),
+                  "basis pass");
+      });
+      timed(7, [&] { check_hip(launch_lanczos_end(dn, misc + 10, j, d, alpha, beta, s), "step end"); });
     }
   }
   std::vector<double> ha(nsteps), hb(nsteps), m0(2);
