@@ -33,6 +33,27 @@ PEAK = {  # MI355X published dense peaks
 }
 WORKLOAD = 5
 
+# HBM bytes per launch of a kernel, from FETCH_SIZE / WRITE_SIZE counter runs
+# scaled by a 1 GiB copy (profiles/hbm_traffic_lanczos40-spin1-chi4096.md).
+# Valid only for the kernel source they were taken on: `src_sha` is the first
+# 16 hex digits of that file's sha256; any change reports traffic as null.
+TRAFFIC = {
+    "gs_update": {"bytes_per_launch": 8.628e8, "src": "paper_2401_01921_amd/csrc/kernels_aux.hip",
+                  "src_sha": "ed897df6a056af0b",
+                  "profile": "profiles/hbm_traffic_lanczos40-spin1-chi4096.md"},
+}
+
+
+def measured_traffic(kernel):
+    import hashlib
+    t = TRAFFIC.get(kernel)
+    if t is None:
+        return None
+    with open(os.path.join(ROOT, t["src"]), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest()[:16] != t["src_sha"]:
+            return None
+    return t["bytes_per_launch"]
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -191,9 +212,11 @@ def main():
     else:
         r = kern[dom]
         per_launch = r["achieved_gbs"] * r["avg_ms"] * 1e6
+        tr = measured_traffic(dom)
         roof = {"bound": "hbm", "kernel": dom, "achieved": round(r["achieved_gbs"], 1),
                 "peak": PEAK["hbm_gbs"], "unit": "GB/s", "frac": round(r["frac"], 4),
-                "traffic": None, "alg_bytes_per_launch": per_launch}
+                "traffic": tr, "alg_bytes_per_launch": per_launch,
+                "traffic_over_alg": None if tr is None else round(tr / per_launch, 4)}
 
     extras = {}
     if not a.no_extras:
