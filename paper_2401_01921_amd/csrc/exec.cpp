@@ -118,11 +118,11 @@ void run_steps_impl(PlanData& P, void* ws, void* const* dptrs, bst_precision pre
           g.tc = st.tc == Elem::Inter ? ElemType::F32 : ElemType::F64;
           g.tile = planes_tile(st, prec);
           const auto& sh = gemm_planes_shapes(np)[g.tile];
-          auto it = st.tile_lists.find({sh.bm, sh.bn});
-          if (it == st.tile_lists.end()) fail(BST_E_INVALID, "internal: missing tile list");
+          auto it = st.tile_lists_alt.find({sh.bm, sh.bn});
+          if (it == st.tile_lists_alt.end()) fail(BST_E_INVALID, "internal: missing tile list");
           g.tiles = reinterpret_cast<const GemmTile*>(blob + it->second.first);
           g.ntiles = it->second.second;
-          g.probs = reinterpret_cast<const GemmProb*>(blob + st.off0);
+          g.probs = reinterpret_cast<const GemmProb*>(blob + st.off3);
           g.segs = reinterpret_cast<const GemmSeg*>(blob + st.off2);
           g.ptrs = dptrs;
           e = launch_gemm_planes(g, s);
@@ -222,12 +222,13 @@ static std::string tune_key(const PlanData& P, const Step& st, bst_precision for
   };
   mix((uint64_t)form);
   mix((uint64_t)st.transb);
-  for (const auto& p : st.probs) {
+  const bool alt = (int)form >= 10 && st.has_alt;   // plane variant keys
+  for (const auto& p : alt ? st.probs_alt : st.probs) {
     mix((uint64_t)p.M);
     mix((uint64_t)p.N);
     mix((uint64_t)p.seg_count);
   }
-  for (const auto& g : st.segs) mix((uint64_t)g.K);
+  for (const auto& g : alt ? st.segs_alt : st.segs) mix((uint64_t)g.K);
   (void)P;
   std::ostringstream os;
   os << st.name << "-" << std::hex << h;

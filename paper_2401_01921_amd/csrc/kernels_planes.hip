@@ -118,10 +118,11 @@ hipError_t launch_split(const SplitLaunch& l, hipStream_t s) {
 // ------------------------------------------------------------------------
 // Grouped GEMM on bfloat16 planes: C[M x N] = sum_seg A[M x K] B[N x K]^T
 // ------------------------------------------------------------------------
-// Tile shapes whose double-buffered LDS fits in 64 KB for each plane count.
+// Tile shapes per plane count (double-buffered LDS: 80 KB at 128x128, two planes).
 // Direct (LDS-free) variants first: index 0 is the default.
 static const std::vector<TileShape> kPlaneShapes2 = {{64, 64, 1}, {128, 64, 1}, {64, 128, 1}, {32, 32, 1},
-                                                     {64, 64, 0}, {128, 64, 0}, {64, 128, 0}, {32, 32, 0}};
+                                                     {64, 64, 0}, {128, 64, 0}, {64, 128, 0}, {32, 32, 0},
+                                                     {128, 128, 0}};
 static const std::vector<TileShape> kPlaneShapes3 = {{64, 64, 1}, {128, 64, 1}, {64, 128, 1}, {32, 32, 1},
                                                      {64, 64, 0}, {32, 32, 0}};
 const std::vector<TileShape>& gemm_planes_shapes(int np) { return np == 3 ? kPlaneShapes3 : kPlaneShapes2; }
@@ -297,7 +298,7 @@ static hipError_t planes_shape(int bm, int bn, const PlanesLaunch& g, hipStream_
   }
   BST_PS(64, 64) BST_PS(32, 32)
   if constexpr (NP == 2) {
-    BST_PS(128, 64) BST_PS(64, 128)
+    BST_PS(128, 64) BST_PS(64, 128) BST_PS(128, 128)
   }
 #undef BST_PS
   return hipErrorInvalidValue;

@@ -346,6 +346,43 @@ static PadLayout pad_layout(const TensorDesc& T, int split, bool transpose) {
   return P;
 }
 
+// Like pad_layout (not transposed), with the blocks ordered by their sector
+// on leg `group_leg` (canonical order inside a group), so that the blocks
+// sharing that sector form one matrix of stacked rows.  gstart[k] is the
+// offset of group k, grow[b] the first row of block b inside its group and
+// gm[k] the rows of group k.
+struct GroupedLayout {
+  PadLayout lay;
+  std::vector<int64_t> gstart, gm, grow;
+};
+
+static GroupedLayout pad_layout_grouped(const TensorDesc& T, int split, int group_leg) {
+  GroupedLayout G;
+  const int ng = (int)T.legs[group_leg].q.size();
+  G.lay.off.assign(T.nblocks, 0);
+  G.lay.ld.assign(T.nblocks, 0);
+  G.grow.assign(T.nblocks, 0);
+  G.gstart.assign(ng, 0);
+  G.gm.assign(ng, 0);
+  int64_t cum = 0;
+  for (int k = 0; k < ng; ++k) {
+    G.gstart[k] = cum;
+    for (int64_t b = 0; b < T.nblocks; ++b) {
+      if (T.block_qn(b)[group_leg] != k) continue;
+      int64_t rows, cols;
+      block_matrix(T, b, split, rows, cols);
+      const int64_t ld = pad8(cols);
+      G.lay.off[b] = cum;
+      G.lay.ld[b] = ld;
+      G.grow[b] = G.gm[k];
+      G.gm[k] += rows;
+      cum += rows * ld;
+    }
+  }
+  G.lay.total = pad8(std::max<int64_t>(cum, 8));
+  return G;
+}
+
 static void add_split_jobs(Step& st, const TensorDesc& T, int split, bool transpose,
                            const PadLayout& Lay, int in_slot, int out_slot) {
   st.kind = StepKind::Split;
@@ -417,8 +454,13 @@ static void heff_plan(const TensorDesc& L, const TensorDesc& W1, const TensorDes
   // psi transposed to [(t1 t2 b') x a'], T3 [(a s1 s2) x (w3 b')]
   P.has_planes = true;
   P.nslots = 12;
-  const PadLayout Lp = pad_layout(L, 2, false), Rp = pad_layout(R, 1, false),
-                  Pp = pad_layout(psi, 1, true), Tp = pad_layout(*T3, 3, false);
+  // L's planes are grouped by the contracted sector a' so that all L rows
+  // meeting one psi sector a' form one matrix (step 1 then runs one GEMM per
+  // a' sector); psi's transposed blocks are already grouped by a'.
+  const GroupedLayout Lg = pad_layout_grouped(L, 2, 2);
+  const PadLayout& Lp = Lg.lay;
+  const PadLayout Rp = pad_layout(R, 1, false), Pp = pad_layout(psi, 1, true),
+                  Tp = pad_layout(*T3, 3, false);
   P.internals.push_back({8, (size_t)Lp.total * 2 * 3, 0});
   P.internals.push_back({9, (size_t)Rp.total * 2 * 3, 0});
   P.internals.push_back({10, (size_t)Pp.total * 2 * 3, 0});
@@ -431,6 +473,9 @@ static void heff_plan(const TensorDesc& L, const TensorDesc& W1, const TensorDes
   add_split_jobs(spR, R, 1, false, Rp, 3, 9);
   add_split_jobs(spP, psi, 1, true, Pp, 4, 10);
   spL.constant = spR.constant = true;
+
+  // merged T1 layout of the plane variant (filled with step 1)
+  std::vector<int64_t> t1m_start, t1m_cols, pcol, t1zero;
 
   // ---- step 1: T1[(a w) x (t1 t2 y)] = sum_a' L[(a w) x a'] psi[a' x (t1 t2 y)]
   Step s1;
@@ -467,21 +512,72 @@ static void heff_plan(const TensorDesc& L, const TensorDesc& W1, const TensorDes
         g.lda = (int32_t)K;
         g.ldb = (int32_t)N;
         s1.segs.push_back(g);
-        GemmSeg h = g;
-        h.a_off = Lp.off[lb];
-        h.a_buf = 8;
-        h.lda = (int32_t)Lp.ld[lb];
-        h.a_ps = Lp.total;
-        h.b_off = Pp.off[pb];
-        h.b_buf = 10;
-        h.ldb = (int32_t)Pp.ld[pb];
-        h.b_ps = Pp.total;
-        s1.segs_alt.push_back(h);
         s1.flops += 2.0 * (double)M * (double)N * (double)K;
       }
       p.seg_count = (int32_t)s1.segs.size() - p.seg_begin;
       s1.probs.push_back(p);
     }
+    s1.segs_alt.clear();
+    // plane variant: one problem per a' sector kx.  Rows: every L block
+    // (a, w, kx) stacked (grouped L planes); columns: every psi block
+    // (kx, t1, t2, y) stacked (transposed psi planes); the result is T1 in a
+    // merged layout, [rows x columns] per kx, read back by the MPO step.
+    t1m_start.assign(nA, 0);
+    t1m_cols.assign(nA, 0);
+    pcol.assign(psi.nblocks, 0);
+    int64_t cum = 0;
+    for (int kx = 0; kx < nA; ++kx) {
+      int64_t ncol = 0, pfirst = -1;
+      for (int64_t b = 0; b < psi.nblocks; ++b) {
+        if (psi.block_qn(b)[0] != kx) continue;
+        if (pfirst < 0) pfirst = b;
+        pcol[b] = ncol;
+        int64_t rows, cols;
+        block_matrix(psi, b, 1, rows, cols);
+        ncol += cols;
+      }
+      t1m_start[kx] = cum;
+      t1m_cols[kx] = ncol;
+      const int64_t M = Lg.gm[kx];
+      cum += M * ncol;
+      if (M == 0 || ncol == 0) continue;
+      if (M > 0x7FFFFFFF || ncol > 0x7FFFFFFF) fail(BST_E_INVALID, "sector group too large");
+      const int64_t K = psi.legs[0].g[kx];
+      GemmProb p{};
+      p.c_off = t1m_start[kx];
+      p.c_buf = 6;
+      p.M = (int32_t)M;
+      p.N = (int32_t)ncol;
+      p.ldc = (int32_t)ncol;
+      p.seg_begin = (int32_t)s1.segs_alt.size();
+      p.seg_count = 1;
+      GemmSeg h{};
+      h.a_off = Lg.gstart[kx];
+      h.a_buf = 8;
+      h.lda = (int32_t)pad8(K);
+      h.a_ps = Lp.total;
+      h.b_off = Pp.off[pfirst];
+      h.b_buf = 10;
+      h.ldb = (int32_t)pad8(K);
+      h.b_ps = Pp.total;
+      h.K = (int32_t)K;
+      s1.segs_alt.push_back(h);
+      s1.probs_alt.push_back(p);
+    }
+    // T1 blocks that no (L, psi) pair reaches stay zero: each gets a region
+    // of its own, written (as zeros) by a problem without segments
+    t1zero.assign(T1->nblocks, -1);
+    for (int64_t cb = 0; cb < T1->nblocks; ++cb) {
+      if (s1.probs[cb].seg_count > 0) continue;
+      t1zero[cb] = cum;
+      GemmProb p = s1.probs[cb];
+      p.c_off = cum;
+      p.seg_begin = (int32_t)s1.segs_alt.size();
+      p.seg_count = 0;
+      s1.probs_alt.push_back(p);
+      cum += T1->block_size(cb);
+    }
+    if (cum != T1->numel) fail(BST_E_INVALID, "internal: merged T1 layout size");
     s1.bytes = 8.0 * ((double)L.numel + (double)psi.numel + (double)T1->numel);
     s1.bytes32 = 8.0 * ((double)L.numel + (double)psi.numel) + 4.0 * (double)T1->numel;
   }
@@ -511,7 +607,7 @@ static void heff_plan(const TensorDesc& L, const TensorDesc& W1, const TensorDes
     int32_t t[5];
     for (int ka = 0; ka < nA; ++ka)
       for (int ky = 0; ky < nY; ++ky) {
-        std::vector<HPlane> ins, outs, outs_alt;
+        std::vector<HPlane> ins, ins_alt, outs, outs_alt;
         std::vector<int64_t> key;   // class key: input then output element triples
         for (int kw = 0; kw < (int)lw.q.size(); ++kw)
           for (int k1 = 0; k1 < (int)lt1.q.size(); ++k1)
@@ -520,10 +616,34 @@ static void heff_plan(const TensorDesc& L, const TensorDesc& W1, const TensorDes
               const int64_t b = T1->find(t);
               if (b < 0) continue;
               const int64_t gw = lw.g[kw], g1 = lt1.g[k1], g2 = lt2.g[k2], gy = psi.legs[3].g[ky];
+              // the a' sector joining (a, w) to (t1, t2, y), and the block's
+              // place in the merged T1 group of that sector
+              // (blocks no pair reaches have a zero region of canonical shape)
+              int64_t lb = -1, pb = -1;
+              int kx = 0;
+              if (t1zero[b] < 0) {
+                for (; kx < (int)psi.legs[0].q.size(); ++kx) {
+                  const int32_t lq[3] = {ka, kw, kx};
+                  const int32_t pq[4] = {kx, k1, k2, ky};
+                  lb = L.find(lq);
+                  pb = psi.find(pq);
+                  if (lb >= 0 && pb >= 0) break;
+                }
+                if (lb < 0 || pb < 0) fail(BST_E_INVALID, "internal: T1 block without a' sector");
+              }
               for (int64_t c = 0; c < gw; ++c)
                 for (int64_t e1 = 0; e1 < g1; ++e1)
                   for (int64_t e2 = 0; e2 < g2; ++e2) {
-                    ins.push_back({T1->offset[b] + ((c * g1 + e1) * g2 + e2) * gy, gw * g1 * g2 * gy});
+                    const int64_t in_blk = ((c * g1 + e1) * g2 + e2) * gy;
+                    ins.push_back({T1->offset[b] + in_blk, gw * g1 * g2 * gy});
+                    if (t1zero[b] >= 0) {
+                      ins_alt.push_back({t1zero[b] + in_blk, gw * g1 * g2 * gy});
+                    } else {
+                      const int64_t ncol = t1m_cols[kx];
+                      ins_alt.push_back({t1m_start[kx] + (Lg.grow[lb] + c) * ncol + pcol[pb] +
+                                             (e1 * g2 + e2) * gy,
+                                         gw * ncol});
+                    }
                     key.push_back(lwm.start[kw] + c);
                     key.push_back(lt1m.start[k1] + e1);
                     key.push_back(lt2m.start[k2] + e2);
@@ -595,7 +715,7 @@ static void heff_plan(const TensorDesc& L, const TensorDesc& W1, const TensorDes
         for (auto& q : ins) ha.planes.push_back(q);
         for (auto& q : outs) ha.planes.push_back(q);
         ha.tasks.push_back(task);
-        for (auto& q : ins) ha.planes_alt.push_back(q);
+        for (auto& q : ins_alt) ha.planes_alt.push_back(q);
         for (auto& q : outs_alt) ha.planes_alt.push_back(q);
         HTask ta = task;
         ta.out_buf = 11;
@@ -686,6 +806,7 @@ static void heff_plan(const TensorDesc& L, const TensorDesc& W1, const TensorDes
       p.seg_count = (int32_t)s4.segs.size() - p.seg_begin;
       s4.probs.push_back(p);
     }
+    s4.probs_alt = s4.probs;
     s4.bytes = 8.0 * ((double)T3->numel + (double)R.numel + (double)psi.numel);
     s4.bytes32 = 4.0 * (double)T3->numel + 8.0 * ((double)R.numel + (double)psi.numel);
   }
@@ -745,10 +866,16 @@ static void heff_batch(const std::vector<const PlanData*>& subs, PlanData& P) {
           p.seg_begin += sb;
           b.probs.push_back(p);
         }
+        const int32_t sba = (int32_t)b.segs_alt.size();
         for (auto g : a.segs_alt) {
           g.a_buf += base;
           g.b_buf += base;
           b.segs_alt.push_back(g);
+        }
+        for (auto p : a.probs_alt) {
+          p.c_buf += base;
+          p.seg_begin += sba;
+          b.probs_alt.push_back(p);
         }
       } else if (a.kind == StepKind::HCoef) {
         for (auto rt : a.terms) {
@@ -834,16 +961,17 @@ static int round_nmax(int n) {
 // empty tiles (prob = -1) that exit at once.
 constexpr int kXcds = 8;
 
-static std::vector<GemmTile> make_tiles(const Step& st, int bm, int bn) {
+static std::vector<GemmTile> make_tiles(const std::vector<GemmProb>& probs,
+                                        const std::vector<GemmSeg>& segs, int bm, int bn) {
   struct Prob {
     double cost;
     int32_t idx;
   };
   std::vector<Prob> pr;
-  for (size_t pi = 0; pi < st.probs.size(); ++pi) {
-    const auto& p = st.probs[pi];
+  for (size_t pi = 0; pi < probs.size(); ++pi) {
+    const auto& p = probs[pi];
     int64_t k = 0;
-    for (int s = 0; s < p.seg_count; ++s) k += st.segs[p.seg_begin + s].K;
+    for (int s = 0; s < p.seg_count; ++s) k += segs[p.seg_begin + s].K;
     const double ntile = (double)((p.M + bm - 1) / bm) * (double)((p.N + bn - 1) / bn);
     pr.push_back({ntile * (double)(k + 16), (int32_t)pi});
   }
@@ -855,7 +983,7 @@ static std::vector<GemmTile> make_tiles(const Step& st, int bm, int bn) {
     for (int i = 1; i < kXcds; ++i)
       if (load[i] < load[x]) x = i;
     load[x] += q.cost;
-    const auto& p = st.probs[q.idx];
+    const auto& p = probs[q.idx];
     for (int m0 = 0; m0 < p.M; m0 += bm)
       for (int n0 = 0; n0 < p.N; n0 += bn) bins[x].push_back({q.idx, m0, n0, 0});
   }
@@ -895,19 +1023,25 @@ void finalize(PlanData& P) {
       case StepKind::Gemm: {
         st.off0 = put(P.blob, st.probs);
         st.off1 = put(P.blob, st.segs);
-        if (st.has_alt) st.off2 = put(P.blob, st.segs_alt);
         st.tile_lists.clear();
-        std::vector<TileShape> all;
+        st.tile_lists_alt.clear();
         for (int f = 0; f < 4; ++f)
-          for (const auto& sh : gemm_tile_shapes((bst_precision)f)) all.push_back(sh);
-        if (st.has_alt)
+          for (const auto& sh : gemm_tile_shapes((bst_precision)f)) {
+            auto key = std::make_pair(sh.bm, sh.bn);
+            if (st.tile_lists.count(key)) continue;
+            auto tl = make_tiles(st.probs, st.segs, sh.bm, sh.bn);
+            st.tile_lists[key] = {put(P.blob, tl), (int64_t)tl.size()};
+          }
+        if (st.has_alt) {
+          st.off2 = put(P.blob, st.segs_alt);
+          st.off3 = put(P.blob, st.probs_alt);
           for (int np = 2; np <= 3; ++np)
-            for (const auto& sh : gemm_planes_shapes(np)) all.push_back(sh);
-        for (const auto& sh : all) {
-          auto key = std::make_pair(sh.bm, sh.bn);
-          if (st.tile_lists.count(key)) continue;
-          auto tl = make_tiles(st, sh.bm, sh.bn);
-          st.tile_lists[key] = {put(P.blob, tl), (int64_t)tl.size()};
+            for (const auto& sh : gemm_planes_shapes(np)) {
+              auto key = std::make_pair(sh.bm, sh.bn);
+              if (st.tile_lists_alt.count(key)) continue;
+              auto tl = make_tiles(st.probs_alt, st.segs_alt, sh.bm, sh.bn);
+              st.tile_lists_alt[key] = {put(P.blob, tl), (int64_t)tl.size()};
+            }
         }
         break;
       }

@@ -68,7 +68,8 @@ struct Step {
   // bfloat16-plane variant used by the split forms (H_eff only): GEMM
   // segments on pre-split operands, MPO tasks writing T3 as planes
   bool has_alt = false;
-  std::vector<GemmSeg> segs_alt;
+  std::vector<GemmProb> probs_alt;   // problems of the plane variant (may merge blocks)
+  std::vector<GemmSeg> segs_alt;     // indexed by probs_alt[].seg_begin
   std::vector<HTask> tasks_alt;
   std::vector<HPlane> planes_alt;
   // Split (float64 -> bfloat16 planes), run only by the split forms
@@ -80,6 +81,7 @@ struct Step {
   size_t off0 = 0, off1 = 0, off2 = 0, off3 = 0, off4 = 0, off5 = 0;
   int64_t n0 = 0, n1 = 0;
   std::map<std::pair<int, int>, std::pair<size_t, int64_t>> tile_lists;  // (bm,bn) -> (off, n)
+  std::map<std::pair<int, int>, std::pair<size_t, int64_t>> tile_lists_alt;  // plane variant
 };
 
 struct InternalBuf {
