@@ -83,6 +83,10 @@ struct GemmProb {
   int64_t c_off;
   int32_t c_buf, M, N, ldc;
   int32_t seg_begin, seg_count;
+  // 0: row r of C starts at c_off + r*ldc.  Otherwise (plane kernels only)
+  // row r starts at rowmap[rowmap1 - 1 + r], an element offset into the
+  // C buffer: the rows of one problem may belong to several output blocks.
+  int32_t rowmap1, pad;
 };
 struct GemmTile {
   int32_t prob, m0, n0, pad;
@@ -215,6 +219,7 @@ struct PlanesLaunch {
   const GemmSeg* segs;
   void* const* ptrs;
   int64_t ntiles;
+  const int64_t* rowmap = nullptr;   // row offsets of problems with rowmap1 > 0
 };
 const std::vector<TileShape>& gemm_planes_shapes(int np);
 hipError_t launch_gemm_planes(const PlanesLaunch& g, hipStream_t s);

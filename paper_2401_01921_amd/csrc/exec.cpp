@@ -124,6 +124,7 @@ void run_steps_impl(PlanData& P, void* ws, void* const* dptrs, bst_precision pre
           g.ntiles = it->second.second;
           g.probs = reinterpret_cast<const GemmProb*>(blob + st.off3);
           g.segs = reinterpret_cast<const GemmSeg*>(blob + st.off2);
+          g.rowmap = reinterpret_cast<const int64_t*>(blob + st.off5);
           g.ptrs = dptrs;
           e = launch_gemm_planes(g, s);
           break;

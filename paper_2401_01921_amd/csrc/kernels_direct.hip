@@ -118,7 +118,8 @@ template <int NP, typename TC, int BM, int BN>
 __global__ __launch_bounds__(256) void gemm_direct_planes_kernel(const GemmTile* __restrict__ tiles,
                                                                  const GemmProb* __restrict__ probs,
                                                                  const GemmSeg* __restrict__ segs,
-                                                                 void* const* __restrict__ ptrs) {
+                                                                 void* const* __restrict__ ptrs,
+                                                                 const int64_t* __restrict__ rowmap) {
   constexpr int WM = BM / 2, WN = BN / 2, SM = WM / 16, SN = WN / 16;
   const GemmTile t = tiles[blockIdx.x];
   if (t.prob < 0) return;   // padding of the per-XCD tile lists
@@ -215,7 +216,7 @@ __global__ __launch_bounds__(256) void gemm_direct_planes_kernel(const GemmTile*
       if (!h0) break;
     }
   }
-  TC* __restrict__ C = reinterpret_cast<TC*>(ptrs[p.c_buf]) + p.c_off;
+  TC* __restrict__ C = reinterpret_cast<TC*>(ptrs[p.c_buf]);
 #pragma unroll
   for (int i = 0; i < SM; ++i)
 #pragma unroll
@@ -224,7 +225,11 @@ __global__ __launch_bounds__(256) void gemm_direct_planes_kernel(const GemmTile*
       for (int r = 0; r < 4; ++r) {
         const int row = t.m0 + wm * WM + i * 16 + 4 * (lane >> 4) + r;
         const int col = t.n0 + wn * WN + j * 16 + r16;
-        if (row < p.M && col < p.N) C[(int64_t)row * p.ldc + col] = (TC)acc[i][j][r];
+        if (row < p.M && col < p.N) {
+          const int64_t rbase =
+              p.rowmap1 > 0 ? rowmap[p.rowmap1 - 1 + row] : p.c_off + (int64_t)row * p.ldc;
+          C[rbase + col] = (TC)acc[i][j][r];
+        }
       }
 }
 
@@ -267,7 +272,7 @@ hipError_t direct_planes_shape(int bm, int bn, const PlanesLaunch& g, hipStream_
 #define BST_DP(BM_, BN_)                                                                        \
   if (bm == BM_ && bn == BN_) {                                                                 \
     hipLaunchKernelGGL((gemm_direct_planes_kernel<NP, TC, BM_, BN_>), grid, block, 0, s, g.tiles, \
-                       g.probs, g.segs, g.ptrs);                                                \
+                       g.probs, g.segs, g.ptrs, g.rowmap);                                      \
     return hipGetLastError();                                                                   \
   }
   BST_DP(64, 64) BST_DP(128, 64) BST_DP(64, 128) BST_DP(32, 32)

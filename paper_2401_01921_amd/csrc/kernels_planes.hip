@@ -131,7 +131,8 @@ template <int NP, typename TC, int BM, int BN>
 __global__ __launch_bounds__(256) void gemm_planes_kernel(const GemmTile* __restrict__ tiles,
                                                           const GemmProb* __restrict__ probs,
                                                           const GemmSeg* __restrict__ segs,
-                                                          void* const* __restrict__ ptrs) {
+                                                          void* const* __restrict__ ptrs,
+                                                          const int64_t* __restrict__ rowmap) {
   constexpr int BK = 32, LDR = BK + 8;   // LDS row: 80 bytes, 16-byte aligned
   constexpr int WM = BM / 2, WN = BN / 2, SM = WM / 16, SN = WN / 16;
   constexpr int NVA = (BM * 4 + 255) / 256, NVB = (BN * 4 + 255) / 256;   // 16-byte vectors per thread
@@ -274,17 +275,20 @@ __global__ __launch_bounds__(256) void gemm_planes_kernel(const GemmTile* __rest
     buf ^= 1;
     more = have_next;
   }
-  TC* __restrict__ C = reinterpret_cast<TC*>(ptrs[p.c_buf]) + p.c_off;
+  TC* __restrict__ C = reinterpret_cast<TC*>(ptrs[p.c_buf]);
 #pragma unroll
   for (int i = 0; i < SM; ++i)
 #pragma unroll
-    for (int j = 0; j < SN; ++j)
+    for (int r = 0; r < 4; ++r) {
+      const int row = m0 + wm * WM + i * 16 + 4 * (lane >> 4) + r;
+      if (row >= p.M) continue;
+      const int64_t rbase = p.rowmap1 > 0 ? rowmap[p.rowmap1 - 1 + row] : p.c_off + (int64_t)row * p.ldc;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = m0 + wm * WM + i * 16 + 4 * (lane >> 4) + r;
+      for (int j = 0; j < SN; ++j) {
         const int col = n0 + wn * WN + j * 16 + (lane & 15);
-        if (row < p.M && col < p.N) C[(int64_t)row * p.ldc + col] = (TC)acc[i][j][r];
+        if (col < p.N) C[rbase + col] = (TC)acc[i][j][r];
       }
+    }
 }
 
 template <int NP, typename TC>
@@ -293,7 +297,7 @@ static hipError_t planes_shape(int bm, int bn, const PlanesLaunch& g, hipStream_
 #define BST_PS(BM_, BN_)                                                                        \
   if (bm == BM_ && bn == BN_) {                                                                 \
     hipLaunchKernelGGL((gemm_planes_kernel<NP, TC, BM_, BN_>), grid, block, 0, s, g.tiles, g.probs, \
-                       g.segs, g.ptrs);                                                         \
+                       g.segs, g.ptrs, g.rowmap);                                               \
     return hipGetLastError();                                                                   \
   }
   BST_PS(64, 64) BST_PS(32, 32)

@@ -459,12 +459,43 @@ static void heff_plan(const TensorDesc& L, const TensorDesc& W1, const TensorDes
   // a' sector); psi's transposed blocks are already grouped by a'.
   const GroupedLayout Lg = pad_layout_grouped(L, 2, 2);
   const PadLayout& Lp = Lg.lay;
-  const PadLayout Rp = pad_layout(R, 1, false), Pp = pad_layout(psi, 1, true),
-                  Tp = pad_layout(*T3, 3, false);
+  const PadLayout Rp = pad_layout(R, 1, false), Pp = pad_layout(psi, 1, true);
+  // T3 planes in a merged layout for step 4: per output sector b, one matrix
+  // whose rows are all psi blocks (a, s1, s2, b) stacked and whose columns
+  // are the K-segments (w3, b') of R's blocks (b, w3, b'), each segment
+  // starting at a multiple of 8 elements.
+  const int nB = (int)psi.legs[3].q.size();
+  std::vector<int64_t> t3g(nB, 0), t3w(nB, 0), t3m(nB, 0), prow(psi.nblocks, 0),
+      rseg(R.nblocks, 0);
+  int64_t t3tot = 0;
+  for (int kb = 0; kb < nB; ++kb) {
+    for (int64_t b = 0; b < psi.nblocks; ++b) {
+      if (psi.block_qn(b)[3] != kb) continue;
+      prow[b] = t3m[kb];
+      t3m[kb] += psi.block_shape(b)[0] * psi.block_shape(b)[1] * psi.block_shape(b)[2];
+    }
+    for (int64_t b = 0; b < R.nblocks; ++b) {
+      if (R.block_qn(b)[0] != kb) continue;
+      rseg[b] = t3w[kb];
+      t3w[kb] += pad8(R.block_shape(b)[1] * R.block_shape(b)[2]);
+    }
+    t3g[kb] = t3tot;
+    t3tot += t3m[kb] * t3w[kb];
+  }
+  // T3 blocks that no output sector b reads (w3 + b' charge outside b's
+  // sectors) are still produced by the MPO step; their planes all go to
+  // one write-only sink after the groups, which step 4 never reads.
+  const int64_t t3sink = t3tot;
+  int64_t sink_need = 0;
+  for (int64_t b = 0; b < T3->nblocks; ++b) {
+    const int64_t* sh = T3->block_shape(b);
+    sink_need = std::max(sink_need, sh[0] * sh[4]);
+  }
+  const int64_t t3ps = pad8(std::max<int64_t>(t3tot + sink_need, 8));   // plane stride
   P.internals.push_back({8, (size_t)Lp.total * 2 * 3, 0});
   P.internals.push_back({9, (size_t)Rp.total * 2 * 3, 0});
   P.internals.push_back({10, (size_t)Pp.total * 2 * 3, 0});
-  P.internals.push_back({11, (size_t)Tp.total * 2 * 3, 0});
+  P.internals.push_back({11, (size_t)t3ps * 2 * 3, 0});
   Step spL, spR, spP;
   spL.name = "split_L";
   spR.name = "split_R";
@@ -657,11 +688,28 @@ static void heff_plan(const TensorDesc& L, const TensorDesc& W1, const TensorDes
               const int64_t b = T3->find(t);
               if (b < 0) continue;
               const int64_t g1 = ls1.g[k1], g2 = ls2.g[k2], gw = lw3.g[kw], gy = psi.legs[3].g[ky];
+              // the output sector b joining (a, s1, s2) to (w3, b'): the
+              // block's rows and columns in the merged T3 matrix of b
+              int kb3 = 0;
+              int64_t pb3 = -1, rb3 = -1;
+              for (; kb3 < nB; ++kb3) {
+                const int32_t pq[4] = {ka, k1, k2, kb3};
+                const int32_t rq[3] = {kb3, kw, ky};
+                pb3 = psi.find(pq);
+                rb3 = R.find(rq);
+                if (pb3 >= 0 && rb3 >= 0) break;
+              }
+              const bool read = pb3 >= 0 && rb3 >= 0;
               for (int64_t e1 = 0; e1 < g1; ++e1)
                 for (int64_t e2 = 0; e2 < g2; ++e2)
                   for (int64_t c = 0; c < gw; ++c) {
                     outs.push_back({T3->offset[b] + ((e1 * g2 + e2) * gw + c) * gy, g1 * g2 * gw * gy});
-                    outs_alt.push_back({Tp.off[b] + (e1 * g2 + e2) * Tp.ld[b] + c * gy, g1 * g2 * Tp.ld[b]});
+                    if (read)
+                      outs_alt.push_back({t3g[kb3] + (prow[pb3] + e1 * g2 + e2) * t3w[kb3] +
+                                              rseg[rb3] + c * gy,
+                                          g1 * g2 * t3w[kb3]});
+                    else
+                      outs_alt.push_back({t3sink, gy});
                     key.push_back(ls1m.start[k1] + e1);
                     key.push_back(ls2m.start[k2] + e2);
                     key.push_back(lw3m.start[kw] + c);
@@ -719,7 +767,7 @@ static void heff_plan(const TensorDesc& L, const TensorDesc& W1, const TensorDes
         for (auto& q : outs_alt) ha.planes_alt.push_back(q);
         HTask ta = task;
         ta.out_buf = 11;
-        ta.out_ps = Tp.total;
+        ta.out_ps = t3ps;
         ha.tasks_alt.push_back(ta);
       }
     hc.ncls = (int32_t)classes.size();
@@ -791,22 +839,48 @@ static void heff_plan(const TensorDesc& L, const TensorDesc& W1, const TensorDes
           g.lda = (int32_t)K;
           g.ldb = (int32_t)K;
           s4.segs.push_back(g);
-          GemmSeg h = g;
-          h.a_off = Tp.off[ab];
-          h.a_buf = 11;
-          h.lda = (int32_t)Tp.ld[ab];
-          h.a_ps = Tp.total;
-          h.b_off = Rp.off[bb];
-          h.b_buf = 9;
-          h.ldb = (int32_t)Rp.ld[bb];
-          h.b_ps = Rp.total;
-          s4.segs_alt.push_back(h);
           s4.flops += 2.0 * (double)M * (double)N * (double)K;
         }
       p.seg_count = (int32_t)s4.segs.size() - p.seg_begin;
       s4.probs.push_back(p);
     }
-    s4.probs_alt = s4.probs;
+    // plane variant: one problem per output sector b over the merged T3
+    // rows; each row is written to its psi block through the row map
+    for (int kb = 0; kb < nB; ++kb) {
+      if (t3m[kb] == 0) continue;
+      if (t3m[kb] > 0x7FFFFFFF) fail(BST_E_INVALID, "sector group too large");
+      const int64_t Nb = psi.legs[3].g[kb];
+      GemmProb p{};
+      p.c_off = 0;
+      p.c_buf = 5;
+      p.M = (int32_t)t3m[kb];
+      p.N = (int32_t)Nb;
+      p.ldc = (int32_t)Nb;
+      p.seg_begin = (int32_t)s4.segs_alt.size();
+      p.rowmap1 = (int32_t)s4.rowmap.size() + 1;
+      for (int64_t b = 0; b < psi.nblocks; ++b) {
+        if (psi.block_qn(b)[3] != kb) continue;
+        const int64_t rows = psi.block_shape(b)[0] * psi.block_shape(b)[1] * psi.block_shape(b)[2];
+        for (int64_t r = 0; r < rows; ++r) s4.rowmap.push_back(psi.offset[b] + r * Nb);
+      }
+      for (int64_t rb = 0; rb < R.nblocks; ++rb) {
+        if (R.block_qn(rb)[0] != kb) continue;
+        GemmSeg h{};
+        h.K = (int32_t)(R.block_shape(rb)[1] * R.block_shape(rb)[2]);
+        h.a_off = t3g[kb] + rseg[rb];
+        h.a_buf = 11;
+        h.lda = (int32_t)t3w[kb];
+        h.a_ps = t3ps;
+        h.b_off = Rp.off[rb];
+        h.b_buf = 9;
+        h.ldb = (int32_t)Rp.ld[rb];
+        h.b_ps = Rp.total;
+        s4.segs_alt.push_back(h);
+      }
+      p.seg_count = (int32_t)s4.segs_alt.size() - p.seg_begin;
+      s4.probs_alt.push_back(p);
+    }
+    if ((int64_t)s4.rowmap.size() > 0x7FFFFFFF) fail(BST_E_INVALID, "row map too large");
     s4.bytes = 8.0 * ((double)T3->numel + (double)R.numel + (double)psi.numel);
     s4.bytes32 = 4.0 * (double)T3->numel + 8.0 * ((double)R.numel + (double)psi.numel);
   }
@@ -872,9 +946,12 @@ static void heff_batch(const std::vector<const PlanData*>& subs, PlanData& P) {
           g.b_buf += base;
           b.segs_alt.push_back(g);
         }
+        const int32_t rmb = (int32_t)b.rowmap.size();
+        for (auto r : a.rowmap) b.rowmap.push_back(r);
         for (auto p : a.probs_alt) {
           p.c_buf += base;
           p.seg_begin += sba;
+          if (p.rowmap1 > 0) p.rowmap1 += rmb;
           b.probs_alt.push_back(p);
         }
       } else if (a.kind == StepKind::HCoef) {
@@ -1035,6 +1112,7 @@ void finalize(PlanData& P) {
         if (st.has_alt) {
           st.off2 = put(P.blob, st.segs_alt);
           st.off3 = put(P.blob, st.probs_alt);
+          st.off5 = put(P.blob, st.rowmap);
           for (int np = 2; np <= 3; ++np)
             for (const auto& sh : gemm_planes_shapes(np)) {
               auto key = std::make_pair(sh.bm, sh.bn);

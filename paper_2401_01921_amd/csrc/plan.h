@@ -69,6 +69,7 @@ struct Step {
   // segments on pre-split operands, MPO tasks writing T3 as planes
   bool has_alt = false;
   std::vector<GemmProb> probs_alt;   // problems of the plane variant (may merge blocks)
+  std::vector<int64_t> rowmap;       // C row offsets of probs_alt with rowmap1 > 0
   std::vector<GemmSeg> segs_alt;     // indexed by probs_alt[].seg_begin
   std::vector<HTask> tasks_alt;
   std::vector<HPlane> planes_alt;
