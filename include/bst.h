@@ -34,7 +34,11 @@
  * (inputs, outputs, workspace) are device pointers owned by the caller; the
  * library never allocates, frees or retains device memory.  Plan tables are
  * uploaded into the caller's workspace on the first execute with that
- * workspace.  Work is enqueued on the caller's HIP stream (passed as void*).
+ * workspace pointer and are assumed to stay there: after the caller frees,
+ * reallocates or overwrites a workspace it used with a plan, it calls
+ * bst_plan_forget_workspace(plan) before the plan's next call (a plan that
+ * last used another pointer re-uploads by itself).  Work is enqueued on the
+ * caller's HIP stream (passed as void*).
  *
  * Errors
  * ------
@@ -224,6 +228,11 @@ bst_status bst_plan_profile(bst_plan* p, const void* const* in, void* const* out
                             int32_t* nsteps);
 
 bst_status bst_plan_destroy(bst_plan* p);
+
+/* Makes the plan's next call upload its tables into the workspace again
+ * (after the caller changed or reallocated the workspace memory), and drops
+ * a captured hipGraph.  Never fails on a valid plan. */
+bst_status bst_plan_forget_workspace(bst_plan* p);
 
 /* ---- Lanczos ground state (Sec. "Eigenvalue decomposition") ----------- */
 

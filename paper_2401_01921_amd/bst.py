@@ -8,6 +8,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import weakref
 from typing import List, Sequence, Tuple
 
 import numpy as np
@@ -27,7 +28,7 @@ EXPORTS = [
     "bst_plan_step_info", "bst_plan_set_precision", "bst_plan_use_graph", "bst_execute",
     "bst_plan_autotune", "bst_plan_tiles", "bst_plan_profile", "bst_plan_destroy",
     "bst_lanczos_workspace", "bst_lanczos_ground", "bst_last_error", "bst_version",
-    "bst_plan_tile_count", "bst_plan_set_tile",
+    "bst_plan_tile_count", "bst_plan_set_tile", "bst_plan_forget_workspace",
 ]
 
 
@@ -91,6 +92,7 @@ def _load():
         "bst_plan_set_tile": [vp, C.c_int, i32],
         "bst_plan_profile": [vp, P(vp), P(vp), vp, vp, i32, P(C.c_double), i32, P(i32)],
         "bst_plan_destroy": [vp],
+        "bst_plan_forget_workspace": [vp],
         "bst_lanczos_workspace": [vp, i32, P(sz)],
         "bst_lanczos_ground": [vp, P(vp), vp, i32, C.c_int, i32, vp, P(C.c_double),
                                P(LanczosInfo), vp, vp],
@@ -326,6 +328,14 @@ class Plan:
         need = self.workspace_bytes if need is None else need
         if ws.numel() * ws.element_size() < need:
             raise BstError(1, f"workspace has {ws.numel() * ws.element_size()} bytes, plan needs {need}")
+        # The library keeps the plan's tables in the workspace between calls
+        # and re-uploads them only when told to: do so whenever this is not
+        # the workspace object of the previous call, or it was modified since.
+        ref = getattr(self, "_ws_ref", None)
+        if ref is None or ref() is not ws or getattr(self, "_ws_version", None) != ws._version:
+            _check(_lib.bst_plan_forget_workspace(self._h))
+            self._ws_ref = weakref.ref(ws)
+            self._ws_version = ws._version
 
     def execute(self, ins, outs, ws, stream=None):
         self._check_ws(ws)

@@ -156,7 +156,8 @@ enum class ElemType : int { F64 = 0, F32 = 1 };
 
 struct TileShape {
   int bm, bn;
-  int direct = 0;   // 1: LDS-free kernel (fragments loaded straight from memory)
+  int direct = 0;   // 1: LDS-free kernel (fragments loaded straight from memory);
+                    // 2: persistent LDS kernel (fixed grid walking the tile list)
 };
 // Tile shapes compiled for each arithmetic form.
 const std::vector<TileShape>& gemm_tile_shapes(bst_precision form);
@@ -263,7 +264,7 @@ hipError_t launch_scale_rnorm(const double* src, const double* norm2, double* ds
 // y[i] = sum_k coef[k] V[k*ldv+i]  (coef on device)
 hipError_t launch_combine(const double* V, int64_t ldv, int64_t n, int nv, const double* coef,
                           double* y, hipStream_t s);
-// out[0] = x.y, out[1] = y.y
+// out[0] = x.y, out[1] = y.y (out == nullptr: block partials only)
 hipError_t launch_dot2(const double* x, const double* y, int64_t n, double* partial, double* out,
                        hipStream_t s);
 // e = num[0]/num[1]; out[0] = |hy - e y|^2

@@ -453,6 +453,20 @@ bst_status bst_plan_set_tile(bst_plan* p, bst_precision form, int32_t tile) {
   BST_CATCH
 }
 
+bst_status bst_plan_forget_workspace(bst_plan* p) {
+  BST_TRY
+  if (!p) fail(BST_E_INVALID, "null plan");
+  drop_graph(p->p);
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  for (auto it = g_ws_owner.begin(); it != g_ws_owner.end();) {
+    if (it->second == p->p.id) it = g_ws_owner.erase(it);
+    else ++it;
+  }
+  p->p.uploaded_ws = nullptr;
+  p->p.last_ptrs.clear();
+  BST_CATCH
+}
+
 bst_status bst_plan_destroy(bst_plan* p) {
   if (p) {
     drop_graph(p->p);

@@ -494,35 +494,45 @@ hipError_t launch_lanczos_step_end(const double* partial, int64_t n_for_grid, co
 // the symmetric three-term recurrence; in exact arithmetic alpha_j and
 // beta_j equal those of Lanczos with two full classical Gram-Schmidt passes.
 //
-// Scalars of step j (one thread, fixed order): coef[0..j] are the
-// coefficients of v_0..v_j in w = z/beta_{j-1} - sum_k coef_k v_k, and
-// aest (= coef_j - e_j/beta_{j-1}) is the three-term estimate of alpha_j.
-__global__ void lanczos_coef_kernel(int j, const double* __restrict__ g,
-                                    const double* __restrict__ alpha,
-                                    const double* __restrict__ beta,
-                                    const double* __restrict__ dprev,
-                                    double* __restrict__ coef, double* __restrict__ aest) {
-  if (threadIdx.x != 0) return;
-  const double bp = j > 0 ? beta[j - 1] : 1.0;
+// Scalars of step j from g = u_j.z: alpha, beta and dprev are staged in LDS
+// and one thread evaluates (fixed order): coef[0..j], the coefficients of
+// v_0..v_j in w = z/beta_{j-1} - sum_k coef_k v_k, and aest, the three-term
+// estimate of alpha_j.
+__global__ __launch_bounds__(64) void lanczos_coef_kernel(int j, const double* __restrict__ g,
+                                                          const double* __restrict__ alpha,
+                                                          const double* __restrict__ beta,
+                                                          const double* __restrict__ dprev,
+                                                          double* __restrict__ coef,
+                                                          double* __restrict__ aest) {
+  __shared__ double al[kMaxVecs], be[kMaxVecs], dp[kMaxVecs];
+  const int lane = threadIdx.x;
+  const double gs = g[0];
+  for (int k = lane; k < j; k += 64) {
+    al[k] = alpha[k];
+    be[k] = beta[k];
+    dp[k] = dprev[k];
+  }
+  __syncthreads();
+  if (lane != 0) return;
+  const double bp = j > 0 ? be[j - 1] : 1.0;
   const double rb = bp > 0.0 ? 1.0 / bp : 0.0;
   // v_j . z = rb (g - dprev . f), f = (T^T y)_{k<j}, y = (dprev, beta_{j-1})
-  double s = 0.0;
+  double sdot = 0.0;
   for (int k = 0; k < j; ++k) {
-    const double yk = dprev[k];
-    const double yn = k + 1 < j ? dprev[k + 1] : bp;
-    double f = alpha[k] * yk + beta[k] * yn;
-    if (k > 0) f += beta[k - 1] * dprev[k - 1];
-    s += dprev[k] * f;
+    const double yn = k + 1 < j ? dp[k + 1] : bp;
+    double f = al[k] * dp[k] + be[k] * yn;
+    if (k > 0) f += be[k - 1] * dp[k - 1];
+    sdot += dp[k] * f;
   }
-  const double vz = rb * (g[0] - s);
+  const double vz = rb * (gs - sdot);
   // e = T dprev over rows 0..j; coef_k = rb e_k (+ beta_{j-1} for k = j-1)
   for (int i = 0; i < j; ++i) {
-    double e = alpha[i] * dprev[i];
-    if (i > 0) e += beta[i - 1] * dprev[i - 1];
-    if (i + 1 < j) e += beta[i] * dprev[i + 1];
+    double e = al[i] * dp[i];
+    if (i > 0) e += be[i - 1] * dp[i - 1];
+    if (i + 1 < j) e += be[i] * dp[i + 1];
     coef[i] = rb * e + (i == j - 1 ? bp : 0.0);
   }
-  const double ej = j > 0 ? beta[j - 1] * dprev[j - 1] : 0.0;
+  const double ej = j > 0 ? be[j - 1] * dp[j - 1] : 0.0;
   const double a = rb * (vz - ej);
   coef[j] = rb * ej + a;
   aest[0] = a;
@@ -610,16 +620,24 @@ __global__ __launch_bounds__(256) void lanczos_pass_kernel(
 // End of step j: dn = (V_j^T w, w.w).  alpha_j = aest + dn_j (the lagged
 // projection's share along v_j); beta_j^2 = w.w - |dn|^2 (the norm of w once
 // projected); dprev <- dn.
-__global__ void lanczos_end_kernel(const double* __restrict__ dn,
-                                   const double* __restrict__ aest, int j, double* dprev,
-                                   double* __restrict__ alpha, double* __restrict__ beta) {
-  if (threadIdx.x != 0) return;
+__global__ __launch_bounds__(64) void lanczos_end_kernel(const double* __restrict__ dn,
+                                                         const double* __restrict__ aest, int j,
+                                                         double* __restrict__ dprev,
+                                                         double* __restrict__ alpha,
+                                                         double* __restrict__ beta) {
+  __shared__ double ds[kMaxVecs + 2];
+  const int lane = threadIdx.x;
+  for (int k = lane; k < j + 2; k += 64) {
+    ds[k] = dn[k];
+    if (k <= j) dprev[k] = dn[k];
+  }
+  __syncthreads();
+  if (lane != 0) return;
   double ss = 0.0;
-  for (int k = 0; k <= j; ++k) ss += dn[k] * dn[k];
-  const double q = dn[j + 1] - ss;
-  alpha[j] = aest[0] + dn[j];
+  for (int k = 0; k <= j; ++k) ss += ds[k] * ds[k];
+  const double q = ds[j + 1] - ss;
+  alpha[j] = aest[0] + ds[j];
   beta[j] = sqrt(q > 0.0 ? q : 0.0);
-  for (int k = 0; k <= j; ++k) dprev[k] = dn[k];
 }
 
 hipError_t launch_lanczos_coef(int j, const double* g, const double* alpha, const double* beta,
@@ -706,7 +724,7 @@ hipError_t launch_dot2(const double* x, const double* y, int64_t n, double* part
                        hipStream_t s) {
   const int G = vec_grid(n);
   hipLaunchKernelGGL(dot2_kernel, dim3(G), dim3(256), 0, s, x, y, n, partial);
-  hipLaunchKernelGGL(reduce_partials_kernel, dim3(2), dim3(256), 0, s, partial, G, out);
+  if (out) hipLaunchKernelGGL(reduce_partials_kernel, dim3(2), dim3(256), 0, s, partial, G, out);
   return hipGetLastError();
 }
 

@@ -122,9 +122,9 @@ hipError_t launch_split(const SplitLaunch& l, hipStream_t s) {
 // Direct (LDS-free) variants first: index 0 is the default.
 static const std::vector<TileShape> kPlaneShapes2 = {{64, 64, 1}, {128, 64, 1}, {64, 128, 1}, {32, 32, 1},
                                                      {64, 64, 0}, {128, 64, 0}, {64, 128, 0}, {32, 32, 0},
-                                                     {128, 128, 0}};
+                                                     {128, 128, 0}, {128, 128, 2}, {64, 64, 2}};
 static const std::vector<TileShape> kPlaneShapes3 = {{64, 64, 1}, {128, 64, 1}, {64, 128, 1}, {32, 32, 1},
-                                                     {64, 64, 0}, {32, 32, 0}};
+                                                     {64, 64, 0}, {32, 32, 0}, {64, 64, 2}};
 const std::vector<TileShape>& gemm_planes_shapes(int np) { return np == 3 ? kPlaneShapes3 : kPlaneShapes2; }
 
 template <int NP, typename TC, int BM, int BN>
@@ -291,6 +291,238 @@ __global__ __launch_bounds__(256) void gemm_planes_kernel(const GemmTile* __rest
     }
 }
 
+// Persistent variant: a fixed grid (a multiple of 8, so that block b stays
+// on XCD b % 8 with the tiles the host placed there) walks the tile list
+// with stride gridDim.x.  The load cursor runs one k-step ahead of the MFMA
+// across tile boundaries, so the first k-step of the next tile is in flight
+// while the current tile finishes and writes its result.
+template <int NP, typename TC, int BM, int BN>
+__global__ __launch_bounds__(256) void gemm_planes_persist_kernel(
+    const GemmTile* __restrict__ tiles, int64_t ntiles, const GemmProb* __restrict__ probs,
+    const GemmSeg* __restrict__ segs, void* const* __restrict__ ptrs,
+    const int64_t* __restrict__ rowmap) {
+  constexpr int BK = 32, LDR = BK + 8;
+  constexpr int WM = BM / 2, WN = BN / 2, SM = WM / 16, SN = WN / 16;
+  constexpr int NVA = (BM * 4 + 255) / 256, NVB = (BN * 4 + 255) / 256;
+  __shared__ __attribute__((aligned(16))) unsigned short As[2][NP][BM * LDR];
+  __shared__ __attribute__((aligned(16))) unsigned short Bs[2][NP][BN * LDR];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int64_t G = gridDim.x;
+  const us8 zero8 = {0, 0, 0, 0, 0, 0, 0, 0};
+
+  auto row_base = [&](const GemmProb& p, int row) -> int64_t {
+    return p.rowmap1 > 0 ? rowmap[p.rowmap1 - 1 + row] : p.c_off + (int64_t)row * p.ldc;
+  };
+  // load cursor: tile index, its problem and origin, segment and k
+  int64_t lt = (int64_t)blockIdx.x - G;
+  GemmProb lp{};
+  int lm0 = 0, ln0 = 0, ls = 0, lk = 0;
+  bool lvalid = false;
+  // moves the load cursor to the next tile with work; tiles of problems
+  // without segments are written as zeros on the way
+  auto next_tile = [&]() {
+    lvalid = false;
+    for (lt += G; lt < ntiles; lt += G) {
+      const GemmTile t = tiles[lt];
+      if (t.prob < 0) continue;
+      lp = probs[t.prob];
+      lm0 = t.m0;
+      ln0 = t.n0;
+      ls = 0;
+      lk = 0;
+      if (lp.seg_count > 0) {
+        lvalid = true;
+        return;
+      }
+      TC* __restrict__ C = reinterpret_cast<TC*>(ptrs[lp.c_buf]);
+      for (int e = tid; e < BM * BN; e += 256) {
+        const int row = lm0 + e / BN, col = ln0 + e % BN;
+        if (row < lp.M && col < lp.N) C[row_base(lp, row) + col] = (TC)0;
+      }
+    }
+  };
+  us8 ra[NP][NVA], rb[NP][NVB];
+  auto load = [&]() {
+    const GemmSeg g = segs[lp.seg_begin + ls];
+    const unsigned short* A = reinterpret_cast<const unsigned short*>(ptrs[g.a_buf]) + g.a_off;
+    const unsigned short* B = reinterpret_cast<const unsigned short*>(ptrs[g.b_buf]) + g.b_off;
+#pragma unroll
+    for (int v = 0; v < NVA; ++v) {
+      const int idx = tid + v * 256;
+      const int r = idx >> 2, kv = lk + (idx & 3) * 8;
+      const int gr = lm0 + r;
+      const bool ok = (idx < BM * 4) && gr < lp.M && kv < g.K;
+#pragma unroll
+      for (int q = 0; q < NP; ++q) {
+        us8 x = ok ? *reinterpret_cast<const us8*>(A + q * g.a_ps + (int64_t)gr * g.lda + kv) : zero8;
+        if (ok && kv + 8 > g.K) {
+#pragma unroll
+          for (int e = 0; e < 8; ++e)
+            if (kv + e >= g.K) x[e] = 0;
+        }
+        ra[q][v] = x;
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < NVB; ++v) {
+      const int idx = tid + v * 256;
+      const int r = idx >> 2, kv = lk + (idx & 3) * 8;
+      const int gn = ln0 + r;
+      const bool ok = (idx < BN * 4) && gn < lp.N && kv < g.K;
+#pragma unroll
+      for (int q = 0; q < NP; ++q) {
+        us8 x = ok ? *reinterpret_cast<const us8*>(B + q * g.b_ps + (int64_t)gn * g.ldb + kv) : zero8;
+        if (ok && kv + 8 > g.K) {
+#pragma unroll
+          for (int e = 0; e < 8; ++e)
+            if (kv + e >= g.K) x[e] = 0;
+        }
+        rb[q][v] = x;
+      }
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int v = 0; v < NVA; ++v) {
+      const int idx = tid + v * 256;
+      if (idx < BM * 4) {
+#pragma unroll
+        for (int q = 0; q < NP; ++q)
+          *reinterpret_cast<us8*>(&As[buf][q][(idx >> 2) * LDR + (idx & 3) * 8]) = ra[q][v];
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < NVB; ++v) {
+      const int idx = tid + v * 256;
+      if (idx < BN * 4) {
+#pragma unroll
+        for (int q = 0; q < NP; ++q)
+          *reinterpret_cast<us8*>(&Bs[buf][q][(idx >> 2) * LDR + (idx & 3) * 8]) = rb[q][v];
+      }
+    }
+  };
+  // true when the cursor's k-step is the last one of its tile
+  auto last_step = [&]() -> bool {
+    return ls == lp.seg_count - 1 && lk + BK >= segs[lp.seg_begin + ls].K;
+  };
+  auto advance = [&]() {
+    lk += BK;
+    if (lk >= segs[lp.seg_begin + ls].K) {
+      ++ls;
+      lk = 0;
+      if (ls >= lp.seg_count) next_tile();
+    }
+  };
+
+  next_tile();
+  if (!lvalid) return;
+  flt4 acc[SM][SN];
+#pragma unroll
+  for (int i = 0; i < SM; ++i)
+#pragma unroll
+    for (int j = 0; j < SN; ++j) acc[i][j] = flt4{0, 0, 0, 0};
+  // the tile whose k-step sits in the current buffer
+  GemmProb cp = lp;
+  int cm0 = lm0, cn0 = ln0;
+  bool clast = last_step();
+  load();
+  advance();
+  store(0);
+  __syncthreads();
+  int buf = 0;
+  for (;;) {
+    const bool nvalid = lvalid;
+    GemmProb np_ = lp;
+    int nm0 = lm0, nn0 = ln0;
+    bool nlast = false;
+    if (nvalid) {
+      nlast = last_step();
+      load();
+      advance();
+    }
+    {
+      const int kl = 8 * (lane >> 4);
+      bf16x8 a[NP][SM], b[NP][SN];
+#pragma unroll
+      for (int q = 0; q < NP; ++q) {
+#pragma unroll
+        for (int i = 0; i < SM; ++i) {
+          const int r = wm * WM + i * 16 + (lane & 15);
+          a[q][i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const us8*>(&As[buf][q][r * LDR + kl]));
+        }
+#pragma unroll
+        for (int j = 0; j < SN; ++j) {
+          const int c = wn * WN + j * 16 + (lane & 15);
+          b[q][j] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const us8*>(&Bs[buf][q][c * LDR + kl]));
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < SM; ++i)
+#pragma unroll
+        for (int j = 0; j < SN; ++j) {
+          if constexpr (NP == 3) {
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2][i], b[0][j], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][i], b[1][j], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[2][j], acc[i][j], 0, 0, 0);
+          }
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][i], b[0][j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[1][j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[0][j], acc[i][j], 0, 0, 0);
+        }
+    }
+    if (clast) {
+      TC* __restrict__ C = reinterpret_cast<TC*>(ptrs[cp.c_buf]);
+#pragma unroll
+      for (int i = 0; i < SM; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = cm0 + wm * WM + i * 16 + 4 * (lane >> 4) + r;
+          if (row >= cp.M) continue;
+          const int64_t rbase = row_base(cp, row);
+#pragma unroll
+          for (int j = 0; j < SN; ++j) {
+            const int col = cn0 + wn * WN + j * 16 + (lane & 15);
+            if (col < cp.N) C[rbase + col] = (TC)acc[i][j][r];
+          }
+        }
+#pragma unroll
+      for (int i = 0; i < SM; ++i)
+#pragma unroll
+        for (int j = 0; j < SN; ++j) acc[i][j] = flt4{0, 0, 0, 0};
+    }
+    if (!nvalid) break;
+    store(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+    cp = np_;
+    cm0 = nm0;
+    cn0 = nn0;
+    clast = nlast;
+  }
+}
+
+template <int NP, typename TC>
+static hipError_t planes_persist_shape(int bm, int bn, const PlanesLaunch& g, hipStream_t s) {
+  // two resident workgroups per CU at 128x128 (80 KB of LDS), four below
+  const int per_cu = (bm * bn >= 128 * 128) ? 2 : 4;
+  int64_t grid = (int64_t)256 * per_cu;
+  if (grid > g.ntiles) grid = (g.ntiles + 7) / 8 * 8;
+  dim3 gr((unsigned)grid), block(256);
+#define BST_PP(BM_, BN_)                                                                           \
+  if (bm == BM_ && bn == BN_) {                                                                    \
+    hipLaunchKernelGGL((gemm_planes_persist_kernel<NP, TC, BM_, BN_>), gr, block, 0, s, g.tiles,    \
+                       g.ntiles, g.probs, g.segs, g.ptrs, g.rowmap);                               \
+    return hipGetLastError();                                                                      \
+  }
+  BST_PP(64, 64)
+  if constexpr (NP == 2) {
+    BST_PP(128, 128)
+  }
+#undef BST_PP
+  return hipErrorInvalidValue;
+}
+
 template <int NP, typename TC>
 static hipError_t planes_shape(int bm, int bn, const PlanesLaunch& g, hipStream_t s) {
   dim3 grid((unsigned)g.ntiles), block(256);
@@ -314,7 +546,14 @@ hipError_t launch_gemm_planes(const PlanesLaunch& g, hipStream_t s) {
   const auto& sh = gemm_planes_shapes(g.np);
   if (g.tile < 0 || g.tile >= (int)sh.size()) return hipErrorInvalidValue;
   const int bm = sh[g.tile].bm, bn = sh[g.tile].bn;
-  if (sh[g.tile].direct) return launch_gemm_direct_planes(g, bm, bn, s);
+  if (sh[g.tile].direct == 1) return launch_gemm_direct_planes(g, bm, bn, s);
+  if (sh[g.tile].direct == 2) {
+    if (g.np == 2)
+      return g.tc == ElemType::F64 ? planes_persist_shape<2, double>(bm, bn, g, s)
+                                   : planes_persist_shape<2, float>(bm, bn, g, s);
+    return g.tc == ElemType::F64 ? planes_persist_shape<3, double>(bm, bn, g, s)
+                                 : planes_persist_shape<3, float>(bm, bn, g, s);
+  }
   if (g.np == 2)
     return g.tc == ElemType::F64 ? planes_shape<2, double>(bm, bn, g, s) : planes_shape<2, float>(bm, bn, g, s);
   if (g.np == 3)

@@ -1381,7 +1381,7 @@ bst_status bst_plan_tiles(const bst_plan* p, char* buf, size_t cap) {
     const TileShape sh = pl ? gemm_planes_shapes(P.prec == BST_BF16X6 ? 3 : 2)[planes_tile(st, P.prec)]
                             : gemm_tile_shapes(P.prec)[default_tile(st, P.prec)];
     s += st.name + ":" + std::to_string(sh.bm) + "x" + std::to_string(sh.bn) +
-         (sh.direct ? "d" : "l") + (pl ? "p" : "") + ";";
+         (sh.direct == 1 ? "d" : sh.direct == 2 ? "q" : "l") + (pl ? "p" : "") + ";";
   }
   std::strncpy(buf, s.c_str(), cap - 1);
   buf[cap - 1] = 0;

@@ -70,8 +70,11 @@ def run_heff(plan, O, prec=None):
     if prec is not None:
         plan.set_precision(prec)
     ins = [dev(O[n].data) for n in ("L", "W1", "W2", "R", "psi")]
-    out = torch.empty(O["psi"].numel, dtype=torch.float64, device=DEV)
+    # output and workspace start as NaN bytes: a value the kernels forget to
+    # write, or an unwritten intermediate they read, shows up as NaN
+    out = torch.full((O["psi"].numel,), float("nan"), dtype=torch.float64, device=DEV)
     ws = bst.workspace(plan.workspace_bytes)
+    ws.fill_(255)
     plan.execute(ins, [out], ws)
     torch.cuda.synchronize()
     return host(out)

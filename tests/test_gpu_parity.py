@@ -198,3 +198,22 @@ def test_every_gemm_variant(prec):
         cplan.execute([dev(A.data), dev(B.data)], [out], bst.workspace(cplan.workspace_bytes))
         torch.cuda.synchronize()
         assert rel_err(host(out), C.data)[0] <= TOL[prec], tile
+
+
+def test_workspace_overwritten_between_calls():
+    """The plan's tables live in the workspace; after the caller overwrites
+    the workspace (here with NaN bytes) the binding makes the plan upload
+    them again, and the result is unchanged."""
+    specs, O = heff_operands(2)
+    T, plan = lib_heff(specs, "bf16x3")
+    ins = [dev(O[n].data) for n in ("L", "W1", "W2", "R", "psi")]
+    out = torch.empty(O["psi"].numel, dtype=torch.float64, device=DEV)
+    ws = bst.workspace(plan.workspace_bytes)
+    plan.execute(ins, [out], ws)
+    torch.cuda.synchronize()
+    first = host(out)
+    ws.fill_(255)
+    out.fill_(float("nan"))
+    plan.execute(ins, [out], ws)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(out), first)
