@@ -118,6 +118,12 @@ hipError_t launch_split(const SplitLaunch& l, hipStream_t s) {
 // ------------------------------------------------------------------------
 // Grouped GEMM on bfloat16 planes: C[M x N] = sum_seg A[M x K] B[N x K]^T
 // ------------------------------------------------------------------------
+// LDS tile rows hold one 32-deep k step: 64 bytes, four 16-byte chunks.
+// Chunk c of row r is stored at chunk c ^ ((r >> 2) & 3), so that the 16
+// rows one MFMA operand read touches (same chunk) and the 4 rows x 4 chunks
+// one 16-lane group stores fall on 16 distinct 4-bank groups.
+__device__ __forceinline__ int lds_chunk(int r, int c) { return r * 32 + ((c ^ ((r >> 2) & 3)) << 3); }
+
 // Tile shapes per plane count (double-buffered LDS: 80 KB at 128x128, two planes).
 // Direct (LDS-free) variants first: index 0 is the default.
 static const std::vector<TileShape> kPlaneShapes2 = {{64, 64, 1}, {128, 64, 1}, {64, 128, 1}, {32, 32, 1},
@@ -133,7 +139,7 @@ __global__ __launch_bounds__(256) void gemm_planes_kernel(const GemmTile* __rest
                                                           const GemmSeg* __restrict__ segs,
                                                           void* const* __restrict__ ptrs,
                                                           const int64_t* __restrict__ rowmap) {
-  constexpr int BK = 32, LDR = BK + 8;   // LDS row: 80 bytes, 16-byte aligned
+  constexpr int BK = 32, LDR = BK;   // LDS row: 64 bytes, chunks swizzled (lds_chunk)
   constexpr int WM = BM / 2, WN = BN / 2, SM = WM / 16, SN = WN / 16;
   constexpr int NVA = (BM * 4 + 255) / 256, NVB = (BN * 4 + 255) / 256;   // 16-byte vectors per thread
   __shared__ __attribute__((aligned(16))) unsigned short As[2][NP][BM * LDR];
@@ -203,7 +209,7 @@ __global__ __launch_bounds__(256) void gemm_planes_kernel(const GemmTile* __rest
       if (idx < BM * 4) {
 #pragma unroll
         for (int q = 0; q < NP; ++q)
-          *reinterpret_cast<us8*>(&As[buf][q][(idx >> 2) * LDR + (idx & 3) * 8]) = ra[q][v];
+          *reinterpret_cast<us8*>(&As[buf][q][lds_chunk(idx >> 2, idx & 3)]) = ra[q][v];
       }
     }
 #pragma unroll
@@ -212,7 +218,7 @@ __global__ __launch_bounds__(256) void gemm_planes_kernel(const GemmTile* __rest
       if (idx < BN * 4) {
 #pragma unroll
         for (int q = 0; q < NP; ++q)
-          *reinterpret_cast<us8*>(&Bs[buf][q][(idx >> 2) * LDR + (idx & 3) * 8]) = rb[q][v];
+          *reinterpret_cast<us8*>(&Bs[buf][q][lds_chunk(idx >> 2, idx & 3)]) = rb[q][v];
       }
     }
   };
@@ -237,19 +243,19 @@ __global__ __launch_bounds__(256) void gemm_planes_kernel(const GemmTile* __rest
     if (have_next) load(ls, lk);
     // MFMA on the current buffer
     {
-      const int kl = 8 * (lane >> 4);
+      const int kc = lane >> 4;   // 8-element k chunk of this lane
       bf16x8 a[NP][SM], b[NP][SN];
 #pragma unroll
       for (int q = 0; q < NP; ++q) {
 #pragma unroll
         for (int i = 0; i < SM; ++i) {
           const int r = wm * WM + i * 16 + (lane & 15);
-          a[q][i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const us8*>(&As[buf][q][r * LDR + kl]));
+          a[q][i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const us8*>(&As[buf][q][lds_chunk(r, kc)]));
         }
 #pragma unroll
         for (int j = 0; j < SN; ++j) {
           const int c = wn * WN + j * 16 + (lane & 15);
-          b[q][j] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const us8*>(&Bs[buf][q][c * LDR + kl]));
+          b[q][j] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const us8*>(&Bs[buf][q][lds_chunk(c, kc)]));
         }
       }
       // second 16-wide half of the 32-deep k step is in the same vectors (K = 32 per MFMA)
@@ -301,7 +307,7 @@ __global__ __launch_bounds__(256) void gemm_planes_persist_kernel(
     const GemmTile* __restrict__ tiles, int64_t ntiles, const GemmProb* __restrict__ probs,
     const GemmSeg* __restrict__ segs, void* const* __restrict__ ptrs,
     const int64_t* __restrict__ rowmap) {
-  constexpr int BK = 32, LDR = BK + 8;
+  constexpr int BK = 32, LDR = BK;
   constexpr int WM = BM / 2, WN = BN / 2, SM = WM / 16, SN = WN / 16;
   constexpr int NVA = (BM * 4 + 255) / 256, NVB = (BN * 4 + 255) / 256;
   __shared__ __attribute__((aligned(16))) unsigned short As[2][NP][BM * LDR];
@@ -389,7 +395,7 @@ __global__ __launch_bounds__(256) void gemm_planes_persist_kernel(
       if (idx < BM * 4) {
 #pragma unroll
         for (int q = 0; q < NP; ++q)
-          *reinterpret_cast<us8*>(&As[buf][q][(idx >> 2) * LDR + (idx & 3) * 8]) = ra[q][v];
+          *reinterpret_cast<us8*>(&As[buf][q][lds_chunk(idx >> 2, idx & 3)]) = ra[q][v];
       }
     }
 #pragma unroll
@@ -398,7 +404,7 @@ __global__ __launch_bounds__(256) void gemm_planes_persist_kernel(
       if (idx < BN * 4) {
 #pragma unroll
         for (int q = 0; q < NP; ++q)
-          *reinterpret_cast<us8*>(&Bs[buf][q][(idx >> 2) * LDR + (idx & 3) * 8]) = rb[q][v];
+          *reinterpret_cast<us8*>(&Bs[buf][q][lds_chunk(idx >> 2, idx & 3)]) = rb[q][v];
       }
     }
   };
@@ -442,19 +448,19 @@ __global__ __launch_bounds__(256) void gemm_planes_persist_kernel(
       advance();
     }
     {
-      const int kl = 8 * (lane >> 4);
+      const int kc = lane >> 4;   // 8-element k chunk of this lane
       bf16x8 a[NP][SM], b[NP][SN];
 #pragma unroll
       for (int q = 0; q < NP; ++q) {
 #pragma unroll
         for (int i = 0; i < SM; ++i) {
           const int r = wm * WM + i * 16 + (lane & 15);
-          a[q][i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const us8*>(&As[buf][q][r * LDR + kl]));
+          a[q][i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const us8*>(&As[buf][q][lds_chunk(r, kc)]));
         }
 #pragma unroll
         for (int j = 0; j < SN; ++j) {
           const int c = wn * WN + j * 16 + (lane & 15);
-          b[q][j] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const us8*>(&Bs[buf][q][c * LDR + kl]));
+          b[q][j] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const us8*>(&Bs[buf][q][lds_chunk(c, kc)]));
         }
       }
 #pragma unroll
