@@ -15,6 +15,12 @@
 
 namespace bst {
 
+// Device pointers taken from a plan's pointer table address global memory;
+// declaring that (address space 1) lets the compiler emit global rather than
+// flat memory instructions, whose completion is tracked apart from scalar
+// loads (a flat access also holds up every wait for a scalar load).
+#define BST_G __attribute__((address_space(1)))
+
 // ------------------------------------------------------------------------
 // Errors
 // ------------------------------------------------------------------------

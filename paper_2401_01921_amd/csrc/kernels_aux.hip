@@ -17,8 +17,8 @@ __global__ __launch_bounds__(256) void permute_kernel(const PermJob* __restrict_
   __shared__ double tile[kPT][kPT + 1];
   const PermWork w = work[blockIdx.x];
   const PermJob& j = jobs[w.job];
-  const double* __restrict__ in = reinterpret_cast<const double*>(ptrs[j.in_buf]) + j.in_off;
-  double* __restrict__ out = reinterpret_cast<double*>(ptrs[j.out_buf]) + j.out_off;
+  const BST_G double* __restrict__ in = (const BST_G double*)(ptrs[j.in_buf]) + j.in_off;
+  BST_G double* __restrict__ out = (BST_G double*)(ptrs[j.out_buf]) + j.out_off;
   const int r = j.rank;
   const int tid = threadIdx.x;
   if (w.kind == 0) {
@@ -33,8 +33,8 @@ __global__ __launch_bounds__(256) void permute_kernel(const PermJob* __restrict_
         rem /= ext;
         ob += idx * j.ostride[d];
       }
-      const double* src = in + row * last;
-      double* dst = out + ob;
+      const BST_G double* src = in + row * last;
+      BST_G double* dst = out + ob;
       for (int64_t c = lane; c < last; c += 64) dst[c] = src[c];
     }
     return;
@@ -101,8 +101,8 @@ __global__ __launch_bounds__(256) void hcoef_kernel(const HTerm* __restrict__ te
     double sum = 0.0;
     for (int32_t k = entry_begin[e]; k < entry_begin[e + 1]; ++k) {
       const HTerm t = terms[k];
-      const double w1 = reinterpret_cast<const double*>(ptrs[t.w1_buf])[t.w1_off];
-      const double w2 = reinterpret_cast<const double*>(ptrs[t.w2_buf])[t.w2_off];
+      const double w1 = ((const BST_G double*)(ptrs[t.w1_buf]))[t.w1_off];
+      const double w2 = ((const BST_G double*)(ptrs[t.w2_buf]))[t.w2_off];
       sum += w1 * w2;
     }
     c64[e] = sum;
@@ -157,7 +157,7 @@ __global__ __launch_bounds__(256) void happly_sparse_kernel(const HTask* __restr
   const int site = w.site0 + tid;
   if (site >= t.rows * t.cols) return;
   const int i = site / t.cols, jc = site % t.cols;
-  const T* __restrict__ in = reinterpret_cast<const T*>(ptrs[t.in_buf]);
+  const BST_G T* __restrict__ in = (const BST_G T*)(ptrs[t.in_buf]);
   // all input loads in flight at once, then staged (each lane reads back
   // only its own column, so no barrier is needed)
   T xr[NMAX];
@@ -173,9 +173,9 @@ __global__ __launch_bounds__(256) void happly_sparse_kernel(const HTask* __restr
     const HPlane q = pl[t.nin + o];
     const int64_t at = q.off + (int64_t)i * q.rowstride + jc;
     if constexpr (NP == 0) {
-      reinterpret_cast<T*>(ptrs[t.out_buf])[at] = y;
+      ((BST_G T*)(ptrs[t.out_buf]))[at] = y;
     } else {
-      unsigned short* out = reinterpret_cast<unsigned short*>(ptrs[t.out_buf]);
+      BST_G unsigned short* out = (BST_G unsigned short*)(ptrs[t.out_buf]);
       const float yf = (float)y;
       unsigned int u = __float_as_uint(yf);
       const unsigned short h0 = (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
@@ -230,8 +230,8 @@ __global__ __launch_bounds__(256) void happly_kernel(const HTask* __restrict__ t
   const int site = w.site0 + tid;
   if (site >= t.rows * t.cols) return;
   const int i = site / t.cols, jc = site % t.cols;
-  const T* __restrict__ in = reinterpret_cast<const T*>(ptrs[t.in_buf]);
-  T* __restrict__ out = reinterpret_cast<T*>(ptrs[t.out_buf]);
+  const BST_G T* __restrict__ in = (const BST_G T*)(ptrs[t.in_buf]);
+  BST_G T* __restrict__ out = (BST_G T*)(ptrs[t.out_buf]);
   T x[NMAX];
 #pragma unroll
   for (int k = 0; k < NMAX; ++k)

@@ -47,8 +47,8 @@ __global__ __launch_bounds__(256) void gemm_direct_kernel(const GemmTile* __rest
 
   auto load = [&](CT (&a)[SM][4], CT (&b)[SN][4]) {
     const GemmSeg sg = segs[p.seg_begin + cs];
-    const TA* __restrict__ A = reinterpret_cast<const TA*>(ptrs[sg.a_buf]) + sg.a_off;
-    const double* __restrict__ B = reinterpret_cast<const double*>(ptrs[sg.b_buf]) + sg.b_off;
+    const BST_G TA* __restrict__ A = (const BST_G TA*)(ptrs[sg.a_buf]) + sg.a_off;
+    const BST_G double* __restrict__ B = (const BST_G double*)(ptrs[sg.b_buf]) + sg.b_off;
 #pragma unroll
     for (int i = 0; i < SM; ++i) {
       const int r = rbase + i * 16;
@@ -101,7 +101,7 @@ __global__ __launch_bounds__(256) void gemm_direct_kernel(const GemmTile* __rest
       if (!h0) break;
     }
   }
-  TC* __restrict__ C = reinterpret_cast<TC*>(ptrs[p.c_buf]) + p.c_off;
+  BST_G TC* __restrict__ C = (BST_G TC*)(ptrs[p.c_buf]) + p.c_off;
 #pragma unroll
   for (int i = 0; i < SM; ++i)
 #pragma unroll
@@ -142,8 +142,8 @@ __global__ __launch_bounds__(256) void gemm_direct_planes_kernel(const GemmTile*
 
   auto load = [&](us8 (&a)[NP][SM], us8 (&b)[NP][SN]) {
     const GemmSeg sg = segs[p.seg_begin + cs];
-    const unsigned short* __restrict__ A = reinterpret_cast<const unsigned short*>(ptrs[sg.a_buf]) + sg.a_off;
-    const unsigned short* __restrict__ B = reinterpret_cast<const unsigned short*>(ptrs[sg.b_buf]) + sg.b_off;
+    const BST_G unsigned short* __restrict__ A = (const BST_G unsigned short*)(ptrs[sg.a_buf]) + sg.a_off;
+    const BST_G unsigned short* __restrict__ B = (const BST_G unsigned short*)(ptrs[sg.b_buf]) + sg.b_off;
     const int kv = ck + g8;
     const bool kin = kv < sg.K, kedge = kv + 8 > sg.K;
 #pragma unroll
@@ -152,7 +152,7 @@ __global__ __launch_bounds__(256) void gemm_direct_planes_kernel(const GemmTile*
       const bool ok = kin && r < p.M;
 #pragma unroll
       for (int q = 0; q < NP; ++q) {
-        us8 x = ok ? *reinterpret_cast<const us8*>(A + q * sg.a_ps + (int64_t)r * sg.lda + kv) : z8;
+        us8 x = ok ? *reinterpret_cast<const BST_G us8*>(A + q * sg.a_ps + (int64_t)r * sg.lda + kv) : z8;
         if (ok && kedge) {
 #pragma unroll
           for (int e = 0; e < 8; ++e)
@@ -167,7 +167,7 @@ __global__ __launch_bounds__(256) void gemm_direct_planes_kernel(const GemmTile*
       const bool ok = kin && c < p.N;
 #pragma unroll
       for (int q = 0; q < NP; ++q) {
-        us8 x = ok ? *reinterpret_cast<const us8*>(B + q * sg.b_ps + (int64_t)c * sg.ldb + kv) : z8;
+        us8 x = ok ? *reinterpret_cast<const BST_G us8*>(B + q * sg.b_ps + (int64_t)c * sg.ldb + kv) : z8;
         if (ok && kedge) {
 #pragma unroll
           for (int e = 0; e < 8; ++e)
@@ -216,7 +216,7 @@ __global__ __launch_bounds__(256) void gemm_direct_planes_kernel(const GemmTile*
       if (!h0) break;
     }
   }
-  TC* __restrict__ C = reinterpret_cast<TC*>(ptrs[p.c_buf]);
+  BST_G TC* __restrict__ C = (BST_G TC*)(ptrs[p.c_buf]);
 #pragma unroll
   for (int i = 0; i < SM; ++i)
 #pragma unroll

@@ -133,8 +133,8 @@ __global__ __launch_bounds__(256) void gemm_grouped_kernel(const GemmTile* __res
   double rb[EB];
   auto fetch = [&]() {
     const GemmSeg g = segs[p.seg_begin + ls];
-    const TA* __restrict__ A = reinterpret_cast<const TA*>(ptrs[g.a_buf]) + g.a_off;
-    const double* __restrict__ B = reinterpret_cast<const double*>(ptrs[g.b_buf]) + g.b_off;
+    const BST_G TA* __restrict__ A = (const BST_G TA*)(ptrs[g.a_buf]) + g.a_off;
+    const BST_G double* __restrict__ B = (const BST_G double*)(ptrs[g.b_buf]) + g.b_off;
 #pragma unroll
     for (int e = 0; e < EA; ++e) {
       const int idx = tid + e * 256;
@@ -261,7 +261,7 @@ __global__ __launch_bounds__(256) void gemm_grouped_kernel(const GemmTile* __res
     }
   }
   // ---- epilogue: each element written exactly once ----
-  TC* __restrict__ C = reinterpret_cast<TC*>(ptrs[p.c_buf]) + p.c_off;
+  BST_G TC* __restrict__ C = (BST_G TC*)(ptrs[p.c_buf]) + p.c_off;
 #pragma unroll
   for (int i = 0; i < SM; ++i)
 #pragma unroll

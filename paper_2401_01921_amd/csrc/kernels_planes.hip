@@ -50,8 +50,8 @@ __global__ __launch_bounds__(256) void split_kernel(const SplitJob* __restrict__
   __shared__ double tile[64][65];
   const SplitWork w = work[blockIdx.x];
   const SplitJob j = jobs[w.job];
-  const double* __restrict__ in = reinterpret_cast<const double*>(ptrs[j.in_buf]) + j.in_off;
-  unsigned short* __restrict__ out = reinterpret_cast<unsigned short*>(ptrs[j.out_buf]) + j.out_off;
+  const BST_G double* __restrict__ in = (const BST_G double*)(ptrs[j.in_buf]) + j.in_off;
+  BST_G unsigned short* __restrict__ out = (BST_G unsigned short*)(ptrs[j.out_buf]) + j.out_off;
   const int tid = threadIdx.x;
   const int orow = tid >> 3, ocol = (tid & 7) * 8;   // 32 rows x 8 vectors per pass
   if (!j.transpose) {
@@ -71,7 +71,7 @@ __global__ __launch_bounds__(256) void split_kernel(const SplitJob* __restrict__
         }
 #pragma unroll
         for (int q = 0; q < NP; ++q)
-          *reinterpret_cast<us8*>(out + q * j.out_ps + (int64_t)r * j.out_ld + c) = h[q];
+          *reinterpret_cast<BST_G us8*>(out + q * j.out_ps + (int64_t)r * j.out_ld + c) = h[q];
       }
     }
     return;
@@ -98,7 +98,7 @@ __global__ __launch_bounds__(256) void split_kernel(const SplitJob* __restrict__
       }
 #pragma unroll
       for (int q = 0; q < NP; ++q)
-        *reinterpret_cast<us8*>(out + q * j.out_ps + (int64_t)gc * j.out_ld + gr) = h[q];
+        *reinterpret_cast<BST_G us8*>(out + q * j.out_ps + (int64_t)gc * j.out_ld + gr) = h[q];
     }
   }
 }
@@ -165,8 +165,8 @@ __global__ __launch_bounds__(256) void gemm_planes_kernel(const GemmTile* __rest
   int ls = 0, lk = 0;
   auto load = [&](int s, int k0) {
     const GemmSeg g = segs[p.seg_begin + s];
-    const unsigned short* A = reinterpret_cast<const unsigned short*>(ptrs[g.a_buf]) + g.a_off;
-    const unsigned short* B = reinterpret_cast<const unsigned short*>(ptrs[g.b_buf]) + g.b_off;
+    const BST_G unsigned short* A = (const BST_G unsigned short*)(ptrs[g.a_buf]) + g.a_off;
+    const BST_G unsigned short* B = (const BST_G unsigned short*)(ptrs[g.b_buf]) + g.b_off;
 #pragma unroll
     for (int v = 0; v < NVA; ++v) {
       const int idx = tid + v * 256;
@@ -175,7 +175,7 @@ __global__ __launch_bounds__(256) void gemm_planes_kernel(const GemmTile* __rest
       const bool ok = (idx < BM * 4) && gr < p.M && kv < g.K;
 #pragma unroll
       for (int q = 0; q < NP; ++q) {
-        us8 x = ok ? *reinterpret_cast<const us8*>(A + q * g.a_ps + (int64_t)gr * g.lda + kv) : zero8;
+        us8 x = ok ? *reinterpret_cast<const BST_G us8*>(A + q * g.a_ps + (int64_t)gr * g.lda + kv) : zero8;
         if (ok && kv + 8 > g.K) {
 #pragma unroll
           for (int e = 0; e < 8; ++e)
@@ -192,7 +192,7 @@ __global__ __launch_bounds__(256) void gemm_planes_kernel(const GemmTile* __rest
       const bool ok = (idx < BN * 4) && gn < p.N && kv < g.K;
 #pragma unroll
       for (int q = 0; q < NP; ++q) {
-        us8 x = ok ? *reinterpret_cast<const us8*>(B + q * g.b_ps + (int64_t)gn * g.ldb + kv) : zero8;
+        us8 x = ok ? *reinterpret_cast<const BST_G us8*>(B + q * g.b_ps + (int64_t)gn * g.ldb + kv) : zero8;
         if (ok && kv + 8 > g.K) {
 #pragma unroll
           for (int e = 0; e < 8; ++e)
@@ -281,7 +281,7 @@ __global__ __launch_bounds__(256) void gemm_planes_kernel(const GemmTile* __rest
     buf ^= 1;
     more = have_next;
   }
-  TC* __restrict__ C = reinterpret_cast<TC*>(ptrs[p.c_buf]);
+  BST_G TC* __restrict__ C = (BST_G TC*)(ptrs[p.c_buf]);
 #pragma unroll
   for (int i = 0; i < SM; ++i)
 #pragma unroll
@@ -341,7 +341,7 @@ __global__ __launch_bounds__(256) void gemm_planes_persist_kernel(
         lvalid = true;
         return;
       }
-      TC* __restrict__ C = reinterpret_cast<TC*>(ptrs[lp.c_buf]);
+      BST_G TC* __restrict__ C = (BST_G TC*)(ptrs[lp.c_buf]);
       for (int e = tid; e < BM * BN; e += 256) {
         const int row = lm0 + e / BN, col = ln0 + e % BN;
         if (row < lp.M && col < lp.N) C[row_base(lp, row) + col] = (TC)0;
@@ -351,8 +351,8 @@ __global__ __launch_bounds__(256) void gemm_planes_persist_kernel(
   us8 ra[NP][NVA], rb[NP][NVB];
   auto load = [&]() {
     const GemmSeg g = segs[lp.seg_begin + ls];
-    const unsigned short* A = reinterpret_cast<const unsigned short*>(ptrs[g.a_buf]) + g.a_off;
-    const unsigned short* B = reinterpret_cast<const unsigned short*>(ptrs[g.b_buf]) + g.b_off;
+    const BST_G unsigned short* A = (const BST_G unsigned short*)(ptrs[g.a_buf]) + g.a_off;
+    const BST_G unsigned short* B = (const BST_G unsigned short*)(ptrs[g.b_buf]) + g.b_off;
 #pragma unroll
     for (int v = 0; v < NVA; ++v) {
       const int idx = tid + v * 256;
@@ -361,7 +361,7 @@ __global__ __launch_bounds__(256) void gemm_planes_persist_kernel(
       const bool ok = (idx < BM * 4) && gr < lp.M && kv < g.K;
 #pragma unroll
       for (int q = 0; q < NP; ++q) {
-        us8 x = ok ? *reinterpret_cast<const us8*>(A + q * g.a_ps + (int64_t)gr * g.lda + kv) : zero8;
+        us8 x = ok ? *reinterpret_cast<const BST_G us8*>(A + q * g.a_ps + (int64_t)gr * g.lda + kv) : zero8;
         if (ok && kv + 8 > g.K) {
 #pragma unroll
           for (int e = 0; e < 8; ++e)
@@ -378,7 +378,7 @@ __global__ __launch_bounds__(256) void gemm_planes_persist_kernel(
       const bool ok = (idx < BN * 4) && gn < lp.N && kv < g.K;
 #pragma unroll
       for (int q = 0; q < NP; ++q) {
-        us8 x = ok ? *reinterpret_cast<const us8*>(B + q * g.b_ps + (int64_t)gn * g.ldb + kv) : zero8;
+        us8 x = ok ? *reinterpret_cast<const BST_G us8*>(B + q * g.b_ps + (int64_t)gn * g.ldb + kv) : zero8;
         if (ok && kv + 8 > g.K) {
 #pragma unroll
           for (int e = 0; e < 8; ++e)
@@ -478,7 +478,7 @@ __global__ __launch_bounds__(256) void gemm_planes_persist_kernel(
         }
     }
     if (clast) {
-      TC* __restrict__ C = reinterpret_cast<TC*>(ptrs[cp.c_buf]);
+      BST_G TC* __restrict__ C = (BST_G TC*)(ptrs[cp.c_buf]);
 #pragma unroll
       for (int i = 0; i < SM; ++i)
 #pragma unroll
@@ -587,8 +587,8 @@ __global__ __launch_bounds__(256) void happly_planes_kernel(const HTask* __restr
   const int site = w.site0 + tid;
   if (site >= t.rows * t.cols) return;
   const int i = site / t.cols, jc = site % t.cols;
-  const float* __restrict__ in = reinterpret_cast<const float*>(ptrs[t.in_buf]);
-  unsigned short* __restrict__ out = reinterpret_cast<unsigned short*>(ptrs[t.out_buf]);
+  const BST_G float* __restrict__ in = (const BST_G float*)(ptrs[t.in_buf]);
+  BST_G unsigned short* __restrict__ out = (BST_G unsigned short*)(ptrs[t.out_buf]);
   float x[NMAX];
 #pragma unroll
   for (int k = 0; k < NMAX; ++k)
