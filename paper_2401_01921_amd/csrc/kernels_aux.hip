@@ -11,6 +11,10 @@ namespace bst {
 // ------------------------------------------------------------------------
 constexpr int kPT = 64;   // transpose tile edge
 
+// Streaming 16-byte access when the address is 16-byte aligned, else two
+// 8-byte accesses (block offsets and strides may be odd).
+typedef double dbl2v __attribute__((ext_vector_type(2)));
+
 __global__ __launch_bounds__(256) void permute_kernel(const PermJob* __restrict__ jobs,
                                                       const PermWork* __restrict__ work,
                                                       void* const* __restrict__ ptrs) {
@@ -22,7 +26,8 @@ __global__ __launch_bounds__(256) void permute_kernel(const PermJob* __restrict_
   const int r = j.rank;
   const int tid = threadIdx.x;
   if (w.kind == 0) {
-    // fastest dim kept: copy whole rows; rows w.batch .. w.batch + w.t0 - 1
+    // fastest dim kept: copy whole rows; rows w.batch .. w.batch + w.t0 - 1,
+    // two elements per lane where source and destination allow it
     const int64_t last = j.shape[r - 1];
     const int wave = tid >> 6, lane = tid & 63;
     for (int64_t row = w.batch + wave; row < w.batch + w.t0; row += 4) {
@@ -35,7 +40,16 @@ __global__ __launch_bounds__(256) void permute_kernel(const PermJob* __restrict_
       }
       const BST_G double* src = in + row * last;
       BST_G double* dst = out + ob;
-      for (int64_t c = lane; c < last; c += 64) dst[c] = src[c];
+      const bool vec = ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & 15) == 0;
+      if (vec) {
+        for (int64_t c = 2 * lane; c + 1 < last; c += 128) {
+          const dbl2v v = __builtin_nontemporal_load(reinterpret_cast<const BST_G dbl2v*>(src + c));
+          __builtin_nontemporal_store(v, reinterpret_cast<BST_G dbl2v*>(dst + c));
+        }
+        if ((last & 1) && lane == 0) dst[last - 1] = src[last - 1];
+      } else {
+        for (int64_t c = lane; c < last; c += 64) dst[c] = src[c];
+      }
     }
     return;
   }
@@ -52,16 +66,43 @@ __global__ __launch_bounds__(256) void permute_kernel(const PermJob* __restrict_
   }
   const int np = j.shape[p], nl = j.shape[r - 1];
   const int64_t isp = j.istride[p], osl = j.ostride[r - 1];
-  for (int e = tid; e < kPT * kPT; e += 256) {
-    const int y = e / kPT, x = e % kPT;
+  // read: pairs of consecutive input columns; write: pairs of consecutive
+  // output positions (input rows).  Odd addresses fall back to 8 bytes.
+#pragma unroll
+  for (int k = 0; k < (kPT * kPT / 2) / 256; ++k) {
+    const int e = tid + 256 * k;
+    const int y = e / (kPT / 2), x = 2 * (e % (kPT / 2));
     const int gy = w.t0 + y, gx = w.t1 + x;
-    if (gy < np && gx < nl) tile[y][x] = in[ib + gy * isp + gx];
+    if (gy < np && gx < nl) {
+      const BST_G double* src = in + ib + gy * isp + gx;
+      if (gx + 1 < nl && (reinterpret_cast<uintptr_t>(src) & 15) == 0) {
+        const dbl2v v = __builtin_nontemporal_load(reinterpret_cast<const BST_G dbl2v*>(src));
+        tile[y][x] = v.x;
+        tile[y][x + 1] = v.y;
+      } else {
+        tile[y][x] = src[0];
+        if (gx + 1 < nl) tile[y][x + 1] = src[1];
+      }
+    }
   }
   __syncthreads();
-  for (int e = tid; e < kPT * kPT; e += 256) {
-    const int x = e / kPT, y = e % kPT;
+#pragma unroll
+  for (int k = 0; k < (kPT * kPT / 2) / 256; ++k) {
+    const int e = tid + 256 * k;
+    const int x = e / (kPT / 2), y = 2 * (e % (kPT / 2));
     const int gy = w.t0 + y, gx = w.t1 + x;
-    if (gy < np && gx < nl) out[ob + gy + gx * osl] = tile[y][x];
+    if (gy < np && gx < nl) {
+      BST_G double* dst = out + ob + gy + gx * osl;
+      if (gy + 1 < np && (reinterpret_cast<uintptr_t>(dst) & 15) == 0) {
+        dbl2v v;
+        v.x = tile[y][x];
+        v.y = tile[y + 1][x];
+        __builtin_nontemporal_store(v, reinterpret_cast<BST_G dbl2v*>(dst));
+      } else {
+        dst[0] = tile[y][x];
+        if (gy + 1 < np) dst[1] = tile[y + 1][x];
+      }
+    }
   }
 }
 
