@@ -346,10 +346,18 @@ def bench_extras(bst, wl, torch, dev, plan, ins_apply, apply_flops):
     prof = pplan.profile([x], [y], wsp, reps=5)
     kms = prof[0][1]
     out["permute"] = {"numel": T.numel, "gib": round(T.numel * 8 / 2**30, 3), "blocks": T.nblocks,
+                      "order": "(c,a,b) <- (a,b,c)",
                       "ms": round(ms_p, 4), "kernel_ms": round(kms, 4),
                       "gbs": round(2 * 8 * T.numel / kms / 1e6, 1),
                       "hbm_frac": round(2 * 8 * T.numel / kms / 1e6 / PEAK["hbm_gbs"], 4)}
-    del x, y, wsp
+    # the same tensor with its fastest leg kept: block rows are copied whole
+    Tq, qplan = bst.permute_plan(T, ["b", "a", "c"])
+    wsq = bst.workspace(qplan.workspace_bytes)
+    kq = qplan.profile([x], [y], wsq, reps=5)[0][1]
+    out["permute_rows"] = {"order": "(b,a,c) <- (a,b,c)", "kernel_ms": round(kq, 4),
+                           "gbs": round(2 * 8 * T.numel / kq / 1e6, 1),
+                           "hbm_frac": round(2 * 8 * T.numel / kq / 1e6 / PEAK["hbm_gbs"], 4)}
+    del x, y, wsp, wsq
     return out
 
 

@@ -112,6 +112,7 @@ struct PermJob {
 };
 // A work item of the permute kernels: a tile (transposing jobs) or a row
 // range (jobs that keep the fastest dim).
+constexpr int kPermRows = 1024;   // most rows in one row-copy work item
 struct PermWork {
   int32_t job;
   int32_t kind;       // 0: rows, 1: tile

@@ -10,6 +10,7 @@ namespace bst {
 // Block permute (Sec. "Permute", App. "Contiguous")
 // ------------------------------------------------------------------------
 constexpr int kPT = 64;   // transpose tile edge
+static_assert(kPermRows <= kPT * (kPT + 1), "row offsets share the transpose tile's LDS");
 
 // Streaming 16-byte access when the address is 16-byte aligned, else two
 // 8-byte accesses (block offsets and strides may be odd).
@@ -26,29 +27,34 @@ __global__ __launch_bounds__(256) void permute_kernel(const PermJob* __restrict_
   const int r = j.rank;
   const int tid = threadIdx.x;
   if (w.kind == 0) {
-    // fastest dim kept: copy whole rows; rows w.batch .. w.batch + w.t0 - 1,
-    // two elements per lane where source and destination allow it
+    // fastest dim kept: rows w.batch .. w.batch + w.t0 - 1 are copied whole.
+    // The rows' output offsets go to LDS first; then the block's element
+    // pairs are spread over all lanes regardless of the row length.
+    int64_t* orow = reinterpret_cast<int64_t*>(&tile[0][0]);   // kPermRows <= tile size
     const int64_t last = j.shape[r - 1];
-    const int wave = tid >> 6, lane = tid & 63;
-    for (int64_t row = w.batch + wave; row < w.batch + w.t0; row += 4) {
-      int64_t rem = row, ob = 0;
+    const int nrow = w.t0;
+    for (int q = tid; q < nrow; q += 256) {
+      int64_t rem = w.batch + q, ob = 0;
       for (int d = r - 2; d >= 0; --d) {
         const int64_t ext = j.shape[d];
         const int64_t idx = rem % ext;
         rem /= ext;
         ob += idx * j.ostride[d];
       }
-      const BST_G double* src = in + row * last;
-      BST_G double* dst = out + ob;
-      const bool vec = ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & 15) == 0;
-      if (vec) {
-        for (int64_t c = 2 * lane; c + 1 < last; c += 128) {
-          const dbl2v v = __builtin_nontemporal_load(reinterpret_cast<const BST_G dbl2v*>(src + c));
-          __builtin_nontemporal_store(v, reinterpret_cast<BST_G dbl2v*>(dst + c));
-        }
-        if ((last & 1) && lane == 0) dst[last - 1] = src[last - 1];
+      orow[q] = ob;
+    }
+    __syncthreads();
+    const int64_t npair = (last + 1) / 2;
+    for (int64_t e = tid; e < (int64_t)nrow * npair; e += 256) {
+      const int64_t q = e / npair, c = 2 * (e - q * npair);
+      const BST_G double* src = in + (w.batch + q) * last + c;
+      BST_G double* dst = out + orow[q] + c;
+      if (c + 1 < last && ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & 15) == 0) {
+        __builtin_nontemporal_store(__builtin_nontemporal_load(reinterpret_cast<const BST_G dbl2v*>(src)),
+                                    reinterpret_cast<BST_G dbl2v*>(dst));
       } else {
-        for (int64_t c = lane; c < last; c += 64) dst[c] = src[c];
+        dst[0] = src[0];
+        if (c + 1 < last) dst[1] = src[1];
       }
     }
     return;

@@ -89,7 +89,7 @@ static void add_permute_jobs(Step& st, const TensorDesc& in, const TensorDesc& o
       st.jobs.push_back(j);
       const int64_t rows = numel / last;
       int64_t per = std::max<int64_t>(1, 8192 / last);
-      per = std::min<int64_t>(per, 1 << 20);
+      per = std::min<int64_t>(per, kPermRows);
       for (int64_t r0 = 0; r0 < rows; r0 += per) {
         PermWork w{};
         w.job = jid;

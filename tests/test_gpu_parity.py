@@ -49,6 +49,22 @@ def test_permute_bit_exact_random_structures():
         assert np.array_equal(host(y), P.data)
 
 
+@pytest.mark.parametrize("order", [["b", "a", "c"], ["c", "a", "b"], ["a", "c", "b"], ["c", "b", "a"]])
+def test_permute_bit_exact_large_blocks(order):
+    """Blocks wider than one tile and rows longer than a wave in both
+    directions, odd extents (odd block offsets), fastest leg kept or moved."""
+    legs = [(1, [(-1, 70), (0, 131), (1, 3)]), (1, [(0, 150), (1, 9)]), (-1, [(-1, 67), (0, 130), (1, 41), (2, 5)])]
+    O = orc.BlockTensor(["a", "b", "c"], legs)
+    O.data[:] = wl.normal(77, O.numel)
+    P = orc.permute(O, order)
+    T = bst.Tensor(["a", "b", "c"], legs)
+    out_t, plan = bst.permute_plan(T, order)
+    y = torch.full((out_t.numel,), np.nan, dtype=torch.float64, device=DEV)
+    plan.execute([dev(O.data)], [y], bst.workspace(plan.workspace_bytes))
+    torch.cuda.synchronize()
+    assert np.array_equal(host(y), P.data)
+
+
 def test_permute_paper_example():
     T = bst.Tensor(["a", "b", "c"], [(1, [(0, 2)]), (1, [(0, 2)]), (-1, [(0, 2)])])
     out_t, plan = bst.permute_plan(T, ["a", "c", "b"])
