@@ -123,6 +123,14 @@ hipError_t launch_split(const SplitLaunch& l, hipStream_t s) {
 // rows one MFMA operand read touches (same chunk) and the 4 rows x 4 chunks
 // one 16-lane group stores fall on 16 distinct 4-bank groups.
 __device__ __forceinline__ int lds_chunk(int r, int c) { return r * 32 + ((c ^ ((r >> 2) & 3)) << 3); }
+// The same for rows of CH chunks (CH = 4: lds_chunk; CH = 8: 128-byte rows,
+// chunk c of row r at c ^ ((r >> 1) & 7), again conflict-free for 16 rows of
+// one chunk and for the 2 rows x 8 chunks of a 16-lane store).
+template <int CH>
+__device__ __forceinline__ int lds_at(int r, int c) {
+  if constexpr (CH == 4) return lds_chunk(r, c);
+  return r * 64 + ((c ^ ((r >> 1) & 7)) << 3);
+}
 
 // Tile shapes per plane count (double-buffered LDS: 80 KB at 128x128, two planes).
 // Direct (LDS-free) variants first: index 0 is the default.
@@ -133,15 +141,16 @@ static const std::vector<TileShape> kPlaneShapes3 = {{64, 64, 1}, {128, 64, 1}, 
                                                      {64, 64, 0}, {32, 32, 0}, {64, 64, 2}};
 const std::vector<TileShape>& gemm_planes_shapes(int np) { return np == 3 ? kPlaneShapes3 : kPlaneShapes2; }
 
-template <int NP, typename TC, int BM, int BN>
+template <int NP, typename TC, int BM, int BN, int BK>
 __global__ __launch_bounds__(256) void gemm_planes_kernel(const GemmTile* __restrict__ tiles,
                                                           const GemmProb* __restrict__ probs,
                                                           const GemmSeg* __restrict__ segs,
                                                           void* const* __restrict__ ptrs,
                                                           const int64_t* __restrict__ rowmap) {
-  constexpr int BK = 32, LDR = BK;   // LDS row: 64 bytes, chunks swizzled (lds_chunk)
+  // LDS row: one BK-deep k step (64 or 128 bytes), 16-byte chunks swizzled
+  constexpr int LDR = BK, CH = BK / 8;
   constexpr int WM = BM / 2, WN = BN / 2, SM = WM / 16, SN = WN / 16;
-  constexpr int NVA = (BM * 4 + 255) / 256, NVB = (BN * 4 + 255) / 256;   // 16-byte vectors per thread
+  constexpr int NVA = (BM * CH + 255) / 256, NVB = (BN * CH + 255) / 256;   // 16-byte vectors per thread
   __shared__ __attribute__((aligned(16))) unsigned short As[2][NP][BM * LDR];
   __shared__ __attribute__((aligned(16))) unsigned short Bs[2][NP][BN * LDR];
 
@@ -158,47 +167,47 @@ __global__ __launch_bounds__(256) void gemm_planes_kernel(const GemmTile* __rest
 #pragma unroll
     for (int j = 0; j < SN; ++j) acc[i][j] = flt4{0, 0, 0, 0};
 
+  // Loads only issue the 16-byte reads; rows past M / N and k past the
+  // segment's K are zeroed when the registers go to LDS (after the MFMAs),
+  // so no wait for the data sits between the loads.
   us8 ra[NP][NVA], rb[NP][NVB];
-  const us8 zero8 = {0, 0, 0, 0, 0, 0, 0, 0};
+  int na[NVA], nb[NVB];   // valid k elements of each vector (0..8)
 
-  // cursor of the next k-step to load: (segment, k0)
+  // cursor of the next k-step to load: segment ls (cached), offset lk
   int ls = 0, lk = 0;
-  auto load = [&](int s, int k0) {
-    const GemmSeg g = segs[p.seg_begin + s];
-    const BST_G unsigned short* A = (const BST_G unsigned short*)(ptrs[g.a_buf]) + g.a_off;
-    const BST_G unsigned short* B = (const BST_G unsigned short*)(ptrs[g.b_buf]) + g.b_off;
+  GemmSeg lg{};
+  const BST_G unsigned short* lA = nullptr;
+  const BST_G unsigned short* lB = nullptr;
+  auto set_seg = [&]() {
+    lg = segs[p.seg_begin + ls];
+    lA = (const BST_G unsigned short*)(ptrs[lg.a_buf]) + lg.a_off;
+    lB = (const BST_G unsigned short*)(ptrs[lg.b_buf]) + lg.b_off;
+  };
+  auto load = [&]() {
 #pragma unroll
     for (int v = 0; v < NVA; ++v) {
       const int idx = tid + v * 256;
-      const int r = idx >> 2, kv = k0 + (idx & 3) * 8;
+      const int r = idx / CH, kv = lk + (idx % CH) * 8;
       const int gr = m0 + r;
-      const bool ok = (idx < BM * 4) && gr < p.M && kv < g.K;
+      const bool ok = (idx < BM * CH) && gr < p.M && kv < lg.K;
+      na[v] = ok ? min(8, lg.K - kv) : 0;
+      if (ok) {
 #pragma unroll
-      for (int q = 0; q < NP; ++q) {
-        us8 x = ok ? *reinterpret_cast<const BST_G us8*>(A + q * g.a_ps + (int64_t)gr * g.lda + kv) : zero8;
-        if (ok && kv + 8 > g.K) {
-#pragma unroll
-          for (int e = 0; e < 8; ++e)
-            if (kv + e >= g.K) x[e] = 0;
-        }
-        ra[q][v] = x;
+        for (int q = 0; q < NP; ++q)
+          ra[q][v] = *reinterpret_cast<const BST_G us8*>(lA + q * lg.a_ps + (int64_t)gr * lg.lda + kv);
       }
     }
 #pragma unroll
     for (int v = 0; v < NVB; ++v) {
       const int idx = tid + v * 256;
-      const int r = idx >> 2, kv = k0 + (idx & 3) * 8;
+      const int r = idx / CH, kv = lk + (idx % CH) * 8;
       const int gn = n0 + r;
-      const bool ok = (idx < BN * 4) && gn < p.N && kv < g.K;
+      const bool ok = (idx < BN * CH) && gn < p.N && kv < lg.K;
+      nb[v] = ok ? min(8, lg.K - kv) : 0;
+      if (ok) {
 #pragma unroll
-      for (int q = 0; q < NP; ++q) {
-        us8 x = ok ? *reinterpret_cast<const BST_G us8*>(B + q * g.b_ps + (int64_t)gn * g.ldb + kv) : zero8;
-        if (ok && kv + 8 > g.K) {
-#pragma unroll
-          for (int e = 0; e < 8; ++e)
-            if (kv + e >= g.K) x[e] = 0;
-        }
-        rb[q][v] = x;
+        for (int q = 0; q < NP; ++q)
+          rb[q][v] = *reinterpret_cast<const BST_G us8*>(lB + q * lg.b_ps + (int64_t)gn * lg.ldb + kv);
       }
     }
   };
@@ -206,33 +215,45 @@ __global__ __launch_bounds__(256) void gemm_planes_kernel(const GemmTile* __rest
 #pragma unroll
     for (int v = 0; v < NVA; ++v) {
       const int idx = tid + v * 256;
-      if (idx < BM * 4) {
+      if (idx < BM * CH) {
 #pragma unroll
-        for (int q = 0; q < NP; ++q)
-          *reinterpret_cast<us8*>(&As[buf][q][lds_chunk(idx >> 2, idx & 3)]) = ra[q][v];
+        for (int q = 0; q < NP; ++q) {
+          us8 x = ra[q][v];
+#pragma unroll
+          for (int e = 0; e < 8; ++e)
+            if (e >= na[v]) x[e] = 0;
+          *reinterpret_cast<us8*>(&As[buf][q][lds_at<CH>(idx / CH, idx % CH)]) = x;
+        }
       }
     }
 #pragma unroll
     for (int v = 0; v < NVB; ++v) {
       const int idx = tid + v * 256;
-      if (idx < BN * 4) {
+      if (idx < BN * CH) {
 #pragma unroll
-        for (int q = 0; q < NP; ++q)
-          *reinterpret_cast<us8*>(&Bs[buf][q][lds_chunk(idx >> 2, idx & 3)]) = rb[q][v];
+        for (int q = 0; q < NP; ++q) {
+          us8 x = rb[q][v];
+#pragma unroll
+          for (int e = 0; e < 8; ++e)
+            if (e >= nb[v]) x[e] = 0;
+          *reinterpret_cast<us8*>(&Bs[buf][q][lds_at<CH>(idx / CH, idx % CH)]) = x;
+        }
       }
     }
   };
   auto advance = [&]() {
     lk += BK;
-    if (lk >= segs[p.seg_begin + ls].K) {
+    if (lk >= lg.K) {
       ls++;
       lk = 0;
+      if (ls < p.seg_count) set_seg();
     }
   };
 
   int buf = 0;
   if (p.seg_count > 0) {
-    load(ls, lk);
+    set_seg();
+    load();
     advance();
     store(0);
   }
@@ -240,25 +261,25 @@ __global__ __launch_bounds__(256) void gemm_planes_kernel(const GemmTile* __rest
   bool more = p.seg_count > 0;
   while (more) {
     const bool have_next = ls < p.seg_count;
-    if (have_next) load(ls, lk);
-    // MFMA on the current buffer
-    {
-      const int kc = lane >> 4;   // 8-element k chunk of this lane
+    if (have_next) load();
+    // MFMA on the current buffer, BK / 32 steps of 32
+#pragma unroll
+    for (int ks = 0; ks < BK / 32; ++ks) {
+      const int kc = (lane >> 4) + 4 * ks;   // 8-element k chunk of this lane
       bf16x8 a[NP][SM], b[NP][SN];
 #pragma unroll
       for (int q = 0; q < NP; ++q) {
 #pragma unroll
         for (int i = 0; i < SM; ++i) {
           const int r = wm * WM + i * 16 + (lane & 15);
-          a[q][i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const us8*>(&As[buf][q][lds_chunk(r, kc)]));
+          a[q][i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const us8*>(&As[buf][q][lds_at<CH>(r, kc)]));
         }
 #pragma unroll
         for (int j = 0; j < SN; ++j) {
           const int c = wn * WN + j * 16 + (lane & 15);
-          b[q][j] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const us8*>(&Bs[buf][q][lds_chunk(c, kc)]));
+          b[q][j] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const us8*>(&Bs[buf][q][lds_at<CH>(c, kc)]));
         }
       }
-      // second 16-wide half of the 32-deep k step is in the same vectors (K = 32 per MFMA)
 #pragma unroll
       for (int i = 0; i < SM; ++i)
 #pragma unroll
@@ -282,17 +303,25 @@ __global__ __launch_bounds__(256) void gemm_planes_kernel(const GemmTile* __rest
     more = have_next;
   }
   BST_G TC* __restrict__ C = (BST_G TC*)(ptrs[p.c_buf]);
+  // all row offsets first (row-mapped problems read them from the table)
+  int64_t rbase[SM][4];
 #pragma unroll
   for (int i = 0; i < SM; ++i)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int row = m0 + wm * WM + i * 16 + 4 * (lane >> 4) + r;
-      if (row >= p.M) continue;
-      const int64_t rbase = p.rowmap1 > 0 ? rowmap[p.rowmap1 - 1 + row] : p.c_off + (int64_t)row * p.ldc;
+      rbase[i][r] = row >= p.M ? -1
+                               : (p.rowmap1 > 0 ? rowmap[p.rowmap1 - 1 + row] : p.c_off + (int64_t)row * p.ldc);
+    }
+#pragma unroll
+  for (int i = 0; i < SM; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      if (rbase[i][r] < 0) continue;
 #pragma unroll
       for (int j = 0; j < SN; ++j) {
         const int col = n0 + wn * WN + j * 16 + (lane & 15);
-        if (col < p.N) C[rbase + col] = (TC)acc[i][j][r];
+        if (col < p.N) C[rbase[i][r] + col] = (TC)acc[i][j][r];
       }
     }
 }
@@ -530,17 +559,17 @@ static hipError_t planes_persist_shape(int bm, int bn, const PlanesLaunch& g, hi
 }
 
 template <int NP, typename TC>
-static hipError_t planes_shape(int bm, int bn, const PlanesLaunch& g, hipStream_t s) {
+static hipError_t planes_shape(int bm, int bn, int bk, const PlanesLaunch& g, hipStream_t s) {
   dim3 grid((unsigned)g.ntiles), block(256);
-#define BST_PS(BM_, BN_)                                                                        \
-  if (bm == BM_ && bn == BN_) {                                                                 \
-    hipLaunchKernelGGL((gemm_planes_kernel<NP, TC, BM_, BN_>), grid, block, 0, s, g.tiles, g.probs, \
-                       g.segs, g.ptrs, g.rowmap);                                               \
+#define BST_PS(BM_, BN_, BK_)                                                                   \
+  if (bm == BM_ && bn == BN_ && bk == BK_) {                                                    \
+    hipLaunchKernelGGL((gemm_planes_kernel<NP, TC, BM_, BN_, BK_>), grid, block, 0, s, g.tiles,  \
+                       g.probs, g.segs, g.ptrs, g.rowmap);                                      \
     return hipGetLastError();                                                                   \
   }
-  BST_PS(64, 64) BST_PS(32, 32)
+  BST_PS(64, 64, 32) BST_PS(32, 32, 32)
   if constexpr (NP == 2) {
-    BST_PS(128, 64) BST_PS(64, 128) BST_PS(128, 128)
+    BST_PS(128, 64, 32) BST_PS(64, 128, 32) BST_PS(128, 128, 32)
   }
 #undef BST_PS
   return hipErrorInvalidValue;
@@ -560,10 +589,13 @@ hipError_t launch_gemm_planes(const PlanesLaunch& g, hipStream_t s) {
     return g.tc == ElemType::F64 ? planes_persist_shape<3, double>(bm, bn, g, s)
                                  : planes_persist_shape<3, float>(bm, bn, g, s);
   }
+  const int bk = 32;   // 64-deep k steps (1 or 2 workgroups per CU) measured slower
   if (g.np == 2)
-    return g.tc == ElemType::F64 ? planes_shape<2, double>(bm, bn, g, s) : planes_shape<2, float>(bm, bn, g, s);
+    return g.tc == ElemType::F64 ? planes_shape<2, double>(bm, bn, bk, g, s)
+                                 : planes_shape<2, float>(bm, bn, bk, g, s);
   if (g.np == 3)
-    return g.tc == ElemType::F64 ? planes_shape<3, double>(bm, bn, g, s) : planes_shape<3, float>(bm, bn, g, s);
+    return g.tc == ElemType::F64 ? planes_shape<3, double>(bm, bn, bk, g, s)
+                                 : planes_shape<3, float>(bm, bn, bk, g, s);
   return hipErrorInvalidValue;
 }
 
