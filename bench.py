@@ -39,7 +39,7 @@ WORKLOAD = 5
 # 16 hex digits of that file's sha256; any change reports traffic as null.
 TRAFFIC = {
     "gs_update": {"bytes_per_launch": 8.628e8, "src": "paper_2401_01921_amd/csrc/kernels_aux.hip",
-                  "src_sha": "ed897df6a056af0b",
+                  "src_sha": "955242ecbd099984",
                   "profile": "profiles/hbm_traffic_lanczos40-spin1-chi4096.md"},
 }
 
