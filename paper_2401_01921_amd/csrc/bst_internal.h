@@ -78,12 +78,24 @@ std::unique_ptr<TensorDesc> make_tensor(std::vector<LegDesc> legs);
 // ------------------------------------------------------------------------
 // One K-segment of a grouped-GEMM problem.  A is [M x K] row-major with
 // leading dim lda; B is [K x N] (ldb) or, for transposed-B steps, [N x K].
+// For bfloat16-plane operands these are planar positions (see plane_at).
 struct GemmSeg {
   int64_t a_off, b_off;
   int32_t a_buf, b_buf;
   int32_t K, lda, ldb, pad;
-  int64_t a_ps, b_ps;   // plane strides (elements) of bfloat16 plane operands
 };
+
+// bfloat16 planes of a split operand are interleaved by 8-element chunks.
+// An operand is laid out by planar positions (block offset + row * ld + k,
+// ld a multiple of 32); with np planes, plane q of position pos is stored
+// at element
+//   np * (pos - pos % 8) + 8 * q + pos % 8,
+// so one 32-deep k step of one row, all planes, is 64 * np contiguous
+// bytes: a whole 128-byte line for np = 2 (rows start on 32-element bounds),
+// which the memory system fetches as one request instead of two.
+__host__ __device__ constexpr int64_t plane_at(int np, int64_t pos, int q) {
+  return np * (pos - (pos & 7)) + 8 * q + (pos & 7);
+}
 // One output block: C[M x N] row-major (ldc) = sum over its segments.
 struct GemmProb {
   int64_t c_off;
@@ -127,15 +139,14 @@ struct HTask {
   int32_t nin, nout;
   int32_t plane_begin;       // nin input planes then nout output planes
   int32_t in_buf, out_buf;
-  int64_t out_ps;            // plane stride of a bfloat16-plane output
 };
 
 // Conversion of float64 blocks into bfloat16 planes with rows padded to a
-// multiple of 8 elements (16 bytes): out[q][out_off + r*out_ld + c] for
-// r < rows, c < out_ld (zero beyond cols).  With transpose set, the block
+// multiple of 32 elements: plane q of position out_off + r*out_ld + c (see
+// plane_at) for r < rows, c < out_ld (zero beyond cols).  With transpose set, the block
 // [rows x cols] is written as [cols x rows] (rows padded instead).
 struct SplitJob {
-  int64_t in_off, out_off, out_ps;
+  int64_t in_off, out_off;
   int32_t in_buf, out_buf;
   int32_t rows, cols, out_ld, transpose;
 };
@@ -164,7 +175,9 @@ enum class ElemType : int { F64 = 0, F32 = 1 };
 struct TileShape {
   int bm, bn;
   int direct = 0;   // 1: LDS-free kernel (fragments loaded straight from memory);
-                    // 2: persistent LDS kernel (fixed grid walking the tile list)
+                    // 3: pipelined persistent kernel on a k-step schedule (planes only)
+  int stages = 0;   // kind 3: LDS stages (copies run stages - 1 k-steps ahead)
+  int waves = 4;    // kind 3: waves per workgroup (4: 2 x 2; 8: 2 x 4, or 4 x 2 when bm > bn)
 };
 // Tile shapes compiled for each arithmetic form.
 const std::vector<TileShape>& gemm_tile_shapes(bst_precision form);
@@ -216,8 +229,8 @@ struct SplitLaunch {
 };
 hipError_t launch_split(const SplitLaunch& l, hipStream_t s);
 
-// Grouped GEMM on pre-split bfloat16 planes: A [M x K] and B [N x K], both
-// with K contiguous, rows padded to 8 elements, float32 accumulate.
+// Grouped GEMM on pre-split bfloat16 planes (layout: plane_at): A [M x K]
+// and B [N x K], both with K contiguous, float32 accumulate.
 struct PlanesLaunch {
   int np;                      // 2 (BF16X3) or 3 (BF16X6)
   ElemType tc;
@@ -231,7 +244,53 @@ struct PlanesLaunch {
 };
 const std::vector<TileShape>& gemm_planes_shapes(int np);
 hipError_t launch_gemm_planes(const PlanesLaunch& g, hipStream_t s);
-hipError_t launch_gemm_direct_planes(const PlanesLaunch& g, int bm, int bn, hipStream_t s);
+
+// Pipelined plane GEMM (kernels_stream.hip).  The host lists, for every
+// workgroup of a fixed grid, the 32-deep k-steps of the output tiles it
+// owns, one 48-byte record per step, the steps of a tile consecutive.
+// A tile row r < rows reads plane q of A at planar position a + r*lda + k, B likewise;
+// chunks of 8 k at or past kch read as zero and chunk kch-1 holds kval valid
+// elements.  The last step of a tile writes it: row r, column j to
+// C[c + r*ldc + j] or, row-mapped, to C[rowtab[c + r] + j] (entries < 0
+// skipped), for j < cols.
+struct KStep {
+  int64_t a, b;           // element offsets (plane 0) of tile row 0 at this k
+  int32_t lda, ldb;
+  uint8_t rows1, cols1;   // valid tile rows / columns minus one (0..bm-1, 0..bn-1)
+  uint8_t kch;            // 8-element k chunks read from memory (0..4)
+  uint8_t flags;          // kStepFirst | kStepLast | kStepRowmap
+  uint8_t kval, pad;      // valid elements of chunk kch - 1 (1..8)
+  uint16_t c_buf;         // pointer-table slots of C, A and B
+  int64_t c;              // C offset of (row 0, col 0), or rowtab index of row 0
+  int32_t ldc;
+  uint16_t a_buf, b_buf;
+};
+static_assert(sizeof(KStep) == 48, "k-step record is 48 bytes");
+constexpr int kStepFirst = 1, kStepLast = 2, kStepRowmap = 4;
+constexpr int kStepBatch = 16;   // records copied into LDS per batch
+constexpr int kStepRing = 3;     // batches resident in LDS
+// LDS bytes of one workgroup of the pipelined kernel and workgroups per CU
+constexpr int stream_lds_bytes(int np, int bm, int bn, int stages) {
+  return stages * (bm + bn) * np * 64 + kStepRing * kStepBatch * 48 + stages * bm * 8;
+}
+constexpr int stream_wgs_per_cu(int np, int bm, int bn, int stages) {
+  return 163840 / stream_lds_bytes(np, bm, bn, stages) < 1   ? 1
+         : 163840 / stream_lds_bytes(np, bm, bn, stages) > 4 ? 4
+                                                             : 163840 / stream_lds_bytes(np, bm, bn, stages);
+}
+constexpr int kStreamCUs = 256;   // compute units the schedule is balanced for
+
+struct StreamLaunch {
+  int np;
+  ElemType tc;
+  int tile;                       // index into gemm_planes_shapes(np), a kind-3 shape
+  const KStep* steps;             // padded with kStepBatch records past the last
+  const int64_t* wg_begin;        // nwg + 1 entries
+  int64_t nwg;
+  void* const* ptrs;
+  const int64_t* rowtab;          // row offsets of row-mapped tiles (bm per tile)
+};
+hipError_t launch_gemm_planes_stream(const StreamLaunch& g, hipStream_t s);
 
 struct HApplyLaunch {
   int np = 0;                  // > 0: outputs written as np bfloat16 planes

@@ -85,9 +85,12 @@ bool step_runs(const PlanData& P, const Step& st, bst_precision prec, bool skip_
 // Tile-choice key of the bfloat16-plane GEMM variant of a form.
 static int planes_key(bst_precision prec) { return 10 + (int)prec; }
 
+// LDS-staged 64x64: the default, and the fallback of the pipelined shapes
+constexpr int kPlanesDefaultTile = 0;
+
 int planes_tile(const Step& st, bst_precision prec) {
   auto it = st.tile_choice.find(planes_key(prec));
-  return it == st.tile_choice.end() ? 4 : it->second;   // default: LDS-staged 64x64
+  return it == st.tile_choice.end() ? kPlanesDefaultTile : it->second;
 }
 
 void run_steps_impl(PlanData& P, void* ws, void* const* dptrs, bst_precision prec, hipStream_t s,
@@ -117,6 +120,24 @@ void run_steps_impl(PlanData& P, void* ws, void* const* dptrs, bst_precision pre
           g.np = np;
           g.tc = st.tc == Elem::Inter ? ElemType::F32 : ElemType::F64;
           g.tile = planes_tile(st, prec);
+          if (gemm_planes_shapes(np)[g.tile].direct == 3) {
+            auto sit = st.streams_alt.find(np * 64 + g.tile);
+            if (sit != st.streams_alt.end() && sit->second.ok) {
+              const auto& L = sit->second;
+              StreamLaunch sl{};
+              sl.np = np;
+              sl.tc = g.tc;
+              sl.tile = g.tile;
+              sl.steps = reinterpret_cast<const KStep*>(blob + L.steps_off);
+              sl.wg_begin = reinterpret_cast<const int64_t*>(blob + L.begin_off);
+              sl.nwg = L.nwg;
+              sl.ptrs = dptrs;
+              sl.rowtab = reinterpret_cast<const int64_t*>(blob + L.rows_off);
+              e = launch_gemm_planes_stream(sl, s);
+              break;
+            }
+            g.tile = kPlanesDefaultTile;   // problems outside the kernel's layout rules
+          }
           const auto& sh = gemm_planes_shapes(np)[g.tile];
           auto it = st.tile_lists_alt.find({sh.bm, sh.bn});
           if (it == st.tile_lists_alt.end()) fail(BST_E_INVALID, "internal: missing tile list");
@@ -236,30 +257,39 @@ static std::string tune_key(const PlanData& P, const Step& st, bst_precision for
   return os.str();
 }
 
-static std::map<std::string, std::pair<int, int>> load_cache(const char* path) {
-  std::map<std::string, std::pair<int, int>> m;
+// A cached tile choice: the shape's fields (kind and stages may be absent
+// in older files: kind 0).
+struct CachedShape {
+  int bm = 0, bn = 0, direct = 0, stages = 0;
+  bool matches(const TileShape& s) const {
+    return s.bm == bm && s.bn == bn && s.direct == direct && s.stages == stages;
+  }
+};
+
+static std::map<std::string, CachedShape> load_cache(const char* path) {
+  std::map<std::string, CachedShape> m;
   std::ifstream f(path);
   std::string line;
-  // one entry per line: "key": [bm, bn],
+  // one entry per line: "key": [bm, bn, kind, stages],
   while (std::getline(f, line)) {
     auto q1 = line.find('"');
     auto q2 = line.find('"', q1 + 1);
     auto b1 = line.find('[');
     if (q1 == std::string::npos || q2 == std::string::npos || b1 == std::string::npos) continue;
-    int bm = 0, bn = 0;
-    if (std::sscanf(line.c_str() + b1, "[%d, %d]", &bm, &bn) == 2)
-      m[line.substr(q1 + 1, q2 - q1 - 1)] = {bm, bn};
+    CachedShape c;
+    if (std::sscanf(line.c_str() + b1, "[%d, %d, %d, %d]", &c.bm, &c.bn, &c.direct, &c.stages) >= 2)
+      m[line.substr(q1 + 1, q2 - q1 - 1)] = c;
   }
   return m;
 }
 
-static void save_cache(const char* path, const std::map<std::string, std::pair<int, int>>& m) {
+static void save_cache(const char* path, const std::map<std::string, CachedShape>& m) {
   std::ofstream f(path);
   f << "{\n";
   size_t i = 0;
   for (const auto& kv : m) {
-    f << "  \"" << kv.first << "\": [" << kv.second.first << ", " << kv.second.second << "]"
-      << (++i < m.size() ? "," : "") << "\n";
+    f << "  \"" << kv.first << "\": [" << kv.second.bm << ", " << kv.second.bn << ", " << kv.second.direct
+      << ", " << kv.second.stages << "]" << (++i < m.size() ? "," : "") << "\n";
   }
   f << "}\n";
 }
@@ -276,8 +306,7 @@ void apply_tune_cache(PlanData& P) {
       if (it == m.end()) continue;
       const auto& shapes = f >= 10 ? gemm_planes_shapes(f == 13 ? 3 : 2) : gemm_tile_shapes((bst_precision)f);
       for (size_t i = 0; i < shapes.size(); ++i)
-        if (shapes[i].bm == it->second.first && shapes[i].bn == it->second.second)
-          st.tile_choice[f] = (int)i;
+        if (it->second.matches(shapes[i])) st.tile_choice[f] = (int)i;
     }
   }
 }
@@ -386,7 +415,7 @@ bst_status bst_plan_autotune(bst_plan* p, const void* const* in, void* const* ou
   check_hip(hipEventCreate(&e0), "event");
   check_hip(hipEventCreate(&e1), "event");
   const char* path = std::getenv("BST_TUNE_CACHE");
-  auto cache = path ? load_cache(path) : std::map<std::string, std::pair<int, int>>{};
+  auto cache = path ? load_cache(path) : std::map<std::string, CachedShape>{};
   const bst_precision form = P.prec;
   for (size_t k = 0; k < P.steps.size(); ++k) {
     Step& st = P.steps[k];
@@ -413,7 +442,8 @@ bst_status bst_plan_autotune(bst_plan* p, const void* const* in, void* const* ou
       }
     }
     st.tile_choice[key] = best_i;
-    cache[tune_key(P, st, (bst_precision)key)] = {shapes[best_i].bm, shapes[best_i].bn};
+    const TileShape& bs = shapes[best_i];
+    cache[tune_key(P, st, (bst_precision)key)] = {bs.bm, bs.bn, bs.direct, bs.stages};
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

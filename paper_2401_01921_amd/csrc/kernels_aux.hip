@@ -229,12 +229,12 @@ __global__ __launch_bounds__(256) void happly_sparse_kernel(const HTask* __restr
       const float r1 = yf - __uint_as_float((unsigned int)h0 << 16);
       u = __float_as_uint(r1);
       const unsigned short h1 = (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
-      out[at] = h0;
-      out[t.out_ps + at] = h1;
+      out[plane_at(NP, at, 0)] = h0;
+      out[plane_at(NP, at, 1)] = h1;
       if constexpr (NP == 3) {
         const float r2 = r1 - __uint_as_float((unsigned int)h1 << 16);
         u = __float_as_uint(r2);
-        out[2 * t.out_ps + at] = (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+        out[plane_at(NP, at, 2)] = (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
       }
     }
   }

@@ -114,125 +114,6 @@ __global__ __launch_bounds__(256) void gemm_direct_kernel(const GemmTile* __rest
       }
 }
 
-template <int NP, typename TC, int BM, int BN>
-__global__ __launch_bounds__(256) void gemm_direct_planes_kernel(const GemmTile* __restrict__ tiles,
-                                                                 const GemmProb* __restrict__ probs,
-                                                                 const GemmSeg* __restrict__ segs,
-                                                                 void* const* __restrict__ ptrs,
-                                                                 const int64_t* __restrict__ rowmap) {
-  constexpr int WM = BM / 2, WN = BN / 2, SM = WM / 16, SN = WN / 16;
-  const GemmTile t = tiles[blockIdx.x];
-  if (t.prob < 0) return;   // padding of the per-XCD tile lists
-  const GemmProb p = probs[t.prob];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
-  const int r16 = lane & 15, g8 = 8 * (lane >> 4);
-  const int rbase = t.m0 + wm * WM + r16, cbase = t.n0 + wn * WN + r16;
-
-  flt4 acc[SM][SN];
-#pragma unroll
-  for (int i = 0; i < SM; ++i)
-#pragma unroll
-    for (int j = 0; j < SN; ++j) acc[i][j] = flt4{0, 0, 0, 0};
-
-  us8 a0[NP][SM], b0[NP][SN], a1[NP][SM], b1[NP][SN];
-  int cs = 0, ck = 0;
-  const int nseg = p.seg_count;
-  const us8 z8 = {0, 0, 0, 0, 0, 0, 0, 0};
-
-  auto load = [&](us8 (&a)[NP][SM], us8 (&b)[NP][SN]) {
-    const GemmSeg sg = segs[p.seg_begin + cs];
-    const BST_G unsigned short* __restrict__ A = (const BST_G unsigned short*)(ptrs[sg.a_buf]) + sg.a_off;
-    const BST_G unsigned short* __restrict__ B = (const BST_G unsigned short*)(ptrs[sg.b_buf]) + sg.b_off;
-    const int kv = ck + g8;
-    const bool kin = kv < sg.K, kedge = kv + 8 > sg.K;
-#pragma unroll
-    for (int i = 0; i < SM; ++i) {
-      const int r = rbase + i * 16;
-      const bool ok = kin && r < p.M;
-#pragma unroll
-      for (int q = 0; q < NP; ++q) {
-        us8 x = ok ? *reinterpret_cast<const BST_G us8*>(A + q * sg.a_ps + (int64_t)r * sg.lda + kv) : z8;
-        if (ok && kedge) {
-#pragma unroll
-          for (int e = 0; e < 8; ++e)
-            if (kv + e >= sg.K) x[e] = 0;
-        }
-        a[q][i] = x;
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < SN; ++j) {
-      const int c = cbase + j * 16;
-      const bool ok = kin && c < p.N;
-#pragma unroll
-      for (int q = 0; q < NP; ++q) {
-        us8 x = ok ? *reinterpret_cast<const BST_G us8*>(B + q * sg.b_ps + (int64_t)c * sg.ldb + kv) : z8;
-        if (ok && kedge) {
-#pragma unroll
-          for (int e = 0; e < 8; ++e)
-            if (kv + e >= sg.K) x[e] = 0;
-        }
-        b[q][j] = x;
-      }
-    }
-    ck += 32;
-    if (ck >= sg.K) {
-      cs++;
-      ck = 0;
-    }
-  };
-  auto compute = [&](us8 (&a)[NP][SM], us8 (&b)[NP][SN]) {
-#pragma unroll
-    for (int i = 0; i < SM; ++i)
-#pragma unroll
-      for (int j = 0; j < SN; ++j) {
-        if constexpr (NP == 3) {
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a[2][i]),
-                                                              __builtin_bit_cast(bf16x8, b[0][j]), acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a[1][i]),
-                                                              __builtin_bit_cast(bf16x8, b[1][j]), acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a[0][i]),
-                                                              __builtin_bit_cast(bf16x8, b[2][j]), acc[i][j], 0, 0, 0);
-        }
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a[1][i]),
-                                                            __builtin_bit_cast(bf16x8, b[0][j]), acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a[0][i]),
-                                                            __builtin_bit_cast(bf16x8, b[1][j]), acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a[0][i]),
-                                                            __builtin_bit_cast(bf16x8, b[0][j]), acc[i][j], 0, 0, 0);
-      }
-  };
-  if (nseg > 0) {
-    load(a0, b0);
-    while (true) {
-      const bool h1 = cs < nseg;
-      if (h1) load(a1, b1);
-      compute(a0, b0);
-      if (!h1) break;
-      const bool h0 = cs < nseg;
-      if (h0) load(a0, b0);
-      compute(a1, b1);
-      if (!h0) break;
-    }
-  }
-  BST_G TC* __restrict__ C = (BST_G TC*)(ptrs[p.c_buf]);
-#pragma unroll
-  for (int i = 0; i < SM; ++i)
-#pragma unroll
-    for (int j = 0; j < SN; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = t.m0 + wm * WM + i * 16 + 4 * (lane >> 4) + r;
-        const int col = t.n0 + wn * WN + j * 16 + r16;
-        if (row < p.M && col < p.N) {
-          const int64_t rbase =
-              p.rowmap1 > 0 ? rowmap[p.rowmap1 - 1 + row] : p.c_off + (int64_t)row * p.ldc;
-          C[rbase + col] = (TC)acc[i][j][r];
-        }
-      }
-}
-
 // ---------------------------------------------------------------- launchers
 template <int FORM, typename TA, typename TC, bool TRANSB>
 hipError_t direct_shape(int bm, int bn, const GemmLaunch& g, hipStream_t s) {
@@ -263,31 +144,6 @@ hipError_t launch_gemm_direct(const GemmLaunch& g, int bm, int bn, hipStream_t s
     if (a64 && !c64 && !g.transb) return direct_shape<BST_FP32, double, float, false>(bm, bn, g, s);
     if (!a64 && c64 && g.transb) return direct_shape<BST_FP32, float, double, true>(bm, bn, g, s);
   }
-  return hipErrorInvalidValue;
-}
-
-template <int NP, typename TC>
-hipError_t direct_planes_shape(int bm, int bn, const PlanesLaunch& g, hipStream_t s) {
-  dim3 grid((unsigned)g.ntiles), block(256);
-#define BST_DP(BM_, BN_)                                                                        \
-  if (bm == BM_ && bn == BN_) {                                                                 \
-    hipLaunchKernelGGL((gemm_direct_planes_kernel<NP, TC, BM_, BN_>), grid, block, 0, s, g.tiles, \
-                       g.probs, g.segs, g.ptrs, g.rowmap);                                      \
-    return hipGetLastError();                                                                   \
-  }
-  BST_DP(64, 64) BST_DP(128, 64) BST_DP(64, 128) BST_DP(32, 32)
-#undef BST_DP
-  return hipErrorInvalidValue;
-}
-
-hipError_t launch_gemm_direct_planes(const PlanesLaunch& g, int bm, int bn, hipStream_t s) {
-  if (g.ntiles <= 0) return hipSuccess;
-  if (g.np == 2)
-    return g.tc == ElemType::F64 ? direct_planes_shape<2, double>(bm, bn, g, s)
-                                 : direct_planes_shape<2, float>(bm, bn, g, s);
-  if (g.np == 3)
-    return g.tc == ElemType::F64 ? direct_planes_shape<3, double>(bm, bn, g, s)
-                                 : direct_planes_shape<3, float>(bm, bn, g, s);
   return hipErrorInvalidValue;
 }
 

@@ -5,8 +5,9 @@
 // Splitting once per operand instead of once per tile load removes the
 // redundant conversions (each element of A is otherwise re-split for every
 // N-tile) and halves the bytes the GEMM streams (4 or 6 bytes instead of 8).
-// Plane rows are padded to 8 elements so that every tile row is a whole
-// number of 16-byte vectors.
+// Planes are interleaved by 8-element chunks (plane_at) and operand rows
+// padded to 32 elements, so that one 32-deep k step of a row, all planes,
+// is one contiguous run of 16-byte vectors (a 128-byte line for two planes).
 #include "bst_internal.h"
 
 namespace bst {
@@ -51,7 +52,7 @@ __global__ __launch_bounds__(256) void split_kernel(const SplitJob* __restrict__
   const SplitWork w = work[blockIdx.x];
   const SplitJob j = jobs[w.job];
   const BST_G double* __restrict__ in = (const BST_G double*)(ptrs[j.in_buf]) + j.in_off;
-  BST_G unsigned short* __restrict__ out = (BST_G unsigned short*)(ptrs[j.out_buf]) + j.out_off;
+  BST_G unsigned short* __restrict__ out = (BST_G unsigned short*)(ptrs[j.out_buf]);
   const int tid = threadIdx.x;
   const int orow = tid >> 3, ocol = (tid & 7) * 8;   // 32 rows x 8 vectors per pass
   if (!j.transpose) {
@@ -69,9 +70,9 @@ __global__ __launch_bounds__(256) void split_kernel(const SplitJob* __restrict__
 #pragma unroll
           for (int q = 0; q < NP; ++q) h[q][e] = t[q];
         }
+        const int64_t pos = j.out_off + (int64_t)r * j.out_ld + c;   // a multiple of 8
 #pragma unroll
-        for (int q = 0; q < NP; ++q)
-          *reinterpret_cast<BST_G us8*>(out + q * j.out_ps + (int64_t)r * j.out_ld + c) = h[q];
+        for (int q = 0; q < NP; ++q) *reinterpret_cast<BST_G us8*>(out + plane_at(NP, pos, q)) = h[q];
       }
     }
     return;
@@ -96,9 +97,9 @@ __global__ __launch_bounds__(256) void split_kernel(const SplitJob* __restrict__
 #pragma unroll
         for (int q = 0; q < NP; ++q) h[q][e] = t[q];
       }
+      const int64_t pos = j.out_off + (int64_t)gc * j.out_ld + gr;   // a multiple of 8
 #pragma unroll
-      for (int q = 0; q < NP; ++q)
-        *reinterpret_cast<BST_G us8*>(out + q * j.out_ps + (int64_t)gc * j.out_ld + gr) = h[q];
+      for (int q = 0; q < NP; ++q) *reinterpret_cast<BST_G us8*>(out + plane_at(NP, pos, q)) = h[q];
     }
   }
 }
@@ -118,27 +119,26 @@ hipError_t launch_split(const SplitLaunch& l, hipStream_t s) {
 // ------------------------------------------------------------------------
 // Grouped GEMM on bfloat16 planes: C[M x N] = sum_seg A[M x K] B[N x K]^T
 // ------------------------------------------------------------------------
-// LDS tile rows hold one 32-deep k step: 64 bytes, four 16-byte chunks.
-// Chunk c of row r is stored at chunk c ^ ((r >> 2) & 3), so that the 16
-// rows one MFMA operand read touches (same chunk) and the 4 rows x 4 chunks
-// one 16-lane group stores fall on 16 distinct 4-bank groups.
-__device__ __forceinline__ int lds_chunk(int r, int c) { return r * 32 + ((c ^ ((r >> 2) & 3)) << 3); }
-// The same for rows of CH chunks (CH = 4: lds_chunk; CH = 8: 128-byte rows,
-// chunk c of row r at c ^ ((r >> 1) & 7), again conflict-free for 16 rows of
-// one chunk and for the 2 rows x 8 chunks of a 16-lane store).
-template <int CH>
-__device__ __forceinline__ int lds_at(int r, int c) {
-  if constexpr (CH == 4) return lds_chunk(r, c);
-  return r * 64 + ((c ^ ((r >> 1) & 7)) << 3);
+// An LDS operand row holds one 32-deep k step of all NP planes: NC = 4 * NP
+// 16-byte pieces, piece cc = chunk * NP + plane, in the order of the
+// interleaved global layout.  Piece cc of row r sits at position swz(r, cc),
+// an involution for a fixed r that spreads the 16 rows one MFMA operand
+// read touches (same cc) over distinct bank groups; a row's pieces are
+// stored by consecutive lanes.
+template <int NP>
+__device__ __forceinline__ int swz(int r, int cc) {
+  if constexpr (NP == 2) return cc ^ ((r >> 1) & 7);
+  return (cc & ~3) | ((cc ^ (r >> 1)) & 3);
 }
 
-// Tile shapes per plane count (double-buffered LDS: 80 KB at 128x128, two planes).
-// Direct (LDS-free) variants first: index 0 is the default.
-static const std::vector<TileShape> kPlaneShapes2 = {{64, 64, 1}, {128, 64, 1}, {64, 128, 1}, {32, 32, 1},
-                                                     {64, 64, 0}, {128, 64, 0}, {64, 128, 0}, {32, 32, 0},
-                                                     {128, 128, 0}, {128, 128, 2}, {64, 64, 2}};
-static const std::vector<TileShape> kPlaneShapes3 = {{64, 64, 1}, {128, 64, 1}, {64, 128, 1}, {32, 32, 1},
-                                                     {64, 64, 0}, {32, 32, 0}, {64, 64, 2}};
+// Tile shapes per plane count: the LDS-staged kernel (index 0, 64x64, is
+// the default) and the pipelined kernel (kind 3, kernels_stream.hip).
+static const std::vector<TileShape> kPlaneShapes2 = {
+    {64, 64, 0},         {128, 64, 0},        {64, 128, 0},       {32, 32, 0},     {128, 128, 0},
+    {128, 64, 3, 3, 4},  {64, 128, 3, 3, 4},  {128, 128, 3, 3, 8}, {128, 256, 3, 3, 8},
+    {256, 128, 3, 3, 8}, {256, 64, 3, 3, 8}};
+static const std::vector<TileShape> kPlaneShapes3 = {{64, 64, 0}, {32, 32, 0}, {64, 64, 3, 3, 4},
+                                                     {128, 128, 3, 3, 8}};
 const std::vector<TileShape>& gemm_planes_shapes(int np) { return np == 3 ? kPlaneShapes3 : kPlaneShapes2; }
 
 template <int NP, typename TC, int BM, int BN, int BK>
@@ -148,11 +148,12 @@ __global__ __launch_bounds__(256) void gemm_planes_kernel(const GemmTile* __rest
                                                           void* const* __restrict__ ptrs,
                                                           const int64_t* __restrict__ rowmap) {
   // LDS row: one BK-deep k step (64 or 128 bytes), 16-byte chunks swizzled
-  constexpr int LDR = BK, CH = BK / 8;
+  constexpr int CH = BK / 8, NC = NP * CH;   // 16-byte pieces per row and k step
   constexpr int WM = BM / 2, WN = BN / 2, SM = WM / 16, SN = WN / 16;
-  constexpr int NVA = (BM * CH + 255) / 256, NVB = (BN * CH + 255) / 256;   // 16-byte vectors per thread
-  __shared__ __attribute__((aligned(16))) unsigned short As[2][NP][BM * LDR];
-  __shared__ __attribute__((aligned(16))) unsigned short Bs[2][NP][BN * LDR];
+  constexpr int NVA = (BM * NC + 255) / 256, NVB = (BN * NC + 255) / 256;   // pieces per thread
+  static_assert(BK == 32, "one 32-deep k step per LDS row");
+  __shared__ __attribute__((aligned(16))) unsigned short As[2][BM * NC * 8];
+  __shared__ __attribute__((aligned(16))) unsigned short Bs[2][BN * NC * 8];
 
   const GemmTile t = tiles[blockIdx.x];
   if (t.prob < 0) return;   // padding of the per-XCD tile lists
@@ -169,9 +170,11 @@ __global__ __launch_bounds__(256) void gemm_planes_kernel(const GemmTile* __rest
 
   // Loads only issue the 16-byte reads; rows past M / N and k past the
   // segment's K are zeroed when the registers go to LDS (after the MFMAs),
-  // so no wait for the data sits between the loads.
-  us8 ra[NP][NVA], rb[NP][NVB];
-  int na[NVA], nb[NVB];   // valid k elements of each vector (0..8)
+  // so no wait for the data sits between the loads.  Piece e of a row's
+  // k step is chunk e / NP of plane e % NP: consecutive lanes read one
+  // contiguous run (plane_at), NC pieces per row.
+  us8 ra[NVA], rb[NVB];
+  int na[NVA], nb[NVB];   // valid k elements of each piece (0..8)
 
   // cursor of the next k-step to load: segment ls (cached), offset lk
   int ls = 0, lk = 0;
@@ -180,64 +183,58 @@ __global__ __launch_bounds__(256) void gemm_planes_kernel(const GemmTile* __rest
   const BST_G unsigned short* lB = nullptr;
   auto set_seg = [&]() {
     lg = segs[p.seg_begin + ls];
-    lA = (const BST_G unsigned short*)(ptrs[lg.a_buf]) + lg.a_off;
-    lB = (const BST_G unsigned short*)(ptrs[lg.b_buf]) + lg.b_off;
+    lA = (const BST_G unsigned short*)(ptrs[lg.a_buf]);
+    lB = (const BST_G unsigned short*)(ptrs[lg.b_buf]);
   };
   auto load = [&]() {
 #pragma unroll
     for (int v = 0; v < NVA; ++v) {
       const int idx = tid + v * 256;
-      const int r = idx / CH, kv = lk + (idx % CH) * 8;
+      const int r = idx / NC, e = idx % NC;
+      const int kv = lk + (e / NP) * 8;
       const int gr = m0 + r;
-      const bool ok = (idx < BM * CH) && gr < p.M && kv < lg.K;
+      const bool ok = (idx < BM * NC) && gr < p.M && kv < lg.K;
       na[v] = ok ? min(8, lg.K - kv) : 0;
-      if (ok) {
-#pragma unroll
-        for (int q = 0; q < NP; ++q)
-          ra[q][v] = *reinterpret_cast<const BST_G us8*>(lA + q * lg.a_ps + (int64_t)gr * lg.lda + kv);
-      }
+      if (ok)
+        ra[v] = *reinterpret_cast<const BST_G us8*>(
+            lA + plane_at(NP, lg.a_off + (int64_t)gr * lg.lda + kv, e % NP));
     }
 #pragma unroll
     for (int v = 0; v < NVB; ++v) {
       const int idx = tid + v * 256;
-      const int r = idx / CH, kv = lk + (idx % CH) * 8;
+      const int r = idx / NC, e = idx % NC;
+      const int kv = lk + (e / NP) * 8;
       const int gn = n0 + r;
-      const bool ok = (idx < BN * CH) && gn < p.N && kv < lg.K;
+      const bool ok = (idx < BN * NC) && gn < p.N && kv < lg.K;
       nb[v] = ok ? min(8, lg.K - kv) : 0;
-      if (ok) {
-#pragma unroll
-        for (int q = 0; q < NP; ++q)
-          rb[q][v] = *reinterpret_cast<const BST_G us8*>(lB + q * lg.b_ps + (int64_t)gn * lg.ldb + kv);
-      }
+      if (ok)
+        rb[v] = *reinterpret_cast<const BST_G us8*>(
+            lB + plane_at(NP, lg.b_off + (int64_t)gn * lg.ldb + kv, e % NP));
     }
   };
   auto store = [&](int buf) {
 #pragma unroll
     for (int v = 0; v < NVA; ++v) {
       const int idx = tid + v * 256;
-      if (idx < BM * CH) {
+      if (idx < BM * NC) {
+        const int r = idx / NC, e = idx % NC;
+        us8 x = ra[v];
 #pragma unroll
-        for (int q = 0; q < NP; ++q) {
-          us8 x = ra[q][v];
-#pragma unroll
-          for (int e = 0; e < 8; ++e)
-            if (e >= na[v]) x[e] = 0;
-          *reinterpret_cast<us8*>(&As[buf][q][lds_at<CH>(idx / CH, idx % CH)]) = x;
-        }
+        for (int k = 0; k < 8; ++k)
+          if (k >= na[v]) x[k] = 0;
+        *reinterpret_cast<us8*>(&As[buf][r * NC * 8 + swz<NP>(r, e) * 8]) = x;
       }
     }
 #pragma unroll
     for (int v = 0; v < NVB; ++v) {
       const int idx = tid + v * 256;
-      if (idx < BN * CH) {
+      if (idx < BN * NC) {
+        const int r = idx / NC, e = idx % NC;
+        us8 x = rb[v];
 #pragma unroll
-        for (int q = 0; q < NP; ++q) {
-          us8 x = rb[q][v];
-#pragma unroll
-          for (int e = 0; e < 8; ++e)
-            if (e >= nb[v]) x[e] = 0;
-          *reinterpret_cast<us8*>(&Bs[buf][q][lds_at<CH>(idx / CH, idx % CH)]) = x;
-        }
+        for (int k = 0; k < 8; ++k)
+          if (k >= nb[v]) x[k] = 0;
+        *reinterpret_cast<us8*>(&Bs[buf][r * NC * 8 + swz<NP>(r, e) * 8]) = x;
       }
     }
   };
@@ -272,12 +269,12 @@ __global__ __launch_bounds__(256) void gemm_planes_kernel(const GemmTile* __rest
 #pragma unroll
         for (int i = 0; i < SM; ++i) {
           const int r = wm * WM + i * 16 + (lane & 15);
-          a[q][i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const us8*>(&As[buf][q][lds_at<CH>(r, kc)]));
+          a[q][i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const us8*>(&As[buf][r * NC * 8 + swz<NP>(r, kc * NP + q) * 8]));
         }
 #pragma unroll
         for (int j = 0; j < SN; ++j) {
           const int c = wn * WN + j * 16 + (lane & 15);
-          b[q][j] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const us8*>(&Bs[buf][q][lds_at<CH>(c, kc)]));
+          b[q][j] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const us8*>(&Bs[buf][c * NC * 8 + swz<NP>(c, kc * NP + q) * 8]));
         }
       }
 #pragma unroll
@@ -326,238 +323,6 @@ __global__ __launch_bounds__(256) void gemm_planes_kernel(const GemmTile* __rest
     }
 }
 
-// Persistent variant: a fixed grid (a multiple of 8, so that block b stays
-// on XCD b % 8 with the tiles the host placed there) walks the tile list
-// with stride gridDim.x.  The load cursor runs one k-step ahead of the MFMA
-// across tile boundaries, so the first k-step of the next tile is in flight
-// while the current tile finishes and writes its result.
-template <int NP, typename TC, int BM, int BN>
-__global__ __launch_bounds__(256) void gemm_planes_persist_kernel(
-    const GemmTile* __restrict__ tiles, int64_t ntiles, const GemmProb* __restrict__ probs,
-    const GemmSeg* __restrict__ segs, void* const* __restrict__ ptrs,
-    const int64_t* __restrict__ rowmap) {
-  constexpr int BK = 32, LDR = BK;
-  constexpr int WM = BM / 2, WN = BN / 2, SM = WM / 16, SN = WN / 16;
-  constexpr int NVA = (BM * 4 + 255) / 256, NVB = (BN * 4 + 255) / 256;
-  __shared__ __attribute__((aligned(16))) unsigned short As[2][NP][BM * LDR];
-  __shared__ __attribute__((aligned(16))) unsigned short Bs[2][NP][BN * LDR];
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int wm = wave >> 1, wn = wave & 1;
-  const int64_t G = gridDim.x;
-  const us8 zero8 = {0, 0, 0, 0, 0, 0, 0, 0};
-
-  auto row_base = [&](const GemmProb& p, int row) -> int64_t {
-    return p.rowmap1 > 0 ? rowmap[p.rowmap1 - 1 + row] : p.c_off + (int64_t)row * p.ldc;
-  };
-  // load cursor: tile index, its problem and origin, segment and k
-  int64_t lt = (int64_t)blockIdx.x - G;
-  GemmProb lp{};
-  int lm0 = 0, ln0 = 0, ls = 0, lk = 0;
-  bool lvalid = false;
-  // moves the load cursor to the next tile with work; tiles of problems
-  // without segments are written as zeros on the way
-  auto next_tile = [&]() {
-    lvalid = false;
-    for (lt += G; lt < ntiles; lt += G) {
-      const GemmTile t = tiles[lt];
-      if (t.prob < 0) continue;
-      lp = probs[t.prob];
-      lm0 = t.m0;
-      ln0 = t.n0;
-      ls = 0;
-      lk = 0;
-      if (lp.seg_count > 0) {
-        lvalid = true;
-        return;
-      }
-      BST_G TC* __restrict__ C = (BST_G TC*)(ptrs[lp.c_buf]);
-      for (int e = tid; e < BM * BN; e += 256) {
-        const int row = lm0 + e / BN, col = ln0 + e % BN;
-        if (row < lp.M && col < lp.N) C[row_base(lp, row) + col] = (TC)0;
-      }
-    }
-  };
-  us8 ra[NP][NVA], rb[NP][NVB];
-  auto load = [&]() {
-    const GemmSeg g = segs[lp.seg_begin + ls];
-    const BST_G unsigned short* A = (const BST_G unsigned short*)(ptrs[g.a_buf]) + g.a_off;
-    const BST_G unsigned short* B = (const BST_G unsigned short*)(ptrs[g.b_buf]) + g.b_off;
-#pragma unroll
-    for (int v = 0; v < NVA; ++v) {
-      const int idx = tid + v * 256;
-      const int r = idx >> 2, kv = lk + (idx & 3) * 8;
-      const int gr = lm0 + r;
-      const bool ok = (idx < BM * 4) && gr < lp.M && kv < g.K;
-#pragma unroll
-      for (int q = 0; q < NP; ++q) {
-        us8 x = ok ? *reinterpret_cast<const BST_G us8*>(A + q * g.a_ps + (int64_t)gr * g.lda + kv) : zero8;
-        if (ok && kv + 8 > g.K) {
-#pragma unroll
-          for (int e = 0; e < 8; ++e)
-            if (kv + e >= g.K) x[e] = 0;
-        }
-        ra[q][v] = x;
-      }
-    }
-#pragma unroll
-    for (int v = 0; v < NVB; ++v) {
-      const int idx = tid + v * 256;
-      const int r = idx >> 2, kv = lk + (idx & 3) * 8;
-      const int gn = ln0 + r;
-      const bool ok = (idx < BN * 4) && gn < lp.N && kv < g.K;
-#pragma unroll
-      for (int q = 0; q < NP; ++q) {
-        us8 x = ok ? *reinterpret_cast<const BST_G us8*>(B + q * g.b_ps + (int64_t)gn * g.ldb + kv) : zero8;
-        if (ok && kv + 8 > g.K) {
-#pragma unroll
-          for (int e = 0; e < 8; ++e)
-            if (kv + e >= g.K) x[e] = 0;
-        }
-        rb[q][v] = x;
-      }
-    }
-  };
-  auto store = [&](int buf) {
-#pragma unroll
-    for (int v = 0; v < NVA; ++v) {
-      const int idx = tid + v * 256;
-      if (idx < BM * 4) {
-#pragma unroll
-        for (int q = 0; q < NP; ++q)
-          *reinterpret_cast<us8*>(&As[buf][q][lds_chunk(idx >> 2, idx & 3)]) = ra[q][v];
-      }
-    }
-#pragma unroll
-    for (int v = 0; v < NVB; ++v) {
-      const int idx = tid + v * 256;
-      if (idx < BN * 4) {
-#pragma unroll
-        for (int q = 0; q < NP; ++q)
-          *reinterpret_cast<us8*>(&Bs[buf][q][lds_chunk(idx >> 2, idx & 3)]) = rb[q][v];
-      }
-    }
-  };
-  // true when the cursor's k-step is the last one of its tile
-  auto last_step = [&]() -> bool {
-    return ls == lp.seg_count - 1 && lk + BK >= segs[lp.seg_begin + ls].K;
-  };
-  auto advance = [&]() {
-    lk += BK;
-    if (lk >= segs[lp.seg_begin + ls].K) {
-      ++ls;
-      lk = 0;
-      if (ls >= lp.seg_count) next_tile();
-    }
-  };
-
-  next_tile();
-  if (!lvalid) return;
-  flt4 acc[SM][SN];
-#pragma unroll
-  for (int i = 0; i < SM; ++i)
-#pragma unroll
-    for (int j = 0; j < SN; ++j) acc[i][j] = flt4{0, 0, 0, 0};
-  // the tile whose k-step sits in the current buffer
-  GemmProb cp = lp;
-  int cm0 = lm0, cn0 = ln0;
-  bool clast = last_step();
-  load();
-  advance();
-  store(0);
-  __syncthreads();
-  int buf = 0;
-  for (;;) {
-    const bool nvalid = lvalid;
-    GemmProb np_ = lp;
-    int nm0 = lm0, nn0 = ln0;
-    bool nlast = false;
-    if (nvalid) {
-      nlast = last_step();
-      load();
-      advance();
-    }
-    {
-      const int kc = lane >> 4;   // 8-element k chunk of this lane
-      bf16x8 a[NP][SM], b[NP][SN];
-#pragma unroll
-      for (int q = 0; q < NP; ++q) {
-#pragma unroll
-        for (int i = 0; i < SM; ++i) {
-          const int r = wm * WM + i * 16 + (lane & 15);
-          a[q][i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const us8*>(&As[buf][q][lds_chunk(r, kc)]));
-        }
-#pragma unroll
-        for (int j = 0; j < SN; ++j) {
-          const int c = wn * WN + j * 16 + (lane & 15);
-          b[q][j] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const us8*>(&Bs[buf][q][lds_chunk(c, kc)]));
-        }
-      }
-#pragma unroll
-      for (int i = 0; i < SM; ++i)
-#pragma unroll
-        for (int j = 0; j < SN; ++j) {
-          if constexpr (NP == 3) {
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2][i], b[0][j], acc[i][j], 0, 0, 0);
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][i], b[1][j], acc[i][j], 0, 0, 0);
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[2][j], acc[i][j], 0, 0, 0);
-          }
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][i], b[0][j], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[1][j], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[0][j], acc[i][j], 0, 0, 0);
-        }
-    }
-    if (clast) {
-      BST_G TC* __restrict__ C = (BST_G TC*)(ptrs[cp.c_buf]);
-#pragma unroll
-      for (int i = 0; i < SM; ++i)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = cm0 + wm * WM + i * 16 + 4 * (lane >> 4) + r;
-          if (row >= cp.M) continue;
-          const int64_t rbase = row_base(cp, row);
-#pragma unroll
-          for (int j = 0; j < SN; ++j) {
-            const int col = cn0 + wn * WN + j * 16 + (lane & 15);
-            if (col < cp.N) C[rbase + col] = (TC)acc[i][j][r];
-          }
-        }
-#pragma unroll
-      for (int i = 0; i < SM; ++i)
-#pragma unroll
-        for (int j = 0; j < SN; ++j) acc[i][j] = flt4{0, 0, 0, 0};
-    }
-    if (!nvalid) break;
-    store(buf ^ 1);
-    __syncthreads();
-    buf ^= 1;
-    cp = np_;
-    cm0 = nm0;
-    cn0 = nn0;
-    clast = nlast;
-  }
-}
-
-template <int NP, typename TC>
-static hipError_t planes_persist_shape(int bm, int bn, const PlanesLaunch& g, hipStream_t s) {
-  // two resident workgroups per CU at 128x128 (80 KB of LDS), four below
-  const int per_cu = (bm * bn >= 128 * 128) ? 2 : 4;
-  int64_t grid = (int64_t)256 * per_cu;
-  if (grid > g.ntiles) grid = (g.ntiles + 7) / 8 * 8;
-  dim3 gr((unsigned)grid), block(256);
-#define BST_PP(BM_, BN_)                                                                           \
-  if (bm == BM_ && bn == BN_) {                                                                    \
-    hipLaunchKernelGGL((gemm_planes_persist_kernel<NP, TC, BM_, BN_>), gr, block, 0, s, g.tiles,    \
-                       g.ntiles, g.probs, g.segs, g.ptrs, g.rowmap);                               \
-    return hipGetLastError();                                                                      \
-  }
-  BST_PP(64, 64)
-  if constexpr (NP == 2) {
-    BST_PP(128, 128)
-  }
-#undef BST_PP
-  return hipErrorInvalidValue;
-}
-
 template <int NP, typename TC>
 static hipError_t planes_shape(int bm, int bn, int bk, const PlanesLaunch& g, hipStream_t s) {
   dim3 grid((unsigned)g.ntiles), block(256);
@@ -581,14 +346,7 @@ hipError_t launch_gemm_planes(const PlanesLaunch& g, hipStream_t s) {
   const auto& sh = gemm_planes_shapes(g.np);
   if (g.tile < 0 || g.tile >= (int)sh.size()) return hipErrorInvalidValue;
   const int bm = sh[g.tile].bm, bn = sh[g.tile].bn;
-  if (sh[g.tile].direct == 1) return launch_gemm_direct_planes(g, bm, bn, s);
-  if (sh[g.tile].direct == 2) {
-    if (g.np == 2)
-      return g.tc == ElemType::F64 ? planes_persist_shape<2, double>(bm, bn, g, s)
-                                   : planes_persist_shape<2, float>(bm, bn, g, s);
-    return g.tc == ElemType::F64 ? planes_persist_shape<3, double>(bm, bn, g, s)
-                                 : planes_persist_shape<3, float>(bm, bn, g, s);
-  }
+  if (sh[g.tile].direct != 0) return hipErrorInvalidValue;   // kind 3: launch_gemm_planes_stream
   const int bk = 32;   // 64-deep k steps (1 or 2 workgroups per CU) measured slower
   if (g.np == 2)
     return g.tc == ElemType::F64 ? planes_shape<2, double>(bm, bn, bk, g, s)
@@ -636,7 +394,7 @@ __global__ __launch_bounds__(256) void happly_planes_kernel(const HTask* __restr
       split_planes<NP>(y, h);
       const int64_t at = q.off + (int64_t)i * q.rowstride + jc;
 #pragma unroll
-      for (int pq = 0; pq < NP; ++pq) out[pq * t.out_ps + at] = h[pq];
+      for (int pq = 0; pq < NP; ++pq) out[plane_at(NP, at, pq)] = h[pq];
     }
   }
 }

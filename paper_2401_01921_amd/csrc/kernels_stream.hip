@@ -1,0 +1,350 @@
+// Pipelined persistent GEMM on bfloat16 planes.
+//
+// The plane GEMMs of the two-site H_eff apply have short K (one charge
+// sector, or a few of them) and many output tiles, so a kernel that loads one
+// k-step ahead spends most of its time waiting: on the chain of table reads
+// that starts each tile, on the first operand load, and on one memory
+// latency per k-step.  This kernel removes the waits instead of hiding them
+// behind occupancy:
+//   - a fixed grid; every workgroup walks a host-built list of k-steps (one
+//     48-byte record each, the steps of a tile consecutive), so no table is
+//     read on the critical path;
+//   - operand tiles go from global memory straight into LDS
+//     (global_load_lds_dwordx4: no registers, no LDS store instructions),
+//     S - 1 k-steps ahead of the MFMAs, into a ring of S stages, across tile
+//     boundaries, so the first loads of the next tile are in flight while the
+//     current one finishes and writes its result;
+//   - the step records themselves are copied into LDS 16 at a time, one batch
+//     ahead; the row offsets of row-mapped tiles are copied at the tile's
+//     first step.
+// Waits are explicit: before k-step u the wave waits until only the copies
+// issued after step u's copies are outstanding (vector memory operations
+// complete in issue order on this target) and then meets the other waves at
+// a barrier.  Copies that are not counted (record batches, row offsets)
+// only make a wait stricter.  The stores of a tile are counted exactly: every
+// lane stores every element, lanes outside the tile to a sink.
+#include "bst_internal.h"
+
+#pragma clang diagnostic ignored "-Winline-asm"
+
+namespace bst {
+
+namespace {
+typedef float flt4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+#define BST_LDS __attribute__((address_space(3)))
+
+// An LDS operand row holds one 32-deep k step of all NP planes: NC = 4 * NP
+// 16-byte pieces, piece cc = chunk * NP + plane, in global order (so that
+// the lanes copying a row read one contiguous run).  Piece cc of row r sits
+// at position swz(r, cc), an involution for a fixed r that spreads the 16
+// rows one MFMA operand read touches (same cc) over distinct bank groups.
+template <int NP>
+__device__ __forceinline__ int swz(int r, int cc) {
+  if constexpr (NP == 2) return cc ^ ((r >> 1) & 7);
+  return (cc & ~3) | ((cc ^ (r >> 1)) & 3);
+}
+
+// Copy 16 bytes per lane from global address g into LDS at lds_addr + 16 * lane.
+// lds_addr is the same in every lane.
+__device__ __forceinline__ void lds_copy16(uint32_t lds_addr, const void* g) {
+  const int m0 = __builtin_amdgcn_readfirstlane((int)lds_addr);
+  asm volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dwordx4 %1, off" : : "s"(m0), "v"(g) : "memory", "m0");
+}
+// Wait until at most N vector memory operations of this wave are
+// outstanding and all its LDS reads are done, then meet the workgroup.
+template <int N>
+__device__ __forceinline__ void wait_and_meet() {
+  asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" : : "n"(N) : "memory");
+}
+constexpr int clamp63(int x) { return x < 63 ? x : 63; }
+// N = BASE + e * NS for e in [0, E] (e is wave-uniform)
+template <int BASE, int NS, int E>
+__device__ __forceinline__ void wait_and_meet_sel(int e) {
+  if constexpr (E == 0) {
+    wait_and_meet<clamp63(BASE)>();
+  } else {
+    if (e == E)
+      wait_and_meet<clamp63(BASE + E * NS)>();
+    else
+      wait_and_meet_sel<BASE, NS, E - 1>(e);
+  }
+}
+
+// A k-step record read from LDS, made wave-uniform.
+struct Rec {
+  int64_t a, b, c;
+  int lda, ldb, rows, cols, kch, flags, kval, ldc, c_buf, a_buf, b_buf;
+};
+__device__ __forceinline__ bf16x8 bf(u4 x) { return __builtin_bit_cast(bf16x8, x); }
+__device__ __forceinline__ uint32_t uni(uint32_t x) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)x); }
+__device__ __forceinline__ Rec read_rec(const unsigned char* p) {
+  const u4 w0 = *reinterpret_cast<const u4*>(p);
+  const u4 w1 = *reinterpret_cast<const u4*>(p + 16);
+  const u4 w2 = *reinterpret_cast<const u4*>(p + 32);
+  Rec r;
+  r.a = (int64_t)((uint64_t)uni(w0.x) | ((uint64_t)uni(w0.y) << 32));
+  r.b = (int64_t)((uint64_t)uni(w0.z) | ((uint64_t)uni(w0.w) << 32));
+  r.lda = (int)uni(w1.x);
+  r.ldb = (int)uni(w1.y);
+  const uint32_t pk = uni(w1.z);
+  r.rows = (int)(pk & 0xFF) + 1;
+  r.cols = (int)((pk >> 8) & 0xFF) + 1;
+  r.kch = (int)((pk >> 16) & 0xFF);
+  r.flags = (int)(pk >> 24);
+  const uint32_t pk2 = uni(w1.w);
+  r.kval = (int)(pk2 & 0xFF);
+  r.c_buf = (int)(pk2 >> 16);
+  r.c = (int64_t)((uint64_t)uni(w2.x) | ((uint64_t)uni(w2.y) << 32));
+  r.ldc = (int)uni(w2.z);
+  const uint32_t pk3 = uni(w2.w);
+  r.a_buf = (int)(pk3 & 0xFFFF);
+  r.b_buf = (int)(pk3 >> 16);
+  return r;
+}
+}  // namespace
+
+// Read by lanes whose k chunk lies past the operand rows, 16 bytes per lane
+// (one shared address for a whole wave serialises in the cache); never written.
+__device__ __attribute__((aligned(1024))) unsigned int g_stream_zero[64 * 4] = {};
+// WGM x WGN waves, each owning a (BM / WGM) x (BN / WGN) part of the tile.
+// Written by lanes outside the output tile (a 16-word slot per wave, so the
+// lanes of one store stay within two cache lines; one word shared by the
+// whole chip would serialise); never read.
+constexpr int kSinkWgs = 4 * kStreamCUs;
+__device__ __attribute__((aligned(256))) double g_stream_sink[kSinkWgs * 8 * 16];
+
+template <int NP, typename TC, int BM, int BN, int S, int WGM, int WGN>
+__global__ __launch_bounds__(64 * WGM * WGN) void gemm_planes_stream_kernel(const KStep* __restrict__ steps,
+                                                                 const int64_t* __restrict__ wg_begin,
+                                                                 void* const* __restrict__ ptrs,
+                                                                 const int64_t* __restrict__ rowtab) {
+  constexpr int NW = WGM * WGN, NT = 64 * NW;             // waves, lanes
+  constexpr int WM = BM / WGM, WN = BN / WGN, SM = WM / 16, SN = WN / 16;
+  constexpr int NC = 4 * NP;                            // 16-byte pieces per operand row
+  constexpr int SLA = BM * NC, SLB = BN * NC;           // 16-byte slots of a stage
+  constexpr int LPS = (SLA + SLB) / NT;                 // copies per lane per stage
+  constexpr int RL = BM / NW / 2;                       // lanes per wave copying row offsets
+  constexpr int BL = kStepBatch * 3 / NW;               // lanes per wave copying records
+  constexpr int STB = (SLA + SLB) * 16;                 // stage bytes
+  constexpr int REC = S * STB;                          // record ring
+  constexpr int ROWS = REC + kStepRing * kStepBatch * 48;   // row-offset ring
+  constexpr int LDSB = ROWS + S * BM * 8;
+  constexpr int NS = SM * SN * 4;                       // stores per lane per tile
+  static_assert(LDSB == stream_lds_bytes(NP, BM, BN, S), "LDS layout");
+  static_assert(SLA % NT == 0 && SLB % NT == 0, "a copy round covers A or B slots only");
+  static_assert(S >= 2 && S <= 16, "stages");
+  static_assert(SM >= 1 && SN >= 1 && WM % 16 == 0 && WN % 16 == 0, "wave tiles of whole MFMA blocks");
+  static_assert(RL >= 1 && RL * 2 * NW == BM && RL <= 64, "row-offset copy");
+  static_assert(BL * NW == kStepBatch * 3, "record copy");
+  __shared__ __attribute__((aligned(16))) unsigned char smem[LDSB];
+
+  const int64_t first = wg_begin[blockIdx.x];
+  const int n = (int)(wg_begin[blockIdx.x + 1] - first);
+  if (n <= 0) return;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = wave / WGN, wn = wave % WGN;
+  const uint32_t lds0 = (uint32_t)(uintptr_t)(BST_LDS unsigned char*)smem;
+  const unsigned char* gsteps = reinterpret_cast<const unsigned char*>(steps + first);
+  // operand buffers of the current copies (re-read when a record names others)
+  int a_buf = -1, b_buf = -1;
+  const unsigned short* A = nullptr;
+  const unsigned short* B = nullptr;
+  const void* zero = g_stream_zero + 4 * lane;
+
+  // record batch bi -> ring slot bi % kStepRing: 768 bytes, BL lanes per wave
+  auto copy_batch = [&](int bi) {
+    if (bi * kStepBatch < n && lane < BL)
+      lds_copy16(lds0 + REC + (uint32_t)(bi % kStepRing) * (kStepBatch * 48) + wave * (BL * 16),
+                 gsteps + (int64_t)bi * (kStepBatch * 48) + wave * (BL * 16) + lane * 16);
+  };
+  auto rec_ptr = [&](int v) -> const unsigned char* {
+    return smem + REC + ((v / kStepBatch) % kStepRing) * (kStepBatch * 48) + (v % kStepBatch) * 48;
+  };
+
+  int tiles_in = 0, tiles_out = 0;   // tiles started by the copy cursor / written
+  // copies of k-step v into stage v % S
+  auto issue = [&](int v) {
+    if (v % kStepBatch == 0) copy_batch(v / kStepBatch + 1);
+    const Rec d = read_rec(rec_ptr(v));
+    if ((d.flags & (kStepFirst | kStepRowmap)) == (kStepFirst | kStepRowmap)) {
+      if (lane < RL)
+        lds_copy16(lds0 + ROWS + (uint32_t)(tiles_in % S) * (BM * 8) + wave * (RL * 16),
+                   rowtab + d.c + wave * (RL * 2) + lane * 2);
+    }
+    if (d.flags & kStepFirst) ++tiles_in;
+    if (d.a_buf != a_buf) {
+      a_buf = d.a_buf;
+      A = static_cast<const unsigned short*>(ptrs[a_buf]);
+    }
+    if (d.b_buf != b_buf) {
+      b_buf = d.b_buf;
+      B = static_cast<const unsigned short*>(ptrs[b_buf]);
+    }
+    const uint32_t sb = lds0 + (uint32_t)(v % S) * STB;
+#pragma unroll
+    for (int i = 0; i < LPS; ++i) {
+      const bool isA = i * NT < SLA;   // the same in every lane
+      const int sl = isA ? i * NT + tid : i * NT - SLA + tid;   // slot within the operand
+      const int r = sl / NC, cc = swz<NP>(r, sl % NC), kc = cc / NP;
+      const int row = min(r, (isA ? d.rows : d.cols) - 1);
+      // plane_at of (row, chunk kc, plane cc % NP): the row's pieces are contiguous
+      const int64_t e = NP * (isA ? d.a + (int64_t)row * d.lda : d.b + (int64_t)row * d.ldb) + cc * 8;
+      const void* g = kc < d.kch ? static_cast<const void*>((isA ? A : B) + e) : zero;
+      lds_copy16(sb + (uint32_t)(i * NT * 16 + wave * 1024), g);
+    }
+  };
+
+  flt4 acc[SM][SN];
+
+  auto compute = [&](int u, const Rec& d) {
+    const unsigned short* As = reinterpret_cast<const unsigned short*>(smem + (u % S) * STB);
+    const unsigned short* Bs = As + BM * NC * 8;
+    const int kc = lane >> 4;   // 8-element k chunk of this lane
+    u4 a[NP][SM], b[NP][SN];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+#pragma unroll
+      for (int i = 0; i < SM; ++i) {
+        const int r = wm * WM + i * 16 + (lane & 15);
+        a[q][i] = *reinterpret_cast<const u4*>(As + r * NC * 8 + swz<NP>(r, kc * NP + q) * 8);
+      }
+#pragma unroll
+      for (int j = 0; j < SN; ++j) {
+        const int r = wn * WN + j * 16 + (lane & 15);
+        b[q][j] = *reinterpret_cast<const u4*>(Bs + r * NC * 8 + swz<NP>(r, kc * NP + q) * 8);
+      }
+    }
+    // a partial last chunk (kval < 8 valid elements, in lanes of chunk
+    // kch - 1): zero the elements past kval in both operands, so that
+    // whatever the padding holds cannot reach the sums
+    if (d.kval < 8) {
+      const bool part = kc == d.kch - 1;
+      auto mk = [&](int e) -> uint32_t {
+        return !part ? ~0u : ((2 * e < d.kval ? 0xFFFFu : 0u) | (2 * e + 1 < d.kval ? 0xFFFF0000u : 0u));
+      };
+      const u4 m = {mk(0), mk(1), mk(2), mk(3)};
+#pragma unroll
+      for (int q = 0; q < NP; ++q) {
+#pragma unroll
+        for (int i = 0; i < SM; ++i) a[q][i] &= m;
+#pragma unroll
+        for (int j = 0; j < SN; ++j) b[q][j] &= m;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < SM; ++i)
+#pragma unroll
+      for (int j = 0; j < SN; ++j) {
+        if constexpr (NP == 3) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf(a[2][i]), bf(b[0][j]), acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf(a[1][i]), bf(b[1][j]), acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf(a[0][i]), bf(b[2][j]), acc[i][j], 0, 0, 0);
+        }
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf(a[1][i]), bf(b[0][j]), acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf(a[0][i]), bf(b[1][j]), acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf(a[0][i]), bf(b[0][j]), acc[i][j], 0, 0, 0);
+      }
+  };
+
+  // every lane stores all SM * SN * 4 of its elements (exactly NS store
+  // instructions per wave); lanes outside the tile store to the wave's
+  // 16-word slot of the sink
+  auto epilogue = [&](const Rec& d) {
+    BST_G TC* C = (BST_G TC*)(ptrs[d.c_buf]);
+    BST_G TC* sink = (BST_G TC*)(g_stream_sink + ((blockIdx.x % kSinkWgs) * 8 + wave) * 16 + (lane & 15));
+    const int64_t* rmap = reinterpret_cast<const int64_t*>(smem + ROWS + (tiles_out % S) * (BM * 8));
+#pragma unroll
+    for (int i = 0; i < SM; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = wm * WM + i * 16 + 4 * (lane >> 4) + r;
+        int64_t rb;
+        if (d.flags & kStepRowmap)
+          rb = rmap[row];
+        else
+          rb = row < d.rows ? d.c + (int64_t)row * d.ldc : -1;
+#pragma unroll
+        for (int j = 0; j < SN; ++j) {
+          const int col = wn * WN + j * 16 + (lane & 15);
+          BST_G TC* p = (rb >= 0 && col < d.cols) ? C + rb + col : sink;
+          *p = (TC)acc[i][j][r];
+        }
+      }
+    ++tiles_out;
+  };
+
+  // prologue: first record batch, then the first S - 1 steps' copies
+  copy_batch(0);
+  wait_and_meet<0>();
+  int v = 0;
+  for (; v < n && v < S - 1; ++v) issue(v);
+  unsigned epi = 0;   // bit k set: stores were issued k + 1 iterations ago (k < S - 1)
+  constexpr unsigned kEpiMask = (1u << (S - 1)) - 1;
+  int u = 0;
+  // one tile per outer iteration (the accumulators start at zero), its
+  // k-steps in the inner loop; copies run on across tile boundaries
+  while (u < n) {
+#pragma unroll
+    for (int i = 0; i < SM; ++i)
+#pragma unroll
+      for (int j = 0; j < SN; ++j) acc[i][j] = flt4{0, 0, 0, 0};
+    Rec d;
+    do {
+      // outstanding after step u's copies: the copies of steps u+1 .. u+S-2
+      // and the stores of the tiles finished since step u was issued
+      if (n - 1 - u >= S - 2)
+        wait_and_meet_sel<(S - 2) * LPS, NS, S - 1>(__builtin_popcount(epi));
+      else
+        wait_and_meet<0>();
+      if (v < n) {
+        issue(v);
+        ++v;
+      }
+      d = read_rec(rec_ptr(u));
+      compute(u, d);
+      epi = (epi << 1) & kEpiMask;
+      ++u;
+    } while (!(d.flags & kStepLast) && u < n);
+    epilogue(d);
+    epi |= 1;
+  }
+}
+
+// Shapes of kind 3 in gemm_planes_shapes(np), instantiated here
+// (np, bm, bn, stages, waves along M, waves along N).
+#define BST_STREAM_SHAPES(X) \
+  X(2, 128, 64, 3, 2, 2)     \
+  X(2, 64, 128, 3, 2, 2)     \
+  X(2, 128, 128, 3, 2, 4)    \
+  X(2, 128, 256, 3, 2, 4)    \
+  X(2, 256, 128, 3, 4, 2)    \
+  X(2, 256, 64, 3, 4, 2)     \
+  X(3, 64, 64, 3, 2, 2)      \
+  X(3, 128, 128, 3, 2, 4)
+
+hipError_t launch_gemm_planes_stream(const StreamLaunch& g, hipStream_t s) {
+  if (g.nwg <= 0) return hipSuccess;
+  if (g.nwg > 0x7FFFFFFF) return hipErrorInvalidValue;
+  const TileShape& sh = gemm_planes_shapes(g.np)[g.tile];
+  if (sh.direct != 3) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)g.nwg);
+#define BST_LAUNCH(NP_, BM_, BN_, S_, WGM_, WGN_)                                                          \
+  if (g.np == NP_ && sh.bm == BM_ && sh.bn == BN_ && sh.stages == S_ && sh.waves == WGM_ * WGN_) {        \
+    const dim3 block(64 * WGM_ * WGN_);                                                                    \
+    if (g.tc == ElemType::F32)                                                                            \
+      hipLaunchKernelGGL((gemm_planes_stream_kernel<NP_, float, BM_, BN_, S_, WGM_, WGN_>), grid, block, 0, \
+                         s, g.steps, g.wg_begin, g.ptrs, g.rowtab);                            \
+    else                                                                                                  \
+      hipLaunchKernelGGL((gemm_planes_stream_kernel<NP_, double, BM_, BN_, S_, WGM_, WGN_>), grid, block, \
+                         0, s, g.steps, g.wg_begin, g.ptrs, g.rowtab);                         \
+    return hipGetLastError();                                                                             \
+  }
+  BST_STREAM_SHAPES(BST_LAUNCH)
+#undef BST_LAUNCH
+  return hipErrorInvalidValue;
+}
+
+}  // namespace bst

@@ -318,12 +318,15 @@ static int64_t elem_offset4(const TensorDesc& T, const LegMap* maps, const int64
 
 // bfloat16-plane layout of a tensor seen as a matrix per block: rows are the
 // first `split` legs, columns the rest; rows (or, transposed, columns) are
-// padded to a multiple of 8 elements.
+// padded to a multiple of 32 elements (one 32-deep k step), so every row of
+// every block starts on a 32-element bound.  Positions are planar; the
+// planes are interleaved by chunks (plane_at).
 struct PadLayout {
   std::vector<int64_t> off, ld;
-  int64_t total = 0;   // elements per plane, a multiple of 8
+  int64_t total = 0;   // positions per plane, a multiple of 32
 };
 static int64_t pad8(int64_t x) { return (x + 7) / 8 * 8; }
+static int64_t pad32(int64_t x) { return (x + 31) / 32 * 32; }
 
 static void block_matrix(const TensorDesc& T, int64_t b, int split, int64_t& rows, int64_t& cols) {
   rows = 1;
@@ -337,12 +340,12 @@ static PadLayout pad_layout(const TensorDesc& T, int split, bool transpose) {
   for (int64_t b = 0; b < T.nblocks; ++b) {
     int64_t rows, cols;
     block_matrix(T, b, split, rows, cols);
-    const int64_t ld = transpose ? pad8(rows) : pad8(cols);
+    const int64_t ld = transpose ? pad32(rows) : pad32(cols);
     P.off.push_back(cum);
     P.ld.push_back(ld);
     cum += (transpose ? cols : rows) * ld;
   }
-  P.total = pad8(std::max<int64_t>(cum, 8));
+  P.total = pad32(std::max<int64_t>(cum, 32));
   return P;
 }
 
@@ -371,7 +374,7 @@ static GroupedLayout pad_layout_grouped(const TensorDesc& T, int split, int grou
       if (T.block_qn(b)[group_leg] != k) continue;
       int64_t rows, cols;
       block_matrix(T, b, split, rows, cols);
-      const int64_t ld = pad8(cols);
+      const int64_t ld = pad32(cols);
       G.lay.off[b] = cum;
       G.lay.ld[b] = ld;
       G.grow[b] = G.gm[k];
@@ -379,7 +382,7 @@ static GroupedLayout pad_layout_grouped(const TensorDesc& T, int split, int grou
       cum += rows * ld;
     }
   }
-  G.lay.total = pad8(std::max<int64_t>(cum, 8));
+  G.lay.total = pad32(std::max<int64_t>(cum, 32));
   return G;
 }
 
@@ -394,7 +397,6 @@ static void add_split_jobs(Step& st, const TensorDesc& T, int split, bool transp
     SplitJob j{};
     j.in_off = T.offset[b];
     j.out_off = Lay.off[b];
-    j.out_ps = Lay.total;
     j.in_buf = in_slot;
     j.out_buf = out_slot;
     j.rows = (int32_t)rows;
@@ -477,7 +479,7 @@ static void heff_plan(const TensorDesc& L, const TensorDesc& W1, const TensorDes
     for (int64_t b = 0; b < R.nblocks; ++b) {
       if (R.block_qn(b)[0] != kb) continue;
       rseg[b] = t3w[kb];
-      t3w[kb] += pad8(R.block_shape(b)[1] * R.block_shape(b)[2]);
+      t3w[kb] += pad32(R.block_shape(b)[1] * R.block_shape(b)[2]);
     }
     t3g[kb] = t3tot;
     t3tot += t3m[kb] * t3w[kb];
@@ -491,7 +493,7 @@ static void heff_plan(const TensorDesc& L, const TensorDesc& W1, const TensorDes
     const int64_t* sh = T3->block_shape(b);
     sink_need = std::max(sink_need, sh[0] * sh[4]);
   }
-  const int64_t t3ps = pad8(std::max<int64_t>(t3tot + sink_need, 8));   // plane stride
+  const int64_t t3ps = pad32(std::max<int64_t>(t3tot + sink_need, 32));   // positions per plane
   P.internals.push_back({8, (size_t)Lp.total * 2 * 3, 0});
   P.internals.push_back({9, (size_t)Rp.total * 2 * 3, 0});
   P.internals.push_back({10, (size_t)Pp.total * 2 * 3, 0});
@@ -506,7 +508,7 @@ static void heff_plan(const TensorDesc& L, const TensorDesc& W1, const TensorDes
   spL.constant = spR.constant = true;
 
   // merged T1 layout of the plane variant (filled with step 1)
-  std::vector<int64_t> t1m_start, t1m_cols, pcol, t1zero;
+  std::vector<int64_t> t1m_start, t1m_ld, pcol, t1zero;
 
   // ---- step 1: T1[(a w) x (t1 t2 y)] = sum_a' L[(a w) x a'] psi[a' x (t1 t2 y)]
   Step s1;
@@ -552,9 +554,11 @@ static void heff_plan(const TensorDesc& L, const TensorDesc& W1, const TensorDes
     // plane variant: one problem per a' sector kx.  Rows: every L block
     // (a, w, kx) stacked (grouped L planes); columns: every psi block
     // (kx, t1, t2, y) stacked (transposed psi planes); the result is T1 in a
-    // merged layout, [rows x columns] per kx, read back by the MPO step.
+    // merged layout, [rows x columns] per kx, read back by the MPO step;
+    // rows padded to 16 floats, so that the GEMM's 64-byte row stores are
+    // whole 64-byte blocks.
     t1m_start.assign(nA, 0);
-    t1m_cols.assign(nA, 0);
+    t1m_ld.assign(nA, 0);
     pcol.assign(psi.nblocks, 0);
     int64_t cum = 0;
     for (int kx = 0; kx < nA; ++kx) {
@@ -568,9 +572,9 @@ static void heff_plan(const TensorDesc& L, const TensorDesc& W1, const TensorDes
         ncol += cols;
       }
       t1m_start[kx] = cum;
-      t1m_cols[kx] = ncol;
+      t1m_ld[kx] = (ncol + 15) / 16 * 16;
       const int64_t M = Lg.gm[kx];
-      cum += M * ncol;
+      cum += M * t1m_ld[kx];
       if (M == 0 || ncol == 0) continue;
       if (M > 0x7FFFFFFF || ncol > 0x7FFFFFFF) fail(BST_E_INVALID, "sector group too large");
       const int64_t K = psi.legs[0].g[kx];
@@ -579,18 +583,16 @@ static void heff_plan(const TensorDesc& L, const TensorDesc& W1, const TensorDes
       p.c_buf = 6;
       p.M = (int32_t)M;
       p.N = (int32_t)ncol;
-      p.ldc = (int32_t)ncol;
+      p.ldc = (int32_t)t1m_ld[kx];
       p.seg_begin = (int32_t)s1.segs_alt.size();
       p.seg_count = 1;
       GemmSeg h{};
       h.a_off = Lg.gstart[kx];
       h.a_buf = 8;
-      h.lda = (int32_t)pad8(K);
-      h.a_ps = Lp.total;
+      h.lda = (int32_t)pad32(K);
       h.b_off = Pp.off[pfirst];
       h.b_buf = 10;
-      h.ldb = (int32_t)pad8(K);
-      h.b_ps = Pp.total;
+      h.ldb = (int32_t)pad32(K);
       h.K = (int32_t)K;
       s1.segs_alt.push_back(h);
       s1.probs_alt.push_back(p);
@@ -608,7 +610,9 @@ static void heff_plan(const TensorDesc& L, const TensorDesc& W1, const TensorDes
       s1.probs_alt.push_back(p);
       cum += T1->block_size(cb);
     }
-    if (cum != T1->numel) fail(BST_E_INVALID, "internal: merged T1 layout size");
+    // the T1 buffer holds the float64 block layout or this float32 one
+    for (auto& ib : P.internals)
+      if (ib.slot == 6) ib.bytes = std::max(ib.bytes, (size_t)cum * 4);
     s1.bytes = 8.0 * ((double)L.numel + (double)psi.numel + (double)T1->numel);
     s1.bytes32 = 8.0 * ((double)L.numel + (double)psi.numel) + 4.0 * (double)T1->numel;
   }
@@ -670,10 +674,10 @@ static void heff_plan(const TensorDesc& L, const TensorDesc& W1, const TensorDes
                     if (t1zero[b] >= 0) {
                       ins_alt.push_back({t1zero[b] + in_blk, gw * g1 * g2 * gy});
                     } else {
-                      const int64_t ncol = t1m_cols[kx];
-                      ins_alt.push_back({t1m_start[kx] + (Lg.grow[lb] + c) * ncol + pcol[pb] +
+                      const int64_t ld = t1m_ld[kx];
+                      ins_alt.push_back({t1m_start[kx] + (Lg.grow[lb] + c) * ld + pcol[pb] +
                                              (e1 * g2 + e2) * gy,
-                                         gw * ncol});
+                                         gw * ld});
                     }
                     key.push_back(lwm.start[kw] + c);
                     key.push_back(lt1m.start[k1] + e1);
@@ -767,7 +771,6 @@ static void heff_plan(const TensorDesc& L, const TensorDesc& W1, const TensorDes
         for (auto& q : outs_alt) ha.planes_alt.push_back(q);
         HTask ta = task;
         ta.out_buf = 11;
-        ta.out_ps = t3ps;
         ha.tasks_alt.push_back(ta);
       }
     hc.ncls = (int32_t)classes.size();
@@ -870,11 +873,9 @@ static void heff_plan(const TensorDesc& L, const TensorDesc& W1, const TensorDes
         h.a_off = t3g[kb] + rseg[rb];
         h.a_buf = 11;
         h.lda = (int32_t)t3w[kb];
-        h.a_ps = t3ps;
         h.b_off = Rp.off[rb];
         h.b_buf = 9;
         h.ldb = (int32_t)Rp.ld[rb];
-        h.b_ps = Rp.total;
         s4.segs_alt.push_back(h);
       }
       p.seg_count = (int32_t)s4.segs_alt.size() - p.seg_begin;
@@ -1076,6 +1077,129 @@ static std::vector<GemmTile> make_tiles(const std::vector<GemmProb>& probs,
   return out;
 }
 
+// k-step schedule of the pipelined plane kernel for one tile shape.  The
+// problems go to the XCDs as in make_tiles; each XCD's tiles, in that
+// order, go one by one to the least loaded of the XCD's workgroups
+// (workgroup w runs on XCD w % 8); a workgroup's tiles become consecutive
+// k-step records.  ok stays false if an operand offset or row stride is not
+// a multiple of 8 positions (whole 16-byte pieces) or a table slot does not
+// fit the record.
+static Step::StreamList make_stream(std::vector<uint8_t>& blob, const Step& st, int np, const TileShape& sh) {
+  Step::StreamList L;
+  const auto& probs = st.probs_alt;
+  const auto& segs = st.segs_alt;
+  const int bm = sh.bm, bn = sh.bn;
+  if (bm > 256 || bn > 256) return L;   // row / column counts are stored in a byte
+  for (const auto& g : segs) {
+    if (g.K <= 0) continue;
+    if (g.a_off % 8 || g.b_off % 8 || g.lda % 8 || g.ldb % 8) return L;
+    if (g.a_buf < 0 || g.a_buf > 0xFFFF || g.b_buf < 0 || g.b_buf > 0xFFFF) return L;
+  }
+  for (const auto& p : probs)
+    if (p.c_buf < 0 || p.c_buf > 0xFFFF) return L;
+  auto ksteps = [&](const GemmProb& p) {
+    int64_t k = 0;
+    for (int q = 0; q < p.seg_count; ++q) {
+      const int64_t K = segs[p.seg_begin + q].K;
+      if (K > 0) k += (pad8(K) + 31) / 32;
+    }
+    return std::max<int64_t>(k, 1);
+  };
+  // problems to XCDs: largest first, each to the least loaded
+  struct Prob {
+    double cost;
+    int32_t idx;
+  };
+  std::vector<Prob> pr;
+  for (size_t pi = 0; pi < probs.size(); ++pi) {
+    const auto& p = probs[pi];
+    const double nt = (double)((p.M + bm - 1) / bm) * (double)((p.N + bn - 1) / bn);
+    pr.push_back({nt * (double)(ksteps(p) + 2), (int32_t)pi});
+  }
+  std::stable_sort(pr.begin(), pr.end(), [](const Prob& a, const Prob& b) { return a.cost > b.cost; });
+  std::vector<double> xload(kXcds, 0.0);
+  std::vector<std::vector<GemmTile>> bins(kXcds);
+  for (const auto& q : pr) {
+    int x = 0;
+    for (int i = 1; i < kXcds; ++i)
+      if (xload[i] < xload[x]) x = i;
+    xload[x] += q.cost;
+    const auto& p = probs[q.idx];
+    for (int m0 = 0; m0 < p.M; m0 += bm)
+      for (int n0 = 0; n0 < p.N; n0 += bn) bins[x].push_back({q.idx, m0, n0, 0});
+  }
+  const int64_t nwg = (int64_t)kStreamCUs * stream_wgs_per_cu(np, bm, bn, sh.stages);
+  std::vector<std::vector<GemmTile>> per(nwg);
+  std::vector<int64_t> wload(nwg, 0);
+  for (int x = 0; x < kXcds; ++x)
+    for (const auto& t : bins[x]) {
+      int64_t w = x;
+      for (int64_t c = x + kXcds; c < nwg; c += kXcds)
+        if (wload[c] < wload[w]) w = c;
+      per[w].push_back(t);
+      wload[w] += ksteps(probs[t.prob]) + 2;
+    }
+  std::vector<KStep> recs;
+  std::vector<int64_t> begin((size_t)nwg + 1, 0), rowtab;
+  for (int64_t w = 0; w < nwg; ++w) {
+    begin[w] = (int64_t)recs.size();
+    for (const auto& t : per[w]) {
+      const GemmProb& p = probs[t.prob];
+      KStep base{};
+      const int rows = std::min(bm, p.M - t.m0), cols = std::min(bn, p.N - t.n0);
+      base.rows1 = (uint8_t)(rows - 1);
+      base.cols1 = (uint8_t)(cols - 1);
+      base.c_buf = (uint16_t)p.c_buf;
+      base.kval = 8;
+      if (p.rowmap1 > 0) {
+        base.flags = kStepRowmap;
+        base.c = (int64_t)rowtab.size();
+        for (int r = 0; r < bm; ++r)
+          rowtab.push_back(r < rows ? st.rowmap[(size_t)(p.rowmap1 - 1 + t.m0 + r)] + t.n0 : -1);
+      } else {
+        base.c = p.c_off + (int64_t)t.m0 * p.ldc + t.n0;
+        base.ldc = p.ldc;
+      }
+      const size_t first = recs.size();
+      for (int q = 0; q < p.seg_count; ++q) {
+        const GemmSeg& g = segs[p.seg_begin + q];
+        if (g.K <= 0) continue;
+        const int64_t K8 = pad8(g.K);
+        for (int64_t lk = 0; lk < K8; lk += 32) {
+          KStep k = base;
+          k.a = g.a_off + (int64_t)t.m0 * g.lda + lk;
+          k.b = g.b_off + (int64_t)t.n0 * g.ldb + lk;
+          k.lda = g.lda;
+          k.ldb = g.ldb;
+          k.a_buf = (uint16_t)g.a_buf;
+          k.b_buf = (uint16_t)g.b_buf;
+          k.kch = (uint8_t)std::min<int64_t>(4, (K8 - lk) / 8);
+          k.kval = (uint8_t)((lk + 8 * k.kch == K8 && g.K % 8) ? g.K % 8 : 8);
+          recs.push_back(k);
+        }
+      }
+      if (recs.size() == first) {   // no k-steps: one step of zeros writes the tile
+        KStep k = base;
+        k.kch = 0;
+        k.a_buf = k.b_buf = (uint16_t)p.c_buf;
+        recs.push_back(k);
+      }
+      recs[first].flags |= kStepFirst;
+      recs.back().flags |= kStepLast;
+    }
+  }
+  begin[nwg] = (int64_t)recs.size();
+  recs.resize(recs.size() + kStepBatch, KStep{});   // batches read whole
+  rowtab.push_back(-1);
+  rowtab.push_back(-1);
+  L.steps_off = put(blob, recs);
+  L.begin_off = put(blob, begin);
+  L.rows_off = put(blob, rowtab);
+  L.nwg = nwg;
+  L.ok = true;
+  return L;
+}
+
 int default_tile(const Step& st, bst_precision form) {
   auto it = st.tile_choice.find((int)form);
   if (it != st.tile_choice.end()) return it->second;
@@ -1113,13 +1237,21 @@ void finalize(PlanData& P) {
           st.off2 = put(P.blob, st.segs_alt);
           st.off3 = put(P.blob, st.probs_alt);
           st.off5 = put(P.blob, st.rowmap);
-          for (int np = 2; np <= 3; ++np)
-            for (const auto& sh : gemm_planes_shapes(np)) {
+          st.streams_alt.clear();
+          for (int np = 2; np <= 3; ++np) {
+            const auto& shapes = gemm_planes_shapes(np);
+            for (size_t i = 0; i < shapes.size(); ++i) {
+              const auto& sh = shapes[i];
+              if (sh.direct == 3) {
+                st.streams_alt[np * 64 + (int)i] = make_stream(P.blob, st, np, sh);
+                continue;
+              }
               auto key = std::make_pair(sh.bm, sh.bn);
               if (st.tile_lists_alt.count(key)) continue;
               auto tl = make_tiles(st.probs_alt, st.segs_alt, sh.bm, sh.bn);
               st.tile_lists_alt[key] = {put(P.blob, tl), (int64_t)tl.size()};
             }
+          }
         }
         break;
       }
@@ -1380,8 +1512,10 @@ bst_status bst_plan_tiles(const bst_plan* p, char* buf, size_t cap) {
     const bool pl = uses_planes(P, P.prec) && st.has_alt;
     const TileShape sh = pl ? gemm_planes_shapes(P.prec == BST_BF16X6 ? 3 : 2)[planes_tile(st, P.prec)]
                             : gemm_tile_shapes(P.prec)[default_tile(st, P.prec)];
-    s += st.name + ":" + std::to_string(sh.bm) + "x" + std::to_string(sh.bn) +
-         (sh.direct == 1 ? "d" : sh.direct == 2 ? "q" : "l") + (pl ? "p" : "") + ";";
+    const std::string kind = sh.direct == 1   ? "d"
+                             : sh.direct == 3 ? "s" + std::to_string(sh.stages) + "w" + std::to_string(sh.waves)
+                                              : "l";
+    s += st.name + ":" + std::to_string(sh.bm) + "x" + std::to_string(sh.bn) + kind + (pl ? "p" : "") + ";";
   }
   std::strncpy(buf, s.c_str(), cap - 1);
   buf[cap - 1] = 0;

@@ -83,6 +83,13 @@ struct Step {
   int64_t n0 = 0, n1 = 0;
   std::map<std::pair<int, int>, std::pair<size_t, int64_t>> tile_lists;  // (bm,bn) -> (off, n)
   std::map<std::pair<int, int>, std::pair<size_t, int64_t>> tile_lists_alt;  // plane variant
+  // k-step schedules of the pipelined plane kernel, by np * 64 + shape index
+  struct StreamList {
+    bool ok = false;               // the problems fit the kernel's layout rules
+    size_t steps_off = 0, begin_off = 0, rows_off = 0;
+    int64_t nwg = 0;
+  };
+  std::map<int, StreamList> streams_alt;
 };
 
 struct InternalBuf {

@@ -216,6 +216,39 @@ def test_every_gemm_variant(prec):
         assert rel_err(host(out), C.data)[0] <= TOL[prec], tile
 
 
+def _pipelined_tiles(plan, prec):
+    """Indices of the pipelined (k-step schedule) plane-GEMM shapes."""
+    out = []
+    for tile in range(plan.tile_count(prec)):
+        plan.set_tile(prec, tile)
+        if "s" in plan.tiles().split(";")[0].split(":")[1]:
+            out.append(tile)
+    return out
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "bf16x6"])
+def test_pipelined_gemm_full_size(prec):
+    """The pipelined plane GEMMs on the spin-1 chi = 4096 operator: every
+    shape equals the LDS-staged kernel bit for bit (same products, same
+    k order) and the oracle within the form's tolerance."""
+    specs, O = heff_operands(5, recipe="dmrg_like")
+    ref = orc.heff_apply(O["L"], O["W1"], O["W2"], O["R"], O["psi"]).data
+    T, plan = lib_heff(specs, prec)
+    plan.set_tile(prec, 0)   # LDS-staged 64x64
+    base = run_heff(plan, O)
+    assert rel_err(base, ref)[0] <= TOL[prec]
+    tiles = _pipelined_tiles(plan, prec)
+    assert tiles
+    for tile in tiles:
+        plan.set_tile(prec, tile)
+        got = run_heff(plan, O)
+        nrm, mx = rel_err(got, ref)
+        _print("pipelined", prec, tile, plan.tiles(), nrm, "max|diff| vs LDS kernel",
+               float(np.max(np.abs(got - base))))
+        assert np.array_equal(got, base), plan.tiles()
+        assert nrm <= TOL[prec]
+
+
 def test_workspace_overwritten_between_calls():
     """The plan's tables live in the workspace; after the caller overwrites
     the workspace (here with NaN bytes) the binding makes the plan upload

@@ -74,6 +74,34 @@ def test_batched_heff_matches_single_applies(prec):
         assert nrm <= TOL[prec]
 
 
+def test_batched_heff_pipelined_gemm():
+    """The batch's merged problem lists (operands in many buffers) through
+    the pipelined plane GEMM: bit-identical to the LDS-staged kernel."""
+    members = _batch_members(64)
+    plans = [bst.heff_plan(T["L"], T["W1"], T["W2"], T["R"], T["psi"], "bf16x3") for _, T, _ in members]
+    batch = bst.heff_batch_plan(plans)
+    ins, outs = [], []
+    for _, T, d in members:
+        ins += [dev(d[k]) for k in ("L", "W1", "W2", "R", "psi")]
+        outs.append(torch.full((T["psi"].numel,), np.nan, dtype=torch.float64, device=DEV))
+    ws = bst.workspace(batch.workspace_bytes)
+    batch.set_tile("bf16x3", 0)   # LDS-staged 64x64
+    batch.execute(ins, outs, ws)
+    torch.cuda.synchronize()
+    base = [host(o) for o in outs]
+    for tile in range(batch.tile_count("bf16x3")):
+        batch.set_tile("bf16x3", tile)
+        if "s" not in batch.tiles().split(";")[0].split(":")[1]:
+            continue
+        for o in outs:
+            o.fill_(float("nan"))
+        batch.execute(ins, outs, ws)
+        torch.cuda.synchronize()
+        _print("batch pipelined", tile, batch.tiles())
+        for i, o in enumerate(outs):
+            assert np.array_equal(host(o), base[i]), (tile, i)
+
+
 def test_autotune_keeps_results():
     specs, O = heff_operands(3)
     ref = orc.heff_apply(O["L"], O["W1"], O["W2"], O["R"], O["psi"]).data
