@@ -174,17 +174,21 @@ def main():
                     bytes_gbs=(steps[name]["bytes_fp32" if prec != "fp64" else "bytes_fp64"])
                     / avg_ms / 1e6)
 
-    def gs_bytes(kind):
+    # Krylov rows are float32 with the split matvec forms, float64 otherwise
+    vb = 4.0 if a.prec in ("bf16x3", "bf16x6") else 8.0
+
+    def gs_bytes(kind, rowb=None):
         # algorithmic bytes of one solve's Gram-Schmidt kernels (default
         # schedule): the dot reads u_j and z; the pass of step j (0-based)
-        # reads basis rows 0..j and z and writes row j and (except on the
-        # last step) row j+1
+        # reads basis rows 0..j and z (float64) and writes row j and (except
+        # on the last step) row j+1
+        rb = vb if rowb is None else rowb
         tot = 0.0
         for j in range(m):
             if kind == "dots":
-                tot += 16.0 * n
+                tot += (rb + 8.0) * n
             else:
-                tot += 8.0 * n * (j + 2) + 8.0 * n * (2 if j + 1 < m else 1)
+                tot += rb * n * (j + 1) + 8.0 * n + rb * n * (2 if j + 1 < m else 1)
         return tot
 
     def hbm_roof(key, total_bytes, prof):

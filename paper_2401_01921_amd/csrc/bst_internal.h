@@ -222,6 +222,7 @@ hipError_t launch_hcoef(const HCoefLaunch& c, hipStream_t s);
 
 struct SplitLaunch {
   int np;
+  bool in_f32 = false;         // the input blocks are float32 (a float32 Krylov row)
   const SplitJob* jobs;
   const SplitWork* work;
   void* const* ptrs;
@@ -327,11 +328,17 @@ hipError_t launch_project(const double* V, int64_t ldv, int64_t n, int nv, const
 // dst[i] = src[i] / sqrt(norm2[0]) (0 if norm2 <= 0); norm2 read on device.
 hipError_t launch_scale_rnorm(const double* src, const double* norm2, double* dst, int64_t n,
                               hipStream_t s);
+hipError_t launch_scale_rnorm(const double* src, const double* norm2, float* dst, int64_t n,
+                              hipStream_t s);
 // y[i] = sum_k coef[k] V[k*ldv+i]  (coef on device)
 hipError_t launch_combine(const double* V, int64_t ldv, int64_t n, int nv, const double* coef,
                           double* y, hipStream_t s);
+hipError_t launch_combine(const float* V, int64_t ldv, int64_t n, int nv, const double* coef,
+                          double* y, hipStream_t s);
 // out[0] = x.y, out[1] = y.y (out == nullptr: block partials only)
 hipError_t launch_dot2(const double* x, const double* y, int64_t n, double* partial, double* out,
+                       hipStream_t s);
+hipError_t launch_dot2(const float* x, const double* y, int64_t n, double* partial, double* out,
                        hipStream_t s);
 // e = num[0]/num[1]; out[0] = |hy - e y|^2
 hipError_t launch_resid(const double* hy, const double* y, const double* num, int64_t n,
@@ -354,6 +361,11 @@ hipError_t launch_lanczos_coef(int j, const double* g, const double* alpha, cons
 hipError_t launch_lanczos_pass(double* V, int64_t ldv, int64_t n, int j, const double* z,
                                const double* coef, const double* dprev, const double* beta,
                                double* vnext, double* partial, double* dn, hipStream_t s);
+// The same over a float32 basis (rows rounded to float32 when written; dots
+// and scalars in float64).
+hipError_t launch_lanczos_pass(float* V, int64_t ldv, int64_t n, int j, const double* z,
+                               const double* coef, const double* dprev, const double* beta,
+                               float* vnext, double* partial, double* dn, hipStream_t s);
 hipError_t launch_lanczos_end(const double* dn, const double* aest, int j, double* dprev,
                               double* alpha, double* beta, hipStream_t s);
 // alpha[j] = c[j] + d[j]; beta[j] = sqrt(norm2[0])

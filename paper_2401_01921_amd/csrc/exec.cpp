@@ -85,12 +85,45 @@ bool step_runs(const PlanData& P, const Step& st, bst_precision prec, bool skip_
 // Tile-choice key of the bfloat16-plane GEMM variant of a form.
 static int planes_key(bst_precision prec) { return 10 + (int)prec; }
 
-// LDS-staged 64x64: the default, and the fallback of the pipelined shapes
+// LDS-staged 64x64: the fallback of the pipelined shapes (problems outside
+// their layout rules)
 constexpr int kPlanesDefaultTile = 0;
+
+// Without a tuned choice: the largest pipelined tile, 128 x 256 for wide
+// problems and 256 x 128 for tall ones (by the flop-weighted mean of M and
+// N); the larger tile cuts the operand traffic from L2 more than its
+// padding costs (measured on the H_eff GEMMs).  Falls back to a 128 x 128
+// shape, then to the LDS-staged kernel.
+static int planes_auto_tile(const Step& st, int np) {
+  double wm = 0, wn = 0;
+  for (const auto& p : st.probs_alt) {
+    int64_t k = 0;
+    for (int q = 0; q < p.seg_count; ++q) k += st.segs_alt[p.seg_begin + q].K;
+    const double w = (double)p.M * (double)p.N * (double)std::max<int64_t>(k, 1);
+    wm += w * p.M;
+    wn += w * p.N;
+  }
+  const int want_bm = wn >= wm ? 128 : 256, want_bn = wn >= wm ? 256 : 128;
+  const auto& shapes = gemm_planes_shapes(np);
+  int best = kPlanesDefaultTile, rank = 0;
+  for (size_t i = 0; i < shapes.size(); ++i) {
+    const TileShape& sh = shapes[i];
+    if (sh.direct != 3) continue;
+    auto it = st.streams_alt.find(np * 64 + (int)i);
+    if (it == st.streams_alt.end() || !it->second.ok) continue;
+    const int r = (sh.bm == want_bm && sh.bn == want_bn) ? 2 : (sh.bm == 128 && sh.bn == 128) ? 1 : 0;
+    if (r > rank) {
+      rank = r;
+      best = (int)i;
+    }
+  }
+  return best;
+}
 
 int planes_tile(const Step& st, bst_precision prec) {
   auto it = st.tile_choice.find(planes_key(prec));
-  return it == st.tile_choice.end() ? kPlanesDefaultTile : it->second;
+  if (it != st.tile_choice.end()) return it->second;
+  return planes_auto_tile(st, prec == BST_BF16X6 ? 3 : 2);
 }
 
 void run_steps_impl(PlanData& P, void* ws, void* const* dptrs, bst_precision prec, hipStream_t s,
@@ -109,8 +142,13 @@ void run_steps_impl(PlanData& P, void* ws, void* const* dptrs, bst_precision pre
     hipError_t e = hipSuccess;
     switch (st.kind) {
       case StepKind::Split: {
-        SplitLaunch l{np, reinterpret_cast<const SplitJob*>(blob + st.off0),
-                      reinterpret_cast<const SplitWork*>(blob + st.off1), dptrs, st.n0};
+        SplitLaunch l{};
+        l.np = np;
+        l.in_f32 = st.reads_psi && P.psi_f32;
+        l.jobs = reinterpret_cast<const SplitJob*>(blob + st.off0);
+        l.work = reinterpret_cast<const SplitWork*>(blob + st.off1);
+        l.ptrs = dptrs;
+        l.nwork = st.n0;
         e = launch_split(l, s);
         break;
       }

@@ -664,6 +664,95 @@ __global__ __launch_bounds__(256) void lanczos_pass_kernel(
   }
 }
 
+// The same pass over a float32 basis (the split forms): two elements per
+// lane, so every row access is 8 bytes.  v_j and w are rounded to float32
+// before they enter the dot products, so the measured projections are those
+// of the rows as stored.  An odd n leaves one padding element in the last
+// pair (rows are padded, z holds n doubles): it is read, never counted.
+template <int NV>
+__global__ __launch_bounds__(256) void lanczos_pass_f32_kernel(
+    float* V, uint32_t ldv, uint32_t n, int j, const double* __restrict__ z,
+    const double* __restrict__ coef, const double* __restrict__ dprev,
+    const double* __restrict__ beta, float* vnext, double* __restrict__ partial) {
+  typedef float fl2 __attribute__((ext_vector_type(2)));
+  constexpr int NR = NV + 2;
+  __shared__ double red[4 * NR];
+  __shared__ double cs[NV], ds[NV];
+  const int tid = threadIdx.x;
+  const double b = j > 0 ? beta[j - 1] : 1.0;
+  const double rb = b > 0.0 ? 1.0 / b : 0.0;
+  for (int k = tid; k < NV; k += 256) {
+    cs[k] = k < j ? coef[k] : 0.0;
+    ds[k] = k < j ? dprev[k] : 0.0;
+  }
+  __syncthreads();
+  const double csj = coef[j];
+  double acc[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+  double accj = 0.0, accw = 0.0;
+  char* Vb = reinterpret_cast<char*>(V);
+  const uint32_t rowb = ldv * 4u;
+  const uint32_t rowj = (uint32_t)j * rowb;
+  const uint32_t npair = (n + 1u) / 2u;
+  const uint32_t stride = gridDim.x * 256u;
+  for (uint32_t p = blockIdx.x * 256u + tid; p < npair; p += stride) {
+    const bool two = 2u * p + 1u < n;
+    fl2 v[NV];
+    uint32_t off = p * 8u;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      v[k] = (k < j) ? __builtin_nontemporal_load(reinterpret_cast<const fl2*>(Vb + off)) : fl2{0.f, 0.f};
+      if (!two) v[k].y = 0.f;
+      off += rowb;
+      asm volatile("" : "+v"(off));
+    }
+    fl2* uj = reinterpret_cast<fl2*>(Vb + (p * 8u + rowj));
+    const fl2 u = __builtin_nontemporal_load(uj);
+    const double z0 = __builtin_nontemporal_load(z + 2u * p);
+    const double z1 = two ? __builtin_nontemporal_load(z + 2u * p + 1u) : 0.0;
+    double t0 = 0.0, t1 = 0.0, s0 = 0.0, s1 = 0.0;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      t0 += ds[k] * v[k].x;
+      t1 += ds[k] * v[k].y;
+      s0 += cs[k] * v[k].x;
+      s1 += cs[k] * v[k].y;
+    }
+    const float vj0 = (float)((u.x - t0) * rb);
+    const float vj1 = two ? (float)((u.y - t1) * rb) : 0.f;
+    const float w0 = (float)((z0 * rb - s0) - csj * (double)vj0);
+    const float w1 = two ? (float)((z1 * rb - s1) - csj * (double)vj1) : 0.f;
+    __builtin_nontemporal_store(fl2{vj0, vj1}, uj);
+    if (vnext) __builtin_nontemporal_store(fl2{w0, w1}, reinterpret_cast<fl2*>(vnext) + p);
+#pragma unroll
+    for (int k = 0; k < NV; ++k) acc[k] += (double)v[k].x * w0 + (double)v[k].y * w1;
+    accj += (double)vj0 * w0 + (double)vj1 * w1;
+    accw += (double)w0 * w0 + (double)w1 * w1;
+  }
+  const int wave = tid >> 6, lane = tid & 63;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    if (k < j) {
+      const double r = wave_sum(acc[k]);
+      if (lane == 0) red[wave * NR + k] = r;
+    }
+  }
+  {
+    const double r1 = wave_sum(accj);
+    const double r2 = wave_sum(accw);
+    if (lane == 0) {
+      red[wave * NR + j] = r1;
+      red[wave * NR + j + 1] = r2;
+    }
+  }
+  __syncthreads();
+  for (int k = tid; k < j + 2; k += 256) {
+    const double r = ((red[k] + red[NR + k]) + red[2 * NR + k]) + red[3 * NR + k];
+    partial[(int64_t)k * gridDim.x + blockIdx.x] = r;
+  }
+}
+
 // End of step j: dn = (V_j^T w, w.w).  alpha_j = aest + dn_j (the lagged
 // projection's share along v_j); beta_j^2 = w.w - |dn|^2 (the norm of w once
 // projected); dprev <- dn.
@@ -707,14 +796,28 @@ hipError_t launch_lanczos_pass(double* V, int64_t ldv, int64_t n, int j, const d
   return hipGetLastError();
 }
 
+hipError_t launch_lanczos_pass(float* V, int64_t ldv, int64_t n, int j, const double* z,
+                               const double* coef, const double* dprev, const double* beta,
+                               float* vnext, double* partial, double* dn, hipStream_t s) {
+  if (j < 0 || j + 2 > kMaxVecs + 1 || n > 0x7FFFFFFF || ldv > 0x7FFFFFFF || ldv % 2 ||
+      (uint64_t)ldv * (uint64_t)(j + 1) * 4u >= 0xFFFFFFFFull)
+    return hipErrorInvalidValue;
+  const int G = vec_grid((n + 1) / 2);
+  const int nv = j > 0 ? j : 1;
+  BST_NV_DISPATCH(lanczos_pass_f32_kernel, dim3(G), dim3(256), 0, s, V, (uint32_t)ldv, (uint32_t)n, j,
+                  z, coef, dprev, beta, vnext, partial);
+  hipLaunchKernelGGL(reduce_partials_kernel, dim3(j + 2), dim3(256), 0, s, partial, G, dn);
+  return hipGetLastError();
+}
+
 hipError_t launch_lanczos_end(const double* dn, const double* aest, int j, double* dprev,
                               double* alpha, double* beta, hipStream_t s) {
   hipLaunchKernelGGL(lanczos_end_kernel, dim3(1), dim3(64), 0, s, dn, aest, j, dprev, alpha, beta);
   return hipGetLastError();
 }
 
-template <int NV>
-__global__ __launch_bounds__(256) void combine_kernel(const double* __restrict__ V, int64_t ldv,
+template <int NV, typename TV>
+__global__ __launch_bounds__(256) void combine_kernel(const TV* __restrict__ V, int64_t ldv,
                                                       int64_t n, int nv,
                                                       const double* __restrict__ coef,
                                                       double* __restrict__ y) {
@@ -726,53 +829,84 @@ __global__ __launch_bounds__(256) void combine_kernel(const double* __restrict__
     double s = 0.0;
 #pragma unroll
     for (int k = 0; k < NV; ++k)
-      if (k < nv) s += cs[k] * V[k * ldv + i];
+      if (k < nv) s += cs[k] * (double)V[k * ldv + i];
     y[i] = s;
   }
 }
 
-hipError_t launch_combine(const double* V, int64_t ldv, int64_t n, int nv, const double* coef,
-                          double* y, hipStream_t s) {
+template <typename TV>
+static hipError_t combine_impl(const TV* V, int64_t ldv, int64_t n, int nv, const double* coef, double* y,
+                               hipStream_t s) {
   if (nv < 1 || nv > kMaxVecs) return hipErrorInvalidValue;
   const int G = vec_grid(n);
-  BST_NV_DISPATCH(combine_kernel, dim3(G), dim3(256), 0, s, V, ldv, n, nv, coef, y);
+#define BST_CMB(NV_) hipLaunchKernelGGL((combine_kernel<NV_, TV>), dim3(G), dim3(256), 0, s, V, ldv, n, nv, coef, y)
+  if (nv <= 8) BST_CMB(8);
+  else if (nv <= 16) BST_CMB(16);
+  else if (nv <= 32) BST_CMB(32);
+  else if (nv <= 64) BST_CMB(64);
+  else BST_CMB(128);
+#undef BST_CMB
   return hipGetLastError();
 }
+hipError_t launch_combine(const double* V, int64_t ldv, int64_t n, int nv, const double* coef,
+                          double* y, hipStream_t s) {
+  return combine_impl(V, ldv, n, nv, coef, y, s);
+}
+hipError_t launch_combine(const float* V, int64_t ldv, int64_t n, int nv, const double* coef,
+                          double* y, hipStream_t s) {
+  return combine_impl(V, ldv, n, nv, coef, y, s);
+}
 
+template <typename TD>
 __global__ __launch_bounds__(256) void scale_rnorm_kernel(const double* __restrict__ src,
                                                           const double* __restrict__ norm2,
-                                                          double* __restrict__ dst, int64_t n) {
+                                                          TD* __restrict__ dst, int64_t n) {
   const double q = norm2[0];
   const double f = q > 0.0 ? 1.0 / sqrt(q) : 0.0;
   const int64_t stride = (int64_t)gridDim.x * 256;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) dst[i] = src[i] * f;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) dst[i] = (TD)(src[i] * f);
 }
 
 hipError_t launch_scale_rnorm(const double* src, const double* norm2, double* dst, int64_t n,
                               hipStream_t s) {
-  hipLaunchKernelGGL(scale_rnorm_kernel, dim3(vec_grid(n)), dim3(256), 0, s, src, norm2, dst, n);
+  hipLaunchKernelGGL(scale_rnorm_kernel<double>, dim3(vec_grid(n)), dim3(256), 0, s, src, norm2, dst, n);
+  return hipGetLastError();
+}
+hipError_t launch_scale_rnorm(const double* src, const double* norm2, float* dst, int64_t n,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(scale_rnorm_kernel<float>, dim3(vec_grid(n)), dim3(256), 0, s, src, norm2, dst, n);
   return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) void dot2_kernel(const double* __restrict__ x,
+template <typename TX>
+__global__ __launch_bounds__(256) void dot2_kernel(const TX* __restrict__ x,
                                                    const double* __restrict__ y, int64_t n,
                                                    double* __restrict__ partial) {
   __shared__ double red[4 * 2];
   double acc[2] = {0.0, 0.0};
   const int64_t stride = (int64_t)gridDim.x * 256;
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
-    acc[0] += x[i] * y[i];
+    acc[0] += (double)x[i] * y[i];
     acc[1] += y[i] * y[i];
   }
   block_reduce_store<2>(acc, 2, red, partial);
 }
 
-hipError_t launch_dot2(const double* x, const double* y, int64_t n, double* partial, double* out,
-                       hipStream_t s) {
+template <typename TX>
+static hipError_t dot2_impl(const TX* x, const double* y, int64_t n, double* partial, double* out,
+                            hipStream_t s) {
   const int G = vec_grid(n);
-  hipLaunchKernelGGL(dot2_kernel, dim3(G), dim3(256), 0, s, x, y, n, partial);
+  hipLaunchKernelGGL(dot2_kernel<TX>, dim3(G), dim3(256), 0, s, x, y, n, partial);
   if (out) hipLaunchKernelGGL(reduce_partials_kernel, dim3(2), dim3(256), 0, s, partial, G, out);
   return hipGetLastError();
+}
+hipError_t launch_dot2(const double* x, const double* y, int64_t n, double* partial, double* out,
+                       hipStream_t s) {
+  return dot2_impl(x, y, n, partial, out, s);
+}
+hipError_t launch_dot2(const float* x, const double* y, int64_t n, double* partial, double* out,
+                       hipStream_t s) {
+  return dot2_impl(x, y, n, partial, out, s);
 }
 
 __global__ __launch_bounds__(256) void resid_kernel(const double* __restrict__ hy,

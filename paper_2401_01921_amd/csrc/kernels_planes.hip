@@ -41,7 +41,7 @@ __device__ __forceinline__ void split_planes(float a, unsigned short* h) {
 // ------------------------------------------------------------------------
 // float64 blocks -> bfloat16 planes (optionally transposed), 64x64 tiles
 // ------------------------------------------------------------------------
-template <int NP>
+template <int NP, typename TI>
 __global__ __launch_bounds__(256) void split_kernel(const SplitJob* __restrict__ jobs,
                                                     const SplitWork* __restrict__ work,
                                                     void* const* __restrict__ ptrs) {
@@ -51,7 +51,7 @@ __global__ __launch_bounds__(256) void split_kernel(const SplitJob* __restrict__
   __shared__ double tile[64][65];
   const SplitWork w = work[blockIdx.x];
   const SplitJob j = jobs[w.job];
-  const BST_G double* __restrict__ in = (const BST_G double*)(ptrs[j.in_buf]) + j.in_off;
+  const BST_G TI* __restrict__ in = (const BST_G TI*)(ptrs[j.in_buf]) + j.in_off;
   BST_G unsigned short* __restrict__ out = (BST_G unsigned short*)(ptrs[j.out_buf]);
   const int tid = threadIdx.x;
   const int orow = tid >> 3, ocol = (tid & 7) * 8;   // 32 rows x 8 vectors per pass
@@ -64,7 +64,7 @@ __global__ __launch_bounds__(256) void split_kernel(const SplitJob* __restrict__
         us8 h[3];
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-          const double v = (c + e) < j.cols ? in[(int64_t)r * j.cols + c + e] : 0.0;
+          const double v = (c + e) < j.cols ? (double)in[(int64_t)r * j.cols + c + e] : 0.0;
           unsigned short t[3];
           split_planes<NP>(v, t);
 #pragma unroll
@@ -81,7 +81,7 @@ __global__ __launch_bounds__(256) void split_kernel(const SplitJob* __restrict__
   for (int e = tid; e < 64 * 64; e += 256) {
     const int r = e / 64, c = e % 64;
     const int gr = w.r0 + r, gc = w.c0 + c;
-    tile[r][c] = (gr < j.rows && gc < j.cols) ? in[(int64_t)gr * j.cols + gc] : 0.0;
+    tile[r][c] = (gr < j.rows && gc < j.cols) ? (double)in[(int64_t)gr * j.cols + gc] : 0.0;
   }
   __syncthreads();
 #pragma unroll
@@ -107,10 +107,15 @@ __global__ __launch_bounds__(256) void split_kernel(const SplitJob* __restrict__
 hipError_t launch_split(const SplitLaunch& l, hipStream_t s) {
   if (l.nwork <= 0) return hipSuccess;
   if (l.nwork > 0x7FFFFFFF) return hipErrorInvalidValue;
-  if (l.np == 2)
-    hipLaunchKernelGGL(split_kernel<2>, dim3((unsigned)l.nwork), dim3(256), 0, s, l.jobs, l.work, l.ptrs);
+  const dim3 grid((unsigned)l.nwork), block(256);
+  if (l.np == 2 && !l.in_f32)
+    hipLaunchKernelGGL((split_kernel<2, double>), grid, block, 0, s, l.jobs, l.work, l.ptrs);
+  else if (l.np == 2)
+    hipLaunchKernelGGL((split_kernel<2, float>), grid, block, 0, s, l.jobs, l.work, l.ptrs);
+  else if (l.np == 3 && !l.in_f32)
+    hipLaunchKernelGGL((split_kernel<3, double>), grid, block, 0, s, l.jobs, l.work, l.ptrs);
   else if (l.np == 3)
-    hipLaunchKernelGGL(split_kernel<3>, dim3((unsigned)l.nwork), dim3(256), 0, s, l.jobs, l.work, l.ptrs);
+    hipLaunchKernelGGL((split_kernel<3, float>), grid, block, 0, s, l.jobs, l.work, l.ptrs);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

@@ -1,11 +1,14 @@
 // Lanczos ground state of a two-site H_eff (Sec. "Eigenvalue decomposition":
 // the lowest eigenpair of a Hermitian linear operator given as a matvec).
 //
-// The matvec runs in the requested arithmetic form; everything else is
-// float64: two passes of classical Gram-Schmidt against all Krylov vectors
-// per step, the tridiagonal eigensolve on the host, the Ritz vector and the
-// Rayleigh-quotient refinement with one float64 apply.  All vectors stay in
-// the caller's workspace; alpha/beta stay on the device until the end, so a
+// The matvec runs in the requested arithmetic form; the reorthogonalisation
+// against all Krylov vectors, the scalars, the tridiagonal eigensolve (on
+// the host), the Ritz vector and the Rayleigh-quotient refinement with one
+// float64 apply run in float64.  With the split matvec forms the Krylov
+// rows themselves are stored in float32 (rounding them adds 6e-8 per
+// element, far below the matvec's own 2^-17 error; every dot product and
+// scalar stays float64); otherwise in float64.  All vectors stay in the
+// caller's workspace; alpha/beta stay on the device until the end, so a
 // step costs no host round trip.
 #include <hip/hip_runtime.h>
 
@@ -223,7 +226,14 @@ bst_status bst_lanczos_ground(bst_plan* heff, const void* const* ops, const void
   const int64_t ldv = Lo.ldv;
   if ((uint64_t)ldv * (uint64_t)nsteps * 8u >= 0xFFFFFFFFull)
     fail(BST_E_INVALID, "Krylov basis above 4 GiB (reduce nsteps)");
+  const bool three_pass = info && (info->flags & BST_LANCZOS_THREE_PASS);
+  // Krylov rows: float32 with the split forms and the one-pass schedule
+  const bool vf32 = !three_pass && (matvec_prec == BST_BF16X3 || matvec_prec == BST_BF16X6);
   double* V = reinterpret_cast<double*>(wb + Lo.V);
+  float* V32 = reinterpret_cast<float*>(wb + Lo.V);
+  auto row = [&](int j) -> void* {
+    return vf32 ? static_cast<void*>(V32 + (size_t)j * ldv) : static_cast<void*>(V + (size_t)j * ldv);
+  };
   double* W = reinterpret_cast<double*>(wb + Lo.W);
   double* Y = reinterpret_cast<double*>(wb + Lo.Y);
   double* HY = reinterpret_cast<double*>(wb + Lo.HY);
@@ -237,7 +247,6 @@ bst_status bst_lanczos_ground(bst_plan* heff, const void* const* ops, const void
                                       // [8..9] u_j.z, z.z, [10] alpha estimate
   double* cproj = misc + 16;
   double* dn = cproj + kMaxVecs;
-  const bool three_pass = info && (info->flags & BST_LANCZOS_THREE_PASS);
   double* partial = reinterpret_cast<double*>(wb + Lo.partial);
 
   // plan tables, and one pointer table per Krylov vector plus the refinement
@@ -246,8 +255,7 @@ bst_status bst_lanczos_ground(bst_plan* heff, const void* const* ops, const void
   prepare_ws(P, in0, out0, ws, s);
   std::vector<void* const*> tables;
   for (int j = 0; j <= nsteps; ++j) {
-    const void* in[5] = {ops[0], ops[1], ops[2], ops[3], j < nsteps ? (const void*)(V + (size_t)j * ldv)
-                                                                    : (const void*)Y};
+    const void* in[5] = {ops[0], ops[1], ops[2], ops[3], j < nsteps ? (const void*)row(j) : (const void*)Y};
     void* out[1] = {j < nsteps ? (void*)W : (void*)HY};
     auto ptrs = build_ptrs(P, in, out, ws);
     const size_t off = Lo.tables + sizeof(void*) * (size_t)Lo.nslots * (size_t)j;
@@ -282,8 +290,17 @@ bst_status bst_lanczos_ground(bst_plan* heff, const void* const* ops, const void
     check_hip(launch_dot2(static_cast<const double*>(psi0), static_cast<const double*>(psi0), n,
                           partial, misc, s),
               "norm");
-    check_hip(launch_scale_rnorm(static_cast<const double*>(psi0), misc + 1, V, n, s), "scale");
+    if (vf32)
+      check_hip(launch_scale_rnorm(static_cast<const double*>(psi0), misc + 1, V32, n, s), "scale");
+    else
+      check_hip(launch_scale_rnorm(static_cast<const double*>(psi0), misc + 1, V, n, s), "scale");
   });
+  // the split of psi reads float32 rows while the solve runs
+  struct Psi32 {
+    PlanData& P;
+    Psi32(PlanData& p, bool on) : P(p) { P.psi_f32 = on; }
+    ~Psi32() { P.psi_f32 = false; }
+  } psi32(P, vf32);
   for (int j = 0; j < nsteps; ++j) {
     matvec(tables[j], matvec_prec, j > 0);
     const int nv = j + 1;
@@ -301,15 +318,24 @@ bst_status bst_lanczos_ground(bst_plan* heff, const void* const* ops, const void
       // row j holds u_j, W = H u_j: one dot, the step's scalars, then one
       // pass over rows 0..j that finishes v_j and measures the residual
       timed(4, [&] {
-        check_hip(launch_dot2(V + (size_t)j * ldv, W, n, partial, misc + 8, s), "u.z");
+        if (vf32)
+          check_hip(launch_dot2(V32 + (size_t)j * ldv, W, n, partial, misc + 8, s), "u.z");
+        else
+          check_hip(launch_dot2(V + (size_t)j * ldv, W, n, partial, misc + 8, s), "u.z");
       });
       timed(7, [&] {
         check_hip(launch_lanczos_coef(j, misc + 8, alpha, beta, d, cproj, misc + 10, s),
                   "step scalars");
       });
       timed(5, [&] {
-        check_hip(launch_lanczos_pass(V, ldv, n, j, W, cproj, d, beta, vnext, partial, dn, s),
-                  "basis pass");
+        if (vf32)
+          check_hip(launch_lanczos_pass(V32, ldv, n, j, W, cproj, d, beta,
+                                        j + 1 < nsteps ? V32 + (size_t)(j + 1) * ldv : nullptr, partial,
+                                        dn, s),
+                    "basis pass");
+        else
+          check_hip(launch_lanczos_pass(V, ldv, n, j, W, cproj, d, beta, vnext, partial, dn, s),
+                    "basis pass");
       });
       timed(7, [&] { check_hip(launch_lanczos_end(dn, misc + 10, j, d, alpha, beta, s), "step end"); });
     }
@@ -337,7 +363,13 @@ bst_status bst_lanczos_ground(bst_plan* heff, const void* const* ops, const void
   lowest_eigenpair(a, b, theta, sv);
   check_hip(hipMemcpyAsync(svec, sv.data(), sizeof(double) * m, hipMemcpyHostToDevice, s), "h2d");
   check_hip(hipStreamSynchronize(s), "h2d sync");
-  timed(7, [&] { check_hip(launch_combine(V, ldv, n, m, svec, Y, s), "ritz vector"); });
+  psi32.P.psi_f32 = false;   // the refinement applies to the float64 Ritz vector
+  timed(7, [&] {
+    if (vf32)
+      check_hip(launch_combine(V32, ldv, n, m, svec, Y, s), "ritz vector");
+    else
+      check_hip(launch_combine(V, ldv, n, m, svec, Y, s), "ritz vector");
+  });
   double E = theta, resid = -1.0;
   if (refine) {
     matvec(tables[nsteps], BST_FP64, false);

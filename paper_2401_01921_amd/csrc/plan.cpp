@@ -505,6 +505,7 @@ static void heff_plan(const TensorDesc& L, const TensorDesc& W1, const TensorDes
   add_split_jobs(spL, L, 2, false, Lp, 0, 8);
   add_split_jobs(spR, R, 1, false, Rp, 3, 9);
   add_split_jobs(spP, psi, 1, true, Pp, 4, 10);
+  spP.reads_psi = true;
   spL.constant = spR.constant = true;
 
   // merged T1 layout of the plane variant (filled with step 1)

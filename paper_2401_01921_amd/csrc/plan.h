@@ -78,6 +78,9 @@ struct Step {
   std::vector<SplitWork> swork;
   // operand-only preparation, valid for as long as L, W and R do not change
   bool constant = false;
+  // the split of the H_eff input psi (reads float32 rows while the plan runs
+  // inside a float32-basis Lanczos solve)
+  bool reads_psi = false;
   // device table offsets inside the plan blob (filled by finalize)
   size_t off0 = 0, off1 = 0, off2 = 0, off3 = 0, off4 = 0, off5 = 0;
   int64_t n0 = 0, n1 = 0;
@@ -119,6 +122,7 @@ struct PlanData {
   bool finalized = false;
   // execution state
   bool use_graph = false;
+  bool psi_f32 = false;         // set by Lanczos: the psi input is a float32 Krylov row
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph = nullptr;
   void* graph_ws = nullptr;
