@@ -711,6 +711,9 @@ __global__ __launch_bounds__(256) void lanczos_pass_f32_kernel(
     const fl2 u = __builtin_nontemporal_load(uj);
     const double z0 = __builtin_nontemporal_load(z + 2u * p);
     const double z1 = two ? __builtin_nontemporal_load(z + 2u * p + 1u) : 0.0;
+    // Register budget (two waves per SIMD): the coefficients are read from
+    // LDS eight rows at a time, and the float64 images of the rows are formed
+    // again for the dot products instead of being kept from this loop.
     double t0 = 0.0, t1 = 0.0, s0 = 0.0, s1 = 0.0;
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
@@ -718,7 +721,10 @@ __global__ __launch_bounds__(256) void lanczos_pass_f32_kernel(
       t1 += ds[k] * v[k].y;
       s0 += cs[k] * v[k].x;
       s1 += cs[k] * v[k].y;
+      if (k % 8 == 7) __builtin_amdgcn_sched_barrier(0);
     }
+#pragma unroll
+    for (int k = 0; k < NV; ++k) asm volatile("" : "+v"(v[k]));
     const float vj0 = (float)((u.x - t0) * rb);
     const float vj1 = two ? (float)((u.y - t1) * rb) : 0.f;
     const float w0 = (float)((z0 * rb - s0) - csj * (double)vj0);
@@ -816,34 +822,62 @@ hipError_t launch_lanczos_end(const double* dn, const double* aest, int j, doubl
   return hipGetLastError();
 }
 
+// y = sum_{k<nv} coef_k V_k (the Ritz vector).  Two elements per lane, one
+// 8- or 16-byte load per basis row, 32-bit byte offsets (the launcher checks
+// that nv rows fit); rows are padded to an even length, so the second element
+// of the last pair is inside the row even when n is odd (it is not stored).
 template <int NV, typename TV>
-__global__ __launch_bounds__(256) void combine_kernel(const TV* __restrict__ V, int64_t ldv,
-                                                      int64_t n, int nv,
+__global__ __launch_bounds__(256) void combine_kernel(const TV* __restrict__ V, uint32_t ldv,
+                                                      uint32_t n, int nv,
                                                       const double* __restrict__ coef,
                                                       double* __restrict__ y) {
+  typedef TV tv2 __attribute__((ext_vector_type(2)));
   __shared__ double cs[NV];
   for (int k = threadIdx.x; k < NV; k += 256) cs[k] = (k < nv) ? coef[k] : 0.0;
   __syncthreads();
-  const int64_t stride = (int64_t)gridDim.x * 256;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
-    double s = 0.0;
+  const char* Vb = reinterpret_cast<const char*>(V);
+  const uint32_t rowb = ldv * (uint32_t)sizeof(TV);
+  const uint32_t npair = (n + 1u) / 2u;
+  const uint32_t stride = gridDim.x * 256u;
+  for (uint32_t p = blockIdx.x * 256u + threadIdx.x; p < npair; p += stride) {
+    tv2 v[NV];
+    uint32_t off = p * (uint32_t)sizeof(tv2);
 #pragma unroll
-    for (int k = 0; k < NV; ++k)
-      if (k < nv) s += cs[k] * (double)V[k * ldv + i];
-    y[i] = s;
+    for (int k = 0; k < NV; ++k) {
+      v[k] = (k < nv) ? __builtin_nontemporal_load(reinterpret_cast<const tv2*>(Vb + off)) : tv2{0, 0};
+      off += rowb;
+      asm volatile("" : "+v"(off));
+    }
+    double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      s0 += cs[k] * (double)v[k].x;
+      s1 += cs[k] * (double)v[k].y;
+      if (k % 8 == 7) __builtin_amdgcn_sched_barrier(0);
+    }
+    y[2u * p] = s0;
+    if (2u * p + 1u < n) y[2u * p + 1u] = s1;
   }
 }
 
 template <typename TV>
 static hipError_t combine_impl(const TV* V, int64_t ldv, int64_t n, int nv, const double* coef, double* y,
                                hipStream_t s) {
-  if (nv < 1 || nv > kMaxVecs) return hipErrorInvalidValue;
-  const int G = vec_grid(n);
-#define BST_CMB(NV_) hipLaunchKernelGGL((combine_kernel<NV_, TV>), dim3(G), dim3(256), 0, s, V, ldv, n, nv, coef, y)
+  if (nv < 1 || nv > kMaxVecs || n > 0x7FFFFFFF || ldv > 0x7FFFFFFF || ldv % 2 || ldv < n ||
+      (uint64_t)ldv * (uint64_t)nv * sizeof(TV) >= 0xFFFFFFFFull)
+    return hipErrorInvalidValue;
+  if (n == 0) return hipSuccess;
+  const int G = vec_grid((n + 1) / 2);
+#define BST_CMB(NV_) \
+  hipLaunchKernelGGL((combine_kernel<NV_, TV>), dim3(G), dim3(256), 0, s, V, (uint32_t)ldv, (uint32_t)n, nv, coef, y)
   if (nv <= 8) BST_CMB(8);
   else if (nv <= 16) BST_CMB(16);
+  else if (nv <= 24) BST_CMB(24);
   else if (nv <= 32) BST_CMB(32);
+  else if (nv <= 40) BST_CMB(40);
+  else if (nv <= 48) BST_CMB(48);
   else if (nv <= 64) BST_CMB(64);
+  else if (nv <= 96) BST_CMB(96);
   else BST_CMB(128);
 #undef BST_CMB
   return hipGetLastError();

@@ -48,7 +48,7 @@ __global__ __launch_bounds__(256) void split_kernel(const SplitJob* __restrict__
   // One 64 x 64 tile of the output per workgroup; every lane converts 8
   // consecutive output elements and writes them as one 16-byte vector per
   // plane (output rows are padded to 8, so the vectors are aligned).
-  __shared__ double tile[64][65];
+  __shared__ TI tile[64][65];   // input type: a float32 tile leaves room for 8 workgroups per CU
   const SplitWork w = work[blockIdx.x];
   const SplitJob j = jobs[w.job];
   const BST_G TI* __restrict__ in = (const BST_G TI*)(ptrs[j.in_buf]) + j.in_off;
@@ -81,7 +81,7 @@ __global__ __launch_bounds__(256) void split_kernel(const SplitJob* __restrict__
   for (int e = tid; e < 64 * 64; e += 256) {
     const int r = e / 64, c = e % 64;
     const int gr = w.r0 + r, gc = w.c0 + c;
-    tile[r][c] = (gr < j.rows && gc < j.cols) ? (double)in[(int64_t)gr * j.cols + gc] : 0.0;
+    tile[r][c] = (gr < j.rows && gc < j.cols) ? in[(int64_t)gr * j.cols + gc] : (TI)0;
   }
   __syncthreads();
 #pragma unroll
