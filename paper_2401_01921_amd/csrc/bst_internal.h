@@ -366,6 +366,21 @@ hipError_t launch_lanczos_pass(double* V, int64_t ldv, int64_t n, int j, const d
 hipError_t launch_lanczos_pass(float* V, int64_t ldv, int64_t n, int j, const double* z,
                                const double* coef, const double* dprev, const double* beta,
                                float* vnext, double* partial, double* dn, hipStream_t s);
+// The u_j.z dot and the scalar work of step j in two launches (dot partials,
+// then one block that sums them and the partials of the pass of step j - 1,
+// ends step j - 1 and forms the scalars of step j); dn null in
+// launch_lanczos_pass skips that pass's own sums, which this call (or
+// launch_lanczos_pass_sums after the last step) then forms.
+hipError_t launch_lanczos_dot_step(const double* x, const double* z, int64_t n, double* dpart,
+                                   const double* ppart, int pj, double* dn, int j, double* g,
+                                   double* alpha, double* beta, double* dprev, double* coef,
+                                   double* aest, hipStream_t s);
+hipError_t launch_lanczos_dot_step(const float* x, const double* z, int64_t n, double* dpart,
+                                   const double* ppart, int pj, double* dn, int j, double* g,
+                                   double* alpha, double* beta, double* dprev, double* coef,
+                                   double* aest, hipStream_t s);
+hipError_t launch_lanczos_pass_sums(int64_t n, int j, bool f32, const double* partial, double* dn,
+                                   hipStream_t s);
 hipError_t launch_lanczos_end(const double* dn, const double* aest, int j, double* dprev,
                               double* alpha, double* beta, hipStream_t s);
 // alpha[j] = c[j] + d[j]; beta[j] = sqrt(norm2[0])

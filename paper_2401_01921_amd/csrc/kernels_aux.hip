@@ -346,17 +346,28 @@ __device__ __forceinline__ void block_reduce_store(double (&acc)[NV], int nv, do
   }
 }
 
-// out[k] = sum_b partial[k*G + b]  (one block per k, fixed order)
-__global__ __launch_bounds__(256) void reduce_partials_kernel(const double* __restrict__ partial,
-                                                              int G, double* __restrict__ out) {
-  __shared__ double red[4];
-  const int k = blockIdx.x, tid = threadIdx.x;
+// sum_b partial[k*G + b] in a fixed order (thread-strided sums, wave sums,
+// the four waves in order).  Called by all 256 threads of a block; every
+// thread gets the sum.  red: 4 doubles of LDS.
+__device__ __forceinline__ double block_sum_partials(const double* __restrict__ partial, int G, int k,
+                                                     double* red) {
+  const int tid = threadIdx.x;
   double s = 0.0;
   for (int b = tid; b < G; b += 256) s += partial[(int64_t)k * G + b];
   s = wave_sum(s);
   if ((tid & 63) == 0) red[tid >> 6] = s;
   __syncthreads();
-  if (tid == 0) out[k] = ((red[0] + red[1]) + red[2]) + red[3];
+  const double r = ((red[0] + red[1]) + red[2]) + red[3];
+  __syncthreads();
+  return r;
+}
+
+// out[k] = sum_b partial[k*G + b]  (one block per k, fixed order)
+__global__ __launch_bounds__(256) void reduce_partials_kernel(const double* __restrict__ partial,
+                                                              int G, double* __restrict__ out) {
+  __shared__ double red[4];
+  const double r = block_sum_partials(partial, G, blockIdx.x, red);
+  if (threadIdx.x == 0) out[blockIdx.x] = r;
 }
 
 static inline int vec_grid(int64_t n) {
@@ -545,22 +556,11 @@ hipError_t launch_lanczos_step_end(const double* partial, int64_t n_for_grid, co
 // and one thread evaluates (fixed order): coef[0..j], the coefficients of
 // v_0..v_j in w = z/beta_{j-1} - sum_k coef_k v_k, and aest, the three-term
 // estimate of alpha_j.
-__global__ __launch_bounds__(64) void lanczos_coef_kernel(int j, const double* __restrict__ g,
-                                                          const double* __restrict__ alpha,
-                                                          const double* __restrict__ beta,
-                                                          const double* __restrict__ dprev,
-                                                          double* __restrict__ coef,
-                                                          double* __restrict__ aest) {
-  __shared__ double al[kMaxVecs], be[kMaxVecs], dp[kMaxVecs];
-  const int lane = threadIdx.x;
-  const double gs = g[0];
-  for (int k = lane; k < j; k += 64) {
-    al[k] = alpha[k];
-    be[k] = beta[k];
-    dp[k] = dprev[k];
-  }
-  __syncthreads();
-  if (lane != 0) return;
+// The scalars of step j (one thread; al, be, dp hold alpha, beta, dprev for
+// k < j).
+__device__ __forceinline__ void step_coef(int j, double gs, const double* al, const double* be,
+                                          const double* dp, double* __restrict__ coef,
+                                          double* __restrict__ aest) {
   const double bp = j > 0 ? be[j - 1] : 1.0;
   const double rb = bp > 0.0 ? 1.0 / bp : 0.0;
   // v_j . z = rb (g - dprev . f), f = (T^T y)_{k<j}, y = (dprev, beta_{j-1})
@@ -583,6 +583,24 @@ __global__ __launch_bounds__(64) void lanczos_coef_kernel(int j, const double* _
   const double a = rb * (vz - ej);
   coef[j] = rb * ej + a;
   aest[0] = a;
+}
+
+__global__ __launch_bounds__(64) void lanczos_coef_kernel(int j, const double* __restrict__ g,
+                                                          const double* __restrict__ alpha,
+                                                          const double* __restrict__ beta,
+                                                          const double* __restrict__ dprev,
+                                                          double* __restrict__ coef,
+                                                          double* __restrict__ aest) {
+  __shared__ double al[kMaxVecs], be[kMaxVecs], dp[kMaxVecs];
+  const int lane = threadIdx.x;
+  const double gs = g[0];
+  for (int k = lane; k < j; k += 64) {
+    al[k] = alpha[k];
+    be[k] = beta[k];
+    dp[k] = dprev[k];
+  }
+  __syncthreads();
+  if (lane == 0) step_coef(j, gs, al, be, dp, coef, aest);
 }
 
 // The pass of step j: per element
@@ -762,6 +780,16 @@ __global__ __launch_bounds__(256) void lanczos_pass_f32_kernel(
 // End of step j: dn = (V_j^T w, w.w).  alpha_j = aest + dn_j (the lagged
 // projection's share along v_j); beta_j^2 = w.w - |dn|^2 (the norm of w once
 // projected); dprev <- dn.
+// alpha_j and beta_j from ds = dn (one thread).
+__device__ __forceinline__ void step_end(const double* ds, double aest, int j, double& alpha_j,
+                                         double& beta_j) {
+  double ss = 0.0;
+  for (int k = 0; k <= j; ++k) ss += ds[k] * ds[k];
+  const double q = ds[j + 1] - ss;
+  alpha_j = aest + ds[j];
+  beta_j = sqrt(q > 0.0 ? q : 0.0);
+}
+
 __global__ __launch_bounds__(64) void lanczos_end_kernel(const double* __restrict__ dn,
                                                          const double* __restrict__ aest, int j,
                                                          double* __restrict__ dprev,
@@ -775,11 +803,78 @@ __global__ __launch_bounds__(64) void lanczos_end_kernel(const double* __restric
   }
   __syncthreads();
   if (lane != 0) return;
-  double ss = 0.0;
-  for (int k = 0; k <= j; ++k) ss += ds[k] * ds[k];
-  const double q = ds[j + 1] - ss;
-  alpha[j] = aest[0] + ds[j];
-  beta[j] = sqrt(q > 0.0 ? q : 0.0);
+  step_end(ds, aest[0], j, alpha[j], beta[j]);
+}
+
+// The scalar work between two basis passes, in one block of 1024 threads:
+// the sums of the partials of the pass of step pj (dn) and of the u_j.z,
+// z.z partials of dot2_kernel (g), then the end of step pj (alpha, beta,
+// dprev as lanczos_end_kernel) and the scalars of step j (as
+// lanczos_coef_kernel).  One wave forms each sum: lane l adds partials l,
+// l + 64, ... in order, then the wave sum; every load of a sum is issued at
+// once (grids of at most 1024 blocks).  pj < 0: no pass before (step 0).
+__global__ __launch_bounds__(1024) void lanczos_step_scalars_kernel(
+    const double* __restrict__ ppart, int pG, int pj, const double* __restrict__ dpart, int dG,
+    int j, double* __restrict__ dn, double* __restrict__ g, double* __restrict__ alpha,
+    double* __restrict__ beta, double* __restrict__ dprev, double* __restrict__ coef,
+    double* __restrict__ aest) {
+  __shared__ double sv[kMaxVecs + 4];
+  __shared__ double al[kMaxVecs], be[kMaxVecs];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int npv = pj >= 0 ? pj + 2 : 0;
+  const int nval = npv + 2;
+  // value v: the partials of row v of the pass (v < npv) or of the dot
+  auto row_of = [&](int v, int& G) -> const double* {
+    G = v < npv ? pG : dG;
+    return v < npv ? ppart + (int64_t)v * pG : dpart + (int64_t)(v - npv) * dG;
+  };
+  // values wave, wave + 16, wave + 32: all loads in flight together
+  double x[3][16];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const int v = wave + 16 * r;
+    int G = 0;
+    const double* __restrict__ src = row_of(v < nval ? v : 0, G);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) x[r][i] = (v < nval && lane + 64 * i < G) ? src[lane + 64 * i] : 0.0;
+  }
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) s += x[r][i];
+    s = wave_sum(s);
+    if (wave + 16 * r < nval && lane == 0) sv[wave + 16 * r] = s;
+  }
+  // more than 48 values (long solves): the same sums, one value at a time
+  for (int v = wave + 48; v < nval; v += 16) {
+    int G = 0;
+    const double* __restrict__ src = row_of(v, G);
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) s += lane + 64 * i < G ? src[lane + 64 * i] : 0.0;
+    s = wave_sum(s);
+    if (lane == 0) sv[v] = s;
+  }
+  for (int k = tid; k < pj; k += 1024) {
+    al[k] = alpha[k];
+    be[k] = beta[k];
+  }
+  __syncthreads();
+  // sv[0..npv) = dn of step pj, sv[npv] = u_j.z, sv[npv + 1] = z.z
+  for (int k = tid; k < npv; k += 1024) {
+    dn[k] = sv[k];
+    if (k <= pj) dprev[k] = sv[k];
+  }
+  if (tid != 0) return;
+  if (pj >= 0) {
+    step_end(sv, aest[0], pj, al[pj], be[pj]);
+    alpha[pj] = al[pj];
+    beta[pj] = be[pj];
+  }
+  g[0] = sv[npv];
+  g[1] = sv[npv + 1];
+  step_coef(j, sv[npv], al, be, sv, coef, aest);
 }
 
 hipError_t launch_lanczos_coef(int j, const double* g, const double* alpha, const double* beta,
@@ -798,7 +893,7 @@ hipError_t launch_lanczos_pass(double* V, int64_t ldv, int64_t n, int j, const d
   const int nv = j > 0 ? j : 1;
   BST_NV_DISPATCH(lanczos_pass_kernel, dim3(G), dim3(256), 0, s, V, (uint32_t)ldv, (uint32_t)n, j,
                   z, coef, dprev, beta, vnext, partial);
-  hipLaunchKernelGGL(reduce_partials_kernel, dim3(j + 2), dim3(256), 0, s, partial, G, dn);
+  if (dn) hipLaunchKernelGGL(reduce_partials_kernel, dim3(j + 2), dim3(256), 0, s, partial, G, dn);
   return hipGetLastError();
 }
 
@@ -812,6 +907,14 @@ hipError_t launch_lanczos_pass(float* V, int64_t ldv, int64_t n, int j, const do
   const int nv = j > 0 ? j : 1;
   BST_NV_DISPATCH(lanczos_pass_f32_kernel, dim3(G), dim3(256), 0, s, V, (uint32_t)ldv, (uint32_t)n, j,
                   z, coef, dprev, beta, vnext, partial);
+  if (dn) hipLaunchKernelGGL(reduce_partials_kernel, dim3(j + 2), dim3(256), 0, s, partial, G, dn);
+  return hipGetLastError();
+}
+
+hipError_t launch_lanczos_pass_sums(int64_t n, int j, bool f32, const double* partial, double* dn,
+                                   hipStream_t s) {
+  if (j < 0 || j + 2 > kMaxVecs + 1 || n < 0) return hipErrorInvalidValue;
+  const int G = f32 ? vec_grid((n + 1) / 2) : vec_grid(n);
   hipLaunchKernelGGL(reduce_partials_kernel, dim3(j + 2), dim3(256), 0, s, partial, G, dn);
   return hipGetLastError();
 }
@@ -941,6 +1044,34 @@ hipError_t launch_dot2(const double* x, const double* y, int64_t n, double* part
 hipError_t launch_dot2(const float* x, const double* y, int64_t n, double* partial, double* out,
                        hipStream_t s) {
   return dot2_impl(x, y, n, partial, out, s);
+}
+
+template <typename TX>
+static hipError_t dot_step_impl(const TX* x, const double* z, int64_t n, double* dpart,
+                                const double* ppart, int pj, double* dn, int j, double* g,
+                                double* alpha, double* beta, double* dprev, double* coef,
+                                double* aest, hipStream_t s) {
+  if (j < 0 || j >= kMaxVecs || pj != j - 1 || n < 0) return hipErrorInvalidValue;
+  const int G = vec_grid(n);
+  // the basis pass's grid: one element (float64 rows) or pair (float32) per lane
+  const int pG = sizeof(TX) == 4 ? vec_grid((n + 1) / 2) : vec_grid(n);
+  if (G > 1024 || pG > 1024) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(dot2_kernel<TX>, dim3(G), dim3(256), 0, s, x, z, n, dpart);
+  hipLaunchKernelGGL(lanczos_step_scalars_kernel, dim3(1), dim3(1024), 0, s, ppart, pG, pj, dpart, G, j,
+                     dn, g, alpha, beta, dprev, coef, aest);
+  return hipGetLastError();
+}
+hipError_t launch_lanczos_dot_step(const double* x, const double* z, int64_t n, double* dpart,
+                                   const double* ppart, int pj, double* dn, int j, double* g,
+                                   double* alpha, double* beta, double* dprev, double* coef,
+                                   double* aest, hipStream_t s) {
+  return dot_step_impl(x, z, n, dpart, ppart, pj, dn, j, g, alpha, beta, dprev, coef, aest, s);
+}
+hipError_t launch_lanczos_dot_step(const float* x, const double* z, int64_t n, double* dpart,
+                                   const double* ppart, int pj, double* dn, int j, double* g,
+                                   double* alpha, double* beta, double* dprev, double* coef,
+                                   double* aest, hipStream_t s) {
+  return dot_step_impl(x, z, n, dpart, ppart, pj, dn, j, g, alpha, beta, dprev, coef, aest, s);
 }
 
 __global__ __launch_bounds__(256) void resid_kernel(const double* __restrict__ hy,

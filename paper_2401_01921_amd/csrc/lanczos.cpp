@@ -24,7 +24,7 @@ namespace bst {
 namespace {
 
 struct LanczosLayout {
-  size_t tables, V, W, Y, HY, scal, partial, end;
+  size_t tables, V, W, Y, HY, scal, partial, dpart, end;
   int64_t ldv;   // row stride of V: psi's size rounded up to 512 bytes
   int nslots;
 };
@@ -53,6 +53,8 @@ LanczosLayout layout(const PlanData& P, int nsteps) {
   off = al(off + sizeof(double) * (7 * (size_t)kMaxVecs + 32));
   L.partial = off;
   off = al(off + sizeof(double) * (size_t)(kMaxVecs + 1) * kVecBlocks);
+  L.dpart = off;   // partials of the u_j.z dot
+  off = al(off + sizeof(double) * 2 * (size_t)kVecBlocks);
   L.end = off;
   return L;
 }
@@ -248,6 +250,7 @@ bst_status bst_lanczos_ground(bst_plan* heff, const void* const* ops, const void
   double* cproj = misc + 16;
   double* dn = cproj + kMaxVecs;
   double* partial = reinterpret_cast<double*>(wb + Lo.partial);
+  double* dpart = reinterpret_cast<double*>(wb + Lo.dpart);
 
   // plan tables, and one pointer table per Krylov vector plus the refinement
   const void* in0[5] = {ops[0], ops[1], ops[2], ops[3], V};
@@ -315,30 +318,37 @@ bst_status bst_lanczos_ground(bst_plan* heff, const void* const* ops, const void
                   "step end");
       });
     } else {
-      // row j holds u_j, W = H u_j: one dot, the step's scalars, then one
-      // pass over rows 0..j that finishes v_j and measures the residual
+      // row j holds u_j, W = H u_j: one launch for the dot u_j.z, the end
+      // of step j - 1 and the scalars of step j, then one pass over rows
+      // 0..j that finishes v_j and measures the residual
       timed(4, [&] {
         if (vf32)
-          check_hip(launch_dot2(V32 + (size_t)j * ldv, W, n, partial, misc + 8, s), "u.z");
+          check_hip(launch_lanczos_dot_step(V32 + (size_t)j * ldv, W, n, dpart, partial, j - 1, dn, j,
+                                            misc + 8, alpha, beta, d, cproj, misc + 10, s),
+                    "step scalars");
         else
-          check_hip(launch_dot2(V + (size_t)j * ldv, W, n, partial, misc + 8, s), "u.z");
-      });
-      timed(7, [&] {
-        check_hip(launch_lanczos_coef(j, misc + 8, alpha, beta, d, cproj, misc + 10, s),
-                  "step scalars");
+          check_hip(launch_lanczos_dot_step(V + (size_t)j * ldv, W, n, dpart, partial, j - 1, dn, j,
+                                            misc + 8, alpha, beta, d, cproj, misc + 10, s),
+                    "step scalars");
       });
       timed(5, [&] {
         if (vf32)
           check_hip(launch_lanczos_pass(V32, ldv, n, j, W, cproj, d, beta,
                                         j + 1 < nsteps ? V32 + (size_t)(j + 1) * ldv : nullptr, partial,
-                                        dn, s),
+                                        nullptr, s),
                     "basis pass");
         else
-          check_hip(launch_lanczos_pass(V, ldv, n, j, W, cproj, d, beta, vnext, partial, dn, s),
+          check_hip(launch_lanczos_pass(V, ldv, n, j, W, cproj, d, beta, vnext, partial, nullptr, s),
                     "basis pass");
       });
-      timed(7, [&] { check_hip(launch_lanczos_end(dn, misc + 10, j, d, alpha, beta, s), "step end"); });
     }
+  }
+  if (!three_pass) {
+    // the end of the last step
+    timed(7, [&] {
+      check_hip(launch_lanczos_pass_sums(n, nsteps - 1, vf32, partial, dn, s), "step sums");
+      check_hip(launch_lanczos_end(dn, misc + 10, nsteps - 1, d, alpha, beta, s), "step end");
+    });
   }
   std::vector<double> ha(nsteps), hb(nsteps), m0(2);
   check_hip(hipMemcpyAsync(ha.data(), alpha, sizeof(double) * nsteps, hipMemcpyDeviceToHost, s), "d2h");
