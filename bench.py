@@ -168,11 +168,13 @@ def main():
         avg_ms = prof["kernel_ms"][ms_key] / max(calls, 1)
         fl = steps[name]["flops"]
         mult = {"fp64": 1, "fp32": 1, "bf16x3": 3, "bf16x6": 6}[prec]
+        by = steps[name]["bytes_fp32" if prec != "fp64" else "bytes_fp64"]
+        if name == "gemm_T3_R" and prec in ("bf16x3", "bf16x6"):
+            by -= 4.0 * n   # inside the solve H u_j is written as float32
         return dict(kernel=name, avg_ms=avg_ms, alg_tflops=fl / avg_ms / 1e9,
                     mfma_tflops=fl * mult / avg_ms / 1e9, peak_tflops=peak,
                     mfma_frac=fl * mult / avg_ms / 1e9 / peak,
-                    bytes_gbs=(steps[name]["bytes_fp32" if prec != "fp64" else "bytes_fp64"])
-                    / avg_ms / 1e6)
+                    bytes_gbs=by / avg_ms / 1e6)
 
     # Krylov rows are float32 with the split matvec forms, float64 otherwise
     vb = 4.0 if a.prec in ("bf16x3", "bf16x6") else 8.0
@@ -180,15 +182,16 @@ def main():
     def gs_bytes(kind, rowb=None):
         # algorithmic bytes of one solve's Gram-Schmidt kernels (default
         # schedule): the dot reads u_j and z; the pass of step j (0-based)
-        # reads basis rows 0..j and z (float64) and writes row j and (except
-        # on the last step) row j+1
+        # reads basis rows 0..j and z and writes row j and (except on the
+        # last step) row j+1.  z = H u_j has the rows' element type (float32
+        # rows with the split forms, float64 otherwise).
         rb = vb if rowb is None else rowb
         tot = 0.0
         for j in range(m):
             if kind == "dots":
-                tot += (rb + 8.0) * n
+                tot += 2.0 * rb * n
             else:
-                tot += rb * n * (j + 1) + 8.0 * n + rb * n * (2 if j + 1 < m else 1)
+                tot += rb * n * (j + 1) + rb * n + rb * n * (2 if j + 1 < m else 1)
         return tot
 
     def hbm_roof(key, total_bytes, prof):

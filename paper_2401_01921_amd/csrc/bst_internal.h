@@ -363,7 +363,7 @@ hipError_t launch_lanczos_pass(double* V, int64_t ldv, int64_t n, int j, const d
                                double* vnext, double* partial, double* dn, hipStream_t s);
 // The same over a float32 basis (rows rounded to float32 when written; dots
 // and scalars in float64).
-hipError_t launch_lanczos_pass(float* V, int64_t ldv, int64_t n, int j, const double* z,
+hipError_t launch_lanczos_pass(float* V, int64_t ldv, int64_t n, int j, const float* z,
                                const double* coef, const double* dprev, const double* beta,
                                float* vnext, double* partial, double* dn, hipStream_t s);
 // The u_j.z dot and the scalar work of step j in two launches (dot partials,
@@ -375,7 +375,7 @@ hipError_t launch_lanczos_dot_step(const double* x, const double* z, int64_t n, 
                                    const double* ppart, int pj, double* dn, int j, double* g,
                                    double* alpha, double* beta, double* dprev, double* coef,
                                    double* aest, hipStream_t s);
-hipError_t launch_lanczos_dot_step(const float* x, const double* z, int64_t n, double* dpart,
+hipError_t launch_lanczos_dot_step(const float* x, const float* z, int64_t n, double* dpart,
                                    const double* ppart, int pj, double* dn, int j, double* g,
                                    double* alpha, double* beta, double* dprev, double* coef,
                                    double* aest, hipStream_t s);

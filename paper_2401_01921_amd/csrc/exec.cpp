@@ -156,7 +156,7 @@ void run_steps_impl(PlanData& P, void* ws, void* const* dptrs, bst_precision pre
         if (planes && st.has_alt) {
           PlanesLaunch g{};
           g.np = np;
-          g.tc = st.tc == Elem::Inter ? ElemType::F32 : ElemType::F64;
+          g.tc = st.tc == Elem::Inter || (st.writes_out && P.z_f32) ? ElemType::F32 : ElemType::F64;
           g.tile = planes_tile(st, prec);
           if (gemm_planes_shapes(np)[g.tile].direct == 3) {
             auto sit = st.streams_alt.find(np * 64 + g.tile);
@@ -188,6 +188,7 @@ void run_steps_impl(PlanData& P, void* ws, void* const* dptrs, bst_precision pre
           e = launch_gemm_planes(g, s);
           break;
         }
+        if (st.writes_out && P.z_f32) fail(BST_E_INVALID, "internal: float32 output needs the plane path");
         const bst_precision form = st.fixed_fp64 ? BST_FP64 : prec;
         GemmLaunch g{};
         g.form = form;

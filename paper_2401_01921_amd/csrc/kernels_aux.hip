@@ -682,14 +682,14 @@ __global__ __launch_bounds__(256) void lanczos_pass_kernel(
   }
 }
 
-// The same pass over a float32 basis (the split forms): two elements per
-// lane, so every row access is 8 bytes.  v_j and w are rounded to float32
+// The same pass over a float32 basis (the split forms; z float32 too): two
+// elements per lane, so every row access is 8 bytes.  v_j and w are rounded to float32
 // before they enter the dot products, so the measured projections are those
 // of the rows as stored.  An odd n leaves one padding element in the last
 // pair (rows are padded, z holds n doubles): it is read, never counted.
-template <int NV>
+template <int NV, typename TZ>
 __global__ __launch_bounds__(256) void lanczos_pass_f32_kernel(
-    float* V, uint32_t ldv, uint32_t n, int j, const double* __restrict__ z,
+    float* V, uint32_t ldv, uint32_t n, int j, const TZ* __restrict__ z,
     const double* __restrict__ coef, const double* __restrict__ dprev,
     const double* __restrict__ beta, float* vnext, double* __restrict__ partial) {
   typedef float fl2 __attribute__((ext_vector_type(2)));
@@ -727,8 +727,20 @@ __global__ __launch_bounds__(256) void lanczos_pass_f32_kernel(
     }
     fl2* uj = reinterpret_cast<fl2*>(Vb + (p * 8u + rowj));
     const fl2 u = __builtin_nontemporal_load(uj);
-    const double z0 = __builtin_nontemporal_load(z + 2u * p);
-    const double z1 = two ? __builtin_nontemporal_load(z + 2u * p + 1u) : 0.0;
+    double z0, z1;
+    if constexpr (sizeof(TZ) == 4) {
+      if (two) {
+        const fl2 zz = __builtin_nontemporal_load(reinterpret_cast<const fl2*>(z) + p);
+        z0 = zz.x;
+        z1 = zz.y;
+      } else {
+        z0 = __builtin_nontemporal_load(z + 2u * p);
+        z1 = 0.0;
+      }
+    } else {
+      z0 = __builtin_nontemporal_load(z + 2u * p);
+      z1 = two ? __builtin_nontemporal_load(z + 2u * p + 1u) : 0.0;
+    }
     // Register budget (two waves per SIMD): the coefficients are read from
     // LDS eight rows at a time, and the float64 images of the rows are formed
     // again for the dot products instead of being kept from this loop.
@@ -897,7 +909,7 @@ hipError_t launch_lanczos_pass(double* V, int64_t ldv, int64_t n, int j, const d
   return hipGetLastError();
 }
 
-hipError_t launch_lanczos_pass(float* V, int64_t ldv, int64_t n, int j, const double* z,
+hipError_t launch_lanczos_pass(float* V, int64_t ldv, int64_t n, int j, const float* z,
                                const double* coef, const double* dprev, const double* beta,
                                float* vnext, double* partial, double* dn, hipStream_t s) {
   if (j < 0 || j + 2 > kMaxVecs + 1 || n > 0x7FFFFFFF || ldv > 0x7FFFFFFF || ldv % 2 ||
@@ -905,8 +917,19 @@ hipError_t launch_lanczos_pass(float* V, int64_t ldv, int64_t n, int j, const do
     return hipErrorInvalidValue;
   const int G = vec_grid((n + 1) / 2);
   const int nv = j > 0 ? j : 1;
-  BST_NV_DISPATCH(lanczos_pass_f32_kernel, dim3(G), dim3(256), 0, s, V, (uint32_t)ldv, (uint32_t)n, j,
-                  z, coef, dprev, beta, vnext, partial);
+  #define BST_PF32(NV_)                                                                                      \
+  hipLaunchKernelGGL((lanczos_pass_f32_kernel<NV_, float>), dim3(G), dim3(256), 0, s, V, (uint32_t)ldv, \
+                     (uint32_t)n, j, z, coef, dprev, beta, vnext, partial)
+  if (nv <= 8) BST_PF32(8);
+  else if (nv <= 16) BST_PF32(16);
+  else if (nv <= 24) BST_PF32(24);
+  else if (nv <= 32) BST_PF32(32);
+  else if (nv <= 40) BST_PF32(40);
+  else if (nv <= 48) BST_PF32(48);
+  else if (nv <= 64) BST_PF32(64);
+  else if (nv <= 96) BST_PF32(96);
+  else BST_PF32(128);
+#undef BST_PF32
   if (dn) hipLaunchKernelGGL(reduce_partials_kernel, dim3(j + 2), dim3(256), 0, s, partial, G, dn);
   return hipGetLastError();
 }
@@ -1015,16 +1038,17 @@ hipError_t launch_scale_rnorm(const double* src, const double* norm2, float* dst
   return hipGetLastError();
 }
 
-template <typename TX>
+template <typename TX, typename TY>
 __global__ __launch_bounds__(256) void dot2_kernel(const TX* __restrict__ x,
-                                                   const double* __restrict__ y, int64_t n,
+                                                   const TY* __restrict__ y, int64_t n,
                                                    double* __restrict__ partial) {
   __shared__ double red[4 * 2];
   double acc[2] = {0.0, 0.0};
   const int64_t stride = (int64_t)gridDim.x * 256;
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
-    acc[0] += (double)x[i] * y[i];
-    acc[1] += y[i] * y[i];
+    const double yi = (double)y[i];
+    acc[0] += (double)x[i] * yi;
+    acc[1] += yi * yi;
   }
   block_reduce_store<2>(acc, 2, red, partial);
 }
@@ -1033,7 +1057,7 @@ template <typename TX>
 static hipError_t dot2_impl(const TX* x, const double* y, int64_t n, double* partial, double* out,
                             hipStream_t s) {
   const int G = vec_grid(n);
-  hipLaunchKernelGGL(dot2_kernel<TX>, dim3(G), dim3(256), 0, s, x, y, n, partial);
+  hipLaunchKernelGGL((dot2_kernel<TX, double>), dim3(G), dim3(256), 0, s, x, y, n, partial);
   if (out) hipLaunchKernelGGL(reduce_partials_kernel, dim3(2), dim3(256), 0, s, partial, G, out);
   return hipGetLastError();
 }
@@ -1046,8 +1070,8 @@ hipError_t launch_dot2(const float* x, const double* y, int64_t n, double* parti
   return dot2_impl(x, y, n, partial, out, s);
 }
 
-template <typename TX>
-static hipError_t dot_step_impl(const TX* x, const double* z, int64_t n, double* dpart,
+template <typename TX, typename TZ>
+static hipError_t dot_step_impl(const TX* x, const TZ* z, int64_t n, double* dpart,
                                 const double* ppart, int pj, double* dn, int j, double* g,
                                 double* alpha, double* beta, double* dprev, double* coef,
                                 double* aest, hipStream_t s) {
@@ -1056,7 +1080,7 @@ static hipError_t dot_step_impl(const TX* x, const double* z, int64_t n, double*
   // the basis pass's grid: one element (float64 rows) or pair (float32) per lane
   const int pG = sizeof(TX) == 4 ? vec_grid((n + 1) / 2) : vec_grid(n);
   if (G > 1024 || pG > 1024) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(dot2_kernel<TX>, dim3(G), dim3(256), 0, s, x, z, n, dpart);
+  hipLaunchKernelGGL((dot2_kernel<TX, TZ>), dim3(G), dim3(256), 0, s, x, z, n, dpart);
   hipLaunchKernelGGL(lanczos_step_scalars_kernel, dim3(1), dim3(1024), 0, s, ppart, pG, pj, dpart, G, j,
                      dn, g, alpha, beta, dprev, coef, aest);
   return hipGetLastError();
@@ -1067,7 +1091,7 @@ hipError_t launch_lanczos_dot_step(const double* x, const double* z, int64_t n, 
                                    double* aest, hipStream_t s) {
   return dot_step_impl(x, z, n, dpart, ppart, pj, dn, j, g, alpha, beta, dprev, coef, aest, s);
 }
-hipError_t launch_lanczos_dot_step(const float* x, const double* z, int64_t n, double* dpart,
+hipError_t launch_lanczos_dot_step(const float* x, const float* z, int64_t n, double* dpart,
                                    const double* ppart, int pj, double* dn, int j, double* g,
                                    double* alpha, double* beta, double* dprev, double* coef,
                                    double* aest, hipStream_t s) {

@@ -237,6 +237,7 @@ bst_status bst_lanczos_ground(bst_plan* heff, const void* const* ops, const void
     return vf32 ? static_cast<void*>(V32 + (size_t)j * ldv) : static_cast<void*>(V + (size_t)j * ldv);
   };
   double* W = reinterpret_cast<double*>(wb + Lo.W);
+  float* W32 = reinterpret_cast<float*>(wb + Lo.W);   // H u_j with a float32 basis
   double* Y = reinterpret_cast<double*>(wb + Lo.Y);
   double* HY = reinterpret_cast<double*>(wb + Lo.HY);
   double* sc = reinterpret_cast<double*>(wb + Lo.scal);
@@ -298,11 +299,12 @@ bst_status bst_lanczos_ground(bst_plan* heff, const void* const* ops, const void
     else
       check_hip(launch_scale_rnorm(static_cast<const double*>(psi0), misc + 1, V, n, s), "scale");
   });
-  // the split of psi reads float32 rows while the solve runs
+  // with a float32 basis the matvec reads float32 rows and writes H u_j as
+  // float32 while the solve runs
   struct Psi32 {
     PlanData& P;
-    Psi32(PlanData& p, bool on) : P(p) { P.psi_f32 = on; }
-    ~Psi32() { P.psi_f32 = false; }
+    Psi32(PlanData& p, bool on) : P(p) { P.psi_f32 = P.z_f32 = on; }
+    ~Psi32() { P.psi_f32 = P.z_f32 = false; }
   } psi32(P, vf32);
   for (int j = 0; j < nsteps; ++j) {
     matvec(tables[j], matvec_prec, j > 0);
@@ -323,7 +325,7 @@ bst_status bst_lanczos_ground(bst_plan* heff, const void* const* ops, const void
       // 0..j that finishes v_j and measures the residual
       timed(4, [&] {
         if (vf32)
-          check_hip(launch_lanczos_dot_step(V32 + (size_t)j * ldv, W, n, dpart, partial, j - 1, dn, j,
+          check_hip(launch_lanczos_dot_step(V32 + (size_t)j * ldv, W32, n, dpart, partial, j - 1, dn, j,
                                             misc + 8, alpha, beta, d, cproj, misc + 10, s),
                     "step scalars");
         else
@@ -333,7 +335,7 @@ bst_status bst_lanczos_ground(bst_plan* heff, const void* const* ops, const void
       });
       timed(5, [&] {
         if (vf32)
-          check_hip(launch_lanczos_pass(V32, ldv, n, j, W, cproj, d, beta,
+          check_hip(launch_lanczos_pass(V32, ldv, n, j, W32, cproj, d, beta,
                                         j + 1 < nsteps ? V32 + (size_t)(j + 1) * ldv : nullptr, partial,
                                         nullptr, s),
                     "basis pass");
@@ -373,7 +375,7 @@ bst_status bst_lanczos_ground(bst_plan* heff, const void* const* ops, const void
   lowest_eigenpair(a, b, theta, sv);
   check_hip(hipMemcpyAsync(svec, sv.data(), sizeof(double) * m, hipMemcpyHostToDevice, s), "h2d");
   check_hip(hipStreamSynchronize(s), "h2d sync");
-  psi32.P.psi_f32 = false;   // the refinement applies to the float64 Ritz vector
+  psi32.P.psi_f32 = psi32.P.z_f32 = false;   // the refinement: float64 in and out
   timed(7, [&] {
     if (vf32)
       check_hip(launch_combine(V32, ldv, n, m, svec, Y, s), "ritz vector");

@@ -813,6 +813,7 @@ static void heff_plan(const TensorDesc& L, const TensorDesc& W1, const TensorDes
   s4.ta = Elem::Inter;
   s4.transb = true;
   s4.has_alt = true;
+  s4.writes_out = true;
   {
     const int nW = (int)W2.legs[3].q.size(), nY = (int)psi.legs[3].q.size();
     int32_t tt[5], rt[3];

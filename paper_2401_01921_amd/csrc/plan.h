@@ -81,6 +81,9 @@ struct Step {
   // the split of the H_eff input psi (reads float32 rows while the plan runs
   // inside a float32-basis Lanczos solve)
   bool reads_psi = false;
+  // the GEMM that writes the H_eff output (float32 while the plan runs inside
+  // a float32-basis Lanczos solve)
+  bool writes_out = false;
   // device table offsets inside the plan blob (filled by finalize)
   size_t off0 = 0, off1 = 0, off2 = 0, off3 = 0, off4 = 0, off5 = 0;
   int64_t n0 = 0, n1 = 0;
@@ -123,6 +126,7 @@ struct PlanData {
   // execution state
   bool use_graph = false;
   bool psi_f32 = false;         // set by Lanczos: the psi input is a float32 Krylov row
+  bool z_f32 = false;           // set by Lanczos: the output H psi is written as float32
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph = nullptr;
   void* graph_ws = nullptr;
