@@ -342,6 +342,26 @@ def bench_extras(bst, wl, torch, dev, plan, ins_apply, apply_flops):
                              "kernels_per_execute": batch.stats().nsteps,
                              "gemm_problems": batch.stats().gemm_problems}
     del wsb, ins, outs, batch, members
+    # the XX chain's MPO (bond of 4 channels; the model of the paper's DMRG
+    # benchmark): one spin-1/2 apply at chi = 4096, q in [-20, 20]
+    v = wl.gaussian_sector_dims(4096, 20)
+    T = {k: bst.Tensor(*s) for k, s in wl.heff_specs("1/2", v, v, "xx").items()}
+    Wx = torch.from_numpy(T["W1"].from_dense(wl.mpo_dense("1/2", "xx"))).to(dev)
+    ins_x = [torch.randn(T["L"].numel, dtype=torch.float64, device=dev), Wx, Wx,
+             torch.randn(T["R"].numel, dtype=torch.float64, device=dev),
+             torch.randn(T["psi"].numel, dtype=torch.float64, device=dev)]
+    px = bst.heff_plan(T["L"], T["W1"], T["W2"], T["R"], T["psi"], "fp64")
+    res_x = torch.empty(T["psi"].numel, dtype=torch.float64, device=dev)
+    ws_x = bst.workspace(px.workspace_bytes)
+    fl_x = px.stats().flops
+    xx = {"psi_elements": T["psi"].numel, "flops": fl_x}
+    for prec in ("fp64", "bf16x3"):
+        px.set_precision(prec)
+        px.autotune(ins_x, [res_x], ws_x, reps=3)
+        ms = _time_ms(torch, lambda: px.execute(ins_x, [res_x], ws_x), 20)
+        xx[prec] = {"ms": round(ms, 4), "gflops": round(fl_x / ms / 1e6, 1)}
+    out["apply_xx_spin_half_chi4096"] = xx
+    del ws_x, res_x, ins_x, px
     # block permute of a 1.2 GiB tensor (c, a, b) <- (a, b, c)
     sec = [(q, 150) for q in range(-3, 4)]
     T = bst.Tensor(["a", "b", "c"], [(1, sec), (1, sec), (-1, [(q, 150) for q in range(-6, 7)])])

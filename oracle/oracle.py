@@ -19,6 +19,8 @@ Library for Tensor Networks"):
   with and without symmetries"
 * H_eff.psi ............................ Sec. "Benchmarks", Fig. Hpsi_fig
   (L, two-site MPO, R, two-site wavefunction)
+* Heisenberg and XX chains (dense, for . Sec. "Benchmarks" (the DMRG benchmark
+  exact diagonalisation in tests)        is the XX chain)
 * Lanczos on a linear operator ......... Sec. "Eigenvalue decomposition"
   (LinOp + Lanczos; the paper gives no algorithmic detail, so this is the
   textbook method with full classical Gram-Schmidt reorthogonalisation done
@@ -466,22 +468,51 @@ def _spin_ops(spin: str):
     return sp, sp.T, sz, q
 
 
-def heisenberg_chain_hamiltonian(nsites: int, spin: str, J: float = 1.0) -> np.ndarray:
-    """H = J sum_i S_i.S_{i+1} (open chain), dense, basis highest Sz first."""
+def spin_chain_hamiltonian(nsites: int, spin: str, J: float = 1.0, Jz: float = 1.0) -> np.ndarray:
+    """H = sum_i [J (Sx Sx + Sy Sy) + Jz Sz Sz] over the bonds of an open
+    chain, dense, basis highest Sz first; J (Sx Sx + Sy Sy) is written as
+    (J/2)(S+ S- + S- S+)."""
     sp, sm, sz, _ = _spin_ops(spin)
     d = sp.shape[0]
     H = np.zeros((d ** nsites, d ** nsites))
     for i in range(nsites - 1):
         left = np.eye(d ** i)
         right = np.eye(d ** (nsites - i - 2))
-        bond = 0.5 * J * (np.kron(sp, sm) + np.kron(sm, sp)) + J * np.kron(sz, sz)
+        bond = 0.5 * J * (np.kron(sp, sm) + np.kron(sm, sp)) + Jz * np.kron(sz, sz)
         H += np.kron(np.kron(left, bond), right)
     return H
 
 
+def heisenberg_chain_hamiltonian(nsites: int, spin: str, J: float = 1.0) -> np.ndarray:
+    """H = J sum_i S_i.S_{i+1} (open chain)."""
+    return spin_chain_hamiltonian(nsites, spin, J, J)
+
+
+def xx_chain_hamiltonian(nsites: int, spin: str, J: float = 1.0) -> np.ndarray:
+    """H = J sum_i (Sx_i Sx_{i+1} + Sy_i Sy_{i+1}) (open chain): the XX model
+    of the paper's DMRG benchmark (Sec. "Benchmarks")."""
+    return spin_chain_hamiltonian(nsites, spin, J, 0.0)
+
+
+def chain_ground(nsites: int, spin: str, model: str = "heisenberg", J: float = 1.0,
+                 charge: int | None = 0) -> float:
+    """Lowest eigenvalue of the Heisenberg or XX chain, optionally restricted
+    to one total-charge sector."""
+    if model == "heisenberg":
+        H = heisenberg_chain_hamiltonian(nsites, spin, J)
+    elif model == "xx":
+        H = xx_chain_hamiltonian(nsites, spin, J)
+    else:
+        raise ValueError(model)
+    return _lowest_in_sector(H, nsites, spin, charge)
+
+
 def heisenberg_chain_ground(nsites: int, spin: str, J: float = 1.0, charge: int | None = 0) -> float:
     """Lowest eigenvalue, optionally restricted to one total-charge sector."""
-    H = heisenberg_chain_hamiltonian(nsites, spin, J)
+    return chain_ground(nsites, spin, "heisenberg", J, charge)
+
+
+def _lowest_in_sector(H: np.ndarray, nsites: int, spin: str, charge: int | None) -> float:
     if charge is not None:
         _, _, _, q = _spin_ops(spin)
         tot = np.zeros(1, dtype=int)

@@ -141,21 +141,41 @@ def spin_matrices(spin: str):
 # Channel charges are (0, -delta, +delta, 0, 0).  Grouped by ascending charge
 # the bond reads [-delta: ch1], [0: ch0, ch3, ch4], [+delta: ch2].
 MPO_GROUPED_ORDER = (1, 0, 3, 4, 2)
+# The XX chain (the paper's DMRG benchmark model) has no Sz-Sz coupling: the
+# same MPO without channel 3, a bond of dimension 4.
+MPO_GROUPED_ORDER_XX = (1, 0, 4, 2)
+MODELS = ("heisenberg", "xx")
 
 
-def mpo_bond(spin: str) -> List[Tuple[int, int]]:
+def _grouped_order(model: str):
+    if model not in MODELS:
+        raise ValueError(model)
+    return MPO_GROUPED_ORDER if model == "heisenberg" else MPO_GROUPED_ORDER_XX
+
+
+def mpo_bond(spin: str, model: str = "heisenberg") -> List[Tuple[int, int]]:
     d = mpo_charge_step(spin)
-    return [(-d, 1), (0, 3), (+d, 1)]
+    return [(-d, 1), (0, len(_grouped_order(model)) - 2), (+d, 1)]
 
 
-def grouped_index(ch: int) -> int:
+def grouped_index(ch: int, model: str = "heisenberg") -> int:
     """Position of an MPO channel on the grouped (dense) MPO bond."""
-    return MPO_GROUPED_ORDER.index(ch)
+    return _grouped_order(model).index(ch)
 
 
 def channel_position(ch: int) -> Tuple[int, int]:
     """(sector index, index inside the sector) of an MPO channel in the grouped bond."""
     return {1: (0, 0), 0: (1, 0), 3: (1, 1), 4: (1, 2), 2: (2, 0)}[ch]
+
+
+def mpo_dense(spin: str, model: str = "heisenberg", J: float = 1.0) -> np.ndarray:
+    """Dense W of the chosen model: J S.S (Heisenberg, bond 5) or
+    J (Sx Sx + Sy Sy) = (J/2)(S+ S- + S- S+) (XX, bond 4)."""
+    w = heisenberg_mpo_dense(spin, J)
+    if model == "heisenberg":
+        return w
+    keep = [MPO_GROUPED_ORDER.index(ch) for ch in _grouped_order(model)]
+    return np.ascontiguousarray(w[keep][:, :, :, keep])
 
 
 def heisenberg_mpo_dense(spin: str, J: float = 1.0) -> np.ndarray:
@@ -179,9 +199,9 @@ def heisenberg_mpo_dense(spin: str, J: float = 1.0) -> np.ndarray:
     return np.ascontiguousarray(w[p][:, :, :, p])
 
 
-def mpo_legs(spin: str) -> List[Leg]:
+def mpo_legs(spin: str, model: str = "heisenberg") -> List[Leg]:
     """W legs (wl IN, s IN, s' OUT, wr OUT): q_wl + q_s = q_s' + q_wr."""
-    b = mpo_bond(spin)
+    b = mpo_bond(spin, model)
     ph = physical_sectors(spin)
     return [(IN, b), (IN, ph), (OUT, ph), (OUT, b)]
 
@@ -189,18 +209,19 @@ def mpo_legs(spin: str) -> List[Leg]:
 # --------------------------------------------------------------------------
 # Tensor specs of the workloads: (labels, legs)
 # --------------------------------------------------------------------------
-def heff_specs(spin: str, virt_a: List[Tuple[int, int]], virt_b: List[Tuple[int, int]]):
+def heff_specs(spin: str, virt_a: List[Tuple[int, int]], virt_b: List[Tuple[int, int]],
+               model: str = "heisenberg"):
     """Leg specs of L, W1, W2, R and psi for a two-site H_eff.
 
     psi[a, s1, s2, b] (IN, IN, IN, OUT); L[a, w, a'] (IN, OUT, OUT);
     R[b, w, b'] (OUT, IN, IN); W as in mpo_legs.
     """
     ph = physical_sectors(spin)
-    mb = mpo_bond(spin)
+    mb = mpo_bond(spin, model)
     psi = (["a", "s1", "s2", "b"], [(IN, virt_a), (IN, ph), (IN, ph), (OUT, virt_b)])
     L = (["a", "w", "ap"], [(IN, virt_a), (OUT, mb), (OUT, virt_a)])
     R = (["b", "w", "bp"], [(OUT, virt_b), (IN, mb), (IN, virt_b)])
-    W = (["wl", "s", "sp", "wr"], mpo_legs(spin))
+    W = (["wl", "s", "sp", "wr"], mpo_legs(spin, model))
     return {"L": L, "W1": W, "W2": W, "R": R, "psi": psi}
 
 

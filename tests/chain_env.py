@@ -1,4 +1,4 @@
-"""Exact (untruncated) DMRG environments of short open Heisenberg chains.
+"""Exact (untruncated) DMRG environments of short open Heisenberg or XX chains.
 
 Test-harness helper: builds dense L and R by contracting the MPO over the
 product basis of the left / right block with numpy.einsum, then orders the
@@ -18,47 +18,49 @@ def _group(charges):
     return order, [(int(q), int(c)) for q, c in zip(qs, counts)]
 
 
-def left_env(nsites: int, spin: str):
+def left_env(nsites: int, spin: str, model: str = "heisenberg"):
     """Dense L[a, w, a'] over nsites sites and the sector list of leg a.
     Charge of a left-block state = sum of its site charges."""
-    W = wl.heisenberg_mpo_dense(spin)
+    W = wl.mpo_dense(spin, model)
+    dw = W.shape[0]
     qs = np.array([q for q, _ in wl.physical_sectors(spin)])
-    L = np.zeros((1, 5, 1))
-    L[0, wl.grouped_index(4), 0] = 1.0   # left boundary channel
+    L = np.zeros((1, dw, 1))
+    L[0, wl.grouped_index(4, model), 0] = 1.0   # left boundary channel
     ch = np.zeros(1, dtype=int)
     for _ in range(nsites):
         D = L.shape[0]
         d = W.shape[1]
-        L = np.einsum("awb,wstv->asvbt", L, W).reshape(D * d, 5, D * d)
+        L = np.einsum("awb,wstv->asvbt", L, W).reshape(D * d, dw, D * d)
         ch = (ch[:, None] + qs[None, :]).ravel()
     order, secs = _group(ch)
     return np.ascontiguousarray(L[order][:, :, order]), secs
 
 
-def right_env(nsites: int, spin: str):
+def right_env(nsites: int, spin: str, model: str = "heisenberg"):
     """Dense R[b, w, b'] over nsites sites and the sector list of leg b.
     Leg charge of a right-block state = minus its total site charge, so that
     psi[a,s1,s2,b] holds exactly the states of total charge zero."""
-    W = wl.heisenberg_mpo_dense(spin)
+    W = wl.mpo_dense(spin, model)
+    dw = W.shape[0]
     qs = np.array([q for q, _ in wl.physical_sectors(spin)])
-    R = np.zeros((1, 5, 1))
-    R[0, wl.grouped_index(0), 0] = 1.0   # right boundary channel
+    R = np.zeros((1, dw, 1))
+    R[0, wl.grouped_index(0, model), 0] = 1.0   # right boundary channel
     ch = np.zeros(1, dtype=int)
     for _ in range(nsites):
         D = R.shape[0]
         d = W.shape[1]
-        R = np.einsum("wstv,bvc->sbwtc", W, R).reshape(d * D, 5, d * D)
+        R = np.einsum("wstv,bvc->sbwtc", W, R).reshape(d * D, dw, d * D)
         ch = ((-qs)[:, None] + ch[None, :]).ravel()
     order, secs = _group(ch)
     return np.ascontiguousarray(R[order][:, :, order]), secs
 
 
-def chain_heff_dense(nsites: int, spin: str):
+def chain_heff_dense(nsites: int, spin: str, model: str = "heisenberg"):
     """Dense operands and leg specs of the centre two-site H_eff of an open
     chain of nsites sites (nsites even)."""
     nl = (nsites - 2) // 2
     nr = nsites - 2 - nl
-    Ld, sa = left_env(nl, spin)
-    Rd, sb = right_env(nr, spin)
-    specs = wl.heff_specs(spin, sa, sb)
-    return Ld, Rd, wl.heisenberg_mpo_dense(spin), specs
+    Ld, sa = left_env(nl, spin, model)
+    Rd, sb = right_env(nr, spin, model)
+    specs = wl.heff_specs(spin, sa, sb, model)
+    return Ld, Rd, wl.mpo_dense(spin, model), specs

@@ -40,12 +40,14 @@ def rel_err(got: np.ndarray, ref: np.ndarray):
 TOL = {"fp64": 1e-12, "fp32": 2e-6, "bf16x3": 5e-5, "bf16x6": 2e-6}
 
 
-def heff_operands(k: int, recipe: str = "normal", chi=None, qmax=None, spin=None):
-    """Oracle tensors and host data of an H_eff workload."""
+def heff_operands(k: int, recipe: str = "normal", chi=None, qmax=None, spin=None,
+                  model: str = "heisenberg"):
+    """Oracle tensors and host data of an H_eff workload (Heisenberg MPO, or
+    the XX MPO with its bond of 4 channels)."""
     wlk = wl.WORKLOADS[k]
     spin = spin or wlk["spin"]
     v = wl.gaussian_sector_dims(chi or wlk["chi"], qmax if qmax is not None else wlk["qmax"])
-    specs = wl.heff_specs(spin, v, v)
+    specs = wl.heff_specs(spin, v, v, model)
     O = {n: orc.BlockTensor(*s) for n, s in specs.items()}
     if recipe == "normal":
         O["L"].data[:] = wl.normal(wl.seed_for(k, "L"), O["L"].numel)
@@ -53,7 +55,9 @@ def heff_operands(k: int, recipe: str = "normal", chi=None, qmax=None, spin=None
     else:
         O["L"].data[:] = wl.dmrg_like_env(O["L"].table(), O["L"].numel, wl.seed_for(k, "L"), "L", v)
         O["R"].data[:] = wl.dmrg_like_env(O["R"].table(), O["R"].numel, wl.seed_for(k, "R"), "R", v)
-    Wd = wl.heisenberg_mpo_dense(spin)
+    if recipe != "normal" and model != "heisenberg":
+        raise ValueError("DMRG-like environments are built for the Heisenberg MPO")
+    Wd = wl.mpo_dense(spin, model)
     O["W1"] = orc.from_dense(*specs["W1"], Wd)
     O["W2"] = orc.from_dense(*specs["W2"], Wd)
     O["psi"].data[:] = wl.normal(wl.seed_for(k, "psi"), O["psi"].numel)

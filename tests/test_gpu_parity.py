@@ -139,6 +139,21 @@ def test_heff_spin_half_chi512(prec):
     assert nrm <= TOL[prec]
 
 
+@pytest.mark.parametrize("spin", ["1/2", "1"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "bf16x6"])
+def test_heff_xx_mpo(prec, spin):
+    """The XX MPO (the paper's benchmark model; bond of 4 channels, so other
+    MPO coefficient classes and T1/T3 row groups than the Heisenberg MPO)."""
+    specs, O = heff_operands(2, spin=spin, model="xx")
+    assert O["W1"].legs[0][1][1] == (0, 2)
+    ref = orc.heff_apply(O["L"], O["W1"], O["W2"], O["R"], O["psi"]).data
+    T, plan = lib_heff(specs, prec)
+    got = run_heff(plan, O)
+    nrm, mx = rel_err(got, ref)
+    _print("heff xx chi512", spin, prec, nrm, mx)
+    assert nrm <= TOL[prec]
+
+
 def test_heff_fp64_is_deterministic():
     specs, O = heff_operands(2)
     T, plan = lib_heff(specs, "fp64")

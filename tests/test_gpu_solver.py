@@ -166,6 +166,25 @@ def test_lanczos_matches_exact_diagonalisation(spin, nsites, prec):
     assert abs(r["energy"] - E_ed) < 1e-10 * max(1.0, abs(E_ed))
 
 
+@pytest.mark.parametrize("prec", ["fp64", "bf16x6", "bf16x3"])
+def test_lanczos_xx_chain_free_fermions(prec):
+    """A 10-site XX chain through exact environments (MPO bond 4): the refined
+    energy equals the free-fermion closed form (fp64 and bf16x6 to 1e-10
+    relative; bf16x3 to the 1e-6 that the Heisenberg chain test allows it)."""
+    from tests.test_oracle_xx import free_fermion_ground
+    Ld, Rd, Wd, specs = chain_env.chain_heff_dense(10, "1/2", "xx")
+    O = {"L": orc.from_dense(*specs["L"], Ld), "R": orc.from_dense(*specs["R"], Rd),
+         "W1": orc.from_dense(*specs["W1"], Wd), "W2": orc.from_dense(*specs["W2"], Wd),
+         "psi": orc.BlockTensor(*specs["psi"])}
+    E0 = free_fermion_ground(10)
+    r = _lanczos_lib(specs, O, min(O["psi"].numel, 128), prec)
+    _print("XX chain", prec, r["energy"], E0, r["energy"] - E0, r["steps"], r["residual"])
+    if prec == "bf16x3":
+        assert abs(r["energy"] - E0) < 1e-6
+    else:
+        assert abs(r["energy"] - E0) < 1e-10 * abs(E0)
+
+
 def test_lanczos_bf16x3_reports_its_error():
     """bf16x3 matvecs: the refined energy of a 10-site chain, stated (not
     bounded at 1e-10: the split's 2^-17 product error limits the Ritz vector)."""
