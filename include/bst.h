@@ -101,14 +101,41 @@ typedef struct bst_plan bst_plan;
 bst_status bst_tensor_create(int32_t rank, const int32_t* dir, const int32_t* nsec,
                              const int32_t* qn, const int64_t* dim,
                              const char* const* labels, bst_tensor** out);
+
+/* The same with one or more abelian symmetries (Sec. "Symmetry and quantum
+ * numbers", Sec. "Creating bonds with quantum numbers"): every sector
+ * carries one charge per symmetry.  A U(1) component combines by addition;
+ * a Z_n component by addition modulo n; both are negated on outgoing legs.
+ * A block is valid when every component of its combined charge vanishes
+ * (exactly for U(1), modulo n for Z_n).
+ *   nsym     number of symmetries, 1..8
+ *   sym      [nsym] 0 for U(1), n >= 2 for Z_n
+ *   qn       [sum nsec * nsym] charges, sector by sector, nsym per sector;
+ *            Z_n charges in [0, n)
+ * The other arguments are those of bst_tensor_create; bst_tensor_create is
+ * this call with nsym = 1 and sym = {0}.  Contraction requires equal
+ * symmetries on the contracted legs (BST_E_QNUM otherwise).  Errors:
+ * BST_E_INVALID (bad nsym or modulus), BST_E_QNUM (a Z_n charge out of
+ * range), BST_E_LABEL. */
+bst_status bst_tensor_create_sym(int32_t rank, const int32_t* dir, const int32_t* nsec,
+                                 int32_t nsym, const int32_t* sym, const int32_t* qn,
+                                 const int64_t* dim, const char* const* labels, bst_tensor** out);
 bst_status bst_tensor_destroy(bst_tensor* t);
+
+/* The symmetries of a tensor: their number, and (if moduli is non-null) the
+ * moduli (0 = U(1)) into moduli[cap].  Error BST_E_INVALID if cap is short. */
+bst_status bst_tensor_symmetry(const bst_tensor* t, int32_t* nsym, int32_t* moduli, int32_t cap);
+
+/* All charges of a leg, sector by sector, nsym per sector, into
+ * qn[nsec * nsym] (bst_tensor_leg gives the first component only). */
+bst_status bst_tensor_leg_charges(const bst_tensor* t, int32_t leg, int32_t* qn);
 
 /* Rank, number of valid blocks and total element count. */
 bst_status bst_tensor_info(const bst_tensor* t, int32_t* rank, int64_t* nblocks, int64_t* numel);
 
 /* Leg description: direction, sector count, and (if the arrays are non-null)
- * the charges and dims, and the label copied into a buffer of label_cap
- * bytes.  Error BST_E_INVALID for a bad leg index or a short buffer. */
+ * the charges (first symmetry) and dims, and the label copied into a buffer
+ * of label_cap bytes.  Error BST_E_INVALID for a bad leg index or a short buffer. */
 bst_status bst_tensor_leg(const bst_tensor* t, int32_t leg, int32_t* dir, int32_t* nsec,
                           int32_t* qn, int64_t* dim, char* label, size_t label_cap);
 

@@ -7,6 +7,8 @@ does, and this module imports nothing from the library.
 It is written to be read against the paper (arXiv:2401.01921, "The Cytnx
 Library for Tensor Networks"):
 
+* U(1), Z_n and product symmetries .... Sec. "Symmetry and quantum numbers"
+  (combine rules: sum, sum modulo n; reverse rule: negation)
 * block structure and zero flux ........ Sec. "UniTensor with Symmetries",
   Sec. "Bond with quantum numbers", Sec. "Symmetric UniTensor" (the printed
   block list of the rank-3 example fixes the lexicographic block order)
@@ -86,13 +88,26 @@ def check_legs(legs: Sequence[Leg]) -> None:
                 raise OracleError("sector dims must be >= 1")
 
 
-def valid_blocks(legs: Sequence[Leg]) -> List[Tuple[int, ...]]:
+U1 = (0,)   # the default symmetry list: one U(1)
+
+
+def _components(q, nsym: int) -> Tuple[int, ...]:
+    return tuple(int(c) for c in q) if nsym > 1 else (int(q),)
+
+
+def valid_blocks(legs: Sequence[Leg], sym: Sequence[int] = U1) -> List[Tuple[int, ...]]:
     """All sector-index tuples whose flux (sum of in charges minus sum of out
-    charges) is zero, in lexicographic order with leg 0 most significant."""
+    charges) vanishes, in lexicographic order with leg 0 most significant.
+    Sec. "Symmetry and quantum numbers": each symmetry combines charges by its
+    rule (U(1): the sum; Z_n: the sum modulo n) and reverses those of
+    outgoing legs (negation); `sym` lists the moduli, 0 for U(1)."""
     out = []
     for t in itertools.product(*[range(len(secs)) for _, secs in legs]):
-        flux = sum(d * secs[k][0] for (d, secs), k in zip(legs, t))
-        if flux == 0:
+        ok = True
+        for c, n in enumerate(sym):
+            flux = sum(d * _components(secs[k][0], len(sym))[c] for (d, secs), k in zip(legs, t))
+            ok = ok and (flux == 0 if n == 0 else flux % n == 0)
+        if ok:
             out.append(t)
     return out
 
@@ -101,15 +116,30 @@ class BlockTensor:
     """Labels, legs, canonical block list, and one flat float64 buffer with the
     blocks stored one after another in block order, each row-major."""
 
-    def __init__(self, labels: Sequence[str], legs: Sequence[Leg], data: np.ndarray | None = None):
+    def __init__(self, labels: Sequence[str], legs: Sequence[Leg], data: np.ndarray | None = None,
+                 sym: Sequence[int] = U1):
         if len(labels) != len(legs):
             raise LabelError("one label per leg")
         if len(set(labels)) != len(labels):
             raise LabelError("labels must be unique")
         check_legs(legs)
+        self.sym = tuple(int(n) for n in sym)
+        if not self.sym or any(n < 0 or n == 1 for n in self.sym):
+            raise OracleError("a symmetry is U(1) (0) or Z_n with n >= 2")
+        ns = len(self.sym)
+
+        def charge(q):
+            c = _components(q, ns)
+            if len(c) != ns:
+                raise OracleError("one charge per symmetry")
+            for v, n in zip(c, self.sym):
+                if n >= 2 and not 0 <= v < n:
+                    raise QnumError("a Z_n charge must lie in [0, n)")
+            return c if ns > 1 else c[0]
+
         self.labels = list(labels)
-        self.legs = [(int(d), [(int(q), int(g)) for q, g in secs]) for d, secs in legs]
-        self.blocks = valid_blocks(self.legs)
+        self.legs = [(int(d), [(charge(q), int(g)) for q, g in secs]) for d, secs in legs]
+        self.blocks = valid_blocks(self.legs, self.sym)
         self.shapes = [tuple(self.legs[i][1][k][1] for i, k in enumerate(t)) for t in self.blocks]
         self.offsets = []
         off = 0
@@ -178,8 +208,9 @@ def embed(T: BlockTensor) -> np.ndarray:
     return dense
 
 
-def from_dense(labels, legs, dense: np.ndarray, force: bool = False) -> BlockTensor:
-    T = BlockTensor(labels, legs)
+def from_dense(labels, legs, dense: np.ndarray, force: bool = False,
+               sym: Sequence[int] = U1) -> BlockTensor:
+    T = BlockTensor(labels, legs, sym=sym)
     dense = np.asarray(dense, dtype=np.float64)
     if list(dense.shape) != T.dims():
         raise DimError("dense shape does not match the bonds")
@@ -197,14 +228,22 @@ def from_dense(labels, legs, dense: np.ndarray, force: bool = False) -> BlockTen
 # --------------------------------------------------------------------------
 # Combining bonds (Sec. "Combining bonds with quantum numbers")
 # --------------------------------------------------------------------------
-def combine_bonds(a: Leg, b: Leg, grouped: bool = True) -> Leg:
-    """Charges add (U(1) combine rule).  Ungrouped: pairs in row-major order
-    (a slow).  Grouped: equal charges merged, ascending charge."""
+def combine_bonds(a: Leg, b: Leg, grouped: bool = True, sym: Sequence[int] = U1) -> Leg:
+    """Charges combine by each symmetry's rule (U(1): the sum; Z_n: the sum
+    modulo n).  Ungrouped: pairs in row-major order (a slow).  Grouped:
+    equal charges merged, ascending charge."""
     da, sa = a
     db, sb = b
     if da != db:
         raise DirectionError("combined bonds must have the same direction")
-    pairs = [(qa + qb, ga * gb) for qa, ga in sa for qb, gb in sb]
+    ns = len(sym)
+
+    def comb(qa, qb):
+        c = tuple(x + y if n == 0 else (x + y) % n
+                  for x, y, n in zip(_components(qa, ns), _components(qb, ns), sym))
+        return c if ns > 1 else c[0]
+
+    pairs = [(comb(qa, qb), ga * gb) for qa, ga in sa for qb, gb in sb]
     if not grouped:
         return (da, pairs)
     acc: Dict[int, int] = {}
@@ -227,7 +266,7 @@ def permute(T: BlockTensor, order: Sequence) -> BlockTensor:
             raise LabelError("unknown label in permutation")
     if sorted(perm) != list(range(T.rank)):
         raise LabelError("not a permutation of the legs")
-    out = BlockTensor([T.labels[p] for p in perm], [T.legs[p] for p in perm])
+    out = BlockTensor([T.labels[p] for p in perm], [T.legs[p] for p in perm], sym=T.sym)
     for b, t in enumerate(T.blocks):
         nt = tuple(t[p] for p in perm)
         out.block(out.index[nt])[...] = np.transpose(T.block(b), perm)
@@ -251,6 +290,8 @@ def contract(A: BlockTensor, B: BlockTensor) -> BlockTensor:
     common = [l for l in A.labels if l in B.labels]
     ac = [A.labels.index(l) for l in common]
     bc = [B.labels.index(l) for l in common]
+    if A.sym != B.sym:
+        raise QnumError("the tensors carry different symmetries")
     for i, j in zip(ac, bc):
         (da, sa), (db, sb) = A.legs[i], B.legs[j]
         if da == db:
@@ -262,7 +303,7 @@ def contract(A: BlockTensor, B: BlockTensor) -> BlockTensor:
     af = [i for i in range(A.rank) if i not in ac]
     bf = [j for j in range(B.rank) if j not in bc]
     C = BlockTensor([A.labels[i] for i in af] + [B.labels[j] for j in bf],
-                    [A.legs[i] for i in af] + [B.legs[j] for j in bf])
+                    [A.legs[i] for i in af] + [B.legs[j] for j in bf], sym=A.sym)
     by_kc: Dict[Tuple[int, ...], List[int]] = {}
     for b, t in enumerate(B.blocks):
         by_kc.setdefault(tuple(t[j] for j in bc), []).append(b)
@@ -289,7 +330,7 @@ def contract(A: BlockTensor, B: BlockTensor) -> BlockTensor:
 # L -> psi -> W1 -> W2 -> R.
 # --------------------------------------------------------------------------
 def relabel(T: BlockTensor, labels: Sequence[str]) -> BlockTensor:
-    return BlockTensor(labels, T.legs, T.data)
+    return BlockTensor(labels, T.legs, T.data, sym=T.sym)
 
 
 def heff_apply(L: BlockTensor, W1: BlockTensor, W2: BlockTensor, R: BlockTensor,
@@ -319,9 +360,9 @@ def heff_flops(L: BlockTensor, W1: BlockTensor, W2: BlockTensor, R: BlockTensor,
     W2r = relabel(W2, ["w2", "s2", "t2", "w3"])
     Rr = relabel(R, ["b", "w3", "y"])
     f = []
-    T1 = BlockTensor(*_contract_meta(Lr, Pr)); f.append(_contract_flops(Lr, Pr))
-    T2 = BlockTensor(*_contract_meta(T1, W1r)); f.append(_contract_flops(T1, W1r))
-    T3 = BlockTensor(*_contract_meta(T2, W2r)); f.append(_contract_flops(T2, W2r))
+    T1 = BlockTensor(*_contract_meta(Lr, Pr), sym=L.sym); f.append(_contract_flops(Lr, Pr))
+    T2 = BlockTensor(*_contract_meta(T1, W1r), sym=L.sym); f.append(_contract_flops(T1, W1r))
+    T3 = BlockTensor(*_contract_meta(T2, W2r), sym=L.sym); f.append(_contract_flops(T2, W2r))
     f.append(_contract_flops(T3, Rr))
     return f
 

@@ -29,6 +29,7 @@ EXPORTS = [
     "bst_plan_autotune", "bst_plan_tiles", "bst_plan_profile", "bst_plan_destroy",
     "bst_lanczos_workspace", "bst_lanczos_ground", "bst_last_error", "bst_version",
     "bst_plan_tile_count", "bst_plan_set_tile", "bst_plan_forget_workspace",
+    "bst_tensor_create_sym", "bst_tensor_symmetry", "bst_tensor_leg_charges",
 ]
 
 
@@ -71,6 +72,10 @@ def _load():
     P = C.POINTER
     sig = {
         "bst_tensor_create": [i32, P(i32), P(i32), P(i32), P(i64), P(C.c_char_p), P(vp)],
+        "bst_tensor_create_sym": [i32, P(i32), P(i32), i32, P(i32), P(i32), P(i64), P(C.c_char_p),
+                                  P(vp)],
+        "bst_tensor_symmetry": [vp, P(i32), P(i32), i32],
+        "bst_tensor_leg_charges": [vp, i32, P(i32)],
         "bst_tensor_destroy": [vp],
         "bst_tensor_info": [vp, P(i32), P(i64), P(i64)],
         "bst_tensor_leg": [vp, i32, P(i32), P(i32), P(i32), P(i64), C.c_char_p, sz],
@@ -130,9 +135,13 @@ def _prec(p) -> int:
 
 # --------------------------------------------------------------------------
 class Tensor:
-    """Descriptor of a block-sparse tensor: labels and legs ``(dir, [(q, g), ...])``."""
+    """Descriptor of a block-sparse tensor: labels and legs ``(dir, [(q, g), ...])``.
 
-    def __init__(self, labels: Sequence[str], legs, _handle=None):
+    ``sym`` lists the symmetries (0 for U(1), n for Z_n); the default is one
+    U(1).  With several symmetries each charge ``q`` is a tuple, one entry
+    per symmetry."""
+
+    def __init__(self, labels: Sequence[str], legs, _handle=None, sym: Sequence[int] | None = None):
         if _handle is not None:
             self._h = _handle
         else:
@@ -141,13 +150,23 @@ class Tensor:
                 raise BstError(1, "one label per leg")
             dirs = (C.c_int32 * max(rank, 1))(*[int(d) for d, _ in legs])
             nsec = (C.c_int32 * max(rank, 1))(*[len(s) for _, s in legs])
-            qs = [int(q) for _, s in legs for q, _ in s]
             gs = [int(g) for _, s in legs for _, g in s]
-            qn = (C.c_int32 * max(len(qs), 1))(*qs)
             dm = (C.c_int64 * max(len(gs), 1))(*gs)
             labs = (C.c_char_p * max(rank, 1))(*[l.encode() for l in labels])
             h = C.c_void_p()
-            _check(_lib.bst_tensor_create(rank, dirs, nsec, qn, dm, labs, C.byref(h)))
+            if sym is None:
+                qs = [int(q) for _, s in legs for q, _ in s]
+                qn = (C.c_int32 * max(len(qs), 1))(*qs)
+                _check(_lib.bst_tensor_create(rank, dirs, nsec, qn, dm, labs, C.byref(h)))
+            else:
+                ns = len(sym)
+                qs = [int(c) for _, s in legs for q, _ in s
+                      for c in (q if isinstance(q, (tuple, list)) else (q,))]
+                if len(qs) != ns * len(gs):
+                    raise BstError(1, "one charge per symmetry and sector")
+                qn = (C.c_int32 * max(len(qs), 1))(*qs)
+                sy = (C.c_int32 * ns)(*[int(m) for m in sym])
+                _check(_lib.bst_tensor_create_sym(rank, dirs, nsec, ns, sy, qn, dm, labs, C.byref(h)))
             self._h = h
         r, nb, ne = C.c_int32(), C.c_int64(), C.c_int64()
         _check(_lib.bst_tensor_info(self._h, C.byref(r), C.byref(nb), C.byref(ne)))
@@ -180,6 +199,22 @@ class Tensor:
     @property
     def labels(self) -> List[str]:
         return self.legs()[0]
+
+    def symmetry(self) -> List[int]:
+        """Moduli of the symmetries (0 = U(1))."""
+        n = C.c_int32()
+        m = (C.c_int32 * 8)()
+        _check(_lib.bst_tensor_symmetry(self._h, C.byref(n), m, 8))
+        return list(m[:n.value])
+
+    def leg_charges(self, leg: int) -> List[Tuple[int, ...]]:
+        """Every sector's charges (one per symmetry) of a leg."""
+        ns = len(self.symmetry())
+        d, nsec = C.c_int32(), C.c_int32()
+        _check(_lib.bst_tensor_leg(self._h, leg, C.byref(d), C.byref(nsec), None, None, None, 0))
+        q = (C.c_int32 * max(nsec.value * ns, 1))()
+        _check(_lib.bst_tensor_leg_charges(self._h, leg, q))
+        return [tuple(q[k * ns:(k + 1) * ns]) for k in range(nsec.value)]
 
     def table(self) -> List[Tuple[Tuple[int, ...], Tuple[int, ...], int]]:
         """[(sector indices, shape, flat offset)] in canonical block order."""

@@ -34,9 +34,14 @@ void check_hip(hipError_t e, const char* what);
 // ------------------------------------------------------------------------
 // Tensor descriptor (host only)
 // ------------------------------------------------------------------------
+// Charges of a leg: one component per symmetry.  `sym` holds the moduli
+// (0: U(1), n >= 2: Z_n; empty: a single U(1) component); `q` is the first
+// component of every sector and `qx` the others, (sym.size() - 1) per sector.
 struct LegDesc {
   int32_t dir = 1;
   std::vector<int32_t> q;
+  std::vector<int32_t> qx;
+  std::vector<int32_t> sym;
   std::vector<int64_t> g;
   std::string label;
   int64_t total() const {
@@ -44,7 +49,13 @@ struct LegDesc {
     for (auto v : g) s += v;
     return s;
   }
-  bool same_sectors(const LegDesc& o) const { return q == o.q && g == o.g; }
+  int nsym() const { return sym.empty() ? 1 : (int)sym.size(); }
+  int32_t modulus(int c) const { return sym.empty() ? 0 : sym[c]; }
+  int32_t charge(int sector, int c) const {
+    return c == 0 ? q[sector] : qx[(size_t)sector * (nsym() - 1) + (c - 1)];
+  }
+  bool same_charges(const LegDesc& o) const { return q == o.q && qx == o.qx && sym == o.sym; }
+  bool same_sectors(const LegDesc& o) const { return same_charges(o) && g == o.g; }
 };
 
 struct TensorDesc {

@@ -14,12 +14,13 @@ static std::atomic<uint64_t> g_plan_id{1};
 static void check_contractible(const LegDesc& a, const LegDesc& b, const std::string& what) {
   if (a.dir == b.dir)
     fail(BST_E_DIRECTION, "leg '" + what + "' has the same direction on both tensors");
-  if (a.q != b.q) fail(BST_E_QNUM, "leg '" + what + "' has different quantum numbers");
+  if (a.sym != b.sym) fail(BST_E_QNUM, "leg '" + what + "' has different symmetries");
+  if (!a.same_charges(b)) fail(BST_E_QNUM, "leg '" + what + "' has different quantum numbers");
   if (a.g != b.g) fail(BST_E_DIM, "leg '" + what + "' has different sector dims");
 }
 
 static void check_same(const LegDesc& a, const LegDesc& b, const std::string& what) {
-  if (a.dir != b.dir || a.q != b.q || a.g != b.g)
+  if (a.dir != b.dir || !a.same_sectors(b))
     fail(BST_E_STRUCTURE, "leg '" + what + "' of the result does not match psi");
 }
 

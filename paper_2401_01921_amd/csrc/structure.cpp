@@ -32,7 +32,10 @@ void TensorDesc::build() {
   shape.clear();
   offset.clear();
   lookup.clear();
-  // Per-suffix reachable flux range, to prune the lexicographic walk.
+  // Per-suffix reachable flux range of the first charge component, to prune
+  // the lexicographic walk (U(1) only; a Z_n flux wraps, so no pruning).
+  const int nsym = r > 0 ? legs[0].nsym() : 1;
+  const bool prune = r > 0 && legs[0].modulus(0) == 0;
   std::vector<int64_t> lo(r + 1, 0), hi(r + 1, 0);
   for (int i = r - 1; i >= 0; --i) {
     int64_t mn = INT64_MAX, mx = INT64_MIN;
@@ -44,6 +47,10 @@ void TensorDesc::build() {
     lo[i] = lo[i + 1] + mn;
     hi[i] = hi[i + 1] + mx;
   }
+  // A component's total flux vanishes: exactly for U(1), modulo n for Z_n
+  // (the combine rule adds charges, the reverse rule negates them on
+  // outgoing legs).
+  auto vanishes = [](int64_t f, int32_t n) { return n == 0 ? f == 0 : f % n == 0; };
   std::vector<int32_t> t(r, 0);
   int64_t off = 0;
   // Iterative depth-first walk in lexicographic order.
@@ -65,9 +72,16 @@ void TensorDesc::build() {
     }
     int64_t f = flux[depth] + (int64_t)legs[depth].dir * legs[depth].q[t[depth]];
     // remaining legs must be able to cancel f
-    if (f + lo[depth + 1] > 0 || f + hi[depth + 1] < 0) continue;
+    if (prune && (f + lo[depth + 1] > 0 || f + hi[depth + 1] < 0)) continue;
     if (depth == r - 1) {
-      if (f != 0) continue;
+      if (!vanishes(f, legs[0].modulus(0))) continue;
+      bool ok = true;
+      for (int c = 1; c < nsym && ok; ++c) {
+        int64_t fc = 0;
+        for (int i = 0; i < r; ++i) fc += (int64_t)legs[i].dir * legs[i].charge(t[i], c);
+        ok = vanishes(fc, legs[0].modulus(c));
+      }
+      if (!ok) continue;
       int64_t b = (int64_t)offset.size();
       int64_t n = 1;
       for (int i = 0; i < r; ++i) {
@@ -105,6 +119,18 @@ std::unique_ptr<TensorDesc> make_tensor(std::vector<LegDesc> legs) {
     const auto& L = legs[i];
     if (L.dir != 1 && L.dir != -1) fail(BST_E_INVALID, "direction must be +1 or -1");
     if (L.q.empty() || L.q.size() != L.g.size()) fail(BST_E_INVALID, "a leg needs >= 1 sector");
+    if (L.sym != legs[0].sym) fail(BST_E_INVALID, "every leg must carry the same symmetries");
+    if (L.sym.size() > 8) fail(BST_E_INVALID, "at most 8 symmetries");
+    if (L.qx.size() != L.q.size() * (size_t)(L.nsym() - 1))
+      fail(BST_E_INVALID, "one charge per symmetry and sector");
+    for (int c = 0; c < L.nsym(); ++c) {
+      const int32_t n = L.modulus(c);
+      if (n < 0 || n == 1) fail(BST_E_INVALID, "a symmetry is U(1) (0) or Z_n with n >= 2");
+      if (n >= 2)
+        for (size_t k = 0; k < L.q.size(); ++k)
+          if (L.charge((int)k, c) < 0 || L.charge((int)k, c) >= n)
+            fail(BST_E_QNUM, "a Z_n charge must lie in [0, n)");
+    }
     for (auto g : L.g)
       if (g < 1 || g > (int64_t)1 << 30) fail(BST_E_INVALID, "sector dim must be in [1, 2^30]");
     if (L.label.empty()) fail(BST_E_LABEL, "empty label");
@@ -158,6 +184,59 @@ bst_status bst_tensor_create(int32_t rank, const int32_t* dir, const int32_t* ns
     }
   }
   *out = wrap_tensor(make_tensor(std::move(legs)));
+  BST_CATCH
+}
+
+bst_status bst_tensor_create_sym(int32_t rank, const int32_t* dir, const int32_t* nsec, int32_t nsym,
+                                 const int32_t* sym, const int32_t* qn, const int64_t* dim,
+                                 const char* const* labels, bst_tensor** out) {
+  BST_TRY
+  if (!out) fail(BST_E_INVALID, "null output");
+  *out = nullptr;
+  if (rank < 0 || rank > kMaxRank) fail(BST_E_INVALID, "rank must be 0..8");
+  if (nsym < 1 || nsym > 8) fail(BST_E_INVALID, "nsym must be 1..8");
+  if (!sym) fail(BST_E_INVALID, "null argument");
+  if (rank > 0 && (!dir || !nsec || !qn || !dim || !labels)) fail(BST_E_INVALID, "null argument");
+  std::vector<int32_t> moduli(sym, sym + nsym);
+  std::vector<LegDesc> legs(rank);
+  int64_t k = 0;
+  for (int i = 0; i < rank; ++i) {
+    if (nsec[i] < 1) fail(BST_E_INVALID, "a leg needs >= 1 sector");
+    legs[i].dir = dir[i];
+    if (!labels[i]) fail(BST_E_LABEL, "null label");
+    legs[i].label = labels[i];
+    legs[i].sym = moduli;
+    for (int s = 0; s < nsec[i]; ++s, ++k) {
+      legs[i].q.push_back(qn[k * nsym]);
+      for (int c = 1; c < nsym; ++c) legs[i].qx.push_back(qn[k * nsym + c]);
+      legs[i].g.push_back(dim[k]);
+    }
+  }
+  *out = wrap_tensor(make_tensor(std::move(legs)));
+  BST_CATCH
+}
+
+bst_status bst_tensor_symmetry(const bst_tensor* t, int32_t* nsym, int32_t* moduli, int32_t cap) {
+  BST_TRY
+  if (!t) fail(BST_E_INVALID, "null tensor");
+  const int n = t->d->rank() > 0 ? t->d->legs[0].nsym() : 1;
+  if (nsym) *nsym = n;
+  if (moduli) {
+    if (cap < n) fail(BST_E_INVALID, "moduli buffer too small");
+    for (int c = 0; c < n; ++c) moduli[c] = t->d->rank() > 0 ? t->d->legs[0].modulus(c) : 0;
+  }
+  BST_CATCH
+}
+
+bst_status bst_tensor_leg_charges(const bst_tensor* t, int32_t leg, int32_t* qn) {
+  BST_TRY
+  if (!t) fail(BST_E_INVALID, "null tensor");
+  if (leg < 0 || leg >= t->d->rank()) fail(BST_E_INVALID, "leg index out of range");
+  if (!qn) fail(BST_E_INVALID, "null argument");
+  const auto& L = t->d->legs[leg];
+  const int n = L.nsym();
+  for (size_t s = 0; s < L.q.size(); ++s)
+    for (int c = 0; c < n; ++c) qn[s * n + c] = L.charge((int)s, c);
   BST_CATCH
 }
 

@@ -6,7 +6,7 @@ import pytest
 
 from tests.gpu_common import (DEV, TOL, dev, heff_operands, host, lib_heff, rel_err, require_gpu,
                               run_heff, torch)
-from tests.helpers import _random_pair
+from tests.helpers import _random_pair, _random_sym_pair
 from oracle import oracle as orc
 from paper_2401_01921_amd import bst, workloads as wl
 
@@ -76,7 +76,8 @@ def test_permute_paper_example():
 
 def _contract_case(A, B, prec):
     C = orc.contract(A, B)
-    tA, tB = bst.Tensor(A.labels, A.legs), bst.Tensor(B.labels, B.legs)
+    sym = None if A.sym == orc.U1 else list(A.sym)
+    tA, tB = bst.Tensor(A.labels, A.legs, sym=sym), bst.Tensor(B.labels, B.legs, sym=sym)
     tC, plan = bst.contract_plan(tA, tB, prec)
     out = torch.full((tC.numel,), np.nan, dtype=torch.float64, device=DEV)
     plan.execute([dev(A.data), dev(B.data)], [out], bst.workspace(plan.workspace_bytes))
@@ -151,6 +152,70 @@ def test_heff_xx_mpo(prec, spin):
     got = run_heff(plan, O)
     nrm, mx = rel_err(got, ref)
     _print("heff xx chi512", spin, prec, nrm, mx)
+    assert nrm <= TOL[prec]
+
+
+@pytest.mark.parametrize("sym", [(2,), (3,), (0, 2)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "bf16x6"])
+def test_symmetric_contractions(prec, sym):
+    """Z_n and U(1) x Z_2 structures (Sec. "Symmetry and quantum numbers"):
+    random pairs, dims stretched so that tiles are ragged."""
+    rng = np.random.default_rng(5 + sum(sym) + 10 * len(sym))
+    for case in range(12):
+        ra, rb = int(rng.integers(1, 5)), int(rng.integers(1, 5))
+        nc = min(int(rng.integers(0, 4)), ra, rb)
+        A, B = _random_sym_pair(rng, ra, rb, nc, sym, dmax=5)
+        free = [i for i, l in enumerate(A.labels) if l not in B.labels]
+        if free:
+            scale = int(rng.integers(1, 25))
+            A = orc.BlockTensor(A.labels, [(d, [(q, g * scale if i == free[0] else g) for q, g in s])
+                                           for i, (d, s) in enumerate(A.legs)], sym=sym)
+            A.data[:] = rng.standard_normal(A.numel)
+        if A.numel == 0 or B.numel == 0:
+            continue
+        got, ref = _contract_case(A, B, prec)
+        nrm, _ = rel_err(got, ref)
+        _print("sym contract", sym, prec, case, A.labels, B.labels, nrm)
+        assert nrm <= TOL[prec]
+
+
+def _heff_sym_operands(sym, virt, phys, bond, seed):
+    """Random L, W, R, psi of a two-site H_eff under `sym` (legs as in the
+    U(1) workloads: psi in, in, in, out; L in, out, out; R out, in, in;
+    W in, in, out, out)."""
+    rng = np.random.default_rng(seed)
+    specs = {"L": (["a", "w", "ap"], [(1, virt), (-1, bond), (-1, virt)]),
+             "R": (["b", "w", "bp"], [(-1, virt), (1, bond), (1, virt)]),
+             "W1": (["wl", "s", "sp", "wr"], [(1, bond), (1, phys), (-1, phys), (-1, bond)]),
+             "psi": (["a", "s1", "s2", "b"], [(1, virt), (1, phys), (1, phys), (-1, virt)])}
+    specs["W2"] = specs["W1"]
+    O = {n: orc.BlockTensor(*sp, sym=sym) for n, sp in specs.items()}
+    for n in ("L", "R", "W1", "psi"):
+        O[n].data[:] = rng.standard_normal(O[n].numel)
+    O["W2"] = O["W1"]
+    return specs, O
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "bf16x6"])
+@pytest.mark.parametrize("which", ["z2", "u1xz2"])
+def test_heff_symmetric_operands(prec, which):
+    """H_eff with Z_2 legs (virtual {0: 96, 1: 80}, MPO bond {0: 3, 1: 2}) or
+    U(1) x Z_2 legs, random operands, against the oracle's apply."""
+    if which == "z2":
+        sym = (2,)
+        virt, phys, bond = [(0, 96), (1, 80)], [(0, 1), (1, 1)], [(0, 3), (1, 2)]
+    else:
+        sym = (0, 2)
+        virt = [((q, p), 20 + 7 * abs(q) + 5 * p) for q in range(-3, 4) for p in (0, 1)]
+        phys = [((1, 0), 1), ((-1, 1), 1)]
+        bond = [((-2, 1), 1), ((0, 0), 2), ((0, 1), 1), ((2, 1), 1)]
+    specs, O = _heff_sym_operands(sym, virt, phys, bond, 77)
+    ref = orc.heff_apply(O["L"], O["W1"], O["W2"], O["R"], O["psi"]).data
+    T = {n: bst.Tensor(*sp, sym=list(sym)) for n, sp in specs.items()}
+    plan = bst.heff_plan(T["L"], T["W1"], T["W2"], T["R"], T["psi"], prec)
+    got = run_heff(plan, O)
+    nrm, mx = rel_err(got, ref)
+    _print("heff", which, prec, O["psi"].numel, nrm, mx)
     assert nrm <= TOL[prec]
 
 

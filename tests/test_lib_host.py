@@ -10,7 +10,7 @@ from hypothesis import given, settings, strategies as st
 
 from oracle import oracle as orc
 from paper_2401_01921_amd import bst, workloads as wl
-from tests.helpers import _random_pair
+from tests.helpers import _random_pair, _random_sym_pair
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -79,6 +79,72 @@ def test_invalid_descriptors():
         bst.Tensor(["a"], [(2, [(0, 1)])])
     T = bst.Tensor(["a", "b"], [(1, [(0, 2)]), (-1, [(1, 2)])])
     assert (T.nblocks, T.numel) == (0, 0)
+
+
+SYMS = [(2,), (3,), (5,), (0, 2), (0, 3), (2, 3)]
+
+
+@pytest.mark.parametrize("sym", SYMS)
+def test_symmetric_structures_bit_exact(sym):
+    """Z_n and product symmetries: the library's block table equals the
+    oracle's, bit for bit, on random structures (repeated charges allowed)."""
+    rng = np.random.default_rng(sum(sym) * 31 + len(sym))
+    for _ in range(25):
+        rank = int(rng.integers(0, 6))
+        legs = []
+        for _ in range(rank):
+            ns = int(rng.integers(1, 7))
+            secs = []
+            for _ in range(ns):
+                c = tuple(int(rng.integers(-3, 4)) if n == 0 else int(rng.integers(0, n)) for n in sym)
+                secs.append((c if len(sym) > 1 else c[0], int(rng.integers(1, 6))))
+            legs.append((int(rng.choice([1, -1])), secs))
+        labels = [f"l{i}" for i in range(rank)]
+        O = orc.BlockTensor(labels, legs, sym=sym)
+        T = bst.Tensor(labels, legs, sym=list(sym))
+        assert (T.nblocks, T.numel) == (len(O.blocks), O.numel)
+        assert T.table() == [(tuple(t), tuple(sh), o) for t, sh, o in O.table()]
+        if rank:
+            assert T.symmetry() == list(sym)
+            want = [q if len(sym) > 1 else (q,) for q, _ in O.legs[0][1]]
+            assert T.leg_charges(0) == want
+
+
+@pytest.mark.parametrize("sym", SYMS)
+def test_symmetric_contract_plan_structure_and_flops(sym):
+    rng = np.random.default_rng(1000 + sum(sym) * 7 + len(sym))
+    for _ in range(20):
+        ra, rb = int(rng.integers(1, 5)), int(rng.integers(1, 5))
+        A, B = _random_sym_pair(rng, ra, rb, min(int(rng.integers(0, 3)), ra, rb), sym)
+        C = orc.contract(A, B)
+        tA = bst.Tensor(A.labels, A.legs, sym=list(sym))
+        tB = bst.Tensor(B.labels, B.legs, sym=list(sym))
+        tC, plan = bst.contract_plan(tA, tB)
+        assert tC.labels == C.labels
+        if C.rank:   # a scalar result has no leg to carry the symmetries
+            assert tC.symmetry() == list(sym)
+        assert tC.table() == [(tuple(t), tuple(sh), o) for t, sh, o in C.table()]
+        assert plan.stats().gemm_flops == orc._contract_flops(A, B)
+
+
+def test_symmetric_errors_match_oracle():
+    with pytest.raises(bst.BstError) as e:
+        bst.Tensor(["a"], [(1, [(3, 1)])], sym=[3])
+    assert e.value.status == "E_QNUM"
+    with pytest.raises(bst.BstError) as e:
+        bst.Tensor(["a"], [(1, [(0, 1)])], sym=[1])
+    assert e.value.status == "E_INVALID"
+    legs = [(1, [(0, 1), (1, 1)]), (-1, [(0, 1), (1, 1)])]
+    A = bst.Tensor(["a", "x"], legs, sym=[2])
+    B = bst.Tensor(["x", "b"], [(1, [(0, 1), (1, 1)]), (-1, [(0, 1), (1, 1)])], sym=[3])
+    with pytest.raises(bst.BstError) as e:
+        bst.contract_plan(A, B)
+    assert e.value.status == "E_QNUM"
+    # a U(1) leg against a Z_2 leg with the same charge values
+    U = bst.Tensor(["x", "b"], [(1, [(0, 1), (1, 1)]), (-1, [(0, 1), (1, 1)])])
+    with pytest.raises(bst.BstError) as e:
+        bst.contract_plan(A, U)
+    assert e.value.status == "E_QNUM"
 
 
 def _legs_of(T):
