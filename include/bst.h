@@ -149,6 +149,28 @@ bst_status bst_tensor_block(const bst_tensor* t, int64_t b, int32_t* qn_idx, int
  * has nonzero flux (Sec. "Accessing elements of a symmetric tensor"). */
 bst_status bst_tensor_find_block(const bst_tensor* t, const int32_t* qn_idx, int64_t* b);
 
+/* ---- network contraction order ------------------------------------------ */
+
+/* Optimal pairwise contraction order of a network of n tensors (Sec.
+ * "Network", "Setting the contraction order"): dynamic programming over
+ * subsets with cost capping.  Cost of one pairwise contraction = product of
+ * the dims of every index it involves (each once); the order minimises the
+ * sum.  Host only.
+ *   n       number of tensors, 1..16
+ *   nlegs   [n] number of indices of each tensor
+ *   legs    [sum nlegs] index ids (0..nid-1), tensor by tensor; an id on
+ *           two tensors is contracted, an id on one tensor stays open
+ *   nid     number of distinct ids, 0..64
+ *   dims    [nid] total dim of each id, >= 1
+ *   pairs   [2 (n-1)] receives the steps in order: step k contracts nodes
+ *           pairs[2k] and pairs[2k+1], where nodes 0..n-1 are the inputs
+ *           and node n + k is the result of step k (null: not written)
+ *   cost    receives the total cost (null: not written)
+ * Errors: BST_E_INVALID (sizes, an id on more than two tensors or twice on
+ * one tensor). */
+bst_status bst_network_order(int32_t n, const int32_t* nlegs, const int32_t* legs, int32_t nid,
+                             const int64_t* dims, int32_t* pairs, double* cost);
+
 /* ---- plans ------------------------------------------------------------ */
 
 /* Permute (Sec. "Permute", App. "Contiguous"): new leg i is the old leg

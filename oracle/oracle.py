@@ -23,6 +23,8 @@ Library for Tensor Networks"):
   (L, two-site MPO, R, two-site wavefunction)
 * Heisenberg and XX chains (dense, for . Sec. "Benchmarks" (the DMRG benchmark
   exact diagonalisation in tests)        is the XX chain)
+* network contraction and its optimal . Sec. "Network" (exhaustive search
+  order                                  over binary trees, dense cost)
 * Lanczos on a linear operator ......... Sec. "Eigenvalue decomposition"
   (LinOp + Lanczos; the paper gives no algorithmic detail, so this is the
   textbook method with full classical Gram-Schmidt reorthogonalisation done
@@ -323,6 +325,63 @@ def contract(A: BlockTensor, B: BlockTensor) -> BlockTensor:
             cb = C.index[fa + fb]
             C.block(cb)[...] += (amat @ bmat).reshape(C.shapes[cb])
     return C
+
+
+# --------------------------------------------------------------------------
+# Network (Sec. "Network"): contraction along a binary tree of tensor names,
+# and the optimal tree by exhaustive search (every binary tree is tried).
+# Cost of one pairwise step: the product of the dims of every index it
+# involves, each once.
+# --------------------------------------------------------------------------
+def network_step_cost(a_idx: Sequence[str], b_idx: Sequence[str], dims: Dict[str, int]) -> int:
+    return int(np.prod([dims[l] for l in dict.fromkeys(list(a_idx) + list(b_idx))], dtype=object))
+
+
+def network_optimal_bruteforce(indices: Dict[str, Sequence[str]], dims: Dict[str, int]):
+    """(minimal total cost, tree) over every binary contraction tree of the
+    named tensors; indices[name] = its index names, an index on two tensors
+    is summed.  Exponential: for small networks only."""
+    names = list(indices)
+    count: Dict[str, int] = {}
+    for n in names:
+        for l in indices[n]:
+            count[l] = count.get(l, 0) + 1
+
+    def open_indices(group):
+        inside: Dict[str, int] = {}
+        for n in group:
+            for l in indices[n]:
+                inside[l] = inside.get(l, 0) + 1
+        return [l for l in inside if inside[l] < count[l] or count[l] == 1]
+
+    def best(group):
+        if len(group) == 1:
+            return 0, group[0]
+        first, rest = group[0], group[1:]
+        out = None
+        # every split into two non-empty parts; the first tensor stays left
+        for r in range(len(rest)):
+            for right in itertools.combinations(rest, r + 1):
+                left = [first] + [n for n in rest if n not in right]
+                right = list(right)
+                cl, tl = best(left)
+                cr, tr = best(right)
+                c = cl + cr + network_step_cost(open_indices(left), open_indices(right), dims)
+                if out is None or c < out[0]:
+                    out = (c, (tl, tr))
+        return out
+
+    return best(names)
+
+
+def network_contract(tensors: Dict[str, BlockTensor], tree, out_labels: Sequence[str]) -> BlockTensor:
+    """Contract along `tree` (nested pairs of names) and permute to out_labels."""
+    def run(node):
+        if isinstance(node, str):
+            return tensors[node]
+        return contract(run(node[0]), run(node[1]))
+
+    return permute(run(tree), list(out_labels))
 
 
 # --------------------------------------------------------------------------

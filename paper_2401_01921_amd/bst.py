@@ -30,6 +30,7 @@ EXPORTS = [
     "bst_lanczos_workspace", "bst_lanczos_ground", "bst_last_error", "bst_version",
     "bst_plan_tile_count", "bst_plan_set_tile", "bst_plan_forget_workspace",
     "bst_tensor_create_sym", "bst_tensor_symmetry", "bst_tensor_leg_charges",
+    "bst_network_order",
 ]
 
 
@@ -76,6 +77,7 @@ def _load():
                                   P(vp)],
         "bst_tensor_symmetry": [vp, P(i32), P(i32), i32],
         "bst_tensor_leg_charges": [vp, i32, P(i32)],
+        "bst_network_order": [i32, P(i32), P(i32), i32, P(i64), P(i32), P(C.c_double)],
         "bst_tensor_destroy": [vp],
         "bst_tensor_info": [vp, P(i32), P(i64), P(i64)],
         "bst_tensor_leg": [vp, i32, P(i32), P(i32), P(i32), P(i64), C.c_char_p, sz],
