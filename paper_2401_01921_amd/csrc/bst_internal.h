@@ -367,8 +367,6 @@ hipError_t launch_lanczos_step_end(const double* partial, int64_t n_for_grid, co
 // coef[0..j] and aest.  pass: rewrites row j of V as v_j, writes the new
 // residual to vnext (may be null), dn[0..j+1] = (V_j^T w, w.w).  end:
 // alpha[j], beta[j], dprev <- dn[0..j].
-hipError_t launch_lanczos_coef(int j, const double* g, const double* alpha, const double* beta,
-                               const double* dprev, double* coef, double* aest, hipStream_t s);
 hipError_t launch_lanczos_pass(double* V, int64_t ldv, int64_t n, int j, const double* z,
                                const double* coef, const double* dprev, const double* beta,
                                double* vnext, double* partial, double* dn, hipStream_t s);
@@ -395,9 +393,6 @@ hipError_t launch_lanczos_pass_sums(int64_t n, int j, bool f32, const double* pa
 hipError_t launch_lanczos_end(const double* dn, const double* aest, int j, double* dprev,
                               double* alpha, double* beta, hipStream_t s);
 // alpha[j] = c[j] + d[j]; beta[j] = sqrt(norm2[0])
-hipError_t launch_lanczos_scalars(const double* c, const double* d, int j, const double* norm2,
-                                  double* alpha, double* beta, hipStream_t s);
 // plain device copy of n doubles
-hipError_t launch_copy(const double* src, double* dst, int64_t n, hipStream_t s);
 
 }  // namespace bst

@@ -552,12 +552,10 @@ hipError_t launch_lanczos_step_end(const double* partial, int64_t n_for_grid, co
 // the symmetric three-term recurrence; in exact arithmetic alpha_j and
 // beta_j equal those of Lanczos with two full classical Gram-Schmidt passes.
 //
-// Scalars of step j from g = u_j.z: alpha, beta and dprev are staged in LDS
-// and one thread evaluates (fixed order): coef[0..j], the coefficients of
-// v_0..v_j in w = z/beta_{j-1} - sum_k coef_k v_k, and aest, the three-term
-// estimate of alpha_j.
-// The scalars of step j (one thread; al, be, dp hold alpha, beta, dprev for
-// k < j).
+// The scalars of step j from g = u_j.z, evaluated by one thread in a fixed
+// order (al, be, dp hold alpha, beta, dprev for k < j): coef[0..j], the
+// coefficients of v_0..v_j in w = z/beta_{j-1} - sum_k coef_k v_k, and aest,
+// the three-term estimate of alpha_j.
 __device__ __forceinline__ void step_coef(int j, double gs, const double* al, const double* be,
                                           const double* dp, double* __restrict__ coef,
                                           double* __restrict__ aest) {
@@ -583,24 +581,6 @@ __device__ __forceinline__ void step_coef(int j, double gs, const double* al, co
   const double a = rb * (vz - ej);
   coef[j] = rb * ej + a;
   aest[0] = a;
-}
-
-__global__ __launch_bounds__(64) void lanczos_coef_kernel(int j, const double* __restrict__ g,
-                                                          const double* __restrict__ alpha,
-                                                          const double* __restrict__ beta,
-                                                          const double* __restrict__ dprev,
-                                                          double* __restrict__ coef,
-                                                          double* __restrict__ aest) {
-  __shared__ double al[kMaxVecs], be[kMaxVecs], dp[kMaxVecs];
-  const int lane = threadIdx.x;
-  const double gs = g[0];
-  for (int k = lane; k < j; k += 64) {
-    al[k] = alpha[k];
-    be[k] = beta[k];
-    dp[k] = dprev[k];
-  }
-  __syncthreads();
-  if (lane == 0) step_coef(j, gs, al, be, dp, coef, aest);
 }
 
 // The pass of step j: per element
@@ -821,8 +801,7 @@ __global__ __launch_bounds__(64) void lanczos_end_kernel(const double* __restric
 // The scalar work between two basis passes, in one block of 1024 threads:
 // the sums of the partials of the pass of step pj (dn) and of the u_j.z,
 // z.z partials of dot2_kernel (g), then the end of step pj (alpha, beta,
-// dprev as lanczos_end_kernel) and the scalars of step j (as
-// lanczos_coef_kernel).  One wave forms each sum: lane l adds partials l,
+// dprev as lanczos_end_kernel) and the scalars of step j (step_coef).  One wave forms each sum: lane l adds partials l,
 // l + 64, ... in order, then the wave sum; every load of a sum is issued at
 // once (grids of at most 1024 blocks).  pj < 0: no pass before (step 0).
 __global__ __launch_bounds__(1024) void lanczos_step_scalars_kernel(
@@ -887,14 +866,6 @@ __global__ __launch_bounds__(1024) void lanczos_step_scalars_kernel(
   g[0] = sv[npv];
   g[1] = sv[npv + 1];
   step_coef(j, sv[npv], al, be, sv, coef, aest);
-}
-
-hipError_t launch_lanczos_coef(int j, const double* g, const double* alpha, const double* beta,
-                               const double* dprev, double* coef, double* aest, hipStream_t s) {
-  if (j < 0 || j >= kMaxVecs) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(lanczos_coef_kernel, dim3(1), dim3(64), 0, s, j, g, alpha, beta, dprev, coef,
-                     aest);
-  return hipGetLastError();
 }
 
 hipError_t launch_lanczos_pass(double* V, int64_t ldv, int64_t n, int j, const double* z,
@@ -1121,26 +1092,6 @@ hipError_t launch_resid(const double* hy, const double* y, const double* num, in
   return hipGetLastError();
 }
 
-__global__ void lanczos_scalars_kernel(const double* c, const double* d, int j,
-                                       const double* norm2, double* alpha, double* beta) {
-  if (threadIdx.x == 0) {
-    alpha[j] = c[j] + d[j];
-    beta[j] = sqrt(norm2[0] > 0.0 ? norm2[0] : 0.0);
-  }
-}
-
-hipError_t launch_lanczos_scalars(const double* c, const double* d, int j, const double* norm2,
-                                  double* alpha, double* beta, hipStream_t s) {
-  hipLaunchKernelGGL(lanczos_scalars_kernel, dim3(1), dim3(64), 0, s, c, d, j, norm2, alpha, beta);
-  return hipGetLastError();
-}
-
-__global__ __launch_bounds__(256) void copy_kernel(const double* __restrict__ src,
-                                                   double* __restrict__ dst, int64_t n) {
-  const int64_t stride = (int64_t)gridDim.x * 256;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) dst[i] = src[i];
-}
-
 struct PtrChunk {
   void* p[256];
 };
@@ -1163,10 +1114,5 @@ hipError_t launch_set_ptrs(void** table, void* const* src, int n, hipStream_t s)
   return hipSuccess;
 }
 
-hipError_t launch_copy(const double* src, double* dst, int64_t n, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(copy_kernel, dim3(vec_grid(n)), dim3(256), 0, s, src, dst, n);
-  return hipGetLastError();
-}
 
 }  // namespace bst
