@@ -612,6 +612,31 @@ def heisenberg_chain_ground(nsites: int, spin: str, J: float = 1.0, charge: int 
     return chain_ground(nsites, spin, "heisenberg", J, charge)
 
 
+def tfim_chain_hamiltonian(nsites: int, h: float, J: float = 1.0) -> np.ndarray:
+    """H = -J sum_i sx_i sx_{i+1} - h sum_i sz_i (open chain), dense, basis
+    sz = +1 first: the transverse-field Ising model of the paper's MPO
+    example (Sec. "Conversion from/to NumPy") without the longitudinal field."""
+    sx = np.array([[0.0, 1.0], [1.0, 0.0]])
+    sz = np.diag([1.0, -1.0])
+    H = np.zeros((2 ** nsites, 2 ** nsites))
+    for i in range(nsites):
+        H -= h * np.kron(np.kron(np.eye(2 ** i), sz), np.eye(2 ** (nsites - i - 1)))
+    for i in range(nsites - 1):
+        H -= J * np.kron(np.kron(np.eye(2 ** i), np.kron(sx, sx)), np.eye(2 ** (nsites - i - 2)))
+    return H
+
+
+def tfim_chain_ground(nsites: int, h: float, J: float = 1.0, parity: int | None = 0) -> float:
+    """Lowest eigenvalue, optionally in one parity sector (number of
+    sz = -1 sites mod 2)."""
+    H = tfim_chain_hamiltonian(nsites, h, J)
+    if parity is not None:
+        down = np.array([bin(i).count("1") % 2 for i in range(2 ** nsites)])
+        keep = np.nonzero(down == parity)[0]
+        H = H[np.ix_(keep, keep)]
+    return float(np.linalg.eigvalsh(H)[0])
+
+
 def _lowest_in_sector(H: np.ndarray, nsites: int, spin: str, charge: int | None) -> float:
     if charge is not None:
         _, _, _, q = _spin_ops(spin)

@@ -340,3 +340,52 @@ def dmrg_like_env(table: BlockTable, numel: int, seed: int, side: str, virt: Lis
         part = out[poff:poff + int(np.prod(psh))].reshape(psh)
         out[off:off + int(np.prod(sh))] = part.transpose(2, 1, 0).ravel()
     return out
+
+
+# --------------------------------------------------------------------------
+# Transverse-field Ising chain with Z_2 parity (the paper's MPO example in
+# Sec. "Conversion from/to NumPy", without its longitudinal field, so that
+# the parity prod_i sigma^z_i is conserved): H = -J sum sx sx - h sum sz.
+# Basis sigma^z = +1, -1 with Z_2 charges 0, 1; sigma^x carries charge 1.
+# Channels as in the Heisenberg MPO (start 2, end 0, 1 carries sigma^x),
+# grouped by charge: [0: ch0, ch2], [1: ch1].
+# --------------------------------------------------------------------------
+TFIM_GROUPED_ORDER = (0, 2, 1)
+TFIM_SYM = (2,)
+
+
+def tfim_physical_sectors() -> List[Tuple[int, int]]:
+    return [(0, 1), (1, 1)]
+
+
+def tfim_mpo_bond() -> List[Tuple[int, int]]:
+    return [(0, 2), (1, 1)]
+
+
+def tfim_grouped_index(ch: int) -> int:
+    return TFIM_GROUPED_ORDER.index(ch)
+
+
+def tfim_mpo_dense(h: float, J: float = 1.0) -> np.ndarray:
+    """Dense W[wl, s, s', wr] (channels grouped) of H = -J sum sx sx - h sum sz."""
+    sx = np.array([[0.0, 1.0], [1.0, 0.0]])
+    sz = np.diag([1.0, -1.0])
+    w = np.zeros((3, 2, 2, 3))
+    w[0, :, :, 0] = np.eye(2)
+    w[2, :, :, 2] = np.eye(2)
+    w[1, :, :, 0] = sx
+    w[2, :, :, 1] = -J * sx
+    w[2, :, :, 0] = -h * sz
+    p = list(TFIM_GROUPED_ORDER)
+    return np.ascontiguousarray(w[p][:, :, :, p])
+
+
+def tfim_heff_specs(virt_a: List[Tuple[int, int]], virt_b: List[Tuple[int, int]]):
+    """Leg specs (Z_2 charges) of L, W1, W2, R and psi, as heff_specs."""
+    ph = tfim_physical_sectors()
+    mb = tfim_mpo_bond()
+    psi = (["a", "s1", "s2", "b"], [(IN, virt_a), (IN, ph), (IN, ph), (OUT, virt_b)])
+    L = (["a", "w", "ap"], [(IN, virt_a), (OUT, mb), (OUT, virt_a)])
+    R = (["b", "w", "bp"], [(OUT, virt_b), (IN, mb), (IN, virt_b)])
+    W = (["wl", "s", "sp", "wr"], [(IN, mb), (IN, ph), (OUT, ph), (OUT, mb)])
+    return {"L": L, "W1": W, "W2": W, "R": R, "psi": psi}

@@ -64,3 +64,31 @@ def chain_heff_dense(nsites: int, spin: str, model: str = "heisenberg"):
     Rd, sb = right_env(nr, spin, model)
     specs = wl.heff_specs(spin, sa, sb, model)
     return Ld, Rd, wl.mpo_dense(spin, model), specs
+
+
+def tfim_chain_heff_dense(nsites: int, h: float):
+    """Centre two-site H_eff of an open transverse-field Ising chain with Z_2
+    parity legs: dense L, R, W and the leg specs (charges mod 2)."""
+    W = wl.tfim_mpo_dense(h)
+    qs = np.array([q for q, _ in wl.tfim_physical_sectors()])
+    nl = (nsites - 2) // 2
+    nr = nsites - 2 - nl
+    L = np.zeros((1, 3, 1))
+    L[0, wl.tfim_grouped_index(2), 0] = 1.0
+    ch = np.zeros(1, dtype=int)
+    for _ in range(nl):
+        D = L.shape[0]
+        L = np.einsum("awb,wstv->asvbt", L, W).reshape(D * 2, 3, D * 2)
+        ch = ((ch[:, None] + qs[None, :]) % 2).ravel()
+    order, sa = _group(ch)
+    L = np.ascontiguousarray(L[order][:, :, order])
+    R = np.zeros((1, 3, 1))
+    R[0, wl.tfim_grouped_index(0), 0] = 1.0
+    ch = np.zeros(1, dtype=int)
+    for _ in range(nr):
+        D = R.shape[0]
+        R = np.einsum("wstv,bvc->sbwtc", W, R).reshape(2 * D, 3, 2 * D)
+        ch = (((-qs)[:, None] + ch[None, :]) % 2).ravel()
+    order, sb = _group(ch)
+    R = np.ascontiguousarray(R[order][:, :, order])
+    return L, R, W, wl.tfim_heff_specs(sa, sb)

@@ -185,6 +185,28 @@ def test_lanczos_xx_chain_free_fermions(prec):
         assert abs(r["energy"] - E0) < 1e-10 * abs(E0)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "bf16x6"])
+@pytest.mark.parametrize("h", [0.7, 1.0])
+def test_lanczos_tfim_z2_chain(prec, h):
+    """Lanczos on Z_2-symmetric tensors: a 10-site transverse-field Ising
+    chain through exact parity environments; the refined energy equals the
+    free-fermion closed form."""
+    from tests.test_oracle_zn import tfim_closed_form
+    Ld, Rd, Wd, specs = chain_env.tfim_chain_heff_dense(10, h)
+    sym = wl.TFIM_SYM
+    O = {"L": orc.from_dense(*specs["L"], Ld, sym=sym), "R": orc.from_dense(*specs["R"], Rd, sym=sym),
+         "W1": orc.from_dense(*specs["W1"], Wd, sym=sym), "psi": orc.BlockTensor(*specs["psi"], sym=sym)}
+    T = {n: bst.Tensor(*sp, sym=list(sym)) for n, sp in specs.items()}
+    plan = bst.heff_plan(T["L"], T["W1"], T["W2"], T["R"], T["psi"], "fp64")
+    ops = [dev(O[n].data) for n in ("L", "W1", "W1", "R")]
+    n = O["psi"].numel
+    r = bst.lanczos_ground(plan, ops, dev(wl.normal(7, n)), min(n, 128), prec, True)
+    torch.cuda.synchronize()
+    E0 = tfim_closed_form(10, h)
+    _print("TFIM Z2", h, prec, r["energy"], E0, r["energy"] - E0, r["steps"])
+    assert abs(r["energy"] - E0) < 1e-10 * abs(E0)
+
+
 def test_lanczos_bf16x3_reports_its_error():
     """bf16x3 matvecs: the refined energy of a 10-site chain, stated (not
     bounded at 1e-10: the split's 2^-17 product error limits the Ritz vector)."""

@@ -97,3 +97,58 @@ def test_symmetry_errors():
     B = orc.BlockTensor(["x", "b"], [(1, [(0, 1), (1, 1)]), (-1, [(0, 1), (1, 1)])], sym=(3,))
     with pytest.raises(orc.QnumError):
         orc.contract(A, B)
+
+
+def tfim_closed_form(nsites: int, h: float, J: float = 1.0) -> float:
+    """Open transverse-field Ising chain (Jordan-Wigner free fermions): the
+    ground energy is -1/2 the sum of the singular values of the bidiagonal
+    matrix with 2h on the diagonal and 2J above it."""
+    T = np.diag([2.0 * h] * nsites) + np.diag([2.0 * J] * (nsites - 1), 1)
+    return -0.5 * float(np.linalg.svd(T, compute_uv=False).sum())
+
+
+@pytest.mark.parametrize("nsites", [2, 3, 4, 6, 8, 9])
+@pytest.mark.parametrize("h", [0.3, 1.0, 1.7])
+def test_tfim_exact_diagonalisation_closed_form(nsites, h):
+    """The even-parity ground energy of the oracle's dense TFIM equals the
+    free-fermion closed form."""
+    assert abs(orc.tfim_chain_ground(nsites, h, parity=0) - tfim_closed_form(nsites, h)) < 1e-12
+
+
+@pytest.mark.parametrize("h", [0.0, 0.6])
+def test_tfim_mpo_bond_term(h):
+    """sum_w W[start, w] (x) W[w, end] is the two-site TFIM Hamiltonian, and
+    W conserves Z_2 parity on its grouped legs."""
+    from paper_2401_01921_amd import workloads as wl
+    W = wl.tfim_mpo_dense(h)
+    a, b = wl.tfim_grouped_index(2), wl.tfim_grouped_index(0)
+    acc = sum(np.kron(W[a, :, :, w], W[w, :, :, b]) for w in range(3))
+    assert np.array_equal(acc, orc.tfim_chain_hamiltonian(2, h))
+    orc.from_dense(*wl.tfim_heff_specs([(0, 1)], [(0, 1)])["W1"], W, sym=(2,))
+
+
+@pytest.mark.parametrize("nsites,h", [(4, 0.5), (6, 1.0), (8, 1.3)])
+def test_tfim_heff_with_z2_environments(nsites, h):
+    """Z_2-symmetric two-site H_eff with exact environments: its lowest
+    eigenvalue (dense, and by the oracle's Lanczos) is the chain's ground
+    energy."""
+    from tests import chain_env
+    from paper_2401_01921_amd import workloads as wl
+    Ld, Rd, Wd, specs = chain_env.tfim_chain_heff_dense(nsites, h)
+    sym = wl.TFIM_SYM
+    L = orc.from_dense(*specs["L"], Ld, sym=sym)
+    R = orc.from_dense(*specs["R"], Rd, sym=sym)
+    W = orc.from_dense(*specs["W1"], Wd, sym=sym)
+    psi = orc.BlockTensor(*specs["psi"], sym=sym)
+    n = psi.numel
+    H = np.zeros((n, n))
+    for i in range(n):
+        e = orc.BlockTensor(psi.labels, psi.legs, sym=sym)
+        e.data[i] = 1.0
+        H[:, i] = orc.heff_apply(L, W, W, R, e).data
+    E0 = tfim_closed_form(nsites, h)
+    assert np.allclose(H, H.T, atol=1e-13)
+    assert abs(np.linalg.eigvalsh(H)[0] - E0) < 1e-10
+    mv = lambda v: orc.heff_apply(L, W, W, R, orc.BlockTensor(psi.labels, psi.legs, v, sym=sym)).data
+    res = orc.lanczos_ground(mv, np.random.default_rng(nsites).standard_normal(n), n)
+    assert abs(res["energy"] - E0) < 1e-10
