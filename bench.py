@@ -130,18 +130,18 @@ def main():
         tuned[prec] = plan.tiles()
     del tune_ws, tune_out
 
-    def solve(prec, timing=False, three_pass=False):
+    def solve(prec, timing=False, three_pass=False, f64_basis=False):
         return bst.lanczos_ground(plan, ops, g["psi0"], m, prec, True, ws=ws, psi_out=psi_out,
-                                  timing=timing, three_pass=three_pass)
+                                  timing=timing, three_pass=three_pass, f64_basis=f64_basis)
 
-    def timed(prec, steps, warmup, three_pass=False):
+    def timed(prec, steps, warmup, three_pass=False, f64_basis=False):
         for _ in range(warmup):
-            solve(prec, three_pass=three_pass)
+            solve(prec, three_pass=three_pass, f64_basis=f64_basis)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         res = None
         for _ in range(steps):
-            res = solve(prec, three_pass=three_pass)
+            res = solve(prec, three_pass=three_pass, f64_basis=f64_basis)
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / steps, res
 
@@ -234,6 +234,12 @@ def main():
             "kernels": {k: round(v, 4) for k, v in
                         solve(a.prec, timing=True, three_pass=True)["kernel_ms"].items()},
             "energy_rel_diff_vs_lagged": abs(res3["energy"] - es) / abs(es)}
+        # the same split solve with float64 Krylov rows (and float64 H u_j)
+        msb, resb = timed(a.prec, max(2, a.steps // 2), 1, f64_basis=True)
+        extras["float64_basis"] = {
+            "ms_per_solve": round(msb * 1e3, 3),
+            "energy_rel_err_vs_fp64": abs(resb["energy"] - e64) / abs(e64),
+            "speedup_vs_fp64": round(ms64 / msb, 3)}
     extras.update({} if a.no_extras else bench_extras(bst, wl, torch, dev, plan, ins_apply=[
         g["L"], g["W1"], g["W2"], g["R"], g["psi0"]], apply_flops=apply_flops))
 

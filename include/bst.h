@@ -307,6 +307,11 @@ typedef struct {
 /* Run the textbook schedule (three passes over the basis per step) instead
  * of the default single pass with delayed projection. */
 #define BST_LANCZOS_THREE_PASS 2
+/* Keep float64 Krylov rows with the BF16X3 / BF16X6 matvec forms.  By default
+ * those forms store the rows, and H u_j, as float32 (every dot, coefficient,
+ * reduction and the tridiagonal solve stay float64); the three-pass schedule
+ * and the FP64 / FP32 forms always use float64 rows. */
+#define BST_LANCZOS_F64_BASIS 4
 
 /* Workspace of bst_lanczos_ground for a plan and step count. */
 bst_status bst_lanczos_workspace(const bst_plan* heff, int32_t nsteps, size_t* bytes);
@@ -314,7 +319,7 @@ bst_status bst_lanczos_workspace(const bst_plan* heff, int32_t nsteps, size_t* b
 /* Lowest eigenpair of the H_eff of `heff` (a bst_heff_plan), which must be
  * symmetric.  Lanczos with full reorthogonalisation: v1 = psi0/|psi0|; per
  * step w = H v_j in the form `matvec_prec`, w projected against all
- * previous vectors in float64 (the reference order: two classical
+ * previous vectors with float64 arithmetic (the reference order: two classical
  * Gram-Schmidt passes), alpha_j, beta_j = |w|, v_{j+1} = w/beta_j; the steps stop at the first
  * beta_j <= 1e-12 max(|alpha|, beta_j).  By default a step reads the basis
  * once: the operator is applied to the residual of the previous step before
@@ -325,7 +330,8 @@ bst_status bst_lanczos_workspace(const bst_plan* heff, int32_t nsteps, size_t* b
  * 2021 and Bielich et al. 2022); alpha and beta equal those of two full
  * classical Gram-Schmidt passes in exact arithmetic.
  * BST_LANCZOS_THREE_PASS in info->flags runs the textbook order (three
- * passes over the basis per step).  The
+ * passes over the basis per step).  With BF16X3 / BF16X6 the basis rows are
+ * float32 unless BST_LANCZOS_F64_BASIS is set.  The
  * float64 tridiagonal eigensolve (Sturm bisection, inverse iteration) gives
  * the Ritz pair (theta, y = V s).  With refine != 0, one float64 apply gives
  * E = y.Hy / y.y; otherwise E = theta.

@@ -439,11 +439,12 @@ def lanczos_workspace(plan: Plan, nsteps: int) -> int:
 
 def lanczos_ground(plan: Plan, ops, psi0, nsteps: int, prec="fp64", refine: bool = True,
                    ws=None, psi_out=None, stream=None, timing: bool = False,
-                   three_pass: bool = False):
+                   three_pass: bool = False, f64_basis: bool = False):
     """ops = [L, W1, W2, R] device tensors; psi0 device tensor.  Returns a dict
     with energy, theta, steps, residual, beta_min, alpha, beta and psi.
     three_pass selects the textbook reorthogonalisation schedule (three passes
-    over the basis per step) instead of the default single pass."""
+    over the basis per step) instead of the default single pass; f64_basis
+    keeps float64 Krylov rows with the bf16x3 / bf16x6 forms."""
     import torch
     if ws is None:
         ws = workspace(lanczos_workspace(plan, nsteps), psi0.device)
@@ -460,7 +461,7 @@ def lanczos_ground(plan: Plan, ops, psi0, nsteps: int, prec="fp64", refine: bool
     a = (C.c_void_p * 4)(*[_ptr(t) for t in ops])
     e = C.c_double()
     info = LanczosInfo()
-    info.flags = (1 if timing else 0) | (2 if three_pass else 0)
+    info.flags = (1 if timing else 0) | (2 if three_pass else 0) | (4 if f64_basis else 0)
     _check(_lib.bst_lanczos_ground(plan.handle, a, C.c_void_p(_ptr(psi0)), nsteps, _prec(prec),
                                    1 if refine else 0, C.c_void_p(_ptr(psi_out)), C.byref(e),
                                    C.byref(info), C.c_void_p(_ptr(ws)), _stream(stream)))

@@ -230,7 +230,8 @@ bst_status bst_lanczos_ground(bst_plan* heff, const void* const* ops, const void
     fail(BST_E_INVALID, "Krylov basis above 4 GiB (reduce nsteps)");
   const bool three_pass = info && (info->flags & BST_LANCZOS_THREE_PASS);
   // Krylov rows: float32 with the split forms and the one-pass schedule
-  const bool vf32 = !three_pass && (matvec_prec == BST_BF16X3 || matvec_prec == BST_BF16X6);
+  const bool f64_basis = info && (info->flags & BST_LANCZOS_F64_BASIS);
+  const bool vf32 = !three_pass && !f64_basis && (matvec_prec == BST_BF16X3 || matvec_prec == BST_BF16X6);
   double* V = reinterpret_cast<double*>(wb + Lo.V);
   float* V32 = reinterpret_cast<float*>(wb + Lo.V);
   auto row = [&](int j) -> void* {

@@ -130,11 +130,12 @@ def test_empty_and_degenerate_buffers():
 
 
 # ---------------------------------------------------------------- Lanczos
-def _lanczos_lib(specs, O, nsteps, prec, refine=True, psi0=None, three_pass=False):
+def _lanczos_lib(specs, O, nsteps, prec, refine=True, psi0=None, three_pass=False, f64_basis=False):
     T, plan = lib_heff(specs, "fp64")
     ops = [dev(O[n].data) for n in ("L", "W1", "W2", "R")]
     p0 = dev(psi0 if psi0 is not None else wl.normal(999, O["psi"].numel))
-    r = bst.lanczos_ground(plan, ops, p0, nsteps, prec, refine, three_pass=three_pass)
+    r = bst.lanczos_ground(plan, ops, p0, nsteps, prec, refine, three_pass=three_pass,
+                           f64_basis=f64_basis)
     torch.cuda.synchronize()
     return r
 
@@ -239,10 +240,13 @@ def test_lanczos_matches_oracle_medium(three_pass):
     assert abs(r["energy"] - ref["energy"]) <= 1e-12 * abs(ref["energy"])
     y = host(r["psi"])
     assert abs(abs(float(y @ ref["y"]) / np.linalg.norm(ref["y"])) - 1.0) < 1e-10
-    for prec in ("fp32", "bf16x6", "bf16x3"):
-        rs = _lanczos_lib(specs, O, 40, prec, psi0=psi0, three_pass=three_pass)
+    for prec, f64b in (("fp32", False), ("bf16x6", False), ("bf16x3", False), ("bf16x6", True),
+                       ("bf16x3", True)):
+        if three_pass and f64b:
+            continue   # the three-pass schedule always keeps float64 rows
+        rs = _lanczos_lib(specs, O, 40, prec, psi0=psi0, three_pass=three_pass, f64_basis=f64b)
         err = abs(rs["energy"] - ref["energy"]) / abs(ref["energy"])
-        _print("medium", prec, "refined rel err", err, "theta rel err",
+        _print("medium", prec, "f64 basis" if f64b else "", "refined rel err", err, "theta rel err",
                abs(rs["theta"] - ref["theta"]) / abs(ref["theta"]))
         if prec != "bf16x3":
             assert err <= 1e-10
