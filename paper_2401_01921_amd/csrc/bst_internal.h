@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 #include <map>
 #include <memory>
 #include <string>
@@ -106,6 +107,10 @@ struct GemmSeg {
 // which the memory system fetches as one request instead of two.
 __host__ __device__ constexpr int64_t plane_at(int np, int64_t pos, int q) {
   return np * (pos - (pos & 7)) + 8 * q + (pos & 7);
+}
+// The same in 32 bits, for callers that checked that the result fits.
+__host__ __device__ constexpr uint32_t plane_at(int np, uint32_t pos, int q) {
+  return (uint32_t)np * (pos - (pos & 7u)) + 8u * (uint32_t)q + (pos & 7u);
 }
 // One output block: C[M x N] row-major (ldc) = sum over its segments.
 struct GemmProb {
@@ -318,6 +323,7 @@ struct HApplyLaunch {
   const int32_t* cnt = nullptr;
   const int32_t* idx = nullptr;
   const void* val = nullptr;
+  bool off32 = false;          // every plane index fits 32-bit byte offsets (plan-checked)
 };
 hipError_t launch_happly(const HApplyLaunch& h, hipStream_t s);
 hipError_t launch_happly_sparse(const HApplyLaunch& h, hipStream_t s);

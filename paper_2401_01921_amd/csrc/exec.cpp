@@ -241,10 +241,12 @@ void run_steps_impl(PlanData& P, void* ws, void* const* dptrs, bst_precision pre
         h.ptrs = dptrs;
         h.coef = inter == ElemType::F64 ? (const void*)(wsb + P.ws_coef64_off)
                                         : (const void*)(wsb + P.ws_coef32_off);
+        h.off32 = st.mpo_off32;
         if (planes && st.has_alt) {
           h.np = np;
           h.tasks = reinterpret_cast<const HTask*>(blob + st.off3);
           h.planes = reinterpret_cast<const HPlane*>(blob + st.off4);
+          h.off32 = st.mpo_off32_alt;
         }
         if (P.sparse_mpo) {
           h.cnt = reinterpret_cast<const int32_t*>(wsb + P.ws_cnt_off);

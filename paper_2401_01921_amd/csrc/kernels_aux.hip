@@ -177,7 +177,7 @@ hipError_t launch_hcoef(const HCoefLaunch& c, hipStream_t s) {
 // (one column per lane, no bank conflicts) and runs only the nonzero terms
 // of its class.  The terms of an output are added in increasing input order,
 // so the result equals the dense product bit for bit.
-template <typename T, int NMAX, int NP>
+template <typename T, int NMAX, int NP, bool O32>
 __global__ __launch_bounds__(256) void happly_sparse_kernel(const HTask* __restrict__ tasks,
                                                             const HPlane* __restrict__ planes,
                                                             const HWork* __restrict__ work,
@@ -209,8 +209,13 @@ __global__ __launch_bounds__(256) void happly_sparse_kernel(const HTask* __restr
   // only its own column, so no barrier is needed)
   T xr[NMAX];
 #pragma unroll
-  for (int k = 0; k < NMAX; ++k)
-    xr[k] = (k < t.nin) ? in[pl[k].off + (int64_t)i * pl[k].rowstride + jc] : T(0);
+  for (int k = 0; k < NMAX; ++k) {
+    if constexpr (O32)
+      xr[k] = (k < t.nin) ? in[(uint32_t)pl[k].off + (uint32_t)i * (uint32_t)pl[k].rowstride + (uint32_t)jc]
+                          : T(0);
+    else
+      xr[k] = (k < t.nin) ? in[pl[k].off + (int64_t)i * pl[k].rowstride + jc] : T(0);
+  }
 #pragma unroll
   for (int k = 0; k < NMAX; ++k) xs[k][tid] = xr[k];
   for (int o = 0; o < t.nout; ++o) {
@@ -218,7 +223,9 @@ __global__ __launch_bounds__(256) void happly_sparse_kernel(const HTask* __restr
     const int n = sc[o];
     for (int e = 0; e < n; ++e) y += sv[o * NMAX + e] * xs[si[o * NMAX + e]][tid];
     const HPlane q = pl[t.nin + o];
-    const int64_t at = q.off + (int64_t)i * q.rowstride + jc;
+    using IX = typename std::conditional<O32, uint32_t, int64_t>::type;
+    const IX at = O32 ? (IX)((uint32_t)q.off + (uint32_t)i * (uint32_t)q.rowstride + (uint32_t)jc)
+                      : (IX)(q.off + (int64_t)i * q.rowstride + jc);
     if constexpr (NP == 0) {
       ((BST_G T*)(ptrs[t.out_buf]))[at] = y;
     } else {
@@ -246,8 +253,12 @@ hipError_t launch_happly_sparse(const HApplyLaunch& h, hipStream_t s) {
   dim3 grid((unsigned)h.nwork), block(256);
 #define BST_HS(T_, N_, P_)                                                                     \
   if (h.nmax == N_ && h.np == P_) {                                                            \
-    hipLaunchKernelGGL((happly_sparse_kernel<T_, N_, P_>), grid, block, 0, s, h.tasks, h.planes, \
-                       h.work, h.ptrs, h.cnt, h.idx, reinterpret_cast<const T_*>(h.val));      \
+    if (h.off32)                                                                               \
+      hipLaunchKernelGGL((happly_sparse_kernel<T_, N_, P_, true>), grid, block, 0, s, h.tasks,   \
+                         h.planes, h.work, h.ptrs, h.cnt, h.idx, reinterpret_cast<const T_*>(h.val)); \
+    else                                                                                       \
+      hipLaunchKernelGGL((happly_sparse_kernel<T_, N_, P_, false>), grid, block, 0, s, h.tasks,  \
+                         h.planes, h.work, h.ptrs, h.cnt, h.idx, reinterpret_cast<const T_*>(h.val)); \
     return hipGetLastError();                                                                  \
   }
   if (h.t == ElemType::F64) {

@@ -1284,6 +1284,21 @@ void finalize(PlanData& P) {
       }
       case StepKind::HApply: {
         st.nmax = st.ncls == 0 ? 8 : round_nmax(st.nmax);
+        // largest element index of every plane, times 3 (plane interleave)
+        // plus a chunk, times the widest element (8 bytes), below 2^32
+        auto fit32 = [](const std::vector<HTask>& ts, const std::vector<HPlane>& ps) {
+          for (const auto& t : ts)
+            for (int32_t q = 0; q < t.nin + t.nout; ++q) {
+              const HPlane& pl = ps[(size_t)t.plane_begin + q];
+              if (pl.off < 0 || pl.rowstride < 0) return false;
+              const int64_t last = pl.off + (int64_t)(t.rows > 0 ? t.rows - 1 : 0) * pl.rowstride +
+                                   (t.cols > 0 ? t.cols - 1 : 0);
+              if ((last + 8) * 3 * 8 >= ((int64_t)1 << 32)) return false;
+            }
+          return true;
+        };
+        st.mpo_off32 = fit32(st.tasks, st.planes);
+        st.mpo_off32_alt = st.has_alt && fit32(st.tasks_alt, st.planes_alt);
         std::vector<HWork> work;
         for (size_t ti = 0; ti < st.tasks.size(); ++ti) {
           const int64_t sites = (int64_t)st.tasks[ti].rows * st.tasks[ti].cols;

@@ -78,6 +78,9 @@ struct Step {
   std::vector<SplitWork> swork;
   // operand-only preparation, valid for as long as L, W and R do not change
   bool constant = false;
+  // MPO apply: every plane index (scaled for the bfloat16 plane interleave)
+  // has a byte offset below 2^32, so the kernel may index in 32 bits
+  bool mpo_off32 = false, mpo_off32_alt = false;
   // the split of the H_eff input psi (reads float32 rows while the plan runs
   // inside a float32-basis Lanczos solve)
   bool reads_psi = false;
