@@ -39,7 +39,7 @@ WORKLOAD = 5
 # 16 hex digits of that file's sha256; any change reports traffic as null.
 TRAFFIC = {
     "gs_update": {"bytes_per_launch": 4.319e8, "src": "paper_2401_01921_amd/csrc/kernels_aux.hip",
-                  "src_sha": "ad05a84c2d317b8f",
+                  "src_sha": "55cea5fbc56dcd01",
                   "profile": "profiles/hbm_traffic_lanczos40-spin1-chi4096.md"},
 }
 
