@@ -388,6 +388,13 @@ static inline int vec_grid(int64_t n) {
   return (int)g;
 }
 
+// Grid of the float32 basis pass: at most 512 blocks (two per CU at the
+// pass's two waves per SIMD); its partial count is what the step kernel sums.
+static inline int pass_grid_f32(int64_t n) {
+  const int g = vec_grid((n + 1) / 2);
+  return g < 512 ? g : 512;
+}
+
 // The Krylov basis is read through one base pointer plus a 32-bit per-lane
 // byte offset (V is below 4 GiB, checked on the host), so the row addresses
 // need neither 64-bit VGPR pairs nor one SGPR pair per row; the empty asm
@@ -897,7 +904,7 @@ hipError_t launch_lanczos_pass(float* V, int64_t ldv, int64_t n, int j, const fl
   if (j < 0 || j + 2 > kMaxVecs + 1 || n > 0x7FFFFFFF || ldv > 0x7FFFFFFF || ldv % 2 ||
       (uint64_t)ldv * (uint64_t)(j + 1) * 4u >= 0xFFFFFFFFull)
     return hipErrorInvalidValue;
-  const int G = vec_grid((n + 1) / 2);
+  const int G = pass_grid_f32(n);
   const int nv = j > 0 ? j : 1;
   #define BST_PF32(NV_)                                                                                      \
   hipLaunchKernelGGL((lanczos_pass_f32_kernel<NV_, float>), dim3(G), dim3(256), 0, s, V, (uint32_t)ldv, \
@@ -919,7 +926,7 @@ hipError_t launch_lanczos_pass(float* V, int64_t ldv, int64_t n, int j, const fl
 hipError_t launch_lanczos_pass_sums(int64_t n, int j, bool f32, const double* partial, double* dn,
                                    hipStream_t s) {
   if (j < 0 || j + 2 > kMaxVecs + 1 || n < 0) return hipErrorInvalidValue;
-  const int G = f32 ? vec_grid((n + 1) / 2) : vec_grid(n);
+  const int G = f32 ? pass_grid_f32(n) : vec_grid(n);
   hipLaunchKernelGGL(reduce_partials_kernel, dim3(j + 2), dim3(256), 0, s, partial, G, dn);
   return hipGetLastError();
 }
@@ -1020,17 +1027,39 @@ hipError_t launch_scale_rnorm(const double* src, const double* norm2, float* dst
   return hipGetLastError();
 }
 
-template <typename TX, typename TY>
+// PAIR (float32 x and y, both 8-byte aligned, n < 2^31): two elements per
+// lane with one 8-byte load each; otherwise one element per lane.
+template <typename TX, typename TY, bool PAIR>
 __global__ __launch_bounds__(256) void dot2_kernel(const TX* __restrict__ x,
                                                    const TY* __restrict__ y, int64_t n,
                                                    double* __restrict__ partial) {
   __shared__ double red[4 * 2];
   double acc[2] = {0.0, 0.0};
-  const int64_t stride = (int64_t)gridDim.x * 256;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
-    const double yi = (double)y[i];
-    acc[0] += (double)x[i] * yi;
-    acc[1] += yi * yi;
+  if constexpr (PAIR && sizeof(TX) == 4 && sizeof(TY) == 4) {
+    typedef float fl2 __attribute__((ext_vector_type(2)));
+    const uint32_t npair = (uint32_t)((n + 1) / 2);
+    const uint32_t stride = gridDim.x * 256u;
+    for (uint32_t p = blockIdx.x * 256u + threadIdx.x; p < npair; p += stride) {
+      fl2 xv, yv;
+      if (2u * p + 1u < (uint32_t)n) {
+        xv = __builtin_nontemporal_load(reinterpret_cast<const fl2*>(x) + p);
+        yv = __builtin_nontemporal_load(reinterpret_cast<const fl2*>(y) + p);
+      } else {
+        xv = fl2{x[2u * p], 0.f};
+        yv = fl2{y[2u * p], 0.f};
+      }
+      acc[0] += (double)xv.x * (double)yv.x;
+      acc[0] += (double)xv.y * (double)yv.y;
+      acc[1] += (double)yv.x * (double)yv.x;
+      acc[1] += (double)yv.y * (double)yv.y;
+    }
+  } else {
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
+      const double yi = (double)y[i];
+      acc[0] += (double)x[i] * yi;
+      acc[1] += yi * yi;
+    }
   }
   block_reduce_store<2>(acc, 2, red, partial);
 }
@@ -1039,7 +1068,7 @@ template <typename TX>
 static hipError_t dot2_impl(const TX* x, const double* y, int64_t n, double* partial, double* out,
                             hipStream_t s) {
   const int G = vec_grid(n);
-  hipLaunchKernelGGL((dot2_kernel<TX, double>), dim3(G), dim3(256), 0, s, x, y, n, partial);
+  hipLaunchKernelGGL((dot2_kernel<TX, double, false>), dim3(G), dim3(256), 0, s, x, y, n, partial);
   if (out) hipLaunchKernelGGL(reduce_partials_kernel, dim3(2), dim3(256), 0, s, partial, G, out);
   return hipGetLastError();
 }
@@ -1058,11 +1087,16 @@ static hipError_t dot_step_impl(const TX* x, const TZ* z, int64_t n, double* dpa
                                 double* alpha, double* beta, double* dprev, double* coef,
                                 double* aest, hipStream_t s) {
   if (j < 0 || j >= kMaxVecs || pj != j - 1 || n < 0) return hipErrorInvalidValue;
-  const int G = vec_grid(n);
+  const bool pair = sizeof(TX) == 4 && sizeof(TZ) == 4 && n <= 0x7FFFFFFF &&
+                    ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(z)) & 7) == 0;
+  const int G = pair ? vec_grid((n + 1) / 2) : vec_grid(n);
   // the basis pass's grid: one element (float64 rows) or pair (float32) per lane
-  const int pG = sizeof(TX) == 4 ? vec_grid((n + 1) / 2) : vec_grid(n);
+  const int pG = sizeof(TX) == 4 ? pass_grid_f32(n) : vec_grid(n);
   if (G > 1024 || pG > 1024) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((dot2_kernel<TX, TZ>), dim3(G), dim3(256), 0, s, x, z, n, dpart);
+  if (pair)
+    hipLaunchKernelGGL((dot2_kernel<TX, TZ, true>), dim3(G), dim3(256), 0, s, x, z, n, dpart);
+  else
+    hipLaunchKernelGGL((dot2_kernel<TX, TZ, false>), dim3(G), dim3(256), 0, s, x, z, n, dpart);
   hipLaunchKernelGGL(lanczos_step_scalars_kernel, dim3(1), dim3(1024), 0, s, ppart, pG, pj, dpart, G, j,
                      dn, g, alpha, beta, dprev, coef, aest);
   return hipGetLastError();
