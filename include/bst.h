@@ -261,6 +261,13 @@ bst_status bst_execute(bst_plan* p, const void* const* in, void* const* out, voi
 bst_status bst_plan_autotune(bst_plan* p, const void* const* in, void* const* out, void* ws,
                              void* stream, int32_t reps);
 
+/* Records the plan's chosen tile shapes (from bst_plan_autotune or
+ * bst_plan_set_tile) in the file named by BST_TUNE_CACHE, keeping the file's
+ * entries for other structures; plans created later with the same GEMM
+ * structure start from these choices.  Error BST_E_INVALID if the variable
+ * is not set.  Host only. */
+bst_status bst_plan_record_tiles(const bst_plan* p);
+
 /* Number of compiled GEMM kernel variants (tile shape, with or without LDS
  * staging) available to the plan's GEMM steps in the given form, and a manual
  * choice of one of them for every GEMM step (0 <= tile < count). */
@@ -307,11 +314,12 @@ typedef struct {
 /* Run the textbook schedule (three passes over the basis per step) instead
  * of the default single pass with delayed projection. */
 #define BST_LANCZOS_THREE_PASS 2
-/* Keep float64 Krylov rows with the BF16X3 / BF16X6 matvec forms.  By default
- * those forms store the rows, and H u_j, as float32 (every dot, coefficient,
- * reduction and the tridiagonal solve stay float64); the three-pass schedule
- * and the FP64 / FP32 forms always use float64 rows. */
-#define BST_LANCZOS_F64_BASIS 4
+/* Store the Krylov rows, and H u_j, as float32 with the BF16X3 / BF16X6
+ * matvec forms (every dot, coefficient, reduction and the tridiagonal solve
+ * stay float64).  By default every form keeps float64 rows, i.e. the full
+ * reorthogonalisation runs on float64 vectors; the three-pass schedule and
+ * the FP64 / FP32 forms ignore this flag. */
+#define BST_LANCZOS_F32_BASIS 4
 
 /* Workspace of bst_lanczos_ground for a plan and step count. */
 bst_status bst_lanczos_workspace(const bst_plan* heff, int32_t nsteps, size_t* bytes);
@@ -330,8 +338,8 @@ bst_status bst_lanczos_workspace(const bst_plan* heff, int32_t nsteps, size_t* b
  * 2021 and Bielich et al. 2022); alpha and beta equal those of two full
  * classical Gram-Schmidt passes in exact arithmetic.
  * BST_LANCZOS_THREE_PASS in info->flags runs the textbook order (three
- * passes over the basis per step).  With BF16X3 / BF16X6 the basis rows are
- * float32 unless BST_LANCZOS_F64_BASIS is set.  The
+ * passes over the basis per step).  The basis rows are float64 unless
+ * BST_LANCZOS_F32_BASIS is set with BF16X3 / BF16X6.  The
  * float64 tridiagonal eigensolve (Sturm bisection, inverse iteration) gives
  * the Ritz pair (theta, y = V s).  With refine != 0, one float64 apply gives
  * E = y.Hy / y.y; otherwise E = theta.
@@ -345,6 +353,31 @@ bst_status bst_lanczos_ground(bst_plan* heff, const void* const* ops, const void
                               int32_t nsteps, bst_precision matvec_prec, int32_t refine,
                               void* psi_out, double* energy, bst_lanczos_info* info, void* ws,
                               void* stream);
+
+/* ---- calibration (the device's practical rates, measured with this
+ *      library's own code) ------------------------------------------------ */
+
+/* Workgroups of every calibration launch (256 lanes each). */
+int32_t bst_calib_grid(void);
+
+/* Enqueues a streaming copy of `bytes` (a multiple of 16) from src to dst,
+ * both 16-byte aligned device pointers: every byte is read once and written
+ * once with 16-byte non-temporal accesses.  Errors: BST_E_INVALID. */
+bst_status bst_calib_copy(const void* src, void* dst, size_t bytes, void* stream);
+
+/* Enqueues a streaming read of `bytes` (a multiple of 16) at src; each
+ * workgroup writes the sum of its elements to partial[bst_calib_grid()]
+ * (device), so the reads cannot be dropped.  Errors: BST_E_INVALID. */
+bst_status bst_calib_read(const void* src, size_t bytes, double* partial, void* stream);
+
+/* Enqueues iters rounds of eight independent MFMA instructions per wave on
+ * register operands, on every wave of bst_calib_grid() workgroups of 4 waves:
+ * form BST_FP64 uses the 16x16x4 float64 instruction, BST_BF16X3 the
+ * 16x16x32 bfloat16 one (float32 accumulate).  *flops receives the flops of
+ * the launch; out (device) receives 256 * bst_calib_grid() doubles.
+ * Errors: BST_E_INVALID for another form or iters < 1. */
+bst_status bst_calib_mfma(bst_precision form, int64_t iters, double* out, double* flops,
+                          void* stream);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char* bst_last_error(void);

@@ -14,7 +14,9 @@ from typing import List, Sequence, Tuple
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libbst.so")
+# BST_LIB may name another build of the same library (the host-sanitized
+# build used by the test suite); by default the in-tree libbst.so.
+LIB_PATH = os.environ.get("BST_LIB") or os.path.join(HERE, "libbst.so")
 
 STATUS = {0: "OK", 1: "E_INVALID", 2: "E_DIRECTION", 3: "E_QNUM", 4: "E_DIM", 5: "E_LABEL",
           6: "E_NOBLOCK", 7: "E_STRUCTURE", 8: "E_DEVICE", 9: "E_NOTCONV"}
@@ -30,7 +32,7 @@ EXPORTS = [
     "bst_lanczos_workspace", "bst_lanczos_ground", "bst_last_error", "bst_version",
     "bst_plan_tile_count", "bst_plan_set_tile", "bst_plan_forget_workspace",
     "bst_tensor_create_sym", "bst_tensor_symmetry", "bst_tensor_leg_charges",
-    "bst_network_order",
+    "bst_network_order", "bst_plan_record_tiles", "bst_calib_grid", "bst_calib_copy", "bst_calib_read", "bst_calib_mfma",
 ]
 
 
@@ -97,6 +99,7 @@ def _load():
         "bst_plan_tiles": [vp, C.c_char_p, sz],
         "bst_plan_tile_count": [vp, C.c_int, P(i32)],
         "bst_plan_set_tile": [vp, C.c_int, i32],
+        "bst_plan_record_tiles": [vp],
         "bst_plan_profile": [vp, P(vp), P(vp), vp, vp, i32, P(C.c_double), i32, P(i32)],
         "bst_plan_destroy": [vp],
         "bst_plan_forget_workspace": [vp],
@@ -104,12 +107,19 @@ def _load():
         "bst_lanczos_ground": [vp, P(vp), vp, i32, C.c_int, i32, vp, P(C.c_double),
                                P(LanczosInfo), vp, vp],
     }
+    sig.update({
+        "bst_calib_copy": [vp, vp, sz, vp],
+        "bst_calib_read": [vp, sz, vp, vp],
+        "bst_calib_mfma": [C.c_int, i64, vp, P(C.c_double), vp],
+    })
     for name, args in sig.items():
         f = getattr(lib, name)
         f.argtypes = args
         f.restype = C.c_int
     lib.bst_last_error.restype = C.c_char_p
     lib.bst_last_error.argtypes = []
+    lib.bst_calib_grid.restype = C.c_int32
+    lib.bst_calib_grid.argtypes = []
     lib.bst_version.restype = C.c_char_p
     lib.bst_version.argtypes = []
     return lib
@@ -337,6 +347,10 @@ class Plan:
     def set_tile(self, prec, tile: int):
         _check(_lib.bst_plan_set_tile(self._h, _prec(prec), tile))
 
+    def record_tiles(self):
+        """Write the chosen tile shapes into the BST_TUNE_CACHE file."""
+        _check(_lib.bst_plan_record_tiles(self._h))
+
     def tiles(self) -> str:
         buf = C.create_string_buffer(4096)
         _check(_lib.bst_plan_tiles(self._h, buf, 4096))
@@ -439,12 +453,13 @@ def lanczos_workspace(plan: Plan, nsteps: int) -> int:
 
 def lanczos_ground(plan: Plan, ops, psi0, nsteps: int, prec="fp64", refine: bool = True,
                    ws=None, psi_out=None, stream=None, timing: bool = False,
-                   three_pass: bool = False, f64_basis: bool = False):
+                   three_pass: bool = False, f32_basis: bool = False):
     """ops = [L, W1, W2, R] device tensors; psi0 device tensor.  Returns a dict
     with energy, theta, steps, residual, beta_min, alpha, beta and psi.
     three_pass selects the textbook reorthogonalisation schedule (three passes
-    over the basis per step) instead of the default single pass; f64_basis
-    keeps float64 Krylov rows with the bf16x3 / bf16x6 forms."""
+    over the basis per step) instead of the default single pass; f32_basis
+    stores the Krylov rows as float32 with the bf16x3 / bf16x6 forms (float64
+    rows by default)."""
     import torch
     if ws is None:
         ws = workspace(lanczos_workspace(plan, nsteps), psi0.device)
@@ -461,7 +476,7 @@ def lanczos_ground(plan: Plan, ops, psi0, nsteps: int, prec="fp64", refine: bool
     a = (C.c_void_p * 4)(*[_ptr(t) for t in ops])
     e = C.c_double()
     info = LanczosInfo()
-    info.flags = (1 if timing else 0) | (2 if three_pass else 0) | (4 if f64_basis else 0)
+    info.flags = (1 if timing else 0) | (2 if three_pass else 0) | (4 if f32_basis else 0)
     _check(_lib.bst_lanczos_ground(plan.handle, a, C.c_void_p(_ptr(psi0)), nsteps, _prec(prec),
                                    1 if refine else 0, C.c_void_p(_ptr(psi_out)), C.byref(e),
                                    C.byref(info), C.c_void_p(_ptr(ws)), _stream(stream)))
@@ -473,3 +488,40 @@ def lanczos_ground(plan: Plan, ops, psi0, nsteps: int, prec="fp64", refine: bool
         out["kernel_ms"] = {n: info.kernel_ms[i] for i, n in enumerate(LANCZOS_KERNEL_CLASSES)}
         out["kernel_calls"] = {n: info.kernel_calls[i] for i, n in enumerate(LANCZOS_KERNEL_CLASSES)}
     return out
+
+
+# --------------------------------------------------------------------------
+# calibration kernels (the device's practical streaming and MFMA rates)
+def calib_grid() -> int:
+    return int(_lib.bst_calib_grid())
+
+
+def calib_copy(src, dst, stream=None):
+    """Streaming copy of src into dst (device tensors of equal byte size)."""
+    nb = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nb:
+        raise BstError(1, "copy buffers differ in size")
+    _check(_lib.bst_calib_copy(C.c_void_p(_ptr(src)), C.c_void_p(_ptr(dst)), nb, _stream(stream)))
+
+
+def calib_read(src, partial, stream=None):
+    """Streaming read of src; partial (float64, calib_grid() elements) gets
+    one sum per workgroup."""
+    import torch
+    if partial.dtype != torch.float64 or partial.numel() < calib_grid():
+        raise BstError(1, "partial needs calib_grid() float64 elements")
+    _check(_lib.bst_calib_read(C.c_void_p(_ptr(src)), src.numel() * src.element_size(),
+                               C.c_void_p(_ptr(partial)), _stream(stream)))
+
+
+def calib_mfma(prec, iters: int, out, stream=None) -> float:
+    """Back-to-back MFMA loop in form prec ("fp64" or "bf16x3" for the
+    bfloat16 instruction); out holds 256 * calib_grid() float64.  Returns the
+    flops of the launch."""
+    import torch
+    if out.dtype != torch.float64 or out.numel() < 256 * calib_grid():
+        raise BstError(1, "out needs 256 * calib_grid() float64 elements")
+    f = C.c_double()
+    _check(_lib.bst_calib_mfma(_prec(prec), int(iters), C.c_void_p(_ptr(out)), C.byref(f),
+                               _stream(stream)))
+    return f.value

@@ -276,7 +276,7 @@ static void drop_graph(PlanData& P) {
   P.graph_ws = nullptr;
 }
 
-static std::string tune_key(const PlanData& P, const Step& st, bst_precision form) {
+static std::string tune_key(const PlanData& P, const Step& st, int form) {
   // structure signature: problem sizes and segment counts
   uint64_t h = 1469598103934665603ull;
   auto mix = [&](uint64_t v) {
@@ -285,7 +285,7 @@ static std::string tune_key(const PlanData& P, const Step& st, bst_precision for
   };
   mix((uint64_t)form);
   mix((uint64_t)st.transb);
-  const bool alt = (int)form >= 10 && st.has_alt;   // plane variant keys
+  const bool alt = form >= 10 && st.has_alt;   // plane variant keys (10 + form)
   for (const auto& p : alt ? st.probs_alt : st.probs) {
     mix((uint64_t)p.M);
     mix((uint64_t)p.N);
@@ -343,7 +343,7 @@ void apply_tune_cache(PlanData& P) {
   for (auto& st : P.steps) {
     if (st.kind != StepKind::Gemm) continue;
     for (int f : {0, 1, 2, 3, 12, 13}) {
-      auto it = m.find(tune_key(P, st, (bst_precision)f));
+      auto it = m.find(tune_key(P, st, f));
       if (it == m.end()) continue;
       const auto& shapes = f >= 10 ? gemm_planes_shapes(f == 13 ? 3 : 2) : gemm_tile_shapes((bst_precision)f);
       for (size_t i = 0; i < shapes.size(); ++i)
@@ -484,12 +484,33 @@ bst_status bst_plan_autotune(bst_plan* p, const void* const* in, void* const* ou
     }
     st.tile_choice[key] = best_i;
     const TileShape& bs = shapes[best_i];
-    cache[tune_key(P, st, (bst_precision)key)] = {bs.bm, bs.bn, bs.direct, bs.stages};
+    cache[tune_key(P, st, key)] = {bs.bm, bs.bn, bs.direct, bs.stages};
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   drop_graph(P);
   if (path) save_cache(path, cache);
+  BST_CATCH
+}
+
+bst_status bst_plan_record_tiles(const bst_plan* p) {
+  BST_TRY
+  if (!p) fail(BST_E_INVALID, "null plan");
+  const char* path = std::getenv("BST_TUNE_CACHE");
+  if (!path) fail(BST_E_INVALID, "BST_TUNE_CACHE is not set");
+  const PlanData& P = p->p;
+  auto cache = load_cache(path);
+  for (const auto& st : P.steps) {
+    if (st.kind != StepKind::Gemm) continue;
+    for (const auto& kv : st.tile_choice) {
+      const int key = kv.first;
+      const auto& shapes = key >= 10 ? gemm_planes_shapes(key == 13 ? 3 : 2) : gemm_tile_shapes((bst_precision)key);
+      if (kv.second < 0 || kv.second >= (int)shapes.size()) continue;
+      const TileShape& bs = shapes[kv.second];
+      cache[tune_key(P, st, key)] = {bs.bm, bs.bn, bs.direct, bs.stages};
+    }
+  }
+  save_cache(path, cache);
   BST_CATCH
 }
 

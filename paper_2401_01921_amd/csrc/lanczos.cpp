@@ -4,10 +4,10 @@
 // The matvec runs in the requested arithmetic form; the reorthogonalisation
 // against all Krylov vectors, the scalars, the tridiagonal eigensolve (on
 // the host), the Ritz vector and the Rayleigh-quotient refinement with one
-// float64 apply run in float64.  With the split matvec forms the Krylov
-// rows themselves are stored in float32 (rounding them adds 6e-8 per
-// element, far below the matvec's own 2^-17 error; every dot product and
-// scalar stays float64); otherwise in float64.  All vectors stay in the
+// float64 apply run in float64.  The Krylov rows are float64; on request,
+// with the split matvec forms, they are stored in float32 instead (rounding
+// them adds 6e-8 per element, far below the matvec's own 2^-17 error; every
+// dot product and scalar stays float64).  All vectors stay in the
 // caller's workspace; alpha/beta stay on the device until the end, so a
 // step costs no host round trip.
 #include <hip/hip_runtime.h>
@@ -229,9 +229,10 @@ bst_status bst_lanczos_ground(bst_plan* heff, const void* const* ops, const void
   if ((uint64_t)ldv * (uint64_t)nsteps * 8u >= 0xFFFFFFFFull)
     fail(BST_E_INVALID, "Krylov basis above 4 GiB (reduce nsteps)");
   const bool three_pass = info && (info->flags & BST_LANCZOS_THREE_PASS);
-  // Krylov rows: float32 with the split forms and the one-pass schedule
-  const bool f64_basis = info && (info->flags & BST_LANCZOS_F64_BASIS);
-  const bool vf32 = !three_pass && !f64_basis && (matvec_prec == BST_BF16X3 || matvec_prec == BST_BF16X6);
+  // Krylov rows: float64, or float32 on request with the split forms and
+  // the one-pass schedule
+  const bool f32_basis = info && (info->flags & BST_LANCZOS_F32_BASIS);
+  const bool vf32 = !three_pass && f32_basis && (matvec_prec == BST_BF16X3 || matvec_prec == BST_BF16X6);
   double* V = reinterpret_cast<double*>(wb + Lo.V);
   float* V32 = reinterpret_cast<float*>(wb + Lo.V);
   auto row = [&](int j) -> void* {

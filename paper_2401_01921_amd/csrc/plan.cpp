@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 
@@ -1297,8 +1298,11 @@ void finalize(PlanData& P) {
             }
           return true;
         };
-        st.mpo_off32 = fit32(st.tasks, st.planes);
-        st.mpo_off32_alt = st.has_alt && fit32(st.tasks_alt, st.planes_alt);
+        // BST_MPO_INDEX64 (any value) keeps 64-bit indexing even where 32
+        // bits would do, so that path can be exercised on small operators
+        const bool force64 = std::getenv("BST_MPO_INDEX64") != nullptr;
+        st.mpo_off32 = !force64 && fit32(st.tasks, st.planes);
+        st.mpo_off32_alt = !force64 && st.has_alt && fit32(st.tasks_alt, st.planes_alt);
         std::vector<HWork> work;
         for (size_t ti = 0; ti < st.tasks.size(); ++ti) {
           const int64_t sites = (int64_t)st.tasks[ti].rows * st.tasks[ti].cols;
@@ -1526,6 +1530,11 @@ bst_status bst_plan_tiles(const bst_plan* p, char* buf, size_t cap) {
   std::string s;
   const PlanData& P = p->p;
   for (const auto& st : P.steps) {
+    if (st.kind == StepKind::HApply) {
+      const bool o32 = uses_planes(P, P.prec) && st.has_alt ? st.mpo_off32_alt : st.mpo_off32;
+      s += st.name + (o32 ? ":i32;" : ":i64;");
+      continue;
+    }
     if (st.kind != StepKind::Gemm) continue;
     const bool pl = uses_planes(P, P.prec) && st.has_alt;
     const TileShape sh = pl ? gemm_planes_shapes(P.prec == BST_BF16X6 ? 3 : 2)[planes_tile(st, P.prec)]

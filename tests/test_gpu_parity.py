@@ -4,8 +4,8 @@ inputs shared by both sides."""
 import numpy as np
 import pytest
 
-from tests.gpu_common import (DEV, TOL, dev, heff_operands, host, lib_heff, rel_err, require_gpu,
-                              run_heff, torch)
+from tests.gpu_common import (DEV, TOL, check, dev, heff_operands, host, lib_heff, rel_err,
+                              require_gpu, run_heff, torch)
 from tests.helpers import _random_pair, _random_sym_pair
 from oracle import oracle as orc
 from paper_2401_01921_amd import bst, workloads as wl
@@ -93,9 +93,7 @@ def test_pairwise_workload(prec):
     A.data[:] = wl.normal(wl.seed_for(1, "A"), A.numel)
     B.data[:] = wl.normal(wl.seed_for(1, "B"), B.numel)
     got, ref = _contract_case(A, B, prec)
-    nrm, mx = rel_err(got, ref)
-    _print("pairwise", prec, nrm, mx)
-    assert nrm <= TOL[prec]
+    check(got, ref, prec, "pairwise")
     # the two output blocks nothing reaches are exact zeros
     zero = np.zeros_like(ref, dtype=bool)
     C = orc.contract(A, B)
@@ -124,9 +122,7 @@ def test_random_contractions(prec):
         if A.numel == 0 or B.numel == 0:
             continue
         got, ref = _contract_case(A, B, prec)
-        nrm, _ = rel_err(got, ref)
-        _print("contract case", case, A.labels, B.labels, nrm)
-        assert nrm <= TOL[prec]
+        check(got, ref, prec, f"contract case {case} {A.labels} {B.labels}")
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "bf16x6"])
@@ -135,9 +131,26 @@ def test_heff_spin_half_chi512(prec):
     ref = orc.heff_apply(O["L"], O["W1"], O["W2"], O["R"], O["psi"]).data
     T, plan = lib_heff(specs, prec)
     got = run_heff(plan, O)
-    nrm, mx = rel_err(got, ref)
-    _print("heff chi512", prec, nrm, mx)
-    assert nrm <= TOL[prec]
+    check(got, ref, prec, "heff chi512")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+def test_heff_mpo_64bit_indexing(prec, monkeypatch):
+    """The MPO apply with 64-bit plane indexing (chosen by the plan only for
+    operators whose plane offsets pass 2^32 bytes; forced here) gives the
+    same result as the 32-bit indexing and the oracle's."""
+    specs, O = heff_operands(2)
+    ref = orc.heff_apply(O["L"], O["W1"], O["W2"], O["R"], O["psi"]).data
+    T, plan32 = lib_heff(specs, prec)
+    assert "mpo_apply:i32" in plan32.tiles()
+    monkeypatch.setenv("BST_MPO_INDEX64", "1")
+    T, plan64 = lib_heff(specs, prec)
+    monkeypatch.delenv("BST_MPO_INDEX64")
+    assert "mpo_apply:i64" in plan64.tiles(), plan64.tiles()
+    got64 = run_heff(plan64, O)
+    got32 = run_heff(plan32, O)
+    assert np.array_equal(got64, got32)
+    check(got64, ref, prec, "heff chi512 64-bit MPO indexing")
 
 
 @pytest.mark.parametrize("spin", ["1/2", "1"])
@@ -150,9 +163,7 @@ def test_heff_xx_mpo(prec, spin):
     ref = orc.heff_apply(O["L"], O["W1"], O["W2"], O["R"], O["psi"]).data
     T, plan = lib_heff(specs, prec)
     got = run_heff(plan, O)
-    nrm, mx = rel_err(got, ref)
-    _print("heff xx chi512", spin, prec, nrm, mx)
-    assert nrm <= TOL[prec]
+    check(got, ref, prec, f"heff xx chi512 spin {spin}")
 
 
 @pytest.mark.parametrize("sym", [(2,), (3,), (0, 2)])
@@ -174,9 +185,7 @@ def test_symmetric_contractions(prec, sym):
         if A.numel == 0 or B.numel == 0:
             continue
         got, ref = _contract_case(A, B, prec)
-        nrm, _ = rel_err(got, ref)
-        _print("sym contract", sym, prec, case, A.labels, B.labels, nrm)
-        assert nrm <= TOL[prec]
+        check(got, ref, prec, f"sym contract {sym} {case} {A.labels} {B.labels}")
 
 
 def _heff_sym_operands(sym, virt, phys, bond, seed):
@@ -214,9 +223,7 @@ def test_heff_symmetric_operands(prec, which):
     T = {n: bst.Tensor(*sp, sym=list(sym)) for n, sp in specs.items()}
     plan = bst.heff_plan(T["L"], T["W1"], T["W2"], T["R"], T["psi"], prec)
     got = run_heff(plan, O)
-    nrm, mx = rel_err(got, ref)
-    _print("heff", which, prec, O["psi"].numel, nrm, mx)
-    assert nrm <= TOL[prec]
+    check(got, ref, prec, f"heff {which} {O['psi'].numel}")
 
 
 def test_heff_fp64_is_deterministic():
@@ -233,9 +240,7 @@ def test_heff_spin_half_chi2048_error_table(prec):
     ref = orc.heff_apply(O["L"], O["W1"], O["W2"], O["R"], O["psi"]).data
     T, plan = lib_heff(specs, prec)
     got = run_heff(plan, O)
-    nrm, mx = rel_err(got, ref)
-    _print("heff chi2048", prec, "normwise", nrm, "max", mx)
-    assert nrm <= TOL[prec]
+    check(got, ref, prec, "heff chi2048")
 
 
 def test_heff_spin_one_chi4096_fp64():
@@ -244,9 +249,7 @@ def test_heff_spin_one_chi4096_fp64():
     ref = orc.heff_apply(O["L"], O["W1"], O["W2"], O["R"], O["psi"]).data
     T, plan = lib_heff(specs, "fp64")
     got = run_heff(plan, O)
-    nrm, mx = rel_err(got, ref)
-    _print("heff chi4096 fp64", nrm, mx)
-    assert nrm <= TOL["fp64"]
+    check(got, ref, "fp64", "heff chi4096")
 
 
 def test_heff_graph_replay_matches_eager():
@@ -275,9 +278,7 @@ def test_every_gemm_variant(prec):
     for tile in range(plan.tile_count(prec)):
         plan.set_tile(prec, tile)
         got = run_heff(plan, O)
-        nrm, mx = rel_err(got, ref)
-        _print("variant", prec, tile, plan.tiles(), nrm)
-        assert nrm <= TOL[prec]
+        check(got, ref, prec, f"variant {tile} {plan.tiles()}")
     # the generic contraction path (no pre-split planes) with every variant
     rng = np.random.default_rng(5)
     A, B = _random_pair(rng, 3, 3, 2)
@@ -293,7 +294,7 @@ def test_every_gemm_variant(prec):
         out = torch.full((tC.numel,), np.nan, dtype=torch.float64, device=DEV)
         cplan.execute([dev(A.data), dev(B.data)], [out], bst.workspace(cplan.workspace_bytes))
         torch.cuda.synchronize()
-        assert rel_err(host(out), C.data)[0] <= TOL[prec], tile
+        check(host(out), C.data, prec, f"contract variant {tile}")
 
 
 def _pipelined_tiles(plan, prec):
@@ -316,17 +317,16 @@ def test_pipelined_gemm_full_size(prec):
     T, plan = lib_heff(specs, prec)
     plan.set_tile(prec, 0)   # LDS-staged 64x64
     base = run_heff(plan, O)
-    assert rel_err(base, ref)[0] <= TOL[prec]
+    check(base, ref, prec, "pipelined base (LDS kernel)")
     tiles = _pipelined_tiles(plan, prec)
     assert tiles
     for tile in tiles:
         plan.set_tile(prec, tile)
         got = run_heff(plan, O)
-        nrm, mx = rel_err(got, ref)
-        _print("pipelined", prec, tile, plan.tiles(), nrm, "max|diff| vs LDS kernel",
+        _print("pipelined", prec, tile, plan.tiles(), "max|diff| vs LDS kernel",
                float(np.max(np.abs(got - base))))
         assert np.array_equal(got, base), plan.tiles()
-        assert nrm <= TOL[prec]
+        check(got, ref, prec, f"pipelined {tile}")
 
 
 def test_workspace_overwritten_between_calls():

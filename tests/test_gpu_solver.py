@@ -8,8 +8,8 @@ import numpy as np
 import pytest
 
 from tests import chain_env
-from tests.gpu_common import (DEV, TOL, dev, heff_operands, host, lib_heff, rel_err, require_gpu,
-                              run_heff, torch)
+from tests.gpu_common import (DEV, TOL, check, dev, heff_operands, host, lib_heff, rel_err,
+                              require_gpu, run_heff, torch)
 from oracle import oracle as orc
 from paper_2401_01921_amd import bst, workloads as wl
 
@@ -44,8 +44,12 @@ def _batch_members(n):
     return members
 
 
-@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
 def test_batched_heff_matches_single_applies(prec):
+    """The 64 uneven applies in one grouped launch per step (float32 bulk is
+    the batched workload's stated form), captured in a hipGraph: the first
+    execute captures and runs it, the second replays it into outputs that
+    were refilled with NaN, so a replay that writes nothing fails."""
     members = _batch_members(64)
     plans = [bst.heff_plan(T["L"], T["W1"], T["W2"], T["R"], T["psi"], prec) for _, T, _ in members]
     batch = bst.heff_batch_plan(plans)
@@ -55,9 +59,15 @@ def test_batched_heff_matches_single_applies(prec):
         outs.append(torch.full((T["psi"].numel,), np.nan, dtype=torch.float64, device=DEV))
     batch.use_graph(True)
     ws = bst.workspace(batch.workspace_bytes)
-    batch.execute(ins, outs, ws)
+    batch.execute(ins, outs, ws)    # capture and run
+    torch.cuda.synchronize()
+    first = [host(o) for o in outs]
+    for o in outs:
+        o.fill_(float("nan"))
     batch.execute(ins, outs, ws)    # graph replay
     torch.cuda.synchronize()
+    for i, o in enumerate(outs):
+        assert np.array_equal(host(o), first[i]), i
     # every member equals its own single-apply plan (same tiles, same order)
     for i, (p, (_, T, d)) in enumerate(zip(plans, members)):
         single = torch.empty_like(outs[i])
@@ -69,9 +79,7 @@ def test_batched_heff_matches_single_applies(prec):
         specs, T, d = members[i]
         O = {k: orc.BlockTensor(*specs[k], d[k]) for k in ("L", "W1", "W2", "R", "psi")}
         ref = orc.heff_apply(O["L"], O["W1"], O["W2"], O["R"], O["psi"]).data
-        nrm, mx = rel_err(host(outs[i]), ref)
-        _print("batch member", i, prec, nrm, mx)
-        assert nrm <= TOL[prec]
+        check(host(outs[i]), ref, prec, f"batch member {i}")
 
 
 def test_batched_heff_pipelined_gemm():
@@ -112,9 +120,10 @@ def test_autotune_keeps_results():
         ws = bst.workspace(plan.workspace_bytes)
         plan.autotune(ins, [out], ws, reps=2)
         _print("tuned", prec, plan.tiles())
+        out.fill_(float("nan"))
         plan.execute(ins, [out], ws)
         torch.cuda.synchronize()
-        assert rel_err(host(out), ref)[0] <= TOL[prec]
+        check(host(out), ref, prec, "autotuned")
 
 
 def test_empty_and_degenerate_buffers():
@@ -130,12 +139,12 @@ def test_empty_and_degenerate_buffers():
 
 
 # ---------------------------------------------------------------- Lanczos
-def _lanczos_lib(specs, O, nsteps, prec, refine=True, psi0=None, three_pass=False, f64_basis=False):
+def _lanczos_lib(specs, O, nsteps, prec, refine=True, psi0=None, three_pass=False, f32_basis=False):
     T, plan = lib_heff(specs, "fp64")
     ops = [dev(O[n].data) for n in ("L", "W1", "W2", "R")]
     p0 = dev(psi0 if psi0 is not None else wl.normal(999, O["psi"].numel))
     r = bst.lanczos_ground(plan, ops, p0, nsteps, prec, refine, three_pass=three_pass,
-                           f64_basis=f64_basis)
+                           f32_basis=f32_basis)
     torch.cuda.synchronize()
     return r
 
@@ -240,16 +249,17 @@ def test_lanczos_matches_oracle_medium(three_pass):
     assert abs(r["energy"] - ref["energy"]) <= 1e-12 * abs(ref["energy"])
     y = host(r["psi"])
     assert abs(abs(float(y @ ref["y"]) / np.linalg.norm(ref["y"])) - 1.0) < 1e-10
-    for prec, f64b in (("fp32", False), ("bf16x6", False), ("bf16x3", False), ("bf16x6", True),
+    # every split form meets the 1e-10 refined-energy bar, with float64
+    # Krylov rows (the default) and with float32 rows
+    for prec, f32b in (("fp32", False), ("bf16x6", False), ("bf16x3", False), ("bf16x6", True),
                        ("bf16x3", True)):
-        if three_pass and f64b:
+        if three_pass and f32b:
             continue   # the three-pass schedule always keeps float64 rows
-        rs = _lanczos_lib(specs, O, 40, prec, psi0=psi0, three_pass=three_pass, f64_basis=f64b)
+        rs = _lanczos_lib(specs, O, 40, prec, psi0=psi0, three_pass=three_pass, f32_basis=f32b)
         err = abs(rs["energy"] - ref["energy"]) / abs(ref["energy"])
-        _print("medium", prec, "f64 basis" if f64b else "", "refined rel err", err, "theta rel err",
-               abs(rs["theta"] - ref["theta"]) / abs(ref["theta"]))
-        if prec != "bf16x3":
-            assert err <= 1e-10
+        _print("medium", prec, "f32 rows" if f32b else "f64 rows", "refined rel err", err,
+               "theta rel err", abs(rs["theta"] - ref["theta"]) / abs(ref["theta"]))
+        assert err <= 1e-10, (prec, f32b, err)
 
 
 def test_lanczos_full_size_matches_oracle_golden():
@@ -262,12 +272,14 @@ def test_lanczos_full_size_matches_oracle_golden():
         gold = json.load(f)
     specs, O = heff_operands(5, recipe="dmrg_like")
     psi0 = wl.normal(wl.seed_for(5, "psi0"), O["psi"].numel)
-    for prec in ("fp64", "fp32", "bf16x6", "bf16x3"):
-        r = _lanczos_lib(specs, O, 40, prec, psi0=psi0)
+    for prec, f32b in (("fp64", False), ("fp32", False), ("bf16x6", False), ("bf16x3", False),
+                       ("bf16x6", True), ("bf16x3", True)):
+        r = _lanczos_lib(specs, O, 40, prec, psi0=psi0, f32_basis=f32b)
         err = abs(r["energy"] - gold["energy"]) / abs(gold["energy"])
-        _print("chi4096", prec, r["energy"], gold["energy"], "rel err", err, "residual", r["residual"])
+        _print("chi4096", prec, "f32 rows" if f32b else "f64 rows", r["energy"], gold["energy"],
+               "rel err", err, "residual", r["residual"])
         if prec == "fp64":
             assert err <= 1e-12
             assert abs(r["theta"] - gold["theta"]) <= 1e-12 * abs(gold["theta"])
-        elif prec != "bf16x3":
-            assert err <= 1e-10
+        else:
+            assert err <= 1e-10, (prec, f32b, err)

@@ -18,7 +18,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def test_library_exports_every_declared_symbol():
     with open(os.path.join(ROOT, "include", "bst.h")) as f:
         hdr = f.read()
-    declared = set(re.findall(r"^(?:bst_status|const char\*)\s+(bst_\w+)\s*\(", hdr, re.M))
+    declared = set(re.findall(r"^(?:bst_status|const char\*|int32_t)\s+(bst_\w+)\s*\(", hdr, re.M))
     assert declared == set(bst.EXPORTS)
     lib = bst.lib()
     for name in declared:
@@ -263,7 +263,8 @@ def test_binding_fails_loudly_without_library(tmp_path):
             "except ImportError as e:\n"
             "    print('IMPORT_ERROR', e); sys.exit(0)\n"
             "sys.exit(3)\n")
+    env = {k: v for k, v in os.environ.items() if k != "BST_LIB"}
     r = subprocess.run([sys.executable, "-c", code], cwd=str(tmp_path), capture_output=True,
-                       text=True, timeout=120)
+                       text=True, timeout=120, env=env)
     assert r.returncode == 0, r.stdout + r.stderr
     assert "not built" in r.stdout
