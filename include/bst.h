@@ -255,6 +255,20 @@ bst_status bst_plan_use_graph(bst_plan* p, int32_t on);
 bst_status bst_execute(bst_plan* p, const void* const* in, void* const* out, void* ws,
                        void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * bst_execute with the workspace taken from a fixed device array of
+ * BST_STATIC_WORKSPACE_BYTES that the library holds on every device it runs
+ * on until the process ends.  No allocation and no graph capture (kernels are
+ * launched directly whatever bst_plan_use_graph says).  The array needs no
+ * initial contents: every kernel writes what it later reads.  All calls on a
+ * device share that device's array, so calls that overlap on one device
+ * (other streams or threads) race; serialise them.  Errors: BST_E_INVALID if
+ * bst_plan_workspace of the plan exceeds BST_STATIC_WORKSPACE_BYTES (nothing
+ * is enqueued), and the errors of bst_execute. */
+#define BST_STATIC_WORKSPACE_BYTES (64u << 20)
+bst_status bst_execute_static(bst_plan* p, const void* const* in, void* const* out, void* stream);
+
 /* Times every compiled tile shape of each GEMM step on the given buffers,
  * keeps the fastest per step and (if the environment variable BST_TUNE_CACHE
  * names a file) records the choice there.  Synchronises the stream. */

@@ -21,6 +21,7 @@ LIB_PATH = os.environ.get("BST_LIB") or os.path.join(HERE, "libbst.so")
 STATUS = {0: "OK", 1: "E_INVALID", 2: "E_DIRECTION", 3: "E_QNUM", 4: "E_DIM", 5: "E_LABEL",
           6: "E_NOBLOCK", 7: "E_STRUCTURE", 8: "E_DEVICE", 9: "E_NOTCONV"}
 PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3}
+STATIC_WORKSPACE_BYTES = 64 << 20   # BST_STATIC_WORKSPACE_BYTES
 
 # Every symbol include/bst.h declares.
 EXPORTS = [
@@ -32,7 +33,7 @@ EXPORTS = [
     "bst_lanczos_workspace", "bst_lanczos_ground", "bst_last_error", "bst_version",
     "bst_plan_tile_count", "bst_plan_set_tile", "bst_plan_forget_workspace",
     "bst_tensor_create_sym", "bst_tensor_symmetry", "bst_tensor_leg_charges",
-    "bst_network_order", "bst_plan_record_tiles", "bst_calib_grid", "bst_calib_copy", "bst_calib_read", "bst_calib_mfma",
+    "bst_network_order", "bst_plan_record_tiles", "bst_execute_static", "bst_calib_grid", "bst_calib_copy", "bst_calib_read", "bst_calib_mfma",
 ]
 
 
@@ -95,6 +96,7 @@ def _load():
         "bst_plan_set_precision": [vp, C.c_int],
         "bst_plan_use_graph": [vp, i32],
         "bst_execute": [vp, P(vp), P(vp), vp, vp],
+        "bst_execute_static": [vp, P(vp), P(vp), vp],
         "bst_plan_autotune": [vp, P(vp), P(vp), vp, vp, i32],
         "bst_plan_tiles": [vp, C.c_char_p, sz],
         "bst_plan_tile_count": [vp, C.c_int, P(i32)],
@@ -392,6 +394,13 @@ class Plan:
         self._check_ws(ws)
         a, b = self._arrays(ins, outs)
         _check(_lib.bst_execute(self._h, a, b, C.c_void_p(_ptr(ws)), _stream(stream)))
+
+    def execute_static(self, ins, outs, stream=None):
+        """execute() with the library's fixed per-device workspace
+        (STATIC_WORKSPACE_BYTES): allocates nothing; calls overlapping on
+        one device race."""
+        a, b = self._arrays(ins, outs)
+        _check(_lib.bst_execute_static(self._h, a, b, _stream(stream)))
 
     def autotune(self, ins, outs, ws, reps: int = 5, stream=None):
         self._check_ws(ws)

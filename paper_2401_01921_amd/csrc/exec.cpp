@@ -407,6 +407,52 @@ bst_status bst_execute(bst_plan* p, const void* const* in, void* const* out, voi
   BST_CATCH
 }
 
+}  // extern "C"
+
+namespace bst {
+// Workspace of bst_execute_static: a fixed device array instead of caller
+// memory, for callers that cannot allocate.  Each device holds its own copy;
+// host code reaches it only through the address hipGetSymbolAddress returns
+// for the current device, fetched once per device on that device's first
+// call.  Every call on a device shares its copy.
+static __device__ __align__(256) unsigned char scratch[BST_STATIC_WORKSPACE_BYTES];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+static void* scratch_address() {
+  int dev = -1;
+  check_hip(hipGetDevice(&dev), "current device");
+  if (dev < 0 || dev >= kMaxDevices) fail(BST_E_DEVICE, "device index out of range for the static workspace");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    check_hip(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "static workspace address");
+    if (!ptr || (reinterpret_cast<uintptr_t>(ptr) & 255) != 0) fail(BST_E_DEVICE, "static workspace misaligned");
+    g_scratch_ptr[dev] = ptr;
+  }
+  return g_scratch_ptr[dev];
+}
+}  // namespace bst
+
+extern "C" {
+
+bst_status bst_execute_static(bst_plan* p, const void* const* in, void* const* out, void* stream) {
+  BST_TRY
+  if (!p) fail(BST_E_INVALID, "null plan");
+  PlanData& P = p->p;
+  if (P.ws_bytes > (size_t)BST_STATIC_WORKSPACE_BYTES)
+    fail(BST_E_INVALID, "plan needs " + std::to_string(P.ws_bytes) + " bytes of workspace; the static "
+                        "workspace holds " + std::to_string((size_t)BST_STATIC_WORKSPACE_BYTES));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  check_hip(hipGetLastError(), "pending device error");
+  void* ws = scratch_address();
+  // tables go up again if another plan used this device's copy since
+  void* dptrs = prepare_ws(P, in, out, ws, s);
+  run_steps(P, ws, static_cast<void* const*>(dptrs), P.prec, s, false);
+  BST_CATCH
+}
+
 bst_status bst_plan_profile(bst_plan* p, const void* const* in, void* const* out, void* ws,
                             void* stream, int32_t reps, double* step_ms, int32_t cap,
                             int32_t* nsteps) {
