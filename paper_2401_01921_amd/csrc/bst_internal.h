@@ -191,7 +191,7 @@ enum class ElemType : int { F64 = 0, F32 = 1 };
 struct TileShape {
   int bm, bn;
   int direct = 0;   // 1: LDS-free kernel (fragments loaded straight from memory);
-                    // 3: pipelined persistent kernel on a k-step schedule (planes only)
+                    // 3: pipelined persistent kernel on a k-step schedule (padded layouts only)
   int stages = 0;   // kind 3: LDS stages (copies run stages - 1 k-steps ahead)
   int waves = 4;    // kind 3: waves per workgroup (4: 2 x 2; 8: 2 x 4, or 4 x 2 when bm > bn)
 };
@@ -267,7 +267,8 @@ hipError_t launch_gemm_planes(const PlanesLaunch& g, hipStream_t s);
 // owns, one 48-byte record per step, the steps of a tile consecutive.
 // A tile row r < rows reads plane q of A at planar position a + r*lda + k, B likewise;
 // chunks of 8 k at or past kch read as zero and chunk kch-1 holds kval valid
-// elements.  The last step of a tile writes it: row r, column j to
+// elements.  With float64 operands (np = 1) a step is 16 deep and its
+// "chunks" are 16-byte pieces of two elements (kch 0..8, kval 1..2).  The last step of a tile writes it: row r, column j to
 // C[c + r*ldc + j] or, row-mapped, to C[rowtab[c + r] + j] (entries < 0
 // skipped), for j < cols.
 struct KStep {
@@ -287,8 +288,11 @@ constexpr int kStepFirst = 1, kStepLast = 2, kStepRowmap = 4;
 constexpr int kStepBatch = 16;   // records copied into LDS per batch
 constexpr int kStepRing = 3;     // batches resident in LDS
 // LDS bytes of one workgroup of the pipelined kernel and workgroups per CU
+// np = 1 names float64 operands (one plane of doubles): a 16-deep k-step of a
+// row is 128 bytes, like a 32-deep step of two bfloat16 planes.
+constexpr int stream_row_bytes(int np) { return np == 1 ? 128 : np * 64; }
 constexpr int stream_lds_bytes(int np, int bm, int bn, int stages) {
-  return stages * (bm + bn) * np * 64 + kStepRing * kStepBatch * 48 + stages * bm * 8;
+  return stages * (bm + bn) * stream_row_bytes(np) + kStepRing * kStepBatch * 48 + stages * bm * 8;
 }
 constexpr int stream_wgs_per_cu(int np, int bm, int bn, int stages) {
   return 163840 / stream_lds_bytes(np, bm, bn, stages) < 1   ? 1
@@ -298,7 +302,7 @@ constexpr int stream_wgs_per_cu(int np, int bm, int bn, int stages) {
 constexpr int kStreamCUs = 256;   // compute units the schedule is balanced for
 
 struct StreamLaunch {
-  int np;
+  int np;                         // 2, 3: bfloat16 planes; 1: float64 operands
   ElemType tc;
   int tile;                       // index into gemm_planes_shapes(np), a kind-3 shape
   const KStep* steps;             // padded with kStepBatch records past the last

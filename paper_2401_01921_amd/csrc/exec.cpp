@@ -73,8 +73,14 @@ void* prepare_ws(PlanData& P, const void* const* in, void* const* out, void* ws,
 }
 
 bool uses_planes(const PlanData& P, bst_precision prec) {
-  return P.has_planes && (prec == BST_BF16X3 || prec == BST_BF16X6);
+  if (!P.has_planes) return false;
+  if (prec == BST_BF16X3 || prec == BST_BF16X6) return true;
+  if (prec != BST_FP64 || !P.f64_panels || std::getenv("BST_FP64_BLOCKS")) return false;
+  return P.fp64_panels_on || std::getenv("BST_FP64_PANELS") != nullptr;
 }
+
+int plane_count(bst_precision prec) { return prec == BST_FP64 ? 1 : prec == BST_BF16X6 ? 3 : 2; }
+int plane_count_of_key(int key) { return plane_count((bst_precision)(key - 10)); }
 
 bool step_runs(const PlanData& P, const Step& st, bst_precision prec, bool skip_const) {
   if (skip_const && st.constant) return false;
@@ -123,7 +129,7 @@ static int planes_auto_tile(const Step& st, int np) {
 int planes_tile(const Step& st, bst_precision prec) {
   auto it = st.tile_choice.find(planes_key(prec));
   if (it != st.tile_choice.end()) return it->second;
-  return planes_auto_tile(st, prec == BST_BF16X6 ? 3 : 2);
+  return planes_auto_tile(st, plane_count(prec));
 }
 
 void run_steps_impl(PlanData& P, void* ws, void* const* dptrs, bst_precision prec, hipStream_t s,
@@ -133,7 +139,7 @@ void run_steps_impl(PlanData& P, void* ws, void* const* dptrs, bst_precision pre
   char* wsb = static_cast<char*>(ws);
   const ElemType inter = (prec == BST_FP64) ? ElemType::F64 : ElemType::F32;
   const bool planes = uses_planes(P, prec);
-  const int np = prec == BST_BF16X6 ? 3 : 2;
+  const int np = plane_count(prec);
   for (size_t k = 0; k < P.steps.size(); ++k) {
     if (only_step >= 0 && (int)k != only_step) continue;
     Step& st = P.steps[k];
@@ -156,7 +162,8 @@ void run_steps_impl(PlanData& P, void* ws, void* const* dptrs, bst_precision pre
         if (planes && st.has_alt) {
           PlanesLaunch g{};
           g.np = np;
-          g.tc = st.tc == Elem::Inter || (st.writes_out && P.z_f32) ? ElemType::F32 : ElemType::F64;
+          g.tc = np == 1 ? ElemType::F64
+                 : st.tc == Elem::Inter || (st.writes_out && P.z_f32) ? ElemType::F32 : ElemType::F64;
           g.tile = planes_tile(st, prec);
           if (gemm_planes_shapes(np)[g.tile].direct == 3) {
             auto sit = st.streams_alt.find(np * 64 + g.tile);
@@ -174,6 +181,7 @@ void run_steps_impl(PlanData& P, void* ws, void* const* dptrs, bst_precision pre
               e = launch_gemm_planes_stream(sl, s);
               break;
             }
+            if (np == 1) fail(BST_E_INVALID, "internal: float64 tile without a k-step schedule");
             g.tile = kPlanesDefaultTile;   // problems outside the kernel's layout rules
           }
           const auto& sh = gemm_planes_shapes(np)[g.tile];
@@ -243,7 +251,7 @@ void run_steps_impl(PlanData& P, void* ws, void* const* dptrs, bst_precision pre
                                         : (const void*)(wsb + P.ws_coef32_off);
         h.off32 = st.mpo_off32;
         if (planes && st.has_alt) {
-          h.np = np;
+          h.np = np == 1 ? 0 : np;   // float64 panels: plain float64 outputs
           h.tasks = reinterpret_cast<const HTask*>(blob + st.off3);
           h.planes = reinterpret_cast<const HPlane*>(blob + st.off4);
           h.off32 = st.mpo_off32_alt;
@@ -342,10 +350,10 @@ void apply_tune_cache(PlanData& P) {
   auto m = load_cache(path);
   for (auto& st : P.steps) {
     if (st.kind != StepKind::Gemm) continue;
-    for (int f : {0, 1, 2, 3, 12, 13}) {
+    for (int f : {0, 1, 2, 3, 10, 12, 13}) {
       auto it = m.find(tune_key(P, st, f));
       if (it == m.end()) continue;
-      const auto& shapes = f >= 10 ? gemm_planes_shapes(f == 13 ? 3 : 2) : gemm_tile_shapes((bst_precision)f);
+      const auto& shapes = f >= 10 ? gemm_planes_shapes(plane_count_of_key(f)) : gemm_tile_shapes((bst_precision)f);
       for (size_t i = 0; i < shapes.size(); ++i)
         if (it->second.matches(shapes[i])) st.tile_choice[f] = (int)i;
     }
@@ -496,41 +504,65 @@ bst_status bst_plan_autotune(bst_plan* p, const void* const* in, void* const* ou
   hipStream_t s = static_cast<hipStream_t>(stream);
   reps = std::max(reps, 1);
   void* dptrs = prepare_ws(P, in, out, ws, s);
-  // one full run so that intermediates hold realistic data
-  run_steps(P, ws, static_cast<void* const*>(dptrs), P.prec, s, false);
+  void* const* table = static_cast<void* const*>(dptrs);
   hipEvent_t e0, e1;
   check_hip(hipEventCreate(&e0), "event");
   check_hip(hipEventCreate(&e1), "event");
   const char* path = std::getenv("BST_TUNE_CACHE");
   auto cache = path ? load_cache(path) : std::map<std::string, CachedShape>{};
   const bst_precision form = P.prec;
-  for (size_t k = 0; k < P.steps.size(); ++k) {
-    Step& st = P.steps[k];
-    if (st.kind != StepKind::Gemm) continue;
-    const bst_precision f = st.fixed_fp64 ? BST_FP64 : form;
-    const bool pl = uses_planes(P, form) && st.has_alt;
-    const int key = pl ? planes_key(form) : (int)f;
-    const auto& shapes = pl ? gemm_planes_shapes(form == BST_BF16X6 ? 3 : 2) : gemm_tile_shapes(f);
-    double best = 1e30;
-    int best_i = pl ? planes_tile(st, form) : default_tile(st, f);
-    for (size_t i = 0; i < shapes.size(); ++i) {
-      st.tile_choice[key] = (int)i;
-      run_steps_impl(P, ws, static_cast<void* const*>(dptrs), P.prec, s, false, (int)k, nullptr);
-      check_hip(hipEventRecord(e0, s), "event");
-      for (int r = 0; r < reps; ++r)
-        run_steps_impl(P, ws, static_cast<void* const*>(dptrs), P.prec, s, false, (int)k, nullptr);
-      check_hip(hipEventRecord(e1, s), "event");
-      check_hip(hipEventSynchronize(e1), "event sync");
-      float ms = 0;
-      check_hip(hipEventElapsedTime(&ms, e0, e1), "event time");
-      if (ms < best) {
-        best = ms;
-        best_i = (int)i;
+  // reps runs of step k (all steps for k < 0), in ms
+  auto time_runs = [&](int k) {
+    check_hip(hipEventRecord(e0, s), "event");
+    for (int r = 0; r < reps; ++r) run_steps_impl(P, ws, table, P.prec, s, false, k, nullptr);
+    check_hip(hipEventRecord(e1, s), "event");
+    check_hip(hipEventSynchronize(e1), "event sync");
+    float ms = 0;
+    check_hip(hipEventElapsedTime(&ms, e0, e1), "event time");
+    return (double)ms;
+  };
+  // the fastest tile shape of every GEMM step, in the variant the plan runs now
+  auto tune_steps = [&]() {
+    // one full run so that intermediates hold realistic data
+    run_steps(P, ws, table, P.prec, s, false);
+    for (size_t k = 0; k < P.steps.size(); ++k) {
+      Step& st = P.steps[k];
+      if (st.kind != StepKind::Gemm) continue;
+      const bst_precision f = st.fixed_fp64 ? BST_FP64 : form;
+      const bool pl = uses_planes(P, form) && st.has_alt;
+      const int key = pl ? planes_key(form) : (int)f;
+      const auto& shapes = pl ? gemm_planes_shapes(plane_count(form)) : gemm_tile_shapes(f);
+      double best = 1e30;
+      int best_i = pl ? planes_tile(st, form) : default_tile(st, f);
+      for (size_t i = 0; i < shapes.size(); ++i) {
+        st.tile_choice[key] = (int)i;
+        run_steps_impl(P, ws, table, P.prec, s, false, (int)k, nullptr);
+        const double ms = time_runs((int)k);
+        if (ms < best) {
+          best = ms;
+          best_i = (int)i;
+        }
       }
+      st.tile_choice[key] = best_i;
+      const TileShape& bs = shapes[best_i];
+      cache[tune_key(P, st, key)] = {bs.bm, bs.bn, bs.direct, bs.stages};
     }
-    st.tile_choice[key] = best_i;
-    const TileShape& bs = shapes[best_i];
-    cache[tune_key(P, st, key)] = {bs.bm, bs.bn, bs.direct, bs.stages};
+  };
+  // FP64 with padded layouts available: tune both variants (per-block-pair
+  // kernels, float64 panels) and keep the one whose whole apply is faster,
+  // unless an environment override fixes the variant
+  const bool both = form == BST_FP64 && P.has_planes && P.f64_panels && !std::getenv("BST_FP64_BLOCKS") &&
+                    !std::getenv("BST_FP64_PANELS");
+  if (both) {
+    P.fp64_panels_on = false;
+    tune_steps();
+    const double t_blocks = time_runs(-1);
+    P.fp64_panels_on = true;
+    tune_steps();
+    const double t_panels = time_runs(-1);
+    P.fp64_panels_on = t_panels < t_blocks;
+  } else {
+    tune_steps();
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -550,7 +582,7 @@ bst_status bst_plan_record_tiles(const bst_plan* p) {
     if (st.kind != StepKind::Gemm) continue;
     for (const auto& kv : st.tile_choice) {
       const int key = kv.first;
-      const auto& shapes = key >= 10 ? gemm_planes_shapes(key == 13 ? 3 : 2) : gemm_tile_shapes((bst_precision)key);
+      const auto& shapes = key >= 10 ? gemm_planes_shapes(plane_count_of_key(key)) : gemm_tile_shapes((bst_precision)key);
       if (kv.second < 0 || kv.second >= (int)shapes.size()) continue;
       const TileShape& bs = shapes[kv.second];
       cache[tune_key(P, st, key)] = {bs.bm, bs.bn, bs.direct, bs.stages};
@@ -562,7 +594,7 @@ bst_status bst_plan_record_tiles(const bst_plan* p) {
 
 static const std::vector<TileShape>& variant_list(const PlanData& P, bst_precision form, bool& planes) {
   planes = uses_planes(P, form);
-  return planes ? gemm_planes_shapes(form == BST_BF16X6 ? 3 : 2) : gemm_tile_shapes(form);
+  return planes ? gemm_planes_shapes(plane_count(form)) : gemm_tile_shapes(form);
 }
 
 bst_status bst_plan_tile_count(const bst_plan* p, bst_precision form, int32_t* count) {

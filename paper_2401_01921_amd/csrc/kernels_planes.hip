@@ -15,6 +15,7 @@ namespace bst {
 typedef float flt4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned short us8 __attribute__((ext_vector_type(8)));
+typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ unsigned short rne_bf16(float x) {
   unsigned int u = __float_as_uint(x);
@@ -61,6 +62,15 @@ __global__ __launch_bounds__(256) void split_kernel(const SplitJob* __restrict__
     for (int pass = 0; pass < 2; ++pass) {
       const int r = w.r0 + orow + 32 * pass, c = w.c0 + ocol;
       if (r < j.rows && c < j.out_ld) {
+        if constexpr (NP == 1) {   // float64 copy into the padded layout
+          dbl4 v[2];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) v[e >> 2][e & 3] = (c + e) < j.cols ? (double)in[(int64_t)r * j.cols + c + e] : 0.0;
+          BST_G dbl4* o = (BST_G dbl4*)((BST_G double*)(ptrs[j.out_buf]) + j.out_off + (int64_t)r * j.out_ld + c);
+          o[0] = v[0];
+          o[1] = v[1];
+          continue;
+        }
         us8 h[3];
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
@@ -89,6 +99,15 @@ __global__ __launch_bounds__(256) void split_kernel(const SplitJob* __restrict__
     const int c = orow + 32 * pass;          // output row = input column
     const int gc = w.c0 + c, gr = w.r0 + ocol;
     if (gc < j.cols && gr < j.out_ld) {
+      if constexpr (NP == 1) {
+        dbl4 v[2];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e >> 2][e & 3] = (double)tile[ocol + e][c];
+        BST_G dbl4* o = (BST_G dbl4*)((BST_G double*)(ptrs[j.out_buf]) + j.out_off + (int64_t)gc * j.out_ld + gr);
+        o[0] = v[0];
+        o[1] = v[1];
+        continue;
+      }
       us8 h[3];
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
@@ -108,7 +127,9 @@ hipError_t launch_split(const SplitLaunch& l, hipStream_t s) {
   if (l.nwork <= 0) return hipSuccess;
   if (l.nwork > 0x7FFFFFFF) return hipErrorInvalidValue;
   const dim3 grid((unsigned)l.nwork), block(256);
-  if (l.np == 2 && !l.in_f32)
+  if (l.np == 1 && !l.in_f32)
+    hipLaunchKernelGGL((split_kernel<1, double>), grid, block, 0, s, l.jobs, l.work, l.ptrs);
+  else if (l.np == 2 && !l.in_f32)
     hipLaunchKernelGGL((split_kernel<2, double>), grid, block, 0, s, l.jobs, l.work, l.ptrs);
   else if (l.np == 2)
     hipLaunchKernelGGL((split_kernel<2, float>), grid, block, 0, s, l.jobs, l.work, l.ptrs);
@@ -144,7 +165,13 @@ static const std::vector<TileShape> kPlaneShapes2 = {
     {256, 128, 3, 3, 8}, {256, 64, 3, 3, 8}};
 static const std::vector<TileShape> kPlaneShapes3 = {{64, 64, 0}, {32, 32, 0}, {64, 64, 3, 3, 4},
                                                      {128, 128, 3, 3, 8}};
-const std::vector<TileShape>& gemm_planes_shapes(int np) { return np == 3 ? kPlaneShapes3 : kPlaneShapes2; }
+// float64 operands in the padded layouts: the pipelined kernel only
+static const std::vector<TileShape> kPlaneShapes1 = {{64, 64, 3, 3, 4},   {128, 64, 3, 3, 4},
+                                                     {64, 128, 3, 3, 4},  {128, 128, 3, 3, 8},
+                                                     {256, 128, 3, 3, 8}, {128, 256, 3, 3, 8}};
+const std::vector<TileShape>& gemm_planes_shapes(int np) {
+  return np == 1 ? kPlaneShapes1 : np == 3 ? kPlaneShapes3 : kPlaneShapes2;
+}
 
 template <int NP, typename TC, int BM, int BN, int BK>
 __global__ __launch_bounds__(256) void gemm_planes_kernel(const GemmTile* __restrict__ tiles,

@@ -33,6 +33,8 @@ namespace {
 typedef float flt4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+typedef double dbl2 __attribute__((ext_vector_type(2)));
+typedef double dbl4 __attribute__((ext_vector_type(4)));
 #define BST_LDS __attribute__((address_space(3)))
 
 // An LDS operand row holds one 32-deep k step of all NP planes: NC = 4 * NP
@@ -313,6 +315,204 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_planes_stream_kernel(cons
   }
 }
 
+// The same schedule on float64 operands held in the same padded layouts (one
+// plane of doubles, positions = elements).  A k-step is 16 elements of a row:
+// one 128-byte line, eight 16-byte pieces of two doubles, with the swizzle of
+// the two-plane layout.  kch counts valid pieces (0..8) and kval the valid
+// elements of piece kch - 1 (1 or 2).  v_mfma_f64_16x16x4f64 sums four k per
+// instruction: lane group g = lane / 16 supplies element 4g + j of the step to
+// MFMA j, so that every lane reads four consecutive elements of its row (two
+// 16-byte LDS reads) for the step's four MFMAs.  The sum over the step is the
+// same set of products in a fixed order, so results are bitwise repeatable.
+template <int BM, int BN, int S, int WGM, int WGN>
+__global__ __launch_bounds__(64 * WGM * WGN) void gemm_f64_stream_kernel(const KStep* __restrict__ steps,
+                                                                     const int64_t* __restrict__ wg_begin,
+                                                                     void* const* __restrict__ ptrs,
+                                                                     const int64_t* __restrict__ rowtab) {
+  constexpr int NW = WGM * WGN, NT = 64 * NW;
+  constexpr int WM = BM / WGM, WN = BN / WGN, SM = WM / 16, SN = WN / 16;
+  constexpr int NC = 8;                                 // 16-byte pieces per operand row and k-step
+  constexpr int SLA = BM * NC, SLB = BN * NC;
+  constexpr int LPS = (SLA + SLB) / NT;
+  constexpr int RL = BM / NW / 2;
+  constexpr int BL = kStepBatch * 3 / NW;
+  constexpr int STB = (SLA + SLB) * 16;
+  constexpr int REC = S * STB;
+  constexpr int ROWS = REC + kStepRing * kStepBatch * 48;
+  constexpr int LDSB = ROWS + S * BM * 8;
+  constexpr int NS = SM * SN * 4;
+  static_assert(LDSB == stream_lds_bytes(1, BM, BN, S), "LDS layout");
+  static_assert(SLA % NT == 0 && SLB % NT == 0, "a copy round covers A or B slots only");
+  static_assert(S >= 2 && S <= 16, "stages");
+  static_assert(SM >= 1 && SN >= 1 && WM % 16 == 0 && WN % 16 == 0, "wave tiles of whole MFMA blocks");
+  static_assert(RL >= 1 && RL * 2 * NW == BM && RL <= 64, "row-offset copy");
+  static_assert(BL * NW == kStepBatch * 3, "record copy");
+  __shared__ __attribute__((aligned(16))) unsigned char smem[LDSB];
+
+  const int64_t first = wg_begin[blockIdx.x];
+  const int n = (int)(wg_begin[blockIdx.x + 1] - first);
+  if (n <= 0) return;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = wave / WGN, wn = wave % WGN;
+  const uint32_t lds0 = (uint32_t)(uintptr_t)(BST_LDS unsigned char*)smem;
+  const unsigned char* gsteps = reinterpret_cast<const unsigned char*>(steps + first);
+  int a_buf = -1, b_buf = -1;
+  const double* A = nullptr;
+  const double* B = nullptr;
+  const void* zero = g_stream_zero + 4 * lane;
+
+  auto copy_batch = [&](int bi) {
+    if (bi * kStepBatch < n && lane < BL)
+      lds_copy16(lds0 + REC + (uint32_t)(bi % kStepRing) * (kStepBatch * 48) + wave * (BL * 16),
+                 gsteps + (int64_t)bi * (kStepBatch * 48) + wave * (BL * 16) + lane * 16);
+  };
+  auto rec_ptr = [&](int v) -> const unsigned char* {
+    return smem + REC + ((v / kStepBatch) % kStepRing) * (kStepBatch * 48) + (v % kStepBatch) * 48;
+  };
+
+  int tiles_in = 0, tiles_out = 0;
+  auto issue = [&](int v) {
+    if (v % kStepBatch == 0) copy_batch(v / kStepBatch + 1);
+    const Rec d = read_rec(rec_ptr(v));
+    if ((d.flags & (kStepFirst | kStepRowmap)) == (kStepFirst | kStepRowmap)) {
+      if (lane < RL)
+        lds_copy16(lds0 + ROWS + (uint32_t)(tiles_in % S) * (BM * 8) + wave * (RL * 16),
+                   rowtab + d.c + wave * (RL * 2) + lane * 2);
+    }
+    if (d.flags & kStepFirst) ++tiles_in;
+    if (d.a_buf != a_buf) {
+      a_buf = d.a_buf;
+      A = static_cast<const double*>(ptrs[a_buf]);
+    }
+    if (d.b_buf != b_buf) {
+      b_buf = d.b_buf;
+      B = static_cast<const double*>(ptrs[b_buf]);
+    }
+    const uint32_t sb = lds0 + (uint32_t)(v % S) * STB;
+#pragma unroll
+    for (int i = 0; i < LPS; ++i) {
+      const bool isA = i * NT < SLA;
+      const int sl = isA ? i * NT + tid : i * NT - SLA + tid;
+      const int r = sl / NC, cc = swz<2>(r, sl % NC);
+      const int row = min(r, (isA ? d.rows : d.cols) - 1);
+      const int64_t e = (isA ? d.a + (int64_t)row * d.lda : d.b + (int64_t)row * d.ldb) + cc * 2;
+      const void* g = cc < d.kch ? static_cast<const void*>((isA ? A : B) + e) : zero;
+      lds_copy16(sb + (uint32_t)(i * NT * 16 + wave * 1024), g);
+    }
+  };
+
+  dbl4 acc[SM][SN];
+
+  auto compute = [&](int u, const Rec& d) {
+    const unsigned char* As = smem + (u % S) * STB;
+    const unsigned char* Bs = As + BM * NC * 16;
+    const int g = lane >> 4;   // this lane's elements 4g .. 4g + 3 of the step
+    dbl2 a[SM][2], b[SN][2];
+#pragma unroll
+    for (int i = 0; i < SM; ++i) {
+      const int r = wm * WM + i * 16 + (lane & 15);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) a[i][h] = *reinterpret_cast<const dbl2*>(As + (r * NC + swz<2>(r, 2 * g + h)) * 16);
+    }
+#pragma unroll
+    for (int j = 0; j < SN; ++j) {
+      const int r = wn * WN + j * 16 + (lane & 15);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) b[j][h] = *reinterpret_cast<const dbl2*>(Bs + (r * NC + swz<2>(r, 2 * g + h)) * 16);
+    }
+    // a partial last piece (one valid element): zero its second element in
+    // both operands, so that whatever the padding holds cannot reach the sums
+    if (d.kval < 2) {
+      const int p = d.kch - 1;   // piece index; this lane holds pieces 2g, 2g + 1
+      if ((p >> 1) == g) {
+        const int h = p & 1;
+#pragma unroll
+        for (int i = 0; i < SM; ++i) a[i][h].y = 0.0;
+#pragma unroll
+        for (int j = 0; j < SN; ++j) b[j][h].y = 0.0;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int i = 0; i < SM; ++i)
+#pragma unroll
+        for (int j = 0; j < SN; ++j) {
+          const double av = (q & 1) ? a[i][q >> 1].y : a[i][q >> 1].x;
+          const double bv = (q & 1) ? b[j][q >> 1].y : b[j][q >> 1].x;
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[i][j], 0, 0, 0);
+        }
+  };
+
+  // float64 accumulators: register r of lane l holds row 4r + l / 16,
+  // column l % 16 of the 16 x 16 block
+  auto epilogue = [&](const Rec& d) {
+    BST_G double* C = (BST_G double*)(ptrs[d.c_buf]);
+    BST_G double* sink = (BST_G double*)(g_stream_sink + ((blockIdx.x % kSinkWgs) * 8 + wave) * 16 + (lane & 15));
+    const int64_t* rmap = reinterpret_cast<const int64_t*>(smem + ROWS + (tiles_out % S) * (BM * 8));
+#pragma unroll
+    for (int i = 0; i < SM; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = wm * WM + i * 16 + 4 * r + (lane >> 4);
+        int64_t rb;
+        if (d.flags & kStepRowmap)
+          rb = rmap[row];
+        else
+          rb = row < d.rows ? d.c + (int64_t)row * d.ldc : -1;
+#pragma unroll
+        for (int j = 0; j < SN; ++j) {
+          const int col = wn * WN + j * 16 + (lane & 15);
+          BST_G double* p = (rb >= 0 && col < d.cols) ? C + rb + col : sink;
+          *p = acc[i][j][r];
+        }
+      }
+    ++tiles_out;
+  };
+
+  copy_batch(0);
+  wait_and_meet<0>();
+  int v = 0;
+  for (; v < n && v < S - 1; ++v) issue(v);
+  unsigned epi = 0;
+  constexpr unsigned kEpiMask = (1u << (S - 1)) - 1;
+  int u = 0;
+  while (u < n) {
+#pragma unroll
+    for (int i = 0; i < SM; ++i)
+#pragma unroll
+      for (int j = 0; j < SN; ++j) acc[i][j] = dbl4{0, 0, 0, 0};
+    Rec d;
+    do {
+      if (n - 1 - u >= S - 2)
+        wait_and_meet_sel<(S - 2) * LPS, NS, S - 1>(__builtin_popcount(epi));
+      else
+        wait_and_meet<0>();
+      if (v < n) {
+        issue(v);
+        ++v;
+      }
+      d = read_rec(rec_ptr(u));
+      compute(u, d);
+      epi = (epi << 1) & kEpiMask;
+      ++u;
+    } while (!(d.flags & kStepLast) && u < n);
+    epilogue(d);
+    epi |= 1;
+  }
+}
+
+// Float64 shapes (gemm_planes_shapes(1), all of kind 3): bm, bn, stages,
+// waves along M, waves along N.
+#define BST_STREAM64_SHAPES(X) \
+  X(64, 64, 3, 2, 2)           \
+  X(128, 64, 3, 2, 2)          \
+  X(64, 128, 3, 2, 2)          \
+  X(128, 128, 3, 2, 4)         \
+  X(256, 128, 3, 4, 2)         \
+  X(128, 256, 3, 2, 4)
+
 // Shapes of kind 3 in gemm_planes_shapes(np), instantiated here
 // (np, bm, bn, stages, waves along M, waves along N).
 #define BST_STREAM_SHAPES(X) \
@@ -331,6 +531,18 @@ hipError_t launch_gemm_planes_stream(const StreamLaunch& g, hipStream_t s) {
   const TileShape& sh = gemm_planes_shapes(g.np)[g.tile];
   if (sh.direct != 3) return hipErrorInvalidValue;
   const dim3 grid((unsigned)g.nwg);
+  if (g.np == 1) {
+    if (g.tc != ElemType::F64) return hipErrorInvalidValue;
+#define BST_LAUNCH64(BM_, BN_, S_, WGM_, WGN_)                                                              \
+  if (sh.bm == BM_ && sh.bn == BN_ && sh.stages == S_ && sh.waves == WGM_ * WGN_) {                        \
+    hipLaunchKernelGGL((gemm_f64_stream_kernel<BM_, BN_, S_, WGM_, WGN_>), grid, dim3(64 * WGM_ * WGN_), 0, s, \
+                       g.steps, g.wg_begin, g.ptrs, g.rowtab);                                            \
+    return hipGetLastError();                                                                             \
+  }
+    BST_STREAM64_SHAPES(BST_LAUNCH64)
+#undef BST_LAUNCH64
+    return hipErrorInvalidValue;
+  }
 #define BST_LAUNCH(NP_, BM_, BN_, S_, WGM_, WGN_)                                                          \
   if (g.np == NP_ && sh.bm == BM_ && sh.bn == BN_ && sh.stages == S_ && sh.waves == WGM_ * WGN_) {        \
     const dim3 block(64 * WGM_ * WGN_);                                                                    \

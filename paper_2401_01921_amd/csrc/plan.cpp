@@ -496,10 +496,11 @@ static void heff_plan(const TensorDesc& L, const TensorDesc& W1, const TensorDes
     sink_need = std::max(sink_need, sh[0] * sh[4]);
   }
   const int64_t t3ps = pad32(std::max<int64_t>(t3tot + sink_need, 32));   // positions per plane
-  P.internals.push_back({8, (size_t)Lp.total * 2 * 3, 0});
-  P.internals.push_back({9, (size_t)Rp.total * 2 * 3, 0});
-  P.internals.push_back({10, (size_t)Pp.total * 2 * 3, 0});
-  P.internals.push_back({11, (size_t)t3ps * 2 * 3, 0});
+  // 8 bytes per position: three bfloat16 planes or one of float64
+  P.internals.push_back({8, (size_t)Lp.total * 8, 0});
+  P.internals.push_back({9, (size_t)Rp.total * 8, 0});
+  P.internals.push_back({10, (size_t)Pp.total * 8, 0});
+  P.internals.push_back({11, (size_t)t3ps * 8, 0});
   Step spL, spR, spP;
   spL.name = "split_L";
   spR.name = "split_R";
@@ -613,9 +614,10 @@ static void heff_plan(const TensorDesc& L, const TensorDesc& W1, const TensorDes
       s1.probs_alt.push_back(p);
       cum += T1->block_size(cb);
     }
-    // the T1 buffer holds the float64 block layout or this float32 one
+    // the T1 buffer holds the float64 block layout or this merged one (float32
+    // for the split forms, float64 for the float64 panels)
     for (auto& ib : P.internals)
-      if (ib.slot == 6) ib.bytes = std::max(ib.bytes, (size_t)cum * 4);
+      if (ib.slot == 6) ib.bytes = std::max(ib.bytes, (size_t)cum * 8);
     s1.bytes = 8.0 * ((double)L.numel + (double)psi.numel + (double)T1->numel);
     s1.bytes32 = 8.0 * ((double)L.numel + (double)psi.numel) + 4.0 * (double)T1->numel;
   }
@@ -1088,11 +1090,17 @@ static std::vector<GemmTile> make_tiles(const std::vector<GemmProb>& probs,
 // k-step records.  ok stays false if an operand offset or row stride is not
 // a multiple of 8 positions (whole 16-byte pieces) or a table slot does not
 // fit the record.
+//
+// np = 1 (float64 operands): 16-deep steps whose "chunks" are 16-byte
+// pieces of two elements.
 static Step::StreamList make_stream(std::vector<uint8_t>& blob, const Step& st, int np, const TileShape& sh) {
   Step::StreamList L;
   const auto& probs = st.probs_alt;
   const auto& segs = st.segs_alt;
   const int bm = sh.bm, bn = sh.bn;
+  // k elements per step and per chunk, chunks per step
+  const int64_t kdeep = np == 1 ? 16 : 32, kchunk = np == 1 ? 2 : 8, nchunk = kdeep / kchunk;
+  auto padc = [&](int64_t K) { return (K + kchunk - 1) / kchunk * kchunk; };
   if (bm > 256 || bn > 256) return L;   // row / column counts are stored in a byte
   for (const auto& g : segs) {
     if (g.K <= 0) continue;
@@ -1105,7 +1113,7 @@ static Step::StreamList make_stream(std::vector<uint8_t>& blob, const Step& st, 
     int64_t k = 0;
     for (int q = 0; q < p.seg_count; ++q) {
       const int64_t K = segs[p.seg_begin + q].K;
-      if (K > 0) k += (pad8(K) + 31) / 32;
+      if (K > 0) k += (padc(K) + kdeep - 1) / kdeep;
     }
     return std::max<int64_t>(k, 1);
   };
@@ -1154,7 +1162,7 @@ static Step::StreamList make_stream(std::vector<uint8_t>& blob, const Step& st, 
       base.rows1 = (uint8_t)(rows - 1);
       base.cols1 = (uint8_t)(cols - 1);
       base.c_buf = (uint16_t)p.c_buf;
-      base.kval = 8;
+      base.kval = (uint8_t)kchunk;
       if (p.rowmap1 > 0) {
         base.flags = kStepRowmap;
         base.c = (int64_t)rowtab.size();
@@ -1168,8 +1176,8 @@ static Step::StreamList make_stream(std::vector<uint8_t>& blob, const Step& st, 
       for (int q = 0; q < p.seg_count; ++q) {
         const GemmSeg& g = segs[p.seg_begin + q];
         if (g.K <= 0) continue;
-        const int64_t K8 = pad8(g.K);
-        for (int64_t lk = 0; lk < K8; lk += 32) {
+        const int64_t K8 = padc(g.K);
+        for (int64_t lk = 0; lk < K8; lk += kdeep) {
           KStep k = base;
           k.a = g.a_off + (int64_t)t.m0 * g.lda + lk;
           k.b = g.b_off + (int64_t)t.n0 * g.ldb + lk;
@@ -1177,8 +1185,8 @@ static Step::StreamList make_stream(std::vector<uint8_t>& blob, const Step& st, 
           k.ldb = g.ldb;
           k.a_buf = (uint16_t)g.a_buf;
           k.b_buf = (uint16_t)g.b_buf;
-          k.kch = (uint8_t)std::min<int64_t>(4, (K8 - lk) / 8);
-          k.kval = (uint8_t)((lk + 8 * k.kch == K8 && g.K % 8) ? g.K % 8 : 8);
+          k.kch = (uint8_t)std::min<int64_t>(nchunk, (K8 - lk) / kchunk);
+          k.kval = (uint8_t)((lk + kchunk * k.kch == K8 && g.K % kchunk) ? g.K % kchunk : kchunk);
           recs.push_back(k);
         }
       }
@@ -1242,7 +1250,7 @@ void finalize(PlanData& P) {
           st.off3 = put(P.blob, st.probs_alt);
           st.off5 = put(P.blob, st.rowmap);
           st.streams_alt.clear();
-          for (int np = 2; np <= 3; ++np) {
+          for (int np = 1; np <= 3; ++np) {
             const auto& shapes = gemm_planes_shapes(np);
             for (size_t i = 0; i < shapes.size(); ++i) {
               const auto& sh = shapes[i];
@@ -1347,6 +1355,13 @@ void finalize(PlanData& P) {
     off = align256(off + std::max<size_t>(ib.bytes, 8));
   }
   P.ws_bytes = off;
+  P.f64_panels = P.has_planes;
+  for (const auto& st : P.steps) {
+    if (st.kind != StepKind::Gemm || !st.has_alt) continue;
+    bool any = false;
+    for (const auto& kv : st.streams_alt) any = any || (kv.first / 64 == 1 && kv.second.ok);
+    P.f64_panels = P.f64_panels && any;
+  }
   P.finalized = true;
   P.uploaded_ws = nullptr;
   P.last_ptrs.clear();
@@ -1537,7 +1552,7 @@ bst_status bst_plan_tiles(const bst_plan* p, char* buf, size_t cap) {
     }
     if (st.kind != StepKind::Gemm) continue;
     const bool pl = uses_planes(P, P.prec) && st.has_alt;
-    const TileShape sh = pl ? gemm_planes_shapes(P.prec == BST_BF16X6 ? 3 : 2)[planes_tile(st, P.prec)]
+    const TileShape sh = pl ? gemm_planes_shapes(plane_count(P.prec))[planes_tile(st, P.prec)]
                             : gemm_tile_shapes(P.prec)[default_tile(st, P.prec)];
     const std::string kind = sh.direct == 1   ? "d"
                              : sh.direct == 3 ? "s" + std::to_string(sh.stages) + "w" + std::to_string(sh.waves)

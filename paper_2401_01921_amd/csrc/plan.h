@@ -119,6 +119,12 @@ struct PlanData {
   int64_t psi_numel = 0;
   int64_t t1_numel = 0, t3_numel = 0;
   bool has_planes = false;      // split forms run the bfloat16-plane variant
+  // every plane-variant GEMM step has a float64 k-step schedule, so FP64 can
+  // run on float64 operands in the same padded layouts (finalize)
+  bool f64_panels = false;
+  // FP64 runs on the float64 panels (chosen by the autotuner when its whole
+  // apply is faster than with the per-block-pair kernels)
+  bool fp64_panels_on = false;
   bool sparse_mpo = true;       // MPO apply runs only the nonzero h entries
   // finalize
   std::vector<uint8_t> blob;
@@ -152,7 +158,15 @@ std::vector<void*> build_ptrs(PlanData& p, const void* const* in, void* const* o
 // results from an earlier execute on the same workspace are still valid).
 void run_steps(PlanData& p, void* ws, void* const* dptrs, bst_precision prec, hipStream_t s,
                bool skip_const, std::vector<std::pair<hipEvent_t, hipEvent_t>>* ev = nullptr);
+// The padded-layout variant runs for this form: bfloat16 planes for the
+// split forms; float64 operands for FP64 when the autotuner chose them or
+// BST_FP64_PANELS is set (BST_FP64_BLOCKS keeps FP64 on the per-block-pair
+// kernels).
 bool uses_planes(const PlanData& p, bst_precision prec);
+// Planes of the padded-layout variant of a form: 1 (float64), 2 or 3.
+int plane_count(bst_precision prec);
+// Plane count of a tile-choice key of the padded-layout variant (10 + form).
+int plane_count_of_key(int key);
 bool step_runs(const PlanData& p, const Step& st, bst_precision prec, bool skip_const);
 int planes_tile(const Step& st, bst_precision prec);
 int default_tile(const Step& st, bst_precision form);

@@ -346,3 +346,47 @@ def test_workspace_overwritten_between_calls():
     plan.execute(ins, [out], ws)
     torch.cuda.synchronize()
     assert np.array_equal(host(out), first)
+
+
+def test_fp64_panels_full_size(monkeypatch):
+    """Float64 sector GEMMs on the padded layouts (pipelined kernel) on the
+    spin-1 chi = 4096 operator: every tile shape gives the same bits (same
+    products, same k order), the oracle's result to float64 rounding, and
+    the per-block-pair kernels' result to the same tolerance."""
+    specs, O = heff_operands(5, recipe="dmrg_like")
+    ref = orc.heff_apply(O["L"], O["W1"], O["W2"], O["R"], O["psi"]).data
+    T, bplan = lib_heff(specs, "fp64")
+    assert "p;" not in bplan.tiles(), bplan.tiles()   # the default: per-block-pair kernels
+    blocks = run_heff(bplan, O)
+    check(blocks, ref, "fp64", "fp64 per-block kernels")
+    monkeypatch.setenv("BST_FP64_PANELS", "1")
+    T, plan = lib_heff(specs, "fp64")
+    tiles = _pipelined_tiles(plan, "fp64")
+    assert len(tiles) == plan.tile_count("fp64")   # float64 panels: pipelined shapes only
+    base = None
+    for tile in tiles:
+        plan.set_tile("fp64", tile)
+        assert "p;" in plan.tiles(), plan.tiles()
+        got = run_heff(plan, O)
+        check(got, ref, "fp64", f"fp64 panels {plan.tiles()}")
+        if base is None:
+            base = got
+        assert np.array_equal(got, base), plan.tiles()
+
+
+@pytest.mark.parametrize("k", [2, 3])
+def test_fp64_autotuned_variant(k):
+    """The autotuner times the FP64 apply on the per-block-pair kernels and on
+    the float64 panels and keeps the faster; either way the result is the
+    oracle's to float64 rounding and repeats bit for bit."""
+    specs, O = heff_operands(k)
+    ref = orc.heff_apply(O["L"], O["W1"], O["W2"], O["R"], O["psi"]).data
+    T, plan = lib_heff(specs, "fp64")
+    ins = [dev(O[n].data) for n in ("L", "W1", "W2", "R", "psi")]
+    out = torch.empty(O["psi"].numel, dtype=torch.float64, device=DEV)
+    plan.autotune(ins, [out], bst.workspace(plan.workspace_bytes), reps=2)
+    _print("fp64 autotuned", k, plan.tiles())
+    a = run_heff(plan, O)
+    b = run_heff(plan, O)
+    check(a, ref, "fp64", f"fp64 autotuned {plan.tiles()}")
+    assert np.array_equal(a, b)
