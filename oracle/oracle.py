@@ -25,6 +25,11 @@ Library for Tensor Networks"):
   exact diagonalisation in tests)        is the XX chain)
 * network contraction and its optimal . Sec. "Network" (exhaustive search
   order                                  over binary trees, dense cost)
+* SVD of a symmetric tensor and its .... Sec. "Singular value decomposition"
+  truncation (keepdim, err,              (the printed block values of the
+  min_blockdim)                          symmetric example fix the rule)
+* two-site DMRG sweep .................. Sec. "Benchmarks" (DMRG of the XX
+                                         chain)
 * Lanczos on a linear operator ......... Sec. "Eigenvalue decomposition"
   (LinOp + Lanczos; the paper gives no algorithmic detail, so this is the
   textbook method with full classical Gram-Schmidt reorthogonalisation done
@@ -646,3 +651,236 @@ def _lowest_in_sector(H: np.ndarray, nsites: int, spin: str, charge: int | None)
         keep = np.nonzero(tot == charge)[0]
         H = H[np.ix_(keep, keep)]
     return float(np.linalg.eigvalsh(H)[0])
+
+
+# --------------------------------------------------------------------------
+# Singular value decomposition of a symmetric tensor (Sec. "Tensor
+# decomposition and linear algebra": "Matrix form of a UniTensor" and
+# "Singular value decomposition", paragraphs "With truncation" and "SVD for
+# symmetric UniTensor").  The first rowrank legs are the rows, the others the
+# columns.  Every charge q of the new bond has one block matrix M_q: its rows
+# are the row-leg sector tuples whose combined flux (sum of dir * charge) is q,
+# its columns the column-leg tuples of combined flux -q, so that each (row
+# tuple, column tuple) pair is exactly one valid block of T.  The SVD of T is
+# the SVD of every M_q; the new bond leaves U outgoing and enters V^dagger.
+#
+# Readings where the paper is silent (listed in the design notes):
+#   * the sectors of the new bond are ordered as their charges first appear
+#     when the column tuples are enumerated lexicographically (for a single
+#     outgoing column leg this is that leg's sector order, as in the paper's
+#     printed rank-3 example); rows and columns inside M_q are the tuples in
+#     lexicographic order, each tuple's elements row-major;
+#   * truncation: the min_blockdim[q] largest values of each sector are kept
+#     first; the remaining room up to keepdim goes to the largest other values
+#     not below err, ties going to the earlier sector and then the earlier
+#     value; a sector left with no value is dropped from the new bond; s_err
+#     is the largest value not kept (0 when nothing is dropped).
+# --------------------------------------------------------------------------
+def _group_flux(T: BlockTensor, legs_idx: Sequence[int], t: Sequence[int]):
+    comps = []
+    for c, n in enumerate(T.sym):
+        f = sum(T.legs[i][0] * _components(T.legs[i][1][t[i]][0], len(T.sym))[c] for i in legs_idx)
+        comps.append(f % n if n >= 2 else f)
+    return tuple(comps)
+
+
+def _neg_charge(q: Tuple[int, ...], sym: Sequence[int]) -> Tuple[int, ...]:
+    return tuple((-v) % n if n >= 2 else -v for v, n in zip(q, sym))
+
+
+def svd_sectors(T: BlockTensor, rowrank: int):
+    """The block matrices of T seen as a matrix with the first rowrank legs as
+    rows: a list, in new-bond order, of dicts with the bond charge q, the row
+    and column tuples ((sector tuple, first row or column, extent), ...) and M."""
+    if not 0 < rowrank < T.rank:
+        raise OracleError("rowrank must leave at least one row and one column leg")
+    ri = list(range(rowrank))
+    ci = list(range(rowrank, T.rank))
+    rtup = list(itertools.product(*[range(len(T.legs[i][1])) for i in ri]))
+    ctup = list(itertools.product(*[range(len(T.legs[i][1])) for i in ci]))
+    order: List[Tuple[int, ...]] = []
+    for c in ctup:
+        full = tuple([0] * rowrank) + tuple(c)
+        q = _neg_charge(_group_flux(T, ci, full), T.sym)
+        if q not in order:
+            order.append(q)
+    out = []
+    for q in order:
+        rows, cols = [], []
+        nr = nc = 0
+        for r in rtup:
+            full = tuple(r) + tuple([0] * len(ci))
+            if _group_flux(T, ri, full) == q:
+                ext = int(np.prod([T.legs[i][1][k][1] for i, k in zip(ri, r)]))
+                rows.append((tuple(r), nr, ext))
+                nr += ext
+        for c in ctup:
+            full = tuple([0] * rowrank) + tuple(c)
+            if _neg_charge(_group_flux(T, ci, full), T.sym) == q:
+                ext = int(np.prod([T.legs[i][1][k][1] for i, k in zip(ci, c)]))
+                cols.append((tuple(c), nc, ext))
+                nc += ext
+        if nr == 0 or nc == 0:
+            continue
+        M = np.zeros((nr, nc))
+        for r, r0, re in rows:
+            for c, c0, ce in cols:
+                b = T.index[r + c]
+                M[r0:r0 + re, c0:c0 + ce] = T.block(b).reshape(re, ce)
+        out.append(dict(q=q if len(T.sym) > 1 else q[0], rows=rows, cols=cols, M=M))
+    return out
+
+
+def svd(T: BlockTensor, rowrank: int):
+    """Full SVD of every sector matrix (numpy's LAPACK SVD as the per-block
+    step): a list of (q, U_q, s_q descending, Vt_q) in new-bond order."""
+    res = []
+    for sec in svd_sectors(T, rowrank):
+        U, s, Vt = np.linalg.svd(sec["M"], full_matrices=False)
+        res.append((sec["q"], U, s, Vt))
+    return res
+
+
+def truncation_counts(svals: Sequence[np.ndarray], keepdim: int, err: float = 0.0,
+                      min_blockdim: Sequence[int] | None = None):
+    """Values kept per sector and the largest value not kept, for per-sector
+    singular values given in descending order (the truncation rule above)."""
+    ns = len(svals)
+    mb = [0] * ns if min_blockdim is None else [int(x) for x in min_blockdim]
+    if len(mb) != ns:
+        raise OracleError("one min_blockdim entry per sector")
+    kept = [min(mb[q], len(svals[q])) for q in range(ns)]
+    room = keepdim - sum(kept)
+    cand = [(float(svals[q][i]), q, i) for q in range(ns) for i in range(kept[q], len(svals[q]))
+            if float(svals[q][i]) >= err]
+    # descending value, then earlier sector, then earlier position
+    cand.sort(key=lambda x: (-x[0], x[1], x[2]))
+    for v, q, i in cand[:max(room, 0)]:
+        kept[q] += 1
+    s_err = 0.0
+    for q in range(ns):
+        if kept[q] < len(svals[q]):
+            s_err = max(s_err, float(svals[q][kept[q]]))
+    return kept, s_err
+
+
+def svd_truncate(T: BlockTensor, rowrank: int, keepdim: int, err: float = 0.0,
+                 min_blockdim: Sequence[int] | None = None, bond: str = "_m", absorb: str | None = None):
+    """Svd_truncate of a symmetric tensor: U[rows..., bond] (bond outgoing),
+    the kept singular values per kept sector, V^dagger[bond, cols...] (bond
+    incoming) and s_err.  absorb = "u" or "v" multiplies the singular values
+    into that factor."""
+    secs = svd_sectors(T, rowrank)
+    full = svd(T, rowrank)
+    kept, s_err = truncation_counts([s for _, _, s, _ in full], keepdim, err, min_blockdim)
+    keep_idx = [i for i in range(len(secs)) if kept[i] > 0]
+    bond_secs = [(secs[i]["q"], kept[i]) for i in keep_idx]
+    rlegs = T.legs[:rowrank]
+    clegs = T.legs[rowrank:]
+    U = BlockTensor(T.labels[:rowrank] + [bond], list(rlegs) + [(OUT, bond_secs)], sym=T.sym)
+    Vd = BlockTensor([bond] + T.labels[rowrank:], [(IN, bond_secs)] + list(clegs), sym=T.sym)
+    S = []
+    for pos, i in enumerate(keep_idx):
+        q, Uq, sq, Vtq = full[i]
+        k = kept[i]
+        u, s, vt = Uq[:, :k], sq[:k], Vtq[:k, :]
+        if absorb == "u":
+            u = u * s[None, :]
+        elif absorb == "v":
+            vt = vt * s[:, None]
+        S.append(s.copy())
+        for r, r0, re in secs[i]["rows"]:
+            b = U.index[r + (pos,)]
+            U.block(b)[...] = u[r0:r0 + re, :].reshape(U.shapes[b])
+        for c, c0, ce in secs[i]["cols"]:
+            b = Vd.index[(pos,) + c]
+            Vd.block(b)[...] = vt[:, c0:c0 + ce].reshape(Vd.shapes[b])
+    return U, S, Vd, s_err
+
+
+# --------------------------------------------------------------------------
+# Two-site DMRG of an open chain (Sec. "Benchmarks": the DMRG iteration of the
+# XX chain; Fig. Hpsi_fig for the effective Hamiltonian).  MPS tensors
+# A[a, s, b] (in, in, out); environments L[a, w, a'] (in, out, out) and
+# R[b, w, b'] (out, in, in) as in heff_apply.  Textbook procedure: bring the
+# MPS to right-canonical form with SVDs from the right, then sweep: at each
+# bond, the ground state of H_eff (Lanczos) is split by a truncated SVD; the
+# orthonormal factor stays, the singular values move with the centre, and the
+# environment grows by one site.
+# --------------------------------------------------------------------------
+def dagger(T: BlockTensor) -> BlockTensor:
+    """The same real data with every leg's direction reversed (conjugate)."""
+    return BlockTensor(T.labels, [(-d, secs) for d, secs in T.legs], T.data.copy(), sym=T.sym)
+
+
+def left_env_update(L: BlockTensor, A: BlockTensor, W: BlockTensor) -> BlockTensor:
+    """L'[b, w', b'] = sum A*[a, s, b] L[a, w, a'] W[w, s, s', w'] A[a', s', b']."""
+    X = contract(relabel(L, ["a", "w", "ap"]), relabel(A, ["ap", "sp", "bp"]))
+    Y = contract(X, relabel(W, ["w", "s", "sp", "wp"]))
+    Z = contract(Y, relabel(dagger(A), ["a", "s", "b"]))
+    return relabel(permute(Z, ["b", "wp", "bp"]), ["a", "w", "ap"])
+
+
+def right_env_update(R: BlockTensor, B: BlockTensor, W: BlockTensor) -> BlockTensor:
+    """R'[a, w, a'] = sum B*[a, s, b] W[w, s, s', w'] R[b, w', b'] B[a', s', b']."""
+    X = contract(relabel(R, ["b", "wp", "bp"]), relabel(B, ["ap", "sp", "bp"]))
+    Y = contract(X, relabel(W, ["w", "s", "sp", "wp"]))
+    Z = contract(Y, relabel(dagger(B), ["a", "s", "b"]))
+    return relabel(permute(Z, ["a", "w", "ap"]), ["b", "w", "bp"])
+
+
+def _two_site(A: BlockTensor, B: BlockTensor) -> BlockTensor:
+    return contract(relabel(A, ["a", "s1", "m"]), relabel(B, ["m", "s2", "b"]))
+
+
+def dmrg_two_site(mps: Sequence[BlockTensor], W: BlockTensor, Lb: BlockTensor, Rb: BlockTensor,
+                  nsweeps: int, keepdim: int, err: float = 1e-12, lanczos_steps: int = 40):
+    """Right-canonicalise, then nsweeps left-to-right-to-left sweeps.  Returns
+    the refined Lanczos energy of every bond update in order and the final MPS
+    (centre on site 0)."""
+    A = [relabel(t, ["a", "s", "b"]) for t in mps]
+    N = len(A)
+    if N < 2:
+        raise OracleError("two-site DMRG needs at least two sites")
+    # right-canonical form: A_j = V^dagger, U S moves left
+    for j in range(N - 1, 0, -1):
+        U, S, Vd, _ = svd_truncate(A[j], 1, 1 << 30, 0.0, bond="m", absorb="u")
+        A[j] = relabel(Vd, ["a", "s", "b"])
+        A[j - 1] = relabel(contract(relabel(A[j - 1], ["a", "s", "x"]), relabel(U, ["x", "m"])),
+                           ["a", "s", "b"])
+    Rs = [None] * (N + 1)
+    Rs[N] = Rb
+    for j in range(N - 1, 1, -1):
+        Rs[j] = right_env_update(Rs[j + 1], A[j], W)
+    Ls = [None] * (N + 1)
+    Ls[0] = Lb
+    energies = []
+
+    def solve(i):
+        psi = _two_site(A[i], A[i + 1])
+        Lr, Rr = Ls[i], Rs[i + 2]
+
+        def mv(x):
+            return heff_apply(Lr, W, W, Rr, BlockTensor(psi.labels, psi.legs, x, sym=psi.sym)).data
+        steps = min(lanczos_steps, psi.numel)
+        r = lanczos_ground(mv, psi.data, steps)
+        energies.append(r["energy"])
+        y = r["y"] / np.linalg.norm(r["y"])
+        return BlockTensor(psi.labels, psi.legs, y, sym=psi.sym)
+
+    for _ in range(nsweeps):
+        for i in range(N - 1):                  # left to right
+            psi = solve(i)
+            U, S, Vd, _ = svd_truncate(psi, 2, keepdim, err, bond="m", absorb="v")
+            A[i] = relabel(U, ["a", "s", "b"])
+            A[i + 1] = relabel(Vd, ["a", "s", "b"])
+            if i + 1 < N - 1:
+                Ls[i + 1] = left_env_update(Ls[i], A[i], W)
+        for i in range(N - 2, -1, -1):          # right to left
+            psi = solve(i)
+            U, S, Vd, _ = svd_truncate(psi, 2, keepdim, err, bond="m", absorb="u")
+            A[i] = relabel(U, ["a", "s", "b"])
+            A[i + 1] = relabel(Vd, ["a", "s", "b"])
+            if i > 0:
+                Rs[i + 1] = right_env_update(Rs[i + 2], A[i + 1], W)
+    return energies, A

@@ -389,3 +389,55 @@ def tfim_heff_specs(virt_a: List[Tuple[int, int]], virt_b: List[Tuple[int, int]]
     R = (["b", "w", "bp"], [(OUT, virt_b), (IN, mb), (IN, virt_b)])
     W = (["wl", "s", "sp", "wr"], [(IN, mb), (IN, ph), (OUT, ph), (OUT, mb)])
     return {"L": L, "W1": W, "W2": W, "R": R, "psi": psi}
+
+
+# --------------------------------------------------------------------------
+# Open-chain MPS inputs (structure and seeded values only)
+# --------------------------------------------------------------------------
+def _charge_counts(nsites: int, spin: str) -> Dict[int, int]:
+    """Number of product states of nsites sites per total charge."""
+    qs = [q for q, _ in physical_sectors(spin)]
+    c = {0: 1}
+    for _ in range(nsites):
+        n: Dict[int, int] = {}
+        for t, m in c.items():
+            for q in qs:
+                n[t + q] = n.get(t + q, 0) + m
+        c = n
+    return c
+
+
+def mps_bonds(nsites: int, spin: str, charge: int = 0, cap: int | None = None) -> List[List[Tuple[int, int]]]:
+    """Sector lists of the nsites + 1 virtual bonds of an open-chain MPS in the
+    total-charge sector `charge`: bond i carries the charge of sites 0..i-1,
+    with the number of left-block states of that charge as its dim, capped by
+    the number of right-block states completing it to `charge` (and by cap)."""
+    bonds = []
+    for i in range(nsites + 1):
+        left, right = _charge_counts(i, spin), _charge_counts(nsites - i, spin)
+        secs = []
+        for q in sorted(left):
+            d = min(left[q], right.get(charge - q, 0))
+            if cap is not None:
+                d = min(d, cap)
+            if d > 0:
+                secs.append((q, d))
+        bonds.append(secs)
+    return bonds
+
+
+def mps_specs(nsites: int, spin: str, charge: int = 0, cap: int | None = None):
+    """(labels, legs) of the site tensors A_i[a, s, b] (in, in, out)."""
+    bonds = mps_bonds(nsites, spin, charge, cap)
+    ph = physical_sectors(spin)
+    return [(["a", "s", "b"], [(IN, bonds[i]), (IN, ph), (OUT, bonds[i + 1])]) for i in range(nsites)]
+
+
+def boundary_env_specs(spin: str, model: str = "heisenberg", charge: int = 0):
+    """(labels, legs) of the trivial boundary environments L[1, D_W, 1] and
+    R[1, D_W, 1], and the dense position of their single 1.0 (the left
+    boundary channel 4 in L, the right boundary channel 0 in R)."""
+    mb = mpo_bond(spin, model)
+    L = (["a", "w", "ap"], [(IN, [(0, 1)]), (OUT, mb), (OUT, [(0, 1)])])
+    R = (["b", "w", "bp"], [(OUT, [(charge, 1)]), (IN, mb), (IN, [(charge, 1)])])
+    return L, (0, grouped_index(4, model), 0), R, (0, grouped_index(0, model), 0)
