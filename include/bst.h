@@ -368,6 +368,82 @@ bst_status bst_lanczos_ground(bst_plan* heff, const void* const* ops, const void
                               void* psi_out, double* energy, bst_lanczos_info* info, void* ws,
                               void* stream);
 
+/* ---- symmetric SVD with truncation (Sec. "Singular value decomposition":
+ *      paragraphs "With truncation" and "SVD for symmetric UniTensor") ------ */
+
+/* Opaque plan of the SVD of one tensor structure. */
+typedef struct bst_svd bst_svd;
+
+/* Plans the SVD of tensor M seen as a matrix whose rows are its first
+ * rowrank legs and whose columns are the others (Sec. "Matrix form of a
+ * UniTensor").  The matrix splits into one block matrix M_q per charge q of
+ * the new bond: its rows are the row-leg sector tuples of combined flux q
+ * (sum of direction times charge, modulo n for Z_n), its columns the
+ * column-leg tuples of flux -q, tuples in lexicographic order and each
+ * tuple's elements row-major.  The sectors of the new bond are ordered as
+ * their charges first appear over the column tuples in lexicographic order.
+ * Host bookkeeping only.  Errors: BST_E_INVALID (null, rowrank outside
+ * 1..rank-1, a sector matrix above 2^31 rows or columns). */
+bst_status bst_svd_plan(const bst_tensor* M, int32_t rowrank, bst_svd** out);
+
+/* Sector count, total singular values (sum of min(rows, cols)) and the
+ * workspace bytes the plan's calls need (256-byte aligned device memory,
+ * caller-owned; the plan's tables are uploaded on first use of a pointer,
+ * see bst_svd_forget_workspace). */
+bst_status bst_svd_info(const bst_svd* p, int32_t* nsectors, int64_t* nvalues, size_t* ws_bytes);
+
+/* Charge (nsym components) and shape of sector k of the new bond. */
+bst_status bst_svd_sector(const bst_svd* p, int32_t k, int32_t* charge, int64_t* rows, int64_t* cols);
+
+/* Enqueues the full SVD of every sector matrix of M (device pointer, M's
+ * layout) into the workspace: one-sided Jacobi on the tall orientation of
+ * each M_q, float64, sweeps until no pair of columns is rotated
+ * (|x_i.x_j| <= 4 eps sqrt(p) |x_i||x_j|, p the long side, at most 60
+ * sweeps); singular values sorted in descending order per sector.  The
+ * singular vectors of a zero singular value are returned as zero vectors
+ * on the long side.  Results stay in the workspace for bst_svd_truncate
+ * and bst_svd_write. */
+bst_status bst_svd_execute(bst_svd* p, const void* M, void* ws, void* stream);
+
+/* Chooses the kept singular values across all sectors (after
+ * bst_svd_execute on the same workspace and stream): every sector k keeps
+ * its min(min_blockdim[k], rows, cols) largest values (min_blockdim may be
+ * null: zeros); the remaining room up to keepdim goes to the largest other
+ * values that are not below err, ties to the earlier sector, then the
+ * earlier value (the values are not normalised).  kept (host, nsectors
+ * entries) receives the count per sector, s_err (host, may be null) the
+ * largest value not kept (0 if none).  Blocks until the counts are on the
+ * host.  Errors: BST_E_INVALID (keepdim < 0, err < 0 or NaN, a negative
+ * min_blockdim). */
+bst_status bst_svd_truncate(bst_svd* p, int64_t keepdim, double err, const int64_t* min_blockdim,
+                            void* ws, void* stream, int64_t* kept, double* s_err);
+
+/* Descriptors of the truncated factors for the counts kept[nsectors]:
+ * U[row legs..., bond] with the new bond outgoing and V^dagger[bond,
+ * column legs...] with it incoming, both labelled `bond`, whose sectors are
+ * the sectors with kept > 0 (in bond order) with dims kept[k]; a sector
+ * truncated to nothing leaves the bond.  Errors: BST_E_INVALID (a count
+ * outside 0..min(rows, cols), every sector empty), BST_E_LABEL (bond equals
+ * a leg label). */
+bst_status bst_svd_factors(const bst_svd* p, const int64_t* kept, const char* bond, bst_tensor** U,
+                           bst_tensor** Vd);
+
+/* Writes the kept columns of U, the kept singular values and the kept rows
+ * of V^dagger (device pointers, layouts of bst_svd_factors; S receives
+ * sum(kept) values, sector by sector in bond order, descending inside a
+ * sector).  absorb = 1 multiplies the values into U's columns, 2 into
+ * V^dagger's rows, 0 leaves both orthonormal.  Blocks until the write has
+ * run.  Errors: BST_E_INVALID. */
+bst_status bst_svd_write(bst_svd* p, const int64_t* kept, int32_t absorb, void* U, void* S, void* Vd,
+                         void* ws, void* stream);
+
+/* Forget which workspace holds the plan's tables (call before reusing a
+ * plan after freeing or overwriting its workspace). */
+bst_status bst_svd_forget_workspace(bst_svd* p);
+
+/* Release an SVD plan (null is allowed; always BST_OK). */
+bst_status bst_svd_destroy(bst_svd* p);
+
 /* ---- calibration (the device's practical rates, measured with this
  *      library's own code) ------------------------------------------------ */
 

@@ -34,6 +34,8 @@ EXPORTS = [
     "bst_plan_tile_count", "bst_plan_set_tile", "bst_plan_forget_workspace",
     "bst_tensor_create_sym", "bst_tensor_symmetry", "bst_tensor_leg_charges",
     "bst_network_order", "bst_plan_record_tiles", "bst_execute_static", "bst_calib_grid", "bst_calib_copy", "bst_calib_read", "bst_calib_mfma",
+    "bst_svd_plan", "bst_svd_info", "bst_svd_sector", "bst_svd_execute", "bst_svd_truncate",
+    "bst_svd_factors", "bst_svd_write", "bst_svd_forget_workspace", "bst_svd_destroy",
 ]
 
 
@@ -113,6 +115,17 @@ def _load():
         "bst_calib_copy": [vp, vp, sz, vp],
         "bst_calib_read": [vp, sz, vp, vp],
         "bst_calib_mfma": [C.c_int, i64, vp, P(C.c_double), vp],
+    })
+    sig.update({
+        "bst_svd_plan": [vp, i32, P(vp)],
+        "bst_svd_info": [vp, P(i32), P(i64), P(sz)],
+        "bst_svd_sector": [vp, i32, P(i32), P(i64), P(i64)],
+        "bst_svd_execute": [vp, vp, vp, vp],
+        "bst_svd_truncate": [vp, i64, C.c_double, P(i64), vp, vp, P(i64), P(C.c_double)],
+        "bst_svd_factors": [vp, P(i64), C.c_char_p, P(vp), P(vp)],
+        "bst_svd_write": [vp, P(i64), i32, vp, vp, vp, vp, vp],
+        "bst_svd_forget_workspace": [vp],
+        "bst_svd_destroy": [vp],
     })
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -534,3 +547,84 @@ def calib_mfma(prec, iters: int, out, stream=None) -> float:
     _check(_lib.bst_calib_mfma(_prec(prec), int(iters), C.c_void_p(_ptr(out)), C.byref(f),
                                _stream(stream)))
     return f.value
+
+
+# --------------------------------------------------------------------------
+class Svd:
+    """Plan of the SVD of one tensor structure (bst_svd_*): execute, then
+    truncate, then factors / write.  Argument marshalling only."""
+
+    def __init__(self, T: Tensor, rowrank: int):
+        h = C.c_void_p()
+        _check(_lib.bst_svd_plan(T.handle, int(rowrank), C.byref(h)))
+        self._h = h
+        ns, nv, ws = C.c_int32(), C.c_int64(), C.c_size_t()
+        _check(_lib.bst_svd_info(self._h, C.byref(ns), C.byref(nv), C.byref(ws)))
+        self.nsectors, self.nvalues, self.workspace_bytes = ns.value, nv.value, ws.value
+        self.nsym = len(T.symmetry())
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.bst_svd_destroy(h)
+            self._h = None
+
+    def sector(self, k: int):
+        """(charge, rows, cols) of sector k of the new bond."""
+        q = (C.c_int32 * max(self.nsym, 1))()
+        r, c = C.c_int64(), C.c_int64()
+        _check(_lib.bst_svd_sector(self._h, int(k), q, C.byref(r), C.byref(c)))
+        ch = tuple(q[:self.nsym])
+        return (ch if self.nsym > 1 else ch[0]), r.value, c.value
+
+    def execute(self, M, ws, stream=None):
+        _check(_lib.bst_svd_execute(self._h, C.c_void_p(_ptr(M)), C.c_void_p(_ptr(ws)), _stream(stream)))
+
+    def truncate(self, keepdim: int, err: float = 0.0, min_blockdim=None, ws=None, stream=None):
+        """Kept count per sector and the largest value not kept (blocks)."""
+        kept = (C.c_int64 * max(self.nsectors, 1))()
+        se = C.c_double()
+        mb = None
+        if min_blockdim is not None:
+            if len(min_blockdim) != self.nsectors:
+                raise BstError(1, "one min_blockdim entry per sector")
+            mb = (C.c_int64 * max(self.nsectors, 1))(*[int(x) for x in min_blockdim])
+        _check(_lib.bst_svd_truncate(self._h, int(keepdim), float(err), mb, C.c_void_p(_ptr(ws)),
+                                     _stream(stream), kept, C.byref(se)))
+        return list(kept[:self.nsectors]), se.value
+
+    def factors(self, kept, bond: str):
+        """(U, V^dagger) descriptors for the kept counts."""
+        k = (C.c_int64 * max(self.nsectors, 1))(*[int(x) for x in kept])
+        u, v = C.c_void_p(), C.c_void_p()
+        _check(_lib.bst_svd_factors(self._h, k, bond.encode(), C.byref(u), C.byref(v)))
+        return Tensor(None, None, _handle=u), Tensor(None, None, _handle=v)
+
+    def write(self, kept, absorb: int, U, S, Vd, ws, stream=None):
+        k = (C.c_int64 * max(self.nsectors, 1))(*[int(x) for x in kept])
+        _check(_lib.bst_svd_write(self._h, k, int(absorb), C.c_void_p(_ptr(U)), C.c_void_p(_ptr(S)),
+                                  C.c_void_p(_ptr(Vd)), C.c_void_p(_ptr(ws)), _stream(stream)))
+
+    def forget_workspace(self):
+        _check(_lib.bst_svd_forget_workspace(self._h))
+
+
+ABSORB = {None: 0, "u": 1, "v": 2}
+
+
+def svd_truncate(T: Tensor, M, rowrank: int, keepdim: int, err: float = 0.0, min_blockdim=None,
+                 bond: str = "_m", absorb=None, device="cuda"):
+    """Svd_truncate of the device tensor M (structure T): returns
+    (U descriptor, U data, S data, V^dagger descriptor, V^dagger data, s_err,
+    kept counts), data as float64 device tensors."""
+    import torch
+    plan = Svd(T, rowrank)
+    ws = workspace(plan.workspace_bytes, device)
+    plan.execute(M, ws)
+    kept, s_err = plan.truncate(keepdim, err, min_blockdim, ws)
+    Ut, Vt = plan.factors(kept, bond)
+    U = torch.empty(Ut.numel, dtype=torch.float64, device=device)
+    Vd = torch.empty(Vt.numel, dtype=torch.float64, device=device)
+    S = torch.empty(max(sum(kept), 1), dtype=torch.float64, device=device)[:sum(kept)]
+    plan.write(kept, ABSORB[absorb], U, S, Vd, ws)
+    return Ut, U, S, Vt, Vd, s_err, kept

@@ -18,8 +18,9 @@ LIB = os.path.join(HERE, "libbst.so")
 ARCH = "gfx950"
 
 SOURCES = ["structure.cpp", "plan.cpp", "exec.cpp", "lanczos.cpp", "kernels_gemm.hip", "kernels_aux.hip", "kernels_planes.hip",
-           "kernels_direct.hip", "kernels_stream.hip", "network.cpp", "kernels_calib.hip"]
-HEADERS = ["bst_internal.h", "plan.h", os.path.join("..", "..", "include", "bst.h")]
+           "kernels_direct.hip", "kernels_stream.hip", "network.cpp", "kernels_calib.hip",
+           "svd.cpp", "kernels_svd.hip"]
+HEADERS = ["bst_internal.h", "plan.h", "svd.h", os.path.join("..", "..", "include", "bst.h")]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-function",
           "-Wno-unused-variable"]
