@@ -368,6 +368,30 @@ bst_status bst_lanczos_ground(bst_plan* heff, const void* const* ops, const void
                               void* psi_out, double* energy, bst_lanczos_info* info, void* ws,
                               void* stream);
 
+/* ---- complex float64 data ---------------------------------------------- */
+
+/* Complex element type (Sec. "Creating a non-symmetric UniTensor",
+ * paragraph "Complex elements and data types"; used by the quantum-circuit
+ * simulation of App. "Quantum Circuit Simulation"): the same
+ * block structure and block order, each element two float64 (real, then
+ * imaginary), so a complex tensor of numel elements occupies 2 * numel
+ * doubles.  Plans built by the calls below take and produce such buffers in
+ * bst_execute; everything else about them is as for their float64
+ * counterparts.  Labels beginning with "#re" are reserved (BST_E_LABEL). */
+
+/* Permute of complex data (bst_permute_plan semantics; rank 1..7). */
+bst_status bst_permute_plan_c128(const bst_tensor* in, const char* const* new_order, bst_tensor** out_meta,
+                                 bst_plan** plan);
+
+/* Contraction of complex tensors (bst_contract_plan semantics and checks;
+ * A rank 1..7, B rank 1..6, C rank at most 7): C = sum A B with complex
+ * products.  Runs as the
+ * real grouped GEMM of A's interleaved (re, im) form with B expanded once
+ * per element into [[Br, Bi], [-Bi, Br]] (a workspace buffer of 4 * numel(B)
+ * doubles), so every form of `prec` applies to the real arithmetic. */
+bst_status bst_contract_plan_c128(const bst_tensor* A, const bst_tensor* B, bst_precision prec,
+                                  bst_tensor** C_meta, bst_plan** plan);
+
 /* ---- symmetric SVD with truncation (Sec. "Singular value decomposition":
  *      paragraphs "With truncation" and "SVD for symmetric UniTensor") ------ */
 

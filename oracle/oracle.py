@@ -35,8 +35,10 @@ Library for Tensor Networks"):
   textbook method with full classical Gram-Schmidt reorthogonalisation done
   twice, a Sturm-bisection tridiagonal eigensolve and inverse iteration)
 
-Everything is float64.  numpy matmul is used as the per-block product; there
-is no blocking, fusion or reordering beyond the definitions.
+Everything is float64 (complex128 where a tensor holds complex elements,
+Sec. "Creating a non-symmetric UniTensor", paragraph "Complex elements and
+data types").  numpy matmul is used as the per-block product; there is no
+blocking, fusion or reordering beyond the definitions.
 """
 from __future__ import annotations
 
@@ -124,7 +126,7 @@ class BlockTensor:
     blocks stored one after another in block order, each row-major."""
 
     def __init__(self, labels: Sequence[str], legs: Sequence[Leg], data: np.ndarray | None = None,
-                 sym: Sequence[int] = U1):
+                 sym: Sequence[int] = U1, dtype=None):
         if len(labels) != len(legs):
             raise LabelError("one label per leg")
         if len(set(labels)) != len(labels):
@@ -155,9 +157,15 @@ class BlockTensor:
             off += int(np.prod(sh)) if sh else 1
         self.numel = off
         self.index = {t: b for b, t in enumerate(self.blocks)}
+        # float64, or complex128 (two float64 per element, as the paper's
+        # ComplexDouble UniTensors): given, or taken from complex data
+        if dtype is None:
+            dtype = np.complex128 if data is not None and np.iscomplexobj(data) else np.float64
+        if np.dtype(dtype) not in (np.dtype(np.float64), np.dtype(np.complex128)):
+            raise OracleError("element type is float64 or complex128")
         if data is None:
-            data = np.zeros(self.numel)
-        data = np.asarray(data, dtype=np.float64)
+            data = np.zeros(self.numel, dtype=dtype)
+        data = np.asarray(data, dtype=dtype)
         if data.shape != (self.numel,):
             raise OracleError("data length does not match the block structure")
         self.data = data
@@ -207,7 +215,7 @@ class BlockTensor:
 # without symmetries": convert_from, with and without force)
 # --------------------------------------------------------------------------
 def embed(T: BlockTensor) -> np.ndarray:
-    dense = np.zeros(T.dims())
+    dense = np.zeros(T.dims(), dtype=T.data.dtype)
     so = T.sector_offsets()
     for b, t in enumerate(T.blocks):
         sl = tuple(slice(so[i][k], so[i][k] + T.shapes[b][i]) for i, k in enumerate(t))
@@ -273,7 +281,7 @@ def permute(T: BlockTensor, order: Sequence) -> BlockTensor:
             raise LabelError("unknown label in permutation")
     if sorted(perm) != list(range(T.rank)):
         raise LabelError("not a permutation of the legs")
-    out = BlockTensor([T.labels[p] for p in perm], [T.legs[p] for p in perm], sym=T.sym)
+    out = BlockTensor([T.labels[p] for p in perm], [T.legs[p] for p in perm], sym=T.sym, dtype=T.data.dtype)
     for b, t in enumerate(T.blocks):
         nt = tuple(t[p] for p in perm)
         out.block(out.index[nt])[...] = np.transpose(T.block(b), perm)
@@ -310,7 +318,8 @@ def contract(A: BlockTensor, B: BlockTensor) -> BlockTensor:
     af = [i for i in range(A.rank) if i not in ac]
     bf = [j for j in range(B.rank) if j not in bc]
     C = BlockTensor([A.labels[i] for i in af] + [B.labels[j] for j in bf],
-                    [A.legs[i] for i in af] + [B.legs[j] for j in bf], sym=A.sym)
+                    [A.legs[i] for i in af] + [B.legs[j] for j in bf], sym=A.sym,
+                    dtype=np.result_type(A.data, B.data))
     by_kc: Dict[Tuple[int, ...], List[int]] = {}
     for b, t in enumerate(B.blocks):
         by_kc.setdefault(tuple(t[j] for j in bc), []).append(b)
@@ -394,7 +403,7 @@ def network_contract(tensors: Dict[str, BlockTensor], tree, out_labels: Sequence
 # L -> psi -> W1 -> W2 -> R.
 # --------------------------------------------------------------------------
 def relabel(T: BlockTensor, labels: Sequence[str]) -> BlockTensor:
-    return BlockTensor(labels, T.legs, T.data, sym=T.sym)
+    return BlockTensor(labels, T.legs, T.data, sym=T.sym, dtype=T.data.dtype)
 
 
 def heff_apply(L: BlockTensor, W1: BlockTensor, W2: BlockTensor, R: BlockTensor,
@@ -809,8 +818,10 @@ def svd_truncate(T: BlockTensor, rowrank: int, keepdim: int, err: float = 0.0,
 # environment grows by one site.
 # --------------------------------------------------------------------------
 def dagger(T: BlockTensor) -> BlockTensor:
-    """The same real data with every leg's direction reversed (conjugate)."""
-    return BlockTensor(T.labels, [(-d, secs) for d, secs in T.legs], T.data.copy(), sym=T.sym)
+    """Every leg's direction reversed and the elements complex-conjugated
+    (UniTensor.Dagger, Sec. "Change the bond direction")."""
+    return BlockTensor(T.labels, [(-d, secs) for d, secs in T.legs], np.conj(T.data), sym=T.sym,
+                       dtype=T.data.dtype)
 
 
 def left_env_update(L: BlockTensor, A: BlockTensor, W: BlockTensor) -> BlockTensor:

@@ -36,6 +36,7 @@ EXPORTS = [
     "bst_network_order", "bst_plan_record_tiles", "bst_execute_static", "bst_calib_grid", "bst_calib_copy", "bst_calib_read", "bst_calib_mfma",
     "bst_svd_plan", "bst_svd_info", "bst_svd_sector", "bst_svd_execute", "bst_svd_truncate",
     "bst_svd_factors", "bst_svd_write", "bst_svd_forget_workspace", "bst_svd_destroy",
+    "bst_permute_plan_c128", "bst_contract_plan_c128",
 ]
 
 
@@ -126,6 +127,8 @@ def _load():
         "bst_svd_write": [vp, P(i64), i32, vp, vp, vp, vp, vp],
         "bst_svd_forget_workspace": [vp],
         "bst_svd_destroy": [vp],
+        "bst_permute_plan_c128": [vp, P(C.c_char_p), P(vp), P(vp)],
+        "bst_contract_plan_c128": [vp, vp, C.c_int, P(vp), P(vp)],
     })
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -432,19 +435,25 @@ class Plan:
         return [(st[k]["name"], ms[k]) for k in range(n.value)]
 
 
-def permute_plan(T: Tensor, order: Sequence[str]):
+def permute_plan(T: Tensor, order: Sequence[str], dtype: str = "f64"):
+    """dtype "c128": complex data, two float64 per element (buffers of
+    2 * numel doubles, e.g. torch.view_as_real(x).reshape(-1))."""
     labs = (C.c_char_p * max(len(order), 1))(*[l.encode() for l in order])
     h, p = C.c_void_p(), C.c_void_p()
-    _check(_lib.bst_permute_plan(T.handle, labs, C.byref(h), C.byref(p)))
+    f = _lib.bst_permute_plan_c128 if dtype == "c128" else _lib.bst_permute_plan
+    _check(f(T.handle, labs, C.byref(h), C.byref(p)))
     out = Tensor(None, None, _handle=h)
-    return out, Plan(p, 1, 1, [T.numel], [out.numel])
+    w = 2 if dtype == "c128" else 1
+    return out, Plan(p, 1, 1, [w * T.numel], [w * out.numel])
 
 
-def contract_plan(A: Tensor, B: Tensor, prec="fp64"):
+def contract_plan(A: Tensor, B: Tensor, prec="fp64", dtype: str = "f64"):
     h, p = C.c_void_p(), C.c_void_p()
-    _check(_lib.bst_contract_plan(A.handle, B.handle, _prec(prec), C.byref(h), C.byref(p)))
+    f = _lib.bst_contract_plan_c128 if dtype == "c128" else _lib.bst_contract_plan
+    _check(f(A.handle, B.handle, _prec(prec), C.byref(h), C.byref(p)))
     out = Tensor(None, None, _handle=h)
-    return out, Plan(p, 2, 1, [A.numel, B.numel], [out.numel])
+    w = 2 if dtype == "c128" else 1
+    return out, Plan(p, 2, 1, [w * A.numel, w * B.numel], [w * out.numel])
 
 
 def heff_plan(L: Tensor, W1: Tensor, W2: Tensor, R: Tensor, psi: Tensor, prec="fp64") -> Plan:

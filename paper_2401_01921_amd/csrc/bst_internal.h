@@ -212,6 +212,26 @@ struct GemmLaunch {
 hipError_t launch_gemm(const GemmLaunch& g, hipStream_t s);
 hipError_t launch_gemm_direct(const GemmLaunch& g, int bm, int bn, hipStream_t s);
 
+// Complex contraction: one block of B (complex, [K x N] with K the
+// contracted and N the free extent) expanded into the real block
+// [K x 2 x N x 2] = [[Br, Bi], [-Bi, Br]] per element, so that the real
+// product of A's interleaved (re, im) rows with it gives C interleaved.
+struct ExpandJob {
+  int64_t in_off, out_off;   // float64 offsets
+  int32_t in_buf, out_buf;
+  int32_t K, N;
+};
+struct ExpandWork {
+  int32_t job, start;        // 4096 complex elements of a job per workgroup
+};
+struct ExpandLaunch {
+  const ExpandJob* jobs;
+  const ExpandWork* work;
+  void* const* ptrs;
+  int64_t nwork;
+};
+hipError_t launch_expand(const ExpandLaunch& l, hipStream_t s);
+
 struct PermLaunch {
   const PermJob* jobs;
   const PermWork* work;

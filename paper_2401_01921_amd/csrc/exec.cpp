@@ -216,6 +216,12 @@ void run_steps_impl(PlanData& P, void* ws, void* const* dptrs, bst_precision pre
         e = launch_gemm(g, s);
         break;
       }
+      case StepKind::Expand: {
+        ExpandLaunch xl{reinterpret_cast<const ExpandJob*>(blob + st.off0),
+                        reinterpret_cast<const ExpandWork*>(blob + st.off1), dptrs, st.n0};
+        e = launch_expand(xl, s);
+        break;
+      }
       case StepKind::Permute: {
         PermLaunch pl{reinterpret_cast<const PermJob*>(blob + st.off0),
                       reinterpret_cast<const PermWork*>(blob + st.off1), dptrs, st.n0};

@@ -112,6 +112,38 @@ __global__ __launch_bounds__(256) void permute_kernel(const PermJob* __restrict_
   }
 }
 
+// Complex B operand of a complex contraction, expanded for a real GEMM:
+// element (k, n) = br + i bi becomes the 2 x 2 real block
+// out[k][c][n][c'] = [[br, bi], [-bi, br]][c][c'].
+__global__ __launch_bounds__(256) void expand_kernel(const ExpandJob* __restrict__ jobs,
+                                                     const ExpandWork* __restrict__ work,
+                                                     void* const* __restrict__ ptrs) {
+  const ExpandWork w = work[blockIdx.x];
+  const ExpandJob j = jobs[w.job];
+  const double* __restrict__ in = static_cast<const double*>(ptrs[j.in_buf]) + j.in_off;
+  double* __restrict__ out = static_cast<double*>(ptrs[j.out_buf]) + j.out_off;
+  const int64_t total = (int64_t)j.K * j.N;
+  for (int e = threadIdx.x; e < 4096; e += 256) {
+    const int64_t idx = (int64_t)w.start + e;
+    if (idx >= total) break;
+    const int64_t k = idx / j.N, n = idx % j.N;
+    const double br = in[2 * idx], bi = in[2 * idx + 1];
+    double* o0 = out + ((k * 2) * j.N + n) * 2;
+    double* o1 = out + ((k * 2 + 1) * j.N + n) * 2;
+    o0[0] = br;
+    o0[1] = bi;
+    o1[0] = -bi;
+    o1[1] = br;
+  }
+}
+
+hipError_t launch_expand(const ExpandLaunch& l, hipStream_t s) {
+  if (l.nwork <= 0) return hipSuccess;
+  if (l.nwork > 0x7FFFFFFF) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(expand_kernel, dim3((unsigned)l.nwork), dim3(256), 0, s, l.jobs, l.work, l.ptrs);
+  return hipGetLastError();
+}
+
 hipError_t launch_permute(const PermLaunch& p, hipStream_t s) {
   if (p.nwork <= 0) return hipSuccess;
   if (p.nwork > 0x7FFFFFFF) return hipErrorInvalidValue;

@@ -287,6 +287,150 @@ static void contract_plan(const TensorDesc& A, const TensorDesc& B, PlanData& P,
 }
 
 // ------------------------------------------------------------------------
+// Complex float64 data (Sec. "Creating a non-symmetric UniTensor",
+// paragraph "Complex elements and data types"; App. "Quantum Circuit
+// Simulation" works on complex tensors).  A complex tensor
+// stores each element as two float64, real then imaginary: its flat buffer
+// is that of the real tensor with one more, fastest leg of dim 2 (charge 0).
+// A permute keeps that leg last.  A contraction A.B is the real contraction
+// of A in that interleaved form with B expanded element by element into the
+// 2 x 2 block [[Br, Bi], [-Bi, Br]] (legs: B's contracted legs, the re/im leg
+// that meets A's, B's free legs, the output's re/im leg), which gives C in
+// the interleaved form: sum_k (Ar Br - Ai Bi, Ar Bi + Ai Br).
+// ------------------------------------------------------------------------
+static const char* const kReLabel = "#re";
+static const char* const kReOutLabel = "#re'";
+
+static LegDesc reim_leg(const LegDesc& like, int dir, const char* label) {
+  LegDesc l;
+  l.dir = dir;
+  l.sym = like.sym;
+  l.q = {0};
+  for (int c = 1; c < like.nsym(); ++c) l.qx.push_back(0);
+  l.g = {2};
+  l.label = label;
+  return l;
+}
+
+static void check_complex(const TensorDesc& T, int max_rank) {
+  if (T.rank() < 1) fail(BST_E_INVALID, "complex tensors need rank >= 1");
+  if (T.rank() > max_rank)
+    fail(BST_E_INVALID, "complex tensors of this operation are limited to rank " + std::to_string(max_rank));
+  for (const auto& l : T.legs)
+    if (l.label.compare(0, 3, "#re") == 0) fail(BST_E_LABEL, "labels starting with '#re' are reserved");
+}
+
+static std::unique_ptr<TensorDesc> with_reim(const TensorDesc& T) {
+  std::vector<LegDesc> legs = T.legs;
+  legs.push_back(reim_leg(T.legs[0], 1, kReLabel));
+  return make_tensor(std::move(legs));
+}
+
+static void permute_c128_plan(const TensorDesc& T, const std::vector<int>& perm, PlanData& P,
+                              std::unique_ptr<TensorDesc>& out) {
+  check_complex(T, kMaxRank - 1);
+  auto Tr = with_reim(T);
+  std::vector<int> pr = perm;
+  pr.push_back(T.rank());
+  auto Or = permuted_desc(*Tr, pr);
+  P.kind = 0;
+  P.in_slots = {0};
+  P.out_slots = {1};
+  P.in_numel = {Tr->numel};
+  P.out_numel = {Or->numel};
+  P.nslots = 2;
+  Step st;
+  st.kind = StepKind::Permute;
+  st.name = "permute";
+  add_permute_jobs(st, *Tr, *Or, pr, 0, 1);
+  P.steps.push_back(std::move(st));
+  out = permuted_desc(T, perm);
+}
+
+static void contract_c128_plan(const TensorDesc& A, const TensorDesc& B, PlanData& P,
+                               std::unique_ptr<TensorDesc>& Cout) {
+  check_complex(A, kMaxRank - 1);
+  check_complex(B, kMaxRank - 2);
+  std::vector<int> ac, bc, bf;
+  for (int i = 0; i < A.rank(); ++i) {
+    const int j = B.label_index(A.legs[i].label);
+    if (j < 0) continue;
+    check_contractible(A.legs[i], B.legs[j], A.legs[i].label);
+    ac.push_back(i);
+    bc.push_back(j);
+  }
+  for (int j = 0; j < B.rank(); ++j)
+    if (std::find(bc.begin(), bc.end(), j) == bc.end()) bf.push_back(j);
+  const int nc = (int)bc.size();
+  if (A.rank() + B.rank() - 2 * nc + 1 > kMaxRank)
+    fail(BST_E_INVALID, "complex contraction output limited to rank " + std::to_string(kMaxRank - 1));
+  // B in [contracted (A's order).., free..] order, then expanded
+  std::vector<int> permB = bc;
+  permB.insert(permB.end(), bf.begin(), bf.end());
+  auto Bp = permuted_desc(B, permB);
+  std::vector<LegDesc> xl(Bp->legs.begin(), Bp->legs.begin() + nc);
+  xl.push_back(reim_leg(B.legs[0], -1, kReLabel));
+  xl.insert(xl.end(), Bp->legs.begin() + nc, Bp->legs.end());
+  xl.push_back(reim_leg(B.legs[0], -1, kReOutLabel));
+  auto Bx = make_tensor(std::move(xl));
+  auto Ar = with_reim(A);
+  std::unique_ptr<TensorDesc> Cr;
+  contract_plan(*Ar, *Bx, P, Cr);   // slots: 0 A (interleaved), 1 B', 2 C (interleaved)
+  for (const auto& st : P.steps)
+    if (st.name == "pack_b") fail(BST_E_INVALID, "internal: expanded B is not in GEMM order");
+  std::vector<Step> pre;
+  int src = 1;
+  bool ident = true;
+  for (int i = 0; i < (int)permB.size(); ++i) ident = ident && permB[i] == i;
+  if (!ident) {
+    auto Br = with_reim(B);
+    std::vector<int> pr = permB;
+    pr.push_back(B.rank());
+    auto Bpr = permuted_desc(*Br, pr);
+    Step st;
+    st.kind = StepKind::Permute;
+    st.name = "pack_b";
+    src = P.nslots++;
+    P.internals.push_back({src, (size_t)Bpr->numel * 8, 0});
+    add_permute_jobs(st, *Br, *Bpr, pr, 1, src);
+    pre.push_back(std::move(st));
+  }
+  Step ex;
+  ex.kind = StepKind::Expand;
+  ex.name = "expand_b";
+  const int xslot = P.nslots++;
+  P.internals.push_back({xslot, (size_t)Bx->numel * 8, 0});
+  std::vector<int32_t> xt(Bx->rank());
+  for (int64_t b = 0; b < Bp->nblocks; ++b) {
+    const int32_t* t = Bp->block_qn(b);
+    const int64_t* sh = Bp->block_shape(b);
+    int64_t K = 1, N = 1;
+    for (int i = 0; i < nc; ++i) K *= sh[i];
+    for (int i = nc; i < Bp->rank(); ++i) N *= sh[i];
+    if (K > 0x7FFFFFFF || N > 0x7FFFFFFF) fail(BST_E_INVALID, "block too large");
+    for (int i = 0; i < nc; ++i) xt[i] = t[i];
+    xt[nc] = 0;
+    for (int i = nc; i < Bp->rank(); ++i) xt[i + 1] = t[i];
+    xt[Bx->rank() - 1] = 0;
+    const int64_t xb = Bx->find(xt.data());
+    if (xb < 0) fail(BST_E_INVALID, "internal: expanded block missing");
+    const int32_t jid = (int32_t)ex.xjobs.size();
+    ex.xjobs.push_back({2 * Bp->offset[b], Bx->offset[xb], src, xslot, (int32_t)K, (int32_t)N});
+    for (int64_t st0 = 0; st0 < K * N; st0 += 4096) ex.xwork.push_back({jid, (int32_t)st0});
+  }
+  ex.bytes = ex.bytes32 = 16.0 * (double)Bp->numel + 32.0 * (double)Bp->numel;
+  pre.push_back(std::move(ex));
+  // the contraction now reads B' from its internal slot
+  for (auto& st : P.steps)
+    for (auto& g : st.segs)
+      if (g.b_buf == 1) g.b_buf = xslot;
+  P.steps.insert(P.steps.begin(), std::make_move_iterator(pre.begin()), std::make_move_iterator(pre.end()));
+  P.in_numel = {Ar->numel, 2 * B.numel};
+  std::vector<LegDesc> cl(Cr->legs.begin(), Cr->legs.end() - 1);
+  Cout = make_tensor(std::move(cl));
+}
+
+// ------------------------------------------------------------------------
 // Two-site H_eff (Sec. "Benchmarks", Fig. Hpsi_fig)
 // ------------------------------------------------------------------------
 // Dense index -> (sector, index in sector) of a leg.
@@ -1267,6 +1411,11 @@ void finalize(PlanData& P) {
         }
         break;
       }
+      case StepKind::Expand:
+        st.off0 = put(P.blob, st.xjobs);
+        st.off1 = put(P.blob, st.xwork);
+        st.n0 = (int64_t)st.xwork.size();
+        break;
       case StepKind::Permute:
         st.off0 = put(P.blob, st.jobs);
         st.off1 = put(P.blob, st.pwork);
@@ -1424,6 +1573,59 @@ bst_status bst_contract_plan(const bst_tensor* A, const bst_tensor* B, bst_preci
   auto* p = new_plan();
   try {
     contract_plan(*desc_of(A), *desc_of(B), p->p, C);
+    p->p.prec = prec;
+    finalize(p->p);
+    apply_tune_cache(p->p);
+  } catch (...) {
+    delete p;
+    throw;
+  }
+  *plan = p;
+  *C_meta = wrap_tensor(std::move(C));
+  BST_CATCH
+}
+
+bst_status bst_permute_plan_c128(const bst_tensor* in, const char* const* new_order, bst_tensor** out_meta,
+                                 bst_plan** plan) {
+  BST_TRY
+  if (!in || !out_meta || !plan || !new_order) fail(BST_E_INVALID, "null argument");
+  *out_meta = nullptr;
+  *plan = nullptr;
+  const TensorDesc& T = *desc_of(in);
+  std::vector<int> perm;
+  for (int i = 0; i < T.rank(); ++i) {
+    if (!new_order[i]) fail(BST_E_LABEL, "null label");
+    const int k = T.label_index(new_order[i]);
+    if (k < 0) fail(BST_E_LABEL, std::string("unknown label '") + new_order[i] + "'");
+    if (std::find(perm.begin(), perm.end(), k) != perm.end())
+      fail(BST_E_LABEL, std::string("label listed twice '") + new_order[i] + "'");
+    perm.push_back(k);
+  }
+  std::unique_ptr<TensorDesc> out;
+  auto* p = new_plan();
+  try {
+    permute_c128_plan(T, perm, p->p, out);
+    finalize(p->p);
+  } catch (...) {
+    delete p;
+    throw;
+  }
+  *plan = p;
+  *out_meta = wrap_tensor(std::move(out));
+  BST_CATCH
+}
+
+bst_status bst_contract_plan_c128(const bst_tensor* A, const bst_tensor* B, bst_precision prec,
+                                  bst_tensor** C_meta, bst_plan** plan) {
+  BST_TRY
+  if (!A || !B || !C_meta || !plan) fail(BST_E_INVALID, "null argument");
+  *C_meta = nullptr;
+  *plan = nullptr;
+  if (prec < BST_FP64 || prec > BST_BF16X6) fail(BST_E_INVALID, "unknown precision");
+  std::unique_ptr<TensorDesc> C;
+  auto* p = new_plan();
+  try {
+    contract_c128_plan(*desc_of(A), *desc_of(B), p->p, C);
     p->p.prec = prec;
     finalize(p->p);
     apply_tune_cache(p->p);

@@ -32,7 +32,7 @@ const TensorDesc* desc_of(const bst_tensor* t);
 bst_tensor* wrap_tensor(std::unique_ptr<TensorDesc> d);
 void set_last_error(const std::string& s);
 
-enum class StepKind { Permute, Gemm, HCoef, HApply, Split };
+enum class StepKind { Permute, Gemm, HCoef, HApply, Split, Expand };
 
 // Element type of a step operand: fixed, or the plan's intermediate type
 // (float64 for BST_FP64, float32 for the other forms).
@@ -54,6 +54,9 @@ struct Step {
   // Permute
   std::vector<PermJob> jobs;
   std::vector<PermWork> pwork;
+  // Expand (complex contraction)
+  std::vector<ExpandJob> xjobs;
+  std::vector<ExpandWork> xwork;
   // HCoef / HApply (paired: the apply uses the coefficients of the coef step)
   struct RawTerm {
     int32_t cls, o, i;

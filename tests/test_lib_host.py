@@ -268,3 +268,33 @@ def test_binding_fails_loudly_without_library(tmp_path):
                        text=True, timeout=120, env=env)
     assert r.returncode == 0, r.stdout + r.stderr
     assert "not built" in r.stdout
+
+
+def test_complex_plans_structure_and_errors():
+    """Complex plans: output descriptors equal the float64 ones, buffers are
+    two float64 per element, reserved labels and rank limits are refused."""
+    rng = np.random.default_rng(12)
+    A, B = _random_pair(rng, 3, 3, 2)
+    tA, tB = bst.Tensor(A.labels, A.legs), bst.Tensor(B.labels, B.legs)
+    tC, plan = bst.contract_plan(tA, tB, "fp64", dtype="c128")
+    rC, rplan = bst.contract_plan(tA, tB, "fp64")
+    assert tC.table() == rC.table() and tC.labels == rC.labels
+    assert plan.in_numel == [2 * tA.numel, 2 * tB.numel] and plan.out_numel == [2 * tC.numel]
+    assert plan.stats().flops == pytest.approx(4 * rplan.stats().flops)
+    tP, pplan = bst.permute_plan(tA, list(reversed(tA.labels)), dtype="c128")
+    assert pplan.in_numel == [2 * tA.numel]
+    with pytest.raises(bst.BstError) as e:
+        bst.permute_plan(bst.Tensor(["#re", "x"], [(1, [(0, 2)]), (-1, [(0, 2)])]), ["x", "#re"], dtype="c128")
+    assert e.value.status == "E_LABEL"
+    big = bst.Tensor([f"l{i}" for i in range(8)], [(1, [(0, 1)])] * 8)
+    with pytest.raises(bst.BstError) as e:
+        bst.permute_plan(big, [f"l{i}" for i in range(8)], dtype="c128")
+    assert e.value.status == "E_INVALID"
+
+
+def test_complex_output_rank_limit():
+    A = bst.Tensor([f"a{i}" for i in range(4)], [(1, [(0, 1)])] * 4)
+    B = bst.Tensor([f"b{i}" for i in range(4)], [(1, [(0, 1)])] * 4)
+    with pytest.raises(bst.BstError) as e:
+        bst.contract_plan(A, B, "fp64", dtype="c128")
+    assert e.value.status == "E_INVALID" and "rank 7" in str(e.value)
