@@ -169,6 +169,14 @@ struct SplitJob {
 struct SplitWork {
   int32_t job, r0, c0, pad;
 };
+// A split work item with its job's fields copied in (the kernel's table:
+// one dependent read fewer before the first data load).
+struct SplitItem {
+  int64_t in_off, out_off;
+  int32_t in_buf, out_buf;
+  int32_t rows, cols, out_ld, transpose;
+  int32_t r0, c0;
+};
 struct HPlane {
   int64_t off;               // element offset of (row 0, col 0)
   int64_t rowstride;
@@ -259,8 +267,7 @@ hipError_t launch_hcoef(const HCoefLaunch& c, hipStream_t s);
 struct SplitLaunch {
   int np;
   bool in_f32 = false;         // the input blocks are float32 (a float32 Krylov row)
-  const SplitJob* jobs;
-  const SplitWork* work;
+  const SplitItem* items;
   void* const* ptrs;
   int64_t nwork;
 };

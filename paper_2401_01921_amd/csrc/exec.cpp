@@ -151,8 +151,7 @@ void run_steps_impl(PlanData& P, void* ws, void* const* dptrs, bst_precision pre
         SplitLaunch l{};
         l.np = np;
         l.in_f32 = st.reads_psi && P.psi_f32;
-        l.jobs = reinterpret_cast<const SplitJob*>(blob + st.off0);
-        l.work = reinterpret_cast<const SplitWork*>(blob + st.off1);
+        l.items = reinterpret_cast<const SplitItem*>(blob + st.off0);
         l.ptrs = dptrs;
         l.nwork = st.n0;
         e = launch_split(l, s);

@@ -43,15 +43,18 @@ __device__ __forceinline__ void split_planes(float a, unsigned short* h) {
 // float64 blocks -> bfloat16 planes (optionally transposed), 64x64 tiles
 // ------------------------------------------------------------------------
 template <int NP, typename TI>
-__global__ __launch_bounds__(256) void split_kernel(const SplitJob* __restrict__ jobs,
-                                                    const SplitWork* __restrict__ work,
+__global__ __launch_bounds__(256) void split_kernel(const SplitItem* __restrict__ items,
                                                     void* const* __restrict__ ptrs) {
   // One 64 x 64 tile of the output per workgroup; every lane converts 8
   // consecutive output elements and writes them as one 16-byte vector per
-  // plane (output rows are padded to 8, so the vectors are aligned).
-  __shared__ TI tile[64][65];   // input type: a float32 tile leaves room for 8 workgroups per CU
-  const SplitWork w = work[blockIdx.x];
-  const SplitJob j = jobs[w.job];
+  // plane (output rows are padded to 8, so the vectors are aligned).  A
+  // transposed tile is staged in LDS already split: two planes pack into
+  // one 32-bit word (half the LDS of a float64 tile, so twice the
+  // workgroups per CU), three planes and plain float64 copies stage the
+  // input value.
+  using TS = typename std::conditional<NP == 2, uint32_t, TI>::type;
+  __shared__ TS tile[64][65];
+  const SplitItem j = items[blockIdx.x];
   const BST_G TI* __restrict__ in = (const BST_G TI*)(ptrs[j.in_buf]) + j.in_off;
   BST_G unsigned short* __restrict__ out = (BST_G unsigned short*)(ptrs[j.out_buf]);
   const int tid = threadIdx.x;
@@ -60,7 +63,7 @@ __global__ __launch_bounds__(256) void split_kernel(const SplitJob* __restrict__
     // output [rows x out_ld]: rows r0.., columns c0.. (zeros past cols)
 #pragma unroll
     for (int pass = 0; pass < 2; ++pass) {
-      const int r = w.r0 + orow + 32 * pass, c = w.c0 + ocol;
+      const int r = j.r0 + orow + 32 * pass, c = j.c0 + ocol;
       if (r < j.rows && c < j.out_ld) {
         if constexpr (NP == 1) {   // float64 copy into the padded layout
           dbl4 v[2];
@@ -87,34 +90,54 @@ __global__ __launch_bounds__(256) void split_kernel(const SplitJob* __restrict__
     }
     return;
   }
-  // transposed: input [rows x cols] -> output [cols x out_ld], out_ld >= rows
-  for (int e = tid; e < 64 * 64; e += 256) {
-    const int r = e / 64, c = e % 64;
-    const int gr = w.r0 + r, gc = w.c0 + c;
-    tile[r][c] = (gr < j.rows && gc < j.cols) ? in[(int64_t)gr * j.cols + gc] : (TI)0;
+  // transposed: input [rows x cols] -> output [cols x out_ld], out_ld >= rows;
+  // all sixteen loads of a lane in flight before the first LDS store
+  TI v[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int e = tid + 256 * i;
+    const int gr = j.r0 + (e >> 6), gc = j.c0 + (e & 63);
+    v[i] = (gr < j.rows && gc < j.cols) ? in[(int64_t)gr * j.cols + gc] : (TI)0;
+  }
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int e = tid + 256 * i;
+    if constexpr (NP == 2) {
+      unsigned short t[3];
+      split_planes<2>(v[i], t);
+      tile[e >> 6][e & 63] = (uint32_t)t[0] | ((uint32_t)t[1] << 16);
+    } else {
+      tile[e >> 6][e & 63] = v[i];
+    }
   }
   __syncthreads();
 #pragma unroll
   for (int pass = 0; pass < 2; ++pass) {
     const int c = orow + 32 * pass;          // output row = input column
-    const int gc = w.c0 + c, gr = w.r0 + ocol;
+    const int gc = j.c0 + c, gr = j.r0 + ocol;
     if (gc < j.cols && gr < j.out_ld) {
       if constexpr (NP == 1) {
-        dbl4 v[2];
+        dbl4 o8[2];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) v[e >> 2][e & 3] = (double)tile[ocol + e][c];
+        for (int e = 0; e < 8; ++e) o8[e >> 2][e & 3] = (double)tile[ocol + e][c];
         BST_G dbl4* o = (BST_G dbl4*)((BST_G double*)(ptrs[j.out_buf]) + j.out_off + (int64_t)gc * j.out_ld + gr);
-        o[0] = v[0];
-        o[1] = v[1];
+        o[0] = o8[0];
+        o[1] = o8[1];
         continue;
       }
       us8 h[3];
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
-        unsigned short t[3];
-        split_planes<NP>(tile[ocol + e][c], t);
+        if constexpr (NP == 2) {
+          const uint32_t u = tile[ocol + e][c];
+          h[0][e] = (unsigned short)(u & 0xFFFFu);
+          h[1][e] = (unsigned short)(u >> 16);
+        } else {
+          unsigned short t[3];
+          split_planes<NP>(tile[ocol + e][c], t);
 #pragma unroll
-        for (int q = 0; q < NP; ++q) h[q][e] = t[q];
+          for (int q = 0; q < NP; ++q) h[q][e] = t[q];
+        }
       }
       const int64_t pos = j.out_off + (int64_t)gc * j.out_ld + gr;   // a multiple of 8
 #pragma unroll
@@ -128,15 +151,15 @@ hipError_t launch_split(const SplitLaunch& l, hipStream_t s) {
   if (l.nwork > 0x7FFFFFFF) return hipErrorInvalidValue;
   const dim3 grid((unsigned)l.nwork), block(256);
   if (l.np == 1 && !l.in_f32)
-    hipLaunchKernelGGL((split_kernel<1, double>), grid, block, 0, s, l.jobs, l.work, l.ptrs);
+    hipLaunchKernelGGL((split_kernel<1, double>), grid, block, 0, s, l.items, l.ptrs);
   else if (l.np == 2 && !l.in_f32)
-    hipLaunchKernelGGL((split_kernel<2, double>), grid, block, 0, s, l.jobs, l.work, l.ptrs);
+    hipLaunchKernelGGL((split_kernel<2, double>), grid, block, 0, s, l.items, l.ptrs);
   else if (l.np == 2)
-    hipLaunchKernelGGL((split_kernel<2, float>), grid, block, 0, s, l.jobs, l.work, l.ptrs);
+    hipLaunchKernelGGL((split_kernel<2, float>), grid, block, 0, s, l.items, l.ptrs);
   else if (l.np == 3 && !l.in_f32)
-    hipLaunchKernelGGL((split_kernel<3, double>), grid, block, 0, s, l.jobs, l.work, l.ptrs);
+    hipLaunchKernelGGL((split_kernel<3, double>), grid, block, 0, s, l.items, l.ptrs);
   else if (l.np == 3)
-    hipLaunchKernelGGL((split_kernel<3, float>), grid, block, 0, s, l.jobs, l.work, l.ptrs);
+    hipLaunchKernelGGL((split_kernel<3, float>), grid, block, 0, s, l.items, l.ptrs);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

@@ -1476,9 +1476,17 @@ void finalize(PlanData& P) {
         break;
       }
       case StepKind::Split:
-        st.off0 = put(P.blob, st.sjobs);
-        st.off1 = put(P.blob, st.swork);
-        st.n0 = (int64_t)st.swork.size();
+      {
+        std::vector<SplitItem> items;
+        items.reserve(st.swork.size());
+        for (const auto& w : st.swork) {
+          const SplitJob& j = st.sjobs[w.job];
+          items.push_back({j.in_off, j.out_off, j.in_buf, j.out_buf, j.rows, j.cols, j.out_ld, j.transpose, w.r0,
+                           w.c0});
+        }
+        st.off0 = put(P.blob, items);
+        st.n0 = (int64_t)items.size();
+      }
         break;
     }
   }
