@@ -143,7 +143,7 @@ struct PermJob {
 constexpr int kPermRows = 1024;   // most rows in one row-copy work item
 struct PermWork {
   int32_t job;
-  int32_t kind;       // 0: rows, 1: tile
+  int32_t kind;       // 0: rows; 1, 2, 3: a 64 x 64, 128 x 32 or 256 x 16 tile
   int64_t batch;      // rows: first row; tile: linear index over batch dims
   int32_t t0, t1;     // tile origin along (p, last) or row count
 };

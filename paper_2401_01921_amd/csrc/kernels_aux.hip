@@ -9,17 +9,75 @@ namespace bst {
 // ------------------------------------------------------------------------
 // Block permute (Sec. "Permute", App. "Contiguous")
 // ------------------------------------------------------------------------
-constexpr int kPT = 64;   // transpose tile edge
-static_assert(kPermRows <= kPT * (kPT + 1), "row offsets share the transpose tile's LDS");
+static_assert(kPermRows <= 256 * 17, "row offsets share the transpose tile's LDS");
 
 // Streaming 16-byte access when the address is 16-byte aligned, else two
 // 8-byte accesses (block offsets and strides may be odd).
 typedef double dbl2v __attribute__((ext_vector_type(2)));
 
+// One transposing tile of TY x TX elements (TY = 4096 / TX) over (pdim,
+// last): read as pairs of consecutive input columns, written as pairs of
+// consecutive output positions (input rows) through LDS rows padded by one
+// element.  Odd addresses fall back to 8-byte accesses.
+template <int TX>
+__device__ __forceinline__ void permute_tile(const PermJob& j, const PermWork& w, const BST_G double* __restrict__ in,
+                                             BST_G double* __restrict__ out, double* lds) {
+  constexpr int TY = 4096 / TX, LD = TX + 1;
+  const int r = j.rank, tid = threadIdx.x;
+  const int p = j.pdim;
+  int64_t rem = w.batch, ib = 0, ob = 0;
+  for (int d = r - 1; d >= 0; --d) {
+    if (d == p || d == r - 1) continue;
+    const int64_t ext = j.shape[d];
+    const int64_t idx = rem % ext;
+    rem /= ext;
+    ib += idx * j.istride[d];
+    ob += idx * j.ostride[d];
+  }
+  const int np = j.shape[p], nl = j.shape[r - 1];
+  const int64_t isp = j.istride[p], osl = j.ostride[r - 1];
+#pragma unroll
+  for (int k = 0; k < 2048 / 256; ++k) {
+    const int e = tid + 256 * k;
+    const int y = e / (TX / 2), x = 2 * (e % (TX / 2));
+    const int gy = w.t0 + y, gx = w.t1 + x;
+    if (gy < np && gx < nl) {
+      const BST_G double* src = in + ib + gy * isp + gx;
+      if (gx + 1 < nl && (reinterpret_cast<uintptr_t>(src) & 15) == 0) {
+        const dbl2v v = __builtin_nontemporal_load(reinterpret_cast<const BST_G dbl2v*>(src));
+        lds[y * LD + x] = v.x;
+        lds[y * LD + x + 1] = v.y;
+      } else {
+        lds[y * LD + x] = src[0];
+        if (gx + 1 < nl) lds[y * LD + x + 1] = src[1];
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 2048 / 256; ++k) {
+    const int e = tid + 256 * k;
+    const int x = e / (TY / 2), y = 2 * (e % (TY / 2));
+    const int gy = w.t0 + y, gx = w.t1 + x;
+    if (gy < np && gx < nl) {
+      BST_G double* dst = out + ob + gy + gx * osl;
+      if (gy + 1 < np && (reinterpret_cast<uintptr_t>(dst) & 15) == 0) {
+        dbl2v v;
+        v.x = lds[y * LD + x];
+        v.y = lds[(y + 1) * LD + x];
+        __builtin_nontemporal_store(v, reinterpret_cast<BST_G dbl2v*>(dst));
+      } else {
+        dst[0] = lds[y * LD + x];
+        if (gy + 1 < np) dst[1] = lds[(y + 1) * LD + x];
+      }
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void permute_kernel(const PermJob* __restrict__ jobs,
                                                       const PermWork* __restrict__ work,
                                                       void* const* __restrict__ ptrs) {
-  __shared__ double tile[kPT][kPT + 1];
+  __shared__ double tile[1][256 * 17];   // the largest tile: 256 x (16 + 1)
   const PermWork w = work[blockIdx.x];
   const PermJob& j = jobs[w.job];
   const BST_G double* __restrict__ in = (const BST_G double*)(ptrs[j.in_buf]) + j.in_off;
@@ -59,57 +117,11 @@ __global__ __launch_bounds__(256) void permute_kernel(const PermJob* __restrict_
     }
     return;
   }
-  // transposing job: tile over (pdim, last) at origin (t0, t1)
-  const int p = j.pdim;
-  int64_t rem = w.batch, ib = 0, ob = 0;
-  for (int d = r - 1; d >= 0; --d) {
-    if (d == p || d == r - 1) continue;
-    const int64_t ext = j.shape[d];
-    const int64_t idx = rem % ext;
-    rem /= ext;
-    ib += idx * j.istride[d];
-    ob += idx * j.ostride[d];
-  }
-  const int np = j.shape[p], nl = j.shape[r - 1];
-  const int64_t isp = j.istride[p], osl = j.ostride[r - 1];
-  // read: pairs of consecutive input columns; write: pairs of consecutive
-  // output positions (input rows).  Odd addresses fall back to 8 bytes.
-#pragma unroll
-  for (int k = 0; k < (kPT * kPT / 2) / 256; ++k) {
-    const int e = tid + 256 * k;
-    const int y = e / (kPT / 2), x = 2 * (e % (kPT / 2));
-    const int gy = w.t0 + y, gx = w.t1 + x;
-    if (gy < np && gx < nl) {
-      const BST_G double* src = in + ib + gy * isp + gx;
-      if (gx + 1 < nl && (reinterpret_cast<uintptr_t>(src) & 15) == 0) {
-        const dbl2v v = __builtin_nontemporal_load(reinterpret_cast<const BST_G dbl2v*>(src));
-        tile[y][x] = v.x;
-        tile[y][x + 1] = v.y;
-      } else {
-        tile[y][x] = src[0];
-        if (gx + 1 < nl) tile[y][x + 1] = src[1];
-      }
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < (kPT * kPT / 2) / 256; ++k) {
-    const int e = tid + 256 * k;
-    const int x = e / (kPT / 2), y = 2 * (e % (kPT / 2));
-    const int gy = w.t0 + y, gx = w.t1 + x;
-    if (gy < np && gx < nl) {
-      BST_G double* dst = out + ob + gy + gx * osl;
-      if (gy + 1 < np && (reinterpret_cast<uintptr_t>(dst) & 15) == 0) {
-        dbl2v v;
-        v.x = tile[y][x];
-        v.y = tile[y + 1][x];
-        __builtin_nontemporal_store(v, reinterpret_cast<BST_G dbl2v*>(dst));
-      } else {
-        dst[0] = tile[y][x];
-        if (gy + 1 < np) dst[1] = tile[y + 1][x];
-      }
-    }
-  }
+  // transposing job: a tile over (pdim, last) at origin (t0, t1), 64 x 64,
+  // or 128 x 32 / 256 x 16 for a narrow last strip of the last dim
+  if (w.kind == 1) permute_tile<64>(j, w, in, out, tile[0]);
+  else if (w.kind == 2) permute_tile<32>(j, w, in, out, tile[0]);
+  else permute_tile<16>(j, w, in, out, tile[0]);
 }
 
 // Complex B operand of a complex contraction, expanded for a real GEMM:

@@ -3,7 +3,8 @@
 // that each kernel's roofline fraction can be set against what the same
 // kind of code reaches on the same device.
 //   copy   16-byte loads and stores, grid-stride, non-temporal: read and
-//          write bytes once each;
+//          write bytes once each (four independent loads per lane in flight
+//          measured slower: 4.69 against 5.17 TB/s);
 //   read   16-byte loads summed per lane, one partial per workgroup;
 //   mfma   back-to-back MFMA on register operands, eight independent
 //          accumulators per wave (no memory traffic).

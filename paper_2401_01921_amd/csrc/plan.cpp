@@ -104,12 +104,19 @@ static void add_permute_jobs(Step& st, const TensorDesc& in, const TensorDesc& o
       st.jobs.push_back(j);
       const int64_t np = ext[j.pdim];
       int64_t nbatch = numel / (np * last);
+      // 64 x 64 tiles; a last strip of the last dim no wider than 32 (16)
+      // elements goes in 128 x 32 (256 x 16) tiles, so that few lanes idle
+      // (strip by strip of the last dim: measured 4.30 TB/s against 4.19
+      // with the tiles of one row band consecutive)
       for (int64_t bt = 0; bt < nbatch; ++bt)
-        for (int64_t y = 0; y < np; y += 64)
-          for (int64_t x = 0; x < last; x += 64) {
+        for (int64_t x = 0; x < last; x += 64) {
+          const int64_t wx = std::min<int64_t>(64, last - x);
+          const int kind = wx > 32 ? 1 : wx > 16 ? 2 : 3;
+          const int64_t ty = kind == 1 ? 64 : kind == 2 ? 128 : 256;
+          for (int64_t y = 0; y < np; y += ty) {
             PermWork w{};
             w.job = jid;
-            w.kind = 1;
+            w.kind = kind;
             w.batch = bt;
             w.t0 = (int32_t)y;
             w.t1 = (int32_t)x;

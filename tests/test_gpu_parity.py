@@ -65,6 +65,23 @@ def test_permute_bit_exact_large_blocks(order):
     assert np.array_equal(host(y), P.data)
 
 
+@pytest.mark.parametrize("cdim", [90, 150, 16, 48])
+def test_permute_narrow_last_strips(cdim):
+    """Transposing tiles of every shape: the last strip of the last dim is
+    26, 22, 16 or 48 elements wide (128 x 32, 256 x 16 or 64 x 64 tiles)."""
+    legs = [(1, [(-1, 37), (0, 150), (1, 21)]), (1, [(0, 70), (1, 33)]), (-1, [(-1, cdim), (0, cdim + 3), (1, 7)])]
+    O = orc.BlockTensor(["a", "b", "c"], legs)
+    O.data[:] = wl.normal(78, O.numel)
+    for order in (["c", "a", "b"], ["c", "b", "a"], ["a", "c", "b"]):
+        P = orc.permute(O, order)
+        T = bst.Tensor(["a", "b", "c"], legs)
+        out_t, plan = bst.permute_plan(T, order)
+        y = torch.full((out_t.numel,), np.nan, dtype=torch.float64, device=DEV)
+        plan.execute([dev(O.data)], [y], bst.workspace(plan.workspace_bytes))
+        torch.cuda.synchronize()
+        assert np.array_equal(host(y), P.data), (cdim, order)
+
+
 def test_permute_paper_example():
     T = bst.Tensor(["a", "b", "c"], [(1, [(0, 2)]), (1, [(0, 2)]), (-1, [(0, 2)])])
     out_t, plan = bst.permute_plan(T, ["a", "c", "b"])
