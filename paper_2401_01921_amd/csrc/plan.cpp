@@ -122,6 +122,7 @@ static void add_permute_jobs(Step& st, const TensorDesc& in, const TensorDesc& o
             w.t1 = (int32_t)x;
             st.pwork.push_back(w);
           }
+        }
     }
   }
   st.bytes += 16.0 * (double)in.numel;
