@@ -438,6 +438,10 @@ static inline int pass_grid_f32(int64_t n) {
   const int g = vec_grid((n + 1) / 2);
   return g < 512 ? g : 512;
 }
+// The float64 pass: 1024 workgroups (two rounds of resident workgroups at
+// 40 rows: 205 VGPRs, two waves per SIMD); 512, one round, measured 7%
+// slower on the 40-step chi = 4096 solve.
+static inline int pass_grid_f64(int64_t n) { return vec_grid(n); }
 
 // The Krylov basis is read through one base pointer plus a 32-bit per-lane
 // byte offset (V is below 4 GiB, checked on the host), so the row addresses
@@ -934,7 +938,7 @@ hipError_t launch_lanczos_pass(double* V, int64_t ldv, int64_t n, int j, const d
                                const double* coef, const double* dprev, const double* beta,
                                double* vnext, double* partial, double* dn, hipStream_t s) {
   if (j < 0 || j + 2 > kMaxVecs + 1 || !fits32(V, ldv, n, j + 1)) return hipErrorInvalidValue;
-  const int G = vec_grid(n);
+  const int G = pass_grid_f64(n);
   const int nv = j > 0 ? j : 1;
   BST_NV_DISPATCH(lanczos_pass_kernel, dim3(G), dim3(256), 0, s, V, (uint32_t)ldv, (uint32_t)n, j,
                   z, coef, dprev, beta, vnext, partial);
@@ -970,7 +974,7 @@ hipError_t launch_lanczos_pass(float* V, int64_t ldv, int64_t n, int j, const fl
 hipError_t launch_lanczos_pass_sums(int64_t n, int j, bool f32, const double* partial, double* dn,
                                    hipStream_t s) {
   if (j < 0 || j + 2 > kMaxVecs + 1 || n < 0) return hipErrorInvalidValue;
-  const int G = f32 ? pass_grid_f32(n) : vec_grid(n);
+  const int G = f32 ? pass_grid_f32(n) : pass_grid_f64(n);
   hipLaunchKernelGGL(reduce_partials_kernel, dim3(j + 2), dim3(256), 0, s, partial, G, dn);
   return hipGetLastError();
 }
@@ -1071,8 +1075,9 @@ hipError_t launch_scale_rnorm(const double* src, const double* norm2, float* dst
   return hipGetLastError();
 }
 
-// PAIR (float32 x and y, both 8-byte aligned, n < 2^31): two elements per
-// lane with one 8-byte load each; otherwise one element per lane.
+// PAIR (x and y of one type, aligned to two elements, n < 2^31): two
+// elements per lane with one 8-byte (float32) or 16-byte (float64) load
+// each; otherwise one element per lane.
 template <typename TX, typename TY, bool PAIR>
 __global__ __launch_bounds__(256) void dot2_kernel(const TX* __restrict__ x,
                                                    const TY* __restrict__ y, int64_t n,
@@ -1096,6 +1101,24 @@ __global__ __launch_bounds__(256) void dot2_kernel(const TX* __restrict__ x,
       acc[0] += (double)xv.y * (double)yv.y;
       acc[1] += (double)yv.x * (double)yv.x;
       acc[1] += (double)yv.y * (double)yv.y;
+    }
+  } else if constexpr (PAIR && sizeof(TX) == 8 && sizeof(TY) == 8) {
+    // float64 x and y, both 16-byte aligned: two elements per 16-byte load
+    const int64_t npair = (n + 1) / 2;
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < npair; p += stride) {
+      dbl2v xv, yv;
+      if (2 * p + 1 < n) {
+        xv = __builtin_nontemporal_load(reinterpret_cast<const dbl2v*>(x) + p);
+        yv = __builtin_nontemporal_load(reinterpret_cast<const dbl2v*>(y) + p);
+      } else {
+        xv = dbl2v{(double)x[2 * p], 0.0};
+        yv = dbl2v{(double)y[2 * p], 0.0};
+      }
+      acc[0] += xv.x * yv.x;
+      acc[0] += xv.y * yv.y;
+      acc[1] += yv.x * yv.x;
+      acc[1] += yv.y * yv.y;
     }
   } else {
     const int64_t stride = (int64_t)gridDim.x * 256;
@@ -1131,11 +1154,13 @@ static hipError_t dot_step_impl(const TX* x, const TZ* z, int64_t n, double* dpa
                                 double* alpha, double* beta, double* dprev, double* coef,
                                 double* aest, hipStream_t s) {
   if (j < 0 || j >= kMaxVecs || pj != j - 1 || n < 0) return hipErrorInvalidValue;
-  const bool pair = sizeof(TX) == 4 && sizeof(TZ) == 4 && n <= 0x7FFFFFFF &&
-                    ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(z)) & 7) == 0;
+  // two elements per lane: float32 x and z 8-byte aligned, or float64 x and
+  // z 16-byte aligned (one 8- or 16-byte load each)
+  const uintptr_t al = reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(z);
+  const bool pair = sizeof(TX) == sizeof(TZ) && n <= 0x7FFFFFFF && (al & (2 * sizeof(TX) - 1)) == 0;
   const int G = pair ? vec_grid((n + 1) / 2) : vec_grid(n);
   // the basis pass's grid: one element (float64 rows) or pair (float32) per lane
-  const int pG = sizeof(TX) == 4 ? pass_grid_f32(n) : vec_grid(n);
+  const int pG = sizeof(TX) == 4 ? pass_grid_f32(n) : pass_grid_f64(n);
   if (G > 1024 || pG > 1024) return hipErrorInvalidValue;
   if (pair)
     hipLaunchKernelGGL((dot2_kernel<TX, TZ, true>), dim3(G), dim3(256), 0, s, x, z, n, dpart);
