@@ -268,6 +268,7 @@ def main():
             "energy_rel_diff_vs_one_pass": abs(res3["energy"] - es) / abs(es)}
         extras.update(bench_extras(bst, wl, torch, dev, plan, ins_apply=[
             g["L"], g["W1"], g["W2"], g["R"], g["psi0"]], apply_flops=apply_flops))
+        extras.update(bench_widened(bst, wl, torch, dev))
 
     # ---- CPU baseline: the oracle's Lanczos solve on the host cores -------
     cpu = None
@@ -497,6 +498,115 @@ def bench_extras(bst, wl, torch, dev, plan, ins_apply, apply_flops):
         cal[key] = round(fl[0] / ms_m / 1e9, 1)
         cal[key.replace("tflops", "frac_of_peak")] = round(fl[0] / ms_m / 1e9 / peak, 4)
     out["calibration"] = cal
+    return out
+
+
+def bench_widened(bst, wl, torch, dev):
+    """The rows built beyond the H_eff path, each beside the oracle on the
+    host: the symmetric truncated SVD of a two-site state, a two-site DMRG
+    sweep of the XX chain, and a complex contraction."""
+    import math
+    from oracle import oracle as orc
+    from paper_2401_01921_amd import dmrg
+    out = {}
+    # -- Svd_truncate of a spin-1/2 two-site state, bonds chi = 256 (q in [-6, 6])
+    v = wl.gaussian_sector_dims(256, 6)
+    ph = wl.physical_sectors("1/2")
+    O = orc.BlockTensor(["a", "s1", "s2", "b"], [(1, v), (1, ph), (1, ph), (-1, v)])
+    O.data[:] = wl.normal(wl.seed_for(2, "psi", 7), O.numel)
+    T = bst.Tensor(O.labels, O.legs)
+    x = torch.from_numpy(O.data.copy()).to(dev)
+    plan = bst.Svd(T, 2)
+    ws = bst.workspace(plan.workspace_bytes)
+    shapes = [plan.sector(k)[1:] for k in range(plan.nsectors)]
+
+    def run_svd():
+        plan.execute(x, ws)
+        kept, _ = plan.truncate(256, 1e-12, None, ws)
+        Ut, Vt = plan.factors(kept, "m")
+        U = torch.empty(Ut.numel, dtype=torch.float64, device=dev)
+        Vd = torch.empty(Vt.numel, dtype=torch.float64, device=dev)
+        S = torch.empty(sum(kept), dtype=torch.float64, device=dev)
+        plan.write(kept, 2, U, S, Vd, ws)
+        return S
+    ms_svd = _time_ms(torch, run_svd, 5)
+    S = run_svd().cpu().numpy()
+    t0 = time.perf_counter()
+    ou, os_, ov, _ = orc.svd_truncate(O, 2, 256, 1e-12, bond="m", absorb="v")
+    cpu_ms = (time.perf_counter() - t0) * 1e3
+    ref = np.concatenate(os_)
+    out["svd_truncate"] = {
+        "workload": "two-site spin-1/2 state, chi = 256 bonds (13 sectors), rows (a, s1), keepdim 256",
+        "elements": O.numel, "sectors": plan.nsectors,
+        "largest_sector": [int(max(m for m, _ in shapes)), int(max(n_ for _, n_ in shapes))],
+        "ms": round(ms_svd, 3), "oracle_ms": round(cpu_ms, 2),
+        "max_value_err": float(np.max(np.abs(np.sort(S) - np.sort(ref))) / ref.max())}
+    # -- two-site DMRG of the XX chain (N = 16, keepdim 64, 2 sweeps)
+    N, keep = 16, 64
+    specs = wl.mps_specs(N, "1/2", 0)
+    mps = []
+    for i, (lab, legs) in enumerate(specs):
+        t = bst.Tensor(lab, legs)
+        mps.append(dmrg.DevTensor(t, torch.from_numpy(wl.normal(wl.seed_for(2, "A", i), t.numel)).to(dev)))
+    Ws = wl.heff_specs("1/2", [(0, 1)], [(0, 1)], "xx")["W1"]
+    Wo = orc.from_dense(*Ws, wl.mpo_dense("1/2", "xx"))
+    Wg = dmrg.DevTensor(bst.Tensor(*Ws), torch.from_numpy(Wo.data.copy()).to(dev))
+    Ls, lpos, Rs, rpos = wl.boundary_env_specs("1/2", "xx", 0)
+    envs = []
+    for sp, pos in ((Ls, lpos), (Rs, rpos)):
+        D = np.zeros(orc.BlockTensor(*sp).dims())
+        D[pos] = 1.0
+        envs.append(dmrg.DevTensor(bst.Tensor(*sp), torch.from_numpy(orc.from_dense(*sp, D).data).to(dev)))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    E, errs, _ = dmrg.dmrg_two_site(mps, Wg, envs[0], envs[1], 2, keep, 1e-12)
+    torch.cuda.synchronize()
+    sweep_s = (time.perf_counter() - t0) / 2
+    exact = sum(min(0.0, math.cos(math.pi * k / (N + 1))) for k in range(1, N + 1))
+    out["dmrg_sweep_xx"] = {
+        "workload": f"open XX chain, spin 1/2, N = {N}, total Sz 0, keepdim {keep}, 2 sweeps from a random MPS",
+        "s_per_sweep": round(sweep_s, 3), "bond_updates": len(E),
+        "energy": E[-1], "exact_free_fermion": exact, "abs_err": abs(E[-1] - exact),
+        "max_s_err": max(errs)}
+    # -- complex contraction A[l, s, m] . B[m, t, r], chi = 2048 (q in [-16, 16])
+    v = wl.gaussian_sector_dims(2048, 16)
+    A = (["l", "s", "m"], [(1, v), (1, ph), (-1, v)])
+    B = (["m", "t", "r"], [(1, v), (1, ph), (-1, v)])
+    tA, tB = bst.Tensor(*A), bst.Tensor(*B)
+    res = {}
+    for dt in ("f64", "c128"):
+        w_ = 2 if dt == "c128" else 1
+        tC, cp = bst.contract_plan(tA, tB, "fp64", dtype=dt)
+        a_ = torch.randn(w_ * tA.numel, dtype=torch.float64, device=dev)
+        b_ = torch.randn(w_ * tB.numel, dtype=torch.float64, device=dev)
+        c_ = torch.empty(w_ * tC.numel, dtype=torch.float64, device=dev)
+        wsc = bst.workspace(cp.workspace_bytes)
+        cp.autotune([a_, b_], [c_], wsc, reps=3)
+        ms = _time_ms(torch, lambda: cp.execute([a_, b_], [c_], wsc), 10)
+        fl = cp.stats().flops
+        res[dt] = {"ms": round(ms, 4), "gflops": round(fl / ms / 1e6, 1), "flops": fl, "tiles": cp.tiles()}
+    # the oracle's complex contraction of a smaller state (chi = 512) on the host
+    v5 = wl.gaussian_sector_dims(512, 8)
+    Ao = orc.BlockTensor(["l", "s", "m"], [(1, v5), (1, ph), (-1, v5)], dtype=np.complex128)
+    Bo = orc.BlockTensor(["m", "t", "r"], [(1, v5), (1, ph), (-1, v5)], dtype=np.complex128)
+    Ao.data[:] = wl.normal(11, Ao.numel) + 1j * wl.normal(12, Ao.numel)
+    Bo.data[:] = wl.normal(13, Bo.numel) + 1j * wl.normal(14, Bo.numel)
+    t0 = time.perf_counter()
+    Co = orc.contract(Ao, Bo)
+    cpu_s = time.perf_counter() - t0
+    t5A, t5B = bst.Tensor(*(Ao.labels, Ao.legs)), bst.Tensor(*(Bo.labels, Bo.legs))
+    t5C, p5 = bst.contract_plan(t5A, t5B, "fp64", dtype="c128")
+    a5 = torch.view_as_real(torch.from_numpy(Ao.data).to(dev)).reshape(-1)
+    b5 = torch.view_as_real(torch.from_numpy(Bo.data).to(dev)).reshape(-1)
+    c5 = torch.empty(2 * t5C.numel, dtype=torch.float64, device=dev)
+    p5.execute([a5, b5], [c5], bst.workspace(p5.workspace_bytes))
+    got = c5.cpu().numpy().reshape(-1, 2)
+    got = got[:, 0] + 1j * got[:, 1]
+    out["complex_contract"] = {
+        "workload": "A[l,s,m].B[m,t,r], spin-1/2 physical legs, chi = 2048 virtual legs (33 sectors), FP64 arithmetic",
+        "c128": res["c128"], "f64_same_structure": res["f64"],
+        "oracle_chi512_gflops": round(p5.stats().flops / cpu_s / 1e9, 2),
+        "chi512_max_err_vs_oracle": float(np.max(np.abs(got - Co.data)) / np.max(np.abs(Co.data)))}
     return out
 
 
