@@ -618,36 +618,13 @@ hipError_t launch_lanczos_step_end(const double* partial, int64_t n_for_grid, co
 // the symmetric three-term recurrence; in exact arithmetic alpha_j and
 // beta_j equal those of Lanczos with two full classical Gram-Schmidt passes.
 //
-// The scalars of step j from g = u_j.z, evaluated by one thread in a fixed
-// order (al, be, dp hold alpha, beta, dprev for k < j): coef[0..j], the
-// coefficients of v_0..v_j in w = z/beta_{j-1} - sum_k coef_k v_k, and aest,
-// the three-term estimate of alpha_j.
-__device__ __forceinline__ void step_coef(int j, double gs, const double* al, const double* be,
-                                          const double* dp, double* __restrict__ coef,
-                                          double* __restrict__ aest) {
-  const double bp = j > 0 ? be[j - 1] : 1.0;
-  const double rb = bp > 0.0 ? 1.0 / bp : 0.0;
-  // v_j . z = rb (g - dprev . f), f = (T^T y)_{k<j}, y = (dprev, beta_{j-1})
-  double sdot = 0.0;
-  for (int k = 0; k < j; ++k) {
-    const double yn = k + 1 < j ? dp[k + 1] : bp;
-    double f = al[k] * dp[k] + be[k] * yn;
-    if (k > 0) f += be[k - 1] * dp[k - 1];
-    sdot += dp[k] * f;
-  }
-  const double vz = rb * (gs - sdot);
-  // e = T dprev over rows 0..j; coef_k = rb e_k (+ beta_{j-1} for k = j-1)
-  for (int i = 0; i < j; ++i) {
-    double e = al[i] * dp[i];
-    if (i > 0) e += be[i - 1] * dp[i - 1];
-    if (i + 1 < j) e += be[i] * dp[i + 1];
-    coef[i] = rb * e + (i == j - 1 ? bp : 0.0);
-  }
-  const double ej = j > 0 ? be[j - 1] * dp[j - 1] : 0.0;
-  const double a = rb * (vz - ej);
-  coef[j] = rb * ej + a;
-  aest[0] = a;
-}
+// The scalars of step j from g = u_j.z (al, be, dp hold alpha, beta, dprev
+// for k < j; rb = 1 / beta_{j-1}):
+//   v_j . z = rb (g - dprev . f),  f = (T^T y)_{k<j},  y = (dprev, beta_{j-1});
+//   e = T dprev over rows 0..j;  coef_k = rb e_k (+ beta_{j-1} for k = j-1),
+// the coefficients of v_0..v_j in w = z/beta_{j-1} - sum_k coef_k v_k; and
+// aest, the three-term estimate of alpha_j.  lanczos_step_scalars_kernel
+// evaluates them.
 
 // The pass of step j: per element
 //   v_j = (u_j - sum_{k<j} dprev_k v_k) rb      written back into row j
@@ -867,9 +844,11 @@ __global__ __launch_bounds__(64) void lanczos_end_kernel(const double* __restric
 // The scalar work between two basis passes, in one block of 1024 threads:
 // the sums of the partials of the pass of step pj (dn) and of the u_j.z,
 // z.z partials of dot2_kernel (g), then the end of step pj (alpha, beta,
-// dprev as lanczos_end_kernel) and the scalars of step j (step_coef).  One wave forms each sum: lane l adds partials l,
-// l + 64, ... in order, then the wave sum; every load of a sum is issued at
-// once (grids of at most 1024 blocks).  pj < 0: no pass before (step 0).
+// dprev as lanczos_end_kernel) and the scalars of step j.  One wave forms
+// each sum: lane l adds partials l, l + 64, ... in order, then the wave sum;
+// every load of a sum is issued at once (grids of at most 1024 blocks).  The
+// scalars then take one wave, lane-parallel over k.  pj < 0: no pass before
+// (step 0).
 __global__ __launch_bounds__(1024) void lanczos_step_scalars_kernel(
     const double* __restrict__ ppart, int pG, int pj, const double* __restrict__ dpart, int dG,
     int j, double* __restrict__ dn, double* __restrict__ g, double* __restrict__ alpha,
@@ -923,15 +902,55 @@ __global__ __launch_bounds__(1024) void lanczos_step_scalars_kernel(
     dn[k] = sv[k];
     if (k <= pj) dprev[k] = sv[k];
   }
-  if (tid != 0) return;
+  if (wave != 0) return;
+  // The rest in wave 0, lane-parallel over the step index k (k < kMaxVecs,
+  // two per lane).  Each sum is a wave_sum in a fixed order whose result
+  // lane 0 broadcasts, so every lane continues with the same value.
+  // End of step pj (as step_end): alpha_pj, beta_pj.
+  double apj = 0.0, bpj = 0.0;
   if (pj >= 0) {
-    step_end(sv, aest[0], pj, al[pj], be[pj]);
-    alpha[pj] = al[pj];
-    beta[pj] = be[pj];
+    double t = 0.0;
+    for (int k = lane; k <= pj; k += 64) t += sv[k] * sv[k];
+    const double ss = __shfl(wave_sum(t), 0, 64);
+    const double q = sv[pj + 1] - ss;
+    apj = aest[0] + sv[pj];
+    bpj = sqrt(q > 0.0 ? q : 0.0);
+    if (lane == 0) {
+      alpha[pj] = apj;
+      beta[pj] = bpj;
+    }
   }
-  g[0] = sv[npv];
-  g[1] = sv[npv + 1];
-  step_coef(j, sv[npv], al, be, sv, coef, aest);
+  if (lane == 0) {
+    g[0] = sv[npv];
+    g[1] = sv[npv + 1];
+  }
+  // Scalars of step j = pj + 1 (as step_coef, dprev = sv[0..j)).
+  const double* dp = sv;
+  auto AL = [&](int k) { return k == pj ? apj : al[k]; };
+  auto BE = [&](int k) { return k == pj ? bpj : be[k]; };
+  const double bp = j > 0 ? bpj : 1.0;
+  const double rb = bp > 0.0 ? 1.0 / bp : 0.0;
+  double t = 0.0;
+  for (int k = lane; k < j; k += 64) {
+    const double yn = k + 1 < j ? dp[k + 1] : bp;
+    double f = AL(k) * dp[k] + BE(k) * yn;
+    if (k > 0) f += BE(k - 1) * dp[k - 1];
+    t += dp[k] * f;
+  }
+  const double sdot = __shfl(wave_sum(t), 0, 64);
+  const double vz = rb * (sv[npv] - sdot);
+  for (int i = lane; i < j; i += 64) {
+    double e = AL(i) * dp[i];
+    if (i > 0) e += BE(i - 1) * dp[i - 1];
+    if (i + 1 < j) e += BE(i) * dp[i + 1];
+    coef[i] = rb * e + (i == j - 1 ? bp : 0.0);
+  }
+  if (lane == 0) {
+    const double ej = j > 0 ? BE(j - 1) * dp[j - 1] : 0.0;
+    const double a = rb * (vz - ej);
+    coef[j] = rb * ej + a;
+    aest[0] = a;
+  }
 }
 
 hipError_t launch_lanczos_pass(double* V, int64_t ldv, int64_t n, int j, const double* z,
