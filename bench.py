@@ -162,7 +162,7 @@ def main():
         plan.set_precision(prec)
         if not a.no_tune:
             plan.autotune([g["L"], g["W1"], g["W2"], g["R"], g["psi0"]], [tune_out], tune_ws,
-                          reps=3)
+                          reps=5)
         tuned[prec] = plan.tiles()
     del tune_ws, tune_out
 

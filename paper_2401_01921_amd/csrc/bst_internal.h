@@ -201,7 +201,7 @@ struct TileShape {
   int direct = 0;   // 1: LDS-free kernel (fragments loaded straight from memory);
                     // 3: pipelined persistent kernel on a k-step schedule (padded layouts only)
   int stages = 0;   // kind 3: LDS stages (copies run stages - 1 k-steps ahead)
-  int waves = 4;    // kind 3: waves per workgroup (4: 2 x 2; 8: 2 x 4, or 4 x 2 when bm > bn)
+  int waves = 4;    // kind 3: waves per workgroup (4: 2 x 2, or 1 x 4 for 192 columns; 8: 2 x 4, or 4 x 2 when bm > bn)
 };
 // Tile shapes compiled for each arithmetic form.
 const std::vector<TileShape>& gemm_tile_shapes(bst_precision form);
@@ -384,6 +384,9 @@ hipError_t launch_combine(const double* V, int64_t ldv, int64_t n, int nv, const
 hipError_t launch_combine(const float* V, int64_t ldv, int64_t n, int nv, const double* coef,
                           double* y, hipStream_t s);
 // out[0] = x.y, out[1] = y.y (out == nullptr: block partials only)
+// Reads n doubles (zeros) with ordinary cached loads, so that data an earlier
+// kernel left in the L2 and last-level caches is evicted.
+hipError_t launch_cache_flush(double* buf, int64_t n, hipStream_t s);
 hipError_t launch_dot2(const double* x, const double* y, int64_t n, double* partial, double* out,
                        hipStream_t s);
 hipError_t launch_dot2(const float* x, const double* y, int64_t n, double* partial, double* out,

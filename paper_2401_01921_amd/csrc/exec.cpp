@@ -516,17 +516,47 @@ bst_status bst_plan_autotune(bst_plan* p, const void* const* in, void* const* ou
   const char* path = std::getenv("BST_TUNE_CACHE");
   auto cache = path ? load_cache(path) : std::map<std::string, CachedShape>{};
   const bst_precision form = P.prec;
-  // reps runs of step k (all steps for k < 0), in ms
+  // A buffer twice the size of the last-level cache, rewritten before every
+  // timed run: an iterative caller (Lanczos) streams its basis between two
+  // applies, so no operand of one apply is still cached at the next.
+  struct Flush {
+    double* p = nullptr;
+    hipStream_t s = nullptr;
+    ~Flush() {
+      if (!p) return;
+      (void)hipStreamSynchronize(s);
+      (void)hipFree(p);
+    }
+  } flush;
+  flush.s = s;
+  constexpr int64_t kFlushDoubles = (int64_t)64 << 20;   // 512 MiB
+  if (hipMalloc(&flush.p, sizeof(double) * kFlushDoubles) != hipSuccess) {
+    flush.p = nullptr;
+    (void)hipGetLastError();
+  } else {
+    check_hip(hipMemsetAsync(flush.p, 0, sizeof(double) * kFlushDoubles, s), "flush buffer");
+  }
+  // reps runs of step k (all steps for k < 0), each after a cache flush and
+  // the (untimed) steps before k, in ms
   auto time_runs = [&](int k) {
-    check_hip(hipEventRecord(e0, s), "event");
-    for (int r = 0; r < reps; ++r) run_steps_impl(P, ws, table, P.prec, s, false, k, nullptr);
-    check_hip(hipEventRecord(e1, s), "event");
-    check_hip(hipEventSynchronize(e1), "event sync");
-    float ms = 0;
-    check_hip(hipEventElapsedTime(&ms, e0, e1), "event time");
-    return (double)ms;
+    double total = 0.0;
+    for (int r = 0; r < reps; ++r) {
+      if (flush.p) check_hip(launch_cache_flush(flush.p, kFlushDoubles, s), "cache flush");
+      for (int j = 0; j < k; ++j) run_steps_impl(P, ws, table, P.prec, s, true, j, nullptr);
+      check_hip(hipEventRecord(e0, s), "event");
+      run_steps_impl(P, ws, table, P.prec, s, false, k, nullptr);
+      check_hip(hipEventRecord(e1, s), "event");
+      check_hip(hipEventSynchronize(e1), "event sync");
+      float ms = 0;
+      check_hip(hipEventElapsedTime(&ms, e0, e1), "event time");
+      total += ms;
+    }
+    return total;
   };
-  // the fastest tile shape of every GEMM step, in the variant the plan runs now
+  // the fastest tile shape of every GEMM step, in the variant the plan runs
+  // now.  Each candidate is timed in the state an iterative caller leaves
+  // (caches flushed, then the steps before it run): a step timed in a loop
+  // finds its inputs in the caches, which favours shapes that re-read them.
   auto tune_steps = [&]() {
     // one full run so that intermediates hold realistic data
     run_steps(P, ws, table, P.prec, s, false);

@@ -81,7 +81,26 @@ __global__ __launch_bounds__(256) void calib_mfma_bf16_kernel(int64_t iters, dou
   for (int k = 0; k < 8; ++k) s += acc[k][0] + acc[k][1] + acc[k][2] + acc[k][3];
   out[(int64_t)blockIdx.x * 256 + threadIdx.x] = (double)s;
 }
+// Reads only, so that the lines it leaves in the caches are clean and their
+// eviction costs no write-back later.  The buffer holds zeros: the store that
+// keeps the loads alive never happens.
+__global__ __launch_bounds__(256) void cache_flush_kernel(dbl2v* __restrict__ buf, int64_t n2) {
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n2; i += stride) {
+    const dbl2v v = buf[i];
+    s += v.x + v.y;
+  }
+  if (s == 1.0) buf[0] = dbl2v{s, s};
+}
 }  // namespace
+
+hipError_t launch_cache_flush(double* buf, int64_t n, hipStream_t s) {
+  if (!buf || n < 2) return hipSuccess;
+  hipLaunchKernelGGL(cache_flush_kernel, dim3(kCalibGrid), dim3(256), 0, s, reinterpret_cast<dbl2v*>(buf),
+                     n / 2);
+  return hipGetLastError();
+}
 
 }  // namespace bst
 

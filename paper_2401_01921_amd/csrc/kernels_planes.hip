@@ -185,7 +185,9 @@ __device__ __forceinline__ int swz(int r, int cc) {
 static const std::vector<TileShape> kPlaneShapes2 = {
     {64, 64, 0},         {128, 64, 0},        {64, 128, 0},       {32, 32, 0},     {128, 128, 0},
     {128, 64, 3, 3, 4},  {64, 128, 3, 3, 4},  {128, 128, 3, 3, 8}, {128, 256, 3, 3, 8},
-    {256, 128, 3, 3, 8}, {256, 64, 3, 3, 8}};
+    {256, 128, 3, 3, 8}, {256, 64, 3, 3, 8},  {64, 192, 3, 3, 4}, {64, 192, 3, 2, 4},
+    {128, 192, 3, 3, 8}, {128, 128, 3, 2, 8}, {128, 64, 3, 2, 4}, {64, 128, 3, 2, 4},
+    {32, 192, 3, 2, 4}};
 static const std::vector<TileShape> kPlaneShapes3 = {{64, 64, 0}, {32, 32, 0}, {64, 64, 3, 3, 4},
                                                      {128, 128, 3, 3, 8}};
 // float64 operands in the padded layouts: the pipelined kernel only

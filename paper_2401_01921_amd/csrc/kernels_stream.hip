@@ -522,6 +522,13 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_f64_stream_kernel(const K
   X(2, 128, 256, 3, 2, 4)    \
   X(2, 256, 128, 3, 4, 2)    \
   X(2, 256, 64, 3, 4, 2)     \
+  X(2, 64, 192, 3, 1, 4)     \
+  X(2, 64, 192, 2, 1, 4)     \
+  X(2, 128, 192, 3, 2, 4)    \
+  X(2, 128, 128, 2, 2, 4)    \
+  X(2, 128, 64, 2, 2, 2)     \
+  X(2, 64, 128, 2, 2, 2)     \
+  X(2, 32, 192, 2, 1, 4)     \
   X(3, 64, 64, 3, 2, 2)      \
   X(3, 128, 128, 3, 2, 4)
 
