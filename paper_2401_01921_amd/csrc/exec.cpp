@@ -544,7 +544,9 @@ bst_status bst_plan_autotune(bst_plan* p, const void* const* in, void* const* ou
       if (flush.p) check_hip(launch_cache_flush(flush.p, kFlushDoubles, s), "cache flush");
       for (int j = 0; j < k; ++j) run_steps_impl(P, ws, table, P.prec, s, true, j, nullptr);
       check_hip(hipEventRecord(e0, s), "event");
-      run_steps_impl(P, ws, table, P.prec, s, false, k, nullptr);
+      // a whole apply as an iterative caller repeats it: steps on constant
+      // operands (their splits, copies) ran once before and are not timed
+      run_steps_impl(P, ws, table, P.prec, s, k < 0, k, nullptr);
       check_hip(hipEventRecord(e1, s), "event");
       check_hip(hipEventSynchronize(e1), "event sync");
       float ms = 0;

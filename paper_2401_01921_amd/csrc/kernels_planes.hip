@@ -193,7 +193,9 @@ static const std::vector<TileShape> kPlaneShapes3 = {{64, 64, 0}, {32, 32, 0}, {
 // float64 operands in the padded layouts: the pipelined kernel only
 static const std::vector<TileShape> kPlaneShapes1 = {{64, 64, 3, 3, 4},   {128, 64, 3, 3, 4},
                                                      {64, 128, 3, 3, 4},  {128, 128, 3, 3, 8},
-                                                     {256, 128, 3, 3, 8}, {128, 256, 3, 3, 8}};
+                                                     {256, 128, 3, 3, 8}, {128, 256, 3, 3, 8},
+                                                     {64, 64, 3, 2, 4},   {128, 64, 3, 2, 4},
+                                                     {64, 128, 3, 2, 4},  {128, 128, 3, 2, 8}};
 const std::vector<TileShape>& gemm_planes_shapes(int np) {
   return np == 1 ? kPlaneShapes1 : np == 3 ? kPlaneShapes3 : kPlaneShapes2;
 }

@@ -511,7 +511,11 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_f64_stream_kernel(const K
   X(64, 128, 3, 2, 2)          \
   X(128, 128, 3, 2, 4)         \
   X(256, 128, 3, 4, 2)         \
-  X(128, 256, 3, 2, 4)
+  X(128, 256, 3, 2, 4)         \
+  X(64, 64, 2, 2, 2)           \
+  X(128, 64, 2, 2, 2)          \
+  X(64, 128, 2, 2, 2)          \
+  X(128, 128, 2, 2, 4)
 
 // Shapes of kind 3 in gemm_planes_shapes(np), instantiated here
 // (np, bm, bn, stages, waves along M, waves along N).
