@@ -261,6 +261,10 @@ void run_steps_impl(PlanData& P, void* ws, void* const* dptrs, bst_precision pre
           h.tasks = reinterpret_cast<const HTask*>(blob + st.off3);
           h.planes = reinterpret_cast<const HPlane*>(blob + st.off4);
           h.off32 = st.mpo_off32_alt;
+          if (h.np > 0) {   // bfloat16 planes out: the XCD-grouped item order
+            h.work = reinterpret_cast<const HWork*>(blob + st.off5);
+            h.nwork = st.n1;
+          }
         }
         if (P.sparse_mpo) {
           h.cnt = reinterpret_cast<const int32_t*>(wsb + P.ws_cnt_off);

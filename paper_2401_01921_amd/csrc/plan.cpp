@@ -924,6 +924,7 @@ static void heff_plan(const TensorDesc& L, const TensorDesc& W1, const TensorDes
         for (auto& q : ins) ha.planes.push_back(q);
         for (auto& q : outs) ha.planes.push_back(q);
         ha.tasks.push_back(task);
+        ha.task_group.push_back(ka);
         for (auto& q : ins_alt) ha.planes_alt.push_back(q);
         for (auto& q : outs_alt) ha.planes_alt.push_back(q);
         HTask ta = task;
@@ -1124,6 +1125,10 @@ static void heff_batch(const std::vector<const PlanData*>& subs, PlanData& P) {
         b.nmax = std::max(b.nmax, a.nmax);
       } else if (a.kind == StepKind::HApply) {
         const int32_t pb = (int32_t)b.planes.size();
+        // task groups stay distinct between members
+        const int32_t gb =
+            b.task_group.empty() ? 0 : *std::max_element(b.task_group.begin(), b.task_group.end()) + 1;
+        for (auto g : a.task_group) b.task_group.push_back(g + gb);
         for (auto q : a.planes) b.planes.push_back(q);
         for (auto t : a.tasks) {
           t.cls += cls_base;
@@ -1473,15 +1478,62 @@ void finalize(PlanData& P) {
         const bool force64 = std::getenv("BST_MPO_INDEX64") != nullptr;
         st.mpo_off32 = !force64 && fit32(st.tasks, st.planes);
         st.mpo_off32_alt = !force64 && st.has_alt && fit32(st.tasks_alt, st.planes_alt);
-        std::vector<HWork> work;
+        // Work items of 256 sites, in two orders.  Task by task (work):
+        // consecutive items spread over all XCDs.  Grouped (work_grouped,
+        // used when the apply writes bfloat16 planes): the tasks of one a
+        // sector read the same T1 rows and write the same T3 rows, each its
+        // own column segment, so lines at segment ends are shared between
+        // them.  Each XCD has its own L2 and workgroups go to the XCDs
+        // round-robin, so the items of one a sector go to one XCD (sectors
+        // by size, largest first, each to the least loaded XCD), ordered
+        // there by first row, and the eight lists are interleaved
+        // (workgroup 8 pos + x runs item pos of XCD x).  Short lists end in
+        // empty items (site0 past the task).  With float64 outputs the
+        // grouped order measured slower (87 -> 90 us per apply at chi = 4096).
+        std::vector<HWork> work, wgrp;
         for (size_t ti = 0; ti < st.tasks.size(); ++ti) {
           const int64_t sites = (int64_t)st.tasks[ti].rows * st.tasks[ti].cols;
           for (int64_t s0 = 0; s0 < sites; s0 += 256) work.push_back({(int32_t)ti, (int32_t)s0});
+        }
+        {
+          struct Item {
+            int32_t task, s0, row0;
+          };
+          std::map<int32_t, std::vector<Item>> groups;
+          for (size_t ti = 0; ti < st.tasks.size(); ++ti) {
+            const int64_t sites = (int64_t)st.tasks[ti].rows * st.tasks[ti].cols;
+            const int32_t g = ti < st.task_group.size() ? st.task_group[ti] : 0;
+            for (int64_t s0 = 0; s0 < sites; s0 += 256)
+              groups[g].push_back({(int32_t)ti, (int32_t)s0, (int32_t)(s0 / std::max(st.tasks[ti].cols, 1))});
+          }
+          std::vector<std::pair<size_t, int32_t>> order;
+          for (auto& kv : groups) order.push_back({kv.second.size(), kv.first});
+          std::stable_sort(order.begin(), order.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
+          std::vector<std::vector<Item>> bins(kXcds);
+          for (const auto& o : order) {
+            int x = 0;
+            for (int i = 1; i < kXcds; ++i)
+              if (bins[i].size() < bins[x].size()) x = i;
+            auto& items = groups[o.second];
+            std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b) { return a.row0 < b.row0; });
+            bins[x].insert(bins[x].end(), items.begin(), items.end());
+          }
+          size_t longest = 0;
+          for (auto& b : bins) longest = std::max(longest, b.size());
+          const int32_t empty_s0 = st.tasks.empty() ? 0 : st.tasks[0].rows * st.tasks[0].cols;
+          for (size_t pos = 0; pos < longest; ++pos)
+            for (int x = 0; x < kXcds; ++x)
+              wgrp.push_back(pos < bins[x].size() ? HWork{bins[x][pos].task, bins[x][pos].s0}
+                                                  : HWork{0, empty_s0});
+          while (!wgrp.empty() && wgrp.back().task == 0 && wgrp.back().site0 == empty_s0 && empty_s0 > 0)
+            wgrp.pop_back();
         }
         st.off0 = put(P.blob, st.tasks);
         st.off1 = put(P.blob, st.planes);
         st.off2 = put(P.blob, work);
         st.n0 = (int64_t)work.size();
+        st.off5 = put(P.blob, wgrp);
+        st.n1 = (int64_t)wgrp.size();
         if (st.has_alt) {
           st.off3 = put(P.blob, st.tasks_alt);
           st.off4 = put(P.blob, st.planes_alt);

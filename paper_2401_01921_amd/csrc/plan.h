@@ -67,6 +67,7 @@ struct Step {
   int32_t nmax = 0;
   std::vector<HTask> tasks;
   std::vector<HPlane> planes;
+  std::vector<int32_t> task_group;   // per task: its a sector (tasks of one a share T1 and T3 rows)
   Elem th = Elem::Inter;
   // bfloat16-plane variant used by the split forms (H_eff only): GEMM
   // segments on pre-split operands, MPO tasks writing T3 as planes
