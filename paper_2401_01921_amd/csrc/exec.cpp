@@ -353,11 +353,25 @@ static void save_cache(const char* path, const std::map<std::string, CachedShape
   f << "}\n";
 }
 
+// Cache entry of the FP64 variant choice (float64 panels or per-block-pair
+// kernels): keyed by the plan's first GEMM step, value [1, 0, 0, 0] for panels.
+constexpr int kVariantKey = 99;
+static std::string variant_key(const PlanData& P) {
+  for (const auto& st : P.steps)
+    if (st.kind == StepKind::Gemm) return tune_key(P, st, kVariantKey);
+  return std::string();
+}
+
 // Applies cached tile choices (if BST_TUNE_CACHE names a readable file).
 void apply_tune_cache(PlanData& P) {
   const char* path = std::getenv("BST_TUNE_CACHE");
   if (!path) return;
   auto m = load_cache(path);
+  const std::string vk = variant_key(P);
+  if (!vk.empty()) {
+    auto it = m.find(vk);
+    if (it != m.end()) P.fp64_panels_on = it->second.bm != 0;
+  }
   for (auto& st : P.steps) {
     if (st.kind != StepKind::Gemm) continue;
     for (int f : {0, 1, 2, 3, 10, 12, 13}) {
@@ -603,6 +617,8 @@ bst_status bst_plan_autotune(bst_plan* p, const void* const* in, void* const* ou
     tune_steps();
     const double t_panels = time_runs(-1);
     P.fp64_panels_on = t_panels < t_blocks;
+    const std::string vk = variant_key(P);
+    if (!vk.empty()) cache[vk] = {P.fp64_panels_on ? 1 : 0, 0, 0, 0};
   } else {
     tune_steps();
   }
@@ -620,6 +636,8 @@ bst_status bst_plan_record_tiles(const bst_plan* p) {
   if (!path) fail(BST_E_INVALID, "BST_TUNE_CACHE is not set");
   const PlanData& P = p->p;
   auto cache = load_cache(path);
+  const std::string vk = variant_key(P);
+  if (!vk.empty() && P.f64_panels) cache[vk] = {P.fp64_panels_on ? 1 : 0, 0, 0, 0};
   for (const auto& st : P.steps) {
     if (st.kind != StepKind::Gemm) continue;
     for (const auto& kv : st.tile_choice) {

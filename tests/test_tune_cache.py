@@ -64,3 +64,23 @@ def test_cache_round_trip(tmp_path, monkeypatch):
     path.write_text("garbage\n" + path.read_text() + "\n\"x\": [oops]\n")
     _, d = _plan(512, 8)
     assert _tiles(d, "fp64") == chosen["fp64"]
+
+
+def test_fp64_variant_round_trip(tmp_path, monkeypatch):
+    """The FP64 variant choice (float64 panels or per-block-pair kernels) is
+    cached beside the tiles: an entry [1, 0, 0, 0] under the plan's variant
+    key makes a later plan of the same structure start on the panels."""
+    path = tmp_path / "tiles.json"
+    monkeypatch.setenv("BST_TUNE_CACHE", str(path))
+    _, a = _plan(512, 8)
+    blocks = _tiles(a, "fp64")
+    a.record_tiles()
+    entries = json.loads(path.read_text())
+    variant = [k for k, v in entries.items() if v == [0, 0, 0, 0]]
+    assert len(variant) == 1, entries
+    entries[variant[0]] = [1, 0, 0, 0]
+    path.write_text(json.dumps(entries))
+    _, b = _plan(512, 8)
+    panels = _tiles(b, "fp64")
+    assert panels != blocks
+    assert all("p" in t.split(":")[1] for t in panels.split(";") if t.startswith("gemm")), panels
