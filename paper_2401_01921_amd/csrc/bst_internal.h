@@ -332,7 +332,6 @@ struct StreamLaunch {
   int np;                         // 2, 3: bfloat16 planes; 1: float64 operands
   ElemType tc;
   int tile;                       // index into gemm_planes_shapes(np), a kind-3 shape
-  bool vec;                       // float output stored 16 bytes per lane (StreamList::vec_ok)
   const KStep* steps;             // padded with kStepBatch records past the last
   const int64_t* wg_begin;        // nwg + 1 entries
   int64_t nwg;

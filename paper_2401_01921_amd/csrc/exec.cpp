@@ -172,7 +172,6 @@ void run_steps_impl(PlanData& P, void* ws, void* const* dptrs, bst_precision pre
               sl.np = np;
               sl.tc = g.tc;
               sl.tile = g.tile;
-              sl.vec = L.vec_ok && g.tc == ElemType::F32;
               sl.steps = reinterpret_cast<const KStep*>(blob + L.steps_off);
               sl.wg_begin = reinterpret_cast<const int64_t*>(blob + L.begin_off);
               sl.nwg = L.nwg;

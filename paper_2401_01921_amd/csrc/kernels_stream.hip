@@ -115,13 +115,9 @@ __device__ __attribute__((aligned(1024))) unsigned int g_stream_zero[64 * 4] = {
 // lanes of one store stay within two cache lines; one word shared by the
 // whole chip would serialise); never read.
 constexpr int kSinkWgs = 4 * kStreamCUs;
-constexpr int kSinkSlot = 32;   // doubles per wave: 16 lanes x 16 bytes
-__device__ __attribute__((aligned(256))) double g_stream_sink[kSinkWgs * 8 * kSinkSlot];
+__device__ __attribute__((aligned(256))) double g_stream_sink[kSinkWgs * 8 * 16];
 
-// VEC (float output, StreamLaunch::vec): the products are formed as B A^T
-// (operands swapped in the MFMA), so that each lane holds four consecutive
-// columns of one output row and stores them with one 16-byte store.
-template <int NP, typename TC, int BM, int BN, int S, int WGM, int WGN, bool VEC>
+template <int NP, typename TC, int BM, int BN, int S, int WGM, int WGN>
 __global__ __launch_bounds__(64 * WGM * WGN) void gemm_planes_stream_kernel(const KStep* __restrict__ steps,
                                                                  const int64_t* __restrict__ wg_begin,
                                                                  void* const* __restrict__ ptrs,
@@ -137,10 +133,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_planes_stream_kernel(cons
   constexpr int REC = S * STB;                          // record ring
   constexpr int ROWS = REC + kStepRing * kStepBatch * 48;   // row-offset ring
   constexpr int LDSB = ROWS + S * BM * 8;
-  // store instructions per lane per tile (at least: a vector tile's partial
-  // columns add scalar stores, which only makes the waits stricter)
-  constexpr int NS = VEC ? SM * SN : SM * SN * 4;
-  static_assert(!VEC || sizeof(TC) == 4, "vector stores of float outputs");
+  constexpr int NS = SM * SN * 4;                       // stores per lane per tile
   static_assert(LDSB == stream_lds_bytes(NP, BM, BN, S), "LDS layout");
   static_assert(SLA % NT == 0 && SLB % NT == 0, "a copy round covers A or B slots only");
   static_assert(S >= 2 && S <= 16, "stages");
@@ -243,25 +236,18 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_planes_stream_kernel(cons
         for (int j = 0; j < SN; ++j) b[q][j] &= m;
       }
     }
-    // one product of planes (x of A, y of B), in the orientation of VEC
-    auto mm = [&](const u4& x, const u4& y, flt4 c) {
-      if constexpr (VEC)
-        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf(y), bf(x), c, 0, 0, 0);
-      else
-        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf(x), bf(y), c, 0, 0, 0);
-    };
 #pragma unroll
     for (int i = 0; i < SM; ++i)
 #pragma unroll
       for (int j = 0; j < SN; ++j) {
         if constexpr (NP == 3) {
-          acc[i][j] = mm(a[2][i], b[0][j], acc[i][j]);
-          acc[i][j] = mm(a[1][i], b[1][j], acc[i][j]);
-          acc[i][j] = mm(a[0][i], b[2][j], acc[i][j]);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf(a[2][i]), bf(b[0][j]), acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf(a[1][i]), bf(b[1][j]), acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf(a[0][i]), bf(b[2][j]), acc[i][j], 0, 0, 0);
         }
-        acc[i][j] = mm(a[1][i], b[0][j], acc[i][j]);
-        acc[i][j] = mm(a[0][i], b[1][j], acc[i][j]);
-        acc[i][j] = mm(a[0][i], b[0][j], acc[i][j]);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf(a[1][i]), bf(b[0][j]), acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf(a[0][i]), bf(b[1][j]), acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf(a[0][i]), bf(b[0][j]), acc[i][j], 0, 0, 0);
       }
   };
 
@@ -270,31 +256,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_planes_stream_kernel(cons
   // 16-word slot of the sink
   auto epilogue = [&](const Rec& d) {
     BST_G TC* C = (BST_G TC*)(ptrs[d.c_buf]);
-    BST_G double* slot = (BST_G double*)(g_stream_sink + ((blockIdx.x % kSinkWgs) * 8 + wave) * kSinkSlot);
-    if constexpr (VEC) {
-      // lane: row (lane & 15) of each 16 x 16 block, columns 4 (lane >> 4) .. + 3;
-      // no row map (the host sets VEC only without one)
-      BST_G flt4* vsink = (BST_G flt4*)slot + (lane & 15);
-#pragma unroll
-      for (int i = 0; i < SM; ++i) {
-        const int row = wm * WM + i * 16 + (lane & 15);
-        const int64_t rb = row < d.rows ? d.c + (int64_t)row * d.ldc : -1;
-#pragma unroll
-        for (int j = 0; j < SN; ++j) {
-          const int col = wn * WN + j * 16 + 4 * (lane >> 4);
-          const bool full = rb >= 0 && col + 3 < d.cols;
-          *(full ? (BST_G flt4*)(C + rb + col) : vsink) = acc[i][j];
-          if (!full && rb >= 0 && col < d.cols) {   // the tile's last 1..3 columns
-            C[rb + col] = acc[i][j][0];
-            if (col + 1 < d.cols) C[rb + col + 1] = acc[i][j][1];
-            if (col + 2 < d.cols) C[rb + col + 2] = acc[i][j][2];
-          }
-        }
-      }
-      ++tiles_out;
-      return;
-    }
-    BST_G TC* sink = (BST_G TC*)(slot + (lane & 15));
+    BST_G TC* sink = (BST_G TC*)(g_stream_sink + ((blockIdx.x % kSinkWgs) * 8 + wave) * 16 + (lane & 15));
     const int64_t* rmap = reinterpret_cast<const int64_t*>(smem + ROWS + (tiles_out % S) * (BM * 8));
 #pragma unroll
     for (int i = 0; i < SM; ++i)
@@ -487,7 +449,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_f64_stream_kernel(const K
   // column l % 16 of the 16 x 16 block
   auto epilogue = [&](const Rec& d) {
     BST_G double* C = (BST_G double*)(ptrs[d.c_buf]);
-    BST_G double* sink = (BST_G double*)(g_stream_sink + ((blockIdx.x % kSinkWgs) * 8 + wave) * kSinkSlot + (lane & 15));
+    BST_G double* sink = (BST_G double*)(g_stream_sink + ((blockIdx.x % kSinkWgs) * 8 + wave) * 16 + (lane & 15));
     const int64_t* rmap = reinterpret_cast<const int64_t*>(smem + ROWS + (tiles_out % S) * (BM * 8));
 #pragma unroll
     for (int i = 0; i < SM; ++i)
@@ -595,15 +557,12 @@ hipError_t launch_gemm_planes_stream(const StreamLaunch& g, hipStream_t s) {
 #define BST_LAUNCH(NP_, BM_, BN_, S_, WGM_, WGN_)                                                          \
   if (g.np == NP_ && sh.bm == BM_ && sh.bn == BN_ && sh.stages == S_ && sh.waves == WGM_ * WGN_) {        \
     const dim3 block(64 * WGM_ * WGN_);                                                                    \
-    if (g.tc == ElemType::F32 && g.vec)                                                                   \
-      hipLaunchKernelGGL((gemm_planes_stream_kernel<NP_, float, BM_, BN_, S_, WGM_, WGN_, true>), grid,     \
-                         block, 0, s, g.steps, g.wg_begin, g.ptrs, g.rowtab);                              \
-    else if (g.tc == ElemType::F32)                                                                       \
-      hipLaunchKernelGGL((gemm_planes_stream_kernel<NP_, float, BM_, BN_, S_, WGM_, WGN_, false>), grid,    \
-                         block, 0, s, g.steps, g.wg_begin, g.ptrs, g.rowtab);                              \
+    if (g.tc == ElemType::F32)                                                                            \
+      hipLaunchKernelGGL((gemm_planes_stream_kernel<NP_, float, BM_, BN_, S_, WGM_, WGN_>), grid, block, 0, \
+                         s, g.steps, g.wg_begin, g.ptrs, g.rowtab);                            \
     else                                                                                                  \
-      hipLaunchKernelGGL((gemm_planes_stream_kernel<NP_, double, BM_, BN_, S_, WGM_, WGN_, false>), grid,   \
-                         block, 0, s, g.steps, g.wg_begin, g.ptrs, g.rowtab);                              \
+      hipLaunchKernelGGL((gemm_planes_stream_kernel<NP_, double, BM_, BN_, S_, WGM_, WGN_>), grid, block, \
+                         0, s, g.steps, g.wg_begin, g.ptrs, g.rowtab);                         \
     return hipGetLastError();                                                                             \
   }
   BST_STREAM_SHAPES(BST_LAUNCH)

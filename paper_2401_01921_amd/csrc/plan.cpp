@@ -1366,11 +1366,6 @@ static Step::StreamList make_stream(std::vector<uint8_t>& blob, const Step& st, 
   L.rows_off = put(blob, rowtab);
   L.nwg = nwg;
   L.ok = true;
-  // 16-byte stores of four float outputs need every tile row start, so the
-  // output offset, row stride and tile column, to be a multiple of 4
-  L.vec_ok = bn % 4 == 0;
-  for (const auto& p : probs)
-    if (p.rowmap1 > 0 || p.c_off % 4 != 0 || p.ldc % 4 != 0) L.vec_ok = false;
   return L;
 }
 

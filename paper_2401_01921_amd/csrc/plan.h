@@ -99,7 +99,6 @@ struct Step {
   // k-step schedules of the pipelined plane kernel, by np * 64 + shape index
   struct StreamList {
     bool ok = false;               // the problems fit the kernel's layout rules
-    bool vec_ok = false;           // no row map, output rows and offsets multiples of 4 elements
     size_t steps_off = 0, begin_off = 0, rows_off = 0;
     int64_t nwg = 0;
   };
