@@ -312,6 +312,7 @@ struct KStep {
 };
 static_assert(sizeof(KStep) == 48, "k-step record is 48 bytes");
 constexpr int kStepFirst = 1, kStepLast = 2, kStepRowmap = 4;
+constexpr int kStepPlaneEnd = 8;   // fused L.psi + MPO: last k-step of an input channel
 constexpr int kStepBatch = 16;   // records copied into LDS per batch
 constexpr int kStepRing = 3;     // batches resident in LDS
 // LDS bytes of one workgroup of the pipelined kernel and workgroups per CU
@@ -339,6 +340,24 @@ struct StreamLaunch {
   const int64_t* rowtab;          // row offsets of row-mapped tiles (bm per tile)
 };
 hipError_t launch_gemm_planes_stream(const StreamLaunch& g, hipStream_t s);
+
+// L.psi fused with the two-site MPO apply for two bfloat16 planes: 64 x 64
+// tiles of the MPO tasks on 8 waves, one workgroup per CU.  Records as for
+// the pipelined GEMM (see lh_fused_kernel for the fields it reuses).
+constexpr int lh_fused_lds_bytes(int nmax) {
+  return 3 * (64 + 64) * 128 + kStepRing * kStepBatch * 48 + 3 * (nmax * nmax * 4 + nmax * 16);
+}
+struct LhFusedLaunch {
+  int nmax;                       // 8 or 16: the coefficient block is nmax x nmax floats
+  const KStep* steps;             // padded with kStepBatch records past the last
+  const int64_t* wg_begin;        // nwg + 1 entries
+  int64_t nwg;
+  void* const* ptrs;
+  const float* coef;              // dense float32 coefficients [class][o][i]
+  const HPlane* planes;           // task planes, nmax spare records at the end
+  int out_slot;                   // pointer-table slot of the T3 planes
+};
+hipError_t launch_lh_fused(const LhFusedLaunch& f, hipStream_t s);
 
 struct HApplyLaunch {
   int np = 0;                  // > 0: outputs written as np bfloat16 planes

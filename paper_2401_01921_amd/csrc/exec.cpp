@@ -82,8 +82,18 @@ bool uses_planes(const PlanData& P, bst_precision prec) {
 int plane_count(bst_precision prec) { return prec == BST_FP64 ? 1 : prec == BST_BF16X6 ? 3 : 2; }
 int plane_count_of_key(int key) { return plane_count((bst_precision)(key - 10)); }
 
+// The fused L.psi + MPO kernel runs for the two-plane forms when the plan
+// has its schedule and the autotuner chose it; BST_FUSED_MPO=0 / 1
+// overrides the choice.
+bool fused_active(const PlanData& P, bst_precision prec) {
+  if (!P.fused_ok || !uses_planes(P, prec) || plane_count(prec) != 2) return false;
+  if (const char* e = std::getenv("BST_FUSED_MPO")) return std::strcmp(e, "0") != 0;
+  return P.fused_on;
+}
+
 bool step_runs(const PlanData& P, const Step& st, bst_precision prec, bool skip_const) {
   if (skip_const && st.constant) return false;
+  if (st.fusable && fused_active(P, prec)) return false;   // formed inside the fused MPO step
   if (st.kind == StepKind::Split && !uses_planes(P, prec)) return false;
   return true;
 }
@@ -244,6 +254,19 @@ void run_steps_impl(PlanData& P, void* ws, void* const* dptrs, bst_precision pre
         break;
       }
       case StepKind::HApply: {
+        if (planes && st.has_alt && st.fused.ok && fused_active(P, prec)) {
+          LhFusedLaunch f{};
+          f.nmax = st.nmax;
+          f.steps = reinterpret_cast<const KStep*>(blob + st.fused.steps_off);
+          f.wg_begin = reinterpret_cast<const int64_t*>(blob + st.fused.begin_off);
+          f.nwg = st.fused.nwg;
+          f.ptrs = dptrs;
+          f.coef = reinterpret_cast<const float*>(wsb + P.ws_coef32_off);
+          f.planes = reinterpret_cast<const HPlane*>(blob + st.fused_planes_off);
+          f.out_slot = st.tasks_alt.empty() ? 11 : st.tasks_alt[0].out_buf;
+          e = launch_lh_fused(f, s);
+          break;
+        }
         HApplyLaunch h{};
         h.t = inter;
         h.nmax = st.nmax;
@@ -352,12 +375,14 @@ static void save_cache(const char* path, const std::map<std::string, CachedShape
   f << "}\n";
 }
 
-// Cache entry of the FP64 variant choice (float64 panels or per-block-pair
-// kernels): keyed by the plan's first GEMM step, value [1, 0, 0, 0] for panels.
-constexpr int kVariantKey = 99;
-static std::string variant_key(const PlanData& P) {
+// Cache entries of the variant choices, keyed by the plan's first GEMM step:
+// FP64 float64 panels or per-block-pair kernels ([1, 0, 0, 0] for panels),
+// and the fused L.psi + MPO kernel for the two-plane forms ([1, 0, 0, 0]
+// when fused).
+constexpr int kVariantKey = 99, kFusedKey = 98;
+static std::string variant_key(const PlanData& P, int which = kVariantKey) {
   for (const auto& st : P.steps)
-    if (st.kind == StepKind::Gemm) return tune_key(P, st, kVariantKey);
+    if (st.kind == StepKind::Gemm) return tune_key(P, st, which);
   return std::string();
 }
 
@@ -370,6 +395,8 @@ void apply_tune_cache(PlanData& P) {
   if (!vk.empty()) {
     auto it = m.find(vk);
     if (it != m.end()) P.fp64_panels_on = it->second.bm != 0;
+    auto itf = m.find(variant_key(P, kFusedKey));
+    if (itf != m.end()) P.fused_on = itf->second.bm != 0;
   }
   for (auto& st : P.steps) {
     if (st.kind != StepKind::Gemm) continue;
@@ -618,6 +645,17 @@ bst_status bst_plan_autotune(bst_plan* p, const void* const* in, void* const* ou
     P.fp64_panels_on = t_panels < t_blocks;
     const std::string vk = variant_key(P);
     if (!vk.empty()) cache[vk] = {P.fp64_panels_on ? 1 : 0, 0, 0, 0};
+  } else if (P.fused_ok && uses_planes(P, form) && plane_count(form) == 2 && !std::getenv("BST_FUSED_MPO")) {
+    // two-plane form with a fused schedule: tune the GEMM tiles unfused, then
+    // keep the fused L.psi + MPO kernel if the whole apply is faster with it
+    P.fused_on = false;
+    tune_steps();
+    const double t_split = time_runs(-1);
+    P.fused_on = true;
+    const double t_fused = time_runs(-1);
+    P.fused_on = t_fused < t_split;
+    const std::string fk = variant_key(P, kFusedKey);
+    if (!fk.empty()) cache[fk] = {P.fused_on ? 1 : 0, 0, 0, 0};
   } else {
     tune_steps();
   }

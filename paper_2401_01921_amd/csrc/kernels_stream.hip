@@ -74,10 +74,24 @@ __device__ __forceinline__ void wait_and_meet_sel(int e) {
   }
 }
 
+// wait_and_meet<n> for a wave-uniform n in [LO, HI]
+template <int LO, int HI>
+__device__ __forceinline__ void wait_and_meet_rt(int n) {
+  if constexpr (LO == HI) {
+    wait_and_meet<LO>();
+  } else {
+    constexpr int MID = (LO + HI) / 2;
+    if (n <= MID)
+      wait_and_meet_rt<LO, MID>(n);
+    else
+      wait_and_meet_rt<MID + 1, HI>(n);
+  }
+}
+
 // A k-step record read from LDS, made wave-uniform.
 struct Rec {
   int64_t a, b, c;
-  int lda, ldb, rows, cols, kch, flags, kval, ldc, c_buf, a_buf, b_buf;
+  int lda, ldb, rows, cols, kch, flags, kval, pad, ldc, c_buf, a_buf, b_buf;
 };
 __device__ __forceinline__ bf16x8 bf(u4 x) { return __builtin_bit_cast(bf16x8, x); }
 __device__ __forceinline__ uint32_t uni(uint32_t x) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)x); }
@@ -97,6 +111,7 @@ __device__ __forceinline__ Rec read_rec(const unsigned char* p) {
   r.flags = (int)(pk >> 24);
   const uint32_t pk2 = uni(w1.w);
   r.kval = (int)(pk2 & 0xFF);
+  r.pad = (int)((pk2 >> 8) & 0xFF);
   r.c_buf = (int)(pk2 >> 16);
   r.c = (int64_t)((uint64_t)uni(w2.x) | ((uint64_t)uni(w2.y) << 32));
   r.ldc = (int)uni(w2.z);
@@ -568,6 +583,269 @@ hipError_t launch_gemm_planes_stream(const StreamLaunch& g, hipStream_t s) {
   BST_STREAM_SHAPES(BST_LAUNCH)
 #undef BST_LAUNCH
   return hipErrorInvalidValue;
+}
+
+// ------------------------------------------------------------------------
+// L.psi fused with the two-site MPO apply (two bfloat16 planes, BF16x3).
+//
+// One tile is 64 rows (a index) x 64 columns (b' index) of one MPO task
+// (a sector, b' sector).  For every input channel p = (w1, t1, t2) of the
+// task, T1_p = L_(a,w1) . psi_(a',t1,t2,b') over the contracted sector a'
+// (a' = a - w1) is accumulated in registers exactly as the L.psi GEMM
+// forms it (same k-steps, same products and order), then folded into the
+// task's outputs: out_o += h[o][p] T1_p over the nonzero coefficients in
+// increasing p, as the MPO apply adds them.  At the tile's end every output
+// is split into two bfloat16 planes and written to T3, so T1 never goes
+// through memory.  The records are those of the pipelined kernel; per
+// record pad = p, flags add kStepPlaneEnd on the last step of a channel,
+// c_buf = the task's output count, c = coefficient offset (low 32 bits) and
+// output-plane offset (high 32 bits), ldc = first row | first column << 16.
+// At a tile's first step the class's dense coefficients (NMAX x NMAX
+// floats) and its output planes (NMAX HPlane records) are copied into an LDS
+// ring slot beside the operand stages.
+// ------------------------------------------------------------------------
+template <int NMAX>
+__global__ __launch_bounds__(512) void lh_fused_kernel(const KStep* __restrict__ steps,
+                                                       const int64_t* __restrict__ wg_begin,
+                                                       void* const* __restrict__ ptrs,
+                                                       const float* __restrict__ coef,
+                                                       const HPlane* __restrict__ planes, int out_slot) {
+  constexpr int NP = 2, BM = 64, BN = 64, S = 3, WGM = 2, WGN = 4;
+  constexpr int NW = WGM * WGN, NT = 64 * NW;
+  constexpr int WM = BM / WGM, WN = BN / WGN, SM = WM / 16, SN = WN / 16;
+  constexpr int NC = 4 * NP;
+  constexpr int SLA = BM * NC, SLB = BN * NC;
+  constexpr int LPS = (SLA + SLB) / NT;
+  constexpr int BL = kStepBatch * 3 / NW;
+  constexpr int STB = (SLA + SLB) * 16;
+  constexpr int REC = S * STB;
+  constexpr int TABS = REC + kStepRing * kStepBatch * 48;
+  constexpr int TAB = NMAX * NMAX * 4 + NMAX * 16;
+  constexpr int LDSB = TABS + S * TAB;
+  static_assert(SLA % NT == 0 && SLB % NT == 0, "a copy round covers A or B slots only");
+  static_assert(BL * NW == kStepBatch * 3, "record copy");
+  static_assert(NMAX * NMAX / 4 <= 64 && NMAX <= 64, "table copies: one wave each");
+  static_assert(LDSB == lh_fused_lds_bytes(NMAX), "LDS layout");
+  __shared__ __attribute__((aligned(16))) unsigned char smem[LDSB];
+
+  const int64_t first = wg_begin[blockIdx.x];
+  const int n = (int)(wg_begin[blockIdx.x + 1] - first);
+  if (n <= 0) return;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = wave / WGN, wn = wave % WGN;
+  const uint32_t lds0 = (uint32_t)(uintptr_t)(BST_LDS unsigned char*)smem;
+  const unsigned char* gsteps = reinterpret_cast<const unsigned char*>(steps + first);
+  int a_buf = -1, b_buf = -1;
+  const unsigned short* A = nullptr;
+  const unsigned short* B = nullptr;
+  const void* zero = g_stream_zero + 4 * lane;
+  BST_G unsigned short* T3 = (BST_G unsigned short*)(ptrs[out_slot]);
+  BST_G unsigned short* sink =
+      (BST_G unsigned short*)(g_stream_sink + ((blockIdx.x % kSinkWgs) * 8 + wave) * 16) + (lane & 15);
+
+  auto copy_batch = [&](int bi) {
+    if (bi * kStepBatch < n && lane < BL)
+      lds_copy16(lds0 + REC + (uint32_t)(bi % kStepRing) * (kStepBatch * 48) + wave * (BL * 16),
+                 gsteps + (int64_t)bi * (kStepBatch * 48) + wave * (BL * 16) + lane * 16);
+  };
+  auto rec_ptr = [&](int v) -> const unsigned char* {
+    return smem + REC + ((v / kStepBatch) % kStepRing) * (kStepBatch * 48) + (v % kStepBatch) * 48;
+  };
+
+  int tiles_in = 0, tiles_out = 0;
+  auto issue = [&](int v) {
+    if (v % kStepBatch == 0) copy_batch(v / kStepBatch + 1);
+    const Rec d = read_rec(rec_ptr(v));
+    if (d.flags & kStepFirst) {
+      // the tile's coefficient block and output planes into its ring slot
+      const uint32_t tb = lds0 + TABS + (uint32_t)(tiles_in % S) * TAB;
+      const int64_t coff = (int64_t)(uint32_t)(d.c & 0xFFFFFFFF), poff = d.c >> 32;
+      if (wave == 0 && lane < NMAX * NMAX / 4) lds_copy16(tb, coef + coff + 4 * lane);
+      if (wave == 1 && lane < NMAX) lds_copy16(tb + NMAX * NMAX * 4, planes + poff + lane);
+      ++tiles_in;
+    }
+    if (d.a_buf != a_buf) {
+      a_buf = d.a_buf;
+      A = static_cast<const unsigned short*>(ptrs[a_buf]);
+    }
+    if (d.b_buf != b_buf) {
+      b_buf = d.b_buf;
+      B = static_cast<const unsigned short*>(ptrs[b_buf]);
+    }
+    const uint32_t sb = lds0 + (uint32_t)(v % S) * STB;
+#pragma unroll
+    for (int i = 0; i < LPS; ++i) {
+      const bool isA = i * NT < SLA;
+      const int sl = isA ? i * NT + tid : i * NT - SLA + tid;
+      const int r = sl / NC, cc = swz<NP>(r, sl % NC), kc = cc / NP;
+      const int row = min(r, (isA ? d.rows : d.cols) - 1);
+      const int64_t e = NP * (isA ? d.a + (int64_t)row * d.lda : d.b + (int64_t)row * d.ldb) + cc * 8;
+      const void* g = kc < d.kch ? static_cast<const void*>((isA ? A : B) + e) : zero;
+      lds_copy16(sb + (uint32_t)(i * NT * 16 + wave * 1024), g);
+    }
+  };
+
+  flt4 acc[SM][SN];
+  flt4 out[NMAX][SM][SN];
+
+  auto compute = [&](int u, const Rec& d) {
+    const unsigned short* As = reinterpret_cast<const unsigned short*>(smem + (u % S) * STB);
+    const unsigned short* Bs = As + BM * NC * 8;
+    const int kc = lane >> 4;
+    u4 a[NP][SM], b[NP][SN];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+#pragma unroll
+      for (int i = 0; i < SM; ++i) {
+        const int r = wm * WM + i * 16 + (lane & 15);
+        a[q][i] = *reinterpret_cast<const u4*>(As + r * NC * 8 + swz<NP>(r, kc * NP + q) * 8);
+      }
+#pragma unroll
+      for (int j = 0; j < SN; ++j) {
+        const int r = wn * WN + j * 16 + (lane & 15);
+        b[q][j] = *reinterpret_cast<const u4*>(Bs + r * NC * 8 + swz<NP>(r, kc * NP + q) * 8);
+      }
+    }
+    if (d.kval < 8) {
+      const bool part = kc == d.kch - 1;
+      auto mk = [&](int e) -> uint32_t {
+        return !part ? ~0u : ((2 * e < d.kval ? 0xFFFFu : 0u) | (2 * e + 1 < d.kval ? 0xFFFF0000u : 0u));
+      };
+      const u4 m = {mk(0), mk(1), mk(2), mk(3)};
+#pragma unroll
+      for (int q = 0; q < NP; ++q) {
+#pragma unroll
+        for (int i = 0; i < SM; ++i) a[q][i] &= m;
+#pragma unroll
+        for (int j = 0; j < SN; ++j) b[q][j] &= m;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < SM; ++i)
+#pragma unroll
+      for (int j = 0; j < SN; ++j) {
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf(a[1][i]), bf(b[0][j]), acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf(a[0][i]), bf(b[1][j]), acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf(a[0][i]), bf(b[0][j]), acc[i][j], 0, 0, 0);
+      }
+  };
+
+  // T1_p (acc) into the outputs: out_o += h[o][p] T1_p for nonzero h
+  auto fold = [&](const Rec& d) {
+    const float* ct = reinterpret_cast<const float*>(smem + TABS + (tiles_out % S) * TAB);
+    const int p = d.pad, nout = d.c_buf;
+#pragma unroll
+    for (int o = 0; o < NMAX; ++o) {
+      const float hv = o < nout ? ct[o * NMAX + p] : 0.0f;
+      if (hv != 0.0f) {
+#pragma unroll
+        for (int i = 0; i < SM; ++i)
+#pragma unroll
+          for (int j = 0; j < SN; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) out[o][i][j][r] += hv * acc[i][j][r];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < SM; ++i)
+#pragma unroll
+      for (int j = 0; j < SN; ++j) acc[i][j] = flt4{0, 0, 0, 0};
+  };
+
+  // every output o < nout: 2 * SM * SN * 4 stores per lane (lanes outside
+  // the tile to the sink); returns the store count
+  auto epilogue = [&](const Rec& d) -> int {
+    const HPlane* qp = reinterpret_cast<const HPlane*>(smem + TABS + (tiles_out % S) * TAB + NMAX * NMAX * 4);
+    const int nout = d.c_buf, m0 = d.ldc & 0xFFFF, n0 = (int)((uint32_t)d.ldc >> 16);
+#pragma unroll
+    for (int o = 0; o < NMAX; ++o) {
+      if (o < nout) {
+        const HPlane q = qp[o];
+#pragma unroll
+        for (int i = 0; i < SM; ++i)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = wm * WM + i * 16 + 4 * (lane >> 4) + r;
+#pragma unroll
+            for (int j = 0; j < SN; ++j) {
+              const int col = wn * WN + j * 16 + (lane & 15);
+              const bool in = row < d.rows && col < d.cols;
+              const int64_t at = q.off + (int64_t)(m0 + row) * q.rowstride + (n0 + col);
+              const float yf = out[o][i][j][r];
+              unsigned int u = __float_as_uint(yf);
+              const unsigned short h0 = (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+              const float r1 = yf - __uint_as_float((unsigned int)h0 << 16);
+              u = __float_as_uint(r1);
+              const unsigned short h1 = (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+              *(in ? T3 + plane_at(NP, at, 0) : sink) = h0;
+              *(in ? T3 + plane_at(NP, at, 1) : sink) = h1;
+            }
+          }
+      }
+    }
+#pragma unroll
+    for (int o = 0; o < NMAX; ++o)
+#pragma unroll
+      for (int i = 0; i < SM; ++i)
+#pragma unroll
+        for (int j = 0; j < SN; ++j) out[o][i][j] = flt4{0, 0, 0, 0};
+    ++tiles_out;
+    return nout * 2 * SM * SN * 4;
+  };
+
+#pragma unroll
+  for (int o = 0; o < NMAX; ++o)
+#pragma unroll
+    for (int i = 0; i < SM; ++i)
+#pragma unroll
+      for (int j = 0; j < SN; ++j) out[o][i][j] = flt4{0, 0, 0, 0};
+#pragma unroll
+  for (int i = 0; i < SM; ++i)
+#pragma unroll
+    for (int j = 0; j < SN; ++j) acc[i][j] = flt4{0, 0, 0, 0};
+
+  copy_batch(0);
+  wait_and_meet<0>();
+  int v = 0;
+  for (; v < n && v < S - 1; ++v) issue(v);
+  // store instructions issued in the last S - 1 iterations (newest first)
+  int st0 = 0, st1 = 0;
+  for (int u = 0; u < n; ++u) {
+    // outstanding after step u's copies: the copies of steps u+1 .. u+S-2
+    // and the stores issued since step u was issued (a lower bound of the
+    // memory operations issued after step u's copies)
+    if (n - 1 - u >= S - 2) {
+      const int w = (S - 2) * LPS + st0 + st1;
+      wait_and_meet_rt<0, 63>(w < 63 ? w : 63);
+    } else {
+      wait_and_meet<0>();
+    }
+    if (v < n) {
+      issue(v);
+      ++v;
+    }
+    const Rec d = read_rec(rec_ptr(u));
+    compute(u, d);
+    if (d.flags & kStepPlaneEnd) fold(d);
+    st1 = st0;
+    st0 = (d.flags & kStepLast) ? epilogue(d) : 0;
+  }
+}
+
+hipError_t launch_lh_fused(const LhFusedLaunch& f, hipStream_t s) {
+  if (f.nwg <= 0) return hipSuccess;
+  if (f.nwg > 0x7FFFFFFF) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)f.nwg), block(512);
+  if (f.nmax == 8)
+    hipLaunchKernelGGL(lh_fused_kernel<8>, grid, block, 0, s, f.steps, f.wg_begin, f.ptrs, f.coef, f.planes,
+                       f.out_slot);
+  else if (f.nmax == 16)
+    hipLaunchKernelGGL(lh_fused_kernel<16>, grid, block, 0, s, f.steps, f.wg_begin, f.ptrs, f.coef, f.planes,
+                       f.out_slot);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
 }
 
 }  // namespace bst

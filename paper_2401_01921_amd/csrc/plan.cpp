@@ -672,6 +672,7 @@ static void heff_plan(const TensorDesc& L, const TensorDesc& W1, const TensorDes
   s1.name = "gemm_L_psi";
   s1.tc = Elem::Inter;
   s1.has_alt = true;
+  s1.fusable = true;
   {
     const int nA = (int)psi.legs[0].q.size();
     int32_t lt[3], pt[4];
@@ -800,6 +801,7 @@ static void heff_plan(const TensorDesc& L, const TensorDesc& W1, const TensorDes
     for (int ka = 0; ka < nA; ++ka)
       for (int ky = 0; ky < nY; ++ky) {
         std::vector<HPlane> ins, ins_alt, outs, outs_alt;
+        std::vector<Step::FusedIn> fin;
         std::vector<int64_t> key;   // class key: input then output element triples
         for (int kw = 0; kw < (int)lw.q.size(); ++kw)
           for (int k1 = 0; k1 < (int)lt1.q.size(); ++k1)
@@ -830,11 +832,17 @@ static void heff_plan(const TensorDesc& L, const TensorDesc& W1, const TensorDes
                     ins.push_back({T1->offset[b] + in_blk, gw * g1 * g2 * gy});
                     if (t1zero[b] >= 0) {
                       ins_alt.push_back({t1zero[b] + in_blk, gw * g1 * g2 * gy});
+                      fin.push_back({0, 0, 0, 0, 0, 0});
                     } else {
                       const int64_t ld = t1m_ld[kx];
                       ins_alt.push_back({t1m_start[kx] + (Lg.grow[lb] + c) * ld + pcol[pb] +
                                              (e1 * g2 + e2) * gy,
                                          gw * ld});
+                      // the GEMM of this T1 plane: L rows (grow + c + i gw) of
+                      // the a' group against psi rows ((e1 g2 + e2) gy + j)
+                      const int64_t K = psi.legs[0].g[kx], kp = pad32(K);
+                      fin.push_back({Lg.gstart[kx] + (Lg.grow[lb] + c) * kp, Pp.off[pb] + (e1 * g2 + e2) * gy * kp,
+                                     (int32_t)(gw * kp), (int32_t)kp, (int32_t)K, 0});
                     }
                     key.push_back(lwm.start[kw] + c);
                     key.push_back(lt1m.start[k1] + e1);
@@ -925,6 +933,8 @@ static void heff_plan(const TensorDesc& L, const TensorDesc& W1, const TensorDes
         for (auto& q : outs) ha.planes.push_back(q);
         ha.tasks.push_back(task);
         ha.task_group.push_back(ka);
+        ha.task_fin.push_back((int32_t)ha.fins.size());
+        for (auto& f : fin) ha.fins.push_back(f);
         for (auto& q : ins_alt) ha.planes_alt.push_back(q);
         for (auto& q : outs_alt) ha.planes_alt.push_back(q);
         HTask ta = task;
@@ -1369,6 +1379,132 @@ static Step::StreamList make_stream(std::vector<uint8_t>& blob, const Step& st, 
   return L;
 }
 
+// k-step schedule of the fused L.psi + MPO kernel (two bfloat16 planes):
+// 64 x 64 tiles of every task of tasks_alt, each tile's records channel by
+// channel (the k-steps of input p's GEMM, the last flagged kStepPlaneEnd).
+// Tiles go to the XCDs by a sector (as the MPO work items: tasks of one a
+// share L rows, psi blocks and T3 rows), largest a first to the least
+// loaded XCD; there, by first row, each to the least loaded workgroup.  ok
+// stays false unless every task fits the kernel (nmax <= 16 inputs and
+// outputs, 16-byte aligned operands).
+static Step::StreamList make_fused(std::vector<uint8_t>& blob, const Step& st, int nmax) {
+  Step::StreamList L;
+  constexpr int bm = 64, bn = 64;
+  const int64_t kdeep = 32, kchunk = 8, nchunk = 4;
+  auto padc = [&](int64_t K) { return (K + kchunk - 1) / kchunk * kchunk; };
+  if (st.fins.empty() || st.tasks_alt.size() != st.task_fin.size() || nmax > 16) return L;
+  for (size_t ti = 0; ti < st.tasks_alt.size(); ++ti) {
+    const HTask& t = st.tasks_alt[ti];
+    if (t.nin > nmax || t.nout > nmax || t.nin > 255) return L;
+    for (int p = 0; p < t.nin; ++p) {
+      const auto& f = st.fins[(size_t)st.task_fin[ti] + p];
+      if (f.K > 0 && (f.a_off % 8 || f.b_off % 8 || f.a_ld % 8 || f.b_ld % 8)) return L;
+    }
+  }
+  struct Tile {
+    int32_t task, m0, n0;
+    int64_t steps;
+  };
+  auto tile_steps = [&](int32_t ti) {
+    int64_t k = 0;
+    const HTask& t = st.tasks_alt[ti];
+    for (int p = 0; p < t.nin; ++p) {
+      const int32_t K = st.fins[(size_t)st.task_fin[ti] + p].K;
+      if (K > 0) k += (padc(K) + kdeep - 1) / kdeep;
+    }
+    return std::max<int64_t>(k, 1);
+  };
+  std::map<int32_t, std::vector<Tile>> groups;
+  std::map<int32_t, int64_t> gcost;
+  for (size_t ti = 0; ti < st.tasks_alt.size(); ++ti) {
+    const HTask& t = st.tasks_alt[ti];
+    const int32_t g = ti < st.task_group.size() ? st.task_group[ti] : 0;
+    const int64_t ks = tile_steps((int32_t)ti);
+    for (int m0 = 0; m0 < t.rows; m0 += bm)
+      for (int n0 = 0; n0 < t.cols; n0 += bn) {
+        groups[g].push_back({(int32_t)ti, m0, n0, ks + 2});
+        gcost[g] += ks + 2;
+      }
+  }
+  std::vector<std::pair<int64_t, int32_t>> order;
+  for (auto& kv : gcost) order.push_back({kv.second, kv.first});
+  std::stable_sort(order.begin(), order.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
+  std::vector<std::vector<Tile>> bins(kXcds);
+  std::vector<int64_t> xload(kXcds, 0);
+  for (const auto& o : order) {
+    int x = 0;
+    for (int i = 1; i < kXcds; ++i)
+      if (xload[i] < xload[x]) x = i;
+    xload[x] += o.first;
+    auto& tl = groups[o.second];
+    std::stable_sort(tl.begin(), tl.end(), [](const Tile& a, const Tile& b) { return a.m0 < b.m0; });
+    bins[x].insert(bins[x].end(), tl.begin(), tl.end());
+  }
+  const int64_t nwg = kStreamCUs;   // one workgroup of 8 waves per CU
+  std::vector<std::vector<Tile>> per(nwg);
+  std::vector<int64_t> wload(nwg, 0);
+  for (int x = 0; x < kXcds; ++x)
+    for (const auto& t : bins[x]) {
+      int64_t w = x;
+      for (int64_t c = x + kXcds; c < nwg; c += kXcds)
+        if (wload[c] < wload[w]) w = c;
+      per[w].push_back(t);
+      wload[w] += t.steps;
+    }
+  std::vector<KStep> recs;
+  std::vector<int64_t> begin((size_t)nwg + 1, 0);
+  for (int64_t w = 0; w < nwg; ++w) {
+    begin[w] = (int64_t)recs.size();
+    for (const auto& tl : per[w]) {
+      const HTask& t = st.tasks_alt[tl.task];
+      KStep base{};
+      base.rows1 = (uint8_t)(std::min(bm, t.rows - tl.m0) - 1);
+      base.cols1 = (uint8_t)(std::min(bn, t.cols - tl.n0) - 1);
+      base.c_buf = (uint16_t)t.nout;
+      base.c = (int64_t)((uint64_t)(uint32_t)(t.cls * nmax * nmax) |
+                         ((uint64_t)(uint32_t)(t.plane_begin + t.nin) << 32));
+      base.ldc = (int32_t)((uint32_t)tl.m0 | ((uint32_t)tl.n0 << 16));
+      base.a_buf = 8;
+      base.b_buf = 10;
+      base.kval = (uint8_t)kchunk;
+      const size_t first = recs.size();
+      for (int p = 0; p < t.nin; ++p) {
+        const auto& f = st.fins[(size_t)st.task_fin[tl.task] + p];
+        if (f.K <= 0) continue;
+        const int64_t K8 = padc(f.K);
+        for (int64_t lk = 0; lk < K8; lk += kdeep) {
+          KStep k = base;
+          k.a = f.a_off + (int64_t)tl.m0 * f.a_ld + lk;
+          k.b = f.b_off + (int64_t)tl.n0 * f.b_ld + lk;
+          k.lda = f.a_ld;
+          k.ldb = f.b_ld;
+          k.pad = (uint8_t)p;
+          k.kch = (uint8_t)std::min<int64_t>(nchunk, (K8 - lk) / kchunk);
+          k.kval = (uint8_t)((lk + kchunk * k.kch == K8 && f.K % kchunk) ? f.K % kchunk : kchunk);
+          recs.push_back(k);
+        }
+        recs.back().flags |= kStepPlaneEnd;
+      }
+      if (recs.size() == first) {   // every input zero: one step of zeros writes the tile
+        KStep k = base;
+        k.kch = 0;
+        k.pad = 0;
+        k.flags = kStepPlaneEnd;
+        recs.push_back(k);
+      }
+      recs[first].flags |= kStepFirst;
+      recs.back().flags |= kStepLast;
+    }
+  }
+  begin[nwg] = (int64_t)recs.size();
+  recs.resize(recs.size() + kStepBatch, KStep{});
+  L.steps_off = put(blob, recs);
+  L.begin_off = put(blob, begin);
+  L.nwg = nwg;
+  L.ok = true;
+  return L;
+}
+
 int default_tile(const Step& st, bst_precision form) {
   auto it = st.tile_choice.find((int)form);
   if (it != st.tile_choice.end()) return it->second;
@@ -1388,6 +1524,7 @@ int default_tile(const Step& st, bst_precision form) {
 void finalize(PlanData& P) {
   P.blob.clear();
   P.coef_entries = 0;
+  P.fused_ok = false;
   for (auto& st : P.steps) {
     switch (st.kind) {
       case StepKind::Gemm: {
@@ -1532,6 +1669,12 @@ void finalize(PlanData& P) {
         if (st.has_alt) {
           st.off3 = put(P.blob, st.tasks_alt);
           st.off4 = put(P.blob, st.planes_alt);
+          // the fused kernel copies nmax output planes per tile: spare records
+          std::vector<HPlane> pl = st.planes_alt;
+          pl.resize(pl.size() + (size_t)st.nmax, HPlane{0, 0});
+          st.fused_planes_off = put(P.blob, pl);
+          st.fused = make_fused(P.blob, st, st.nmax);
+          if (st.fused.ok) P.fused_ok = true;
         }
         break;
       }
@@ -1816,11 +1959,16 @@ bst_status bst_plan_tiles(const bst_plan* p, char* buf, size_t cap) {
   const PlanData& P = p->p;
   for (const auto& st : P.steps) {
     if (st.kind == StepKind::HApply) {
+      if (st.fused.ok && fused_active(P, P.prec)) {
+        s += st.name + ":fused64x64;";   // L.psi formed inside the MPO step
+        continue;
+      }
       const bool o32 = uses_planes(P, P.prec) && st.has_alt ? st.mpo_off32_alt : st.mpo_off32;
       s += st.name + (o32 ? ":i32;" : ":i64;");
       continue;
     }
     if (st.kind != StepKind::Gemm) continue;
+    if (st.fusable && fused_active(P, P.prec)) continue;
     const bool pl = uses_planes(P, P.prec) && st.has_alt;
     const TileShape sh = pl ? gemm_planes_shapes(plane_count(P.prec))[planes_tile(st, P.prec)]
                             : gemm_tile_shapes(P.prec)[default_tile(st, P.prec)];

@@ -68,6 +68,17 @@ struct Step {
   std::vector<HTask> tasks;
   std::vector<HPlane> planes;
   std::vector<int32_t> task_group;   // per task: its a sector (tasks of one a share T1 and T3 rows)
+  // L.psi fused into the MPO apply (plane variant of an H_eff plan): per
+  // input plane of tasks_alt, the GEMM that forms it (L rows of (a, w1)
+  // against the transposed psi block (a', t1, t2, b'), K = g(a'); K = 0 for
+  // T1 blocks no pair reaches), and task_fin[t] = first input of task t
+  struct FusedIn {
+    int64_t a_off, b_off;
+    int32_t a_ld, b_ld, K, pad;
+  };
+  std::vector<FusedIn> fins;
+  std::vector<int32_t> task_fin;
+  bool fusable = false;              // an L.psi GEMM step the fused kernel replaces
   Elem th = Elem::Inter;
   // bfloat16-plane variant used by the split forms (H_eff only): GEMM
   // segments on pre-split operands, MPO tasks writing T3 as planes
@@ -103,6 +114,8 @@ struct Step {
     int64_t nwg = 0;
   };
   std::map<int, StreamList> streams_alt;
+  StreamList fused;                  // HApply: k-step schedule of the fused kernel
+  size_t fused_planes_off = 0;       // tasks_alt planes with nmax spare records
 };
 
 struct InternalBuf {
@@ -129,6 +142,8 @@ struct PlanData {
   // FP64 runs on the float64 panels (chosen by the autotuner when its whole
   // apply is faster than with the per-block-pair kernels)
   bool fp64_panels_on = false;
+  bool fused_ok = false;             // an MPO step has a fused schedule (two-plane forms)
+  bool fused_on = false;             // run it (autotuner choice, BST_FUSED_MPO overrides)
   bool sparse_mpo = true;       // MPO apply runs only the nonzero h entries
   // finalize
   std::vector<uint8_t> blob;
@@ -172,6 +187,7 @@ int plane_count(bst_precision prec);
 // Plane count of a tile-choice key of the padded-layout variant (10 + form).
 int plane_count_of_key(int key);
 bool step_runs(const PlanData& p, const Step& st, bst_precision prec, bool skip_const);
+bool fused_active(const PlanData& p, bst_precision prec);
 int planes_tile(const Step& st, bst_precision prec);
 int default_tile(const Step& st, bst_precision form);
 void run_steps_impl(PlanData& p, void* ws, void* const* dptrs, bst_precision prec, hipStream_t s,

@@ -407,3 +407,27 @@ def test_fp64_autotuned_variant(k):
     b = run_heff(plan, O)
     check(a, ref, "fp64", f"fp64 autotuned {plan.tiles()}")
     assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("case", ["chi512", "chi4096"])
+def test_fused_lpsi_mpo(case, monkeypatch):
+    """L.psi fused into the MPO apply (BF16x3): T1 is formed in registers
+    with the same products in the same order as the L.psi GEMM and folded
+    into the outputs in the MPO apply's order, so the result equals the
+    two-kernel path bit for bit, and the oracle within the form's bar.
+    chi512: spin-1/2 operator; chi4096: the spin-1 Lanczos operator."""
+    if case == "chi512":
+        specs, O = heff_operands(2)
+    else:
+        specs, O = heff_operands(5, recipe="dmrg_like")
+    ref = orc.heff_apply(O["L"], O["W1"], O["W2"], O["R"], O["psi"]).data
+    monkeypatch.setenv("BST_FUSED_MPO", "0")
+    T, plan = lib_heff(specs, "bf16x3")
+    two = run_heff(plan, O)
+    assert "mpo_apply:i" in plan.tiles()
+    monkeypatch.setenv("BST_FUSED_MPO", "1")
+    assert "mpo_apply:fused" in plan.tiles() and "gemm_L_psi" not in plan.tiles(), plan.tiles()
+    fused = run_heff(plan, O)
+    _print("fused", case, plan.tiles(), "max|diff| vs two kernels", float(np.max(np.abs(fused - two))))
+    assert np.array_equal(fused, two)
+    check(fused, ref, "bf16x3", f"fused L.psi + MPO {case}")

@@ -298,3 +298,21 @@ def test_complex_output_rank_limit():
     with pytest.raises(bst.BstError) as e:
         bst.contract_plan(A, B, "fp64", dtype="c128")
     assert e.value.status == "E_INVALID" and "rank 7" in str(e.value)
+
+
+@pytest.mark.parametrize("k", [2, 5])
+def test_fused_mpo_schedule_built(k, monkeypatch):
+    """The plan builds the fused L.psi + MPO schedule for the H_eff operators
+    (spin-1/2 chi = 512, spin-1 chi = 4096): with BST_FUSED_MPO=1 the BF16x3
+    form reports the fused step and no L.psi GEMM; FP64 never fuses."""
+    from paper_2401_01921_amd import workloads as wl
+    T = {n: bst.Tensor(*s) for n, s in wl.heff_workload_specs(k).items()}
+    plan = bst.heff_plan(T["L"], T["W1"], T["W2"], T["R"], T["psi"], "bf16x3")
+    monkeypatch.setenv("BST_FUSED_MPO", "1")
+    tiles = plan.tiles()
+    assert "mpo_apply:fused" in tiles and "gemm_L_psi" not in tiles, tiles
+    plan.set_precision("fp64")
+    assert "gemm_L_psi" in plan.tiles()
+    monkeypatch.setenv("BST_FUSED_MPO", "0")
+    plan.set_precision("bf16x3")
+    assert "gemm_L_psi" in plan.tiles()
