@@ -842,55 +842,35 @@ __global__ __launch_bounds__(64) void lanczos_end_kernel(const double* __restric
 }
 
 // The scalar work between two basis passes, in one block of 1024 threads:
-// the sums of the partials of the pass of step pj (dn) and of the u_j.z,
-// z.z partials of dot2_kernel (g), then the end of step pj (alpha, beta,
-// dprev as lanczos_end_kernel) and the scalars of step j.  One wave forms
-// each sum: lane l adds partials l, l + 64, ... in order, then the wave sum;
-// every load of a sum is issued at once (grids of at most 1024 blocks).  The
-// scalars then take one wave, lane-parallel over k.  pj < 0: no pass before
-// (step 0).
+// the sums of the u_j.z, z.z partials of dot2_kernel (g) beside the sums of
+// the pass of step pj that dot2_kernel already left in dn, then the end of
+// step pj (alpha, beta, dprev as lanczos_end_kernel) and the scalars of step
+// j.  One wave forms each sum: lane l adds partials l, l + 64, ... in order,
+// then the wave sum; every load of a sum is issued at once (grids of at most
+// 1024 blocks).  The scalars then take one wave, lane-parallel over k.
+// pj < 0: no pass before (step 0).
 __global__ __launch_bounds__(1024) void lanczos_step_scalars_kernel(
-    const double* __restrict__ ppart, int pG, int pj, const double* __restrict__ dpart, int dG,
-    int j, double* __restrict__ dn, double* __restrict__ g, double* __restrict__ alpha,
-    double* __restrict__ beta, double* __restrict__ dprev, double* __restrict__ coef,
-    double* __restrict__ aest) {
+    int pj, const double* __restrict__ dpart, int dG, int j, double* __restrict__ dn,
+    double* __restrict__ g, double* __restrict__ alpha, double* __restrict__ beta,
+    double* __restrict__ dprev, double* __restrict__ coef, double* __restrict__ aest) {
   __shared__ double sv[kMaxVecs + 4];
   __shared__ double al[kMaxVecs], be[kMaxVecs];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int npv = pj >= 0 ? pj + 2 : 0;
-  const int nval = npv + 2;
-  // value v: the partials of row v of the pass (v < npv) or of the dot
-  auto row_of = [&](int v, int& G) -> const double* {
-    G = v < npv ? pG : dG;
-    return v < npv ? ppart + (int64_t)v * pG : dpart + (int64_t)(v - npv) * dG;
-  };
-  // values wave, wave + 16, wave + 32: all loads in flight together
-  double x[3][16];
+  // sv[0..npv): the previous pass's sums, formed by dot2_kernel into dn
+  for (int k = tid; k < npv; k += 1024) sv[k] = dn[k];
+  // sv[npv], sv[npv + 1]: u_j.z and z.z, one wave each (lane l adds
+  // partials l, l + 64, ..., then the wave sum)
+  if (wave < 2) {
+    const double* __restrict__ src = dpart + (int64_t)wave * dG;
+    double x[16];
 #pragma unroll
-  for (int r = 0; r < 3; ++r) {
-    const int v = wave + 16 * r;
-    int G = 0;
-    const double* __restrict__ src = row_of(v < nval ? v : 0, G);
+    for (int i = 0; i < 16; ++i) x[i] = lane + 64 * i < dG ? src[lane + 64 * i] : 0.0;
+    double t = 0.0;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) x[r][i] = (v < nval && lane + 64 * i < G) ? src[lane + 64 * i] : 0.0;
-  }
-#pragma unroll
-  for (int r = 0; r < 3; ++r) {
-    double s = 0.0;
-#pragma unroll
-    for (int i = 0; i < 16; ++i) s += x[r][i];
-    s = wave_sum(s);
-    if (wave + 16 * r < nval && lane == 0) sv[wave + 16 * r] = s;
-  }
-  // more than 48 values (long solves): the same sums, one value at a time
-  for (int v = wave + 48; v < nval; v += 16) {
-    int G = 0;
-    const double* __restrict__ src = row_of(v, G);
-    double s = 0.0;
-#pragma unroll
-    for (int i = 0; i < 16; ++i) s += lane + 64 * i < G ? src[lane + 64 * i] : 0.0;
-    s = wave_sum(s);
-    if (lane == 0) sv[v] = s;
+    for (int i = 0; i < 16; ++i) t += x[i];
+    t = wave_sum(t);
+    if (lane == 0) sv[npv + wave] = t;
   }
   for (int k = tid; k < pj; k += 1024) {
     al[k] = alpha[k];
@@ -898,10 +878,7 @@ __global__ __launch_bounds__(1024) void lanczos_step_scalars_kernel(
   }
   __syncthreads();
   // sv[0..npv) = dn of step pj, sv[npv] = u_j.z, sv[npv + 1] = z.z
-  for (int k = tid; k < npv; k += 1024) {
-    dn[k] = sv[k];
-    if (k <= pj) dprev[k] = sv[k];
-  }
+  for (int k = tid; k <= pj; k += 1024) dprev[k] = sv[k];
   if (wave != 0) return;
   // The rest in wave 0, lane-parallel over the step index k (k < kMaxVecs,
   // two per lane).  Each sum is a wave_sum in a fixed order whose result
@@ -1100,8 +1077,29 @@ hipError_t launch_scale_rnorm(const double* src, const double* norm2, float* dst
 template <typename TX, typename TY, bool PAIR>
 __global__ __launch_bounds__(256) void dot2_kernel(const TX* __restrict__ x,
                                                    const TY* __restrict__ y, int64_t n,
-                                                   double* __restrict__ partial) {
+                                                   double* __restrict__ partial,
+                                                   const double* __restrict__ ppart = nullptr,
+                                                   int pG = 0, int npv = 0,
+                                                   double* __restrict__ psum = nullptr) {
   __shared__ double red[4 * 2];
+  // Inside a Lanczos step: wave 0 of workgroup v (v < npv) also sums row v
+  // of the previous basis pass's partials (pG <= 1024 per row) into psum[v],
+  // in the step scalars kernel's order (lane l adds entries l, l + 64, ...,
+  // then the wave sum), so that kernel reads npv finished sums.
+  if (npv > 0 && threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    for (int v = blockIdx.x; v < npv; v += gridDim.x) {
+      const double* __restrict__ src = ppart + (int64_t)v * pG;
+      double xs[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) xs[i] = lane + 64 * i < pG ? src[lane + 64 * i] : 0.0;
+      double t = 0.0;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) t += xs[i];
+      t = wave_sum(t);
+      if (lane == 0) psum[v] = t;
+    }
+  }
   double acc[2] = {0.0, 0.0};
   if constexpr (PAIR && sizeof(TX) == 4 && sizeof(TY) == 4) {
     typedef float fl2 __attribute__((ext_vector_type(2)));
@@ -1181,12 +1179,16 @@ static hipError_t dot_step_impl(const TX* x, const TZ* z, int64_t n, double* dpa
   // the basis pass's grid: one element (float64 rows) or pair (float32) per lane
   const int pG = sizeof(TX) == 4 ? pass_grid_f32(n) : pass_grid_f64(n);
   if (G > 1024 || pG > 1024) return hipErrorInvalidValue;
+  // the previous pass's sums go straight into dn (the scalars kernel reads them there)
+  const int npv = pj >= 0 ? pj + 2 : 0;
   if (pair)
-    hipLaunchKernelGGL((dot2_kernel<TX, TZ, true>), dim3(G), dim3(256), 0, s, x, z, n, dpart);
+    hipLaunchKernelGGL((dot2_kernel<TX, TZ, true>), dim3(G), dim3(256), 0, s, x, z, n, dpart, ppart, pG, npv,
+                       dn);
   else
-    hipLaunchKernelGGL((dot2_kernel<TX, TZ, false>), dim3(G), dim3(256), 0, s, x, z, n, dpart);
-  hipLaunchKernelGGL(lanczos_step_scalars_kernel, dim3(1), dim3(1024), 0, s, ppart, pG, pj, dpart, G, j,
-                     dn, g, alpha, beta, dprev, coef, aest);
+    hipLaunchKernelGGL((dot2_kernel<TX, TZ, false>), dim3(G), dim3(256), 0, s, x, z, n, dpart, ppart, pG, npv,
+                       dn);
+  hipLaunchKernelGGL(lanczos_step_scalars_kernel, dim3(1), dim3(1024), 0, s, pj, dpart, G, j, dn, g, alpha,
+                     beta, dprev, coef, aest);
   return hipGetLastError();
 }
 hipError_t launch_lanczos_dot_step(const double* x, const double* z, int64_t n, double* dpart,
