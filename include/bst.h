@@ -271,7 +271,14 @@ bst_status bst_execute_static(bst_plan* p, const void* const* in, void* const* o
 
 /* Times every compiled tile shape of each GEMM step on the given buffers,
  * keeps the fastest per step and (if the environment variable BST_TUNE_CACHE
- * names a file) records the choice there.  Synchronises the stream. */
+ * names a file) records the choice there.  Each candidate is timed after a
+ * read of a 512 MiB buffer (allocated for the call, freed before it returns)
+ * and after the steps before it, as an iterative caller would run it.  With
+ * FP64 on padded layouts it also chooses between the float64-panel and the
+ * per-block-pair kernels, and with BF16X3 between the two-kernel L.psi + MPO
+ * steps and the fused kernel, by whole-apply time; BST_FP64_PANELS /
+ * BST_FP64_BLOCKS and BST_FUSED_MPO=0/1 fix those choices instead.  Both
+ * choices go into the tile cache.  Synchronises the stream. */
 bst_status bst_plan_autotune(bst_plan* p, const void* const* in, void* const* out, void* ws,
                              void* stream, int32_t reps);
 
