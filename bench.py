@@ -227,7 +227,10 @@ def main():
 
     mpo_bytes = steps["mpo_apply"]["bytes_fp32" if inter32 else "bytes_fp64"]
     kern = {
-        "gemm_L_psi": gemm_roof("gemm_L_psi", prof_split, a.prec),
+        # with the fused L.psi + MPO kernel the split solve has no L.psi launches
+        # of its own (the refinement's FP64 one remains): no roofline of its own
+        "gemm_L_psi": (None if "mpo_apply:fused" in tuned[a.prec]
+                       else gemm_roof("gemm_L_psi", prof_split, a.prec)),
         "gemm_T3_R": gemm_roof("gemm_T3_R", prof_split, a.prec),
         "mpo_apply": hbm_roof("mpo_apply", mpo_bytes * kc["mpo_apply"], prof_split),
         "gs_dots": hbm_roof("gs_dots", gs_bytes("dots"), prof_split),
@@ -237,7 +240,7 @@ def main():
         "fp64_gs_update": hbm_roof("gs_update", gs_bytes("update"), prof64),
     }
     # dominant kernel of the step = largest summed time
-    dom = max((k for k in km if k in kern), key=km.get)
+    dom = max((k for k in km if kern.get(k) is not None), key=km.get)
     r = kern[dom]
     if dom.startswith("gemm"):
         roof = {"bound": "mfma", "kernel": dom, "achieved": round(r["mfma_tflops"], 2),
