@@ -1440,7 +1440,8 @@ static Step::StreamList make_fused(std::vector<uint8_t>& blob, const Step& st, i
     std::stable_sort(tl.begin(), tl.end(), [](const Tile& a, const Tile& b) { return a.m0 < b.m0; });
     bins[x].insert(bins[x].end(), tl.begin(), tl.end());
   }
-  const int64_t nwg = kStreamCUs;   // one workgroup of 8 waves per CU
+  // one workgroup of 8 waves per CU (16 outputs: 194 VGPRs), two with 8
+  const int64_t nwg = (int64_t)kStreamCUs * (nmax <= 8 ? 2 : 1);
   std::vector<std::vector<Tile>> per(nwg);
   std::vector<int64_t> wload(nwg, 0);
   for (int x = 0; x < kXcds; ++x)
