@@ -55,10 +55,18 @@ __global__ __launch_bounds__(64 * kSvdWaves) void svd_jacobi_kernel(const SvdSec
   constexpr int NT = 64 * kSvdWaves;
   const SvdSec S = secs[blockIdx.x];
   const int p = S.m >= S.n ? S.m : S.n, r = S.m >= S.n ? S.n : S.m;
-  double* x = X + S.x_off;
-  double* vh = V + S.v_off;
+  double* const xg = X + S.x_off;
+  double* const vg = V + S.v_off;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   __shared__ int rotated;
+  // A sector whose X and Vh fit in LDS (kSvdLdsBytes) is rotated there and
+  // copied back at the end; larger ones work in global memory.
+  __shared__ double lds[kSvdLdsBytes / sizeof(double)];
+  const bool in_lds = ((int64_t)p * r + (int64_t)r * r) * (int64_t)sizeof(double) <= kSvdLdsBytes;
+  double* x = in_lds ? lds : xg;
+  double* vh = in_lds ? lds + (int64_t)p * r : vg;
+  if (in_lds)
+    for (int64_t e = tid; e < (int64_t)p * r; e += NT) x[e] = xg[e];
   for (int64_t e = tid; e < (int64_t)r * r; e += NT) vh[e] = (e % r == e / r) ? 1.0 : 0.0;
   if (tid == 0) rotated = 0;
   __syncthreads();
@@ -115,6 +123,10 @@ __global__ __launch_bounds__(64 * kSvdWaves) void svd_jacobi_kernel(const SvdSec
     if (tid == 0) rotated = 0;
     __syncthreads();
     if (done) break;
+  }
+  if (in_lds) {
+    for (int64_t e = tid; e < (int64_t)p * r; e += NT) xg[e] = x[e];
+    for (int64_t e = tid; e < (int64_t)r * r; e += NT) vg[e] = vh[e];
   }
   // sigma_j = |x_j| (one column per wave)
   for (int j = wave; j < r; j += kSvdWaves) {

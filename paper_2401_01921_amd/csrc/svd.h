@@ -50,6 +50,7 @@ struct SvdWriteWork {
 };
 
 constexpr int kSvdWaves = 16;             // waves of the Jacobi workgroup
+constexpr int kSvdLdsBytes = 128 * 1024;  // X and Vh of a sector up to this size are rotated in LDS
 constexpr int kSvdMaxSweeps = 60;
 constexpr int kSvdGatherChunk = 256 * 16;
 
