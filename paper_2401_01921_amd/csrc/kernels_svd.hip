@@ -12,7 +12,7 @@
 // makes the two columns orthogonal; the same rotation applied to the
 // columns of Vh (starting from the identity) accumulates X_0 Vh = X.  Sweeps
 // visit every pair once in the round-robin (circle) order, all pairs of a
-// round at once (one wave each, disjoint columns); they stop after a sweep
+// round at once (one lane group each, disjoint columns); they stop after a sweep
 // without a rotation (|g| <= tol sqrt(a b)).  Then sigma_j = |x_j|.  The
 // arithmetic of every pair is a fixed sequence, so results repeat bit for
 // bit.
@@ -47,6 +47,86 @@ __global__ __launch_bounds__(256) void svd_gather_kernel(const SvdGather* __rest
   }
 }
 
+#define BST_LDS __attribute__((address_space(3)))
+
+// The sweeps of one sector on X (p x r, column-major) and Vh (r x r): P is a
+// pointer to global memory or, for sectors held in LDS, an LDS-addressed
+// pointer (so that the compiler issues LDS accesses, not generic ones).
+// Returns the sweeps used.
+// Sum over groups of LP lanes (LP = 16, 32, 64; every lane of a group gets
+// the same value).
+template <int LP>
+__device__ __forceinline__ double group_allsum(double v) {
+#pragma unroll
+  for (int off = LP / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, LP);
+  return v;
+}
+
+// The sweeps of one sector on X (p x r, column-major) and Vh (r x r): P is a
+// pointer to global memory or, for sectors held in LDS, an LDS-addressed
+// pointer (so that the compiler issues LDS accesses, not generic ones).  One
+// group of LP lanes per pair of a round.  Returns the sweeps used.
+template <int LP, typename P>
+__device__ int jacobi_sweeps(P x, P vh, int p, int r, int* rotated) {
+  constexpr int NH = 64 * kSvdWaves / LP;   // lane groups of the workgroup
+  const int tid = threadIdx.x, hl = tid % LP, half = tid / LP;
+  const double tol = 4.0 * DBL_EPSILON * sqrt((double)p);
+  const int rr = r + (r & 1);   // an odd count gets one idle slot
+  int sw = 0;
+  for (; sw < kSvdMaxSweeps && r > 1; ++sw) {
+    for (int t = 0; t < rr - 1; ++t) {
+      for (int k = half; k < rr / 2; k += NH) {
+        // circle method: slot 0 stays, the others advance by one per round
+        const int s0 = k, s1 = rr - 1 - k;
+        int i = s0 == 0 ? 0 : (s0 - 1 + t) % (rr - 1) + 1;
+        int j = (s1 - 1 + t) % (rr - 1) + 1;
+        if (i > j) {
+          const int q = i;
+          i = j;
+          j = q;
+        }
+        if (j >= r) continue;
+        P xi = x + (int64_t)i * p;
+        P xj = x + (int64_t)j * p;
+        double a = 0.0, b = 0.0, g = 0.0;
+        for (int e = hl; e < p; e += LP) {
+          const double u = xi[e], v = xj[e];
+          a += u * u;
+          b += v * v;
+          g += u * v;
+        }
+        a = group_allsum<LP>(a);
+        b = group_allsum<LP>(b);
+        g = group_allsum<LP>(g);
+        if (a == 0.0 || b == 0.0 || !(fabs(g) > tol * sqrt(a) * sqrt(b))) continue;
+        const double zeta = (b - a) / (2.0 * g);
+        const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double c = 1.0 / sqrt(1.0 + tt * tt), s = c * tt;
+        for (int e = hl; e < p; e += LP) {
+          const double u = xi[e], v = xj[e];
+          xi[e] = c * u - s * v;
+          xj[e] = s * u + c * v;
+        }
+        P vi = vh + (int64_t)i * r;
+        P vj = vh + (int64_t)j * r;
+        for (int e = hl; e < r; e += LP) {
+          const double u = vi[e], v = vj[e];
+          vi[e] = c * u - s * v;
+          vj[e] = s * u + c * v;
+        }
+        if (hl == 0) *rotated = 1;
+      }
+      __syncthreads();
+    }
+    const bool done = *rotated == 0;
+    __syncthreads();
+    if (tid == 0) *rotated = 0;
+    __syncthreads();
+    if (done) break;
+  }
+  return sw;
+}
+
 __global__ __launch_bounds__(64 * kSvdWaves) void svd_jacobi_kernel(const SvdSec* __restrict__ secs, double* X,
                                                                    double* V, double* __restrict__ sig,
                                                                    double* __restrict__ sorted,
@@ -63,78 +143,40 @@ __global__ __launch_bounds__(64 * kSvdWaves) void svd_jacobi_kernel(const SvdSec
   // copied back at the end; larger ones work in global memory.
   __shared__ double lds[kSvdLdsBytes / sizeof(double)];
   const bool in_lds = ((int64_t)p * r + (int64_t)r * r) * (int64_t)sizeof(double) <= kSvdLdsBytes;
-  double* x = in_lds ? lds : xg;
-  double* vh = in_lds ? lds + (int64_t)p * r : vg;
-  if (in_lds)
-    for (int64_t e = tid; e < (int64_t)p * r; e += NT) x[e] = xg[e];
-  for (int64_t e = tid; e < (int64_t)r * r; e += NT) vh[e] = (e % r == e / r) ? 1.0 : 0.0;
+  BST_LDS double* xl = (BST_LDS double*)lds;
+  BST_LDS double* vl = xl + (int64_t)p * r;
+  if (in_lds) {
+    for (int64_t e = tid; e < (int64_t)p * r; e += NT) xl[e] = xg[e];
+    for (int64_t e = tid; e < (int64_t)r * r; e += NT) vl[e] = (e % r == e / r) ? 1.0 : 0.0;
+  } else {
+    for (int64_t e = tid; e < (int64_t)r * r; e += NT) vg[e] = (e % r == e / r) ? 1.0 : 0.0;
+  }
   if (tid == 0) rotated = 0;
   __syncthreads();
-  const double tol = 4.0 * DBL_EPSILON * sqrt((double)p);
-  const int rr = r + (r & 1);   // an odd count gets one idle slot
-  int sw = 0;
-  for (; sw < kSvdMaxSweeps && r > 1; ++sw) {
-    for (int t = 0; t < rr - 1; ++t) {
-      for (int k = wave; k < rr / 2; k += kSvdWaves) {
-        // circle method: slot 0 stays, the others advance by one per round
-        const int s0 = k, s1 = rr - 1 - k;
-        int i = s0 == 0 ? 0 : (s0 - 1 + t) % (rr - 1) + 1;
-        int j = (s1 - 1 + t) % (rr - 1) + 1;
-        if (i > j) {
-          const int q = i;
-          i = j;
-          j = q;
-        }
-        if (j >= r) continue;
-        double* xi = x + (int64_t)i * p;
-        double* xj = x + (int64_t)j * p;
-        double a = 0.0, b = 0.0, g = 0.0;
-        for (int e = lane; e < p; e += 64) {
-          const double u = xi[e], v = xj[e];
-          a += u * u;
-          b += v * v;
-          g += u * v;
-        }
-        a = wave_allsum(a);
-        b = wave_allsum(b);
-        g = wave_allsum(g);
-        if (a == 0.0 || b == 0.0 || !(fabs(g) > tol * sqrt(a) * sqrt(b))) continue;
-        const double zeta = (b - a) / (2.0 * g);
-        const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        const double c = 1.0 / sqrt(1.0 + tt * tt), s = c * tt;
-        for (int e = lane; e < p; e += 64) {
-          const double u = xi[e], v = xj[e];
-          xi[e] = c * u - s * v;
-          xj[e] = s * u + c * v;
-        }
-        double* vi = vh + (int64_t)i * r;
-        double* vj = vh + (int64_t)j * r;
-        for (int e = lane; e < r; e += 64) {
-          const double u = vi[e], v = vj[e];
-          vi[e] = c * u - s * v;
-          vj[e] = s * u + c * v;
-        }
-        if (lane == 0) rotated = 1;
-      }
-      __syncthreads();
-    }
-    const bool done = rotated == 0;
-    __syncthreads();
-    if (tid == 0) rotated = 0;
-    __syncthreads();
-    if (done) break;
-  }
-  if (in_lds) {
-    for (int64_t e = tid; e < (int64_t)p * r; e += NT) xg[e] = x[e];
-    for (int64_t e = tid; e < (int64_t)r * r; e += NT) vg[e] = vh[e];
-  }
-  // sigma_j = |x_j| (one column per wave)
+  // the widest lane groups that still give every pair of a round its own
+  // group (wide groups for few long columns, narrow ones for many short)
+  const int npairs = (r + 1) / 2;
+  int sw;
+  if (npairs <= NT / 64)
+    sw = in_lds ? jacobi_sweeps<64>(xl, vl, p, r, &rotated) : jacobi_sweeps<64>(xg, vg, p, r, &rotated);
+  else if (npairs <= NT / 32)
+    sw = in_lds ? jacobi_sweeps<32>(xl, vl, p, r, &rotated) : jacobi_sweeps<32>(xg, vg, p, r, &rotated);
+  else
+    sw = in_lds ? jacobi_sweeps<16>(xl, vl, p, r, &rotated) : jacobi_sweeps<16>(xg, vg, p, r, &rotated);
+  // sigma_j = |x_j| (one column per wave), from where the sweeps left X
   for (int j = wave; j < r; j += kSvdWaves) {
-    const double* xj = x + (int64_t)j * p;
     double a = 0.0;
-    for (int e = lane; e < p; e += 64) a += xj[e] * xj[e];
+    if (in_lds) {
+      for (int e = lane; e < p; e += 64) a += xl[(int64_t)j * p + e] * xl[(int64_t)j * p + e];
+    } else {
+      for (int e = lane; e < p; e += 64) a += xg[(int64_t)j * p + e] * xg[(int64_t)j * p + e];
+    }
     a = wave_allsum(a);
     if (lane == 0) sig[S.s_off + j] = sqrt(a);
+  }
+  if (in_lds) {
+    for (int64_t e = tid; e < (int64_t)p * r; e += NT) xg[e] = xl[e];
+    for (int64_t e = tid; e < (int64_t)r * r; e += NT) vg[e] = vl[e];
   }
   __syncthreads();
   // descending order, ties by column: rank of every value
