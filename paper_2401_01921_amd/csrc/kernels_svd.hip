@@ -212,6 +212,7 @@ hipError_t launch_svd_execute(const SvdLaunch& l, hipStream_t s) {
 // bits), then on the flat position among values equal to the cut.
 // ------------------------------------------------------------------------
 constexpr int kSelectMaxSectors = 4096;
+constexpr int kSelectLdsValues = 8192;   // values staged in LDS when they all fit
 
 __global__ __launch_bounds__(1024) void svd_select_kernel(const SvdSec* __restrict__ secs, int nsec,
                                                          const double* __restrict__ sorted,
@@ -220,9 +221,22 @@ __global__ __launch_bounds__(1024) void svd_select_kernel(const SvdSec* __restri
                                                          double* __restrict__ s_err) {
   __shared__ unsigned long long red[16];
   __shared__ int cnt[kSelectMaxSectors];
-  __shared__ long long forced_total;
+  __shared__ long long forced_total, total;
+  __shared__ double vals[kSelectLdsValues];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   auto rsec = [&](int q) { return secs[q].m < secs[q].n ? secs[q].m : secs[q].n; };
+  // the sorted values of all sectors (flat, s_off + i) in LDS when they fit:
+  // every bisection step below scans them all
+  if (tid == 0) {
+    long long t = 0;
+    for (int q = 0; q < nsec; ++q) t = secs[q].s_off + rsec(q) > t ? secs[q].s_off + rsec(q) : t;
+    total = t;
+  }
+  __syncthreads();
+  const bool staged = total <= kSelectLdsValues;
+  if (staged)
+    for (long long e = tid; e < total; e += 1024) vals[e] = sorted[e];
+  const double* src = staged ? (const double*)vals : sorted;
   auto forced = [&](int q) -> int {
     const int64_t f = min_blockdim ? min_blockdim[q] : 0;
     return (int)(f < 0 ? 0 : (f < rsec(q) ? f : rsec(q)));
@@ -244,7 +258,7 @@ __global__ __launch_bounds__(1024) void svd_select_kernel(const SvdSec* __restri
     for (int q = 0; q < nsec; ++q) {
       const int r = rsec(q), f = forced(q);
       for (int i = f + tid; i < r; i += 1024) {
-        const double v = sorted[secs[q].s_off + i];
+        const double v = src[secs[q].s_off + i];
         if (!(v >= err)) continue;
         const unsigned long long b = (unsigned long long)__double_as_longlong(v);
         if (mode == 0) c += b >= lo ? 1 : 0;
@@ -290,7 +304,7 @@ __global__ __launch_bounds__(1024) void svd_select_kernel(const SvdSec* __restri
     const int r = rsec(q), f = forced(q);
     int c = 0;
     for (int i = f + tid; i < r; i += 1024) {
-      const double v = sorted[secs[q].s_off + i];
+      const double v = src[secs[q].s_off + i];
       if (!(v >= err) || none) continue;
       const unsigned long long bits = (unsigned long long)__double_as_longlong(v);
       c += (all || bits > cut || (bits == cut && secs[q].s_off + i < lim)) ? 1 : 0;
