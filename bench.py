@@ -209,14 +209,14 @@ def main():
     def gs_bytes(kind, rowb=8.0):
         # algorithmic bytes of one solve's Gram-Schmidt kernels (one-pass
         # schedule): the dot reads u_j and z; the pass of step j (0-based)
-        # reads basis rows 0..j and z and writes row j and (except on the
-        # last step) row j+1.  Rows and z are float64 (4 bytes with float32 rows).
+        # reads basis rows 0..j and z and (except on the last step) writes
+        # row j+1.  Rows and z are float64 (4 bytes with float32 rows).
         tot = 0.0
         for j in range(m):
             if kind == "dots":
                 tot += 2.0 * rowb * n
             else:
-                tot += rowb * n * (j + 1) + rowb * n + rowb * n * (2 if j + 1 < m else 1)
+                tot += rowb * n * (j + 1) + rowb * n + (rowb * n if j + 1 < m else 0.0)
         return tot
 
     def hbm_roof(key, total_bytes, prof):

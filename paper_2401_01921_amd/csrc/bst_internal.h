@@ -421,36 +421,40 @@ hipError_t launch_lanczos_step_end(const double* partial, int64_t n_for_grid, co
                                    const double* d, int j, double* alpha, double* beta,
                                    double* norm2_out, const double* w, double* vnext, int64_t n,
                                    hipStream_t s);
-// One-pass Lanczos step j (see kernels_aux.hip).  coef: from g = u_j.z
-// (device scalar), alpha/beta/dprev of the previous steps, writes
-// coef[0..j] and aest.  pass: rewrites row j of V as v_j, writes the new
-// residual to vnext (may be null), dn[0..j+1] = (V_j^T w, w.w).  end:
-// alpha[j], beta[j], dprev <- dn[0..j].
-hipError_t launch_lanczos_pass(double* V, int64_t ldv, int64_t n, int j, const double* z,
-                               const double* coef, const double* dprev, const double* beta,
-                               double* vnext, double* partial, double* dn, hipStream_t s);
-// The same over a float32 basis (rows rounded to float32 when written; dots
-// and scalars in float64).
-hipError_t launch_lanczos_pass(float* V, int64_t ldv, int64_t n, int j, const float* z,
-                               const double* coef, const double* dprev, const double* beta,
-                               float* vnext, double* partial, double* dn, hipStream_t s);
+// One-pass Lanczos step j (see kernels_aux.hip).  The basis rows hold the
+// residuals as the passes wrote them; cmat (kMaxVecs x kMaxVecs, row k at
+// cmat + k * kMaxVecs, lower triangular) maps them to the orthonormal
+// vectors, v_k = sum_{m<=k} C[k][m] u_m, and gains one row per step.
+// dot step: from g = u_j.z (device scalar) and the previous pass's sums,
+// dprev, alpha and beta of step j - 1, row j of C, and coef[0..j] (the
+// coefficients of rows 0..j in the next residual) and aest.  pass: reads
+// rows 0..j and z, writes the new residual to vnext (may be null), dn[0..j+1]
+// = (u_m . w, w.w).  end: alpha[j], beta[j], dprev of the last step.
+hipError_t launch_lanczos_pass(const double* V, int64_t ldv, int64_t n, int j, const double* z,
+                               const double* coef, const double* beta, double* vnext, double* partial,
+                               double* dn, hipStream_t s);
+// The same over a float32 basis (the residual rounded to float32 when
+// written; dots and scalars in float64).
+hipError_t launch_lanczos_pass(const float* V, int64_t ldv, int64_t n, int j, const float* z,
+                               const double* coef, const double* beta, float* vnext, double* partial,
+                               double* dn, hipStream_t s);
 // The u_j.z dot and the scalar work of step j in two launches (dot partials,
 // then one block that sums them and the partials of the pass of step j - 1,
-// ends step j - 1 and forms the scalars of step j); dn null in
-// launch_lanczos_pass skips that pass's own sums, which this call (or
+// ends step j - 1 and forms row j of C and the scalars of step j); dn null
+// in launch_lanczos_pass skips that pass's own sums, which this call (or
 // launch_lanczos_pass_sums after the last step) then forms.
 hipError_t launch_lanczos_dot_step(const double* x, const double* z, int64_t n, double* dpart,
                                    const double* ppart, int pj, double* dn, int j, double* g,
                                    double* alpha, double* beta, double* dprev, double* coef,
-                                   double* aest, hipStream_t s);
+                                   double* aest, double* cmat, hipStream_t s);
 hipError_t launch_lanczos_dot_step(const float* x, const float* z, int64_t n, double* dpart,
                                    const double* ppart, int pj, double* dn, int j, double* g,
                                    double* alpha, double* beta, double* dprev, double* coef,
-                                   double* aest, hipStream_t s);
+                                   double* aest, double* cmat, hipStream_t s);
 hipError_t launch_lanczos_pass_sums(int64_t n, int j, bool f32, const double* partial, double* dn,
                                    hipStream_t s);
-hipError_t launch_lanczos_end(const double* dn, const double* aest, int j, double* dprev,
-                              double* alpha, double* beta, hipStream_t s);
+hipError_t launch_lanczos_end(const double* dn, const double* aest, int j, const double* cmat,
+                              double* dprev, double* alpha, double* beta, hipStream_t s);
 // alpha[j] = c[j] + d[j]; beta[j] = sqrt(norm2[0])
 // plain device copy of n doubles
 

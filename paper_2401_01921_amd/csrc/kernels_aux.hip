@@ -601,102 +601,91 @@ hipError_t launch_lanczos_step_end(const double* partial, int64_t n_for_grid, co
   return hipGetLastError();
 }
 
-// One pass over the Krylov basis per Lanczos step.  Row j of V holds u_j,
-// the residual of step j-1 before its full projection; dprev = V_{j-1}^T u_j
-// (measured by the previous pass) and beta_{j-1} = |u_j - V_{j-1} dprev|, so
-// v_j = (u_j - V_{j-1} dprev) / beta_{j-1}.  The operator was applied to
-// u_j (z = H u_j); H v_j = (z - H V_{j-1} dprev) / beta_{j-1}, and by the
-// Lanczos relation H V_{j-1} = V_j T (T the tridiagonal of alpha, beta so
-// far) the correction is the combination V_j e, e = T dprev, of vectors the
-// pass reads anyway.  The three-term residual
+// One pass over the Krylov basis per Lanczos step.  Row m of V holds u_m,
+// the residual of step m-1 before its full projection (u_0 = v_0, the
+// normalised start vector), and is never rewritten: the orthonormal vectors
+// are v_k = sum_{m<=k} C[k][m] u_m with C lower triangular, one row per step
+// (C[0][0] = 1).  At step j, dprev = V_{j-1}^T u_j (from the previous
+// pass's sums u_m.u_j through C) and beta_{j-1} = |u_j - V_{j-1} dprev|, so
+// v_j = (u_j - V_{j-1} dprev) / beta_{j-1}, which is row j of C:
+//   C[j][m] = rb (delta_jm - sum_{k<j} dprev_k C[k][m]),  rb = 1 / beta_{j-1}.
+// The operator was applied to u_j (z = H u_j); H v_j = (z - H V_{j-1} dprev)
+// rb, and by the Lanczos relation H V_{j-1} = V_j T (T the tridiagonal of
+// alpha, beta so far) the correction is the combination V_j e, e = T dprev.
+// The three-term residual
 //   w = H v_j - a v_j - beta_{j-1} v_{j-1}
 // (a = v_j.H v_j from g = u_j.z and the same relation) is then measured
-// against all of V_j in the same pass; its projection onto V_j is applied
-// lagged, in the next step.  This is the delayed-reorthogonalisation idea
-// of low-synchronisation Gram-Schmidt (Swirydowicz et al., Numer. Linear
-// Algebra Appl. 2021; Bielich et al., Parallel Comput. 2022) specialised to
-// the symmetric three-term recurrence; in exact arithmetic alpha_j and
-// beta_j equal those of Lanczos with two full classical Gram-Schmidt passes.
+// against all of u_0..u_j in the same pass; its projection onto V_j is
+// applied lagged, in the next step.  This is the delayed-reorthogonalisation
+// idea of low-synchronisation Gram-Schmidt (Swirydowicz et al., Numer.
+// Linear Algebra Appl. 2021; Bielich et al., Parallel Comput. 2022)
+// specialised to the symmetric three-term recurrence; in exact arithmetic
+// alpha_j and beta_j equal those of Lanczos with two full classical
+// Gram-Schmidt passes.  Keeping the rows as written (C carries the
+// projections and scalings) leaves the pass one store per element, w.
 //
 // The scalars of step j from g = u_j.z (al, be, dp hold alpha, beta, dprev
-// for k < j; rb = 1 / beta_{j-1}):
+// for k < j):
 //   v_j . z = rb (g - dprev . f),  f = (T^T y)_{k<j},  y = (dprev, beta_{j-1});
 //   e = T dprev over rows 0..j;  coef_k = rb e_k (+ beta_{j-1} for k = j-1),
-// the coefficients of v_0..v_j in w = z/beta_{j-1} - sum_k coef_k v_k; and
-// aest, the three-term estimate of alpha_j.  lanczos_step_scalars_kernel
-// evaluates them.
+// the coefficients of v_0..v_j in w = z rb - sum_k coef_k v_k; and aest, the
+// three-term estimate of alpha_j.  In the rows as stored,
+//   w = z rb - sum_{m<=j} cp_m u_m,  cp_m = sum_{k=m..j} coef_k C[k][m].
+// lanczos_step_scalars_kernel evaluates them.
 
 // The pass of step j: per element
-//   v_j = (u_j - sum_{k<j} dprev_k v_k) rb      written back into row j
-//   w   = z rb - sum_{k<j} coef_k v_k - coef_j v_j   written to vnext (if any)
-// and the block partials of v_k.w (k < j), v_j.w and w.w (j + 2 values).
+//   w = z rb - sum_{m<=j} cp_m u_m      written to vnext (if any)
+// and the block partials of u_m.w (m <= j) and w.w (j + 2 values).
 template <int NV>
 __global__ __launch_bounds__(256) void lanczos_pass_kernel(
-    double* V, uint32_t ldv, uint32_t n, int j, const double* __restrict__ z,
-    const double* __restrict__ coef, const double* __restrict__ dprev,
-    const double* __restrict__ beta, double* vnext, double* __restrict__ partial) {
+    const double* V, uint32_t ldv, uint32_t n, int j, const double* __restrict__ z,
+    const double* __restrict__ coef, const double* __restrict__ beta, double* vnext,
+    double* __restrict__ partial) {
   constexpr int NR = NV + 2;
   __shared__ double red[4 * NR];
-  __shared__ double cs[NV], ds[NV];
+  __shared__ double cs[NV];
   const int tid = threadIdx.x;
   const double b = j > 0 ? beta[j - 1] : 1.0;
   const double rb = b > 0.0 ? 1.0 / b : 0.0;
-  for (int k = tid; k < NV; k += 256) {
-    cs[k] = k < j ? coef[k] : 0.0;
-    ds[k] = k < j ? dprev[k] : 0.0;
-  }
+  for (int k = tid; k < NV; k += 256) cs[k] = k <= j ? coef[k] : 0.0;
   __syncthreads();
-  const double csj = coef[j];
   double acc[NV];
 #pragma unroll
   for (int k = 0; k < NV; ++k) acc[k] = 0.0;
-  double accj = 0.0, accw = 0.0;
-  char* Vb = reinterpret_cast<char*>(V);
+  double accw = 0.0;
+  const char* Vb = reinterpret_cast<const char*>(V);
   const uint32_t rowb = ldv * 8u;
-  const uint32_t rowj = (uint32_t)j * rowb;
   const uint32_t stride = gridDim.x * 256u;
   for (uint32_t i = blockIdx.x * 256u + tid; i < n; i += stride) {
     double v[NV];
     uint32_t off = i * 8u;
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
-      v[k] = (k < j) ? __builtin_nontemporal_load(reinterpret_cast<const double*>(Vb + off)) : 0.0;
+      v[k] = (k <= j) ? __builtin_nontemporal_load(reinterpret_cast<const double*>(Vb + off)) : 0.0;
       off += rowb;
       asm volatile("" : "+v"(off));
     }
-    double* uj = reinterpret_cast<double*>(Vb + (i * 8u + rowj));
-    const double u = __builtin_nontemporal_load(uj);
     const double zi = __builtin_nontemporal_load(z + i);
-    double t = 0.0, sacc = 0.0;
+    double sacc = 0.0;
 #pragma unroll
-    for (int k = 0; k < NV; ++k) {
-      t += ds[k] * v[k];
-      sacc += cs[k] * v[k];
-    }
-    const double vj = (u - t) * rb;
-    const double w = (zi * rb - sacc) - csj * vj;
-    __builtin_nontemporal_store(vj, uj);
+    for (int k = 0; k < NV; ++k) sacc += cs[k] * v[k];
+    const double w = zi * rb - sacc;
     if (vnext) __builtin_nontemporal_store(w, vnext + i);
 #pragma unroll
     for (int k = 0; k < NV; ++k) acc[k] += v[k] * w;
-    accj += vj * w;
     accw += w * w;
   }
   const int wave = tid >> 6, lane = tid & 63;
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
-    if (k < j) {
+    if (k <= j) {
       const double r = wave_sum(acc[k]);
       if (lane == 0) red[wave * NR + k] = r;
     }
   }
   {
-    const double r1 = wave_sum(accj);
     const double r2 = wave_sum(accw);
-    if (lane == 0) {
-      red[wave * NR + j] = r1;
-      red[wave * NR + j + 1] = r2;
-    }
+    if (lane == 0) red[wave * NR + j + 1] = r2;
   }
   __syncthreads();
   for (int k = tid; k < j + 2; k += 256) {
@@ -706,35 +695,31 @@ __global__ __launch_bounds__(256) void lanczos_pass_kernel(
 }
 
 // The same pass over a float32 basis (the split forms; z float32 too): two
-// elements per lane, so every row access is 8 bytes.  v_j and w are rounded to float32
-// before they enter the dot products, so the measured projections are those
-// of the rows as stored.  An odd n leaves one padding element in the last
-// pair (rows are padded, z holds n doubles): it is read, never counted.
+// elements per lane, so every row access is 8 bytes.  w is rounded to
+// float32 before it enters the dot products, so the measured projections
+// are those of the rows as stored.  An odd n leaves one padding element in
+// the last pair (rows are padded, z holds n doubles): it is read, never
+// counted.
 template <int NV, typename TZ>
 __global__ __launch_bounds__(256) void lanczos_pass_f32_kernel(
-    float* V, uint32_t ldv, uint32_t n, int j, const TZ* __restrict__ z,
-    const double* __restrict__ coef, const double* __restrict__ dprev,
-    const double* __restrict__ beta, float* vnext, double* __restrict__ partial) {
+    const float* V, uint32_t ldv, uint32_t n, int j, const TZ* __restrict__ z,
+    const double* __restrict__ coef, const double* __restrict__ beta, float* vnext,
+    double* __restrict__ partial) {
   typedef float fl2 __attribute__((ext_vector_type(2)));
   constexpr int NR = NV + 2;
   __shared__ double red[4 * NR];
-  __shared__ double cs[NV], ds[NV];
+  __shared__ double cs[NV];
   const int tid = threadIdx.x;
   const double b = j > 0 ? beta[j - 1] : 1.0;
   const double rb = b > 0.0 ? 1.0 / b : 0.0;
-  for (int k = tid; k < NV; k += 256) {
-    cs[k] = k < j ? coef[k] : 0.0;
-    ds[k] = k < j ? dprev[k] : 0.0;
-  }
+  for (int k = tid; k < NV; k += 256) cs[k] = k <= j ? coef[k] : 0.0;
   __syncthreads();
-  const double csj = coef[j];
   double acc[NV];
 #pragma unroll
   for (int k = 0; k < NV; ++k) acc[k] = 0.0;
-  double accj = 0.0, accw = 0.0;
-  char* Vb = reinterpret_cast<char*>(V);
+  double accw = 0.0;
+  const char* Vb = reinterpret_cast<const char*>(V);
   const uint32_t rowb = ldv * 4u;
-  const uint32_t rowj = (uint32_t)j * rowb;
   const uint32_t npair = (n + 1u) / 2u;
   const uint32_t stride = gridDim.x * 256u;
   for (uint32_t p = blockIdx.x * 256u + tid; p < npair; p += stride) {
@@ -743,13 +728,11 @@ __global__ __launch_bounds__(256) void lanczos_pass_f32_kernel(
     uint32_t off = p * 8u;
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
-      v[k] = (k < j) ? __builtin_nontemporal_load(reinterpret_cast<const fl2*>(Vb + off)) : fl2{0.f, 0.f};
+      v[k] = (k <= j) ? __builtin_nontemporal_load(reinterpret_cast<const fl2*>(Vb + off)) : fl2{0.f, 0.f};
       if (!two) v[k].y = 0.f;
       off += rowb;
       asm volatile("" : "+v"(off));
     }
-    fl2* uj = reinterpret_cast<fl2*>(Vb + (p * 8u + rowj));
-    const fl2 u = __builtin_nontemporal_load(uj);
     double z0, z1;
     if constexpr (sizeof(TZ) == 4) {
       if (two) {
@@ -767,43 +750,33 @@ __global__ __launch_bounds__(256) void lanczos_pass_f32_kernel(
     // Register budget (two waves per SIMD): the coefficients are read from
     // LDS eight rows at a time, and the float64 images of the rows are formed
     // again for the dot products instead of being kept from this loop.
-    double t0 = 0.0, t1 = 0.0, s0 = 0.0, s1 = 0.0;
+    double s0 = 0.0, s1 = 0.0;
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
-      t0 += ds[k] * v[k].x;
-      t1 += ds[k] * v[k].y;
       s0 += cs[k] * v[k].x;
       s1 += cs[k] * v[k].y;
       if (k % 8 == 7) __builtin_amdgcn_sched_barrier(0);
     }
 #pragma unroll
     for (int k = 0; k < NV; ++k) asm volatile("" : "+v"(v[k]));
-    const float vj0 = (float)((u.x - t0) * rb);
-    const float vj1 = two ? (float)((u.y - t1) * rb) : 0.f;
-    const float w0 = (float)((z0 * rb - s0) - csj * (double)vj0);
-    const float w1 = two ? (float)((z1 * rb - s1) - csj * (double)vj1) : 0.f;
-    __builtin_nontemporal_store(fl2{vj0, vj1}, uj);
+    const float w0 = (float)(z0 * rb - s0);
+    const float w1 = two ? (float)(z1 * rb - s1) : 0.f;
     if (vnext) __builtin_nontemporal_store(fl2{w0, w1}, reinterpret_cast<fl2*>(vnext) + p);
 #pragma unroll
     for (int k = 0; k < NV; ++k) acc[k] += (double)v[k].x * w0 + (double)v[k].y * w1;
-    accj += (double)vj0 * w0 + (double)vj1 * w1;
     accw += (double)w0 * w0 + (double)w1 * w1;
   }
   const int wave = tid >> 6, lane = tid & 63;
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
-    if (k < j) {
+    if (k <= j) {
       const double r = wave_sum(acc[k]);
       if (lane == 0) red[wave * NR + k] = r;
     }
   }
   {
-    const double r1 = wave_sum(accj);
     const double r2 = wave_sum(accw);
-    if (lane == 0) {
-      red[wave * NR + j] = r1;
-      red[wave * NR + j + 1] = r2;
-    }
+    if (lane == 0) red[wave * NR + j + 1] = r2;
   }
   __syncthreads();
   for (int k = tid; k < j + 2; k += 256) {
@@ -825,38 +798,98 @@ __device__ __forceinline__ void step_end(const double* ds, double aest, int j, d
   beta_j = sqrt(q > 0.0 ? q : 0.0);
 }
 
-__global__ __launch_bounds__(64) void lanczos_end_kernel(const double* __restrict__ dn,
-                                                         const double* __restrict__ aest, int j,
-                                                         double* __restrict__ dprev,
-                                                         double* __restrict__ alpha,
-                                                         double* __restrict__ beta) {
-  __shared__ double ds[kMaxVecs + 2];
-  const int lane = threadIdx.x;
-  for (int k = lane; k < j + 2; k += 64) {
-    ds[k] = dn[k];
-    if (k <= j) dprev[k] = dn[k];
+// The basis pass measures w against the rows as stored (u_m . w); the
+// projections onto the orthonormal vectors are v_k . w = sum_{m<=k} C[k][m]
+// (u_m . w).  Rows k < nk of C (row k at cmat + k * kMaxVecs) are spread
+// over the 16 waves of a 1024-thread block, row k on wave k % 16, columns
+// lane and lane + 64; each wave loads its rows once, at the start.
+constexpr int kCRowsPerWave = kMaxVecs / 16;
+__device__ __forceinline__ void load_c_rows(const double* __restrict__ cmat, int nk, int wave, int lane,
+                                            double (&creg)[kCRowsPerWave][2]) {
+#pragma unroll
+  for (int r = 0; r < kCRowsPerWave; ++r) {
+    const int k = wave + 16 * r;
+    creg[r][0] = (k < nk && lane <= k) ? cmat[(int64_t)k * kMaxVecs + lane] : 0.0;
+    creg[r][1] = (k < nk && lane + 64 <= k) ? cmat[(int64_t)k * kMaxVecs + lane + 64] : 0.0;
   }
+}
+// out[k] = sum_{m<=k} C[k][m] x[m] for k < nk (x in LDS, valid below nk);
+// each row's sum is a wave_sum in a fixed order.
+__device__ __forceinline__ void c_times(const double (&creg)[kCRowsPerWave][2], int nk, int wave, int lane,
+                                        const double* x, double* out) {
+#pragma unroll
+  for (int r = 0; r < kCRowsPerWave; ++r) {
+    const int k = wave + 16 * r;
+    if (k < nk) {
+      const double x0 = lane <= k ? x[lane] : 0.0;
+      const double x1 = lane + 64 <= k ? x[lane + 64] : 0.0;
+      const double t = wave_sum(creg[r][0] * x0 + creg[r][1] * x1);
+      if (lane == 0) out[k] = t;
+    }
+  }
+}
+// Per-wave partials of sum_{k<nk} y[k] C[k][m] over the wave's rows, for
+// m = lane, lane + 64, into part[wave][m].
+__device__ __forceinline__ void ct_times_part(const double (&creg)[kCRowsPerWave][2], int nk, int wave,
+                                              int lane, const double* y, double (*part)[kMaxVecs]) {
+  double p0 = 0.0, p1 = 0.0;
+#pragma unroll
+  for (int r = 0; r < kCRowsPerWave; ++r) {
+    const int k = wave + 16 * r;
+    if (k < nk) {
+      p0 += y[k] * creg[r][0];
+      p1 += y[k] * creg[r][1];
+    }
+  }
+  part[wave][lane] = p0;
+  part[wave][lane + 64] = p1;
+}
+
+// End of the last step j: the raw sums dn (u_m . w for m <= j, then w.w)
+// become dprev = V_j^T w through C, then alpha_j, beta_j as step_end.
+__global__ __launch_bounds__(1024) void lanczos_end_kernel(const double* __restrict__ dn,
+                                                           const double* __restrict__ aest, int j,
+                                                           const double* __restrict__ cmat,
+                                                           double* __restrict__ dprev,
+                                                           double* __restrict__ alpha,
+                                                           double* __restrict__ beta) {
+  __shared__ double raw[kMaxVecs + 2], ds[kMaxVecs + 2];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  double creg[kCRowsPerWave][2];
+  load_c_rows(cmat, j + 1, wave, lane, creg);
+  for (int k = tid; k < j + 2; k += 1024) raw[k] = dn[k];
   __syncthreads();
-  if (lane != 0) return;
+  c_times(creg, j + 1, wave, lane, raw, ds);
+  if (tid == 0) ds[j + 1] = raw[j + 1];
+  __syncthreads();
+  for (int k = tid; k <= j; k += 1024) dprev[k] = ds[k];
+  if (tid != 0) return;
   step_end(ds, aest[0], j, alpha[j], beta[j]);
 }
 
 // The scalar work between two basis passes, in one block of 1024 threads:
 // the sums of the u_j.z, z.z partials of dot2_kernel (g) beside the sums of
-// the pass of step pj that dot2_kernel already left in dn, then the end of
-// step pj (alpha, beta, dprev as lanczos_end_kernel) and the scalars of step
-// j.  One wave forms each sum: lane l adds partials l, l + 64, ... in order,
-// then the wave sum; every load of a sum is issued at once (grids of at most
-// 1024 blocks).  The scalars then take one wave, lane-parallel over k.
-// pj < 0: no pass before (step 0).
+// the pass of step pj that dot2_kernel already left in dn (u_m . u_j for
+// m <= pj, then u_j . u_j), which C turns into dprev = V_pj^T u_j; then the
+// end of step pj (alpha, beta as lanczos_end_kernel), row j of C, and the
+// scalars of step j, first as coefficients of v_0..v_j, then of the rows as
+// stored (coef).  One wave forms each partial sum (lane l adds partials l,
+// l + 64, ..., then the wave sum); every load of a sum is issued at once
+// (grids of at most 1024 blocks).  The scalars themselves take one wave,
+// lane-parallel over k.  pj < 0: no pass before (step 0).
 __global__ __launch_bounds__(1024) void lanczos_step_scalars_kernel(
     int pj, const double* __restrict__ dpart, int dG, int j, double* __restrict__ dn,
     double* __restrict__ g, double* __restrict__ alpha, double* __restrict__ beta,
-    double* __restrict__ dprev, double* __restrict__ coef, double* __restrict__ aest) {
-  __shared__ double sv[kMaxVecs + 4];
+    double* __restrict__ dprev, double* __restrict__ coef, double* __restrict__ aest,
+    double* __restrict__ cmat) {
+  __shared__ double sv[kMaxVecs + 4], dps[kMaxVecs];
   __shared__ double al[kMaxVecs], be[kMaxVecs];
+  __shared__ double cf[kMaxVecs], crow[1];
+  __shared__ double part[16][kMaxVecs], part2[16][kMaxVecs];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int npv = pj >= 0 ? pj + 2 : 0;
+  double creg[kCRowsPerWave][2];
+  load_c_rows(cmat, j, wave, lane, creg);   // rows 0..j-1
   // sv[0..npv): the previous pass's sums, formed by dot2_kernel into dn
   for (int k = tid; k < npv; k += 1024) sv[k] = dn[k];
   // sv[npv], sv[npv + 1]: u_j.z and z.z, one wave each (lane l adds
@@ -877,82 +910,122 @@ __global__ __launch_bounds__(1024) void lanczos_step_scalars_kernel(
     be[k] = beta[k];
   }
   __syncthreads();
-  // sv[0..npv) = dn of step pj, sv[npv] = u_j.z, sv[npv + 1] = z.z
-  for (int k = tid; k <= pj; k += 1024) dprev[k] = sv[k];
-  if (wave != 0) return;
-  // The rest in wave 0, lane-parallel over the step index k (k < kMaxVecs,
-  // two per lane).  Each sum is a wave_sum in a fixed order whose result
-  // lane 0 broadcasts, so every lane continues with the same value.
-  // End of step pj (as step_end): alpha_pj, beta_pj.
-  double apj = 0.0, bpj = 0.0;
-  if (pj >= 0) {
-    double t = 0.0;
-    for (int k = lane; k <= pj; k += 64) t += sv[k] * sv[k];
-    const double ss = __shfl(wave_sum(t), 0, 64);
-    const double q = sv[pj + 1] - ss;
-    apj = aest[0] + sv[pj];
-    bpj = sqrt(q > 0.0 ? q : 0.0);
+  // dprev_k = v_k . u_j = sum_{m<=k} C[k][m] (u_m . u_j), k < j
+  c_times(creg, j, wave, lane, sv, dps);
+  __syncthreads();
+  // dps = dprev, sv[j] = u_j . u_j, sv[npv] = u_j.z, sv[npv + 1] = z.z;
+  // part = per-wave shares of dprev^T C (row j of C: rb (e_j - C^T dprev))
+  for (int k = tid; k < j; k += 1024) dprev[k] = dps[k];
+  ct_times_part(creg, j, wave, lane, dps, part);
+  if (wave == 0) {
+    // The scalars in wave 0, lane-parallel over the step index k (k <
+    // kMaxVecs, two per lane).  Each sum is a wave_sum in a fixed order
+    // whose result lane 0 broadcasts, so every lane continues with the same
+    // value.
+    // End of step pj (as step_end): alpha_pj, beta_pj.
+    const double* dp = dps;
+    double apj = 0.0, bpj = 0.0;
+    if (pj >= 0) {
+      double t = 0.0;
+      for (int k = lane; k <= pj; k += 64) t += dp[k] * dp[k];
+      const double ss = __shfl(wave_sum(t), 0, 64);
+      const double q = sv[pj + 1] - ss;
+      apj = aest[0] + dp[pj];
+      bpj = sqrt(q > 0.0 ? q : 0.0);
+      if (lane == 0) {
+        alpha[pj] = apj;
+        beta[pj] = bpj;
+      }
+    }
     if (lane == 0) {
-      alpha[pj] = apj;
-      beta[pj] = bpj;
+      g[0] = sv[npv];
+      g[1] = sv[npv + 1];
+    }
+    auto AL = [&](int k) { return k == pj ? apj : al[k]; };
+    auto BE = [&](int k) { return k == pj ? bpj : be[k]; };
+    const double bp = j > 0 ? bpj : 1.0;
+    const double rb = bp > 0.0 ? 1.0 / bp : 0.0;
+    // Scalars of step j = pj + 1.
+    double t = 0.0;
+    for (int k = lane; k < j; k += 64) {
+      const double yn = k + 1 < j ? dp[k + 1] : bp;
+      double f = AL(k) * dp[k] + BE(k) * yn;
+      if (k > 0) f += BE(k - 1) * dp[k - 1];
+      t += dp[k] * f;
+    }
+    const double sdot = __shfl(wave_sum(t), 0, 64);
+    const double vz = rb * (sv[npv] - sdot);
+    for (int i = lane; i < j; i += 64) {
+      double e = AL(i) * dp[i];
+      if (i > 0) e += BE(i - 1) * dp[i - 1];
+      if (i + 1 < j) e += BE(i) * dp[i + 1];
+      cf[i] = rb * e + (i == j - 1 ? bp : 0.0);
+    }
+    if (lane == 0) {
+      const double ej = j > 0 ? BE(j - 1) * dp[j - 1] : 0.0;
+      const double a = rb * (vz - ej);
+      cf[j] = rb * ej + a;
+      aest[0] = a;
+      crow[0] = rb;   // crow[0] carries rb to the other waves
     }
   }
-  if (lane == 0) {
-    g[0] = sv[npv];
-    g[1] = sv[npv + 1];
+  __syncthreads();
+  // In the rows as stored, with C[j][m] = rb (delta_jm - (C^T dprev)_m):
+  //   coef_m = sum_{k<j} (cf_k - cf_j rb dprev_k) C[k][m] + cf_j rb delta_jm;
+  // the waves' shares of the sum go to part2, then one thread per m adds
+  // them in wave order and also stores row j of C.
+  const double rb = crow[0];
+  {
+    const double cj = cf[j] * rb;
+    double p0 = 0.0, p1 = 0.0;
+#pragma unroll
+    for (int r = 0; r < kCRowsPerWave; ++r) {
+      const int k = wave + 16 * r;
+      if (k < j) {
+        const double y = cf[k] - cj * dps[k];
+        p0 += y * creg[r][0];
+        p1 += y * creg[r][1];
+      }
+    }
+    part2[wave][lane] = p0;
+    part2[wave][lane + 64] = p1;
   }
-  // Scalars of step j = pj + 1 (as step_coef, dprev = sv[0..j)).
-  const double* dp = sv;
-  auto AL = [&](int k) { return k == pj ? apj : al[k]; };
-  auto BE = [&](int k) { return k == pj ? bpj : be[k]; };
-  const double bp = j > 0 ? bpj : 1.0;
-  const double rb = bp > 0.0 ? 1.0 / bp : 0.0;
-  double t = 0.0;
-  for (int k = lane; k < j; k += 64) {
-    const double yn = k + 1 < j ? dp[k + 1] : bp;
-    double f = AL(k) * dp[k] + BE(k) * yn;
-    if (k > 0) f += BE(k - 1) * dp[k - 1];
-    t += dp[k] * f;
-  }
-  const double sdot = __shfl(wave_sum(t), 0, 64);
-  const double vz = rb * (sv[npv] - sdot);
-  for (int i = lane; i < j; i += 64) {
-    double e = AL(i) * dp[i];
-    if (i > 0) e += BE(i - 1) * dp[i - 1];
-    if (i + 1 < j) e += BE(i) * dp[i + 1];
-    coef[i] = rb * e + (i == j - 1 ? bp : 0.0);
-  }
-  if (lane == 0) {
-    const double ej = j > 0 ? BE(j - 1) * dp[j - 1] : 0.0;
-    const double a = rb * (vz - ej);
-    coef[j] = rb * ej + a;
-    aest[0] = a;
+  __syncthreads();
+  for (int m = tid; m <= j; m += 1024) {
+    double cs = 0.0, cp = 0.0;
+    for (int w = 0; w < 16; ++w) {
+      cs += part[w][m];
+      cp += part2[w][m];
+    }
+    const double dj = m == j ? 1.0 : 0.0;
+    cmat[(int64_t)j * kMaxVecs + m] = rb * (dj - cs);
+    coef[m] = cp + cf[j] * rb * dj;
   }
 }
 
-hipError_t launch_lanczos_pass(double* V, int64_t ldv, int64_t n, int j, const double* z,
-                               const double* coef, const double* dprev, const double* beta,
-                               double* vnext, double* partial, double* dn, hipStream_t s) {
+hipError_t launch_lanczos_pass(const double* V, int64_t ldv, int64_t n, int j, const double* z,
+                               const double* coef, const double* beta, double* vnext, double* partial,
+                               double* dn, hipStream_t s) {
   if (j < 0 || j + 2 > kMaxVecs + 1 || !fits32(V, ldv, n, j + 1)) return hipErrorInvalidValue;
   const int G = pass_grid_f64(n);
-  const int nv = j > 0 ? j : 1;
+  const int nv = j + 1;   // rows 0..j
   BST_NV_DISPATCH(lanczos_pass_kernel, dim3(G), dim3(256), 0, s, V, (uint32_t)ldv, (uint32_t)n, j,
-                  z, coef, dprev, beta, vnext, partial);
+                  z, coef, beta, vnext, partial);
   if (dn) hipLaunchKernelGGL(reduce_partials_kernel, dim3(j + 2), dim3(256), 0, s, partial, G, dn);
   return hipGetLastError();
 }
 
-hipError_t launch_lanczos_pass(float* V, int64_t ldv, int64_t n, int j, const float* z,
-                               const double* coef, const double* dprev, const double* beta,
-                               float* vnext, double* partial, double* dn, hipStream_t s) {
+hipError_t launch_lanczos_pass(const float* V, int64_t ldv, int64_t n, int j, const float* z,
+                               const double* coef, const double* beta, float* vnext, double* partial,
+                               double* dn, hipStream_t s) {
   if (j < 0 || j + 2 > kMaxVecs + 1 || n > 0x7FFFFFFF || ldv > 0x7FFFFFFF || ldv % 2 ||
       (uint64_t)ldv * (uint64_t)(j + 1) * 4u >= 0xFFFFFFFFull)
     return hipErrorInvalidValue;
   const int G = pass_grid_f32(n);
-  const int nv = j > 0 ? j : 1;
+  const int nv = j + 1;   // rows 0..j
   #define BST_PF32(NV_)                                                                                      \
   hipLaunchKernelGGL((lanczos_pass_f32_kernel<NV_, float>), dim3(G), dim3(256), 0, s, V, (uint32_t)ldv, \
-                     (uint32_t)n, j, z, coef, dprev, beta, vnext, partial)
+                     (uint32_t)n, j, z, coef, beta, vnext, partial)
   if (nv <= 8) BST_PF32(8);
   else if (nv <= 16) BST_PF32(16);
   else if (nv <= 24) BST_PF32(24);
@@ -975,9 +1048,10 @@ hipError_t launch_lanczos_pass_sums(int64_t n, int j, bool f32, const double* pa
   return hipGetLastError();
 }
 
-hipError_t launch_lanczos_end(const double* dn, const double* aest, int j, double* dprev,
-                              double* alpha, double* beta, hipStream_t s) {
-  hipLaunchKernelGGL(lanczos_end_kernel, dim3(1), dim3(64), 0, s, dn, aest, j, dprev, alpha, beta);
+hipError_t launch_lanczos_end(const double* dn, const double* aest, int j, const double* cmat,
+                              double* dprev, double* alpha, double* beta, hipStream_t s) {
+  if (j < 0 || j >= kMaxVecs) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(lanczos_end_kernel, dim3(1), dim3(1024), 0, s, dn, aest, j, cmat, dprev, alpha, beta);
   return hipGetLastError();
 }
 
@@ -1169,7 +1243,7 @@ template <typename TX, typename TZ>
 static hipError_t dot_step_impl(const TX* x, const TZ* z, int64_t n, double* dpart,
                                 const double* ppart, int pj, double* dn, int j, double* g,
                                 double* alpha, double* beta, double* dprev, double* coef,
-                                double* aest, hipStream_t s) {
+                                double* aest, double* cmat, hipStream_t s) {
   if (j < 0 || j >= kMaxVecs || pj != j - 1 || n < 0) return hipErrorInvalidValue;
   // two elements per lane: float32 x and z 8-byte aligned, or float64 x and
   // z 16-byte aligned (one 8- or 16-byte load each)
@@ -1188,20 +1262,20 @@ static hipError_t dot_step_impl(const TX* x, const TZ* z, int64_t n, double* dpa
     hipLaunchKernelGGL((dot2_kernel<TX, TZ, false>), dim3(G), dim3(256), 0, s, x, z, n, dpart, ppart, pG, npv,
                        dn);
   hipLaunchKernelGGL(lanczos_step_scalars_kernel, dim3(1), dim3(1024), 0, s, pj, dpart, G, j, dn, g, alpha,
-                     beta, dprev, coef, aest);
+                     beta, dprev, coef, aest, cmat);
   return hipGetLastError();
 }
 hipError_t launch_lanczos_dot_step(const double* x, const double* z, int64_t n, double* dpart,
                                    const double* ppart, int pj, double* dn, int j, double* g,
                                    double* alpha, double* beta, double* dprev, double* coef,
-                                   double* aest, hipStream_t s) {
-  return dot_step_impl(x, z, n, dpart, ppart, pj, dn, j, g, alpha, beta, dprev, coef, aest, s);
+                                   double* aest, double* cmat, hipStream_t s) {
+  return dot_step_impl(x, z, n, dpart, ppart, pj, dn, j, g, alpha, beta, dprev, coef, aest, cmat, s);
 }
 hipError_t launch_lanczos_dot_step(const float* x, const float* z, int64_t n, double* dpart,
                                    const double* ppart, int pj, double* dn, int j, double* g,
                                    double* alpha, double* beta, double* dprev, double* coef,
-                                   double* aest, hipStream_t s) {
-  return dot_step_impl(x, z, n, dpart, ppart, pj, dn, j, g, alpha, beta, dprev, coef, aest, s);
+                                   double* aest, double* cmat, hipStream_t s) {
+  return dot_step_impl(x, z, n, dpart, ppart, pj, dn, j, g, alpha, beta, dprev, coef, aest, cmat, s);
 }
 
 __global__ __launch_bounds__(256) void resid_kernel(const double* __restrict__ hy,

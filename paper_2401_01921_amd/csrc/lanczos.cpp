@@ -24,7 +24,7 @@ namespace bst {
 namespace {
 
 struct LanczosLayout {
-  size_t tables, V, W, Y, HY, scal, partial, dpart, end;
+  size_t tables, V, W, Y, HY, scal, cmat, partial, dpart, end;
   int64_t ldv;   // row stride of V: psi's size rounded up to 512 bytes
   int nslots;
 };
@@ -51,6 +51,8 @@ LanczosLayout layout(const PlanData& P, int nsteps) {
   // c, d, alpha, beta, s [kMaxVecs each], misc[16], cproj[kMaxVecs],
   // dn[kMaxVecs + 2]
   off = al(off + sizeof(double) * (7 * (size_t)kMaxVecs + 32));
+  L.cmat = off;   // the one-pass schedule's row-to-basis map, kMaxVecs x kMaxVecs
+  off = al(off + sizeof(double) * (size_t)kMaxVecs * kMaxVecs);
   L.partial = off;
   off = al(off + sizeof(double) * (size_t)(kMaxVecs + 1) * kVecBlocks);
   L.dpart = off;   // partials of the u_j.z dot
@@ -252,6 +254,7 @@ bst_status bst_lanczos_ground(bst_plan* heff, const void* const* ops, const void
                                       // [8..9] u_j.z, z.z, [10] alpha estimate
   double* cproj = misc + 16;
   double* dn = cproj + kMaxVecs;
+  double* cmat = reinterpret_cast<double*>(wb + Lo.cmat);
   double* partial = reinterpret_cast<double*>(wb + Lo.partial);
   double* dpart = reinterpret_cast<double*>(wb + Lo.dpart);
 
@@ -323,26 +326,26 @@ bst_status bst_lanczos_ground(bst_plan* heff, const void* const* ops, const void
       });
     } else {
       // row j holds u_j, W = H u_j: one launch for the dot u_j.z, the end
-      // of step j - 1 and the scalars of step j, then one pass over rows
-      // 0..j that finishes v_j and measures the residual
+      // of step j - 1, row j of C and the scalars of step j, then one pass
+      // over rows 0..j that forms the residual and measures it
       timed(4, [&] {
         if (vf32)
           check_hip(launch_lanczos_dot_step(V32 + (size_t)j * ldv, W32, n, dpart, partial, j - 1, dn, j,
-                                            misc + 8, alpha, beta, d, cproj, misc + 10, s),
+                                            misc + 8, alpha, beta, d, cproj, misc + 10, cmat, s),
                     "step scalars");
         else
           check_hip(launch_lanczos_dot_step(V + (size_t)j * ldv, W, n, dpart, partial, j - 1, dn, j,
-                                            misc + 8, alpha, beta, d, cproj, misc + 10, s),
+                                            misc + 8, alpha, beta, d, cproj, misc + 10, cmat, s),
                     "step scalars");
       });
       timed(5, [&] {
         if (vf32)
-          check_hip(launch_lanczos_pass(V32, ldv, n, j, W32, cproj, d, beta,
+          check_hip(launch_lanczos_pass(V32, ldv, n, j, W32, cproj, beta,
                                         j + 1 < nsteps ? V32 + (size_t)(j + 1) * ldv : nullptr, partial,
                                         nullptr, s),
                     "basis pass");
         else
-          check_hip(launch_lanczos_pass(V, ldv, n, j, W, cproj, d, beta, vnext, partial, nullptr, s),
+          check_hip(launch_lanczos_pass(V, ldv, n, j, W, cproj, beta, vnext, partial, nullptr, s),
                     "basis pass");
       });
     }
@@ -351,7 +354,7 @@ bst_status bst_lanczos_ground(bst_plan* heff, const void* const* ops, const void
     // the end of the last step
     timed(7, [&] {
       check_hip(launch_lanczos_pass_sums(n, nsteps - 1, vf32, partial, dn, s), "step sums");
-      check_hip(launch_lanczos_end(dn, misc + 10, nsteps - 1, d, alpha, beta, s), "step end");
+      check_hip(launch_lanczos_end(dn, misc + 10, nsteps - 1, cmat, d, alpha, beta, s), "step end");
     });
   }
   std::vector<double> ha(nsteps), hb(nsteps), m0(2);
@@ -375,7 +378,21 @@ bst_status bst_lanczos_ground(bst_plan* heff, const void* const* ops, const void
   double theta;
   std::vector<double> sv;
   lowest_eigenpair(a, b, theta, sv);
-  check_hip(hipMemcpyAsync(svec, sv.data(), sizeof(double) * m, hipMemcpyHostToDevice, s), "h2d");
+  // y = V s: with the one-pass schedule the rows are the residuals as
+  // written and v_k = sum_{i<=k} C[k][i] u_i, so the combination takes
+  // s'_i = sum_{k>=i} s_k C[k][i] over rows 0..m-1
+  std::vector<double> ycoef = sv;
+  if (!three_pass) {
+    std::vector<double> C((size_t)m * kMaxVecs);
+    check_hip(hipMemcpyAsync(C.data(), cmat, sizeof(double) * C.size(), hipMemcpyDeviceToHost, s), "d2h");
+    check_hip(hipStreamSynchronize(s), "d2h sync");
+    for (int i = 0; i < m; ++i) {
+      double t = 0.0;
+      for (int k = i; k < m; ++k) t += sv[k] * C[(size_t)k * kMaxVecs + i];
+      ycoef[i] = t;
+    }
+  }
+  check_hip(hipMemcpyAsync(svec, ycoef.data(), sizeof(double) * m, hipMemcpyHostToDevice, s), "h2d");
   check_hip(hipStreamSynchronize(s), "h2d sync");
   psi32.P.psi_f32 = psi32.P.z_f32 = false;   // the refinement: float64 in and out
   timed(7, [&] {
