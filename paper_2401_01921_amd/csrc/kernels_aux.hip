@@ -1301,10 +1301,12 @@ hipError_t launch_resid(const double* hy, const double* y, const double* num, in
   return hipGetLastError();
 }
 
+// 480 pointers (3840 bytes) per launch: within the 4 KiB of kernel arguments
+constexpr int kPtrChunk = 480;
 struct PtrChunk {
-  void* p[256];
+  void* p[kPtrChunk];
 };
-__global__ void set_ptrs_kernel(void** table, PtrChunk c, int n) {
+__global__ __launch_bounds__(512) void set_ptrs_kernel(void** table, PtrChunk c, int n) {
   const int i = threadIdx.x;
   if (i < n) table[i] = c.p[i];
 }
@@ -1312,11 +1314,11 @@ __global__ void set_ptrs_kernel(void** table, PtrChunk c, int n) {
 // Writes a device pointer table through a kernel argument (no host staging
 // buffer has to outlive the call).
 hipError_t launch_set_ptrs(void** table, void* const* src, int n, hipStream_t s) {
-  for (int base = 0; base < n; base += 256) {
+  for (int base = 0; base < n; base += kPtrChunk) {
     PtrChunk c{};
-    const int m = n - base < 256 ? n - base : 256;
+    const int m = n - base < kPtrChunk ? n - base : kPtrChunk;
     for (int i = 0; i < m; ++i) c.p[i] = src[base + i];
-    hipLaunchKernelGGL(set_ptrs_kernel, dim3(1), dim3(256), 0, s, table + base, c, m);
+    hipLaunchKernelGGL(set_ptrs_kernel, dim3(1), dim3(512), 0, s, table + base, c, m);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -262,14 +262,19 @@ bst_status bst_lanczos_ground(bst_plan* heff, const void* const* ops, const void
   const void* in0[5] = {ops[0], ops[1], ops[2], ops[3], V};
   void* out0[1] = {W};
   prepare_ws(P, in0, out0, ws, s);
+  // the nsteps + 1 tables sit back to back: one upload writes them all
   std::vector<void* const*> tables;
+  std::vector<void*> all;
+  all.reserve((size_t)Lo.nslots * (size_t)(nsteps + 1));
   for (int j = 0; j <= nsteps; ++j) {
     const void* in[5] = {ops[0], ops[1], ops[2], ops[3], j < nsteps ? (const void*)row(j) : (const void*)Y};
     void* out[1] = {j < nsteps ? (void*)W : (void*)HY};
     auto ptrs = build_ptrs(P, in, out, ws);
-    const size_t off = Lo.tables + sizeof(void*) * (size_t)Lo.nslots * (size_t)j;
-    tables.push_back(static_cast<void* const*>(upload_table(P, ptrs, ws, off, s)));
+    ptrs.resize((size_t)Lo.nslots, nullptr);
+    all.insert(all.end(), ptrs.begin(), ptrs.end());
   }
+  void* const* tab0 = static_cast<void* const*>(upload_table(P, all, ws, Lo.tables, s));
+  for (int j = 0; j <= nsteps; ++j) tables.push_back(tab0 + (size_t)Lo.nslots * (size_t)j);
   ClassTimer tm;
   tm.on = info && (info->flags & BST_LANCZOS_TIMING);
   const size_t nps = P.steps.size();
