@@ -83,12 +83,13 @@ def onepass_vector_flops(n: int, m: int) -> float:
     """Flops of the vector work a solve executes with the one-pass schedule
     (float64 arithmetic throughout): the start vector's norm and scaling;
     per step j the u_j.z and z.z dot (4n) and the basis pass (per element
-    2j for the lagged projection, 2j for the residual's combination, 2j for
-    the projections V^T w, plus 10 for v_j, w and their dots); the Ritz
-    vector (2nm); the refinement's two dots, residual and scaling."""
+    2(j+1) for the residual's combination of the stored rows 0..j, 2 for the
+    scaled z term, 2(j+1) for the measures u_m.w and 2 for w.w); the Ritz
+    vector (2nm); the refinement's two dots, residual and scaling.  The
+    scalar work on the triangular row map is O(j^2) per step, not counted."""
     f = 5.0 * n
     for j in range(m):
-        f += 4.0 * n + (6.0 * j + 10.0) * n
+        f += 4.0 * n + (4.0 * j + 8.0) * n
     return f + 2.0 * n * m + 9.0 * n
 
 
