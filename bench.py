@@ -207,17 +207,19 @@ def main():
                     mfma_tflops=fl * mult / avg_ms / 1e9, peak_tflops=MFMA_PEAK[prec],
                     mfma_frac=fl * mult / avg_ms / 1e9 / MFMA_PEAK[prec])
 
-    def gs_bytes(kind, rowb=8.0):
+    def gs_bytes(kind, res, rowb=8.0):
         # algorithmic bytes of one solve's Gram-Schmidt kernels (one-pass
         # schedule): the dot reads u_j and z; the pass of step j (0-based)
         # reads basis rows 0..j and z and (except on the last step) writes
-        # row j+1.  Rows and z are float64 (4 bytes with float32 rows).
+        # row j+1.  Rows are float64 (4 bytes with float32 rows); z is float64,
+        # or float32 when the solve reports it kept H u_j in float32.
+        zb = 4.0 if res.get("z32") else rowb
         tot = 0.0
         for j in range(m):
             if kind == "dots":
-                tot += 2.0 * rowb * n
+                tot += rowb * n + zb * n
             else:
-                tot += rowb * n * (j + 1) + rowb * n + (rowb * n if j + 1 < m else 0.0)
+                tot += rowb * n * (j + 1) + zb * n + (rowb * n if j + 1 < m else 0.0)
         return tot
 
     def hbm_roof(key, total_bytes, prof):
@@ -234,11 +236,11 @@ def main():
                        else gemm_roof("gemm_L_psi", prof_split, a.prec)),
         "gemm_T3_R": gemm_roof("gemm_T3_R", prof_split, a.prec),
         "mpo_apply": hbm_roof("mpo_apply", mpo_bytes * kc["mpo_apply"], prof_split),
-        "gs_dots": hbm_roof("gs_dots", gs_bytes("dots"), prof_split),
-        "gs_update": hbm_roof("gs_update", gs_bytes("update"), prof_split),
+        "gs_dots": hbm_roof("gs_dots", gs_bytes("dots", prof_split), prof_split),
+        "gs_update": hbm_roof("gs_update", gs_bytes("update", prof_split), prof_split),
         "fp64_gemm_L_psi": gemm_roof("gemm_L_psi", prof64, "fp64"),
         "fp64_gemm_T3_R": gemm_roof("gemm_T3_R", prof64, "fp64"),
-        "fp64_gs_update": hbm_roof("gs_update", gs_bytes("update"), prof64),
+        "fp64_gs_update": hbm_roof("gs_update", gs_bytes("update", prof64), prof64),
     }
     # dominant kernel of the step = largest summed time
     dom = max((k for k in km if kern.get(k) is not None), key=km.get)
@@ -295,6 +297,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": w["name"], "chi": w["chi"], "sectors": len(v), "spin": w["spin"],
                    "psi_elements": n, "lanczos_steps": m, "matvec": a.prec, "krylov_rows": "fp64",
+                   "h_u": ("fp32 (the matvec's float32 accumulators, exact)" if res_split.get("z32")
+                           else "fp64"),
                    "reorthogonalisation": "full, fp64, one basis pass per step",
                    "refine": "fp64", "flops_per_step": step_flops,
                    "heff_flops_per_apply": apply_flops},

@@ -341,6 +341,12 @@ typedef struct {
  * reorthogonalisation runs on float64 vectors; the three-pass schedule and
  * the FP64 / FP32 forms ignore this flag. */
 #define BST_LANCZOS_F32_BASIS 4
+/* Out (set in info->flags on return): H u_j was kept as float32 during the
+ * steps.  With BF16X3 / BF16X6 matvecs the products accumulate in float32,
+ * so this stores the same values in half the bytes; float64 rows and every
+ * dot and scalar stay float64.  BST_LANCZOS_Z64 in the environment keeps
+ * H u_j float64. */
+#define BST_LANCZOS_Z32 16
 
 /* Workspace of bst_lanczos_ground for a plan and step count. */
 bst_status bst_lanczos_workspace(const bst_plan* heff, int32_t nsteps, size_t* bytes);

@@ -514,7 +514,7 @@ def lanczos_ground(plan: Plan, ops, psi0, nsteps: int, prec="fp64", refine: bool
     m = info.steps
     out = dict(energy=e.value, theta=info.theta, steps=m, residual=info.residual,
                beta_min=info.beta_min, alpha=np.array(info.alpha[:m]), beta=np.array(info.beta[:m]),
-               psi=psi_out)
+               psi=psi_out, z32=bool(info.flags & 16))
     if timing:
         out["kernel_ms"] = {n: info.kernel_ms[i] for i, n in enumerate(LANCZOS_KERNEL_CLASSES)}
         out["kernel_calls"] = {n: info.kernel_calls[i] for i, n in enumerate(LANCZOS_KERNEL_CLASSES)}

@@ -433,6 +433,11 @@ hipError_t launch_lanczos_step_end(const double* partial, int64_t n_for_grid, co
 hipError_t launch_lanczos_pass(const double* V, int64_t ldv, int64_t n, int j, const double* z,
                                const double* coef, const double* beta, double* vnext, double* partial,
                                double* dn, hipStream_t s);
+// The same with z in float32 (a split-form matvec's float32 accumulators,
+// stored exactly).
+hipError_t launch_lanczos_pass(const double* V, int64_t ldv, int64_t n, int j, const float* z,
+                               const double* coef, const double* beta, double* vnext, double* partial,
+                               double* dn, hipStream_t s);
 // The same over a float32 basis (the residual rounded to float32 when
 // written; dots and scalars in float64).
 hipError_t launch_lanczos_pass(const float* V, int64_t ldv, int64_t n, int j, const float* z,
@@ -444,6 +449,10 @@ hipError_t launch_lanczos_pass(const float* V, int64_t ldv, int64_t n, int j, co
 // in launch_lanczos_pass skips that pass's own sums, which this call (or
 // launch_lanczos_pass_sums after the last step) then forms.
 hipError_t launch_lanczos_dot_step(const double* x, const double* z, int64_t n, double* dpart,
+                                   const double* ppart, int pj, double* dn, int j, double* g,
+                                   double* alpha, double* beta, double* dprev, double* coef,
+                                   double* aest, double* cmat, hipStream_t s);
+hipError_t launch_lanczos_dot_step(const double* x, const float* z, int64_t n, double* dpart,
                                    const double* ppart, int pj, double* dn, int j, double* g,
                                    double* alpha, double* beta, double* dprev, double* coef,
                                    double* aest, double* cmat, hipStream_t s);

@@ -636,9 +636,11 @@ hipError_t launch_lanczos_step_end(const double* partial, int64_t n_for_grid, co
 // The pass of step j: per element
 //   w = z rb - sum_{m<=j} cp_m u_m      written to vnext (if any)
 // and the block partials of u_m.w (m <= j) and w.w (j + 2 values).
-template <int NV>
+// z is float64, or float32 when the matvec's float32 accumulators wrote it
+// (exact: the same values).
+template <int NV, typename TZ>
 __global__ __launch_bounds__(256) void lanczos_pass_kernel(
-    const double* V, uint32_t ldv, uint32_t n, int j, const double* __restrict__ z,
+    const double* V, uint32_t ldv, uint32_t n, int j, const TZ* __restrict__ z,
     const double* __restrict__ coef, const double* __restrict__ beta, double* vnext,
     double* __restrict__ partial) {
   constexpr int NR = NV + 2;
@@ -665,7 +667,7 @@ __global__ __launch_bounds__(256) void lanczos_pass_kernel(
       off += rowb;
       asm volatile("" : "+v"(off));
     }
-    const double zi = __builtin_nontemporal_load(z + i);
+    const double zi = (double)__builtin_nontemporal_load(z + i);
     double sacc = 0.0;
 #pragma unroll
     for (int k = 0; k < NV; ++k) sacc += cs[k] * v[k];
@@ -1003,16 +1005,38 @@ __global__ __launch_bounds__(1024) void lanczos_step_scalars_kernel(
   }
 }
 
-hipError_t launch_lanczos_pass(const double* V, int64_t ldv, int64_t n, int j, const double* z,
-                               const double* coef, const double* beta, double* vnext, double* partial,
-                               double* dn, hipStream_t s) {
+template <typename TZ>
+static hipError_t pass_f64_impl(const double* V, int64_t ldv, int64_t n, int j, const TZ* z,
+                                const double* coef, const double* beta, double* vnext, double* partial,
+                                double* dn, hipStream_t s) {
   if (j < 0 || j + 2 > kMaxVecs + 1 || !fits32(V, ldv, n, j + 1)) return hipErrorInvalidValue;
   const int G = pass_grid_f64(n);
   const int nv = j + 1;   // rows 0..j
-  BST_NV_DISPATCH(lanczos_pass_kernel, dim3(G), dim3(256), 0, s, V, (uint32_t)ldv, (uint32_t)n, j,
-                  z, coef, beta, vnext, partial);
+#define BST_PF64(NV_)                                                                                  \
+  hipLaunchKernelGGL((lanczos_pass_kernel<NV_, TZ>), dim3(G), dim3(256), 0, s, V, (uint32_t)ldv, \
+                     (uint32_t)n, j, z, coef, beta, vnext, partial)
+  if (nv <= 8) BST_PF64(8);
+  else if (nv <= 16) BST_PF64(16);
+  else if (nv <= 24) BST_PF64(24);
+  else if (nv <= 32) BST_PF64(32);
+  else if (nv <= 40) BST_PF64(40);
+  else if (nv <= 48) BST_PF64(48);
+  else if (nv <= 64) BST_PF64(64);
+  else if (nv <= 96) BST_PF64(96);
+  else BST_PF64(128);
+#undef BST_PF64
   if (dn) hipLaunchKernelGGL(reduce_partials_kernel, dim3(j + 2), dim3(256), 0, s, partial, G, dn);
   return hipGetLastError();
+}
+hipError_t launch_lanczos_pass(const double* V, int64_t ldv, int64_t n, int j, const double* z,
+                               const double* coef, const double* beta, double* vnext, double* partial,
+                               double* dn, hipStream_t s) {
+  return pass_f64_impl(V, ldv, n, j, z, coef, beta, vnext, partial, dn, s);
+}
+hipError_t launch_lanczos_pass(const double* V, int64_t ldv, int64_t n, int j, const float* z,
+                               const double* coef, const double* beta, double* vnext, double* partial,
+                               double* dn, hipStream_t s) {
+  return pass_f64_impl(V, ldv, n, j, z, coef, beta, vnext, partial, dn, s);
 }
 
 hipError_t launch_lanczos_pass(const float* V, int64_t ldv, int64_t n, int j, const float* z,
@@ -1193,6 +1217,27 @@ __global__ __launch_bounds__(256) void dot2_kernel(const TX* __restrict__ x,
       acc[1] += (double)yv.x * (double)yv.x;
       acc[1] += (double)yv.y * (double)yv.y;
     }
+  } else if constexpr (PAIR && sizeof(TX) == 8 && sizeof(TY) == 4) {
+    // float64 x (16-byte aligned), float32 y (8-byte aligned): the pairs
+    // and the order of the float64 pair path, y widened exactly
+    typedef float fl2 __attribute__((ext_vector_type(2)));
+    const int64_t npair = (n + 1) / 2;
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < npair; p += stride) {
+      dbl2v xv, yv;
+      if (2 * p + 1 < n) {
+        xv = __builtin_nontemporal_load(reinterpret_cast<const dbl2v*>(x) + p);
+        const fl2 yf = __builtin_nontemporal_load(reinterpret_cast<const fl2*>(y) + p);
+        yv = dbl2v{(double)yf.x, (double)yf.y};
+      } else {
+        xv = dbl2v{(double)x[2 * p], 0.0};
+        yv = dbl2v{(double)y[2 * p], 0.0};
+      }
+      acc[0] += xv.x * yv.x;
+      acc[0] += xv.y * yv.y;
+      acc[1] += yv.x * yv.x;
+      acc[1] += yv.y * yv.y;
+    }
   } else if constexpr (PAIR && sizeof(TX) == 8 && sizeof(TY) == 8) {
     // float64 x and y, both 16-byte aligned: two elements per 16-byte load
     const int64_t npair = (n + 1) / 2;
@@ -1245,10 +1290,11 @@ static hipError_t dot_step_impl(const TX* x, const TZ* z, int64_t n, double* dpa
                                 double* alpha, double* beta, double* dprev, double* coef,
                                 double* aest, double* cmat, hipStream_t s) {
   if (j < 0 || j >= kMaxVecs || pj != j - 1 || n < 0) return hipErrorInvalidValue;
-  // two elements per lane: float32 x and z 8-byte aligned, or float64 x and
-  // z 16-byte aligned (one 8- or 16-byte load each)
-  const uintptr_t al = reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(z);
-  const bool pair = sizeof(TX) == sizeof(TZ) && n <= 0x7FFFFFFF && (al & (2 * sizeof(TX) - 1)) == 0;
+  // two elements per lane: x and z each aligned to two of its elements (one
+  // 8- or 16-byte load each)
+  const bool aligned = (reinterpret_cast<uintptr_t>(x) & (2 * sizeof(TX) - 1)) == 0 &&
+                       (reinterpret_cast<uintptr_t>(z) & (2 * sizeof(TZ) - 1)) == 0;
+  const bool pair = sizeof(TX) >= sizeof(TZ) && n <= 0x7FFFFFFF && aligned;
   const int G = pair ? vec_grid((n + 1) / 2) : vec_grid(n);
   // the basis pass's grid: one element (float64 rows) or pair (float32) per lane
   const int pG = sizeof(TX) == 4 ? pass_grid_f32(n) : pass_grid_f64(n);
@@ -1266,6 +1312,12 @@ static hipError_t dot_step_impl(const TX* x, const TZ* z, int64_t n, double* dpa
   return hipGetLastError();
 }
 hipError_t launch_lanczos_dot_step(const double* x, const double* z, int64_t n, double* dpart,
+                                   const double* ppart, int pj, double* dn, int j, double* g,
+                                   double* alpha, double* beta, double* dprev, double* coef,
+                                   double* aest, double* cmat, hipStream_t s) {
+  return dot_step_impl(x, z, n, dpart, ppart, pj, dn, j, g, alpha, beta, dprev, coef, aest, cmat, s);
+}
+hipError_t launch_lanczos_dot_step(const double* x, const float* z, int64_t n, double* dpart,
                                    const double* ppart, int pj, double* dn, int j, double* g,
                                    double* alpha, double* beta, double* dprev, double* coef,
                                    double* aest, double* cmat, hipStream_t s) {

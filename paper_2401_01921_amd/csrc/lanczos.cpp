@@ -310,12 +310,19 @@ bst_status bst_lanczos_ground(bst_plan* heff, const void* const* ops, const void
       check_hip(launch_scale_rnorm(static_cast<const double*>(psi0), misc + 1, V, n, s), "scale");
   });
   // with a float32 basis the matvec reads float32 rows and writes H u_j as
-  // float32 while the solve runs
+  // float32 while the solve runs.  With float64 rows and a split form, H u_j
+  // is still written as float32: the split GEMMs accumulate in float32, so
+  // the stored values are the same (BST_LANCZOS_Z64 keeps it float64).
+  const bool z32 = !three_pass && !vf32 && (matvec_prec == BST_BF16X3 || matvec_prec == BST_BF16X6) &&
+                   !std::getenv("BST_LANCZOS_Z64");
   struct Psi32 {
     PlanData& P;
-    Psi32(PlanData& p, bool on) : P(p) { P.psi_f32 = P.z_f32 = on; }
+    Psi32(PlanData& p, bool rows32, bool z) : P(p) {
+      P.psi_f32 = rows32;
+      P.z_f32 = rows32 || z;
+    }
     ~Psi32() { P.psi_f32 = P.z_f32 = false; }
-  } psi32(P, vf32);
+  } psi32(P, vf32, z32);
   for (int j = 0; j < nsteps; ++j) {
     matvec(tables[j], matvec_prec, j > 0);
     const int nv = j + 1;
@@ -338,6 +345,10 @@ bst_status bst_lanczos_ground(bst_plan* heff, const void* const* ops, const void
           check_hip(launch_lanczos_dot_step(V32 + (size_t)j * ldv, W32, n, dpart, partial, j - 1, dn, j,
                                             misc + 8, alpha, beta, d, cproj, misc + 10, cmat, s),
                     "step scalars");
+        else if (z32)
+          check_hip(launch_lanczos_dot_step(V + (size_t)j * ldv, W32, n, dpart, partial, j - 1, dn, j,
+                                            misc + 8, alpha, beta, d, cproj, misc + 10, cmat, s),
+                    "step scalars");
         else
           check_hip(launch_lanczos_dot_step(V + (size_t)j * ldv, W, n, dpart, partial, j - 1, dn, j,
                                             misc + 8, alpha, beta, d, cproj, misc + 10, cmat, s),
@@ -348,6 +359,9 @@ bst_status bst_lanczos_ground(bst_plan* heff, const void* const* ops, const void
           check_hip(launch_lanczos_pass(V32, ldv, n, j, W32, cproj, beta,
                                         j + 1 < nsteps ? V32 + (size_t)(j + 1) * ldv : nullptr, partial,
                                         nullptr, s),
+                    "basis pass");
+        else if (z32)
+          check_hip(launch_lanczos_pass(V, ldv, n, j, W32, cproj, beta, vnext, partial, nullptr, s),
                     "basis pass");
         else
           check_hip(launch_lanczos_pass(V, ldv, n, j, W, cproj, beta, vnext, partial, nullptr, s),
@@ -426,7 +440,7 @@ bst_status bst_lanczos_ground(bst_plan* heff, const void* const* ops, const void
   if (info) {
     const int32_t flags = info->flags;
     std::memset(info, 0, sizeof(*info));
-    info->flags = flags;
+    info->flags = (flags & ~BST_LANCZOS_Z32) | (z32 ? BST_LANCZOS_Z32 : 0);
     if (tm.on) tm.collect(info->kernel_ms, info->kernel_calls);
     info->steps = m;
     info->theta = theta;

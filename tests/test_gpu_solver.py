@@ -262,6 +262,27 @@ def test_lanczos_matches_oracle_medium(three_pass):
         assert err <= 1e-10, (prec, f32b, err)
 
 
+@pytest.mark.parametrize("prec", ["bf16x3", "bf16x6"])
+def test_lanczos_float32_z_is_exact(prec, monkeypatch):
+    """With float64 rows and a split form, H u_j is kept as float32 during the
+    steps: the split GEMMs accumulate in float32, so the values stored are
+    the ones a float64 H u_j holds, and the whole solve (every alpha and
+    beta, the Ritz value, the refined energy) is bit-identical to the one
+    that keeps H u_j float64 (BST_LANCZOS_Z64)."""
+    specs, O = heff_operands(5, recipe="dmrg_like", chi=256, qmax=8)
+    psi0 = wl.normal(wl.seed_for(5, "psi0"), O["psi"].numel)
+    r32 = _lanczos_lib(specs, O, 40, prec, psi0=psi0)
+    monkeypatch.setenv("BST_LANCZOS_Z64", "1")
+    r64 = _lanczos_lib(specs, O, 40, prec, psi0=psi0)
+    _print("z float32", prec, r32["z32"], r64["z32"], r32["energy"], r64["energy"])
+    assert r32["z32"] and not r64["z32"]
+    assert r32["steps"] == r64["steps"]
+    assert np.array_equal(r32["alpha"], r64["alpha"])
+    assert np.array_equal(r32["beta"], r64["beta"])
+    assert r32["theta"] == r64["theta"] and r32["energy"] == r64["energy"]
+    assert np.array_equal(host(r32["psi"]), host(r64["psi"]))
+
+
 def test_lanczos_full_size_matches_oracle_golden():
     """Spin-1 chi = 4096, 40 steps: refined energies against the oracle's
     value stored by tests/golden/make_lanczos_golden.py."""
