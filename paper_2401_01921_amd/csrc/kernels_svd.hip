@@ -17,8 +17,10 @@
 // arithmetic of every pair is a fixed sequence, so results repeat bit for
 // bit.
 #include <cfloat>
+#include <type_traits>
 
 #include "plan.h"
+
 #include "svd.h"
 
 namespace bst {
@@ -62,12 +64,13 @@ __device__ __forceinline__ double group_allsum(double v) {
   return v;
 }
 
-// The sweeps of one sector on X (p x r, column-major) and Vh (r x r): P is a
-// pointer to global memory or, for sectors held in LDS, an LDS-addressed
-// pointer (so that the compiler issues LDS accesses, not generic ones).  One
-// group of LP lanes per pair of a round.  Returns the sweeps used.
-template <int LP, typename P>
-__device__ int jacobi_sweeps(P x, P vh, int p, int r, int* rotated) {
+// The sweeps of one sector on X (p x r, column-major) and Vh (r x r): PX
+// and PV are pointers to global memory or, for what is held in LDS,
+// LDS-addressed pointers (so that the compiler issues LDS accesses, not
+// generic ones).  One group of LP lanes per pair of a round.  Returns the
+// sweeps used.
+template <int LP, typename PX, typename PV>
+__device__ int jacobi_sweeps(PX x, PV vh, int p, int r, int* rotated) {
   constexpr int NH = 64 * kSvdWaves / LP;   // lane groups of the workgroup
   const int tid = threadIdx.x, hl = tid % LP, half = tid / LP;
   const double tol = 4.0 * DBL_EPSILON * sqrt((double)p);
@@ -86,8 +89,8 @@ __device__ int jacobi_sweeps(P x, P vh, int p, int r, int* rotated) {
           j = q;
         }
         if (j >= r) continue;
-        P xi = x + (int64_t)i * p;
-        P xj = x + (int64_t)j * p;
+        PX xi = x + (int64_t)i * p;
+        PX xj = x + (int64_t)j * p;
         double a = 0.0, b = 0.0, g = 0.0;
         for (int e = hl; e < p; e += LP) {
           const double u = xi[e], v = xj[e];
@@ -107,8 +110,8 @@ __device__ int jacobi_sweeps(P x, P vh, int p, int r, int* rotated) {
           xi[e] = c * u - s * v;
           xj[e] = s * u + c * v;
         }
-        P vi = vh + (int64_t)i * r;
-        P vj = vh + (int64_t)j * r;
+        PV vi = vh + (int64_t)i * r;
+        PV vj = vh + (int64_t)j * r;
         for (int e = hl; e < r; e += LP) {
           const double u = vi[e], v = vj[e];
           vi[e] = c * u - s * v;
@@ -139,34 +142,43 @@ __global__ __launch_bounds__(64 * kSvdWaves) void svd_jacobi_kernel(const SvdSec
   double* const vg = V + S.v_off;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   __shared__ int rotated;
-  // A sector whose X and Vh fit in LDS (kSvdLdsBytes) is rotated there and
-  // copied back at the end; larger ones work in global memory.
+  // X is rotated in LDS when it fits kSvdLdsBytes, and Vh with it when both
+  // fit; what does not fit works in global memory (the three dots of a pair
+  // read X only, so X in LDS keeps them off global latency).  Copied back
+  // at the end.
   __shared__ double lds[kSvdLdsBytes / sizeof(double)];
-  const bool in_lds = ((int64_t)p * r + (int64_t)r * r) * (int64_t)sizeof(double) <= kSvdLdsBytes;
+  const bool x_lds = (int64_t)p * r * (int64_t)sizeof(double) <= kSvdLdsBytes;
+  const bool v_lds = x_lds && ((int64_t)p * r + (int64_t)r * r) * (int64_t)sizeof(double) <= kSvdLdsBytes;
   BST_LDS double* xl = (BST_LDS double*)lds;
   BST_LDS double* vl = xl + (int64_t)p * r;
-  if (in_lds) {
+  if (x_lds)
     for (int64_t e = tid; e < (int64_t)p * r; e += NT) xl[e] = xg[e];
+  if (v_lds)
     for (int64_t e = tid; e < (int64_t)r * r; e += NT) vl[e] = (e % r == e / r) ? 1.0 : 0.0;
-  } else {
+  else
     for (int64_t e = tid; e < (int64_t)r * r; e += NT) vg[e] = (e % r == e / r) ? 1.0 : 0.0;
-  }
   if (tid == 0) rotated = 0;
   __syncthreads();
   // the widest lane groups that still give every pair of a round its own
   // group (wide groups for few long columns, narrow ones for many short)
   const int npairs = (r + 1) / 2;
+  auto sweeps_lp = [&](auto lp) {
+    constexpr int L = decltype(lp)::value;
+    if (v_lds) return jacobi_sweeps<L>(xl, vl, p, r, &rotated);
+    if (x_lds) return jacobi_sweeps<L>(xl, vg, p, r, &rotated);
+    return jacobi_sweeps<L>(xg, vg, p, r, &rotated);
+  };
   int sw;
   if (npairs <= NT / 64)
-    sw = in_lds ? jacobi_sweeps<64>(xl, vl, p, r, &rotated) : jacobi_sweeps<64>(xg, vg, p, r, &rotated);
+    sw = sweeps_lp(std::integral_constant<int, 64>());
   else if (npairs <= NT / 32)
-    sw = in_lds ? jacobi_sweeps<32>(xl, vl, p, r, &rotated) : jacobi_sweeps<32>(xg, vg, p, r, &rotated);
+    sw = sweeps_lp(std::integral_constant<int, 32>());
   else
-    sw = in_lds ? jacobi_sweeps<16>(xl, vl, p, r, &rotated) : jacobi_sweeps<16>(xg, vg, p, r, &rotated);
+    sw = sweeps_lp(std::integral_constant<int, 16>());
   // sigma_j = |x_j| (one column per wave), from where the sweeps left X
   for (int j = wave; j < r; j += kSvdWaves) {
     double a = 0.0;
-    if (in_lds) {
+    if (x_lds) {
       for (int e = lane; e < p; e += 64) a += xl[(int64_t)j * p + e] * xl[(int64_t)j * p + e];
     } else {
       for (int e = lane; e < p; e += 64) a += xg[(int64_t)j * p + e] * xg[(int64_t)j * p + e];
@@ -174,10 +186,10 @@ __global__ __launch_bounds__(64 * kSvdWaves) void svd_jacobi_kernel(const SvdSec
     a = wave_allsum(a);
     if (lane == 0) sig[S.s_off + j] = sqrt(a);
   }
-  if (in_lds) {
+  if (x_lds)
     for (int64_t e = tid; e < (int64_t)p * r; e += NT) xg[e] = xl[e];
+  if (v_lds)
     for (int64_t e = tid; e < (int64_t)r * r; e += NT) vg[e] = vl[e];
-  }
   __syncthreads();
   // descending order, ties by column: rank of every value
   for (int j = tid; j < r; j += NT) {

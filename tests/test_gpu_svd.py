@@ -141,6 +141,21 @@ def test_large_sector_matrices():
     assert sum(g["kept"]) == 120
 
 
+def test_sector_residency_paths():
+    """The three places a sector's Jacobi sweeps run: X and Vh in LDS (the
+    30 x 40 sectors), X in LDS with Vh in global memory (110 x 130: X 114 KB,
+    Vh 97 KB), and both in global memory (110 x 240: X 211 KB)."""
+    va = [(-2, 30), (0, 80), (2, 30)]
+    for vb, big in (([(-2, 40), (0, 90), (2, 40)], 130), ([(-2, 40), (0, 200), (2, 40)], 240)):
+        ph = [(1, 1), (-1, 1)]
+        O = orc.BlockTensor(["a", "s1", "s2", "b"], [(1, va), (1, ph), (1, ph), (-1, vb)])
+        secs = orc.svd_sectors(O, 2)
+        assert max(max(s["M"].shape) for s in secs) == big
+        O.data[:] = np.random.default_rng(11).standard_normal(O.numel)
+        g = _compare(O, 2, 150, 1e-12, None, f"residency {big}")
+        assert sum(g["kept"]) == 150
+
+
 def test_rank_deficient_and_thin():
     """Zero singular values (a rank-deficient sector), a sector with a
     single column, and exact repeats."""
