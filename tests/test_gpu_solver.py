@@ -262,6 +262,28 @@ def test_lanczos_matches_oracle_medium(three_pass):
         assert err <= 1e-10, (prec, f32b, err)
 
 
+@pytest.mark.parametrize("nsteps", [1, 2, 3])
+def test_lanczos_few_steps(nsteps):
+    """One to three steps (the first and last steps of the one-pass schedule
+    at once, C of size 1 to 3): alpha, beta and the refined energy against
+    the oracle's textbook Lanczos with the same steps; the split forms,
+    whose few-step Ritz vector is far from an eigenvector, to their matvec
+    error."""
+    specs, O = heff_operands(5, recipe="dmrg_like", chi=256, qmax=8)
+    psi0 = wl.normal(wl.seed_for(5, "psi0"), O["psi"].numel)
+    mv = lambda v: orc.heff_apply(O["L"], O["W1"], O["W2"], O["R"],
+                                  orc.BlockTensor(O["psi"].labels, O["psi"].legs, v)).data
+    ref = orc.lanczos_ground(mv, psi0, nsteps)
+    scale = np.max(np.abs(ref["alpha"]))
+    for prec, f32b, tol in (("fp64", False, 1e-12), ("bf16x3", False, 1e-5), ("bf16x3", True, 1e-5)):
+        r = _lanczos_lib(specs, O, nsteps, prec, psi0=psi0, f32_basis=f32b)
+        _print("few steps", nsteps, prec, f32b, r["alpha"], ref["alpha"], r["energy"], ref["energy"])
+        assert r["steps"] == ref["steps"] == nsteps
+        assert np.max(np.abs(r["alpha"] - ref["alpha"])) <= tol * scale
+        assert np.max(np.abs(r["beta"][:nsteps] - ref["beta"][:nsteps])) <= tol * scale
+        assert abs(r["energy"] - ref["energy"]) <= tol * abs(ref["energy"])
+
+
 @pytest.mark.parametrize("prec", ["bf16x3", "bf16x6"])
 def test_lanczos_float32_z_is_exact(prec, monkeypatch):
     """With float64 rows and a split form, H u_j is kept as float32 during the
