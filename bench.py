@@ -576,6 +576,27 @@ def bench_widened(bst, wl, torch, dev):
         "s_per_sweep": round(sweep_s, 3), "bond_updates": len(E),
         "energy": E[-1], "exact_free_fermion": exact, "abs_err": abs(E[-1] - exact),
         "max_s_err": max(errs)}
+    # -- the same chain at N = 64, keepdim 256 (random start with every sector
+    # of every bond capped at 16, so that the first sweep grows the bonds)
+    N, keep, cap, nsw = 64, 256, 16, 2
+    specs = wl.mps_specs(N, "1/2", 0, cap=cap)
+    mps = []
+    for i, (lab, legs) in enumerate(specs):
+        t = bst.Tensor(lab, legs)
+        mps.append(dmrg.DevTensor(t, torch.from_numpy(wl.normal(wl.seed_for(2, "A", i), t.numel)).to(dev)))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    E, errs, fin = dmrg.dmrg_two_site(mps, Wg, envs[0], envs[1], nsw, keep, 1e-12)
+    torch.cuda.synchronize()
+    sweep_s = (time.perf_counter() - t0) / nsw
+    exact = sum(min(0.0, math.cos(math.pi * k / (N + 1))) for k in range(1, N + 1))
+    out["dmrg_sweep_xx_n64_chi256"] = {
+        "workload": f"open XX chain, spin 1/2, N = {N}, total Sz 0, keepdim {keep}, {nsw} sweeps from a random MPS "
+                    f"with sectors capped at {cap}",
+        "s_per_sweep": round(sweep_s, 3), "bond_updates": len(E),
+        "largest_bond": max(int(sum(g for _, g in T.t.legs()[1][2][1])) for T in fin),
+        "energy": E[-1], "exact_free_fermion": exact, "abs_err": abs(E[-1] - exact),
+        "max_s_err": max(errs)}
     # -- complex contraction A[l, s, m] . B[m, t, r], chi = 2048 (q in [-16, 16])
     v = wl.gaussian_sector_dims(2048, 16)
     A = (["l", "s", "m"], [(1, v), (1, ph), (-1, v)])
