@@ -170,13 +170,13 @@ hipError_t launch_permute(const PermLaunch& p, hipStream_t s) {
 // matrix h[o][i] = sum_w2 W1[w1,s1,t1,w2] W2[w2,s2,t2,w3] (Sec. "Benchmarks",
 // Fig. Hpsi_fig: the two W's form the two-site operator h).
 // ------------------------------------------------------------------------
-// One thread per coefficient row (class, output o): every entry of the row
-// is the sum of its W1*W2 terms in a fixed order; the row is written dense
-// (coef64/coef32) and compacted to its nonzero entries in increasing input
-// order (cnt, idx, val64, val32) for the sparse apply.
+// Every entry of a coefficient row (class, output o) is the sum of its W1*W2
+// terms in a fixed order; the row is written dense (coef64/coef32) and
+// compacted to its nonzero entries in increasing input order (cnt, idx,
+// val64, val32) for the sparse apply.
 __global__ __launch_bounds__(256) void hcoef_kernel(const HTerm* __restrict__ terms,
                                                     const int32_t* __restrict__ entry_begin,
-                                                    int64_t nrows, int nmax,
+                                                    int64_t nentries, int nmax,
                                                     void* const* __restrict__ ptrs,
                                                     double* __restrict__ c64,
                                                     float* __restrict__ c32,
@@ -184,12 +184,13 @@ __global__ __launch_bounds__(256) void hcoef_kernel(const HTerm* __restrict__ te
                                                     int32_t* __restrict__ idx,
                                                     double* __restrict__ v64,
                                                     float* __restrict__ v32) {
-  const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (row >= nrows) return;
-  int32_t n = 0;
-  for (int i = 0; i < nmax; ++i) {
-    const int64_t e = row * nmax + i;
-    double sum = 0.0;
+  // one lane per entry, then one lane per row compacts the row (nmax
+  // divides 256, so a workgroup holds whole rows)
+  __shared__ double cs[256];
+  const int tid = threadIdx.x;
+  const int64_t e = (int64_t)blockIdx.x * 256 + tid;
+  double sum = 0.0;
+  if (e < nentries) {
     for (int32_t k = entry_begin[e]; k < entry_begin[e + 1]; ++k) {
       const HTerm t = terms[k];
       const double w1 = ((const BST_G double*)(ptrs[t.w1_buf]))[t.w1_off];
@@ -198,10 +199,20 @@ __global__ __launch_bounds__(256) void hcoef_kernel(const HTerm* __restrict__ te
     }
     c64[e] = sum;
     c32[e] = (float)sum;
-    if (sum != 0.0) {
+  }
+  cs[tid] = sum;
+  __syncthreads();
+  const int rpb = 256 / nmax;
+  if (tid >= rpb) return;
+  const int64_t row = (int64_t)blockIdx.x * rpb + tid;
+  if (row * nmax >= nentries) return;
+  int32_t n = 0;
+  for (int i = 0; i < nmax; ++i) {
+    const double v = cs[tid * nmax + i];
+    if (v != 0.0) {
       idx[row * nmax + n] = i;
-      v64[row * nmax + n] = sum;
-      v32[row * nmax + n] = (float)sum;
+      v64[row * nmax + n] = v;
+      v32[row * nmax + n] = (float)v;
       ++n;
     }
   }
@@ -210,9 +221,9 @@ __global__ __launch_bounds__(256) void hcoef_kernel(const HTerm* __restrict__ te
 
 hipError_t launch_hcoef(const HCoefLaunch& c, hipStream_t s) {
   if (c.nentries <= 0) return hipSuccess;
-  const int64_t nrows = c.nentries / c.nmax;
-  const unsigned blocks = (unsigned)((nrows + 255) / 256);
-  hipLaunchKernelGGL(hcoef_kernel, dim3(blocks), dim3(256), 0, s, c.terms, c.entry_begin, nrows,
+  if (c.nmax <= 0 || 256 % c.nmax != 0 || c.nentries % c.nmax != 0) return hipErrorInvalidValue;
+  const unsigned blocks = (unsigned)((c.nentries + 255) / 256);
+  hipLaunchKernelGGL(hcoef_kernel, dim3(blocks), dim3(256), 0, s, c.terms, c.entry_begin, c.nentries,
                      c.nmax, c.ptrs, c.coef64, c.coef32, c.cnt, c.idx, c.val64, c.val32);
   return hipGetLastError();
 }
