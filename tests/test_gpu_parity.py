@@ -260,13 +260,21 @@ def test_heff_spin_half_chi2048_error_table(prec):
     check(got, ref, prec, "heff chi2048")
 
 
-def test_heff_spin_one_chi4096_fp64():
-    """The Lanczos workload's operator at full size, float64 form."""
-    specs, O = heff_operands(5, recipe="dmrg_like")
-    ref = orc.heff_apply(O["L"], O["W1"], O["W2"], O["R"], O["psi"]).data
-    T, plan = lib_heff(specs, "fp64")
+_CHI4096 = {}
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "bf16x6"])
+def test_heff_spin_one_chi4096(prec):
+    """The Lanczos workload's operator at full size, every form, against the
+    oracle at the form's tolerance (the oracle's apply is computed once)."""
+    if not _CHI4096:
+        specs, O = heff_operands(5, recipe="dmrg_like")
+        _CHI4096.update(specs=specs, O=O,
+                        ref=orc.heff_apply(O["L"], O["W1"], O["W2"], O["R"], O["psi"]).data)
+    specs, O, ref = _CHI4096["specs"], _CHI4096["O"], _CHI4096["ref"]
+    T, plan = lib_heff(specs, prec)
     got = run_heff(plan, O)
-    check(got, ref, "fp64", "heff chi4096")
+    check(got, ref, prec, "heff chi4096")
 
 
 def test_heff_graph_replay_matches_eager():
