@@ -439,7 +439,10 @@ bst_status bst_svd_sector(const bst_svd* p, int32_t k, int32_t* charge, int64_t*
  * sweeps); singular values sorted in descending order per sector.  The
  * singular vectors of a zero singular value are returned as zero vectors
  * on the long side.  Results stay in the workspace for bst_svd_truncate
- * and bst_svd_write. */
+ * and bst_svd_write.  A sector matrix above 128 KiB (long side x short side
+ * float64 values) runs each round of its sweeps as one launch across the
+ * device; the call then waits for the stream after every sweep to test
+ * convergence (otherwise it only enqueues). */
 bst_status bst_svd_execute(bst_svd* p, const void* M, void* ws, void* stream);
 
 /* Chooses the kept singular values across all sectors (after

@@ -15,7 +15,10 @@
 // round at once (one lane group each, disjoint columns); they stop after a sweep
 // without a rotation (|g| <= tol sqrt(a b)).  Then sigma_j = |x_j|.  The
 // arithmetic of every pair is a fixed sequence, so results repeat bit for
-// bit.
+// bit.  A sector whose X does not fit LDS would pull every round's columns
+// through one CU's L2; such sectors instead run a round per launch, each
+// pair of the round on a workgroup of its own (svd_round_kernel).
+#include <algorithm>
 #include <cfloat>
 #include <type_traits>
 
@@ -151,11 +154,13 @@ __global__ __launch_bounds__(64 * kSvdWaves) void svd_jacobi_kernel(const SvdSec
   const bool v_lds = x_lds && ((int64_t)p * r + (int64_t)r * r) * (int64_t)sizeof(double) <= kSvdLdsBytes;
   BST_LDS double* xl = (BST_LDS double*)lds;
   BST_LDS double* vl = xl + (int64_t)p * r;
+  // a big sector arrives rotated (svd_round_kernel), its sweeps counted
+  const bool pre = svd_sector_is_big(S.m, S.n);
   if (x_lds)
     for (int64_t e = tid; e < (int64_t)p * r; e += NT) xl[e] = xg[e];
   if (v_lds)
     for (int64_t e = tid; e < (int64_t)r * r; e += NT) vl[e] = (e % r == e / r) ? 1.0 : 0.0;
-  else
+  else if (!pre)
     for (int64_t e = tid; e < (int64_t)r * r; e += NT) vg[e] = (e % r == e / r) ? 1.0 : 0.0;
   if (tid == 0) rotated = 0;
   __syncthreads();
@@ -169,7 +174,9 @@ __global__ __launch_bounds__(64 * kSvdWaves) void svd_jacobi_kernel(const SvdSec
     return jacobi_sweeps<L>(xg, vg, p, r, &rotated);
   };
   int sw;
-  if (npairs <= NT / 64)
+  if (pre)
+    sw = sweeps[blockIdx.x];
+  else if (npairs <= NT / 64)
     sw = sweeps_lp(std::integral_constant<int, 64>());
   else if (npairs <= NT / 32)
     sw = sweeps_lp(std::integral_constant<int, 32>());
@@ -205,10 +212,130 @@ __global__ __launch_bounds__(64 * kSvdWaves) void svd_jacobi_kernel(const SvdSec
   if (tid == 0) sweeps[blockIdx.x] = sw;
 }
 
-hipError_t launch_svd_execute(const SvdLaunch& l, hipStream_t s) {
-  if (l.ngwork > 0x7FFFFFFF || l.nsec < 0) return hipErrorInvalidValue;
+// Rounds of the big sectors, a launch per round.  Block (k, b) takes pair k
+// of round t of big sector b (the circle order of jacobi_sweeps) with 256
+// lanes: the three sums over the column (lane-strided, then the wave sums
+// and the four waves in order), the same test and rotation, both columns of
+// X and of Vh updated.  Any rotation sets the sector's flag for the sweep.
+__global__ __launch_bounds__(256) void svd_round_kernel(const SvdSec* __restrict__ secs,
+                                                        const int32_t* __restrict__ big, double* X, double* V,
+                                                        int t, int32_t* flags) {
+  const int b = blockIdx.y;
+  if (flags[2 * b + 1]) return;   // converged
+  const SvdSec S = secs[big[b]];
+  const int p = S.m >= S.n ? S.m : S.n, r = S.m >= S.n ? S.n : S.m;
+  const int rr = r + (r & 1);
+  const int k = blockIdx.x;
+  if (t >= rr - 1 || k >= rr / 2) return;
+  const int s0 = k, s1 = rr - 1 - k;
+  int i = s0 == 0 ? 0 : (s0 - 1 + t) % (rr - 1) + 1;
+  int j = (s1 - 1 + t) % (rr - 1) + 1;
+  if (i > j) {
+    const int q = i;
+    i = j;
+    j = q;
+  }
+  if (j >= r) return;
+  double* const xi = X + S.x_off + (int64_t)i * p;
+  double* const xj = X + S.x_off + (int64_t)j * p;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double a = 0.0, bb = 0.0, g = 0.0;
+  for (int e = tid; e < p; e += 256) {
+    const double u = xi[e], v = xj[e];
+    a += u * u;
+    bb += v * v;
+    g += u * v;
+  }
+  a = wave_allsum(a);
+  bb = wave_allsum(bb);
+  g = wave_allsum(g);
+  __shared__ double red[3][4];
+  if (lane == 0) {
+    red[0][wave] = a;
+    red[1][wave] = bb;
+    red[2][wave] = g;
+  }
+  __syncthreads();
+  a = ((red[0][0] + red[0][1]) + red[0][2]) + red[0][3];
+  bb = ((red[1][0] + red[1][1]) + red[1][2]) + red[1][3];
+  g = ((red[2][0] + red[2][1]) + red[2][2]) + red[2][3];
+  const double tol = 4.0 * DBL_EPSILON * sqrt((double)p);
+  if (a == 0.0 || bb == 0.0 || !(fabs(g) > tol * sqrt(a) * sqrt(bb))) return;
+  const double zeta = (bb - a) / (2.0 * g);
+  const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  const double c = 1.0 / sqrt(1.0 + tt * tt), sn = c * tt;
+  for (int e = tid; e < p; e += 256) {
+    const double u = xi[e], v = xj[e];
+    xi[e] = c * u - sn * v;
+    xj[e] = sn * u + c * v;
+  }
+  double* const vi = V + S.v_off + (int64_t)i * r;
+  double* const vj = V + S.v_off + (int64_t)j * r;
+  for (int e = tid; e < r; e += 256) {
+    const double u = vi[e], v = vj[e];
+    vi[e] = c * u - sn * v;
+    vj[e] = sn * u + c * v;
+  }
+  if (tid == 0) flags[2 * b] = 1;
+}
+
+// Identity Vh and cleared flags and counts of the big sectors (grid y: the
+// sector, x: pieces of its r x r).
+__global__ __launch_bounds__(256) void svd_big_init_kernel(const SvdSec* __restrict__ secs,
+                                                           const int32_t* __restrict__ big, double* V,
+                                                           int32_t* flags, int32_t* sweeps) {
+  const int b = blockIdx.y;
+  const SvdSec S = secs[big[b]];
+  const int64_t r = S.m >= S.n ? S.n : S.m;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < r * r; e += (int64_t)gridDim.x * 256)
+    V[S.v_off + e] = (e % r == e / r) ? 1.0 : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    flags[2 * b] = 0;
+    flags[2 * b + 1] = 0;
+    sweeps[big[b]] = 0;
+  }
+}
+
+// End of a sweep of the big sectors: a sector that rotated counts the
+// sweep, one that did not is converged (as jacobi_sweeps stops).
+__global__ __launch_bounds__(256) void svd_sweep_end_kernel(int nbig, const int32_t* __restrict__ big,
+                                                            int32_t* flags, int32_t* sweeps) {
+  for (int b = blockIdx.x * 256 + threadIdx.x; b < nbig; b += gridDim.x * 256) {
+    if (!flags[2 * b + 1]) {
+      if (flags[2 * b])
+        sweeps[big[b]] += 1;
+      else
+        flags[2 * b + 1] = 1;
+    }
+    flags[2 * b] = 0;
+  }
+}
+
+hipError_t launch_svd_gather(const SvdLaunch& l, hipStream_t s) {
+  if (l.ngwork > 0x7FFFFFFF || l.nsec < 0 || l.nbig < 0 || l.nbig > 65535) return hipErrorInvalidValue;
   if (l.ngwork > 0)
     hipLaunchKernelGGL(svd_gather_kernel, dim3((unsigned)l.ngwork), dim3(256), 0, s, l.gjobs, l.gwork, l.in, l.X);
+  if (l.nbig > 0) {
+    const int64_t gx = std::min<int64_t>(std::max<int64_t>((l.vmax + 4095) / 4096, 1), 1024);
+    hipLaunchKernelGGL(svd_big_init_kernel, dim3((unsigned)gx, (unsigned)l.nbig), dim3(256), 0, s, l.secs, l.big,
+                       l.V, l.flags, l.sweeps);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_svd_sweep(const SvdLaunch& l, hipStream_t s) {
+  if (l.nbig <= 0) return hipSuccess;
+  if (l.nbig > 65535 || l.pairs <= 0 || l.rounds <= 0) return hipErrorInvalidValue;
+  for (int t = 0; t < l.rounds; ++t)
+    hipLaunchKernelGGL(svd_round_kernel, dim3((unsigned)l.pairs, (unsigned)l.nbig), dim3(256), 0, s, l.secs, l.big,
+                       l.X, l.V, t, l.flags);
+  hipLaunchKernelGGL(svd_sweep_end_kernel, dim3((unsigned)((l.nbig + 255) / 256)), dim3(256), 0, s, l.nbig, l.big,
+                     l.flags, l.sweeps);
+  return hipGetLastError();
+}
+
+hipError_t launch_svd_finish(const SvdLaunch& l, hipStream_t s) {
+  if (l.nsec < 0) return hipErrorInvalidValue;
   if (l.nsec > 0)
     hipLaunchKernelGGL(svd_jacobi_kernel, dim3((unsigned)l.nsec), dim3(64 * kSvdWaves), 0, s, l.secs, l.X, l.V,
                        l.sig, l.sorted, l.perm, l.sweeps);

@@ -49,6 +49,11 @@ struct SvdPlanData {
   size_t ws_tab = 0, ws_secs = 0, ws_gjobs = 0, ws_gwork = 0, ws_x = 0, ws_v = 0, ws_sig = 0, ws_sorted = 0,
          ws_perm = 0, ws_sweeps = 0, ws_kept = 0, ws_serr = 0, ws_mb = 0, ws_wtab = 0, ws_bytes = 0;
   size_t wtab_cap = 0;   // bytes reserved for the write tables
+  // sectors rotated a round per launch (X larger than the LDS budget)
+  std::vector<int32_t> big;
+  size_t ws_big = 0, ws_flags = 0;
+  int32_t rounds = 0, pairs = 0;
+  int64_t vmax = 0;
   std::vector<uint8_t> blob;   // sector and gather tables
   int64_t ngwork = 0;
   void* uploaded = nullptr;
@@ -171,6 +176,19 @@ void build(SvdPlanData& P) {
   }
   P.nvalues = so;
   if (so > 0x7FFFFFFF) fail(BST_E_INVALID, "too many singular values");
+  P.big.clear();
+  P.rounds = P.pairs = 0;
+  P.vmax = 0;
+  for (size_t k = 0; k < P.secs.size(); ++k) {
+    const int64_t m = P.secs[k].m, n = P.secs[k].n;
+    if (!svd_sector_is_big(m, n)) continue;
+    const int64_t r = std::min(m, n), rr = r + (r & 1);
+    P.big.push_back((int32_t)k);
+    P.rounds = (int32_t)std::max<int64_t>(P.rounds, rr - 1);
+    P.pairs = (int32_t)std::max<int64_t>(P.pairs, rr / 2);
+    P.vmax = std::max(P.vmax, r * r);
+  }
+  if (P.big.size() > 65535) fail(BST_E_INVALID, "more than 65535 sector matrices above the LDS budget");
   // gather jobs: every block of T into its sector matrix
   std::vector<SvdGather> gj;
   std::vector<SvdWork> gw;
@@ -206,6 +224,7 @@ void build(SvdPlanData& P) {
   P.ws_secs = put(P.blob, dsecs);
   P.ws_gjobs = put(P.blob, gj);
   P.ws_gwork = put(P.blob, gw);
+  P.ws_big = put(P.blob, P.big);
   size_t off = align256(P.blob.size());
   P.ws_tab = 0;
   auto take = [&](size_t bytes) {
@@ -222,6 +241,7 @@ void build(SvdPlanData& P) {
   P.ws_kept = take(sizeof(int64_t) * P.secs.size());
   P.ws_serr = take(sizeof(double));
   P.ws_mb = take(sizeof(int64_t) * P.secs.size());
+  P.ws_flags = take(sizeof(int32_t) * 2 * P.big.size());
   // write tables: one job per block of U and V^dagger and one per S sector,
   // work items of kSvdGatherChunk elements
   int64_t wjobs = 2 * (int64_t)P.secs.size();
@@ -341,7 +361,28 @@ bst_status bst_svd_execute(bst_svd* p, const void* M, void* ws, void* stream) {
   l.sorted = at<double>(ws, P.ws_sorted);
   l.perm = at<int32_t>(ws, P.ws_perm);
   l.sweeps = at<int32_t>(ws, P.ws_sweeps);
-  check_hip(launch_svd_execute(l, s), "svd");
+  l.big = at<const int32_t>(ws, P.ws_big);
+  l.nbig = (int32_t)P.big.size();
+  l.rounds = P.rounds;
+  l.pairs = P.pairs;
+  l.vmax = P.vmax;
+  l.flags = at<int32_t>(ws, P.ws_flags);
+  check_hip(launch_svd_gather(l, s), "svd gather");
+  if (l.nbig > 0) {
+    // sweeps of the big sectors until each has had one without a rotation
+    // (at most kSvdMaxSweeps): the host reads the flags after every sweep
+    std::vector<int32_t> fl(2 * (size_t)l.nbig);
+    for (int sw = 0; sw < kSvdMaxSweeps; ++sw) {
+      check_hip(launch_svd_sweep(l, s), "svd sweep");
+      check_hip(hipMemcpyAsync(fl.data(), l.flags, sizeof(int32_t) * fl.size(), hipMemcpyDeviceToHost, s),
+                "svd flags");
+      check_hip(hipStreamSynchronize(s), "svd flags");
+      bool all = true;
+      for (int b = 0; b < l.nbig; ++b) all = all && fl[2 * (size_t)b + 1] != 0;
+      if (all) break;
+    }
+  }
+  check_hip(launch_svd_finish(l, s), "svd");
   BST_CATCH
 }
 

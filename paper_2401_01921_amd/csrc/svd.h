@@ -10,6 +10,8 @@
 //   tall: U = x_j / sigma_j, V = Vh;      wide: U = Vh, V = x_j / sigma_j.
 #pragma once
 
+#include <hip/hip_runtime.h>
+
 #include <cstdint>
 
 namespace bst {
@@ -67,8 +69,30 @@ struct SvdLaunch {
   double* sorted;     // the same values in descending order
   int32_t* perm;      // column of X (or Vh) of the c-th largest value
   int32_t* sweeps;    // per sector: sweeps used (diagnostic)
+  // sectors whose X exceeds kSvdLdsBytes (and r > 1): rotated a round per
+  // launch by the whole device before the per-sector kernel
+  const int32_t* big;   // their sector indices
+  int32_t nbig;
+  int32_t rounds;       // most rounds per sweep over them (r + (r & 1) - 1)
+  int32_t pairs;        // most pairs per round
+  int64_t vmax;         // largest r * r
+  int32_t* flags;       // per big sector: [rotated this sweep, converged]
 };
-hipError_t launch_svd_execute(const SvdLaunch& l, hipStream_t s);
+// The gather, and the identity Vh and cleared flags of the big sectors.
+hipError_t launch_svd_gather(const SvdLaunch& l, hipStream_t s);
+// One sweep over the big sectors not yet converged: every round, then the
+// sweep's count (a sector whose sweep rotated nothing is marked converged).
+hipError_t launch_svd_sweep(const SvdLaunch& l, hipStream_t s);
+// The sweeps of the other sectors (one workgroup each), then sigma and the
+// sorted order of every sector.
+hipError_t launch_svd_finish(const SvdLaunch& l, hipStream_t s);
+
+// True when sector (m, n)'s sweeps run a round per launch on the device
+// rather than in one workgroup (its X does not fit kSvdLdsBytes).
+__host__ __device__ inline bool svd_sector_is_big(int64_t m, int64_t n) {
+  const int64_t p = m >= n ? m : n, r = m >= n ? n : m;
+  return r > 1 && p * r * 8 > kSvdLdsBytes;
+}
 
 struct SvdSelectLaunch {
   const SvdSec* secs;

@@ -144,7 +144,8 @@ def test_large_sector_matrices():
 def test_sector_residency_paths():
     """The three places a sector's Jacobi sweeps run: X and Vh in LDS (the
     30 x 40 sectors), X in LDS with Vh in global memory (110 x 130: X 114 KB,
-    Vh 97 KB), and both in global memory (110 x 240: X 211 KB)."""
+    Vh 97 KB), and above the LDS budget a round per launch over the device
+    (110 x 240: X 211 KB)."""
     va = [(-2, 30), (0, 80), (2, 30)]
     for vb, big in (([(-2, 40), (0, 90), (2, 40)], 130), ([(-2, 40), (0, 200), (2, 40)], 240)):
         ph = [(1, 1), (-1, 1)]
@@ -154,6 +155,24 @@ def test_sector_residency_paths():
         O.data[:] = np.random.default_rng(11).standard_normal(O.numel)
         g = _compare(O, 2, 150, 1e-12, None, f"residency {big}")
         assert sum(g["kept"]) == 150
+
+
+def test_big_sectors_run_a_round_per_launch():
+    """Sectors above the LDS budget rotate a round per launch, a workgroup
+    per pair: a tall 300 x 260 sector of rank 200 (60 zero values) and a
+    wide 150 x 400 one (fewer rounds, so its workgroups of the later rounds
+    exit at once), beside a 5 x 7 sector on the one-workgroup path, in one
+    execute."""
+    legs = [(1, [(0, 300), (1, 150), (2, 5)]), (-1, [(0, 260), (1, 400), (2, 7)])]
+    O = orc.BlockTensor(["a", "b"], legs)
+    rng = np.random.default_rng(23)
+    O.block(0)[...] = rng.standard_normal((300, 200)) @ rng.standard_normal((200, 260))
+    O.block(1)[...] = rng.standard_normal((150, 400))
+    O.block(2)[...] = rng.standard_normal((5, 7))
+    assert [s["M"].shape for s in orc.svd_sectors(O, 1)] == [(300, 260), (150, 400), (5, 7)]
+    g = _compare(O, 1, 300, 0.0, None, "big sectors")
+    assert sum(g["kept"]) == 300
+    assert np.sum(g["svals"][0] > 1e-9 * g["svals"][0][0]) == 200
 
 
 def test_rank_deficient_and_thin():
