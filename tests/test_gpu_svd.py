@@ -159,17 +159,18 @@ def test_sector_residency_paths():
 
 def test_big_sectors_run_a_round_per_launch():
     """Sectors above the LDS budget rotate a round per launch, a workgroup
-    per pair: a tall 300 x 260 sector of rank 200 (60 zero values) and a
-    wide 150 x 400 one (fewer rounds, so its workgroups of the later rounds
-    exit at once), beside a 5 x 7 sector on the one-workgroup path, in one
-    execute."""
-    legs = [(1, [(0, 300), (1, 150), (2, 5)]), (-1, [(0, 260), (1, 400), (2, 7)])]
+    per pair: a tall 300 x 260 sector of rank 200 (60 zero values), a wide
+    150 x 400 one and a 2100 x 20 one (fewer rounds, so their workgroups of
+    the later rounds exit at once), beside a 5 x 7 sector on the
+    one-workgroup path, in one execute."""
+    legs = [(1, [(0, 300), (1, 150), (2, 5), (3, 2100)]), (-1, [(0, 260), (1, 400), (2, 7), (3, 20)])]
     O = orc.BlockTensor(["a", "b"], legs)
     rng = np.random.default_rng(23)
     O.block(0)[...] = rng.standard_normal((300, 200)) @ rng.standard_normal((200, 260))
     O.block(1)[...] = rng.standard_normal((150, 400))
     O.block(2)[...] = rng.standard_normal((5, 7))
-    assert [s["M"].shape for s in orc.svd_sectors(O, 1)] == [(300, 260), (150, 400), (5, 7)]
+    O.block(3)[...] = rng.standard_normal((2100, 20))
+    assert [s["M"].shape for s in orc.svd_sectors(O, 1)] == [(300, 260), (150, 400), (5, 7), (2100, 20)]
     g = _compare(O, 1, 300, 0.0, None, "big sectors")
     assert sum(g["kept"]) == 300
     assert np.sum(g["svals"][0] > 1e-9 * g["svals"][0][0]) == 200
