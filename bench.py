@@ -517,38 +517,41 @@ def bench_widened(bst, wl, torch, dev):
     from oracle import oracle as orc
     from paper_2401_01921_amd import dmrg
     out = {}
-    # -- Svd_truncate of a spin-1/2 two-site state, bonds chi = 256 (q in [-6, 6])
-    v = wl.gaussian_sector_dims(256, 6)
-    ph = wl.physical_sectors("1/2")
-    O = orc.BlockTensor(["a", "s1", "s2", "b"], [(1, v), (1, ph), (1, ph), (-1, v)])
-    O.data[:] = wl.normal(wl.seed_for(2, "psi", 7), O.numel)
-    T = bst.Tensor(O.labels, O.legs)
-    x = torch.from_numpy(O.data.copy()).to(dev)
-    plan = bst.Svd(T, 2)
-    ws = bst.workspace(plan.workspace_bytes)
-    shapes = [plan.sector(k)[1:] for k in range(plan.nsectors)]
+    # -- Svd_truncate of a spin-1/2 two-site state, bonds chi = 256 and 1024
+    # (q in [-6, 6]); at 1024, seven sectors (170 x 170 to 266 x 266) exceed
+    # the LDS budget and run a launch per Jacobi round
+    for chi, key in ((256, "svd_truncate"), (1024, "svd_truncate_chi1024")):
+        v = wl.gaussian_sector_dims(chi, 6)
+        ph = wl.physical_sectors("1/2")
+        O = orc.BlockTensor(["a", "s1", "s2", "b"], [(1, v), (1, ph), (1, ph), (-1, v)])
+        O.data[:] = wl.normal(wl.seed_for(2, "psi", 7), O.numel)
+        T = bst.Tensor(O.labels, O.legs)
+        x = torch.from_numpy(O.data.copy()).to(dev)
+        plan = bst.Svd(T, 2)
+        ws = bst.workspace(plan.workspace_bytes)
+        shapes = [plan.sector(k)[1:] for k in range(plan.nsectors)]
 
-    def run_svd():
-        plan.execute(x, ws)
-        kept, _ = plan.truncate(256, 1e-12, None, ws)
-        Ut, Vt = plan.factors(kept, "m")
-        U = torch.empty(Ut.numel, dtype=torch.float64, device=dev)
-        Vd = torch.empty(Vt.numel, dtype=torch.float64, device=dev)
-        S = torch.empty(sum(kept), dtype=torch.float64, device=dev)
-        plan.write(kept, 2, U, S, Vd, ws)
-        return S
-    ms_svd = _time_ms(torch, run_svd, 5)
-    S = run_svd().cpu().numpy()
-    t0 = time.perf_counter()
-    ou, os_, ov, _ = orc.svd_truncate(O, 2, 256, 1e-12, bond="m", absorb="v")
-    cpu_ms = (time.perf_counter() - t0) * 1e3
-    ref = np.concatenate(os_)
-    out["svd_truncate"] = {
-        "workload": "two-site spin-1/2 state, chi = 256 bonds (13 sectors), rows (a, s1), keepdim 256",
-        "elements": O.numel, "sectors": plan.nsectors,
-        "largest_sector": [int(max(m for m, _ in shapes)), int(max(n_ for _, n_ in shapes))],
-        "ms": round(ms_svd, 3), "oracle_ms": round(cpu_ms, 2),
-        "max_value_err": float(np.max(np.abs(np.sort(S) - np.sort(ref))) / ref.max())}
+        def run_svd():
+            plan.execute(x, ws)
+            kept, _ = plan.truncate(chi, 1e-12, None, ws)
+            Ut, Vt = plan.factors(kept, "m")
+            U = torch.empty(Ut.numel, dtype=torch.float64, device=dev)
+            Vd = torch.empty(Vt.numel, dtype=torch.float64, device=dev)
+            S = torch.empty(sum(kept), dtype=torch.float64, device=dev)
+            plan.write(kept, 2, U, S, Vd, ws)
+            return S
+        ms_svd = _time_ms(torch, run_svd, 5 if chi <= 256 else 2)
+        S = run_svd().cpu().numpy()
+        t0 = time.perf_counter()
+        ou, os_, ov, _ = orc.svd_truncate(O, 2, chi, 1e-12, bond="m", absorb="v")
+        cpu_ms = (time.perf_counter() - t0) * 1e3
+        ref = np.concatenate(os_)
+        out[key] = {
+            "workload": f"two-site spin-1/2 state, chi = {chi} bonds ({len(v)} sectors), rows (a, s1), keepdim {chi}",
+            "elements": O.numel, "sectors": plan.nsectors,
+            "largest_sector": [int(max(m for m, _ in shapes)), int(max(n_ for _, n_ in shapes))],
+            "ms": round(ms_svd, 3), "oracle_ms": round(cpu_ms, 2),
+            "max_value_err": float(np.max(np.abs(np.sort(S) - np.sort(ref))) / ref.max())}
     # -- two-site DMRG of the XX chain (N = 16, keepdim 64, 2 sweeps)
     N, keep = 16, 64
     specs = wl.mps_specs(N, "1/2", 0)
