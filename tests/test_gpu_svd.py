@@ -174,6 +174,11 @@ def test_big_sectors_run_a_round_per_launch():
     g = _compare(O, 1, 300, 0.0, None, "big sectors")
     assert sum(g["kept"]) == 300
     assert np.sum(g["svals"][0] > 1e-9 * g["svals"][0][0]) == 200
+    # the rounds' fixed order makes a second run bit-identical
+    h = _gpu_svd(O, 1, 300)
+    for x, y in zip(g["svals"], h["svals"]):
+        assert np.array_equal(x, y)
+    assert np.array_equal(h["U"].data, _gpu_svd(O, 1, 300)["U"].data)
 
 
 def test_rank_deficient_and_thin():
