@@ -442,7 +442,10 @@ bst_status bst_svd_sector(const bst_svd* p, int32_t k, int32_t* charge, int64_t*
  * and bst_svd_write.  A sector matrix above 128 KiB (long side x short side
  * float64 values) runs each round of its sweeps as one launch across the
  * device; the call then waits for the stream after every sweep to test
- * convergence (otherwise it only enqueues). */
+ * convergence (otherwise it only enqueues), and the other sectors' sweeps
+ * run meanwhile on a second stream the plan keeps (default priority, made
+ * on first use on the current device; joined to `stream` before the call
+ * returns). */
 bst_status bst_svd_execute(bst_svd* p, const void* M, void* ws, void* stream);
 
 /* Chooses the kept singular values across all sectors (after

@@ -137,10 +137,13 @@ __global__ __launch_bounds__(64 * kSvdWaves) void svd_jacobi_kernel(const SvdSec
                                                                    double* V, double* __restrict__ sig,
                                                                    double* __restrict__ sorted,
                                                                    int32_t* __restrict__ perm,
-                                                                   int32_t* __restrict__ sweeps) {
+                                                                   int32_t* __restrict__ sweeps, int only) {
   constexpr int NT = 64 * kSvdWaves;
   const SvdSec S = secs[blockIdx.x];
   const int p = S.m >= S.n ? S.m : S.n, r = S.m >= S.n ? S.n : S.m;
+  // only = 1: the sectors that fit (their sweeps); 2: the big ones (sigma
+  // and order after their rounds); 0: all
+  if ((only == 1 && svd_sector_is_big(S.m, S.n)) || (only == 2 && !svd_sector_is_big(S.m, S.n))) return;
   double* const xg = X + S.x_off;
   double* const vg = V + S.v_off;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -334,11 +337,11 @@ hipError_t launch_svd_sweep(const SvdLaunch& l, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_svd_finish(const SvdLaunch& l, hipStream_t s) {
-  if (l.nsec < 0) return hipErrorInvalidValue;
+hipError_t launch_svd_finish(const SvdLaunch& l, hipStream_t s, int only) {
+  if (l.nsec < 0 || only < 0 || only > 2) return hipErrorInvalidValue;
   if (l.nsec > 0)
     hipLaunchKernelGGL(svd_jacobi_kernel, dim3((unsigned)l.nsec), dim3(64 * kSvdWaves), 0, s, l.secs, l.X, l.V,
-                       l.sig, l.sorted, l.perm, l.sweeps);
+                       l.sig, l.sorted, l.perm, l.sweeps, only);
   return hipGetLastError();
 }
 

@@ -57,6 +57,25 @@ struct SvdPlanData {
   std::vector<uint8_t> blob;   // sector and gather tables
   int64_t ngwork = 0;
   void* uploaded = nullptr;
+  // a second stream (default priority) on which the sectors that fit LDS
+  // run their sweeps beside the big sectors' rounds; made on first use, on
+  // the device then current
+  hipStream_t aux = nullptr;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  int aux_dev = -1;
+  void release_aux() {
+    if (!aux) return;
+    int cur = -1;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(aux_dev);
+    (void)hipStreamDestroy(aux);
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    (void)hipSetDevice(cur);
+    aux = nullptr;
+    ev[0] = ev[1] = nullptr;
+    aux_dev = -1;
+  }
+  ~SvdPlanData() { release_aux(); }
 };
 
 }  // namespace bst
@@ -368,21 +387,39 @@ bst_status bst_svd_execute(bst_svd* p, const void* M, void* ws, void* stream) {
   l.vmax = P.vmax;
   l.flags = at<int32_t>(ws, P.ws_flags);
   check_hip(launch_svd_gather(l, s), "svd gather");
-  if (l.nbig > 0) {
-    // sweeps of the big sectors until each has had one without a rotation
-    // (at most kSvdMaxSweeps): the host reads the flags after every sweep
-    std::vector<int32_t> fl(2 * (size_t)l.nbig);
-    for (int sw = 0; sw < kSvdMaxSweeps; ++sw) {
-      check_hip(launch_svd_sweep(l, s), "svd sweep");
-      check_hip(hipMemcpyAsync(fl.data(), l.flags, sizeof(int32_t) * fl.size(), hipMemcpyDeviceToHost, s),
-                "svd flags");
-      check_hip(hipStreamSynchronize(s), "svd flags");
-      bool all = true;
-      for (int b = 0; b < l.nbig; ++b) all = all && fl[2 * (size_t)b + 1] != 0;
-      if (all) break;
+  if (l.nbig == 0) {
+    check_hip(launch_svd_finish(l, s, 0), "svd");
+  } else {
+    // the sectors that fit run their sweeps on the second stream meanwhile
+    int dev = -1;
+    check_hip(hipGetDevice(&dev), "device");
+    if (P.aux && P.aux_dev != dev) P.release_aux();
+    if (!P.aux) {
+      check_hip(hipStreamCreateWithFlags(&P.aux, hipStreamNonBlocking), "svd stream");
+      P.aux_dev = dev;
+      for (auto& e : P.ev) check_hip(hipEventCreateWithFlags(&e, hipEventDisableTiming), "svd event");
     }
+    check_hip(hipEventRecord(P.ev[0], s), "svd event");
+    check_hip(hipStreamWaitEvent(P.aux, P.ev[0], 0), "svd event");
+    check_hip(launch_svd_finish(l, P.aux, 1), "svd");
+    check_hip(hipEventRecord(P.ev[1], P.aux), "svd event");
+    {
+      // sweeps of the big sectors until each has had one without a rotation
+      // (at most kSvdMaxSweeps): the host reads the flags after every sweep
+      std::vector<int32_t> fl(2 * (size_t)l.nbig);
+      for (int sw = 0; sw < kSvdMaxSweeps; ++sw) {
+        check_hip(launch_svd_sweep(l, s), "svd sweep");
+        check_hip(hipMemcpyAsync(fl.data(), l.flags, sizeof(int32_t) * fl.size(), hipMemcpyDeviceToHost, s),
+                  "svd flags");
+        check_hip(hipStreamSynchronize(s), "svd flags");
+        bool all = true;
+        for (int b = 0; b < l.nbig; ++b) all = all && fl[2 * (size_t)b + 1] != 0;
+        if (all) break;
+      }
+    }
+    check_hip(hipStreamWaitEvent(s, P.ev[1], 0), "svd event");
+    check_hip(launch_svd_finish(l, s, 2), "svd");
   }
-  check_hip(launch_svd_finish(l, s), "svd");
   BST_CATCH
 }
 

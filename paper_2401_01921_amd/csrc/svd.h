@@ -84,8 +84,9 @@ hipError_t launch_svd_gather(const SvdLaunch& l, hipStream_t s);
 // sweep's count (a sector whose sweep rotated nothing is marked converged).
 hipError_t launch_svd_sweep(const SvdLaunch& l, hipStream_t s);
 // The sweeps of the other sectors (one workgroup each), then sigma and the
-// sorted order of every sector.
-hipError_t launch_svd_finish(const SvdLaunch& l, hipStream_t s);
+// sorted order of every sector; only = 1 restricts it to the sectors that
+// are not big, 2 to the big ones (after their rounds), 0 takes all.
+hipError_t launch_svd_finish(const SvdLaunch& l, hipStream_t s, int only);
 
 // True when sector (m, n)'s sweeps run a round per launch on the device
 // rather than in one workgroup (its X does not fit kSvdLdsBytes).
