@@ -61,6 +61,9 @@ def measured_traffic(kernel):
     return t["bytes_per_launch"]
 
 
+WIDENED_ROWS = ("svd256", "svd1024", "dmrg16", "dmrg64", "complex")
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -76,6 +79,10 @@ def parse():
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run the library's streaming copy over this many MiB (a kernel "
                          "of known traffic that calibrates hardware byte counters)")
+    ap.add_argument("--widened-only", metavar="ROWS", default=None,
+                    help="run only the named rows beyond the H_eff solve, comma separated, "
+                         f"from {','.join(WIDENED_ROWS)} (one JSON line of their results; "
+                         "for per-workload profiles)")
     return ap.parse_args()
 
 
@@ -133,6 +140,13 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
     dev = "cuda"
+    if a.widened_only is not None:
+        rows = [r for r in a.widened_only.split(",") if r]
+        bad = [r for r in rows if r not in WIDENED_ROWS]
+        if bad or not rows:
+            raise SystemExit(f"--widened-only takes rows from {','.join(WIDENED_ROWS)}")
+        print(json.dumps({"widened": bench_widened(bst, wl, torch, dev, set(rows))}), flush=True)
+        return
     copy_cal = copy_calibration(bst, torch, dev, a.copy_mib) if a.copy_mib > 0 else None
     w = wl.WORKLOADS[WORKLOAD]
     v = wl.gaussian_sector_dims(w["chi"], w["qmax"])
@@ -509,20 +523,24 @@ def bench_extras(bst, wl, torch, dev, plan, ins_apply, apply_flops):
     return out
 
 
-def bench_widened(bst, wl, torch, dev):
+def bench_widened(bst, wl, torch, dev, rows=None):
     """The rows built beyond the H_eff path, each beside the oracle on the
     host: the symmetric truncated SVD of a two-site state, a two-site DMRG
-    sweep of the XX chain, and a complex contraction."""
+    sweep of the XX chain, and a complex contraction.  rows: the subset of
+    WIDENED_ROWS to run (all when None)."""
     import math
     from oracle import oracle as orc
     from paper_2401_01921_amd import dmrg
     out = {}
+    want = (lambda r: True) if rows is None else (lambda r: r in rows)
+    ph = wl.physical_sectors("1/2")
     # -- Svd_truncate of a spin-1/2 two-site state, bonds chi = 256 and 1024
     # (q in [-6, 6]); at 1024, seven sectors (170 x 170 to 266 x 266) exceed
     # the LDS budget and run a launch per Jacobi round
-    for chi, key in ((256, "svd_truncate"), (1024, "svd_truncate_chi1024")):
+    for chi, key, row in ((256, "svd_truncate", "svd256"), (1024, "svd_truncate_chi1024", "svd1024")):
+        if not want(row):
+            continue
         v = wl.gaussian_sector_dims(chi, 6)
-        ph = wl.physical_sectors("1/2")
         O = orc.BlockTensor(["a", "s1", "s2", "b"], [(1, v), (1, ph), (1, ph), (-1, v)])
         O.data[:] = wl.normal(wl.seed_for(2, "psi", 7), O.numel)
         T = bst.Tensor(O.labels, O.legs)
@@ -552,93 +570,98 @@ def bench_widened(bst, wl, torch, dev):
             "largest_sector": [int(max(m for m, _ in shapes)), int(max(n_ for _, n_ in shapes))],
             "ms": round(ms_svd, 3), "oracle_ms": round(cpu_ms, 2),
             "max_value_err": float(np.max(np.abs(np.sort(S) - np.sort(ref))) / ref.max())}
+    # -- the XX MPO and the boundary environments of both chains
+    if want("dmrg16") or want("dmrg64"):
+        Ws = wl.heff_specs("1/2", [(0, 1)], [(0, 1)], "xx")["W1"]
+        Wo = orc.from_dense(*Ws, wl.mpo_dense("1/2", "xx"))
+        Wg = dmrg.DevTensor(bst.Tensor(*Ws), torch.from_numpy(Wo.data.copy()).to(dev))
+        Ls, lpos, Rs, rpos = wl.boundary_env_specs("1/2", "xx", 0)
+        envs = []
+        for sp, pos in ((Ls, lpos), (Rs, rpos)):
+            D = np.zeros(orc.BlockTensor(*sp).dims())
+            D[pos] = 1.0
+            envs.append(dmrg.DevTensor(bst.Tensor(*sp), torch.from_numpy(orc.from_dense(*sp, D).data).to(dev)))
     # -- two-site DMRG of the XX chain (N = 16, keepdim 64, 2 sweeps)
-    N, keep = 16, 64
-    specs = wl.mps_specs(N, "1/2", 0)
-    mps = []
-    for i, (lab, legs) in enumerate(specs):
-        t = bst.Tensor(lab, legs)
-        mps.append(dmrg.DevTensor(t, torch.from_numpy(wl.normal(wl.seed_for(2, "A", i), t.numel)).to(dev)))
-    Ws = wl.heff_specs("1/2", [(0, 1)], [(0, 1)], "xx")["W1"]
-    Wo = orc.from_dense(*Ws, wl.mpo_dense("1/2", "xx"))
-    Wg = dmrg.DevTensor(bst.Tensor(*Ws), torch.from_numpy(Wo.data.copy()).to(dev))
-    Ls, lpos, Rs, rpos = wl.boundary_env_specs("1/2", "xx", 0)
-    envs = []
-    for sp, pos in ((Ls, lpos), (Rs, rpos)):
-        D = np.zeros(orc.BlockTensor(*sp).dims())
-        D[pos] = 1.0
-        envs.append(dmrg.DevTensor(bst.Tensor(*sp), torch.from_numpy(orc.from_dense(*sp, D).data).to(dev)))
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    E, errs, _ = dmrg.dmrg_two_site(mps, Wg, envs[0], envs[1], 2, keep, 1e-12)
-    torch.cuda.synchronize()
-    sweep_s = (time.perf_counter() - t0) / 2
-    exact = sum(min(0.0, math.cos(math.pi * k / (N + 1))) for k in range(1, N + 1))
-    out["dmrg_sweep_xx"] = {
-        "workload": f"open XX chain, spin 1/2, N = {N}, total Sz 0, keepdim {keep}, 2 sweeps from a random MPS",
-        "s_per_sweep": round(sweep_s, 3), "bond_updates": len(E),
-        "energy": E[-1], "exact_free_fermion": exact, "abs_err": abs(E[-1] - exact),
-        "max_s_err": max(errs)}
+    if want("dmrg16"):
+        N, keep = 16, 64
+        specs = wl.mps_specs(N, "1/2", 0)
+        mps = []
+        for i, (lab, legs) in enumerate(specs):
+            t = bst.Tensor(lab, legs)
+            mps.append(dmrg.DevTensor(t, torch.from_numpy(wl.normal(wl.seed_for(2, "A", i), t.numel)).to(dev)))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        E, errs, _ = dmrg.dmrg_two_site(mps, Wg, envs[0], envs[1], 2, keep, 1e-12)
+        torch.cuda.synchronize()
+        sweep_s = (time.perf_counter() - t0) / 2
+        exact = sum(min(0.0, math.cos(math.pi * k / (N + 1))) for k in range(1, N + 1))
+        out["dmrg_sweep_xx"] = {
+            "workload": f"open XX chain, spin 1/2, N = {N}, total Sz 0, keepdim {keep}, 2 sweeps from a random MPS",
+            "s_per_sweep": round(sweep_s, 3), "bond_updates": len(E),
+            "energy": E[-1], "exact_free_fermion": exact, "abs_err": abs(E[-1] - exact),
+            "max_s_err": max(errs)}
     # -- the same chain at N = 64, keepdim 256 (random start with every sector
     # of every bond capped at 16, so that the first sweep grows the bonds)
-    N, keep, cap, nsw = 64, 256, 16, 2
-    specs = wl.mps_specs(N, "1/2", 0, cap=cap)
-    mps = []
-    for i, (lab, legs) in enumerate(specs):
-        t = bst.Tensor(lab, legs)
-        mps.append(dmrg.DevTensor(t, torch.from_numpy(wl.normal(wl.seed_for(2, "A", i), t.numel)).to(dev)))
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    E, errs, fin = dmrg.dmrg_two_site(mps, Wg, envs[0], envs[1], nsw, keep, 1e-12)
-    torch.cuda.synchronize()
-    sweep_s = (time.perf_counter() - t0) / nsw
-    exact = sum(min(0.0, math.cos(math.pi * k / (N + 1))) for k in range(1, N + 1))
-    out["dmrg_sweep_xx_n64_chi256"] = {
-        "workload": f"open XX chain, spin 1/2, N = {N}, total Sz 0, keepdim {keep}, {nsw} sweeps from a random MPS "
-                    f"with sectors capped at {cap}",
-        "s_per_sweep": round(sweep_s, 3), "bond_updates": len(E),
-        "largest_bond": max(int(sum(g for _, g in T.t.legs()[1][2][1])) for T in fin),
-        "energy": E[-1], "exact_free_fermion": exact, "abs_err": abs(E[-1] - exact),
-        "max_s_err": max(errs)}
+    if want("dmrg64"):
+        N, keep, cap, nsw = 64, 256, 16, 2
+        specs = wl.mps_specs(N, "1/2", 0, cap=cap)
+        mps = []
+        for i, (lab, legs) in enumerate(specs):
+            t = bst.Tensor(lab, legs)
+            mps.append(dmrg.DevTensor(t, torch.from_numpy(wl.normal(wl.seed_for(2, "A", i), t.numel)).to(dev)))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        E, errs, fin = dmrg.dmrg_two_site(mps, Wg, envs[0], envs[1], nsw, keep, 1e-12)
+        torch.cuda.synchronize()
+        sweep_s = (time.perf_counter() - t0) / nsw
+        exact = sum(min(0.0, math.cos(math.pi * k / (N + 1))) for k in range(1, N + 1))
+        out["dmrg_sweep_xx_n64_chi256"] = {
+            "workload": f"open XX chain, spin 1/2, N = {N}, total Sz 0, keepdim {keep}, {nsw} sweeps from a random MPS "
+                        f"with sectors capped at {cap}",
+            "s_per_sweep": round(sweep_s, 3), "bond_updates": len(E),
+            "largest_bond": max(int(sum(g for _, g in T.t.legs()[1][2][1])) for T in fin),
+            "energy": E[-1], "exact_free_fermion": exact, "abs_err": abs(E[-1] - exact),
+            "max_s_err": max(errs)}
     # -- complex contraction A[l, s, m] . B[m, t, r], chi = 2048 (q in [-16, 16])
-    v = wl.gaussian_sector_dims(2048, 16)
-    A = (["l", "s", "m"], [(1, v), (1, ph), (-1, v)])
-    B = (["m", "t", "r"], [(1, v), (1, ph), (-1, v)])
-    tA, tB = bst.Tensor(*A), bst.Tensor(*B)
-    res = {}
-    for dt in ("f64", "c128"):
-        w_ = 2 if dt == "c128" else 1
-        tC, cp = bst.contract_plan(tA, tB, "fp64", dtype=dt)
-        a_ = torch.randn(w_ * tA.numel, dtype=torch.float64, device=dev)
-        b_ = torch.randn(w_ * tB.numel, dtype=torch.float64, device=dev)
-        c_ = torch.empty(w_ * tC.numel, dtype=torch.float64, device=dev)
-        wsc = bst.workspace(cp.workspace_bytes)
-        cp.autotune([a_, b_], [c_], wsc, reps=3)
-        ms = _time_ms(torch, lambda: cp.execute([a_, b_], [c_], wsc), 10)
-        fl = cp.stats().flops
-        res[dt] = {"ms": round(ms, 4), "gflops": round(fl / ms / 1e6, 1), "flops": fl, "tiles": cp.tiles()}
-    # the oracle's complex contraction of a smaller state (chi = 512) on the host
-    v5 = wl.gaussian_sector_dims(512, 8)
-    Ao = orc.BlockTensor(["l", "s", "m"], [(1, v5), (1, ph), (-1, v5)], dtype=np.complex128)
-    Bo = orc.BlockTensor(["m", "t", "r"], [(1, v5), (1, ph), (-1, v5)], dtype=np.complex128)
-    Ao.data[:] = wl.normal(11, Ao.numel) + 1j * wl.normal(12, Ao.numel)
-    Bo.data[:] = wl.normal(13, Bo.numel) + 1j * wl.normal(14, Bo.numel)
-    t0 = time.perf_counter()
-    Co = orc.contract(Ao, Bo)
-    cpu_s = time.perf_counter() - t0
-    t5A, t5B = bst.Tensor(*(Ao.labels, Ao.legs)), bst.Tensor(*(Bo.labels, Bo.legs))
-    t5C, p5 = bst.contract_plan(t5A, t5B, "fp64", dtype="c128")
-    a5 = torch.view_as_real(torch.from_numpy(Ao.data).to(dev)).reshape(-1)
-    b5 = torch.view_as_real(torch.from_numpy(Bo.data).to(dev)).reshape(-1)
-    c5 = torch.empty(2 * t5C.numel, dtype=torch.float64, device=dev)
-    p5.execute([a5, b5], [c5], bst.workspace(p5.workspace_bytes))
-    got = c5.cpu().numpy().reshape(-1, 2)
-    got = got[:, 0] + 1j * got[:, 1]
-    out["complex_contract"] = {
-        "workload": "A[l,s,m].B[m,t,r], spin-1/2 physical legs, chi = 2048 virtual legs (33 sectors), FP64 arithmetic",
-        "c128": res["c128"], "f64_same_structure": res["f64"],
-        "oracle_chi512_gflops": round(p5.stats().flops / cpu_s / 1e9, 2),
-        "chi512_max_err_vs_oracle": float(np.max(np.abs(got - Co.data)) / np.max(np.abs(Co.data)))}
+    if want("complex"):
+        v = wl.gaussian_sector_dims(2048, 16)
+        A = (["l", "s", "m"], [(1, v), (1, ph), (-1, v)])
+        B = (["m", "t", "r"], [(1, v), (1, ph), (-1, v)])
+        tA, tB = bst.Tensor(*A), bst.Tensor(*B)
+        res = {}
+        for dt in ("f64", "c128"):
+            w_ = 2 if dt == "c128" else 1
+            tC, cp = bst.contract_plan(tA, tB, "fp64", dtype=dt)
+            a_ = torch.randn(w_ * tA.numel, dtype=torch.float64, device=dev)
+            b_ = torch.randn(w_ * tB.numel, dtype=torch.float64, device=dev)
+            c_ = torch.empty(w_ * tC.numel, dtype=torch.float64, device=dev)
+            wsc = bst.workspace(cp.workspace_bytes)
+            cp.autotune([a_, b_], [c_], wsc, reps=3)
+            ms = _time_ms(torch, lambda: cp.execute([a_, b_], [c_], wsc), 10)
+            fl = cp.stats().flops
+            res[dt] = {"ms": round(ms, 4), "gflops": round(fl / ms / 1e6, 1), "flops": fl, "tiles": cp.tiles()}
+        # the oracle's complex contraction of a smaller state (chi = 512) on the host
+        v5 = wl.gaussian_sector_dims(512, 8)
+        Ao = orc.BlockTensor(["l", "s", "m"], [(1, v5), (1, ph), (-1, v5)], dtype=np.complex128)
+        Bo = orc.BlockTensor(["m", "t", "r"], [(1, v5), (1, ph), (-1, v5)], dtype=np.complex128)
+        Ao.data[:] = wl.normal(11, Ao.numel) + 1j * wl.normal(12, Ao.numel)
+        Bo.data[:] = wl.normal(13, Bo.numel) + 1j * wl.normal(14, Bo.numel)
+        t0 = time.perf_counter()
+        Co = orc.contract(Ao, Bo)
+        cpu_s = time.perf_counter() - t0
+        t5A, t5B = bst.Tensor(*(Ao.labels, Ao.legs)), bst.Tensor(*(Bo.labels, Bo.legs))
+        t5C, p5 = bst.contract_plan(t5A, t5B, "fp64", dtype="c128")
+        a5 = torch.view_as_real(torch.from_numpy(Ao.data).to(dev)).reshape(-1)
+        b5 = torch.view_as_real(torch.from_numpy(Bo.data).to(dev)).reshape(-1)
+        c5 = torch.empty(2 * t5C.numel, dtype=torch.float64, device=dev)
+        p5.execute([a5, b5], [c5], bst.workspace(p5.workspace_bytes))
+        got = c5.cpu().numpy().reshape(-1, 2)
+        got = got[:, 0] + 1j * got[:, 1]
+        out["complex_contract"] = {
+            "workload": "A[l,s,m].B[m,t,r], spin-1/2 physical legs, chi = 2048 virtual legs (33 sectors), FP64 arithmetic",
+            "c128": res["c128"], "f64_same_structure": res["f64"],
+            "oracle_chi512_gflops": round(p5.stats().flops / cpu_s / 1e9, 2),
+            "chi512_max_err_vs_oracle": float(np.max(np.abs(got - Co.data)) / np.max(np.abs(Co.data)))}
     return out
 
 
