@@ -480,6 +480,14 @@ bst_status bst_svd_factors(const bst_svd* p, const int64_t* kept, const char* bo
 bst_status bst_svd_write(bst_svd* p, const int64_t* kept, int32_t absorb, void* U, void* S, void* Vd,
                          void* ws, void* stream);
 
+/* Convergence report of the last bst_svd_execute on this workspace: per
+ * sector, in sector order, the number of Jacobi sweeps that rotated at
+ * least one pair (nsectors int32 values into host memory `sweeps`).  A
+ * converged sector ran one more sweep that rotated nothing; 60, the cap,
+ * means it stopped there; a sector with one column reports 0.  Waits for
+ * `stream`.  Errors: BST_E_INVALID. */
+bst_status bst_svd_sweeps(const bst_svd* p, const void* ws, void* stream, int32_t* sweeps);
+
 /* Forget which workspace holds the plan's tables (call before reusing a
  * plan after freeing or overwriting its workspace). */
 bst_status bst_svd_forget_workspace(bst_svd* p);

@@ -35,7 +35,7 @@ EXPORTS = [
     "bst_tensor_create_sym", "bst_tensor_symmetry", "bst_tensor_leg_charges",
     "bst_network_order", "bst_plan_record_tiles", "bst_execute_static", "bst_calib_grid", "bst_calib_copy", "bst_calib_read", "bst_calib_mfma",
     "bst_svd_plan", "bst_svd_info", "bst_svd_sector", "bst_svd_execute", "bst_svd_truncate",
-    "bst_svd_factors", "bst_svd_write", "bst_svd_forget_workspace", "bst_svd_destroy",
+    "bst_svd_factors", "bst_svd_write", "bst_svd_sweeps", "bst_svd_forget_workspace", "bst_svd_destroy",
     "bst_permute_plan_c128", "bst_contract_plan_c128",
 ]
 
@@ -125,6 +125,7 @@ def _load():
         "bst_svd_truncate": [vp, i64, C.c_double, P(i64), vp, vp, P(i64), P(C.c_double)],
         "bst_svd_factors": [vp, P(i64), C.c_char_p, P(vp), P(vp)],
         "bst_svd_write": [vp, P(i64), i32, vp, vp, vp, vp, vp],
+        "bst_svd_sweeps": [vp, vp, vp, P(i32)],
         "bst_svd_forget_workspace": [vp],
         "bst_svd_destroy": [vp],
         "bst_permute_plan_c128": [vp, P(C.c_char_p), P(vp), P(vp)],
@@ -613,6 +614,12 @@ class Svd:
         k = (C.c_int64 * max(self.nsectors, 1))(*[int(x) for x in kept])
         _check(_lib.bst_svd_write(self._h, k, int(absorb), C.c_void_p(_ptr(U)), C.c_void_p(_ptr(S)),
                                   C.c_void_p(_ptr(Vd)), C.c_void_p(_ptr(ws)), _stream(stream)))
+
+    def sweeps(self, ws, stream=None):
+        """Jacobi sweeps each sector used in the last execute on ws."""
+        out = (C.c_int32 * max(self.nsectors, 1))()
+        _check(_lib.bst_svd_sweeps(self._h, C.c_void_p(_ptr(ws)), _stream(stream), out))
+        return [int(x) for x in out[:self.nsectors]]
 
     def forget_workspace(self):
         _check(_lib.bst_svd_forget_workspace(self._h))

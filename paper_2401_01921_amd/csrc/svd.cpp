@@ -550,6 +550,20 @@ bst_status bst_svd_write(bst_svd* p, const int64_t* kept, int32_t absorb, void* 
   BST_CATCH
 }
 
+bst_status bst_svd_sweeps(const bst_svd* p, const void* ws, void* stream, int32_t* sweeps) {
+  BST_TRY
+  if (!p || !ws || !sweeps) fail(BST_E_INVALID, "null argument");
+  const SvdPlanData& P = p->p;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (!P.secs.empty()) {
+    check_hip(hipMemcpyAsync(sweeps, static_cast<const char*>(ws) + P.ws_sweeps, sizeof(int32_t) * P.secs.size(),
+                             hipMemcpyDeviceToHost, s),
+              "svd sweeps");
+    check_hip(hipStreamSynchronize(s), "svd sweeps");
+  }
+  BST_CATCH
+}
+
 bst_status bst_svd_forget_workspace(bst_svd* p) {
   BST_TRY
   if (!p) fail(BST_E_INVALID, "null plan");

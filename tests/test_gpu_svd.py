@@ -157,6 +157,25 @@ def test_sector_residency_paths():
         assert sum(g["kept"]) == 150
 
 
+def test_sweep_report():
+    """bst_svd_sweeps: a diagonal sector (columns already orthogonal) rotates
+    in no sweep, a one-column sector has none, and a random 300 x 260 one
+    (rotated a round per launch) converges within the cap."""
+    legs = [(1, [(0, 6), (1, 30), (2, 300)]), (-1, [(0, 6), (1, 1), (2, 260)])]
+    O = orc.BlockTensor(["a", "b"], legs)
+    O.block(0)[...] = np.diag(np.arange(1.0, 7.0))
+    rng = np.random.default_rng(5)
+    O.block(1)[...] = rng.standard_normal((30, 1))
+    O.block(2)[...] = rng.standard_normal((300, 260))
+    plan = bst.Svd(bst.Tensor(O.labels, O.legs), 1)
+    assert [plan.sector(k)[1:] for k in range(plan.nsectors)] == [(6, 6), (30, 1), (300, 260)]
+    ws = bst.workspace(plan.workspace_bytes)
+    plan.execute(dev(O.data), ws)
+    sw = plan.sweeps(ws)
+    assert sw[0] == 0 and sw[1] == 0
+    assert 1 <= sw[2] < 60
+
+
 def test_big_sectors_run_a_round_per_launch():
     """Sectors above the LDS budget rotate a round per launch, a workgroup
     per pair: a tall 300 x 260 sector of rank 200 (60 zero values), a wide
