@@ -365,13 +365,26 @@ __global__ __launch_bounds__(1024) void svd_select_kernel(const SvdSec* __restri
   __shared__ int cnt[kSelectMaxSectors];
   __shared__ long long forced_total, total;
   __shared__ double vals[kSelectLdsValues];
+  // per sector: value offset (below 2^31: the plan refuses more values),
+  // rank and forced count, staged once, since every counting pass of the
+  // bisections below walks all sectors
+  __shared__ int soff[kSelectMaxSectors], srank[kSelectMaxSectors], sforced[kSelectMaxSectors];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  auto rsec = [&](int q) { return secs[q].m < secs[q].n ? secs[q].m : secs[q].n; };
+  for (int q = tid; q < nsec; q += 1024) {
+    const SvdSec S = secs[q];
+    const int r = S.m < S.n ? S.m : S.n;
+    const int64_t f = min_blockdim ? min_blockdim[q] : 0;
+    soff[q] = (int)S.s_off;
+    srank[q] = r;
+    sforced[q] = (int)(f < 0 ? 0 : (f < r ? f : r));
+  }
+  __syncthreads();
+  auto rsec = [&](int q) { return srank[q]; };
   // the sorted values of all sectors (flat, s_off + i) in LDS when they fit:
   // every bisection step below scans them all
   if (tid == 0) {
     long long t = 0;
-    for (int q = 0; q < nsec; ++q) t = secs[q].s_off + rsec(q) > t ? secs[q].s_off + rsec(q) : t;
+    for (int q = 0; q < nsec; ++q) t = (long long)soff[q] + rsec(q) > t ? (long long)soff[q] + rsec(q) : t;
     total = t;
   }
   __syncthreads();
@@ -379,10 +392,7 @@ __global__ __launch_bounds__(1024) void svd_select_kernel(const SvdSec* __restri
   if (staged)
     for (long long e = tid; e < total; e += 1024) vals[e] = sorted[e];
   const double* src = staged ? (const double*)vals : sorted;
-  auto forced = [&](int q) -> int {
-    const int64_t f = min_blockdim ? min_blockdim[q] : 0;
-    return (int)(f < 0 ? 0 : (f < rsec(q) ? f : rsec(q)));
-  };
+  auto forced = [&](int q) -> int { return sforced[q]; };
   // block-wide sum of per-thread counts
   auto block_sum = [&](unsigned long long v) -> unsigned long long {
 #pragma unroll
@@ -400,11 +410,11 @@ __global__ __launch_bounds__(1024) void svd_select_kernel(const SvdSec* __restri
     for (int q = 0; q < nsec; ++q) {
       const int r = rsec(q), f = forced(q);
       for (int i = f + tid; i < r; i += 1024) {
-        const double v = src[secs[q].s_off + i];
+        const double v = src[(long long)soff[q] + i];
         if (!(v >= err)) continue;
         const unsigned long long b = (unsigned long long)__double_as_longlong(v);
         if (mode == 0) c += b >= lo ? 1 : 0;
-        else c += (b == lo && secs[q].s_off + i < lim) ? 1 : 0;
+        else c += (b == lo && (long long)soff[q] + i < lim) ? 1 : 0;
       }
     }
     return block_sum(c);
@@ -434,7 +444,7 @@ __global__ __launch_bounds__(1024) void svd_select_kernel(const SvdSec* __restri
     const long long need = room - (long long)count(0, cut + 1, 0);
     // the smallest flat bound with need equal values before it
     long long a = 0, b = 0;
-    for (int q = 0; q < nsec; ++q) b = secs[q].s_off + rsec(q) > b ? secs[q].s_off + rsec(q) : b;
+    for (int q = 0; q < nsec; ++q) b = (long long)soff[q] + rsec(q) > b ? (long long)soff[q] + rsec(q) : b;
     while (a < b) {
       const long long mid = a + (b - a) / 2;
       if ((long long)count(1, cut, mid) >= need) b = mid;
@@ -446,10 +456,10 @@ __global__ __launch_bounds__(1024) void svd_select_kernel(const SvdSec* __restri
     const int r = rsec(q), f = forced(q);
     int c = 0;
     for (int i = f + tid; i < r; i += 1024) {
-      const double v = src[secs[q].s_off + i];
+      const double v = src[(long long)soff[q] + i];
       if (!(v >= err) || none) continue;
       const unsigned long long bits = (unsigned long long)__double_as_longlong(v);
-      c += (all || bits > cut || (bits == cut && secs[q].s_off + i < lim)) ? 1 : 0;
+      c += (all || bits > cut || (bits == cut && (long long)soff[q] + i < lim)) ? 1 : 0;
     }
     if (c) atomicAdd(&cnt[q], c);
   }
@@ -459,7 +469,7 @@ __global__ __launch_bounds__(1024) void svd_select_kernel(const SvdSec* __restri
     for (int q = 0; q < nsec; ++q) {
       const int k = forced(q) + cnt[q];
       kept[q] = k;
-      if (k < rsec(q)) e = fmax(e, sorted[secs[q].s_off + k]);
+      if (k < rsec(q)) e = fmax(e, sorted[(long long)soff[q] + k]);
     }
     *s_err = e;
   }
